@@ -1,0 +1,380 @@
+"""CPU oracle for the extruded-mesh numbering and column iteration.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``; never by the product package.
+It shares no code with the HIP path; the only common module is the seeded
+input generator.
+
+Reference: Bercea et al., arXiv 1604.05937.
+* Algorithm 1 (Section 3.2) -- vertical-innermost numbering, in ``number``
+  (a literal counter loop in ``oracle.c``).
+* Algorithm 2 (Section 3.3) -- vertical offsets, in ``stencil``.
+* Algorithm 3 (Section 3.3) -- column iteration ``L + n * offset`` with a
+  stencil kernel, in ``par_loop``.
+* The kernels integrate the forms of Section 4.1.1 (the residual of the
+  integral of f v) and the mass action, cubic residual and its derivatives,
+  by quadrature with a full Jacobian at each point.  The rules are Gauss
+  rules from scipy (Gauss-Legendre on the interval; the collapsed
+  Gauss-Jacobi conical product on the triangle), chosen exact for the
+  polynomial degree each form reaches on a prism whose columns are vertical
+  (x, y fixed along a column, any z).
+
+Readings where the paper is silent (each also listed in the design notes):
+* entities are visited dimension-major (d1 = 0, 1, 2), then by base index;
+* several DoFs on one entity are ordered horizontal-node major, vertical-node
+  minor;
+* a prism's stencil lists its closure entities as vertex 0, 1, 2, edge 0, 1,
+  2 (edge a opposite vertex a), cell; per entity the bottom horizontal DoFs,
+  the top horizontal DoFs, then the vertical DoFs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from functools import lru_cache
+
+import numpy as np
+from scipy.special import roots_jacobi, roots_legendre
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FORM_MASS = 1
+FORM_CUBIC = 2
+FORM_CUBIC_VJP = 3
+FORM_CUBIC_JVP = 4
+FORM_CUBIC_FUSED = 5
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                        _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+@lru_cache(maxsize=1)
+def _lib():
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    lib.oracle_alg1_number.restype = ctypes.c_int64
+    lib.oracle_alg1_number.argtypes = [P, ctypes.c_int32, P, P, P, P]
+    lib.oracle_stencil.restype = ctypes.c_int32
+    lib.oracle_stencil.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, P, P]
+    lib.oracle_par_loop.restype = None
+    lib.oracle_par_loop.argtypes = [ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int32,
+                                    P, P, P, ctypes.c_int32, P, P,
+                                    P, P, P, P, P, P, ctypes.c_int32,
+                                    ctypes.c_int32, P, P, P, P]
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Finite element families on the prism (tensor products, Section 3.1.1 and
+# Section 4.1.2).  Horizontal families live on the triangle, vertical ones on
+# the interval; a space is a pair (h, v).
+
+# number of horizontal nodes carried by a base entity of dimension 0, 1, 2
+_H_NODES = {"CG1": (1, 0, 0), "CG2": (1, 1, 0), "DG0": (0, 0, 1), "DG1": (0, 0, 3)}
+# number of vertical nodes on an interval end point and in its interior
+_V_NODES = {"CG1": (1, 0), "CG2": (1, 1), "DG0": (0, 1), "DG1": (0, 2)}
+
+
+def delta_table(h: str, v: str) -> np.ndarray:
+    """delta((d1, d2)) for the tensor-product space h x v, as a [3, 2] table."""
+    hn = _H_NODES[h]
+    vn = _V_NODES[v]
+    return np.array([[hn[d] * vn[0], hn[d] * vn[1]] for d in range(3)], dtype=np.int32)
+
+
+def _h_basis(h: str, d: int, ent: int, j: int, lam):
+    """Horizontal basis function of node j on closure entity ``ent`` (local
+    index within its dimension) evaluated at barycentric coordinates lam[3]."""
+    if h == "CG1":
+        return lam[ent]
+    if h == "CG2":
+        if d == 0:
+            return lam[ent] * (2.0 * lam[ent] - 1.0)
+        a, b = (ent + 1) % 3, (ent + 2) % 3
+        return 4.0 * lam[a] * lam[b]
+    if h == "DG0":
+        return np.ones_like(lam[0])
+    if h == "DG1":
+        return lam[j]
+    raise ValueError(h)
+
+
+def _v_basis(v: str, part: str, j: int, z):
+    """Vertical basis function: part 'bot' / 'top' endpoint node or interior node j."""
+    if part == "bot":
+        return (1.0 - z) if v == "CG1" else (1.0 - z) * (1.0 - 2.0 * z)
+    if part == "top":
+        return z if v == "CG1" else z * (2.0 * z - 1.0)
+    if v == "CG2":
+        return 4.0 * z * (1.0 - z)
+    if v == "DG0":
+        return np.ones_like(z)
+    if v == "DG1":
+        return (1.0 - z) if j == 0 else z
+    raise ValueError(v)
+
+
+def stencil_layout(h: str, v: str):
+    """For each stencil position p: (entity dim d, local entity, part, horizontal
+    node index alpha within the entity, vertical node index beta)."""
+    dl = delta_table(h, v)
+    hn = _H_NODES[h]
+    vn = _V_NODES[v]
+    out = []
+    for e in range(7):
+        d = 0 if e < 3 else (1 if e < 6 else 2)
+        ent = e if d == 0 else (e - 3 if d == 1 else 0)
+        for part, count, nvp in (("bot", dl[d, 0], vn[0]), ("top", dl[d, 0], vn[0]), ("int", dl[d, 1], vn[1])):
+            for j in range(count):
+                alpha, beta = divmod(j, nvp) if nvp else (j, 0)
+                out.append((d, ent, part, alpha, beta))
+    assert len(out) == sum(2 * dl[d, 0] + dl[d, 1] for d in (0, 0, 0, 1, 1, 1, 2))
+    del hn
+    return out
+
+
+def tabulate(h: str, v: str, pts: np.ndarray) -> np.ndarray:
+    """phi[q, p] for the space h x v at reference points pts[q] = (xi, eta, zeta)."""
+    lam = np.stack([1.0 - pts[:, 0] - pts[:, 1], pts[:, 0], pts[:, 1]])
+    z = pts[:, 2]
+    cols = []
+    for d, ent, part, alpha, beta in stencil_layout(h, v):
+        cols.append(_h_basis(h, d, ent, alpha, lam) * _v_basis(v, part, beta, z))
+    return np.stack(cols, axis=1)
+
+
+def tabulate_coords(pts: np.ndarray):
+    """P1 x P1 basis of the coordinate field and its reference derivatives."""
+    phi = tabulate("CG1", "CG1", pts)
+    nq = pts.shape[0]
+    dphi = np.zeros((nq, 6, 3))
+    dlam = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])  # d lambda_a / d(xi, eta)
+    lam = np.stack([1.0 - pts[:, 0] - pts[:, 1], pts[:, 0], pts[:, 1]], axis=1)
+    z = pts[:, 2]
+    for a in range(3):
+        for beta, (vz, dvz) in enumerate(((1.0 - z, -1.0), (z, 1.0))):
+            p = 2 * a + beta
+            dphi[:, p, 0] = dlam[a, 0] * vz
+            dphi[:, p, 1] = dlam[a, 1] * vz
+            dphi[:, p, 2] = lam[:, a] * dvz
+    return phi, dphi
+
+
+# ---------------------------------------------------------------------------
+# Quadrature
+
+def gauss_legendre01(m: int):
+    """m-point Gauss-Legendre rule on [0, 1] (exact to degree 2m-1)."""
+    x, w = roots_legendre(m)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def triangle_rule(n: int):
+    """Conical-product rule on the reference triangle {xi, eta >= 0, xi+eta <= 1}
+    with n*n points, exact to total degree 2n-1: xi = u, eta = t (1 - u), with u
+    from n-point Gauss-Jacobi (weight 1-u) and t from n-point Gauss-Legendre."""
+    xj, wj = roots_jacobi(n, 1.0, 0.0)
+    u = 0.5 * (xj + 1.0)
+    wu = 0.25 * wj
+    t, wt = gauss_legendre01(n)
+    pts = np.array([[ui, ti * (1.0 - ui)] for ui in u for ti in t])
+    wts = np.array([a * b for a in wu for b in wt])
+    return pts, wts
+
+
+def prism_rule(n_tri: int, n_int: int):
+    tp, tw = triangle_rule(n_tri)
+    zp, zw = gauss_legendre01(n_int)
+    pts = np.array([[p[0], p[1], z] for p in tp for z in zp])
+    wts = np.array([a * b for a in tw for b in zw])
+    return pts, wts
+
+
+# Highest polynomial degree (horizontal, vertical) of each form's integrand on
+# vertical-column prisms: det J is linear in the horizontal variables there.
+_DEG_V = {"CG1": 1, "CG2": 2, "DG0": 0, "DG1": 1}
+_DEG_H = {"CG1": 1, "CG2": 2, "DG0": 0, "DG1": 1}
+
+
+def rule_for(form: int, h: str, v: str):
+    dh, dv = _DEG_H[h], _DEG_V[v]
+    if form == FORM_MASS:
+        nh, nv = 2 * dh + 1, 2 * dv
+    else:  # cubic family: four field factors times a test function
+        nh, nv = 4 * dh + 1, 4 * dv
+    n_tri = max(1, (nh + 2) // 2)
+    n_int = max(1, (nv + 2) // 2)
+    return prism_rule(n_tri, n_int)
+
+
+# ---------------------------------------------------------------------------
+# Numbering
+
+@dataclass
+class Numbering:
+    counts: tuple
+    n_layers: int
+    delta: np.ndarray           # [3, 2]
+    n_dofs: int
+    first: list                 # first[d1]: [N_d1, lam+1, 2] int64 (-1 = no entity)
+    lmap: np.ndarray            # [N2, k] int64 explicit list at layer 0
+    offsets: np.ndarray         # [k] int32
+    entity_dim: np.ndarray      # [k] int32
+
+    @property
+    def k(self) -> int:
+        return int(self.offsets.size)
+
+    def column_starts(self, d1: int) -> np.ndarray:
+        """First DoF of the column of every base entity of dimension d1."""
+        return self.first[d1][:, 0, 0].copy()
+
+
+def number(counts, n_layers: int, delta, cell_vertex, cell_edge=None) -> Numbering:
+    """Algorithm 1 + the explicit lists + Algorithm 2 for one function space."""
+    lib = _lib()
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    delta = np.ascontiguousarray(np.asarray(delta, dtype=np.int32).reshape(3, 2))
+    if n_layers < 1:
+        raise ValueError("need at least one layer")
+    first = [np.full((int(counts[d]), n_layers + 1, 2), -1, dtype=np.int64) for d in range(3)]
+    n_dofs = lib.oracle_alg1_number(_ptr(counts), n_layers, _ptr(delta), _ptr(first[0]), _ptr(first[1]), _ptr(first[2]))
+    k = lib.oracle_stencil(0, n_layers, _ptr(delta), None, None, None, None, None, None, None, None)
+    offsets = np.zeros(k, dtype=np.int32)
+    edim = np.zeros(k, dtype=np.int32)
+    lmap = np.zeros((int(counts[2]), k), dtype=np.int64)
+    cv = np.ascontiguousarray(cell_vertex, dtype=np.int32)
+    if delta[1].sum() > 0:
+        if cell_edge is None:
+            raise ValueError("this space has edge DoFs: cell_edge is required")
+        ce = np.ascontiguousarray(cell_edge, dtype=np.int32)
+    else:
+        ce = None
+    lib.oracle_stencil(int(counts[2]), n_layers, _ptr(delta), _ptr(cv), _ptr(ce),
+                       _ptr(first[0]), _ptr(first[1]), _ptr(first[2]), _ptr(lmap), _ptr(offsets), _ptr(edim))
+    return Numbering(tuple(int(x) for x in counts), n_layers, delta, int(n_dofs), first, lmap, offsets, edim)
+
+
+def coordinate_field(num_x: Numbering, vertex_coords: np.ndarray) -> np.ndarray:
+    """Place coords[v, l, :] of the extruded vertices at the DoFs of the P1 x P1
+    coordinate space: X[dof(v, l), :]."""
+    nv, nl, _ = vertex_coords.shape
+    X = np.zeros((num_x.n_dofs, 3))
+    dof = num_x.first[0][:, :, 0]          # [N0, lam+1]
+    X[dof.ravel()] = vertex_coords.reshape(-1, 3)
+    return X
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3 with the element kernels
+
+def par_loop(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray,
+             ins, outs, write: bool = False, cells=None, rule=None):
+    """Run Algorithm 3 over all base cells (or the given subset) for one form.
+
+    ins / outs: lists of FP64 vectors on space V (outs are updated in place:
+    assigned when ``write`` else incremented)."""
+    h, v = space
+    lib = _lib()
+    pts, wts = rule if rule is not None else rule_for(form, h, v)
+    phiv = np.ascontiguousarray(tabulate(h, v, pts))
+    phix, dphix = tabulate_coords(pts)
+    assert phiv.shape[1] == num_v.k
+    ins = list(ins) + [None] * (3 - len(ins))
+    outs = list(outs) + [None] * (3 - len(outs))
+    for a in ins + outs:
+        if a is not None:
+            assert a.dtype == np.float64 and a.flags.c_contiguous and a.size == num_v.n_dofs
+    Xc = np.ascontiguousarray(X, dtype=np.float64)
+    if cells is None:
+        n_iter, cptr = num_v.counts[2], None
+    else:
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        n_iter, cptr = cells.size, _ptr(cells)
+    lib.oracle_par_loop(form, n_iter, cptr, num_v.n_layers,
+                        _ptr(num_x.lmap), _ptr(num_x.offsets), _ptr(Xc),
+                        num_v.k, _ptr(num_v.lmap), _ptr(num_v.offsets),
+                        _ptr(ins[0]), _ptr(ins[1]), _ptr(ins[2]),
+                        _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), 1 if write else 0,
+                        int(wts.size), _ptr(np.ascontiguousarray(wts)), _ptr(np.ascontiguousarray(phix)),
+                        _ptr(np.ascontiguousarray(dphix)), _ptr(phiv))
+    return outs
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrappers for the forms of the hot path
+
+SPACES = {
+    "P1": ("CG1", "CG1"),
+    "DG0": ("DG0", "DG0"),
+    "DG1": ("DG1", "DG1"),
+    "P2": ("CG2", "CG2"),
+}
+
+
+def is_continuous(space: tuple) -> bool:
+    return space[0].startswith("CG") or space[1].startswith("CG")
+
+
+class Problem:
+    """A base mesh extruded to n_layers with its coordinate field and one space."""
+
+    def __init__(self, mesh, n_layers: int, space: str | tuple, vertex_coords: np.ndarray):
+        self.mesh = mesh
+        self.n_layers = n_layers
+        self.space = SPACES.get(space, space) if isinstance(space, str) else space
+        counts = mesh.counts
+        self.num_x = number(counts, n_layers, delta_table("CG1", "CG1"), mesh.cell_vertex, mesh.cell_edge)
+        self.num_v = number(counts, n_layers, delta_table(*self.space), mesh.cell_vertex, mesh.cell_edge)
+        self.X = coordinate_field(self.num_x, vertex_coords)
+
+    @property
+    def n_dofs(self) -> int:
+        return self.num_v.n_dofs
+
+    def mass(self, x, cells=None):
+        """y = M x, i.e. the residual y_i = integral of x_h v_i (Section 4.1.1)."""
+        y = np.zeros(self.n_dofs)
+        par_loop(FORM_MASS, self.space, self.num_v, self.num_x, self.X, [x], [y],
+                 write=not is_continuous(self.space), cells=cells)
+        return y
+
+    def cubic(self, u, f, cells=None):
+        F = np.zeros(self.n_dofs)
+        par_loop(FORM_CUBIC, self.space, self.num_v, self.num_x, self.X, [u, f], [F], cells=cells)
+        return F
+
+    def cubic_vjp(self, u, w, cells=None):
+        gu = np.zeros(self.n_dofs)
+        gf = np.zeros(self.n_dofs)
+        par_loop(FORM_CUBIC_VJP, self.space, self.num_v, self.num_x, self.X, [u, w], [gu, gf], cells=cells)
+        return gu, gf
+
+    def cubic_jvp(self, u, du, df, cells=None):
+        dF = np.zeros(self.n_dofs)
+        par_loop(FORM_CUBIC_JVP, self.space, self.num_v, self.num_x, self.X, [u, du, df], [dF], cells=cells)
+        return dF
+
+    def cubic_fused(self, u, f, w, cells=None):
+        F = np.zeros(self.n_dofs)
+        gu = np.zeros(self.n_dofs)
+        gf = np.zeros(self.n_dofs)
+        par_loop(FORM_CUBIC_FUSED, self.space, self.num_v, self.num_x, self.X, [u, f, w], [F, gu, gf], cells=cells)
+        return F, gu, gf

@@ -1,0 +1,220 @@
+/*
+ * CPU oracle for the extruded-mesh numbering and column iteration of
+ * Bercea et al., "A structure-exploiting numbering algorithm for finite
+ * elements on extruded meshes" (arXiv 1604.05937).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference the HIP
+ * path is checked against.  It shares no code with the HIP library and must
+ * never be linked into, or called from, the product path.
+ *
+ * Everything here is written for clarity, not speed: FP64 throughout, no
+ * blocking, no fusion, the numbering as a literal counter loop and the cell
+ * loop exactly in the paper's order, with the element integrals evaluated by
+ * quadrature with a full Jacobian at every quadrature point.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared oracle.c -o liboracle.so -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* delta[(d1)*2 + d2] = number of DoFs attached to an extruded entity of type
+ * (d1, d2): d1 the horizontal (base) dimension 0..2, d2 the vertical
+ * dimension 0..1 (Section 3.1.2 entity pairs, Section 3.2). */
+#define DELTA(delta, d1, d2) ((delta)[(d1) * 2 + (d2)])
+
+/*
+ * Algorithm 1 (Section 3.2): vertical-innermost numbering.
+ *
+ * Base entities (d1, i) are visited dimension by dimension (d1 = 0, 1, 2) and
+ * by index within a dimension; for each, the layers l = 0..lam-1 are visited
+ * and, inside a layer, first the horizontal entity (d1, 0) at level l and then
+ * the vertical entity (d1, 1) over interval l receive the next delta numbers;
+ * finally the top horizontal entity (d1, 0) at level lam.
+ *
+ * Output: first_d[d1][(i*(lam+1) + l)*2 + d2] = first DoF number of entity
+ * ((d1, d2), (i, l)), or -1 for the non-existent vertical entity at l = lam.
+ * The entity's DoFs are first .. first + delta - 1.  Returns the DoF count.
+ */
+int64_t oracle_alg1_number(const int32_t counts[3], int32_t lam, const int32_t delta[6],
+                           int64_t* first0, int64_t* first1, int64_t* first2)
+{
+    int64_t* first[3] = {first0, first1, first2};
+    int64_t c = 0;
+    for (int d1 = 0; d1 < 3; ++d1) {
+        for (int64_t i = 0; i < counts[d1]; ++i) {
+            int64_t* f = first[d1] + i * (int64_t)(lam + 1) * 2;
+            for (int32_t l = 0; l < lam; ++l) {
+                for (int d2 = 0; d2 < 2; ++d2) {
+                    f[l * 2 + d2] = c;
+                    c += DELTA(delta, d1, d2);
+                }
+            }
+            f[lam * 2 + 0] = c;
+            c += DELTA(delta, d1, 0);
+            f[lam * 2 + 1] = -1;
+        }
+    }
+    return c;
+}
+
+/*
+ * The stencil of a prism (the explicit list L of Section 3.3): the DoFs of
+ * all entities in the closure of base cell c extruded over one layer.  The
+ * closure entities are taken in the order vertex 0, 1, 2 (cell_vertex order),
+ * edge 0, 1, 2 (edge a opposite vertex a) and the cell itself; for each, its
+ * delta(d,0) DoFs on the bottom horizontal entity, then its delta(d,0) DoFs on
+ * the top horizontal entity, then its delta(d,1) DoFs on the vertical entity.
+ *
+ * Algorithm 2: the vertical offset of stencil position p is
+ * delta(d,0) + delta(d,1), d the base entity dimension of position p.
+ *
+ * Writes L for layer 0 into lmap[c*k + p] (k = stencil size), offsets[p],
+ * entity_dim[p]; returns k.
+ */
+int32_t oracle_stencil(int32_t n_cells, int32_t lam, const int32_t delta[6],
+                       const int32_t* cell_vertex, const int32_t* cell_edge,
+                       const int64_t* first0, const int64_t* first1, const int64_t* first2,
+                       int64_t* lmap, int32_t* offsets, int32_t* entity_dim)
+{
+    const int64_t* first[3] = {first0, first1, first2};
+    int32_t k = 0;
+    /* Algorithm 2 over the stencil layout (same for every cell). */
+    for (int e = 0; e < 7; ++e) {
+        int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+        int n = 2 * DELTA(delta, d, 0) + DELTA(delta, d, 1);
+        for (int j = 0; j < n; ++j) {
+            if (offsets) offsets[k] = DELTA(delta, d, 0) + DELTA(delta, d, 1);
+            if (entity_dim) entity_dim[k] = d;
+            ++k;
+        }
+    }
+    if (!lmap) return k;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        int64_t* row = lmap + c * k;
+        int32_t p = 0;
+        for (int e = 0; e < 7; ++e) {
+            int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+            int64_t i;
+            if (d == 0) i = cell_vertex[c * 3 + e];
+            else if (d == 1) i = cell_edge ? cell_edge[c * 3 + (e - 3)] : -1;
+            else i = c;
+            int nh = DELTA(delta, d, 0), nv = DELTA(delta, d, 1);
+            if (nh + nv == 0) continue;
+            const int64_t* f = first[d] + i * (int64_t)(lam + 1) * 2;
+            for (int j = 0; j < nh; ++j) row[p++] = f[0 * 2 + 0] + j;   /* bottom, level 0 */
+            for (int j = 0; j < nh; ++j) row[p++] = f[1 * 2 + 0] + j;   /* top, level 1 */
+            for (int j = 0; j < nv; ++j) row[p++] = f[0 * 2 + 1] + j;   /* vertical, interval 0 */
+        }
+    }
+    return k;
+}
+
+/* Forms evaluated by the oracle's element kernel. */
+enum {
+    ORACLE_MASS = 1,        /* out0 (+)= int in0 * v                              */
+    ORACLE_CUBIC = 2,       /* out0 += int (in0^3 - in1) v                         */
+    ORACLE_CUBIC_VJP = 3,   /* out0 += int 3 in0^2 in1 v ; out1 += -int in1 v      */
+    ORACLE_CUBIC_JVP = 4,   /* out0 += int (3 in0^2 in1 - in2) v                   */
+    ORACLE_CUBIC_FUSED = 5  /* out0 += int (u^3-f) v; out1 += int 3u^2 w v; out2 += -int w v
+                               with u = in0, f = in1, w = in2                      */
+};
+
+static double det3(const double J[3][3])
+{
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+         - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+         + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/*
+ * Algorithm 3 (Section 3.3): iterate a stencil function over the prisms of
+ * the extruded mesh.  For each base cell, the explicit lists are read once and
+ * then, layer by layer, the kernel is applied and every DoF index is advanced
+ * by its vertical offset.
+ *
+ * Two function spaces are involved, each with its own list (end of Section
+ * 3.3): the coordinate space (P1 x P1, a 3-vector per DoF, stored [dof][xyz])
+ * and the space V of the fields.  The kernel integrates its form with the
+ * quadrature rule (qw, reference points implicit in the tabulations):
+ *   phix[q*6 + p], dphix[(q*6 + p)*3 + r]  coordinate basis and its reference
+ *                                           derivatives d/dxi, d/deta, d/dzeta
+ *   phiv[q*k + p]                           basis of V
+ * and |det J| of the full 3x3 Jacobian at every point.
+ *
+ * cells: the base cells to visit (NULL: all 0..n_iter-1).
+ * write_mode: 1 = WRITE (assign), 0 = INC (add) for the outputs.
+ */
+void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t lam,
+                     const int64_t* mapx, const int32_t* offx, const double* X,
+                     int32_t k, const int64_t* mapv, const int32_t* offv,
+                     const double* in0, const double* in1, const double* in2,
+                     double* out0, double* out1, double* out2, int32_t write_mode,
+                     int32_t nq, const double* qw, const double* phix, const double* dphix,
+                     const double* phiv)
+{
+    int64_t dx[6];
+    int64_t* dv = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+    double* e0 = (double*)malloc(sizeof(double) * (size_t)k);
+    double* e1 = (double*)malloc(sizeof(double) * (size_t)k);
+    double* e2 = (double*)malloc(sizeof(double) * (size_t)k);
+    for (int64_t it = 0; it < n_iter; ++it) {
+        int64_t c = cells ? cells[it] : it;
+        /* (dof_0, ..., dof_{k-1}) <- L(c), for both spaces */
+        for (int p = 0; p < 6; ++p) dx[p] = mapx[c * 6 + p];
+        for (int p = 0; p < k; ++p) dv[p] = mapv[c * k + p];
+        for (int32_t l = 0; l < lam; ++l) {
+            /* S(f(dof_0), ..., f(dof_{k-1})): the element kernel */
+            for (int p = 0; p < k; ++p) e0[p] = e1[p] = e2[p] = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                for (int p = 0; p < 6; ++p)
+                    for (int i = 0; i < 3; ++i)
+                        for (int r = 0; r < 3; ++r)
+                            J[i][r] += X[dx[p] * 3 + i] * dphix[(q * 6 + p) * 3 + r];
+                double w = qw[q] * fabs(det3(J));
+                double a = 0.0, b = 0.0, g = 0.0;
+                for (int p = 0; p < k; ++p) {
+                    double ph = phiv[q * k + p];
+                    if (in0) a += in0[dv[p]] * ph;
+                    if (in1) b += in1[dv[p]] * ph;
+                    if (in2) g += in2[dv[p]] * ph;
+                }
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+                switch (form) {
+                case ORACLE_MASS: s0 = a; break;
+                case ORACLE_CUBIC: s0 = a * a * a - b; break;
+                case ORACLE_CUBIC_VJP: s0 = 3.0 * a * a * b; s1 = -b; break;
+                case ORACLE_CUBIC_JVP: s0 = 3.0 * a * a * b - g; break;
+                case ORACLE_CUBIC_FUSED: s0 = a * a * a - b; s1 = 3.0 * a * a * g; s2 = -g; break;
+                default: break;
+                }
+                for (int p = 0; p < k; ++p) {
+                    double ph = phiv[q * k + p];
+                    e0[p] += w * s0 * ph;
+                    e1[p] += w * s1 * ph;
+                    e2[p] += w * s2 * ph;
+                }
+            }
+            for (int p = 0; p < k; ++p) {
+                if (write_mode) {
+                    if (out0) out0[dv[p]] = e0[p];
+                    if (out1) out1[dv[p]] = e1[p];
+                    if (out2) out2[dv[p]] = e2[p];
+                } else {
+                    if (out0) out0[dv[p]] += e0[p];
+                    if (out1) out1[dv[p]] += e1[p];
+                    if (out2) out2[dv[p]] += e2[p];
+                }
+            }
+            /* dof_j <- dof_j + offset(j) */
+            for (int p = 0; p < 6; ++p) dx[p] += offx[p];
+            for (int p = 0; p < k; ++p) dv[p] += offv[p];
+        }
+    }
+    free(dv);
+    free(e0);
+    free(e1);
+    free(e2);
+}

@@ -1,0 +1,102 @@
+"""Pins of the oracle's numbering (Algorithm 1), explicit lists and offsets
+(Algorithm 2) and direct addressing (the n-th application formula of Section
+3.3) against a brute-force numbering of the explicit 3D mesh."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_05937_amd import meshgen
+from tests import bruteforce
+
+SPACES = [("CG1", "CG1"), ("DG0", "DG0"), ("DG1", "DG1"), ("CG2", "CG2"),
+          ("CG1", "DG0"), ("CG1", "DG1"), ("DG0", "CG1"), ("DG0", "DG1"),
+          ("DG1", "CG1"), ("DG1", "DG0")]
+
+
+@pytest.mark.parametrize("space", SPACES)
+@pytest.mark.parametrize("order", ["rcm", "random"])
+def test_numbering_matches_bruteforce(space, order):
+    mesh = meshgen.tri_square(3, order=order)
+    lam = 3
+    delta = oracle.delta_table(*space)
+    num = oracle.number(mesh.counts, lam, delta, mesh.cell_vertex, mesh.cell_edge)
+    n, first, stencils, entities = bruteforce.bruteforce_numbering(mesh, lam, delta)
+    assert num.n_dofs == n
+    # every entity of the explicit 3D mesh gets the same first DoF
+    for ((d1, d2), i, l), f in first.items():
+        assert num.first[d1][i, l, d2] == f
+    # every prism's stencil is L(c) + l * offset (Section 3.3, n-th application)
+    for (c, l), row in stencils.items():
+        np.testing.assert_array_equal(num.lmap[c] + l * num.offsets, row)
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_entity_set_sizes_and_bijection(space):
+    mesh = meshgen.tri_square(4)
+    lam = 5
+    delta = oracle.delta_table(*space)
+    num = oracle.number(mesh.counts, lam, delta, mesh.cell_vertex, mesh.cell_edge)
+    # |V_{d1,d2}| = N_d1 (lam + 1 - d2) (Section 3.1.3); the DoF count follows
+    expect = sum(mesh.counts[d1] * (lam + 1 - d2) * delta[d1, d2] for d1 in range(3) for d2 in range(2))
+    assert num.n_dofs == expect
+    # DoFs form a bijection onto [0, n_dofs)
+    seen = np.zeros(num.n_dofs, dtype=np.int64)
+    for d1 in range(3):
+        for d2 in range(2):
+            nd = int(delta[d1, d2])
+            for i in range(mesh.counts[d1]):
+                for l in range(lam + 1 - d2):
+                    f = num.first[d1][i, l, d2]
+                    seen[f:f + nd] += 1
+    assert np.all(seen == 1)
+
+
+def test_vertically_adjacent_entities_have_adjacent_numbers():
+    # Section 3.2: DoFs of vertically adjacent entities have adjacent numbers,
+    # i.e. each entity column is one contiguous block walked bottom to top.
+    mesh = meshgen.tri_square(3)
+    lam = 4
+    delta = oracle.delta_table("CG2", "CG2")
+    num = oracle.number(mesh.counts, lam, delta, mesh.cell_vertex, mesh.cell_edge)
+    for d1 in range(2):
+        for i in range(mesh.counts[d1]):
+            seq = []
+            for l in range(lam + 1):
+                for d2 in range(2 if l < lam else 1):
+                    f = num.first[d1][i, l, d2]
+                    seq += list(range(f, f + int(delta[d1, d2])))
+            assert seq == list(range(seq[0], seq[0] + len(seq)))
+
+
+@pytest.mark.parametrize("space,k,off", [
+    (("CG1", "CG1"), 6, 1), (("DG0", "DG0"), 1, 1), (("DG1", "DG1"), 6, 6), (("CG2", "CG2"), 18, 2),
+    (("CG1", "DG0"), 3, 1), (("CG1", "DG1"), 6, 2), (("DG0", "CG1"), 2, 1), (("DG0", "DG1"), 2, 2),
+    (("DG1", "CG1"), 6, 3), (("DG1", "DG0"), 3, 3)])
+def test_stencil_sizes_and_offsets(space, k, off):
+    # DoFs per cell 1/2/3/6 for the nine low-order pairs (Section 4.3), 18 for
+    # P2 x P2; Algorithm 2 gives delta(d,0) + delta(d,1) for every position.
+    mesh = meshgen.tri_square(2)
+    num = oracle.number(mesh.counts, 2, oracle.delta_table(*space), mesh.cell_vertex, mesh.cell_edge)
+    assert num.k == k
+    assert np.all(num.offsets == off)
+
+
+def test_lists_reduce_by_lambda():
+    # Section 3.3: one explicit list per column instead of one per layer.
+    mesh = meshgen.tri_square(3)
+    for lam in (1, 2, 7):
+        num = oracle.number(mesh.counts, lam, oracle.delta_table("CG1", "CG1"), mesh.cell_vertex, mesh.cell_edge)
+        assert num.lmap.shape == (mesh.n_cells, 6)
+
+
+def test_p1_row_layout():
+    # P1 x P1: column of vertex v starts at v (lam + 1); the row of a cell is
+    # (S(v0), S(v0)+1, S(v1), S(v1)+1, S(v2), S(v2)+1).
+    mesh = meshgen.tri_square(3)
+    lam = 4
+    num = oracle.number(mesh.counts, lam, oracle.delta_table("CG1", "CG1"), mesh.cell_vertex, mesh.cell_edge)
+    S = num.column_starts(0)
+    np.testing.assert_array_equal(S, np.arange(mesh.n_vertices) * (lam + 1))
+    for c in range(mesh.n_cells):
+        v = mesh.cell_vertex[c]
+        np.testing.assert_array_equal(num.lmap[c], [S[v[0]], S[v[0]] + 1, S[v[1]], S[v[1]] + 1, S[v[2]], S[v[2]] + 1])
