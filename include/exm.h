@@ -1,0 +1,255 @@
+/*
+ * exm -- extruded-mesh numbering and column iteration for AMD MI355X (gfx950).
+ *
+ * C ABI of libexm.so.  The operations follow the statement of the method in
+ * Bercea et al., "A structure-exploiting numbering algorithm for finite
+ * elements on extruded meshes, and its performance evaluation in Firedrake"
+ * (arXiv 1604.05937):
+ *   - an extruded mesh is an unstructured 2D base mesh replicated over
+ *     lambda layers of prisms (Section 3.1);
+ *   - a function space attaches delta((d1, d2)) DoFs to every extruded entity
+ *     of type (d1, d2) and numbers them vertical-innermost (Algorithm 1);
+ *   - a stencil over the prisms is given by one explicit list per base cell
+ *     plus a constant vertical offset per list position (Algorithm 2), and the
+ *     iteration walks every column by direct addressing (Algorithm 3).
+ *
+ * Conventions shared by every entry point:
+ *   - Integers are int32 unless stated; DoF numbers and map entries are int32
+ *     (a space with 2^31 or more DoFs is rejected with EXM_EOVERFLOW).
+ *   - "host" pointers are read during the call only; the library copies what
+ *     it keeps.  "device" pointers are HIP device memory owned by the caller
+ *     and must stay valid until the stream work that uses them has finished.
+ *   - Field data is FP64.  A vector field of dimension dim stores component
+ *     i of DoF n at data[n * dim + i].
+ *   - Every entry point validates its arguments on the host before any device
+ *     work and returns a negative status with a message for exm_last_error()
+ *     on failure; nothing is launched then.  Errors raised by asynchronous
+ *     device work surface as EXM_EHIP from a later call or from exm_sync().
+ *   - Work is enqueued on the HIP stream passed as `stream` (NULL = the
+ *     default stream).  Handles are not thread-safe.
+ *   - Base-mesh conventions: cell_vertex lists the three vertices of each
+ *     triangle; cell_edge[c*3 + a] is the edge opposite local vertex a, i.e.
+ *     the edge joining vertices (a+1)%3 and (a+2)%3.
+ */
+#ifndef EXM_H
+#define EXM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EXM_ABI_VERSION 1
+
+/* Status codes. */
+#define EXM_OK 0
+#define EXM_EINVAL (-1)        /* malformed argument (null pointer, bad enum, mismatch)   */
+#define EXM_ERANGE (-2)        /* an index or count outside its valid range               */
+#define EXM_EOVERFLOW (-3)     /* a size that does not fit the int32 numbering            */
+#define EXM_ENOMEM (-4)        /* device or host allocation failed                        */
+#define EXM_EHIP (-5)          /* a HIP runtime call or an earlier launch failed          */
+#define EXM_EUNSUPPORTED (-6)  /* valid request that this library does not implement      */
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char* exm_last_error(void);
+
+/* EXM_ABI_VERSION of the loaded library. */
+int32_t exm_abi_version(void);
+
+/* Wait for all work on `stream` and report any asynchronous device error. */
+int32_t exm_sync(void* stream);
+
+/* ------------------------------------------------------------------------
+ * Extruded mesh (Section 3.1): base mesh adjacency + number of layers.
+ *
+ * n_vertices, n_edges, n_cells: N_0, N_1, N_2 of the triangular base mesh.
+ * cell_vertex: host [n_cells * 3]; every entry in [0, n_vertices).
+ * cell_edge:   host [n_cells * 3] or NULL (needed only by spaces with DoFs on
+ *              edges); every entry in [0, n_edges) and consistent with
+ *              cell_vertex is NOT checked beyond range.
+ * n_layers:    lambda >= 1, the number of layers (prisms per column).
+ * The arrays are copied to the current HIP device.  Returns the handle in
+ * *out (library-owned; free with exm_mesh_destroy).
+ */
+typedef struct exm_mesh exm_mesh;
+int32_t exm_mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
+                        const int32_t* cell_vertex, const int32_t* cell_edge,
+                        int32_t n_layers, exm_mesh** out);
+void exm_mesh_destroy(exm_mesh* mesh);
+
+/* ------------------------------------------------------------------------
+ * Function space: the vertical-innermost numbering of Algorithm 1 and the
+ * explicit lists and offsets of Algorithms 2-3.
+ *
+ * delta: host [6], delta[d1*2 + d2] = DoFs on each extruded entity of type
+ *        (d1, d2) (d1 = 0 vertex, 1 edge, 2 cell of the base; d2 = 0
+ *        horizontal, 1 vertical).  Entries >= 0 and at most 64.
+ * element: the local element the space's DoFs belong to, which the element
+ *        kernels of exm_par_loop need (EXM_ELEMENT_NONE = numbering only).
+ *        A named element requires the delta table it implies.
+ *
+ * Numbering (a reading where the paper leaves the order open): base entities
+ * are visited dimension-major (d1 = 0, 1, 2), then by index; within an
+ * entity with several DoFs, horizontal node index major, vertical minor.
+ * The explicit list L(c) of base cell c lists its closure entities in the
+ * order vertex 0, 1, 2, edge 0, 1, 2, cell; for each, its delta(d,0) DoFs on
+ * the bottom horizontal entity, its delta(d,0) DoFs on the top horizontal
+ * entity, then its delta(d,1) DoFs on the vertical entity, all for layer 0.
+ * Its length is the arity k.  Layer l uses L(c)[p] + l * offset[p] with
+ * offset[p] = delta(d,0) + delta(d,1), d the entity dimension of position p.
+ *
+ * The numbering is built on the device (kernels on `stream`).  The space
+ * keeps a reference to `mesh`, which must outlive it.
+ */
+#define EXM_ELEMENT_NONE 0
+#define EXM_ELEMENT_P1P1 1     /* CG1 x CG1, delta(0,0) = 1, arity 6            */
+#define EXM_ELEMENT_DG0DG0 2   /* DG0 x DG0, delta(2,1) = 1, arity 1            */
+#define EXM_ELEMENT_DG1DG1 3   /* DG1 x DG1, delta(2,1) = 6, arity 6            */
+#define EXM_ELEMENT_P2P2 4     /* CG2 x CG2, delta(0,*) = delta(1,*) = 1, arity 18 */
+
+typedef struct exm_space exm_space;
+int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t element,
+                         void* stream, exm_space** out);
+/* n_dofs (may be NULL) and arity k (may be NULL). */
+int32_t exm_space_info(const exm_space* space, int64_t* n_dofs, int32_t* arity);
+/* offsets: host [k] (Algorithm 2). */
+int32_t exm_space_offsets(const exm_space* space, int32_t* offsets);
+/* dst: device [N_d1], first DoF of the column of every base entity of
+ * dimension d1 (-1 where the space has no DoFs on that column). */
+int32_t exm_space_column_starts(const exm_space* space, int32_t d1, int32_t* dst, void* stream);
+/* dst: device [n_cells * k], the explicit lists L(c) of layer 0, row-major. */
+int32_t exm_space_bottom_map(const exm_space* space, int32_t* dst, void* stream);
+void exm_space_destroy(exm_space* space);
+
+/* ------------------------------------------------------------------------
+ * Parallel loop over the prisms of an extruded mesh (Algorithm 3) applying a
+ * local element kernel.
+ *
+ * Every kernel takes as args[0] the coordinate field: a P1 x P1 space
+ * (EXM_ELEMENT_P1P1) on the same mesh, dim 3, EXM_READ.  Prisms must have
+ * vertical columns: the (x, y) of a base vertex is the same at every level
+ * (z is free, so terrain-following layers are allowed); the kernels integrate
+ * exactly under that assumption and do not check it.
+ *
+ *   EXM_K_MASS       y = M x, i.e. y_i = integral of x_h v_i, the residual of
+ *                    Section 4.1.1 (args: X, x READ, y).  Elements P1P1,
+ *                    DG0DG0, DG1DG1, P2P2.  y is EXM_INC for continuous
+ *                    spaces, EXM_WRITE or EXM_INC for DG spaces.  The adjoint
+ *                    of this linear residual with respect to x is the same
+ *                    call with the cotangent as x (M is symmetric).
+ *   EXM_K_CUBIC      F_i = integral (u^3 - f) v_i  (args: X, u, f READ, F INC), P1P1.
+ *   EXM_K_CUBIC_VJP  g_u,i = integral 3 u^2 w v_i, g_f,i = -integral w v_i
+ *                    (args: X, u, w READ, g_u INC, g_f INC), P1P1.
+ *   EXM_K_CUBIC_FUSED  F, g_u, g_f in one sweep
+ *                    (args: X, u, f, w READ, F INC, g_u INC, g_f INC), P1P1.
+ *
+ * INC adds into the caller's buffer (zero it first for a plain assembly);
+ * WRITE overwrites every DoF of the space.  All field args of one call must
+ * be distinct buffers, all on one space.  Floating-point results may differ in
+ * the last bits between race strategies (different summation order).
+ */
+#define EXM_READ 1
+#define EXM_WRITE 2
+#define EXM_INC 3
+
+#define EXM_K_MASS 1
+#define EXM_K_CUBIC 2
+#define EXM_K_CUBIC_VJP 3
+#define EXM_K_CUBIC_FUSED 4
+
+typedef struct {
+    void* data;               /* device FP64 [n_dofs * dim]               */
+    const exm_space* space;   /* space the field lives on                 */
+    int32_t dim;              /* components per DoF                       */
+    int32_t access;           /* EXM_READ / EXM_WRITE / EXM_INC           */
+} exm_arg;
+
+/* Race resolution for INC into continuous spaces, where base cells share
+ * DoF columns horizontally. */
+#define EXM_RACE_AUTO 0       /* library choice (autotuned if available)            */
+#define EXM_RACE_ATOMIC 1     /* hardware FP64 atomic adds, one launch             */
+#define EXM_RACE_COLOUR 2     /* base cells greedily coloured (no shared vertex),   */
+                              /* one launch per colour with plain read-add-write   */
+
+typedef struct {
+    int32_t race;              /* EXM_RACE_*                                        */
+    int32_t cols_per_wave;     /* base-cell columns side by side in one wavefront;  */
+                               /* each gets 64 / cols_per_wave lanes, one layer per  */
+                               /* lane (0 = choose)                                 */
+    int32_t waves_per_block;   /* wavefronts per workgroup, 1..16 (0 = choose)      */
+    int32_t reserved;
+} exm_loop_opts;
+
+/* opts may be NULL (all defaults). */
+int32_t exm_par_loop(int32_t kernel, const exm_mesh* iterset, int32_t nargs, const exm_arg* args,
+                     const exm_loop_opts* opts, void* stream);
+
+/* The launch configuration exm_par_loop uses for these arguments when opts is
+ * NULL or has zero fields (filled into *chosen). */
+int32_t exm_par_loop_config(int32_t kernel, const exm_mesh* iterset, int32_t nargs, const exm_arg* args,
+                            const exm_loop_opts* opts, exm_loop_opts* chosen);
+
+/* Number of colours of the base-cell colouring used by EXM_RACE_COLOUR for
+ * this space (builds it if needed). */
+int32_t exm_mesh_colours(const exm_mesh* mesh, int32_t* n_colours);
+
+/* ------------------------------------------------------------------------
+ * Autotuner: times the candidate launch configurations of `kernel` on these
+ * arguments (outputs are written to scratch copies, the caller's buffers are
+ * not modified) and records the fastest for the (kernel, element, layer
+ * count, cell count) bucket in the process-wide table used when opts is NULL.
+ * The choice is returned in *best (may be NULL).  Synchronises `stream`.
+ */
+int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, const exm_arg* args,
+                     void* stream, exm_loop_opts* best);
+/* Save / load the tuning table as text (one entry per line). */
+int32_t exm_autotune_save(const char* path);
+int32_t exm_autotune_load(const char* path);
+
+/* ------------------------------------------------------------------------
+ * Batched assembly: many extruded meshes, several fields per mesh, forward
+ * residual (EXM_K_MASS) plus its adjoint, in one persistent launch captured
+ * in a HIP graph.
+ *
+ * Item m: a space (EXM_ELEMENT_P1P1 or EXM_ELEMENT_DG0DG0) and its coordinate
+ * field on the same mesh; n_fields inputs f[j] with outputs b[j] = M f[j], and
+ * optionally cotangents w[j] with adjoint outputs g[j] = M^T w[j] = M w[j].
+ * Pointer arrays are host arrays of device pointers (copied at create).
+ * Outputs are overwritten (the launch zeroes continuous-space outputs itself).
+ * The meshes, spaces and buffers must outlive the batch.
+ */
+typedef struct {
+    const exm_space* space;
+    const exm_space* coord_space;
+    const double* coords;
+    int32_t n_fields;
+    const double* const* f;   /* [n_fields] */
+    double* const* b;         /* [n_fields] */
+    const double* const* w;   /* [n_fields] or NULL */
+    double* const* g;         /* [n_fields] or NULL (NULL iff w is NULL) */
+} exm_batch_item;
+
+typedef struct exm_batch exm_batch;
+/* opts may be NULL; opts->cols_per_wave applies to every item when set. */
+int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm_loop_opts* opts,
+                         void* stream, exm_batch** out);
+/* Replay the captured graph on `stream`. */
+int32_t exm_batch_launch(exm_batch* batch, void* stream);
+/* Work units (cell groups) and persistent workgroups of the batch. */
+int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_blocks);
+void exm_batch_destroy(exm_batch* batch);
+
+/* ------------------------------------------------------------------------
+ * STREAM triad a_i = b_i + alpha c_i (FP64), the bandwidth yardstick of
+ * Section 4.2.1.  block: threads per workgroup (64..1024, multiple of 64);
+ * grid: workgroups (0 = one element per thread).  All three arrays device
+ * [n], distinct.
+ */
+int32_t exm_stream_triad(double* a, const double* b, const double* c, double alpha, int64_t n,
+                         int32_t block, int32_t grid, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXM_H */

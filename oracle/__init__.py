@@ -47,6 +47,9 @@ FORM_CUBIC = 2
 FORM_CUBIC_VJP = 3
 FORM_CUBIC_JVP = 4
 FORM_CUBIC_FUSED = 5
+FORM_MASS_ABS = 6
+FORM_CUBIC_ABS = 7
+FORM_VJP_ABS = 8
 
 
 def build(force: bool = True) -> str:
@@ -215,7 +218,7 @@ _DEG_H = {"CG1": 1, "CG2": 2, "DG0": 0, "DG1": 1}
 
 def rule_for(form: int, h: str, v: str):
     dh, dv = _DEG_H[h], _DEG_V[v]
-    if form == FORM_MASS:
+    if form in (FORM_MASS, FORM_MASS_ABS):
         nh, nv = 2 * dh + 1, 2 * dv
     else:  # cubic family: four field factors times a test function
         nh, nv = 4 * dh + 1, 4 * dv
@@ -254,7 +257,9 @@ def number(counts, n_layers: int, delta, cell_vertex, cell_edge=None) -> Numberi
     delta = np.ascontiguousarray(np.asarray(delta, dtype=np.int32).reshape(3, 2))
     if n_layers < 1:
         raise ValueError("need at least one layer")
-    first = [np.full((int(counts[d]), n_layers + 1, 2), -1, dtype=np.int64) for d in range(3)]
+    # dimensions without DoFs get no table (the counter loop still visits them)
+    first = [np.full((int(counts[d]), n_layers + 1, 2), -1, dtype=np.int64) if delta[d].sum() else None
+             for d in range(3)]
     n_dofs = lib.oracle_alg1_number(_ptr(counts), n_layers, _ptr(delta), _ptr(first[0]), _ptr(first[1]), _ptr(first[2]))
     k = lib.oracle_stencil(0, n_layers, _ptr(delta), None, None, None, None, None, None, None, None)
     offsets = np.zeros(k, dtype=np.int32)
@@ -371,6 +376,25 @@ class Problem:
         dF = np.zeros(self.n_dofs)
         par_loop(FORM_CUBIC_JVP, self.space, self.num_v, self.num_x, self.X, [u, du, df], [dF], cells=cells)
         return dF
+
+    def mass_abs(self, x, cells=None):
+        """Integral of |x_h| |v_i| with |.| on every factor: the scale of the
+        rounding error of any summation order of mass(x)."""
+        y = np.zeros(self.n_dofs)
+        par_loop(FORM_MASS_ABS, self.space, self.num_v, self.num_x, self.X, [x], [y],
+                 write=not is_continuous(self.space), cells=cells)
+        return y
+
+    def cubic_abs(self, u, f, cells=None):
+        y = np.zeros(self.n_dofs)
+        par_loop(FORM_CUBIC_ABS, self.space, self.num_v, self.num_x, self.X, [u, f], [y], cells=cells)
+        return y
+
+    def vjp_abs(self, u, w, cells=None):
+        a = np.zeros(self.n_dofs)
+        b = np.zeros(self.n_dofs)
+        par_loop(FORM_VJP_ABS, self.space, self.num_v, self.num_x, self.X, [u, w], [a, b], cells=cells)
+        return a, b
 
     def cubic_fused(self, u, f, w, cells=None):
         F = np.zeros(self.n_dofs)

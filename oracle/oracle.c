@@ -44,16 +44,17 @@ int64_t oracle_alg1_number(const int32_t counts[3], int32_t lam, const int32_t d
     int64_t c = 0;
     for (int d1 = 0; d1 < 3; ++d1) {
         for (int64_t i = 0; i < counts[d1]; ++i) {
-            int64_t* f = first[d1] + i * (int64_t)(lam + 1) * 2;
+            /* a NULL table (a dimension without DoFs) still advances the counter */
+            int64_t* f = first[d1] ? first[d1] + i * (int64_t)(lam + 1) * 2 : NULL;
             for (int32_t l = 0; l < lam; ++l) {
                 for (int d2 = 0; d2 < 2; ++d2) {
-                    f[l * 2 + d2] = c;
+                    if (f) f[l * 2 + d2] = c;
                     c += DELTA(delta, d1, d2);
                 }
             }
-            f[lam * 2 + 0] = c;
+            if (f) f[lam * 2 + 0] = c;
             c += DELTA(delta, d1, 0);
-            f[lam * 2 + 1] = -1;
+            if (f) f[lam * 2 + 1] = -1;
         }
     }
     return c;
@@ -117,8 +118,14 @@ enum {
     ORACLE_CUBIC = 2,       /* out0 += int (in0^3 - in1) v                         */
     ORACLE_CUBIC_VJP = 3,   /* out0 += int 3 in0^2 in1 v ; out1 += -int in1 v      */
     ORACLE_CUBIC_JVP = 4,   /* out0 += int (3 in0^2 in1 - in2) v                   */
-    ORACLE_CUBIC_FUSED = 5  /* out0 += int (u^3-f) v; out1 += int 3u^2 w v; out2 += -int w v
+    ORACLE_CUBIC_FUSED = 5, /* out0 += int (u^3-f) v; out1 += int 3u^2 w v; out2 += -int w v
                                with u = in0, f = in1, w = in2                      */
+    /* Magnitude forms: the same sums with every factor replaced by its absolute
+     * value.  They bound the rounding error of any summation order of the
+     * corresponding form and scale the componentwise parity tolerance. */
+    ORACLE_MASS_ABS = 6,    /* out0 += int |in0| |v|                               */
+    ORACLE_CUBIC_ABS = 7,   /* out0 += int (|in0|^3 + |in1|) |v|                   */
+    ORACLE_VJP_ABS = 8      /* out0 += int 3 in0^2 |in1| |v| ; out1 += int |in1| |v| */
 };
 
 static double det3(const double J[3][3])
@@ -175,11 +182,12 @@ void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t
                             J[i][r] += X[dx[p] * 3 + i] * dphix[(q * 6 + p) * 3 + r];
                 double w = qw[q] * fabs(det3(J));
                 double a = 0.0, b = 0.0, g = 0.0;
+                const int absf = form >= ORACLE_MASS_ABS;
                 for (int p = 0; p < k; ++p) {
-                    double ph = phiv[q * k + p];
-                    if (in0) a += in0[dv[p]] * ph;
-                    if (in1) b += in1[dv[p]] * ph;
-                    if (in2) g += in2[dv[p]] * ph;
+                    double ph = absf ? fabs(phiv[q * k + p]) : phiv[q * k + p];
+                    if (in0) a += (absf ? fabs(in0[dv[p]]) : in0[dv[p]]) * ph;
+                    if (in1) b += (absf ? fabs(in1[dv[p]]) : in1[dv[p]]) * ph;
+                    if (in2) g += (absf ? fabs(in2[dv[p]]) : in2[dv[p]]) * ph;
                 }
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0;
                 switch (form) {
@@ -188,10 +196,13 @@ void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t
                 case ORACLE_CUBIC_VJP: s0 = 3.0 * a * a * b; s1 = -b; break;
                 case ORACLE_CUBIC_JVP: s0 = 3.0 * a * a * b - g; break;
                 case ORACLE_CUBIC_FUSED: s0 = a * a * a - b; s1 = 3.0 * a * a * g; s2 = -g; break;
+                case ORACLE_MASS_ABS: s0 = a; break;
+                case ORACLE_CUBIC_ABS: s0 = a * a * a + b; break;
+                case ORACLE_VJP_ABS: s0 = 3.0 * a * a * b; s1 = b; break;
                 default: break;
                 }
                 for (int p = 0; p < k; ++p) {
-                    double ph = phiv[q * k + p];
+                    double ph = absf ? fabs(phiv[q * k + p]) : phiv[q * k + p];
                     e0[p] += w * s0 * ph;
                     e1[p] += w * s1 * ph;
                     e2[p] += w * s2 * ph;

@@ -1,0 +1,197 @@
+"""exm: extruded-mesh numbering and column iteration on AMD MI355X.
+
+Python face of libexm.so (hand-written HIP for gfx950).  The classes here hold
+library handles and marshal torch tensors (device memory) and torch streams
+into the C ABI; all numbering and assembly work runs in the library.  There is
+no CPU fallback: without the built library every call raises.
+
+Method: Bercea et al., arXiv 1604.05937 -- vertical-innermost numbering
+(Algorithm 1), vertical offsets (Algorithm 2), column iteration by direct
+addressing (Algorithm 3).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import (EXM_ELEMENT_DG0DG0, EXM_ELEMENT_DG1DG1, EXM_ELEMENT_NONE, EXM_ELEMENT_P1P1, EXM_ELEMENT_P2P2,
+                   EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_VJP, EXM_K_MASS, EXM_RACE_ATOMIC,
+                   EXM_RACE_AUTO, EXM_RACE_COLOUR, EXM_READ, EXM_WRITE, ExmError)
+
+__all__ = ["Mesh", "Space", "par_loop", "ExmError", "ELEMENTS", "DELTA", "load_library", "stream_handle"]
+
+# delta((d1, d2)) tables, flattened as d1 * 2 + d2 (Section 3.2)
+DELTA = {
+    EXM_ELEMENT_P1P1: (1, 0, 0, 0, 0, 0),
+    EXM_ELEMENT_DG0DG0: (0, 0, 0, 0, 0, 1),
+    EXM_ELEMENT_DG1DG1: (0, 0, 0, 0, 0, 6),
+    EXM_ELEMENT_P2P2: (1, 1, 1, 1, 0, 0),
+}
+ELEMENTS = {"P1": EXM_ELEMENT_P1P1, "DG0": EXM_ELEMENT_DG0DG0, "DG1": EXM_ELEMENT_DG1DG1, "P2": EXM_ELEMENT_P2P2}
+
+
+def load_library():
+    return _abi.load()
+
+
+def stream_handle(stream=None) -> int | None:
+    """Raw HIP stream handle of a torch stream (default: the current stream)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Mesh:
+    """An extruded mesh: triangular base mesh (cell->vertex, cell->edge) and
+    a layer count.  Wraps exm_mesh."""
+
+    def __init__(self, base, n_layers: int):
+        _abi.load()
+        self.base = base
+        self.n_layers = int(n_layers)
+        cv = _i32(base.cell_vertex)
+        ce = _i32(base.cell_edge) if getattr(base, "cell_edge", None) is not None else None
+        h = ctypes.c_void_p()
+        _abi.exm_mesh_create(int(base.n_vertices), int(base.n_edges), int(base.n_cells),
+                             cv.ctypes.data_as(ctypes.c_void_p),
+                             None if ce is None else ce.ctypes.data_as(ctypes.c_void_p),
+                             self.n_layers, ctypes.byref(h))
+        self.handle = h
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.base.n_cells)
+
+    def colours(self) -> int:
+        n = ctypes.c_int32()
+        _abi.exm_mesh_colours(self.handle, ctypes.byref(n))
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _abi is not None and _abi._lib is not None:
+            _abi._lib.exm_mesh_destroy(h)
+        self.handle = None
+
+
+class Space:
+    """A function space on an extruded mesh (numbering of Algorithm 1, lists
+    and offsets of Algorithm 2).  Wraps exm_space; built on the device."""
+
+    def __init__(self, mesh: Mesh, element, delta=None, stream=None):
+        if isinstance(element, str):
+            element = ELEMENTS[element]
+        self.mesh = mesh
+        self.element = element
+        d = np.asarray(delta if delta is not None else DELTA[element], dtype=np.int32).reshape(6)
+        self.delta = d
+        h = ctypes.c_void_p()
+        _abi.exm_space_create(mesh.handle, d.ctypes.data_as(ctypes.c_void_p), int(element),
+                              stream_handle(stream), ctypes.byref(h))
+        self.handle = h
+        n = ctypes.c_int64()
+        k = ctypes.c_int32()
+        _abi.exm_space_info(h, ctypes.byref(n), ctypes.byref(k))
+        self.n_dofs = n.value
+        self.arity = k.value
+
+    def offsets(self) -> np.ndarray:
+        out = np.zeros(self.arity, dtype=np.int32)
+        _abi.exm_space_offsets(self.handle, out.ctypes.data_as(ctypes.c_void_p))
+        return out
+
+    def column_starts(self, d1: int, stream=None):
+        import torch
+        n = [self.mesh.base.n_vertices, self.mesh.base.n_edges, self.mesh.base.n_cells][d1]
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        _abi.exm_space_column_starts(self.handle, d1, ctypes.c_void_p(out.data_ptr()), stream_handle(stream))
+        return out
+
+    def bottom_map(self, stream=None):
+        import torch
+        out = torch.empty((self.mesh.n_cells, self.arity), dtype=torch.int32, device="cuda")
+        _abi.exm_space_bottom_map(self.handle, ctypes.c_void_p(out.data_ptr()), stream_handle(stream))
+        return out
+
+    def zeros(self, dim: int = 1):
+        import torch
+        shape = (self.n_dofs,) if dim == 1 else (self.n_dofs, dim)
+        return torch.zeros(shape, dtype=torch.float64, device="cuda")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _abi is not None and _abi._lib is not None:
+            _abi._lib.exm_space_destroy(h)
+        self.handle = None
+
+
+def coordinate_field(space: Space, vertex_coords: np.ndarray):
+    """Coordinate field [n_dofs, 3] (FP64, device) of a P1 x P1 space from
+    per-vertex, per-level coordinates [N0, lambda+1, 3]: the value of extruded
+    vertex (v, l) goes to DoF S(v) + l, S the column starts the library built."""
+    import torch
+    assert space.element == EXM_ELEMENT_P1P1
+    starts = space.column_starts(0).cpu().numpy().astype(np.int64)
+    nl = vertex_coords.shape[1]
+    host = np.zeros((space.n_dofs, 3))
+    host[(starts[:, None] + np.arange(nl)[None, :]).ravel()] = vertex_coords.reshape(-1, 3)
+    return torch.from_numpy(host).to("cuda")
+
+
+def _arg(t, space: Space, access: int, dim: int = 1) -> _abi.exm_arg:
+    import torch
+    assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous(), "fields are contiguous FP64 device tensors"
+    assert t.numel() == space.n_dofs * dim, "field size does not match its space"
+    return _abi.exm_arg(ctypes.c_void_p(t.data_ptr()), space.handle, dim, access)
+
+
+def make_args(coords, coord_space: Space, fields):
+    """exm_arg array: coordinates first, then (tensor, space, access) triples."""
+    arr = (_abi.exm_arg * (1 + len(fields)))()
+    arr[0] = _arg(coords, coord_space, EXM_READ, 3)
+    for i, (t, sp, acc) in enumerate(fields):
+        arr[1 + i] = _arg(t, sp, acc)
+    return arr
+
+
+def loop_opts(race: int = 0, cols_per_wave: int = 0, waves_per_block: int = 0):
+    return _abi.exm_loop_opts(race, cols_per_wave, waves_per_block, 0)
+
+
+def par_loop(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, race: int = 0, cols_per_wave: int = 0,
+             waves_per_block: int = 0, stream=None):
+    """exm_par_loop on the current torch stream."""
+    args = make_args(coords, coord_space, fields)
+    opts = loop_opts(race, cols_per_wave, waves_per_block)
+    _abi.exm_par_loop(kernel, mesh.handle, len(args), args, ctypes.byref(opts), stream_handle(stream))
+
+
+def par_loop_config(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, race: int = 0,
+                    cols_per_wave: int = 0, waves_per_block: int = 0):
+    args = make_args(coords, coord_space, fields)
+    opts = loop_opts(race, cols_per_wave, waves_per_block)
+    ch = _abi.exm_loop_opts()
+    _abi.exm_par_loop_config(kernel, mesh.handle, len(args), args, ctypes.byref(opts), ctypes.byref(ch))
+    return ch.race, ch.cols_per_wave, ch.waves_per_block
+
+
+def autotune(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, stream=None):
+    args = make_args(coords, coord_space, fields)
+    best = _abi.exm_loop_opts()
+    _abi.exm_autotune(kernel, mesh.handle, len(args), args, stream_handle(stream), ctypes.byref(best))
+    return best.race, best.cols_per_wave, best.waves_per_block
+
+
+def sync(stream=None):
+    _abi.exm_sync(stream_handle(stream))
+
+
+def stream_triad(a, b, c, alpha: float, block: int = 256, grid: int = 0, stream=None):
+    _abi.exm_stream_triad(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                          float(alpha), a.numel(), block, grid, stream_handle(stream))

@@ -1,0 +1,356 @@
+// Handles, validation and the numbering builder (Algorithms 1 and 2) of
+// libexm.so, plus the base-cell colouring and the STREAM triad.
+#include <algorithm>
+#include <cstring>
+
+#include "exm_internal.hpp"
+
+namespace exm {
+
+static thread_local std::string g_error;
+
+int32_t fail(int32_t code, const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+void clear_error() { g_error.clear(); }
+
+int32_t check_pending()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(EXM_EHIP, "earlier device work failed: %s", hipGetErrorString(e));
+    return EXM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Numbering kernels.
+//
+// With a constant layer count the counter of Algorithm 1 advances by the same
+// amount for every entity of one dimension: the column of base entity (d, i)
+// holds (lambda + 1) delta(d,0) + lambda delta(d,1) DoFs and starts at
+// base[d] + i * col_size[d], base[d] being the DoFs of all columns of lower
+// dimension.  Inside a column, level l starts at l (delta(d,0) + delta(d,1))
+// and the vertical entity over interval l follows its bottom level.
+
+__global__ void k_column_starts(int32_t n, int64_t base, int32_t col_size, int32_t* dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = col_size ? (int32_t)(base + i * (int64_t)col_size) : -1;
+}
+
+// One position of the explicit list: closure entity e (0..2 vertex, 3..5 edge,
+// 6 cell) and the DoF offset inside that entity's column for layer 0.
+struct StencilPos {
+    int32_t entity;
+    int32_t shift;
+};
+
+__global__ void k_bottom_map(int32_t n_cells, int32_t k, const StencilPos* __restrict__ pos,
+                             const int32_t* __restrict__ cell_vertex, const int32_t* __restrict__ cell_edge,
+                             int64_t base0, int64_t base1, int64_t base2, int32_t cs0, int32_t cs1, int32_t cs2,
+                             int32_t* __restrict__ map)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)n_cells * k;
+    if (t >= total) return;
+    int64_t c = t / k;
+    int32_t p = (int32_t)(t - c * k);
+    StencilPos sp = pos[p];
+    int64_t start;
+    if (sp.entity < 3) start = base0 + (int64_t)cell_vertex[c * 3 + sp.entity] * cs0;
+    else if (sp.entity < 6) start = base1 + (int64_t)cell_edge[c * 3 + sp.entity - 3] * cs1;
+    else start = base2 + c * (int64_t)cs2;
+    map[t] = (int32_t)(start + sp.shift);
+}
+
+// ---------------------------------------------------------------------------
+// Greedy base-cell colouring (host): cells are visited in base order and take
+// the smallest colour not used by an already coloured cell sharing a vertex.
+
+int32_t build_colouring(const exm_mesh* m, const Colouring** out)
+{
+    std::lock_guard<std::mutex> lock(m->mu);
+    if (m->colouring) {
+        *out = m->colouring.get();
+        return EXM_OK;
+    }
+    const int32_t nv = m->n[0], nc = m->n[2];
+    const int32_t* cv = m->h_cell_vertex.data();
+    // vertex -> cells adjacency (CSR)
+    std::vector<int64_t> vstart(nv + 1, 0);
+    for (int64_t i = 0; i < (int64_t)nc * 3; ++i) vstart[cv[i] + 1]++;
+    for (int32_t v = 0; v < nv; ++v) vstart[v + 1] += vstart[v];
+    std::vector<int32_t> vcells(vstart[nv]);
+    std::vector<int64_t> fill(vstart.begin(), vstart.end() - 1);
+    for (int32_t c = 0; c < nc; ++c)
+        for (int a = 0; a < 3; ++a) vcells[fill[cv[c * 3 + a]]++] = c;
+    std::vector<int32_t> colour(nc, -1);
+    std::vector<int32_t> mark;   // mark[col] == c when colour col is taken by a neighbour of c
+    int32_t ncol = 0;
+    for (int32_t c = 0; c < nc; ++c) {
+        for (int a = 0; a < 3; ++a) {
+            int32_t v = cv[c * 3 + a];
+            for (int64_t j = vstart[v]; j < vstart[v + 1]; ++j) {
+                int32_t o = colour[vcells[j]];
+                if (o >= 0) mark[o] = c;
+            }
+        }
+        int32_t col = 0;
+        while (col < ncol && mark[col] == c) ++col;
+        if (col == ncol) {
+            ++ncol;
+            mark.push_back(-1);
+        }
+        colour[c] = col;
+    }
+    auto col = std::make_unique<Colouring>();
+    col->n_colours = ncol;
+    col->offsets.assign(ncol + 1, 0);
+    for (int32_t c = 0; c < nc; ++c) col->offsets[colour[c] + 1]++;
+    for (int32_t k = 0; k < ncol; ++k) col->offsets[k + 1] += col->offsets[k];
+    col->host_cells.resize(nc);
+    std::vector<int64_t> f2(col->offsets.begin(), col->offsets.end() - 1);
+    for (int32_t c = 0; c < nc; ++c) col->host_cells[f2[colour[c]]++] = c;
+    int32_t s = col->cells.upload(col->host_cells.data(), col->host_cells.size());
+    if (s != EXM_OK) return s;
+    m->colouring = std::move(col);
+    *out = m->colouring.get();
+    return EXM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// STREAM triad.
+
+__global__ void k_triad(double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+                        double alpha, int64_t n)
+{
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        a[i] = b[i] + alpha * c[i];
+}
+
+}  // namespace exm
+
+using namespace exm;
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char* exm_last_error(void) { return g_error.c_str(); }
+
+int32_t exm_abi_version(void) { return EXM_ABI_VERSION; }
+
+int32_t exm_sync(void* stream)
+{
+    clear_error();
+    EXM_TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return check_pending();
+}
+
+int32_t exm_mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells, const int32_t* cell_vertex,
+                        const int32_t* cell_edge, int32_t n_layers, exm_mesh** out)
+{
+    clear_error();
+    EXM_CHECK(out != nullptr, EXM_EINVAL, "out is NULL");
+    *out = nullptr;
+    EXM_CHECK(cell_vertex != nullptr, EXM_EINVAL, "cell_vertex is NULL");
+    EXM_CHECK(n_vertices >= 3 && n_cells >= 1 && n_edges >= 0, EXM_ERANGE,
+              "need n_vertices >= 3, n_cells >= 1, n_edges >= 0 (got %d, %d, %d)", n_vertices, n_cells, n_edges);
+    EXM_CHECK(n_layers >= 1, EXM_ERANGE, "n_layers must be >= 1 (got %d)", n_layers);
+    EXM_CHECK(cell_edge == nullptr || n_edges >= 3, EXM_ERANGE, "cell_edge given but n_edges = %d", n_edges);
+    for (int64_t i = 0; i < (int64_t)n_cells * 3; ++i)
+        EXM_CHECK(cell_vertex[i] >= 0 && cell_vertex[i] < n_vertices, EXM_ERANGE,
+                  "cell_vertex[%lld] = %d outside [0, %d)", (long long)i, cell_vertex[i], n_vertices);
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const int32_t* v = cell_vertex + c * 3;
+        EXM_CHECK(v[0] != v[1] && v[1] != v[2] && v[0] != v[2], EXM_EINVAL,
+                  "cell %lld repeats a vertex", (long long)c);
+    }
+    if (cell_edge)
+        for (int64_t i = 0; i < (int64_t)n_cells * 3; ++i)
+            EXM_CHECK(cell_edge[i] >= 0 && cell_edge[i] < n_edges, EXM_ERANGE,
+                      "cell_edge[%lld] = %d outside [0, %d)", (long long)i, cell_edge[i], n_edges);
+    auto m = std::make_unique<exm_mesh>();
+    m->n[0] = n_vertices;
+    m->n[1] = n_edges;
+    m->n[2] = n_cells;
+    m->n_layers = n_layers;
+    EXM_TRY_HIP(hipGetDevice(&m->device));
+    m->h_cell_vertex.assign(cell_vertex, cell_vertex + (size_t)n_cells * 3);
+    int32_t s = m->d_cell_vertex.upload(cell_vertex, (size_t)n_cells * 3);
+    if (s != EXM_OK) return s;
+    if (cell_edge) {
+        m->h_cell_edge.assign(cell_edge, cell_edge + (size_t)n_cells * 3);
+        s = m->d_cell_edge.upload(cell_edge, (size_t)n_cells * 3);
+        if (s != EXM_OK) return s;
+    }
+    *out = m.release();
+    return EXM_OK;
+}
+
+void exm_mesh_destroy(exm_mesh* mesh) { delete mesh; }
+
+static bool element_delta(int32_t element, int32_t d[6])
+{
+    for (int i = 0; i < 6; ++i) d[i] = 0;
+    switch (element) {
+    case EXM_ELEMENT_P1P1: d[0] = 1; return true;
+    case EXM_ELEMENT_DG0DG0: d[5] = 1; return true;
+    case EXM_ELEMENT_DG1DG1: d[5] = 6; return true;
+    case EXM_ELEMENT_P2P2: d[0] = d[1] = d[2] = d[3] = 1; return true;
+    default: return false;
+    }
+}
+
+int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t element, void* stream,
+                         exm_space** out)
+{
+    clear_error();
+    EXM_CHECK(out != nullptr, EXM_EINVAL, "out is NULL");
+    *out = nullptr;
+    EXM_CHECK(mesh != nullptr && delta != nullptr, EXM_EINVAL, "mesh or delta is NULL");
+    int32_t total = 0;
+    for (int i = 0; i < 6; ++i) {
+        EXM_CHECK(delta[i] >= 0 && delta[i] <= 64, EXM_ERANGE, "delta[%d] = %d outside [0, 64]", i, delta[i]);
+        total += delta[i];
+    }
+    EXM_CHECK(total > 0, EXM_EINVAL, "delta table is all zero");
+    if (element != EXM_ELEMENT_NONE) {
+        int32_t want[6];
+        EXM_CHECK(element_delta(element, want), EXM_EINVAL, "unknown element %d", element);
+        for (int i = 0; i < 6; ++i)
+            EXM_CHECK(want[i] == delta[i], EXM_EINVAL, "delta[%d] = %d does not match element %d (expects %d)", i,
+                      delta[i], element, want[i]);
+    }
+    EXM_CHECK(delta[2] + delta[3] == 0 || !mesh->h_cell_edge.empty(), EXM_EINVAL,
+              "space has DoFs on edges but the mesh has no cell_edge map");
+    const int64_t lam = mesh->n_layers;
+    auto s = std::make_unique<exm_space>();
+    s->mesh = mesh;
+    s->element = element;
+    std::memcpy(s->delta, delta, sizeof(s->delta));
+    int64_t base = 0;
+    for (int d = 0; d < 3; ++d) {
+        int64_t cs = (lam + 1) * delta[2 * d] + lam * delta[2 * d + 1];
+        EXM_CHECK(cs < INT32_MAX, EXM_EOVERFLOW, "column size too large");
+        s->col_size[d] = (int32_t)cs;
+        s->base[d] = base;
+        base += (int64_t)mesh->n[d] * cs;
+    }
+    s->n_dofs = base;
+    EXM_CHECK(s->n_dofs < (int64_t)INT32_MAX, EXM_EOVERFLOW,
+              "space has %lld DoFs; the int32 numbering allows at most %d", (long long)s->n_dofs, INT32_MAX - 1);
+    // Stencil layout and Algorithm 2 offsets.
+    std::vector<StencilPos> pos;
+    for (int e = 0; e < 7; ++e) {
+        int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+        int nh = delta[2 * d], nv = delta[2 * d + 1];
+        for (int j = 0; j < nh; ++j) pos.push_back({e, j});                 // bottom level
+        for (int j = 0; j < nh; ++j) pos.push_back({e, nh + nv + j});       // top level
+        for (int j = 0; j < nv; ++j) pos.push_back({e, nh + j});            // vertical entity
+        for (int j = 0; j < 2 * nh + nv; ++j) {
+            s->offsets.push_back(nh + nv);
+            s->entity_dim.push_back(d);
+        }
+    }
+    s->k = (int32_t)pos.size();
+    const int64_t nmap = (int64_t)mesh->n[2] * s->k;
+    int32_t st = s->d_map.alloc((size_t)nmap);
+    if (st != EXM_OK) return st;
+    DevBuf<StencilPos> dpos;
+    st = dpos.upload(pos.data(), pos.size());
+    if (st != EXM_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_bottom_map, dim3((unsigned)((nmap + bs - 1) / bs)), dim3(bs), 0, hs, mesh->n[2], s->k,
+                       dpos.p, mesh->d_cell_vertex.p, mesh->d_cell_edge.p, s->base[0], s->base[1], s->base[2],
+                       s->col_size[0], s->col_size[1], s->col_size[2], s->d_map.p);
+    EXM_TRY_HIP(hipGetLastError());
+    // dpos is freed on return: wait for the kernel that reads it.
+    EXM_TRY_HIP(hipStreamSynchronize(hs));
+    *out = s.release();
+    return EXM_OK;
+}
+
+int32_t exm_space_info(const exm_space* space, int64_t* n_dofs, int32_t* arity)
+{
+    clear_error();
+    EXM_CHECK(space != nullptr, EXM_EINVAL, "space is NULL");
+    if (n_dofs) *n_dofs = space->n_dofs;
+    if (arity) *arity = space->k;
+    return EXM_OK;
+}
+
+int32_t exm_space_offsets(const exm_space* space, int32_t* offsets)
+{
+    clear_error();
+    EXM_CHECK(space != nullptr && offsets != nullptr, EXM_EINVAL, "space or offsets is NULL");
+    std::memcpy(offsets, space->offsets.data(), sizeof(int32_t) * space->offsets.size());
+    return EXM_OK;
+}
+
+int32_t exm_space_column_starts(const exm_space* space, int32_t d1, int32_t* dst, void* stream)
+{
+    clear_error();
+    EXM_CHECK(space != nullptr && dst != nullptr, EXM_EINVAL, "space or dst is NULL");
+    EXM_CHECK(d1 >= 0 && d1 <= 2, EXM_ERANGE, "d1 = %d outside [0, 2]", d1);
+    int32_t n = space->mesh->n[d1];
+    if (n == 0) return EXM_OK;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_column_starts, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, n,
+                       space->base[d1], space->col_size[d1], dst);
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+int32_t exm_space_bottom_map(const exm_space* space, int32_t* dst, void* stream)
+{
+    clear_error();
+    EXM_CHECK(space != nullptr && dst != nullptr, EXM_EINVAL, "space or dst is NULL");
+    size_t bytes = sizeof(int32_t) * space->d_map.n;
+    if (bytes)
+        EXM_TRY_HIP(hipMemcpyAsync(dst, space->d_map.p, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return EXM_OK;
+}
+
+void exm_space_destroy(exm_space* space) { delete space; }
+
+int32_t exm_mesh_colours(const exm_mesh* mesh, int32_t* n_colours)
+{
+    clear_error();
+    EXM_CHECK(mesh != nullptr && n_colours != nullptr, EXM_EINVAL, "mesh or n_colours is NULL");
+    const Colouring* c = nullptr;
+    int32_t s = build_colouring(mesh, &c);
+    if (s != EXM_OK) return s;
+    *n_colours = c->n_colours;
+    return EXM_OK;
+}
+
+int32_t exm_stream_triad(double* a, const double* b, const double* c, double alpha, int64_t n, int32_t block,
+                         int32_t grid, void* stream)
+{
+    clear_error();
+    EXM_CHECK(a && b && c, EXM_EINVAL, "null array");
+    EXM_CHECK(a != b && a != c && b != c, EXM_EINVAL, "arrays must be distinct");
+    EXM_CHECK(n >= 0, EXM_ERANGE, "n < 0");
+    EXM_CHECK(block >= 64 && block <= 1024 && block % 64 == 0, EXM_ERANGE, "block = %d not a multiple of 64 in [64, 1024]", block);
+    EXM_CHECK(grid >= 0, EXM_ERANGE, "grid < 0");
+    if (n == 0) return EXM_OK;
+    int64_t g = grid ? grid : (n + block - 1) / block;
+    EXM_CHECK(g <= INT32_MAX, EXM_ERANGE, "grid too large");
+    hipLaunchKernelGGL(k_triad, dim3((unsigned)g), dim3(block), 0, (hipStream_t)stream, a, b, c, alpha, n);
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Internal declarations shared by the translation units of libexm.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "exm.h"
+
+namespace exm {
+
+// ---------------------------------------------------------------------------
+// Errors: a thread-local message plus the status code.
+
+int32_t fail(int32_t code, const char* fmt, ...);
+void clear_error();
+
+#define EXM_TRY_HIP(expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::exm::fail(EXM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define EXM_CHECK(cond, code, ...)                   \
+    do {                                             \
+        if (!(cond)) return ::exm::fail(code, __VA_ARGS__); \
+    } while (0)
+
+// Report an error from an earlier asynchronous launch, if any.
+int32_t check_pending();
+
+// ---------------------------------------------------------------------------
+// Device buffers owned by the library.
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    int32_t alloc(size_t count) {
+        reset();
+        if (count == 0) return EXM_OK;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(EXM_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+        }
+        n = count;
+        return EXM_OK;
+    }
+    int32_t upload(const T* host, size_t count) {
+        int32_t s = alloc(count);
+        if (s != EXM_OK) return s;
+        if (count) EXM_TRY_HIP(hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice));
+        return EXM_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Colouring of the base cells: no two cells of one colour share a vertex.
+
+struct Colouring {
+    int32_t n_colours = 0;
+    std::vector<int64_t> offsets;   // [n_colours + 1] into cells
+    DevBuf<int32_t> cells;          // cells grouped by colour, ascending within a colour
+    std::vector<int32_t> host_cells;
+};
+
+}  // namespace exm
+
+struct exm_mesh {
+    int32_t n[3] = {0, 0, 0};      // N_0, N_1, N_2
+    int32_t n_layers = 0;
+    int device = 0;
+    std::vector<int32_t> h_cell_vertex, h_cell_edge;
+    exm::DevBuf<int32_t> d_cell_vertex, d_cell_edge;
+    mutable std::mutex mu;
+    mutable std::unique_ptr<exm::Colouring> colouring;   // built on first use
+};
+
+struct exm_space {
+    const exm_mesh* mesh = nullptr;
+    int32_t delta[6] = {0, 0, 0, 0, 0, 0};
+    int32_t element = EXM_ELEMENT_NONE;
+    int64_t n_dofs = 0;
+    int32_t k = 0;
+    int32_t col_size[3] = {0, 0, 0};   // DoFs in one column of a base entity of dimension d
+    int64_t base[3] = {0, 0, 0};       // first DoF of the first column of dimension d
+    std::vector<int32_t> offsets;      // [k], Algorithm 2
+    std::vector<int32_t> entity_dim;   // [k]
+    exm::DevBuf<int32_t> d_map;        // [n_cells * k], explicit lists of layer 0
+};
+
+namespace exm {
+
+int32_t build_colouring(const exm_mesh* m, const Colouring** out);
+
+// Work decomposition of the column loop.
+struct LoopShape {
+    int32_t cpw;     // base-cell columns per wavefront
+    int32_t seg;     // lanes (layers per step) per column
+    int32_t wpb;     // wavefronts per workgroup
+};
+
+LoopShape default_shape(int32_t kernel, int32_t element, int32_t n_layers, int64_t n_cells);
+LoopShape shape_from_opts(int32_t kernel, int32_t element, int32_t n_layers, int64_t n_cells,
+                          const exm_loop_opts* opts);
+int32_t lookup_tuned(int32_t kernel, int32_t element, int32_t n_layers, int64_t n_cells, exm_loop_opts* out);
+
+// Launch the column loop of one element kernel (validated arguments).
+struct LoopLaunch {
+    int32_t kernel;
+    int32_t element;
+    int32_t race;
+    LoopShape shape;
+    int32_t n_layers;
+    int32_t field_offset;         // vertical offset of every position of the field space
+    const int32_t* fmap;          // field explicit lists [n_cells * k]
+    const int32_t* xmap;          // coordinate explicit lists [n_cells * 6]
+    const double* X;              // coordinates [n * 3]
+    const double* in[3];
+    double* out[3];
+    int32_t write;                // 1 WRITE, 0 INC
+    int32_t n_cells;              // total base cells
+    const int32_t* cells;         // cell list (colour mode) or null
+    int64_t cell_begin, cell_count;  // range of the list (or of cells) handled by this launch
+};
+int32_t launch_column_loop(const LoopLaunch& L, hipStream_t stream);
+
+}  // namespace exm

@@ -1,0 +1,100 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on seeded
+inputs: numbering and lists bit-exact, FP64 values to the componentwise
+tolerance of tests/gpu_common.py."""
+import numpy as np
+import pytest
+
+import paper_1604_05937_amd as exm
+from paper_1604_05937_amd import meshgen
+from tests.gpu_common import RTOL, Case, assert_close, say
+
+pytestmark = pytest.mark.gpu
+
+# configs: (n, layers) -- 16x16 base x 10 layers is the tiny workload; the
+# others cover lambda = 1, lambda not a multiple of any lane group, and more
+# layers than one 64-lane step.
+SHAPES = [(16, 10), (5, 1), (7, 63), (6, 65), (3, 130)]
+
+
+@pytest.mark.parametrize("space", ["P1", "DG0", "DG1", "P2"])
+@pytest.mark.parametrize("n,lam", SHAPES)
+@pytest.mark.parametrize("order", ["rcm", "random"])
+def test_numbering_bit_exact(space, n, lam, order):
+    say(f"numbering {space} n={n} lam={lam} {order}")
+    base = meshgen.tri_square(n, order=order)
+    c = Case(base, lam, space)
+    ref = c.ref.num_v
+    assert c.V.n_dofs == ref.n_dofs
+    assert c.V.arity == ref.k
+    np.testing.assert_array_equal(c.V.offsets(), ref.offsets)
+    np.testing.assert_array_equal(c.V.bottom_map().cpu().numpy(), ref.lmap.astype(np.int32))
+    for d1 in range(3):
+        starts = c.V.column_starts(d1).cpu().numpy()
+        if ref.first[d1] is None:
+            assert np.all(starts == -1)
+        else:
+            np.testing.assert_array_equal(starts, ref.column_starts(d1).astype(np.int32))
+
+
+@pytest.mark.parametrize("space", ["P1", "DG0", "DG1", "P2"])
+@pytest.mark.parametrize("n,lam", SHAPES)
+@pytest.mark.parametrize("race", [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR])
+def test_mass_parity(space, n, lam, race):
+    say(f"mass {space} n={n} lam={lam} race={race}")
+    base = meshgen.tri_square(n)
+    c = Case(base, lam, space, terrain=0.25)
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    got = c.mass(x, race=race)
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"mass {space}")
+
+
+@pytest.mark.parametrize("space", ["P1", "P2", "DG1", "DG0"])
+@pytest.mark.parametrize("cpw", [1, 2, 3, 4, 5, 7, 8, 16])
+@pytest.mark.parametrize("wpb", [1, 4])
+def test_mass_launch_shapes(space, cpw, wpb):
+    say(f"shape {space} cpw={cpw} wpb={wpb}")
+    base = meshgen.tri_square(9)
+    c = Case(base, 23, space)
+    x = meshgen.uniform_values(c.n, seed=5)
+    got = c.mass(x, cols_per_wave=cpw, waves_per_block=wpb)
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"mass {space} cpw={cpw}")
+
+
+def test_tiny_config_p1_rhs():
+    # 16x16 triangulated square, 10 layers of height 0.1, P1 x P1, f ~ U[-1, 1]
+    base = meshgen.tri_square(16)
+    c = Case(base, 10, "P1")
+    f = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    for race in (exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR):
+        got = c.mass(f, race=race)
+        assert_close(got, c.ref.mass(f), c.ref.mass_abs(f), what="tiny P1 rhs")
+    # partition of unity on the device result: sum_i b_i = integral of f
+    one = c.mass(np.ones(c.n))
+    assert abs(one.sum() - 1.0) < 1e-13
+
+
+def test_single_cell_mesh():
+    base = meshgen.tri_rectangle(1, 1, 1.0, jitter=0.0)
+    for space in ("P1", "DG0", "DG1", "P2"):
+        c = Case(base, 3, space)
+        x = meshgen.uniform_values(c.n, seed=2)
+        assert_close(c.mass(x), c.ref.mass(x), c.ref.mass_abs(x), what=f"single quad {space}")
+
+
+def test_inc_accumulates():
+    base = meshgen.tri_square(6)
+    c = Case(base, 5, "P1")
+    x = meshgen.uniform_values(c.n, seed=3)
+    xd = c.dev(x)
+    y = c.dev(np.full(c.n, 2.0))
+    exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)])
+    ref = c.ref.mass(x) + 2.0
+    assert_close(c.host(y), ref, c.ref.mass_abs(x) + 2.0, what="INC into non-zero output")
+
+
+def test_colour_counts():
+    base = meshgen.tri_square(16)
+    mesh = exm.Mesh(base, 4)
+    n = mesh.colours()
+    # a vertex of the triangulated square touches at most 6 cells
+    assert 6 <= n <= 13
