@@ -19,8 +19,9 @@
  *   - "host" pointers are read during the call only; the library copies what
  *     it keeps.  "device" pointers are HIP device memory owned by the caller
  *     and must stay valid until the stream work that uses them has finished.
- *   - Field data is FP64.  A vector field of dimension dim stores component
- *     i of DoF n at data[n * dim + i].
+ *   - Field data is FP64.  A vector field of dimension dim is stored
+ *     component-major: component i of DoF n at data[i * n_dofs + n], so that
+ *     every component of an entity column is one contiguous run.
  *   - Every entry point validates its arguments on the host before any device
  *     work and returns a negative status with a message for exm_last_error()
  *     on failure; nothing is launched then.  Errors raised by asynchronous
@@ -167,18 +168,38 @@ typedef struct {
 
 /* Race resolution for INC into continuous spaces, where base cells share
  * DoF columns horizontally. */
-#define EXM_RACE_AUTO 0       /* library choice (autotuned if available)            */
-#define EXM_RACE_ATOMIC 1     /* hardware FP64 atomic adds, one launch             */
-#define EXM_RACE_COLOUR 2     /* base cells greedily coloured (no shared vertex),   */
-                              /* one launch per colour with plain read-add-write   */
+#define EXM_RACE_AUTO 0       /* library choice (autotuned if available)                 */
+#define EXM_RACE_ATOMIC 1     /* hardware FP64 atomic adds for DoFs another unit shares  */
+#define EXM_RACE_COLOUR 2     /* units greedily coloured (no shared vertex within one    */
+                              /* colour), one launch per colour, plain read-add-write    */
+
+/* Work schedule of the column loop. */
+#define EXM_SCHED_AUTO 0
+#define EXM_SCHED_DIRECT 1    /* one wavefront takes cols_per_wave base cells side by side,  */
+                              /* 64 / cols_per_wave consecutive layers each (one per lane),  */
+                              /* gathering straight from HBM; the unit of colouring is the   */
+                              /* base cell                                                  */
+#define EXM_SCHED_TILED 2     /* one workgroup takes a compact tile of about tile_cells base  */
+                              /* cells (grown breadth-first from the base ordering); its      */
+                              /* wavefronts walk the tile's cells like DIRECT but sum every   */
+                              /* update in LDS, and the workgroup adds each (vertex or edge,  */
+                              /* level) sum to the output once; the unit of colouring is the  */
+                              /* tile.  DG spaces, which share no DoFs, run DIRECT.           */
+#define EXM_SCHED_STAGED 3    /* like TILED, but the workgroup also copies every column       */
+                              /* segment its tile touches (coordinates and inputs) into LDS   */
+                              /* once per chunk of chunk_layers layers, loading the next      */
+                              /* chunk while it computes the current one; the element kernels */
+                              /* read LDS only.  P1xP1, DG0DG0 and DG1DG1 (P2P2 runs TILED)   */
 
 typedef struct {
-    int32_t race;              /* EXM_RACE_*                                        */
-    int32_t cols_per_wave;     /* base-cell columns side by side in one wavefront;  */
-                               /* each gets 64 / cols_per_wave lanes, one layer per  */
-                               /* lane (0 = choose)                                 */
-    int32_t waves_per_block;   /* wavefronts per workgroup, 1..16 (0 = choose)      */
-    int32_t reserved;
+    int32_t race;              /* EXM_RACE_*                                             */
+    int32_t schedule;          /* EXM_SCHED_*                                            */
+    int32_t cols_per_wave;     /* DIRECT, TILED: base cells side by side in one          */
+                               /* wavefront, each taking 64 / cols_per_wave lanes =      */
+                               /* layers per step: 1..16 (0 = choose)                    */
+    int32_t waves_per_block;   /* DIRECT: 1..4; TILED: 1..8; STAGED: 4 (0 = choose)      */
+    int32_t tile_cells;        /* TILED, STAGED: 8..1024 target cells per tile (0 = choose) */
+    int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64 layers per chunk (0 = choose) */
 } exm_loop_opts;
 
 /* opts may be NULL (all defaults). */

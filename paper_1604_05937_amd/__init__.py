@@ -18,7 +18,8 @@ import numpy as np
 from . import _abi
 from ._abi import (EXM_ELEMENT_DG0DG0, EXM_ELEMENT_DG1DG1, EXM_ELEMENT_NONE, EXM_ELEMENT_P1P1, EXM_ELEMENT_P2P2,
                    EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_VJP, EXM_K_MASS, EXM_RACE_ATOMIC,
-                   EXM_RACE_AUTO, EXM_RACE_COLOUR, EXM_READ, EXM_WRITE, ExmError)
+                   EXM_RACE_AUTO, EXM_RACE_COLOUR, EXM_READ, EXM_SCHED_AUTO, EXM_SCHED_DIRECT, EXM_SCHED_STAGED, EXM_SCHED_TILED,
+                   EXM_WRITE, ExmError)
 
 __all__ = ["Mesh", "Space", "par_loop", "ExmError", "ELEMENTS", "DELTA", "load_library", "stream_handle"]
 
@@ -132,15 +133,18 @@ class Space:
 
 
 def coordinate_field(space: Space, vertex_coords: np.ndarray):
-    """Coordinate field [n_dofs, 3] (FP64, device) of a P1 x P1 space from
-    per-vertex, per-level coordinates [N0, lambda+1, 3]: the value of extruded
-    vertex (v, l) goes to DoF S(v) + l, S the column starts the library built."""
+    """Coordinate field (FP64, device, component-major [3, n_dofs]) of a P1 x P1
+    space from per-vertex, per-level coordinates [N0, lambda+1, 3]: component i
+    of extruded vertex (v, l) goes to X[i, S(v) + l], S the column starts the
+    library built."""
     import torch
     assert space.element == EXM_ELEMENT_P1P1
     starts = space.column_starts(0).cpu().numpy().astype(np.int64)
     nl = vertex_coords.shape[1]
-    host = np.zeros((space.n_dofs, 3))
-    host[(starts[:, None] + np.arange(nl)[None, :]).ravel()] = vertex_coords.reshape(-1, 3)
+    host = np.zeros((3, space.n_dofs))
+    idx = (starts[:, None] + np.arange(nl)[None, :]).ravel()
+    for i in range(3):
+        host[i, idx] = vertex_coords[:, :, i].ravel()
     return torch.from_numpy(host).to("cuda")
 
 
@@ -160,32 +164,39 @@ def make_args(coords, coord_space: Space, fields):
     return arr
 
 
-def loop_opts(race: int = 0, cols_per_wave: int = 0, waves_per_block: int = 0):
-    return _abi.exm_loop_opts(race, cols_per_wave, waves_per_block, 0)
+OPT_FIELDS = ("race", "schedule", "cols_per_wave", "waves_per_block", "tile_cells", "chunk_layers")
 
 
-def par_loop(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, race: int = 0, cols_per_wave: int = 0,
-             waves_per_block: int = 0, stream=None):
-    """exm_par_loop on the current torch stream."""
+def loop_opts(race: int = 0, schedule: int = 0, cols_per_wave: int = 0, waves_per_block: int = 0,
+              tile_cells: int = 0, chunk_layers: int = 0):
+    return _abi.exm_loop_opts(race, schedule, cols_per_wave, waves_per_block, tile_cells, chunk_layers)
+
+
+def _opts_dict(o) -> dict:
+    return {k: getattr(o, k) for k in OPT_FIELDS}
+
+
+def par_loop(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, stream=None, **opts):
+    """exm_par_loop on the current torch stream (opts: exm_loop_opts fields)."""
     args = make_args(coords, coord_space, fields)
-    opts = loop_opts(race, cols_per_wave, waves_per_block)
-    _abi.exm_par_loop(kernel, mesh.handle, len(args), args, ctypes.byref(opts), stream_handle(stream))
+    o = loop_opts(**opts)
+    _abi.exm_par_loop(kernel, mesh.handle, len(args), args, ctypes.byref(o), stream_handle(stream))
 
 
-def par_loop_config(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, race: int = 0,
-                    cols_per_wave: int = 0, waves_per_block: int = 0):
+def par_loop_config(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, **opts) -> dict:
+    """The launch configuration exm_par_loop would use."""
     args = make_args(coords, coord_space, fields)
-    opts = loop_opts(race, cols_per_wave, waves_per_block)
+    o = loop_opts(**opts)
     ch = _abi.exm_loop_opts()
-    _abi.exm_par_loop_config(kernel, mesh.handle, len(args), args, ctypes.byref(opts), ctypes.byref(ch))
-    return ch.race, ch.cols_per_wave, ch.waves_per_block
+    _abi.exm_par_loop_config(kernel, mesh.handle, len(args), args, ctypes.byref(o), ctypes.byref(ch))
+    return _opts_dict(ch)
 
 
-def autotune(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, stream=None):
+def autotune(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, stream=None) -> dict:
     args = make_args(coords, coord_space, fields)
     best = _abi.exm_loop_opts()
     _abi.exm_autotune(kernel, mesh.handle, len(args), args, stream_handle(stream), ctypes.byref(best))
-    return best.race, best.cols_per_wave, best.waves_per_block
+    return _opts_dict(best)
 
 
 def sync(stream=None):

@@ -41,6 +41,11 @@ EXM_RACE_AUTO = 0
 EXM_RACE_ATOMIC = 1
 EXM_RACE_COLOUR = 2
 
+EXM_SCHED_AUTO = 0
+EXM_SCHED_DIRECT = 1
+EXM_SCHED_TILED = 2
+EXM_SCHED_STAGED = 3
+
 STATUS_NAMES = {0: "EXM_OK", -1: "EXM_EINVAL", -2: "EXM_ERANGE", -3: "EXM_EOVERFLOW", -4: "EXM_ENOMEM",
                 -5: "EXM_EHIP", -6: "EXM_EUNSUPPORTED"}
 
@@ -56,7 +61,8 @@ class exm_arg(ctypes.Structure):
 
 
 class exm_loop_opts(ctypes.Structure):
-    _fields_ = [("race", c_int32), ("cols_per_wave", c_int32), ("waves_per_block", c_int32), ("reserved", c_int32)]
+    _fields_ = [("race", c_int32), ("schedule", c_int32), ("cols_per_wave", c_int32), ("waves_per_block", c_int32),
+                ("tile_cells", c_int32), ("chunk_layers", c_int32)]
 
 
 class exm_batch_item(ctypes.Structure):

@@ -1,4 +1,4 @@
-// exm_par_loop: argument validation, launch-shape selection, race strategy,
+// exm_par_loop: argument validation, schedule and race-strategy selection,
 // and the autotuner.
 #include <algorithm>
 #include <cmath>
@@ -9,13 +9,19 @@
 #include <tuple>
 
 #include "exm_internal.hpp"
+#include "exm_tiled.hpp"
 
 namespace exm {
 
+// Largest LDS a workgroup may use; a chunk is shrunk until its staging fits.
+static constexpr size_t kLdsLimit = 160 * 1024;
+// Default LDS budget: two tile workgroups per compute unit.
+static constexpr size_t kLdsDefault = 64 * 1024;
+
 // ---------------------------------------------------------------------------
-// Launch shapes.  cols_per_wave = cpw columns share a wavefront; each gets
-// seg = 64 / cpw lanes.  A column of lambda layers takes ceil(lambda / seg)
-// steps, so the fraction of busy lanes is cpw lambda / (64 ceil(lambda / seg)).
+// DIRECT schedule shapes.  cols_per_wave = cpw columns share a wavefront; each
+// gets seg = 64 / cpw lanes.  A column of lambda layers takes ceil(lambda /
+// seg) steps, so the fraction of busy lanes is cpw lambda / (64 ceil(lambda / seg)).
 
 static LoopShape make_shape(int32_t cpw, int32_t wpb)
 {
@@ -38,8 +44,8 @@ LoopShape default_shape(int32_t kernel, int32_t element, int32_t n_layers, int64
     (void)kernel;
     (void)element;
     (void)n_cells;
-    // Wider groups of lanes per column keep the accesses coalesced; consider
-    // at most four columns per wavefront (16 lanes = 128 bytes of FP64).
+    // Wider lane groups per column keep accesses coalesced: at most four
+    // columns per wavefront (16 lanes = 128 bytes of FP64 per column).
     int32_t best = 1;
     double bu = lane_use(1, n_layers);
     for (int32_t c = 2; c <= 4; ++c) {
@@ -77,12 +83,8 @@ LoopShape shape_from_opts(int32_t kernel, int32_t element, int32_t n_layers, int
                           const exm_loop_opts* opts)
 {
     LoopShape s = default_shape(kernel, element, n_layers, n_cells);
-    exm_loop_opts tuned;
-    if (lookup_tuned(kernel, element, n_layers, n_cells, &tuned)) s = make_shape(tuned.cols_per_wave, tuned.waves_per_block);
-    if (opts) {
-        if (opts->cols_per_wave > 0) s = make_shape(opts->cols_per_wave, s.wpb);
-        if (opts->waves_per_block > 0) s = make_shape(s.cpw, opts->waves_per_block);
-    }
+    if (opts && opts->cols_per_wave > 0) s = make_shape(opts->cols_per_wave, s.wpb);
+    if (opts && opts->waves_per_block > 0) s = make_shape(s.cpw, opts->waves_per_block);
     return s;
 }
 
@@ -106,7 +108,7 @@ static bool signature(int32_t kernel, Signature& s)
 
 static bool continuous(int32_t element) { return element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2; }
 
-// Validate and fill everything but the race strategy and shape.
+// Validate and fill everything but the schedule.
 static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const exm_arg* args, LoopLaunch& P)
 {
     Signature sig;
@@ -139,7 +141,8 @@ static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const e
         if (!is_out) {
             EXM_CHECK(A.access == EXM_READ, EXM_EINVAL, "args[%d] must be EXM_READ", i);
         } else {
-            EXM_CHECK(A.access == EXM_INC || A.access == EXM_WRITE, EXM_EINVAL, "args[%d] must be EXM_INC or EXM_WRITE", i);
+            EXM_CHECK(A.access == EXM_INC || A.access == EXM_WRITE, EXM_EINVAL, "args[%d] must be EXM_INC or EXM_WRITE",
+                      i);
             if (A.access == EXM_WRITE)
                 EXM_CHECK(!continuous(el), EXM_EINVAL,
                           "args[%d]: EXM_WRITE on a continuous space (DoFs shared between cells need EXM_INC)", i);
@@ -152,6 +155,8 @@ static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const e
         for (int j = 0; j < nargs; ++j)
             EXM_CHECK(i == j || args[i].data != args[j].data, EXM_EINVAL, "output args[%d] aliases args[%d]", i, j);
     std::memset(&P, 0, sizeof(P));
+    P.fspace = V;
+    P.xspace = X.space;
     P.kernel = kernel;
     P.element = el;
     P.n_layers = m->n_layers;
@@ -169,24 +174,118 @@ static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const e
     return EXM_OK;
 }
 
-static int32_t choose(const LoopLaunch& P, const exm_loop_opts* opts, exm_loop_opts& ch)
+static int32_t default_tile_cells(const LoopLaunch& P)
 {
-    exm_loop_opts tuned;
-    const bool have_tuned = lookup_tuned(P.kernel, P.element, P.n_layers, P.n_cells, &tuned) != 0;
-    ch.race = opts && opts->race ? opts->race : (have_tuned && tuned.race ? tuned.race : EXM_RACE_ATOMIC);
-    EXM_CHECK(ch.race == EXM_RACE_ATOMIC || ch.race == EXM_RACE_COLOUR, EXM_EINVAL, "unknown race strategy %d", ch.race);
-    EXM_CHECK(!opts || (opts->cols_per_wave >= 0 && opts->cols_per_wave <= 64), EXM_ERANGE,
-              "cols_per_wave = %d outside [0, 64]", opts->cols_per_wave);
-    EXM_CHECK(!opts || (opts->waves_per_block >= 0 && opts->waves_per_block <= 4), EXM_ERANGE,
-              "waves_per_block = %d outside [0, 4]", opts->waves_per_block);
-    LoopShape s = shape_from_opts(P.kernel, P.element, P.n_layers, P.n_cells, opts);
-    ch.cols_per_wave = s.cpw;
-    ch.waves_per_block = s.wpb;
-    ch.reserved = 0;
+    if (P.element == EXM_ELEMENT_P2P2 || P.kernel == EXM_K_CUBIC_FUSED) return 64;
+    return 128;
+}
+
+// Lane layout of the TILED schedule: the requested columns per wavefront,
+// else the fewest (longest steps) whose per-tile sums fit the default LDS
+// budget; always within the hardware limit.  Returns cpw (0 if nothing fits).
+static int32_t resolve_tiled_cpw(const LoopLaunch& P, const TilePlan* plan, int32_t requested, size_t* lds_out)
+{
+    auto bytes = [&](int32_t cpw) {
+        return tiled_lds_bytes(P.kernel, P.element, plan->max_verts, plan->has_edges ? plan->max_edges : 0, 64 / cpw);
+    };
+    int32_t cpw = requested > 0 ? requested : default_shape(P.kernel, P.element, P.n_layers, P.n_cells).cpw;
+    if (requested <= 0)
+        while (cpw < 16 && bytes(cpw) > kLdsDefault) ++cpw;
+    if (bytes(cpw) > kLdsLimit) return 0;
+    *lds_out = bytes(cpw);
+    return cpw;
+}
+
+static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_opts* opts, exm_loop_opts& ch)
+{
+    exm_loop_opts d;
+    std::memset(&d, 0, sizeof(d));
+    if (!lookup_tuned(P.kernel, P.element, P.n_layers, P.n_cells, &d)) {
+        d.race = EXM_RACE_ATOMIC;
+        d.schedule = EXM_SCHED_DIRECT;
+    }
+    if (opts) {
+        EXM_CHECK(opts->race >= 0 && opts->race <= 2, EXM_EINVAL, "unknown race strategy %d", opts->race);
+        EXM_CHECK(opts->schedule >= 0 && opts->schedule <= 3, EXM_EINVAL, "unknown schedule %d", opts->schedule);
+        EXM_CHECK(opts->cols_per_wave >= 0 && opts->cols_per_wave <= 16, EXM_ERANGE,
+                  "cols_per_wave = %d outside [0, 16]", opts->cols_per_wave);
+        EXM_CHECK(opts->waves_per_block >= 0 && opts->waves_per_block <= 16, EXM_ERANGE,
+                  "waves_per_block = %d outside [0, 16]", opts->waves_per_block);
+        EXM_CHECK(opts->tile_cells == 0 || (opts->tile_cells >= 8 && opts->tile_cells <= 1024), EXM_ERANGE,
+                  "tile_cells = %d outside [8, 1024]", opts->tile_cells);
+        EXM_CHECK(opts->chunk_layers == 0 || opts->chunk_layers == 8 || opts->chunk_layers == 16 ||
+                      opts->chunk_layers == 32 || opts->chunk_layers == 64,
+                  EXM_ERANGE, "chunk_layers = %d: use 8, 16, 32 or 64 (0 = choose)", opts->chunk_layers);
+        if (opts->race) d.race = opts->race;
+        if (opts->schedule) {
+            if (opts->schedule != d.schedule) {
+                // a schedule switch drops the other schedule's tuned shape
+                d.cols_per_wave = d.waves_per_block = d.tile_cells = d.chunk_layers = 0;
+            }
+            d.schedule = opts->schedule;
+        }
+        if (opts->cols_per_wave) d.cols_per_wave = opts->cols_per_wave;
+        if (opts->waves_per_block) d.waves_per_block = opts->waves_per_block;
+        if (opts->tile_cells) d.tile_cells = opts->tile_cells;
+        if (opts->chunk_layers) d.chunk_layers = opts->chunk_layers;
+    }
+    if (!d.race) d.race = EXM_RACE_ATOMIC;
+    if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
+    if (d.schedule == EXM_SCHED_STAGED && !staged_supported(P.kernel, P.element)) {
+        d.schedule = EXM_SCHED_TILED;
+        d.chunk_layers = 0;
+    }
+    // DG columns belong to one cell: nothing to sum per tile
+    if (!continuous(P.element) && d.schedule == EXM_SCHED_TILED) {
+        d.schedule = EXM_SCHED_DIRECT;
+        d.tile_cells = 0;
+        if (d.waves_per_block > 4) d.waves_per_block = 4;
+    }
+    if (d.schedule == EXM_SCHED_STAGED) {
+        if (!d.tile_cells) d.tile_cells = default_tile_cells(P);
+        d.waves_per_block = 4;
+        d.cols_per_wave = 0;
+        const TilePlan* plan = nullptr;
+        int32_t s = build_tile_plan(mesh, d.tile_cells, &plan);
+        if (s != EXM_OK) return s;
+        if (!d.chunk_layers) {
+            d.chunk_layers = P.n_layers >= 48 ? 32 : (P.n_layers >= 12 ? 16 : 8);
+            while (d.chunk_layers > 8 &&
+                   staged_lds_bytes(P.kernel, P.element, plan->max_verts, d.chunk_layers) > kLdsDefault)
+                d.chunk_layers /= 2;
+        }
+        EXM_CHECK(staged_lds_bytes(P.kernel, P.element, plan->max_verts, d.chunk_layers) <= kLdsLimit,
+                  EXM_EUNSUPPORTED, "tiles of %d cells with %d-layer chunks do not fit in LDS", d.tile_cells,
+                  d.chunk_layers);
+        ch = d;
+        return EXM_OK;
+    }
+    d.chunk_layers = 0;
+    if (d.schedule == EXM_SCHED_DIRECT) {
+        EXM_CHECK(d.waves_per_block <= 4, EXM_ERANGE, "DIRECT schedule: waves_per_block = %d outside [0, 4]",
+                  d.waves_per_block);
+        LoopShape s = shape_from_opts(P.kernel, P.element, P.n_layers, P.n_cells, &d);
+        d.cols_per_wave = s.cpw;
+        d.waves_per_block = s.wpb;
+        d.tile_cells = 0;
+    } else {
+        if (!d.tile_cells) d.tile_cells = default_tile_cells(P);
+        if (!d.waves_per_block) d.waves_per_block = 4;
+        d.waves_per_block = std::min(d.waves_per_block, tiled_max_threads(P.kernel, P.element) / 64);
+        const TilePlan* plan = nullptr;
+        int32_t s = build_tile_plan(mesh, d.tile_cells, &plan);
+        if (s != EXM_OK) return s;
+        size_t lds = 0;
+        const int32_t cpw = resolve_tiled_cpw(P, plan, d.cols_per_wave, &lds);
+        EXM_CHECK(cpw > 0, EXM_EUNSUPPORTED, "tiles of %d cells do not fit in LDS; use smaller tile_cells or more "
+                  "cols_per_wave", d.tile_cells);
+        d.cols_per_wave = cpw;
+    }
+    ch = d;
     return EXM_OK;
 }
 
-static int32_t run_on_mesh(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
+static int32_t run_direct(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
 {
     P.race = ch.race;
     P.shape = make_shape(ch.cols_per_wave, ch.waves_per_block);
@@ -203,10 +302,95 @@ static int32_t run_on_mesh(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_o
         }
         return EXM_OK;
     }
+    P.race = EXM_RACE_ATOMIC;
     P.cells = nullptr;
     P.cell_begin = 0;
     P.cell_count = P.n_cells;
     return launch_column_loop(P, stream);
+}
+
+static void fill_tile_args(const TilePlan* plan, const LoopLaunch& P, TileArgs& t)
+{
+    std::memset(&t, 0, sizeof(t));
+    t.vstride = plan->max_verts;
+    t.estride = plan->has_edges ? plan->max_edges : 0;
+    t.cell_off = plan->cell_off.p;
+    t.cells = plan->cells.p;
+    t.vert_off = plan->vert_off.p;
+    t.verts = plan->verts.p;
+    t.edge_off = plan->has_edges ? plan->edge_off.p : nullptr;
+    t.edges = plan->has_edges ? plan->edges.p : nullptr;
+    t.lcv = plan->local_cv.p;
+    t.lce = plan->has_edges ? plan->local_ce.p : nullptr;
+    t.xstart = P.xspace->d_starts[0].p;
+    t.fstart0 = P.fspace->d_starts[0].p;
+    t.fstart1 = P.fspace->d_starts[1].p;
+}
+
+static int32_t run_tiled(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
+{
+    const TilePlan* plan = nullptr;
+    int32_t s = build_tile_plan(mesh, ch.tile_cells, &plan);
+    if (s != EXM_OK) return s;
+    size_t lds = 0;
+    const int32_t cpw = resolve_tiled_cpw(P, plan, ch.cols_per_wave, &lds);
+    EXM_CHECK(cpw > 0, EXM_EUNSUPPORTED, "tiles of %d cells do not fit in LDS", ch.tile_cells);
+    if (P.element == EXM_ELEMENT_P2P2) EXM_CHECK(plan->has_edges, EXM_EINVAL, "P2 needs the mesh's cell_edge map");
+    P.race = ch.race;
+    P.shape = make_shape(cpw, 1);
+    TileArgs t;
+    fill_tile_args(plan, P, t);
+    const int32_t threads = 64 * std::max(1, std::min(ch.waves_per_block, 16));
+    if (ch.race == EXM_RACE_COLOUR) {
+        t.tiles = plan->colour_tiles.p;
+        for (int32_t k = 0; k < plan->n_colours; ++k) {
+            t.tile_begin = (int32_t)plan->colour_off[k];
+            t.tile_count = (int32_t)(plan->colour_off[k + 1] - plan->colour_off[k]);
+            s = launch_tiled(P, t, threads, lds, stream);
+            if (s != EXM_OK) return s;
+        }
+        return EXM_OK;
+    }
+    t.tiles = nullptr;
+    t.tile_begin = 0;
+    t.tile_count = plan->n_tiles;
+    return launch_tiled(P, t, threads, lds, stream);
+}
+
+static int32_t run_staged(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
+{
+    const TilePlan* plan = nullptr;
+    int32_t s = build_tile_plan(mesh, ch.tile_cells, &plan);
+    if (s != EXM_OK) return s;
+    const size_t lds = staged_lds_bytes(P.kernel, P.element, plan->max_verts, ch.chunk_layers);
+    EXM_CHECK(lds <= kLdsLimit, EXM_EUNSUPPORTED, "staging does not fit in LDS");
+    P.race = ch.race;
+    P.shape = make_shape(1, 1);
+    const ColArgs a = col_args(P);
+    TileArgs t;
+    fill_tile_args(plan, P, t);
+    if (ch.race == EXM_RACE_COLOUR && continuous(P.element)) {
+        t.tiles = plan->colour_tiles.p;
+        for (int32_t k = 0; k < plan->n_colours; ++k) {
+            t.tile_begin = (int32_t)plan->colour_off[k];
+            t.tile_count = (int32_t)(plan->colour_off[k + 1] - plan->colour_off[k]);
+            s = launch_staged(P, a, t, ch.chunk_layers, lds, stream);
+            if (s != EXM_OK) return s;
+        }
+        return EXM_OK;
+    }
+    if (!continuous(P.element)) P.race = EXM_RACE_ATOMIC;   // nothing is shared
+    t.tiles = nullptr;
+    t.tile_begin = 0;
+    t.tile_count = plan->n_tiles;
+    return launch_staged(P, a, t, ch.chunk_layers, lds, stream);
+}
+
+static int32_t run_on_mesh(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
+{
+    if (ch.schedule == EXM_SCHED_DIRECT) return run_direct(mesh, P, ch, stream);
+    if (ch.schedule == EXM_SCHED_STAGED) return run_staged(mesh, P, ch, stream);
+    return run_tiled(mesh, P, ch, stream);
 }
 
 }  // namespace exm
@@ -223,7 +407,7 @@ int32_t exm_par_loop(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     int32_t s = prepare(kernel, iterset, nargs, args, P);
     if (s != EXM_OK) return s;
     exm_loop_opts ch;
-    s = choose(P, opts, ch);
+    s = choose(iterset, P, opts, ch);
     if (s != EXM_OK) return s;
     s = check_pending();
     if (s != EXM_OK) return s;
@@ -238,7 +422,7 @@ int32_t exm_par_loop_config(int32_t kernel, const exm_mesh* iterset, int32_t nar
     LoopLaunch P;
     int32_t s = prepare(kernel, iterset, nargs, args, P);
     if (s != EXM_OK) return s;
-    return choose(P, opts, *chosen);
+    return choose(iterset, P, opts, *chosen);
 }
 
 int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, const exm_arg* args, void* stream,
@@ -261,27 +445,34 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
         P.out[i] = scratch[i].p;
     }
     std::vector<exm_loop_opts> cand;
+    const bool cg = continuous(P.element);
     const int32_t races[2] = {EXM_RACE_ATOMIC, EXM_RACE_COLOUR};
-    const int nr = continuous(P.element) ? 2 : 1;
-    const int32_t cpws[] = {1, 2, 3, 4, 5, 6, 8};
-    const int32_t wpbs[] = {1, 2, 4};
-    for (int r = 0; r < nr; ++r)
-        for (int32_t c : cpws)
-            for (int32_t w : wpbs) cand.push_back(exm_loop_opts{races[r], c, w, 0});
+    for (int r = 0; r < (cg ? 2 : 1); ++r) {
+        for (int32_t c : {1, 2, 3, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 4, 0, 0});
+        if (staged_supported(P.kernel, P.element))
+            for (int32_t tc : {32, 64, 128, 256})
+                for (int32_t S : {8, 16, 32, 64}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
+        if (cg)
+            for (int32_t t : {32, 64, 128, 256})
+                for (int32_t c : {0, 2, 4})
+                    for (int32_t w : {4, 8}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_TILED, c, w, t, 0});
+    }
     hipEvent_t e0, e1;
     EXM_TRY_HIP(hipEventCreate(&e0));
     EXM_TRY_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
     exm_loop_opts best_opts = cand[0];
     for (const exm_loop_opts& c : cand) {
+        exm_loop_opts ch;
+        if (choose(iterset, P, &c, ch) != EXM_OK) continue;   // e.g. a tile too large for LDS
         LoopLaunch Q = P;
-        s = run_on_mesh(iterset, Q, c, hs);   // warm-up
+        s = run_on_mesh(iterset, Q, ch, hs);   // warm-up
         if (s != EXM_OK) break;
         float t_min = 1e30f;
         for (int rep = 0; rep < 3 && s == EXM_OK; ++rep) {
             EXM_TRY_HIP(hipEventRecord(e0, hs));
             Q = P;
-            s = run_on_mesh(iterset, Q, c, hs);
+            s = run_on_mesh(iterset, Q, ch, hs);
             EXM_TRY_HIP(hipEventRecord(e1, hs));
             EXM_TRY_HIP(hipEventSynchronize(e1));
             float ms = 0;
@@ -291,7 +482,7 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
         if (s != EXM_OK) break;
         if (t_min < best_ms) {
             best_ms = t_min;
-            best_opts = c;
+            best_opts = ch;
         }
     }
     (void)hipEventDestroy(e0);
@@ -313,11 +504,12 @@ int32_t exm_autotune_save(const char* path)
     std::ofstream f(path);
     EXM_CHECK(f.good(), EXM_EINVAL, "cannot open %s", path);
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    f << "# kernel element n_layers log2_cells race cols_per_wave waves_per_block\n";
+    f << "# kernel element n_layers log2_cells race schedule cols_per_wave waves_per_block tile_cells chunk_layers\n";
     for (auto& kv : g_tuned)
         f << std::get<0>(kv.first) << ' ' << std::get<1>(kv.first) << ' ' << std::get<2>(kv.first) << ' '
-          << std::get<3>(kv.first) << ' ' << kv.second.race << ' ' << kv.second.cols_per_wave << ' '
-          << kv.second.waves_per_block << '\n';
+          << std::get<3>(kv.first) << ' ' << kv.second.race << ' ' << kv.second.schedule << ' '
+          << kv.second.cols_per_wave << ' ' << kv.second.waves_per_block << ' ' << kv.second.tile_cells << ' '
+          << kv.second.chunk_layers << '\n';
     return EXM_OK;
 }
 
@@ -334,11 +526,19 @@ int32_t exm_autotune_load(const char* path)
         ++ln;
         if (line.empty() || line[0] == '#') continue;
         std::istringstream is(line);
-        int32_t k, e, l, b, r, c, w;
-        EXM_CHECK((bool)(is >> k >> e >> l >> b >> r >> c >> w), EXM_EINVAL, "%s:%d: malformed line", path, ln);
-        EXM_CHECK((r == EXM_RACE_ATOMIC || r == EXM_RACE_COLOUR) && c >= 1 && c <= 64 && w >= 1 && w <= 4,
+        int32_t k, e, l, b;
+        exm_loop_opts o;
+        EXM_CHECK((bool)(is >> k >> e >> l >> b >> o.race >> o.schedule >> o.cols_per_wave >> o.waves_per_block >>
+                         o.tile_cells >> o.chunk_layers),
+                  EXM_EINVAL, "%s:%d: malformed line", path, ln);
+        EXM_CHECK((o.race == EXM_RACE_ATOMIC || o.race == EXM_RACE_COLOUR) &&
+                      o.schedule >= EXM_SCHED_DIRECT && o.schedule <= EXM_SCHED_STAGED && o.cols_per_wave >= 0 &&
+                      o.cols_per_wave <= 16 && o.waves_per_block >= 1 && o.waves_per_block <= 16 &&
+                      o.tile_cells >= 0 && o.tile_cells <= 1024 &&
+                      (o.chunk_layers == 0 || o.chunk_layers == 8 || o.chunk_layers == 16 || o.chunk_layers == 32 ||
+                       o.chunk_layers == 64),
                   EXM_ERANGE, "%s:%d: values out of range", path, ln);
-        table[TuneKey(k, e, l, b)] = exm_loop_opts{r, c, w, 0};
+        table[TuneKey(k, e, l, b)] = o;
     }
     std::lock_guard<std::mutex> lock(g_tune_mu);
     for (auto& kv : table) g_tuned[kv.first] = kv.second;

@@ -276,6 +276,15 @@ int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t ele
                        dpos.p, mesh->d_cell_vertex.p, mesh->d_cell_edge.p, s->base[0], s->base[1], s->base[2],
                        s->col_size[0], s->col_size[1], s->col_size[2], s->d_map.p);
     EXM_TRY_HIP(hipGetLastError());
+    for (int d = 0; d < 3; ++d) {
+        const int32_t n = mesh->n[d];
+        if (n == 0) continue;
+        st = s->d_starts[d].alloc((size_t)n);
+        if (st != EXM_OK) return st;
+        hipLaunchKernelGGL(k_column_starts, dim3((n + bs - 1) / bs), dim3(bs), 0, hs, n, s->base[d], s->col_size[d],
+                           s->d_starts[d].p);
+        EXM_TRY_HIP(hipGetLastError());
+    }
     // dpos is freed on return: wait for the kernel that reads it.
     EXM_TRY_HIP(hipStreamSynchronize(hs));
     *out = s.release();

@@ -81,6 +81,27 @@ struct Colouring {
     std::vector<int32_t> host_cells;
 };
 
+// Tiles of compact groups of base cells for the LDS-staged column loop.
+struct TilePlan {
+    int32_t target = 0;          // requested cells per tile
+    int32_t n_tiles = 0;
+    int32_t max_cells = 0, max_verts = 0, max_edges = 0;
+    int64_t n_tile_verts = 0;    // sum over tiles of their vertex counts
+    int64_t n_shared_verts = 0;  // ... of which also touched by another tile
+    bool has_edges = false;
+    DevBuf<int32_t> cell_off;    // [n_tiles + 1] into cells / local_cv / local_ce
+    DevBuf<int32_t> cells;       // base cells, tile by tile
+    DevBuf<int32_t> vert_off;    // [n_tiles + 1] into verts
+    DevBuf<int32_t> verts;       // base vertex ids; bit 31 set when shared with another tile
+    DevBuf<int32_t> edge_off;    // [n_tiles + 1] into edges
+    DevBuf<int32_t> edges;       // base edge ids; bit 31 set when shared
+    DevBuf<uint16_t> local_cv;   // [n_cells * 3] tile-local vertex index of each cell vertex
+    DevBuf<uint16_t> local_ce;   // [n_cells * 3] tile-local edge index of each cell edge
+    int32_t n_colours = 0;
+    std::vector<int64_t> colour_off;   // [n_colours + 1] into colour_tiles
+    DevBuf<int32_t> colour_tiles;      // tiles grouped by colour
+};
+
 }  // namespace exm
 
 struct exm_mesh {
@@ -91,6 +112,7 @@ struct exm_mesh {
     exm::DevBuf<int32_t> d_cell_vertex, d_cell_edge;
     mutable std::mutex mu;
     mutable std::unique_ptr<exm::Colouring> colouring;   // built on first use
+    mutable std::vector<std::unique_ptr<exm::TilePlan>> plans;
 };
 
 struct exm_space {
@@ -104,11 +126,13 @@ struct exm_space {
     std::vector<int32_t> offsets;      // [k], Algorithm 2
     std::vector<int32_t> entity_dim;   // [k]
     exm::DevBuf<int32_t> d_map;        // [n_cells * k], explicit lists of layer 0
+    exm::DevBuf<int32_t> d_starts[3];  // column start of every base entity (-1: no column)
 };
 
 namespace exm {
 
 int32_t build_colouring(const exm_mesh* m, const Colouring** out);
+int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out);
 
 // Work decomposition of the column loop.
 struct LoopShape {
@@ -124,6 +148,8 @@ int32_t lookup_tuned(int32_t kernel, int32_t element, int32_t n_layers, int64_t 
 
 // Launch the column loop of one element kernel (validated arguments).
 struct LoopLaunch {
+    const exm_space* fspace;      // field space
+    const exm_space* xspace;      // coordinate space
     int32_t kernel;
     int32_t element;
     int32_t race;

@@ -1,85 +1,75 @@
 // The extruded parallel loop (Algorithm 3 of arXiv 1604.05937) for gfx950.
 //
-// Work decomposition ("vertical lanes").  The vertical-innermost numbering
-// makes the DoFs of one entity column contiguous, so a 64-lane wavefront
-// takes cols_per_wave base cells side by side and gives each 64 / cols_per_wave
-// consecutive lanes, one layer per lane.  A lane reads its cell's explicit
-// lists once, then the wavefront walks the column in steps of `seg` layers:
-// the DoF of stencil position p at layer l is L(c)[p] + l * offset[p], and the
-// `seg` lanes of one cell read `seg` consecutive DoFs of every column, so each
-// gather and scatter is a coalesced run instead of one cache line per lane.
+// Lanes and layers.  The vertical-innermost numbering makes the DoFs of one
+// entity column contiguous, so a 64-lane wavefront takes cpw base cells side
+// by side and gives each seg = 64 / cpw consecutive lanes, one layer per lane.
+// A lane reads its cell's explicit lists once; the DoF of stencil position p
+// at layer l is L(c)[p] + l * offset[p], so the seg lanes of one cell read seg
+// consecutive DoFs of every column: each gather and scatter is a coalesced run
+// rather than one cache line per lane.  A value on the top level of layer l is
+// the bottom-level value of layer l + 1, so it is taken from the next lane
+// with a cross-lane shuffle instead of a second load.
 //
-// DoFs on horizontal levels are shared by the layers below and above (CG in
-// the vertical).  A lane adds its top-level contribution to the next lane's
-// bottom-level one through a cross-lane shuffle (the first lane of a step
-// takes it from a carry left by the previous step), so every level of every
-// column receives exactly one update per base cell.
+// Vertically shared levels.  The top-level contribution of a lane is added to
+// the next lane's bottom-level one through a shuffle, so every level of every
+// column receives one update per base cell and step.
 //
-// Horizontal sharing (CG in the horizontal) is resolved either by hardware
-// FP64 atomic adds or by launching one colour of base cells at a time.
+// Two schedules (see exm.h):
+//  * DIRECT: wavefronts walk whole columns of their own cells in steps of seg
+//    layers and update the output directly -- hardware FP64 atomic adds, or
+//    plain read-add-write when one launch holds one colour of base cells.
+//  * TILED: a workgroup owns a compact tile of base cells; its wavefronts walk
+//    the tile's cells step by step and sum the updates of every (vertex or
+//    edge, level) of the tile in LDS, then the workgroup adds each sum to HBM
+//    once -- atomically only for entities another tile also touches, or with
+//    plain read-add-write when one launch holds one colour of tiles.  Columns
+//    of DG spaces belong to one cell, so those run DIRECT.
+//
+// Vector fields (the coordinates) are stored component-major: component i of
+// DoF n at X[i * n_dofs + n], so each component of a column is one contiguous
+// run as well.
 #include <algorithm>
 
 #include "exm_elements.hpp"
 #include "exm_internal.hpp"
+#include "exm_tiled.hpp"
 
 namespace exm {
 
-struct ColArgs {
-    int32_t n_layers;
-    int32_t off;           // vertical offset of the field space (same for every position)
-    int32_t cpw, seg;
-    const int32_t* __restrict__ fmap;
-    const int32_t* __restrict__ xmap;
-    const double* __restrict__ X;
-    const double* __restrict__ in0;
-    const double* __restrict__ in1;
-    const double* __restrict__ in2;
-    double* __restrict__ out0;
-    double* __restrict__ out1;
-    double* __restrict__ out2;
-    const int32_t* __restrict__ cells;
-    int64_t cell_begin, cell_count;
-};
-
 // Workgroups are dispatched to the eight XCDs round-robin; renumber them so
-// that every XCD (and its L2) works through one contiguous range of cells.
+// that every XCD (and its L2) works through one contiguous range of work.
 __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned G)
 {
     const unsigned q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-struct LaneInfo {
+struct Lane {
     int lane, sub, lsub;
-    bool valid;
-    int32_t cell;
 };
 
-template <bool LIST>
-__device__ __forceinline__ bool lane_info(const ColArgs& a, LaneInfo& L)
+__device__ __forceinline__ Lane lane_of(int seg)
 {
-    const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+    Lane L;
     L.lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (wave * a.cpw >= a.cell_count) return false;   // uniform over the wavefront
-    L.sub = L.lane / a.seg;
-    L.lsub = L.lane - L.sub * a.seg;
-    const int64_t slot = wave * a.cpw + L.sub;
-    L.valid = L.sub < a.cpw && slot < a.cell_count;
-    L.cell = 0;
-    if (L.valid) L.cell = LIST ? a.cells[a.cell_begin + slot] : (int32_t)(a.cell_begin + slot);
-    return true;
+    L.sub = L.lane / seg;
+    L.lsub = L.lane - L.sub * seg;
+    return L;
 }
 
-// Value of a vertically shared level for the lane's layer l: the lane's own
-// bottom contribution plus the top contribution of layer l - 1.
-__device__ __forceinline__ double level_value(double bot, double top, double& carry, const LaneInfo& L, int seg)
+// The value the next lane holds (level l + 1 of the same column when this lane
+// is not the last of its column segment); the segment's last lane loads it.
+__device__ __forceinline__ double from_above(double mine, const double* next_addr, bool load_it)
 {
-    const double below = __shfl(top, (L.lane + 63) & 63, 64);
-    const double last = __shfl(top, min(L.sub * seg + seg - 1, 63), 64);
-    const double v = bot + (L.lsub == 0 ? carry : below);
-    carry = last;
+    double v = __shfl_down(mine, 1, 64);
+    if (load_it) v = *next_addr;
     return v;
+}
+
+// Top-level contribution of layer l - 1, held by the previous lane.
+__device__ __forceinline__ double from_below(double top)
+{
+    return __shfl_up(top, 1, 64);
 }
 
 template <int RACE>
@@ -91,340 +81,525 @@ __device__ __forceinline__ void inc(double* p, double v)
         *p += v;
 }
 
-// Coordinates of the prism's base triangle and its column heights at layer l.
-// xb[a], xt[a]: bottom and top DoFs of base vertex a in the coordinate space
-// (offset 1 per layer).
-__device__ __forceinline__ void prism_geometry(const double* __restrict__ X, const int xb[3], const int xt[3], int l,
-                                               double& twoA, double h[3])
-{
+// (x, y) of the three base vertices, read once per cell: columns are vertical,
+// so the coordinate field holds the same (x, y) at every level of a column.
+// xb[a]: DoF of base vertex a at level 0 in the coordinate space; xn: its DoF
+// count (component stride).
+struct BaseXY {
     double x[3], y[3];
+};
+
+__device__ __forceinline__ BaseXY base_xy(const double* __restrict__ X, int64_t xn, const int xb[3], bool valid)
+{
+    BaseXY g;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double* pb = X + 3 * (int64_t)(xb[a] + l);
-        x[a] = pb[0];
-        y[a] = pb[1];
-        h[a] = X[3 * (int64_t)(xt[a] + l) + 2] - pb[2];
+        g.x[a] = valid ? X[xb[a]] : 0.0;
+        g.y[a] = valid ? X[xn + xb[a]] : 0.0;
     }
-    twoA = twice_area(x, y);
+    return g;
 }
 
-__device__ __forceinline__ void load_coord_map(const ColArgs& a, const LaneInfo& L, int xb[3], int xt[3])
+// Geometry of the prism above the lane's layer l: twice the area of the base
+// triangle and the three column heights (top z shuffled from the next lane).
+__device__ __forceinline__ void geometry(const double* __restrict__ X, int64_t xn, const int xb[3], const BaseXY& g,
+                                         int l, bool act, bool last, double& twoA, double h[3])
 {
+    double zb[3];
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-        xb[v] = L.valid ? a.xmap[(int64_t)L.cell * 6 + 2 * v] : 0;
-        xt[v] = L.valid ? a.xmap[(int64_t)L.cell * 6 + 2 * v + 1] : 0;
+    for (int a = 0; a < 3; ++a) zb[a] = act ? X[2 * xn + (int64_t)xb[a] + l] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double zt = from_above(zb[a], X + 2 * xn + (int64_t)xb[a] + l + 1, act && last);
+        h[a] = zt - zb[a];
     }
+    twoA = twice_area(g.x, g.y);
 }
 
 // ---------------------------------------------------------------------------
-// P1 x P1 mass action / residual of the integral of f v: y (+)= M x.
+// P1 x P1 element kernels on one lane.  FORM 0: mass (in0 -> y0); 1: cubic
+// residual (u, f -> F); 2: cubic VJP (u, w -> g_u, g_f); 3: fused (u, f, w ->
+// F, g_u, g_f).  b[k][a], t[k][a]: input k at the bottom / top node of vertex a.
 
-template <int RACE, bool LIST>
-__global__ void __launch_bounds__(256) k_mass_p1(const ColArgs a)
+template <int FORM>
+struct P1Form {
+    static constexpr int NIN = FORM == 0 ? 1 : (FORM == 3 ? 3 : 2);
+    static constexpr int NOUT = FORM == 0 ? 1 : (FORM == 1 ? 1 : (FORM == 2 ? 2 : 3));
+};
+
+template <int FORM>
+__device__ __forceinline__ void p1_element(double twoA, const double h[3], const double b[][3], const double t[][3],
+                                           double yb[][3], double yt[][3])
 {
-    LaneInfo L;
-    if (!lane_info<LIST>(a, L)) return;
-    int fb[3], ft[3], xb[3], xt[3];
+    if constexpr (FORM == 0) {
+        p1_mass(twoA, h, b[0], t[0], yb[0], yt[0]);
+    } else {
+        CubicRule Q;
+        cubic_rule(Q);
+        double W[7][3], uq[7][3];
+        cubic_weights(Q, twoA, h, W);
+        p1_at_points(Q, b[0], t[0], uq);
+        if constexpr (FORM == 1 || FORM == 3) {
+            double fq[7][3], s[7][3];
+            p1_at_points(Q, b[1], t[1], fq);
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-        fb[v] = L.valid ? a.fmap[(int64_t)L.cell * 6 + 2 * v] : 0;
-        ft[v] = L.valid ? a.fmap[(int64_t)L.cell * 6 + 2 * v + 1] : 0;
-    }
-    load_coord_map(a, L, xb, xt);
-    double carry[3] = {0.0, 0.0, 0.0};
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
-        const int l = l0 + L.lsub;
-        const bool act = L.valid && l < a.n_layers;
-        const int lo = l * a.off;
-        double yb[3] = {0.0, 0.0, 0.0}, yt[3] = {0.0, 0.0, 0.0};
-        if (act) {
-            double xbv[3], xtv[3], h[3], twoA;
+            for (int i = 0; i < 7; ++i)
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                xbv[v] = a.in0[fb[v] + lo];
-                xtv[v] = a.in0[ft[v] + lo];
-            }
-            prism_geometry(a.X, xb, xt, l, twoA, h);
-            p1_mass(twoA, h, xbv, xtv, yb, yt);
+                for (int j = 0; j < 3; ++j) s[i][j] = W[i][j] * (uq[i][j] * uq[i][j] * uq[i][j] - fq[i][j]);
+            p1_test(Q, s, yb[0], yt[0]);
         }
+        if constexpr (FORM == 2 || FORM == 3) {
+            constexpr int wi = FORM == 2 ? 1 : 2;
+            constexpr int og = FORM == 2 ? 0 : 1;
+            double wq[7][3], s[7][3], mb[3], mt[3];
+            p1_at_points(Q, b[wi], t[wi], wq);
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) s[i][j] = W[i][j] * 3.0 * uq[i][j] * uq[i][j] * wq[i][j];
+            p1_test(Q, s, yb[og], yt[og]);
+            p1_mass(twoA, h, b[wi], t[wi], mb, mt);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                yb[og + 1][a] = -mb[a];
+                yt[og + 1][a] = -mt[a];
+            }
+        }
+    }
+}
+
+// Gather the inputs of a P1 lane and evaluate its element: level values of
+// every output at the lane's own level (bottom contribution of layer l plus
+// top contribution of layer l - 1 from the previous lane; `first` lanes get
+// only their bottom) and the top-level contribution yt.
+template <int FORM>
+__device__ __forceinline__ void p1_lane(const ColArgs& a, const int fb[3], const int xb[3], const BaseXY& g, int l,
+                                        bool act, bool last, bool first, double lev[][3], double yt[][3])
+{
+    constexpr int NIN = P1Form<FORM>::NIN;
+    constexpr int NOUT = P1Form<FORM>::NOUT;
+    const double* in[3] = {a.in0, a.in1, a.in2};
+    double b[NIN][3], t[NIN][3];
+    const int lo = l * a.off;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) b[k][v] = act ? in[k][fb[v] + lo] : 0.0;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) t[k][v] = from_above(b[k][v], in[k] + fb[v] + lo + a.off, act && last);
+    double twoA, h[3];
+    geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
+    double yb[NOUT][3];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) yb[o][v] = yt[o][v] = 0.0;
+    if (act) p1_element<FORM>(twoA, h, b, t, yb, yt);
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o)
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-            const double lv = level_value(yb[v], yt[v], carry[v], L, a.seg);
-            if (act) {
-                inc<RACE>(a.out0 + fb[v] + lo, lv);
-                if (l == a.n_layers - 1) inc<RACE>(a.out0 + ft[v] + lo, yt[v]);
-            }
+            const double below = from_below(yt[o][v]);
+            lev[o][v] = yb[o][v] + (first ? 0.0 : below);
         }
-    }
 }
 
 // ---------------------------------------------------------------------------
-// DG0 x DG0 mass action: one DoF per prism, no sharing.
+// DIRECT schedule.
 
-template <bool LIST>
-__global__ void __launch_bounds__(256) k_mass_dg0(const ColArgs a, int write)
+__device__ __forceinline__ bool direct_cell(const ColArgs& a, const Lane& L, int32_t& cell, bool& valid)
 {
-    LaneInfo L;
-    if (!lane_info<LIST>(a, L)) return;
-    const int f0 = L.valid ? a.fmap[L.cell] : 0;
-    int xb[3], xt[3];
-    load_coord_map(a, L, xb, xt);
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
-        const int l = l0 + L.lsub;
-        if (!(L.valid && l < a.n_layers)) continue;
-        double h[3], twoA;
-        prism_geometry(a.X, xb, xt, l, twoA, h);
-        const int d = f0 + l * a.off;
-        const double y = dg0_mass(twoA, h, a.in0[d]);
-        if (write)
-            a.out0[d] = y;
-        else
-            a.out0[d] += y;
-    }
+    const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t wave = (int64_t)blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (wave * a.cpw >= a.cell_count) return false;   // uniform over the wavefront
+    const int64_t slot = wave * a.cpw + L.sub;
+    valid = L.sub < a.cpw && slot < a.cell_count;
+    cell = valid ? (a.cells ? a.cells[a.cell_begin + slot] : (int32_t)(a.cell_begin + slot)) : 0;
+    return true;
 }
 
-// ---------------------------------------------------------------------------
-// DG1 x DG1 mass action: six DoFs per prism, no sharing.  Position p of the
-// list is horizontal node p / 2 (at vertex p / 2), vertical node p % 2.
-
-template <bool LIST>
-__global__ void __launch_bounds__(256) k_mass_dg1(const ColArgs a, int write)
+template <int FORM, int RACE>
+__global__ void __launch_bounds__(256) k_direct_p1(const ColArgs a)
 {
-    LaneInfo L;
-    if (!lane_info<LIST>(a, L)) return;
-    int fm[6];
-#pragma unroll
-    for (int p = 0; p < 6; ++p) fm[p] = L.valid ? a.fmap[(int64_t)L.cell * 6 + p] : 0;
-    int xb[3], xt[3];
-    load_coord_map(a, L, xb, xt);
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
-        const int l = l0 + L.lsub;
-        if (!(L.valid && l < a.n_layers)) continue;
-        const int lo = l * a.off;
-        double xbv[3], xtv[3], yb[3], yt[3], h[3], twoA;
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            xbv[v] = a.in0[fm[2 * v] + lo];
-            xtv[v] = a.in0[fm[2 * v + 1] + lo];
-        }
-        prism_geometry(a.X, xb, xt, l, twoA, h);
-        p1_mass(twoA, h, xbv, xtv, yb, yt);
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-            if (write) {
-                a.out0[fm[2 * v] + lo] = yb[v];
-                a.out0[fm[2 * v + 1] + lo] = yt[v];
-            } else {
-                a.out0[fm[2 * v] + lo] += yb[v];
-                a.out0[fm[2 * v + 1] + lo] += yt[v];
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// P2 x P2 mass action.  Position 3e + beta of the list: horizontal node e
-// (vertices 0..2, edges 0..2), vertical node beta (bottom, top, middle).
-
-template <int RACE, bool LIST>
-__global__ void __launch_bounds__(256) k_mass_p2(const ColArgs a)
-{
-    LaneInfo L;
-    if (!lane_info<LIST>(a, L)) return;
-    int fm[18];
-#pragma unroll
-    for (int p = 0; p < 18; ++p) fm[p] = L.valid ? a.fmap[(int64_t)L.cell * 18 + p] : 0;
-    int xb[3], xt[3];
-    load_coord_map(a, L, xb, xt);
-    double carry[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
-        const int l = l0 + L.lsub;
-        const bool act = L.valid && l < a.n_layers;
-        const int lo = l * a.off;
-        double y[6][3];
-#pragma unroll
-        for (int e = 0; e < 6; ++e) y[e][0] = y[e][1] = y[e][2] = 0.0;
-        if (act) {
-            double x[6][3], h[3], twoA;
-#pragma unroll
-            for (int e = 0; e < 6; ++e)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) x[e][b] = a.in0[fm[3 * e + b] + lo];
-            prism_geometry(a.X, xb, xt, l, twoA, h);
-            p2_mass(twoA, h, x, y);
-        }
-#pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            const double lv = level_value(y[e][0], y[e][1], carry[e], L, a.seg);
-            if (act) {
-                inc<RACE>(a.out0 + fm[3 * e] + lo, lv);
-                inc<RACE>(a.out0 + fm[3 * e + 2] + lo, y[e][2]);
-                if (l == a.n_layers - 1) inc<RACE>(a.out0 + fm[3 * e + 1] + lo, y[e][1]);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Cubic residual F = integral (u^3 - f) v and its vector-Jacobian product
-// with cotangent w:  g_u = integral 3 u^2 w v,  g_f = -integral w v = -M w.
-// MODE 0: F (in0 = u, in1 = f; out0 = F)
-// MODE 1: g_u, g_f (in0 = u, in1 = w; out0 = g_u, out1 = g_f)
-// MODE 2: F, g_u, g_f (in0 = u, in1 = f, in2 = w; out0 = F, out1 = g_u, out2 = g_f)
-// The adjoint reads w where the forward scatters F and scatters g_u, g_f where
-// the forward gathers u, f.
-
-template <int MODE, int RACE, bool LIST>
-__global__ void __launch_bounds__(256) k_cubic_p1(const ColArgs a)
-{
-    constexpr int NOUT = MODE == 0 ? 1 : (MODE == 1 ? 2 : 3);
-    LaneInfo L;
-    if (!lane_info<LIST>(a, L)) return;
-    int fb[3], ft[3], xb[3], xt[3];
+    constexpr int NOUT = P1Form<FORM>::NOUT;
+    const Lane L = lane_of(a.seg);
+    int32_t cell;
+    bool valid;
+    if (!direct_cell(a, L, cell, valid)) return;
+    int fb[3], xb[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
-        fb[v] = L.valid ? a.fmap[(int64_t)L.cell * 6 + 2 * v] : 0;
-        ft[v] = L.valid ? a.fmap[(int64_t)L.cell * 6 + 2 * v + 1] : 0;
+        fb[v] = valid ? a.fmap[(int64_t)cell * 6 + 2 * v] : 0;
+        xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
     }
-    load_coord_map(a, L, xb, xt);
-    CubicRule R;
-    cubic_rule(R);
+    double* out[3] = {a.out0, a.out1, a.out2};
+    const BaseXY g = base_xy(a.X, a.xn, xb, valid);
     double carry[NOUT][3];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) carry[o][0] = carry[o][1] = carry[o][2] = 0.0;
-    double* outs[3] = {a.out0, a.out1, a.out2};
     for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
         const int l = l0 + L.lsub;
-        const bool act = L.valid && l < a.n_layers;
+        const bool act = valid && l < a.n_layers;
+        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        double lev[NOUT][3], yt[NOUT][3];
+        p1_lane<FORM>(a, fb, xb, g, l, act, last, L.lsub == 0, lev, yt);
         const int lo = l * a.off;
-        double yb[NOUT][3], yt[NOUT][3];
 #pragma unroll
         for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-            for (int v = 0; v < 3; ++v) yb[o][v] = yt[o][v] = 0.0;
-        if (act) {
-            double h[3], twoA;
-            prism_geometry(a.X, xb, xt, l, twoA, h);
-            double W[7][3];
-            cubic_weights(R, twoA, h, W);
-            double ub[3], ut[3];
-#pragma unroll
             for (int v = 0; v < 3; ++v) {
-                ub[v] = a.in0[fb[v] + lo];
-                ut[v] = a.in0[ft[v] + lo];
-            }
-            double uq[7][3];
-            p1_at_points(R, ub, ut, uq);
-            if constexpr (MODE == 0 || MODE == 2) {
-                double fbv[3], ftv[3], fq[7][3], s[7][3];
-#pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    fbv[v] = a.in1[fb[v] + lo];
-                    ftv[v] = a.in1[ft[v] + lo];
+                // the segment's first lane takes the previous step's top contribution
+                const double val = lev[o][v] + (L.lsub == 0 ? carry[o][v] : 0.0);
+                carry[o][v] = __shfl(yt[o][v], min(L.sub * a.seg + a.seg - 1, 63), 64);
+                if (act) {
+                    inc<RACE>(out[o] + fb[v] + lo, val);
+                    if (l == a.n_layers - 1) inc<RACE>(out[o] + fb[v] + lo + a.off, yt[o][v]);
                 }
-                p1_at_points(R, fbv, ftv, fq);
-#pragma unroll
-                for (int i = 0; i < 7; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) s[i][j] = W[i][j] * (uq[i][j] * uq[i][j] * uq[i][j] - fq[i][j]);
-                p1_test(R, s, yb[0], yt[0]);
             }
-            if constexpr (MODE == 1 || MODE == 2) {
-                const double* w = MODE == 1 ? a.in1 : a.in2;
-                double wb[3], wt[3], wq[7][3], s[7][3];
+    }
+}
+
+// DG0 x DG0 mass action: one DoF per prism (L(c)[0] + l), no sharing.
+__global__ void __launch_bounds__(256) k_direct_dg0(const ColArgs a)
+{
+    const Lane L = lane_of(a.seg);
+    int32_t cell;
+    bool valid;
+    if (!direct_cell(a, L, cell, valid)) return;
+    const int f0 = valid ? a.fmap[cell] : 0;
+    int xb[3];
 #pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    wb[v] = w[fb[v] + lo];
-                    wt[v] = w[ft[v] + lo];
-                }
-                p1_at_points(R, wb, wt, wq);
+    for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+    const BaseXY g = base_xy(a.X, a.xn, xb, valid);
+    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+        const int l = l0 + L.lsub;
+        const bool act = valid && l < a.n_layers;
+        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        double twoA, h[3];
+        geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
+        if (act) {
+            const int64_t d = f0 + (int64_t)l * a.off;
+            const double y = dg0_mass(twoA, h, a.in0[d]);
+            if (a.write)
+                a.out0[d] = y;
+            else
+                a.out0[d] += y;
+        }
+    }
+}
+
+// DG1 x DG1 mass action: six consecutive DoFs per prism, L(c)[p] + 6 l; position
+// p is horizontal node p / 2 (at vertex p / 2) and vertical node p % 2.
+__global__ void __launch_bounds__(256) k_direct_dg1(const ColArgs a)
+{
+    const Lane L = lane_of(a.seg);
+    int32_t cell;
+    bool valid;
+    if (!direct_cell(a, L, cell, valid)) return;
+    const int f0 = valid ? a.fmap[(int64_t)cell * 6] : 0;
+    int xb[3];
 #pragma unroll
-                for (int i = 0; i < 7; ++i)
+    for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+    const BaseXY g = base_xy(a.X, a.xn, xb, valid);
+    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+        const int l = l0 + L.lsub;
+        const bool act = valid && l < a.n_layers;
+        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        double twoA, h[3];
+        geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
+        if (act) {
+            const int64_t d = f0 + (int64_t)l * a.off;
+            double xb_[3], xt_[3], yb[3], yt[3];
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) s[i][j] = W[i][j] * 3.0 * uq[i][j] * uq[i][j] * wq[i][j];
-                constexpr int og = MODE == 1 ? 0 : 1;
-                p1_test(R, s, yb[og], yt[og]);
-                double mb[3], mt[3];
-                p1_mass(twoA, h, wb, wt, mb, mt);
+            for (int q = 0; q < 3; ++q) {
+                xb_[q] = a.in0[d + 2 * q];
+                xt_[q] = a.in0[d + 2 * q + 1];
+            }
+            p1_mass(twoA, h, xb_, xt_, yb, yt);
 #pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    yb[og + 1][v] = -mb[v];
-                    yt[og + 1][v] = -mt[v];
+            for (int q = 0; q < 3; ++q) {
+                if (a.write) {
+                    a.out0[d + 2 * q] = yb[q];
+                    a.out0[d + 2 * q + 1] = yt[q];
+                } else {
+                    a.out0[d + 2 * q] += yb[q];
+                    a.out0[d + 2 * q + 1] += yt[q];
                 }
             }
         }
+    }
+}
+
+// P2 x P2 on one lane.  Entity e (vertices 0..2, edges 0..2) has its level
+// nodes at L(c)[3e] + 2 l (bottom) and + 2 (top), its middle node at
+// L(c)[3e + 2] + 2 l.  lev[e]: bottom value plus the top value of layer l - 1;
+// yt[e]: top contribution; ym[e]: middle-node value.
+__device__ __forceinline__ void p2_lane(const ColArgs& a, const int fb[6], const int fm[6], const int xb[3],
+                                        const BaseXY& g, int l, bool act, bool last, bool first, double lev[6],
+                                        double yt[6], double ym[6])
+{
+    double x[6][3], y[6][3];
+    const int lo = l * a.off;
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o)
+    for (int e = 0; e < 6; ++e) {
+        x[e][0] = act ? a.in0[fb[e] + lo] : 0.0;
+        x[e][2] = act ? a.in0[fm[e] + lo] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) x[e][1] = from_above(x[e][0], a.in0 + fb[e] + lo + a.off, act && last);
+    double twoA, h[3];
+    geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) y[e][0] = y[e][1] = y[e][2] = 0.0;
+    if (act) p2_mass(twoA, h, x, y);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const double below = from_below(y[e][1]);
+        lev[e] = y[e][0] + (first ? 0.0 : below);
+        yt[e] = y[e][1];
+        ym[e] = y[e][2];
+    }
+}
+
+template <int RACE>
+__global__ void __launch_bounds__(256) k_direct_p2(const ColArgs a)
+{
+    const Lane L = lane_of(a.seg);
+    int32_t cell;
+    bool valid;
+    if (!direct_cell(a, L, cell, valid)) return;
+    int fb[6], fm[6], xb[3];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        fb[e] = valid ? a.fmap[(int64_t)cell * 18 + 3 * e] : 0;
+        fm[e] = valid ? a.fmap[(int64_t)cell * 18 + 3 * e + 2] : 0;
+    }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+    const BaseXY g = base_xy(a.X, a.xn, xb, valid);
+    double carry[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+        const int l = l0 + L.lsub;
+        const bool act = valid && l < a.n_layers;
+        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        double lev[6], yt[6], ym[6];
+        p2_lane(a, fb, fm, xb, g, l, act, last, L.lsub == 0, lev, yt, ym);
+        const int lo = l * a.off;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const double val = lev[e] + (L.lsub == 0 ? carry[e] : 0.0);
+            carry[e] = __shfl(yt[e], min(L.sub * a.seg + a.seg - 1, 63), 64);
+            if (act) {
+                inc<RACE>(a.out0 + fb[e] + lo, val);
+                inc<RACE>(a.out0 + fm[e] + lo, ym[e]);
+                if (l == a.n_layers - 1) inc<RACE>(a.out0 + fb[e] + lo + a.off, yt[e]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TILED schedule: per-tile sums in LDS.
+
+__device__ __forceinline__ int32_t entity_id(int32_t tagged) { return tagged & 0x7fffffff; }
+__device__ __forceinline__ bool entity_shared(int32_t tagged) { return tagged < 0; }
+
+template <bool ATOMIC>
+__device__ __forceinline__ void global_add(double* p, double v, bool shared)
+{
+    if (ATOMIC && shared)
+        unsafeAtomicAdd(p, v);
+    else
+        *p += v;
+}
+
+struct TileRange {
+    int32_t cb, nc, vb, nv, eb, ne;
+};
+
+__device__ __forceinline__ TileRange tile_range(const ColArgs& a, const TileArgs& t)
+{
+    TileRange r;
+    const int32_t b = (int32_t)xcd_block(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + b] : t.tile_begin + b;
+    r.cb = t.cell_off[tile];
+    r.nc = t.cell_off[tile + 1] - r.cb;
+    r.vb = t.vert_off[tile];
+    r.nv = t.vert_off[tile + 1] - r.vb;
+    if (t.edge_off) {
+        r.eb = t.edge_off[tile];
+        r.ne = t.edge_off[tile + 1] - r.eb;
+    } else {
+        r.eb = r.ne = 0;
+    }
+    return r;
+}
+
+// LDS layout: acc[o][slot * P + j] for output o, entity slot, position j in
+// 0 .. P - 1 (P = seg + 1 levels for P1, 2 seg + 1 nodes for P2), then
+// carry[o][slot].
+template <int FORM, bool ATOMIC>
+__global__ void __launch_bounds__(512) k_tiled_p1(const ColArgs a, const TileArgs t)
+{
+    constexpr int NOUT = P1Form<FORM>::NOUT;
+    extern __shared__ double lds[];
+    const Lane L = lane_of(a.seg);
+    const TileRange R = tile_range(a, t);
+    const int P = a.seg + 1;
+    const int SP = t.vstride * P;
+    double* acc = lds;
+    double* carry = acc + NOUT * SP;
+    double* out[3] = {a.out0, a.out1, a.out2};
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < NOUT * R.nv; i += blockDim.x) carry[(i / R.nv) * t.vstride + i % R.nv] = 0.0;
+    __syncthreads();
+    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+        const int nl = min(a.seg, a.n_layers - l0);
+        const int nlev = nl + 1;
+        const bool last_step = l0 + nl == a.n_layers;
+        for (int i = threadIdx.x; i < R.nv * nlev; i += blockDim.x) {
+            const int v = i / nlev;
+            const int j = i - v * nlev;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) acc[o * SP + v * P + j] = j == 0 ? carry[o * t.vstride + v] : 0.0;
+        }
+        __syncthreads();
+        for (int g = wave; g * a.cpw < R.nc; g += nwaves) {   // uniform over the wavefront
+            const int slot = g * a.cpw + L.sub;
+            const bool valid = L.sub < a.cpw && slot < R.nc;
+            const int32_t cell = valid ? t.cells[R.cb + slot] : 0;
+            int fb[3], xb[3], lv[3];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
-                const double lv = level_value(yb[o][v], yt[o][v], carry[o][v], L, a.seg);
-                if (act) {
-                    inc<RACE>(outs[o] + fb[v] + lo, lv);
-                    if (l == a.n_layers - 1) inc<RACE>(outs[o] + ft[v] + lo, yt[o][v]);
+                fb[v] = valid ? a.fmap[(int64_t)cell * 6 + 2 * v] : 0;
+                xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+                lv[v] = valid ? t.lcv[(int64_t)(R.cb + slot) * 3 + v] : 0;
+            }
+            const int l = l0 + L.lsub;
+            const bool act = valid && L.lsub < nl;
+            const bool last = L.lsub == nl - 1;
+            const BaseXY gxy = base_xy(a.X, a.xn, xb, valid);
+            double lev[NOUT][3], yt[NOUT][3];
+            p1_lane<FORM>(a, fb, xb, gxy, l, act, last, L.lsub == 0, lev, yt);
+            if (act) {
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) {
+                        atomicAdd(acc + o * SP + lv[v] * P + L.lsub, lev[o][v]);
+                        if (last) atomicAdd(acc + o * SP + lv[v] * P + nl, yt[o][v]);
+                    }
+            }
+        }
+        __syncthreads();
+        const int nflush = last_step ? nlev : nl;
+        for (int i = threadIdx.x; i < R.nv * nlev; i += blockDim.x) {
+            const int v = i / nlev;
+            const int j = i - v * nlev;
+            const int32_t tag = t.verts[R.vb + v];
+            if (j < nflush) {
+                const int64_t d = (int64_t)t.fstart0[entity_id(tag)] + (int64_t)(l0 + j) * a.off;
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o) global_add<ATOMIC>(out[o] + d, acc[o * SP + v * P + j], entity_shared(tag));
+            } else {
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o) carry[o * t.vstride + v] = acc[o * SP + v * P + j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <bool ATOMIC>
+__global__ void __launch_bounds__(512) k_tiled_p2(const ColArgs a, const TileArgs t)
+{
+    extern __shared__ double lds[];
+    const Lane L = lane_of(a.seg);
+    const TileRange R = tile_range(a, t);
+    const int P = 2 * a.seg + 1;
+    const int ES = t.vstride + t.estride;
+    double* acc = lds;
+    double* carry = acc + ES * P;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int nent = R.nv + R.ne;
+    for (int i = threadIdx.x; i < ES; i += blockDim.x) carry[i] = 0.0;
+    __syncthreads();
+    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+        const int nl = min(a.seg, a.n_layers - l0);
+        const int npos = 2 * nl + 1;
+        const bool last_step = l0 + nl == a.n_layers;
+        for (int i = threadIdx.x; i < nent * npos; i += blockDim.x) {
+            const int e = i / npos;
+            const int jj = i - e * npos;
+            const int slot = e < R.nv ? e : t.vstride + (e - R.nv);
+            acc[slot * P + jj] = jj == 0 ? carry[slot] : 0.0;
+        }
+        __syncthreads();
+        for (int g = wave; g * a.cpw < R.nc; g += nwaves) {
+            const int slot = g * a.cpw + L.sub;
+            const bool valid = L.sub < a.cpw && slot < R.nc;
+            const int32_t cell = valid ? t.cells[R.cb + slot] : 0;
+            int fb[6], fm[6], xb[3], es[6];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                fb[e] = valid ? a.fmap[(int64_t)cell * 18 + 3 * e] : 0;
+                fm[e] = valid ? a.fmap[(int64_t)cell * 18 + 3 * e + 2] : 0;
+            }
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+                es[v] = valid ? t.lcv[(int64_t)(R.cb + slot) * 3 + v] : 0;
+                es[3 + v] = valid ? t.vstride + t.lce[(int64_t)(R.cb + slot) * 3 + v] : 0;
+            }
+            const int l = l0 + L.lsub;
+            const bool act = valid && L.lsub < nl;
+            const bool last = L.lsub == nl - 1;
+            const BaseXY gxy = base_xy(a.X, a.xn, xb, valid);
+            double lev[6], yt[6], ym[6];
+            p2_lane(a, fb, fm, xb, gxy, l, act, last, L.lsub == 0, lev, yt, ym);
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    atomicAdd(acc + es[e] * P + 2 * L.lsub, lev[e]);
+                    atomicAdd(acc + es[e] * P + 2 * L.lsub + 1, ym[e]);
+                    if (last) atomicAdd(acc + es[e] * P + 2 * nl, yt[e]);
                 }
             }
+        }
+        __syncthreads();
+        const int nflush = last_step ? npos : npos - 1;
+        for (int i = threadIdx.x; i < nent * npos; i += blockDim.x) {
+            const int e = i / npos;
+            const int jj = i - e * npos;
+            const int slot = e < R.nv ? e : t.vstride + (e - R.nv);
+            const int32_t tag = e < R.nv ? t.verts[R.vb + e] : t.edges[R.eb + e - R.nv];
+            if (jj < nflush) {
+                const int32_t start = e < R.nv ? t.fstart0[entity_id(tag)] : t.fstart1[entity_id(tag)];
+                global_add<ATOMIC>(a.out0 + (int64_t)start + (int64_t)l0 * a.off + jj, acc[slot * P + jj],
+                                   entity_shared(tag));
+            } else {
+                carry[slot] = acc[slot * P + jj];
+            }
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Dispatch.
 
-template <bool LIST>
-static int32_t dispatch(const LoopLaunch& P, const ColArgs& a, dim3 grid, dim3 block, hipStream_t s)
+ColArgs col_args(const LoopLaunch& P)
 {
-    const bool atomic = P.race == EXM_RACE_ATOMIC;
-#define EXM_LAUNCH(K) hipLaunchKernelGGL(K, grid, block, 0, s, a)
-    switch (P.element) {
-    case EXM_ELEMENT_P1P1:
-        switch (P.kernel) {
-        case EXM_K_MASS:
-            if (atomic) EXM_LAUNCH((k_mass_p1<EXM_RACE_ATOMIC, LIST>));
-            else EXM_LAUNCH((k_mass_p1<EXM_RACE_COLOUR, LIST>));
-            break;
-        case EXM_K_CUBIC:
-            if (atomic) EXM_LAUNCH((k_cubic_p1<0, EXM_RACE_ATOMIC, LIST>));
-            else EXM_LAUNCH((k_cubic_p1<0, EXM_RACE_COLOUR, LIST>));
-            break;
-        case EXM_K_CUBIC_VJP:
-            if (atomic) EXM_LAUNCH((k_cubic_p1<1, EXM_RACE_ATOMIC, LIST>));
-            else EXM_LAUNCH((k_cubic_p1<1, EXM_RACE_COLOUR, LIST>));
-            break;
-        case EXM_K_CUBIC_FUSED:
-            if (atomic) EXM_LAUNCH((k_cubic_p1<2, EXM_RACE_ATOMIC, LIST>));
-            else EXM_LAUNCH((k_cubic_p1<2, EXM_RACE_COLOUR, LIST>));
-            break;
-        default: return fail(EXM_EUNSUPPORTED, "kernel %d not available on P1xP1", P.kernel);
-        }
-        break;
-    case EXM_ELEMENT_P2P2:
-        if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on P2xP2", P.kernel);
-        if (atomic) EXM_LAUNCH((k_mass_p2<EXM_RACE_ATOMIC, LIST>));
-        else EXM_LAUNCH((k_mass_p2<EXM_RACE_COLOUR, LIST>));
-        break;
-    case EXM_ELEMENT_DG0DG0:
-        if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on DG0xDG0", P.kernel);
-        hipLaunchKernelGGL((k_mass_dg0<LIST>), grid, block, 0, s, a, P.write);
-        break;
-    case EXM_ELEMENT_DG1DG1:
-        if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on DG1xDG1", P.kernel);
-        hipLaunchKernelGGL((k_mass_dg1<LIST>), grid, block, 0, s, a, P.write);
-        break;
-    default: return fail(EXM_EUNSUPPORTED, "element %d has no kernels", P.element);
-    }
-#undef EXM_LAUNCH
-    EXM_TRY_HIP(hipGetLastError());
-    return EXM_OK;
-}
-
-int32_t launch_column_loop(const LoopLaunch& P, hipStream_t stream)
-{
-    if (P.cell_count <= 0) return EXM_OK;
     ColArgs a;
     a.n_layers = P.n_layers;
     a.off = P.field_offset;
     a.cpw = P.shape.cpw;
     a.seg = P.shape.seg;
+    a.xn = P.xspace->n_dofs;
     a.fmap = P.fmap;
     a.xmap = P.xmap;
     a.X = P.X;
@@ -434,14 +609,115 @@ int32_t launch_column_loop(const LoopLaunch& P, hipStream_t stream)
     a.out0 = P.out[0];
     a.out1 = P.out[1];
     a.out2 = P.out[2];
+    a.write = P.write;
     a.cells = P.cells;
     a.cell_begin = P.cell_begin;
     a.cell_count = P.cell_count;
+    return a;
+}
+
+int32_t launch_column_loop(const LoopLaunch& P, hipStream_t stream)
+{
+    if (P.cell_count <= 0) return EXM_OK;
+    const ColArgs a = col_args(P);
     const int64_t waves = (P.cell_count + a.cpw - 1) / a.cpw;
     const int64_t blocks = (waves + P.shape.wpb - 1) / P.shape.wpb;
     if (blocks > INT32_MAX) return fail(EXM_ERANGE, "grid too large");
     dim3 grid((unsigned)blocks), block((unsigned)(64 * P.shape.wpb));
-    return P.cells ? dispatch<true>(P, a, grid, block, stream) : dispatch<false>(P, a, grid, block, stream);
+    const bool atomic = P.race == EXM_RACE_ATOMIC;
+#define EXM_LAUNCH(K) hipLaunchKernelGGL(K, grid, block, 0, stream, a)
+#define EXM_LAUNCH_RACE(F)                                                           \
+    do {                                                                             \
+        if (atomic) EXM_LAUNCH((k_direct_p1<F, EXM_RACE_ATOMIC>));                   \
+        else EXM_LAUNCH((k_direct_p1<F, EXM_RACE_COLOUR>));                          \
+    } while (0)
+    switch (P.element) {
+    case EXM_ELEMENT_P1P1:
+        switch (P.kernel) {
+        case EXM_K_MASS: EXM_LAUNCH_RACE(0); break;
+        case EXM_K_CUBIC: EXM_LAUNCH_RACE(1); break;
+        case EXM_K_CUBIC_VJP: EXM_LAUNCH_RACE(2); break;
+        case EXM_K_CUBIC_FUSED: EXM_LAUNCH_RACE(3); break;
+        default: return fail(EXM_EUNSUPPORTED, "kernel %d not available on P1xP1", P.kernel);
+        }
+        break;
+    case EXM_ELEMENT_P2P2:
+        if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on P2xP2", P.kernel);
+        if (atomic) EXM_LAUNCH((k_direct_p2<EXM_RACE_ATOMIC>));
+        else EXM_LAUNCH((k_direct_p2<EXM_RACE_COLOUR>));
+        break;
+    case EXM_ELEMENT_DG0DG0:
+        if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on DG0xDG0", P.kernel);
+        EXM_LAUNCH(k_direct_dg0);
+        break;
+    case EXM_ELEMENT_DG1DG1:
+        if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on DG1xDG1", P.kernel);
+        EXM_LAUNCH(k_direct_dg1);
+        break;
+    default: return fail(EXM_EUNSUPPORTED, "element %d has no kernels", P.element);
+    }
+#undef EXM_LAUNCH_RACE
+#undef EXM_LAUNCH
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+int32_t tiled_max_threads(int32_t kernel, int32_t element)
+{
+    (void)kernel;
+    (void)element;
+    return 512;
+}
+
+size_t tiled_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t seg)
+{
+    switch (element) {
+    case EXM_ELEMENT_P1P1: {
+        int nout = 1;
+        if (kernel == EXM_K_CUBIC_VJP) nout = 2;
+        if (kernel == EXM_K_CUBIC_FUSED) nout = 3;
+        return sizeof(double) * (size_t)nout * vstride * (seg + 2);
+    }
+    case EXM_ELEMENT_P2P2: {
+        const size_t es = (size_t)vstride + estride;
+        return sizeof(double) * es * (2 * (size_t)seg + 2);
+    }
+    default: return 0;
+    }
+}
+
+int32_t launch_tiled(const LoopLaunch& P, const TileArgs& t, int32_t threads, size_t lds, hipStream_t s)
+{
+    if (t.tile_count <= 0) return EXM_OK;
+    const ColArgs a = col_args(P);
+    dim3 grid((unsigned)t.tile_count), block((unsigned)threads);
+    const bool atomic = P.race == EXM_RACE_ATOMIC;
+#define EXM_TL(K) hipLaunchKernelGGL(K, grid, block, lds, s, a, t)
+#define EXM_TL_RACE(F)                                 \
+    do {                                               \
+        if (atomic) EXM_TL((k_tiled_p1<F, true>));     \
+        else EXM_TL((k_tiled_p1<F, false>));           \
+    } while (0)
+    switch (P.element) {
+    case EXM_ELEMENT_P1P1:
+        switch (P.kernel) {
+        case EXM_K_MASS: EXM_TL_RACE(0); break;
+        case EXM_K_CUBIC: EXM_TL_RACE(1); break;
+        case EXM_K_CUBIC_VJP: EXM_TL_RACE(2); break;
+        case EXM_K_CUBIC_FUSED: EXM_TL_RACE(3); break;
+        default: return fail(EXM_EUNSUPPORTED, "kernel %d not available on P1xP1", P.kernel);
+        }
+        break;
+    case EXM_ELEMENT_P2P2:
+        if (atomic) EXM_TL((k_tiled_p2<true>));
+        else EXM_TL((k_tiled_p2<false>));
+        break;
+    default: return fail(EXM_EUNSUPPORTED, "element %d has no tiled kernels", P.element);
+    }
+#undef EXM_TL_RACE
+#undef EXM_TL
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
 }
 
 }  // namespace exm

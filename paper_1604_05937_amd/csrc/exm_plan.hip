@@ -1,0 +1,202 @@
+// Tile plans for the LDS-staged column loop (host code).
+//
+// A tile is a compact group of base cells grown by breadth-first search over
+// the cells sharing an edge, seeded at the lowest-numbered unassigned cell, so
+// it follows the locality of the base ordering.  For every tile the plan lists
+// the base vertices (and, if asked, edges) its cells touch; each is flagged
+// when another tile touches it too.  Tiles are also greedily coloured so that
+// tiles of one colour share no vertex.
+#include <algorithm>
+#include <cstring>
+#include <deque>
+
+#include "exm_internal.hpp"
+
+namespace exm {
+
+namespace {
+
+struct Csr {
+    std::vector<int64_t> start;
+    std::vector<int32_t> items;
+};
+
+Csr vertex_cells(const exm_mesh* m)
+{
+    const int32_t nv = m->n[0], nc = m->n[2];
+    const int32_t* cv = m->h_cell_vertex.data();
+    Csr r;
+    r.start.assign(nv + 1, 0);
+    for (int64_t i = 0; i < (int64_t)nc * 3; ++i) r.start[cv[i] + 1]++;
+    for (int32_t v = 0; v < nv; ++v) r.start[v + 1] += r.start[v];
+    r.items.resize(r.start[nv]);
+    std::vector<int64_t> fill(r.start.begin(), r.start.end() - 1);
+    for (int32_t c = 0; c < nc; ++c)
+        for (int a = 0; a < 3; ++a) r.items[fill[cv[c * 3 + a]]++] = c;
+    return r;
+}
+
+}  // namespace
+
+int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out)
+{
+    std::lock_guard<std::mutex> lock(m->mu);
+    for (auto& p : m->plans)
+        if (p->target == target) {
+            *out = p.get();
+            return EXM_OK;
+        }
+    const int32_t nv = m->n[0], ne = m->n[1], nc = m->n[2];
+    const int32_t* cv = m->h_cell_vertex.data();
+    const bool edges = !m->h_cell_edge.empty();
+    const int32_t* ce = edges ? m->h_cell_edge.data() : nullptr;
+    Csr vc = vertex_cells(m);
+
+    // 1. grow tiles
+    std::vector<int32_t> tile_of(nc, -1);
+    auto plan = std::make_unique<TilePlan>();
+    plan->target = target;
+    std::vector<int32_t> order;
+    order.reserve(nc);
+    std::vector<int64_t> tile_cell_off(1, 0);
+    std::deque<int32_t> q;
+    int32_t nt = 0;
+    for (int32_t s = 0; s < nc; ++s) {
+        if (tile_of[s] >= 0) continue;
+        int32_t cnt = 0;
+        q.clear();
+        q.push_back(s);
+        tile_of[s] = nt;
+        order.push_back(s);
+        ++cnt;
+        while (!q.empty() && cnt < target) {
+            const int32_t c = q.front();
+            q.pop_front();
+            // edge neighbours: cells holding two vertices of c
+            for (int a = 0; a < 3 && cnt < target; ++a) {
+                const int32_t p = cv[c * 3 + (a + 1) % 3], r = cv[c * 3 + (a + 2) % 3];
+                for (int64_t j = vc.start[p]; j < vc.start[p + 1] && cnt < target; ++j) {
+                    const int32_t o = vc.items[j];
+                    if (tile_of[o] >= 0) continue;
+                    const int32_t* w = cv + (int64_t)o * 3;
+                    if (w[0] != r && w[1] != r && w[2] != r) continue;
+                    tile_of[o] = nt;
+                    order.push_back(o);
+                    q.push_back(o);
+                    ++cnt;
+                }
+            }
+        }
+        tile_cell_off.push_back((int64_t)order.size());
+        ++nt;
+    }
+    plan->n_tiles = nt;
+
+    // 2. per-tile vertex and edge lists with local indices
+    std::vector<int32_t> touch_v(nv, 0), touch_e(edges ? ne : 0, 0);
+    std::vector<int32_t> stamp_v(nv, -1), local_v(nv, 0), stamp_e(edges ? ne : 0, -1), local_e(edges ? ne : 0, 0);
+    std::vector<int64_t> voff(1, 0), eoff(1, 0);
+    std::vector<int32_t> verts, edgs;
+    std::vector<uint16_t> lcv((size_t)nc * 3), lce(edges ? (size_t)nc * 3 : 0);
+    int32_t maxc = 0, maxv = 0, maxe = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+        const int64_t b = tile_cell_off[t], e = tile_cell_off[t + 1];
+        maxc = std::max<int32_t>(maxc, (int32_t)(e - b));
+        int32_t nvl = 0, nel = 0;
+        for (int64_t i = b; i < e; ++i) {
+            const int32_t c = order[i];
+            for (int a = 0; a < 3; ++a) {
+                const int32_t v = cv[(int64_t)c * 3 + a];
+                if (stamp_v[v] != t) {
+                    stamp_v[v] = t;
+                    local_v[v] = nvl++;
+                    verts.push_back(v);
+                    touch_v[v]++;
+                }
+                lcv[(size_t)i * 3 + a] = (uint16_t)local_v[v];
+                if (edges) {
+                    const int32_t g = ce[(int64_t)c * 3 + a];
+                    if (stamp_e[g] != t) {
+                        stamp_e[g] = t;
+                        local_e[g] = nel++;
+                        edgs.push_back(g);
+                        touch_e[g]++;
+                    }
+                    lce[(size_t)i * 3 + a] = (uint16_t)local_e[g];
+                }
+            }
+        }
+        EXM_CHECK(nvl < 65535 && nel < 65535, EXM_ERANGE, "tile too large");
+        maxv = std::max(maxv, nvl);
+        maxe = std::max(maxe, nel);
+        voff.push_back((int64_t)verts.size());
+        eoff.push_back((int64_t)edgs.size());
+    }
+    plan->max_cells = maxc;
+    plan->max_verts = maxv;
+    plan->max_edges = maxe;
+    // shared flag in bit 31 of the stored id
+    std::vector<int32_t> vflag(verts.size()), eflag(edgs.size());
+    int64_t shared_v = 0;
+    for (size_t i = 0; i < verts.size(); ++i) {
+        const bool sh = touch_v[verts[i]] > 1;
+        shared_v += sh;
+        vflag[i] = verts[i] | (sh ? (int32_t)0x80000000 : 0);
+    }
+    for (size_t i = 0; i < edgs.size(); ++i) eflag[i] = edgs[i] | (touch_e[edgs[i]] > 1 ? (int32_t)0x80000000 : 0);
+    plan->n_tile_verts = (int64_t)verts.size();
+    plan->n_shared_verts = shared_v;
+
+    // 3. greedy tile colouring: tiles sharing a vertex differ in colour
+    std::vector<int32_t> tcol(nt, -1), mark;
+    int32_t ncol = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+        for (int64_t i = voff[t]; i < voff[t + 1]; ++i) {
+            const int32_t v = verts[i];
+            for (int64_t j = vc.start[v]; j < vc.start[v + 1]; ++j) {
+                const int32_t o = tcol[tile_of[vc.items[j]]];
+                if (o >= 0) mark[o] = t;
+            }
+        }
+        int32_t col = 0;
+        while (col < ncol && mark[col] == t) ++col;
+        if (col == ncol) {
+            ++ncol;
+            mark.push_back(-1);
+        }
+        tcol[t] = col;
+    }
+    plan->n_colours = ncol;
+    plan->colour_off.assign(ncol + 1, 0);
+    for (int32_t t = 0; t < nt; ++t) plan->colour_off[tcol[t] + 1]++;
+    for (int32_t k = 0; k < ncol; ++k) plan->colour_off[k + 1] += plan->colour_off[k];
+    std::vector<int32_t> tiles_by_colour(nt);
+    {
+        std::vector<int64_t> f(plan->colour_off.begin(), plan->colour_off.end() - 1);
+        for (int32_t t = 0; t < nt; ++t) tiles_by_colour[f[tcol[t]]++] = t;
+    }
+
+    // 4. device copies
+    std::vector<int32_t> tco(tile_cell_off.begin(), tile_cell_off.end());
+    std::vector<int32_t> vo(voff.begin(), voff.end()), eo(eoff.begin(), eoff.end());
+    EXM_CHECK(tile_cell_off.back() < INT32_MAX && voff.back() < INT32_MAX && eoff.back() < INT32_MAX, EXM_EOVERFLOW,
+              "plan too large");
+    int32_t s;
+    if ((s = plan->cell_off.upload(tco.data(), tco.size())) != EXM_OK) return s;
+    if ((s = plan->cells.upload(order.data(), order.size())) != EXM_OK) return s;
+    if ((s = plan->vert_off.upload(vo.data(), vo.size())) != EXM_OK) return s;
+    if ((s = plan->verts.upload(vflag.data(), vflag.size())) != EXM_OK) return s;
+    if ((s = plan->local_cv.upload(lcv.data(), lcv.size())) != EXM_OK) return s;
+    if (edges) {
+        if ((s = plan->edge_off.upload(eo.data(), eo.size())) != EXM_OK) return s;
+        if ((s = plan->edges.upload(eflag.data(), eflag.size())) != EXM_OK) return s;
+        if ((s = plan->local_ce.upload(lce.data(), lce.size())) != EXM_OK) return s;
+    }
+    if ((s = plan->colour_tiles.upload(tiles_by_colour.data(), tiles_by_colour.size())) != EXM_OK) return s;
+    plan->has_edges = edges;
+    m->plans.push_back(std::move(plan));
+    *out = m->plans.back().get();
+    return EXM_OK;
+}
+
+}  // namespace exm

@@ -1,0 +1,55 @@
+// Kernel arguments and launchers of the column loop (DIRECT and TILED schedules).
+#pragma once
+
+#include "exm_internal.hpp"
+
+namespace exm {
+
+// Arguments shared by every column-loop kernel.
+struct ColArgs {
+    int32_t n_layers;
+    int32_t off;           // vertical offset of the field space (same for every list position)
+    int32_t cpw, seg;      // columns per wavefront, lanes (layers per step) per column
+    int32_t write;         // DG outputs: 1 WRITE, 0 INC
+    int64_t xn;            // DoFs of the coordinate space (component stride of X)
+    const int32_t* __restrict__ fmap;   // field explicit lists [n_cells * k]
+    const int32_t* __restrict__ xmap;   // coordinate explicit lists [n_cells * 6]
+    const double* __restrict__ X;       // coordinates, component-major [3 * xn]
+    const double* __restrict__ in0;
+    const double* __restrict__ in1;
+    const double* __restrict__ in2;
+    double* __restrict__ out0;
+    double* __restrict__ out1;
+    double* __restrict__ out2;
+    const int32_t* __restrict__ cells;  // DIRECT: cell list (one colour) or null
+    int64_t cell_begin, cell_count;     // DIRECT: range of the list (or of the cells)
+};
+
+// TILED: the tile plan.
+struct TileArgs {
+    int32_t vstride;       // LDS entity slots for vertices (the plan's max_verts)
+    int32_t estride;       // LDS entity slots for edges (the plan's max_edges)
+    const int32_t* __restrict__ tiles;   // tile list (one colour) or null for tiles tile_begin ..
+    int32_t tile_begin, tile_count;
+    const int32_t* __restrict__ cell_off;
+    const int32_t* __restrict__ cells;
+    const int32_t* __restrict__ vert_off;
+    const int32_t* __restrict__ verts;
+    const int32_t* __restrict__ edge_off;
+    const int32_t* __restrict__ edges;
+    const uint16_t* __restrict__ lcv;
+    const uint16_t* __restrict__ lce;
+    const int32_t* __restrict__ xstart;    // coordinate column start of every base vertex
+    const int32_t* __restrict__ fstart0;   // field column start of every base vertex
+    const int32_t* __restrict__ fstart1;   // field column start of every base edge
+};
+
+ColArgs col_args(const LoopLaunch& P);
+int32_t tiled_max_threads(int32_t kernel, int32_t element);
+size_t staged_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t S);
+bool staged_supported(int32_t kernel, int32_t element);
+int32_t launch_staged(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t S, size_t lds, hipStream_t s);
+size_t tiled_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t seg);
+int32_t launch_tiled(const LoopLaunch& P, const TileArgs& t, int32_t threads, size_t lds, hipStream_t s);
+
+}  // namespace exm

@@ -1,0 +1,49 @@
+"""Parity of the cubic residual, its vector-Jacobian product and the fused
+forward+adjoint kernel with the oracle."""
+import numpy as np
+import pytest
+
+import paper_1604_05937_amd as exm
+from paper_1604_05937_amd import meshgen
+from tests.gpu_common import Case, assert_close, say
+
+pytestmark = pytest.mark.gpu
+
+OPTS = [dict(schedule=exm.EXM_SCHED_DIRECT, race=exm.EXM_RACE_ATOMIC),
+        dict(schedule=exm.EXM_SCHED_DIRECT, race=exm.EXM_RACE_COLOUR, cols_per_wave=3),
+        dict(schedule=exm.EXM_SCHED_TILED, race=exm.EXM_RACE_ATOMIC),
+        dict(schedule=exm.EXM_SCHED_TILED, race=exm.EXM_RACE_COLOUR, tile_cells=24, cols_per_wave=3),
+        dict(schedule=exm.EXM_SCHED_STAGED, race=exm.EXM_RACE_ATOMIC, tile_cells=40, chunk_layers=16),
+        dict(schedule=exm.EXM_SCHED_STAGED, race=exm.EXM_RACE_COLOUR, tile_cells=16, chunk_layers=8)]
+
+
+def _run(c, kernel, ins, nout, **opts):
+    dev_in = [c.dev(x) for x in ins]
+    outs = [c.V.zeros() for _ in range(nout)]
+    fields = [(d, c.V, exm.EXM_READ) for d in dev_in] + [(o, c.V, exm.EXM_INC) for o in outs]
+    exm.par_loop(kernel, c.mesh, c.X, c.Vx, fields, **opts)
+    return [c.host(o) for o in outs]
+
+
+@pytest.mark.parametrize("opts", OPTS)
+@pytest.mark.parametrize("n,lam,terrain", [(8, 10, 0.0), (6, 33, 0.3), (3, 1, 0.0), (5, 70, 0.1)])
+def test_cubic_forward_vjp_fused(opts, n, lam, terrain):
+    say(f"cubic n={n} lam={lam} opts={opts}")
+    base = meshgen.tri_square(n)
+    c = Case(base, lam, "P1", terrain=terrain)
+    u = meshgen.uniform_values(c.n, seed=31)
+    f = meshgen.uniform_values(c.n, seed=32)
+    w = meshgen.uniform_values(c.n, seed=meshgen.SEED_COTAN)
+    F_ref = c.ref.cubic(u, f)
+    F_scale = c.ref.cubic_abs(u, f)
+    gu_ref, gf_ref = c.ref.cubic_vjp(u, w)
+    gu_scale, gf_scale = c.ref.vjp_abs(u, w)
+    (F,) = _run(c, exm.EXM_K_CUBIC, [u, f], 1, **opts)
+    assert_close(F, F_ref, F_scale, what="cubic F")
+    gu, gf = _run(c, exm.EXM_K_CUBIC_VJP, [u, w], 2, **opts)
+    assert_close(gu, gu_ref, gu_scale, what="vjp g_u")
+    assert_close(gf, gf_ref, gf_scale, what="vjp g_f")
+    F2, gu2, gf2 = _run(c, exm.EXM_K_CUBIC_FUSED, [u, f, w], 3, **opts)
+    assert_close(F2, F_ref, F_scale, what="fused F")
+    assert_close(gu2, gu_ref, gu_scale, what="fused g_u")
+    assert_close(gf2, gf_ref, gf_scale, what="fused g_f")

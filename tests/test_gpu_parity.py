@@ -36,28 +36,66 @@ def test_numbering_bit_exact(space, n, lam, order):
             np.testing.assert_array_equal(starts, ref.column_starts(d1).astype(np.int32))
 
 
+SCHEDULES = [exm.EXM_SCHED_DIRECT, exm.EXM_SCHED_TILED, exm.EXM_SCHED_STAGED]
+RACES = [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR]
+
+
 @pytest.mark.parametrize("space", ["P1", "DG0", "DG1", "P2"])
 @pytest.mark.parametrize("n,lam", SHAPES)
-@pytest.mark.parametrize("race", [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR])
-def test_mass_parity(space, n, lam, race):
-    say(f"mass {space} n={n} lam={lam} race={race}")
+@pytest.mark.parametrize("race", RACES)
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_mass_parity(space, n, lam, race, schedule):
+    say(f"mass {space} n={n} lam={lam} race={race} schedule={schedule}")
     base = meshgen.tri_square(n)
     c = Case(base, lam, space, terrain=0.25)
     x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
-    got = c.mass(x, race=race)
+    got = c.mass(x, race=race, schedule=schedule)
     assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"mass {space}")
 
 
 @pytest.mark.parametrize("space", ["P1", "P2", "DG1", "DG0"])
 @pytest.mark.parametrize("cpw", [1, 2, 3, 4, 5, 7, 8, 16])
 @pytest.mark.parametrize("wpb", [1, 4])
-def test_mass_launch_shapes(space, cpw, wpb):
-    say(f"shape {space} cpw={cpw} wpb={wpb}")
+def test_mass_direct_shapes(space, cpw, wpb):
+    say(f"direct shape {space} cpw={cpw} wpb={wpb}")
     base = meshgen.tri_square(9)
     c = Case(base, 23, space)
     x = meshgen.uniform_values(c.n, seed=5)
-    got = c.mass(x, cols_per_wave=cpw, waves_per_block=wpb)
+    got = c.mass(x, schedule=exm.EXM_SCHED_DIRECT, cols_per_wave=cpw, waves_per_block=wpb)
     assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"mass {space} cpw={cpw}")
+
+
+@pytest.mark.parametrize("space", ["P1", "P2", "DG1", "DG0"])
+@pytest.mark.parametrize("tile", [8, 17, 64, 300])
+@pytest.mark.parametrize("cpw", [0, 1, 3, 8])
+@pytest.mark.parametrize("race", RACES)
+def test_mass_tiled_shapes(space, tile, cpw, race):
+    say(f"tiled shape {space} tile={tile} cpw={cpw} race={race}")
+    base = meshgen.tri_square(11, order="random" if tile == 17 else "rcm")
+    c = Case(base, 23, space, terrain=0.2)
+    x = meshgen.uniform_values(c.n, seed=6)
+    try:
+        got = c.mass(x, schedule=exm.EXM_SCHED_TILED, tile_cells=tile, cols_per_wave=cpw, race=race,
+                     waves_per_block=2 if cpw == 3 else 0)
+    except exm.ExmError as e:
+        # a tile whose per-level sums exceed LDS is refused before any launch
+        assert e.status == exm._abi.EXM_EUNSUPPORTED and "LDS" in str(e) and cpw in (1, 3), str(e)
+        return
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"tiled mass {space} tile={tile} cpw={cpw}")
+
+
+@pytest.mark.parametrize("space", ["P1", "DG1", "DG0"])
+@pytest.mark.parametrize("tile", [8, 29, 128])
+@pytest.mark.parametrize("chunk", [8, 16, 32, 64])
+@pytest.mark.parametrize("race", RACES)
+def test_mass_staged_shapes(space, tile, chunk, race):
+    say(f"staged shape {space} tile={tile} chunk={chunk} race={race}")
+    base = meshgen.tri_square(10, order="random" if tile == 29 else "rcm")
+    for lam in (chunk - 1, chunk, 2 * chunk + 3):
+        c = Case(base, lam, space, terrain=0.2)
+        x = meshgen.uniform_values(c.n, seed=7)
+        got = c.mass(x, schedule=exm.EXM_SCHED_STAGED, tile_cells=tile, chunk_layers=chunk, race=race)
+        assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"staged mass {space} tile={tile} S={chunk} lam={lam}")
 
 
 def test_tiny_config_p1_rhs():
