@@ -1,0 +1,374 @@
+"""Benchmark of the extruded column loop on one MI355X.
+
+Workload (one step): FP64 residual assembly of the integral of f v on a
+512 x 512 triangulated unit square (524,288 jittered triangles, RCM-ordered)
+extruded to 100 layers of prisms -- once on P1 x P1 (CG, INC) and once on
+DG0 x DG0 (WRITE) -- with inputs resident in HBM.  Prints one JSON line:
+whole-step throughput in GB/s of algorithmic bytes, the roofline of the
+dominant kernel, the measured STREAM triad, and the CPU oracle on a bounded
+sample of the same workload.  Secondary figures (higher-order mass actions,
+cubic forward vs fused forward+adjoint, batched vs individual launches) are
+added unless --quick.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(torch, fn, reps):
+    """min and mean time (ms) of fn over reps runs, HIP events on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return min(ts), sum(ts) / len(ts)
+
+
+def stream_triad(torch, exm):
+    n = 1 << 28   # 3 arrays of 2 GiB
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    best = 0.0
+    for block in (256, 512, 1024):
+        for grid in (0, 4096, 16384):
+            t, _ = timed(torch, lambda: exm.stream_triad(a, b, c, 3.0, block=block, grid=grid), 5)
+            best = max(best, 24.0 * n / (t * 1e-3) / 1e9)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return best
+
+
+def read_traffic(kernel_tag: str, src_hash: str):
+    """HBM bytes per launch from the rocprofv3 counter summary of this kernel
+    build (profiles/<tag>.md, a line 'traffic: {json}'), else None."""
+    p = os.path.join(ROOT, "profiles", f"{kernel_tag}.md")
+    if not os.path.exists(p):
+        return None
+    m = re.search(r"^traffic:\s*(\{.*\})\s*$", open(p).read(), flags=re.M)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != src_hash:
+        return None   # counters were taken on another kernel build
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(work, f1_host, f0_host, budget_s: float):
+    """The oracle (plain C, one thread) on a bounded sample of the same
+    workload: the first base cells of the RCM order, all layers, P1 and DG0.
+    The per-prism time is extrapolated to the whole step."""
+    import numpy as np
+
+    import oracle
+    base, lam = work.base, work.n_layers
+    t0 = time.time()
+    num_x = oracle.number(base.counts, lam, oracle.delta_table("CG1", "CG1"), base.cell_vertex, base.cell_edge)
+    num_0 = oracle.number(base.counts, lam, oracle.delta_table("DG0", "DG0"), base.cell_vertex, base.cell_edge)
+    X = oracle.coordinate_field(num_x, work.vc)
+    log(f"cpu baseline: oracle numbering {time.time() - t0:.1f}s")
+    out1 = np.zeros(num_x.n_dofs)
+    out0 = np.zeros(num_0.n_dofs)
+    per = {}
+    for name, num, f, out, space in (("P1", num_x, f1_host, out1, ("CG1", "CG1")),
+                                     ("DG0", num_0, f0_host, out0, ("DG0", "DG0"))):
+        n = 256
+        while True:
+            cells = np.arange(n)
+            t = time.perf_counter()
+            oracle.par_loop(oracle.FORM_MASS, space, num, num_x, X, [f], [out], write=(name == "DG0"), cells=cells)
+            dt = time.perf_counter() - t
+            if dt > budget_s / 8 or n >= base.n_cells:
+                break
+            n = min(base.n_cells, int(n * max(2.0, budget_s / 2 / max(dt, 1e-3))))
+        per[name] = (dt / (n * lam), n)
+        log(f"cpu baseline {name}: {n} cells x {lam} layers in {dt:.2f}s")
+    return per
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["p1", "dg0"], help="launch only this kernel (for profiling)")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1604_05937_amd as exm
+    from paper_1604_05937_amd import meshgen, workloads as W
+
+    exm.load_library()
+    torch.cuda.init()
+    t0 = time.time()
+    work = W.extruded(512, 100, keep_host_coords=not args.no_cpu)
+    V1, V0 = work.space("P1"), work.space("DG0")
+    f1_host = meshgen.uniform_values(V1.n_dofs, seed=meshgen.SEED_FIELD)
+    f0_host = meshgen.uniform_values(V0.n_dofs, seed=meshgen.SEED_FIELD)
+    f1 = torch.from_numpy(f1_host).to("cuda")
+    f0 = torch.from_numpy(f0_host).to("cuda")
+    b1 = V1.zeros()
+    b0 = V0.zeros()
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    log(f"setup {setup_s:.1f}s: {work.base.n_cells} cells x {work.n_layers} layers, P1 {V1.n_dofs} DoFs, DG0 {V0.n_dofs} DoFs")
+
+    # autotuned launch configurations (the library keeps them for later calls)
+    t0 = time.time()
+    cfg1 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "P1", f1, b1))
+    cfg0 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "DG0", f0, b0))
+    log(f"autotune {time.time() - t0:.1f}s: P1 {cfg1}  DG0 {cfg0}")
+
+    by1 = W.mass_bytes(work, "P1")
+    by0 = W.mass_bytes(work, "DG0")
+    k1 = lambda: W.run_mass(work, "P1", f1, b1)
+    k2 = lambda: W.run_mass(work, "DG0", f0, b0)
+    if args.only == "p1":
+        for _ in range(args.warmup + args.steps):
+            k1()
+        torch.cuda.synchronize()
+        log("done")
+        return
+    if args.only == "dg0":
+        for _ in range(args.warmup + args.steps):
+            k2()
+        torch.cuda.synchronize()
+        log("done")
+        return
+
+    # ---- timed region: K steps of (P1 assembly, DG0 assembly) ----
+    s = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        k1()
+        k2()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(s)
+        k1()
+        ev[i][1].record(s)
+        k2()
+        ev[i][2].record(s)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_start) * 1e3
+    t1 = [ev[i][0].elapsed_time(ev[i][1]) for i in range(args.steps)]
+    t2 = [ev[i][1].elapsed_time(ev[i][2]) for i in range(args.steps)]
+    step_ms = ev[0][0].elapsed_time(ev[-1][2]) / args.steps
+    step_bytes = by1["algorithmic"] + by0["algorithmic"]
+    value = step_bytes / (step_ms * 1e-3) / 1e9
+    log(f"step {step_ms:.3f} ms (P1 {np.mean(t1):.3f}, DG0 {np.mean(t2):.3f}); wall {wall_ms / args.steps:.3f} ms/step")
+
+    stream_gbs = stream_triad(torch, exm)
+    log(f"STREAM triad {stream_gbs:.0f} GB/s")
+
+    k1_gbs = by1["algorithmic"] / (np.mean(t1) * 1e-3) / 1e9
+    k2_gbs = by0["algorithmic"] / (np.mean(t2) * 1e-3) / 1e9
+    dominant = ("p1_rhs_512x512x100", by1, t1, k1_gbs) if np.mean(t1) >= np.mean(t2) else \
+               ("dg0_rhs_512x512x100", by0, t2, k2_gbs)
+    src_hash = W.source_hash()
+    traffic = read_traffic(dominant[0], src_hash)
+    roofline = {
+        "kernel": dominant[0],
+        "bound": "hbm",
+        "achieved": round(dominant[3], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(dominant[3] / HBM_PEAK_GBS, 4),
+        "frac_of_stream": round(dominant[3] / stream_gbs, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": dominant[1]["algorithmic"],
+        "avg_launch_ms": round(float(np.mean(dominant[2])), 4),
+    }
+
+    result = {
+        "metric": "extruded assembly GB/s & % HBM peak; batched+adjoint vs plain, same GPU",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "RHS assembly of integral f v, P1xP1 (INC) + DG0xDG0 (WRITE), 512x512 triangulated "
+                        "square (524288 tris, jittered, RCM) x 100 layers, FP64",
+            "n_prisms": work.n_prisms,
+            "p1_dofs": V1.n_dofs,
+            "dg0_dofs": V0.n_dofs,
+            "launch_p1": cfg1,
+            "launch_dg0": cfg0,
+            "source_hash": src_hash,
+        },
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "stream_triad_gbs": round(stream_gbs, 1),
+        "pct_stream": round(100 * value / stream_gbs, 2),
+        "kernels": {
+            "p1_rhs": {"ms": round(float(np.mean(t1)), 4), "gbs": round(k1_gbs, 1),
+                       "pct_stream": round(100 * k1_gbs / stream_gbs, 2),
+                       "valuable_gbs_paper_def": round(by1["valuable"] / (np.mean(t1) * 1e-3) / 1e9, 1),
+                       "dofs_per_s": V1.n_dofs / (np.mean(t1) * 1e-3)},
+            "dg0_rhs": {"ms": round(float(np.mean(t2)), 4), "gbs": round(k2_gbs, 1),
+                        "pct_stream": round(100 * k2_gbs / stream_gbs, 2),
+                        "valuable_gbs_paper_def": round(by0["valuable"] / (np.mean(t2) * 1e-3) / 1e9, 1),
+                        "dofs_per_s": V0.n_dofs / (np.mean(t2) * 1e-3)},
+        },
+        "roofline": roofline,
+        "setup_s": round(setup_s, 2),
+    }
+
+    if not args.quick:
+        try:
+            result["secondary"] = secondary(torch, exm, W, meshgen)
+        except Exception as e:   # secondary figures never hide the main line
+            log(f"secondary measurements failed: {e!r}")
+            result["secondary"] = {"error": repr(e)}
+
+    if not args.no_cpu:
+        per = cpu_baseline(work, f1_host, f0_host, args.cpu_seconds)
+        cpu_step_s = (per["P1"][0] + per["DG0"][0]) * work.n_prisms
+        result["cpu_baseline"] = {
+            "value": round(step_bytes / cpu_step_s / 1e9, 4),
+            "unit": "GB/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"P1xP1 and DG0xDG0 oracle assembly of the first {per['P1'][1]} and {per['DG0'][1]} base "
+                      f"cells (RCM order) x 100 layers, single thread, per-prism time extrapolated to the "
+                      f"{work.n_prisms}-prism step",
+            "step_s_extrapolated": round(cpu_step_s, 2),
+            "gpu_speedup": round(cpu_step_s / (step_ms * 1e-3), 1),
+        }
+    print(json.dumps(result), flush=True)
+
+
+def secondary(torch, exm, W, meshgen):
+    out = {}
+    # higher-order mass actions: 256 x 256 x 64, DG1 x DG1 and P2 x P2
+    e3 = W.extruded(256, 64)
+    for name in ("DG1", "P2"):
+        V = e3.space(name)
+        x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
+        y = V.zeros()
+        args_ = W.mass_args(e3, name, x, y)
+        cfg = exm.autotune(exm.EXM_K_MASS, e3.mesh, e3.X, e3.Vx, args_)
+        t, _ = timed(torch, lambda: W.run_mass(e3, name, x, y), 10)
+        b = W.mass_bytes(e3, name)
+        out[f"mass_{name.lower()}_256x256x64"] = {"ms": round(t, 4), "gbs": round(b["algorithmic"] / t / 1e6, 1),
+                                                  "launch": cfg}
+        log(f"mass {name}: {t:.3f} ms")
+        del x, y
+    del e3
+    # cubic residual vs fused forward+adjoint: 256 x 256 x 50, P1 x P1
+    e4 = W.extruded(256, 50)
+    V = e4.Vx
+    u = W.device_values(V.n_dofs, 31)
+    f = W.device_values(V.n_dofs, 32)
+    w = W.device_values(V.n_dofs, meshgen.SEED_COTAN)
+    F, gu, gf = V.zeros(), V.zeros(), V.zeros()
+    fw = [(u, V, exm.EXM_READ), (f, V, exm.EXM_READ), (F, V, exm.EXM_INC)]
+    fu = [(u, V, exm.EXM_READ), (f, V, exm.EXM_READ), (w, V, exm.EXM_READ), (F, V, exm.EXM_INC),
+          (gu, V, exm.EXM_INC), (gf, V, exm.EXM_INC)]
+    c_fw = exm.autotune(exm.EXM_K_CUBIC, e4.mesh, e4.X, V, fw)
+    c_fu = exm.autotune(exm.EXM_K_CUBIC_FUSED, e4.mesh, e4.X, V, fu)
+    t_fw, _ = timed(torch, lambda: W.run_cubic(e4, u, f, F), 10)
+    t_fu, _ = timed(torch, lambda: W.run_fused(e4, u, f, w, F, gu, gf), 10)
+    out["cubic_256x256x50"] = {"forward_ms": round(t_fw, 4), "fused_fwd_adj_ms": round(t_fu, 4),
+                               "fused_over_forward": round(t_fu / t_fw, 3), "launch_forward": c_fw,
+                               "launch_fused": c_fu,
+                               "forward_gflops_est": None}
+    log(f"cubic forward {t_fw:.3f} ms, fused {t_fu:.3f} ms")
+    del e4, u, f, w, F, gu, gf
+    torch.cuda.empty_cache()
+    out["batch"] = batch_vs_plain(torch, exm, W, meshgen)
+    return out
+
+
+def batch_vs_plain(torch, exm, W, meshgen):
+    """64 meshes (half P1, half DG0), 8 fields each: the batched forward +
+    adjoint graph against the 1024 individual launches, same GPU."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(meshgen.SEED_BATCH)
+    t0 = time.time()
+    items = []
+    total_bytes = 0
+    for it in meshgen.batch_meshes(n_meshes=64):
+        mesh = exm.Mesh(it.mesh, it.n_layers)
+        Vx = exm.Space(mesh, "P1")
+        V = exm.Space(mesh, it.space) if it.space != "P1" else Vx
+        X = exm.coordinate_field(Vx, meshgen.extruded_vertex_coords(it.mesh, it.n_layers))
+        rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        d = dict(space=V, coord_space=Vx, coords=X, mesh=mesh, name=it.space,
+                 f=[rnd() for _ in range(8)], b=[V.zeros() for _ in range(8)],
+                 w=[rnd() for _ in range(8)], g=[V.zeros() for _ in range(8)])
+        items.append(d)
+        n = V.n_dofs
+        inc = it.space == "P1"
+        # 8 fields x (forward + adjoint): input, output (+ INC read and zeroing); geometry and lists once
+        total_bytes += 16 * (8 * n + 8 * n * (3 if inc else 1)) + 8 * Vx.n_dofs + 16 * it.mesh.n_vertices \
+            + 4 * it.mesh.n_cells * (6 if inc else 7)
+    log(f"batch setup {time.time() - t0:.1f}s")
+    t0 = time.time()
+    B = exm.Batch(items)
+    log(f"batch create (autotuned, captured) {time.time() - t0:.1f}s, units/blocks {B.info()}")
+    t_batch, _ = timed(torch, B.launch, 5)
+
+    def plain():
+        for d in items:
+            for src, dst in ((d["f"], d["b"]), (d["w"], d["g"])):
+                for x, y in zip(src, dst):
+                    if d["name"] == "P1":
+                        y.zero_()
+                        acc = exm.EXM_INC
+                    else:
+                        acc = exm.EXM_WRITE
+                    exm.par_loop(exm.EXM_K_MASS, d["mesh"], d["coords"], d["coord_space"],
+                                 [(x, d["space"], exm.EXM_READ), (y, d["space"], acc)])
+    t_plain, _ = timed(torch, plain, 3)
+    log(f"batch {t_batch:.3f} ms vs individual {t_plain:.3f} ms")
+    res = {"meshes": len(items), "fields_per_mesh": 8, "batched_ms": round(t_batch, 3),
+           "individual_launches_ms": round(t_plain, 3), "batched_speedup": round(t_plain / t_batch, 3),
+           "batched_gbs": round(total_bytes / t_batch / 1e6, 1)}
+    del items, B
+    torch.cuda.empty_cache()
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -206,3 +206,59 @@ def sync(stream=None):
 def stream_triad(a, b, c, alpha: float, block: int = 256, grid: int = 0, stream=None):
     _abi.exm_stream_triad(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
                           float(alpha), a.numel(), block, grid, stream_handle(stream))
+
+
+class Batch:
+    """exm_batch: forward residual b = M f and adjoint g = M w for several
+    fields on many extruded meshes, one persistent kernel in a HIP graph.
+
+    items: list of dicts with keys space, coord_space, coords, f, b and
+    optionally w, g (lists of device FP64 tensors on `space`)."""
+
+    def __init__(self, items, cols_per_wave: int = 0, unit_cells: int = 0, stream=None):
+        _abi.load()
+        self._keep = []
+        arr = (_abi.exm_batch_item * len(items))()
+        for i, it in enumerate(items):
+            nf = len(it["f"])
+            ptr_arrays = []
+            for key in ("f", "b", "w", "g"):
+                ts = it.get(key)
+                if ts is None:
+                    ptr_arrays.append(None)
+                    continue
+                assert len(ts) == nf
+                for t in ts:
+                    assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous()
+                    assert t.numel() == it["space"].n_dofs
+                pa = (ctypes.c_void_p * nf)(*[t.data_ptr() for t in ts])
+                ptr_arrays.append(pa)
+                self._keep.append(pa)
+            f, b, w, g = ptr_arrays
+            P = ctypes.POINTER(ctypes.c_void_p)
+            arr[i] = _abi.exm_batch_item(it["space"].handle, it["coord_space"].handle,
+                                         ctypes.c_void_p(it["coords"].data_ptr()), nf,
+                                         ctypes.cast(f, P), ctypes.cast(b, P),
+                                         ctypes.cast(w, P) if w is not None else None,
+                                         ctypes.cast(g, P) if g is not None else None)
+        self._keep.append(arr)
+        self.items = items
+        opts = loop_opts(cols_per_wave=cols_per_wave, tile_cells=unit_cells)
+        h = ctypes.c_void_p()
+        _abi.exm_batch_create(len(items), arr, ctypes.byref(opts), stream_handle(stream), ctypes.byref(h))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _abi.exm_batch_launch(self.handle, stream_handle(stream))
+
+    def info(self):
+        n = ctypes.c_int64()
+        b = ctypes.c_int32()
+        _abi.exm_batch_info(self.handle, ctypes.byref(n), ctypes.byref(b))
+        return n.value, b.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _abi is not None and _abi._lib is not None:
+            _abi._lib.exm_batch_destroy(h)
+        self.handle = None

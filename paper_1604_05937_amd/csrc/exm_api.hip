@@ -242,18 +242,16 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         if (d.waves_per_block > 4) d.waves_per_block = 4;
     }
     if (d.schedule == EXM_SCHED_STAGED) {
-        if (!d.tile_cells) d.tile_cells = default_tile_cells(P);
         d.waves_per_block = 4;
         d.cols_per_wave = 0;
+        if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 ? 16 : 8;
+        if (!d.tile_cells) d.tile_cells = std::min(64, staged_max_tile_cells(d.chunk_layers));
+        EXM_CHECK(d.tile_cells <= staged_max_tile_cells(d.chunk_layers), EXM_EUNSUPPORTED,
+                  "STAGED: tiles of %d cells need chunk_layers <= %d", d.tile_cells,
+                  staged_max_tile_cells(d.chunk_layers));
         const TilePlan* plan = nullptr;
         int32_t s = build_tile_plan(mesh, d.tile_cells, &plan);
         if (s != EXM_OK) return s;
-        if (!d.chunk_layers) {
-            d.chunk_layers = P.n_layers >= 48 ? 32 : (P.n_layers >= 12 ? 16 : 8);
-            while (d.chunk_layers > 8 &&
-                   staged_lds_bytes(P.kernel, P.element, plan->max_verts, d.chunk_layers) > kLdsDefault)
-                d.chunk_layers /= 2;
-        }
         EXM_CHECK(staged_lds_bytes(P.kernel, P.element, plan->max_verts, d.chunk_layers) <= kLdsLimit,
                   EXM_EUNSUPPORTED, "tiles of %d cells with %d-layer chunks do not fit in LDS", d.tile_cells,
                   d.chunk_layers);
@@ -451,7 +449,9 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
         for (int32_t c : {1, 2, 3, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 4, 0, 0});
         if (staged_supported(P.kernel, P.element))
             for (int32_t tc : {32, 64, 128, 256})
-                for (int32_t S : {8, 16, 32, 64}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
+                for (int32_t S : {8, 16, 32, 64})
+                    if (tc <= staged_max_tile_cells(S))
+                        cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
         if (cg)
             for (int32_t t : {32, 64, 128, 256})
                 for (int32_t c : {0, 2, 4})

@@ -1,29 +1,428 @@
-// Batched assembly (placeholder until the persistent kernel lands).
+// Batched assembly: many extruded meshes, several fields per mesh, forward
+// residual b = M f plus its adjoint g = M^T w = M w, in one persistent kernel
+// launch captured in a HIP graph.
+//
+// Work list.  Every mesh is cut into units of about unit_cells consecutive
+// base cells; a fixed grid of workgroups pulls units from a device counter
+// until the list is exhausted, so meshes of very different sizes and layer
+// counts balance across the GPU.  Within a unit the wavefronts walk columns as
+// in the DIRECT schedule (cols_per_wave cells side by side, one layer per
+// lane).  All fields of a mesh live on one space and share its explicit lists
+// (end of Section 3.3 of the paper): the lists and the prism geometry are read
+// once per column step and reused by every field and by the adjoint.
+//
+// Continuous (P1 x P1) outputs are summed with FP64 atomic adds; a step adds
+// its top level directly (no carry between steps), so a level shared by two
+// steps receives two adds.  DG0 outputs are written.  The graph first resets
+// the work counter and zeroes the continuous outputs with small kernels.
+#include <algorithm>
+#include <cstring>
+
+#include "exm_elements.hpp"
 #include "exm_internal.hpp"
+
+namespace exm {
+
+struct BatchItemDev {
+    int32_t element;
+    int32_t n_layers;
+    int32_t off;
+    int32_t cpw, seg;
+    int32_t n_fields;
+    int32_t adjoint;
+    int32_t pad;
+    int64_t xn;
+    const int32_t* fmap;
+    const int32_t* xmap;
+    const double* X;
+    const double* const* f;
+    double* const* b;
+    const double* const* w;
+    double* const* g;
+};
+
+struct Unit {
+    int32_t item;
+    int32_t cell_begin;
+    int32_t cell_count;
+    int32_t pad;
+};
+
+struct ZeroSeg {
+    double* p;
+    int64_t n;
+};
+
+__global__ void k_batch_reset(int32_t* counter) { *counter = 0; }
+
+__global__ void k_batch_zero(const ZeroSeg* __restrict__ segs)
+{
+    const ZeroSeg s = segs[blockIdx.y];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride) s.p[i] = 0.0;
+}
+
+__device__ __forceinline__ double next_lane(double v) { return __shfl_down(v, 1, 64); }
+
+// One step of a P1 x P1 column walk for every field of the item.
+__device__ __forceinline__ void batch_p1_step(const BatchItemDev& I, const int fb[3], const int xb[3],
+                                              const double gx[3], const double gy[3], int lsub, int seg, int l,
+                                              bool act, bool last)
+{
+    double zb[3], h[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) zb[a] = act ? I.X[2 * I.xn + (int64_t)xb[a] + l] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double zt = next_lane(zb[a]);
+        if (act && last) zt = I.X[2 * I.xn + (int64_t)xb[a] + l + 1];
+        h[a] = zt - zb[a];
+    }
+    const double twoA = twice_area(gx, gy);
+    const int lo = l * I.off;
+    const int passes = I.adjoint ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
+        for (int k = 0; k < I.n_fields; ++k) {
+            const double* src = pass == 0 ? I.f[k] : I.w[k];
+            double* dst = pass == 0 ? I.b[k] : I.g[k];
+            double xbv[3], xtv[3], yb[3] = {0.0, 0.0, 0.0}, yt[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xbv[a] = act ? src[fb[a] + lo] : 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xtv[a] = next_lane(xbv[a]);
+                if (act && last) xtv[a] = src[fb[a] + lo + I.off];
+            }
+            if (act) p1_mass(twoA, h, xbv, xtv, yb, yt);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double below = __shfl_up(yt[a], 1, 64);
+                if (act) {
+                    unsafeAtomicAdd(dst + fb[a] + lo, yb[a] + (lsub > 0 ? below : 0.0));
+                    if (last) unsafeAtomicAdd(dst + fb[a] + lo + I.off, yt[a]);
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void batch_dg0_step(const BatchItemDev& I, int f0, const int xb[3], const double gx[3],
+                                               const double gy[3], int l, bool act, bool last)
+{
+    double zb[3], h[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) zb[a] = act ? I.X[2 * I.xn + (int64_t)xb[a] + l] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double zt = next_lane(zb[a]);
+        if (act && last) zt = I.X[2 * I.xn + (int64_t)xb[a] + l + 1];
+        h[a] = zt - zb[a];
+    }
+    if (!act) return;
+    const double vol = twice_area(gx, gy) * (h[0] + h[1] + h[2]) * (1.0 / 6.0);
+    const int64_t d = f0 + (int64_t)l * I.off;
+    for (int k = 0; k < I.n_fields; ++k) I.b[k][d] = I.f[k][d] * vol;
+    if (I.adjoint)
+        for (int k = 0; k < I.n_fields; ++k) I.g[k][d] = I.w[k][d] * vol;
+}
+
+__global__ void __launch_bounds__(256) k_batch(const BatchItemDev* __restrict__ items, const Unit* __restrict__ units,
+                                               int32_t n_units, int32_t* counter)
+{
+    __shared__ int32_t s_unit;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t u = s_unit;
+        __syncthreads();
+        if (u >= n_units) break;   // every wave of the workgroup leaves together
+        const Unit U = units[u];
+        const BatchItemDev& I = items[U.item];
+        const int sub = lane / I.seg;
+        const int lsub = lane - sub * I.seg;
+        for (int grp = wave; grp * I.cpw < U.cell_count; grp += nwaves) {   // uniform over the wavefront
+            const int slot = grp * I.cpw + sub;
+            const bool valid = sub < I.cpw && slot < U.cell_count;
+            const int32_t cell = valid ? U.cell_begin + slot : 0;
+            int xb[3];
+            double gx[3], gy[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xb[a] = valid ? I.xmap[(int64_t)cell * 6 + 2 * a] : 0;
+                gx[a] = valid ? I.X[xb[a]] : 0.0;
+                gy[a] = valid ? I.X[I.xn + xb[a]] : 0.0;
+            }
+            if (I.element == EXM_ELEMENT_P1P1) {
+                int fb[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) fb[a] = valid ? I.fmap[(int64_t)cell * 6 + 2 * a] : 0;
+                for (int l0 = 0; l0 < I.n_layers; l0 += I.seg) {
+                    const int l = l0 + lsub;
+                    const bool act = valid && l < I.n_layers;
+                    const bool last = lsub == I.seg - 1 || l == I.n_layers - 1;
+                    batch_p1_step(I, fb, xb, gx, gy, lsub, I.seg, l, act, last);
+                }
+            } else {
+                const int f0 = valid ? I.fmap[cell] : 0;
+                for (int l0 = 0; l0 < I.n_layers; l0 += I.seg) {
+                    const int l = l0 + lsub;
+                    const bool act = valid && l < I.n_layers;
+                    const bool last = lsub == I.seg - 1 || l == I.n_layers - 1;
+                    batch_dg0_step(I, f0, xb, gx, gy, l, act, last);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace exm
 
 using namespace exm;
 
+struct exm_batch {
+    int device = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DevBuf<BatchItemDev> items;
+    DevBuf<Unit> units;
+    DevBuf<ZeroSeg> zsegs;
+    DevBuf<int32_t> counter;
+    DevBuf<const double*> ptrs;   // all field pointer arrays, item by item
+    int64_t n_units = 0;
+    int32_t n_zero = 0;
+    int32_t n_blocks = 0;
+    int32_t unit_cells = 0;
+    std::vector<int32_t> cpw;     // per item
+    ~exm_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace {
+
+int32_t batch_cpw(int32_t n_layers)
+{
+    // the cols_per_wave of the DIRECT schedule with the best lane use (<= 4)
+    int32_t best = 1;
+    double bu = 0.0;
+    for (int32_t c = 1; c <= 4; ++c) {
+        const int32_t seg = 64 / c;
+        const int64_t steps = (n_layers + seg - 1) / seg;
+        const double u = (double)c * n_layers / (64.0 * (double)steps);
+        if (u > bu + 1e-9) {
+            bu = u;
+            best = c;
+        }
+    }
+    return best;
+}
+
+int32_t enqueue(exm_batch* B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->counter.p);
+    EXM_TRY_HIP(hipGetLastError());
+    if (B->n_zero > 0) {
+        hipLaunchKernelGGL(k_batch_zero, dim3(256, (unsigned)B->n_zero), dim3(256), 0, s, B->zsegs.p);
+        EXM_TRY_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_batch, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p, B->units.p,
+                       (int32_t)B->n_units, B->counter.p);
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+int32_t build_units(exm_batch* B, const std::vector<int32_t>& n_cells, const std::vector<int32_t>& n_layers,
+                    int32_t unit_cells)
+{
+    // units of about unit_cells cells, scaled so that every unit holds a
+    // similar number of prisms (cells x layers)
+    std::vector<Unit> units;
+    int64_t ref_layers = 64;
+    for (size_t m = 0; m < n_cells.size(); ++m) {
+        int64_t uc = std::max<int64_t>(1, unit_cells * ref_layers / std::max(1, n_layers[m]));
+        uc = std::max<int64_t>(uc, B->cpw[m]);
+        for (int64_t c = 0; c < n_cells[m]; c += uc)
+            units.push_back(Unit{(int32_t)m, (int32_t)c, (int32_t)std::min<int64_t>(uc, n_cells[m] - c), 0});
+    }
+    // largest units first keeps the tail short
+    std::stable_sort(units.begin(), units.end(), [&](const Unit& a, const Unit& b) {
+        return (int64_t)a.cell_count * n_layers[a.item] > (int64_t)b.cell_count * n_layers[b.item];
+    });
+    EXM_CHECK(units.size() < (size_t)INT32_MAX, EXM_EOVERFLOW, "too many work units");
+    B->n_units = (int64_t)units.size();
+    B->unit_cells = unit_cells;
+    return B->units.upload(units.data(), units.size());
+}
+
+}  // namespace
+
 extern "C" {
 
-int32_t exm_batch_create(int32_t, const exm_batch_item*, const exm_loop_opts*, void*, exm_batch** out)
+int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm_loop_opts* opts, void* stream,
+                         exm_batch** out)
 {
     clear_error();
-    if (out) *out = nullptr;
-    return fail(EXM_EUNSUPPORTED, "batched assembly is not built yet");
+    EXM_CHECK(out != nullptr, EXM_EINVAL, "out is NULL");
+    *out = nullptr;
+    EXM_CHECK(n_items >= 1 && items != nullptr, EXM_EINVAL, "need n_items >= 1 and an item array");
+    EXM_CHECK(!opts || (opts->cols_per_wave >= 0 && opts->cols_per_wave <= 16), EXM_ERANGE,
+              "cols_per_wave outside [0, 16]");
+    EXM_CHECK(!opts || (opts->tile_cells >= 0 && opts->tile_cells <= 65536), EXM_ERANGE,
+              "tile_cells (cells per work unit) outside [0, 65536]");
+    auto B = std::make_unique<exm_batch>();
+    EXM_TRY_HIP(hipGetDevice(&B->device));
+    std::vector<BatchItemDev> dev(n_items);
+    std::vector<const double*> ptrs;
+    std::vector<ZeroSeg> zero;
+    std::vector<int32_t> n_cells(n_items), n_layers(n_items);
+    std::vector<size_t> ptr_base(n_items);
+    B->cpw.resize(n_items);
+    for (int32_t m = 0; m < n_items; ++m) {
+        const exm_batch_item& it = items[m];
+        EXM_CHECK(it.space && it.coord_space && it.coords, EXM_EINVAL, "item %d: NULL space, coord_space or coords", m);
+        EXM_CHECK(it.space->element == EXM_ELEMENT_P1P1 || it.space->element == EXM_ELEMENT_DG0DG0,
+                  EXM_EUNSUPPORTED, "item %d: batched assembly supports P1xP1 and DG0xDG0 spaces", m);
+        EXM_CHECK(it.coord_space->element == EXM_ELEMENT_P1P1 && it.coord_space->mesh == it.space->mesh, EXM_EINVAL,
+                  "item %d: coord_space must be a P1xP1 space on the same mesh", m);
+        EXM_CHECK(it.n_fields >= 1 && it.n_fields <= 64, EXM_ERANGE, "item %d: n_fields = %d outside [1, 64]", m,
+                  it.n_fields);
+        EXM_CHECK(it.f && it.b, EXM_EINVAL, "item %d: NULL f or b", m);
+        EXM_CHECK((it.w == nullptr) == (it.g == nullptr), EXM_EINVAL, "item %d: w and g must both be given or both NULL",
+                  m);
+        const int64_t n = it.space->n_dofs;
+        for (int32_t k = 0; k < it.n_fields; ++k) {
+            EXM_CHECK(it.f[k] && it.b[k], EXM_EINVAL, "item %d field %d: NULL pointer", m, k);
+            EXM_CHECK(it.f[k] != it.b[k], EXM_EINVAL, "item %d field %d: b aliases f", m, k);
+            if (it.w) {
+                EXM_CHECK(it.w[k] && it.g[k], EXM_EINVAL, "item %d field %d: NULL pointer", m, k);
+                EXM_CHECK(it.g[k] != it.b[k] && it.g[k] != it.w[k] && it.g[k] != it.f[k], EXM_EINVAL,
+                          "item %d field %d: g aliases another field", m, k);
+            }
+        }
+        const exm_mesh* mesh = it.space->mesh;
+        n_cells[m] = mesh->n[2];
+        n_layers[m] = mesh->n_layers;
+        B->cpw[m] = opts && opts->cols_per_wave ? opts->cols_per_wave : batch_cpw(mesh->n_layers);
+        BatchItemDev& d = dev[m];
+        std::memset(&d, 0, sizeof(d));
+        d.element = it.space->element;
+        d.n_layers = mesh->n_layers;
+        d.off = it.space->offsets[0];
+        d.cpw = B->cpw[m];
+        d.seg = 64 / d.cpw;
+        d.n_fields = it.n_fields;
+        d.adjoint = it.w ? 1 : 0;
+        d.xn = it.coord_space->n_dofs;
+        d.fmap = it.space->d_map.p;
+        d.xmap = it.coord_space->d_map.p;
+        d.X = it.coords;
+        ptr_base[m] = ptrs.size();
+        for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.f[k]);
+        for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.b[k]);
+        if (it.w) {
+            for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.w[k]);
+            for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.g[k]);
+        }
+        if (d.element == EXM_ELEMENT_P1P1) {
+            for (int32_t k = 0; k < it.n_fields; ++k) zero.push_back(ZeroSeg{it.b[k], n});
+            if (it.w)
+                for (int32_t k = 0; k < it.n_fields; ++k) zero.push_back(ZeroSeg{it.g[k], n});
+        }
+    }
+    EXM_CHECK(zero.size() <= 65535, EXM_ERANGE, "too many continuous outputs (%zu)", zero.size());
+    int32_t s = B->ptrs.upload(ptrs.data(), ptrs.size());
+    if (s != EXM_OK) return s;
+    for (int32_t m = 0; m < n_items; ++m) {
+        const double** p = B->ptrs.p + ptr_base[m];
+        const int32_t nf = items[m].n_fields;
+        dev[m].f = p;
+        dev[m].b = (double* const*)(p + nf);
+        if (items[m].w) {
+            dev[m].w = p + 2 * nf;
+            dev[m].g = (double* const*)(p + 3 * nf);
+        }
+    }
+    if ((s = B->items.upload(dev.data(), dev.size())) != EXM_OK) return s;
+    if ((s = B->zsegs.upload(zero.data(), zero.size())) != EXM_OK) return s;
+    B->n_zero = (int32_t)zero.size();
+    if ((s = B->counter.alloc(1)) != EXM_OK) return s;
+    int cus = 0;
+    EXM_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
+    B->n_blocks = std::max(1, cus) * 8;
+    hipStream_t hs = (hipStream_t)stream;
+    if (opts && opts->tile_cells) {
+        if ((s = build_units(B.get(), n_cells, n_layers, opts->tile_cells)) != EXM_OK) return s;
+    } else {
+        // project autotuner: time the candidate unit sizes on these buffers
+        // (the launch overwrites every output, so timing runs are harmless)
+        hipEvent_t e0, e1;
+        EXM_TRY_HIP(hipEventCreate(&e0));
+        EXM_TRY_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        int32_t best_uc = 64;
+        for (int32_t uc : {16, 64, 256}) {
+            if ((s = build_units(B.get(), n_cells, n_layers, uc)) != EXM_OK) break;
+            if ((s = enqueue(B.get(), hs)) != EXM_OK) break;
+            EXM_TRY_HIP(hipEventRecord(e0, hs));
+            if ((s = enqueue(B.get(), hs)) != EXM_OK) break;
+            EXM_TRY_HIP(hipEventRecord(e1, hs));
+            EXM_TRY_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            EXM_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_uc = uc;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (s != EXM_OK) return s;
+        if ((s = build_units(B.get(), n_cells, n_layers, best_uc)) != EXM_OK) return s;
+    }
+    // capture reset + zero + persistent kernel into a graph on a private stream
+    EXM_TRY_HIP(hipStreamSynchronize(hs));
+    EXM_TRY_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    EXM_TRY_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    s = enqueue(B.get(), B->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(B->cap, &g);
+    if (s != EXM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return fail(EXM_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    B->graph = g;
+    EXM_TRY_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    *out = B.release();
+    return EXM_OK;
 }
 
-int32_t exm_batch_launch(exm_batch*, void*)
+int32_t exm_batch_launch(exm_batch* batch, void* stream)
 {
     clear_error();
-    return fail(EXM_EUNSUPPORTED, "batched assembly is not built yet");
+    EXM_CHECK(batch != nullptr, EXM_EINVAL, "batch is NULL");
+    int32_t s = check_pending();
+    if (s != EXM_OK) return s;
+    EXM_TRY_HIP(hipGraphLaunch(batch->exec, (hipStream_t)stream));
+    return EXM_OK;
 }
 
-int32_t exm_batch_info(const exm_batch*, int64_t*, int32_t*)
+int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_blocks)
 {
     clear_error();
-    return fail(EXM_EUNSUPPORTED, "batched assembly is not built yet");
+    EXM_CHECK(batch != nullptr, EXM_EINVAL, "batch is NULL");
+    if (n_units) *n_units = batch->n_units;
+    if (n_blocks) *n_blocks = batch->n_blocks;
+    return EXM_OK;
 }
 
-void exm_batch_destroy(exm_batch*) {}
+void exm_batch_destroy(exm_batch* batch) { delete batch; }
 
 }  // extern "C"

@@ -10,20 +10,25 @@
 // vertical-innermost numbering) into LDS once; the element kernels of all
 // (cell, layer) pairs read LDS only and sum their element vectors into LDS;
 // the workgroup then adds every (vertex, level) sum to HBM once, and in the
-// same phase copies the next chunk in.  The (x, y) of every tile vertex is
-// read once per tile: columns are vertical.
+// same phase copies the next chunk in.
+//
+// Everything that does not change along the column is fetched once per tile:
+// the column starts, shared flags and (x, y) of the tile's vertices go to LDS,
+// and each thread keeps the tile-local vertices of its (at most NP) cells in
+// registers for all chunks -- thread t owns layer t % S of cells t / S + k *
+// (256 / S).  Columns are vertical, so (x, y) is the same at every level.
 //
 // Shared vertices (touched by another tile) are updated with FP64 atomics, or
 // with plain read-add-write when one launch holds one colour of tiles.
-//
-// Index maps use shifts only: S is a power of two, items (row, j) with j in
-// [0, S) fastest, and the chunk's top level handled by its own short loop.
 #include "exm_elements.hpp"
 #include "exm_tiled.hpp"
 
 namespace exm {
 
 namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPasses = 4;   // cells per thread: tile_cells <= kPasses * 256 / S
 
 __device__ __forceinline__ unsigned xcd_block_s(unsigned b, unsigned G)
 {
@@ -55,37 +60,55 @@ struct Log2 {
     static constexpr int v = S == 8 ? 3 : (S == 16 ? 4 : (S == 32 ? 5 : 6));
 };
 
-// Copy levels l0 .. l0 + nl of NA vertex-column arrays into st[k][v * L + j].
-// Array k < NZ is the z coordinate (k == 0), the others are inputs.
+// Per-tile vertex data in LDS: tag (id | shared bit), coordinate and field
+// column starts, x and y.
+struct VertLds {
+    int32_t* tag;
+    int32_t* xst;
+    int32_t* fst;
+    double* xs;
+    double* ys;
+};
+
+__device__ __forceinline__ void load_vertices(const ColArgs& a, const TileArgs& t, const Tile& T, const VertLds& V,
+                                              bool with_field)
+{
+    for (int v = threadIdx.x; v < T.nv; v += blockDim.x) {
+        const int32_t tag = t.verts[T.vb + v];
+        const int32_t xs = t.xstart[eid(tag)];
+        V.tag[v] = tag;
+        V.xst[v] = xs;
+        V.fst[v] = with_field ? t.fstart0[eid(tag)] : 0;
+        V.xs[v] = a.X[xs];
+        V.ys[v] = a.X[a.xn + xs];
+    }
+}
+
+// Copy levels l0 .. l0 + nl of NA vertex-column arrays into st[k][v * L + j]
+// (array 0 is z, the others are inputs on the field space).
 template <int S, int NA>
-__device__ __forceinline__ void stage(const ColArgs& a, const TileArgs& t, const Tile& T, int l0, int nl,
-                                      const double* const src[NA], const int32_t* const* starts, double* st, int VL)
+__device__ __forceinline__ void stage(const Tile& T, const VertLds& V, int l0, int nl, const double* const src[NA],
+                                      double* st, int VL)
 {
     constexpr int L = S + 1;
     constexpr int LS = Log2<S>::v;
     const int nvS = T.nv << LS;
+    for (int it = threadIdx.x; it < nvS; it += blockDim.x) {
+        const int v = it >> LS;
+        const int j = it & (S - 1);
+        if (j > nl) continue;
+        const int64_t xo = (int64_t)V.xst[v] + l0 + j;
+        const int64_t fo = (int64_t)V.fst[v] + l0 + j;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) {
-        const int32_t* sk = starts[k];
-        for (int it = threadIdx.x; it < nvS; it += blockDim.x) {
-            const int v = it >> LS;
-            const int j = it & (S - 1);
-            if (j <= nl) st[k * VL + v * L + j] = src[k][(int64_t)sk[eid(t.verts[T.vb + v])] + l0 + j];
+        for (int k = 0; k < NA; ++k) st[k * VL + v * L + j] = src[k][k == 0 ? xo : fo];
+    }
+    if (nl == S)   // the chunk's top level
+        for (int v = threadIdx.x; v < T.nv; v += blockDim.x) {
+            const int64_t xo = (int64_t)V.xst[v] + l0 + S;
+            const int64_t fo = (int64_t)V.fst[v] + l0 + S;
+#pragma unroll
+            for (int k = 0; k < NA; ++k) st[k * VL + v * L + S] = src[k][k == 0 ? xo : fo];
         }
-        if (nl == S)   // the chunk's top level
-            for (int v = threadIdx.x; v < T.nv; v += blockDim.x)
-                st[k * VL + v * L + S] = src[k][(int64_t)sk[eid(t.verts[T.vb + v])] + l0 + S];
-    }
-}
-
-// (x, y) of every tile vertex, once.
-__device__ __forceinline__ void stage_xy(const ColArgs& a, const TileArgs& t, const Tile& T, double* xs, double* ys)
-{
-    for (int v = threadIdx.x; v < T.nv; v += blockDim.x) {
-        const int64_t d = t.xstart[eid(t.verts[T.vb + v])];
-        xs[v] = a.X[d];
-        ys[v] = a.X[a.xn + d];
-    }
 }
 
 template <int FORM>
@@ -137,38 +160,53 @@ __device__ __forceinline__ void element(double twoA, const double h[3], const do
 
 }  // namespace
 
-// P1 x P1 forms.  LDS (doubles): xs, ys [vstride]; st [1 + NIN][vstride * L]
-// (z, then the inputs); acc [2][NOUT][vstride * L] (two chunks in flight).
+// P1 x P1 forms.  LDS: ints tag/xst/fst [vstride]; doubles xs, ys [vstride],
+// st [1 + NIN][vstride * L] (z, then the inputs), acc [2][NOUT][vstride * L]
+// (this chunk and the next).
 template <int FORM, bool ATOMIC, int S>
-__global__ void __launch_bounds__(256) k_staged_p1(const ColArgs a, const TileArgs t)
+__global__ void __launch_bounds__(kThreads) k_staged_p1(const ColArgs a, const TileArgs t)
 {
     constexpr int NIN = Form<FORM>::NIN;
     constexpr int NOUT = Form<FORM>::NOUT;
     constexpr int NA = 1 + NIN;
     constexpr int L = S + 1;
     constexpr int LS = Log2<S>::v;
+    constexpr int CPP = kThreads >> LS;   // cells per pass
     extern __shared__ double lds[];
     const Tile T = tile_of(t);
     const int VL = t.vstride * L;
-    double* xs = lds;
-    double* ys = xs + t.vstride;
-    double* st = ys + t.vstride;
+    VertLds V;
+    V.xs = lds;
+    V.ys = V.xs + t.vstride;
+    double* st = V.ys + t.vstride;
     double* accb[2] = {st + NA * VL, st + NA * VL + NOUT * VL};
+    V.tag = (int32_t*)(accb[1] + NOUT * VL);
+    V.xst = V.tag + t.vstride;
+    V.fst = V.xst + t.vstride;
     const double* const ins[3] = {a.in0, a.in1, a.in2};
     const double* src[NA];
-    const int32_t* starts[NA];
     src[0] = a.X + 2 * a.xn;
-    starts[0] = t.xstart;
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) {
-        src[1 + k] = ins[k];
-        starts[1 + k] = t.fstart0;
-    }
+    for (int k = 0; k < NIN; ++k) src[1 + k] = ins[k];
     double* const out[3] = {a.out0, a.out1, a.out2};
     const int lane = threadIdx.x & 63;
+    const int j = threadIdx.x & (S - 1);
 
-    stage_xy(a, t, T, xs, ys);
-    stage<S, NA>(a, t, T, 0, min(S, a.n_layers), src, starts, st, VL);
+    // the thread's cells (tile-local vertex indices), fixed for all chunks
+    int lv[kPasses][3];
+    bool has[kPasses];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        const int c = (threadIdx.x >> LS) + p * CPP;
+        has[p] = c < T.nc;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lv[p][q] = has[p] ? t.lcv[(int64_t)(T.cb + c) * 3 + q] : 0;
+    }
+    const int npass = (T.nc + CPP - 1) / CPP;   // uniform over the workgroup
+
+    load_vertices(a, t, T, V, true);
+    __syncthreads();
+    stage<S, NA>(T, V, 0, min(S, a.n_layers), src, st, VL);
     for (int i = threadIdx.x; i < NOUT * VL; i += blockDim.x) accb[0][i] = 0.0;
     __syncthreads();
     int cur = 0;
@@ -176,17 +214,12 @@ __global__ void __launch_bounds__(256) k_staged_p1(const ColArgs a, const TileAr
         const int nl = min(S, a.n_layers - l0);
         const bool last_chunk = l0 + nl == a.n_layers;
         double* acc = accb[cur];
-        // element kernels of the chunk; item (cell, j) with j fastest, so a
-        // wavefront holds consecutive layers of a cell and a shuffle adds the
-        // top contribution of layer j - 1 to the bottom of layer j.
-        const int nitems = T.nc << LS;
-        const int wave_base = threadIdx.x - lane;
-        for (int base = wave_base; base < nitems; base += blockDim.x) {   // uniform over the wavefront
-            const int it = base + lane;
-            const int c = it >> LS;
-            const int j = it & (S - 1);
-            const bool act = it < nitems && j < nl;
-            int lv[3] = {0, 0, 0};
+        // element kernels; lanes hold consecutive layers of a cell, so the
+        // top contribution of layer j - 1 comes from the previous lane
+#pragma unroll
+        for (int p = 0; p < kPasses; ++p) {
+            if (p >= npass) break;
+            const bool act = has[p] && j < nl;
             double yb[NOUT][3], yt[NOUT][3];
 #pragma unroll
             for (int o = 0; o < NOUT; ++o)
@@ -196,10 +229,9 @@ __global__ void __launch_bounds__(256) k_staged_p1(const ColArgs a, const TileAr
                 double x[3], y[3], h[3], b[NIN][3], tp[NIN][3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    lv[q] = t.lcv[(int64_t)(T.cb + c) * 3 + q];
-                    const int o = lv[q] * L + j;
-                    x[q] = xs[lv[q]];
-                    y[q] = ys[lv[q]];
+                    const int o = lv[p][q] * L + j;
+                    x[q] = V.xs[lv[p][q]];
+                    y[q] = V.ys[lv[p][q]];
                     h[q] = st[o + 1] - st[o];
 #pragma unroll
                     for (int k = 0; k < NIN; ++k) {
@@ -215,9 +247,9 @@ __global__ void __launch_bounds__(256) k_staged_p1(const ColArgs a, const TileAr
                 for (int q = 0; q < 3; ++q) {
                     const double below = __shfl_up(yt[o][q], 1, 64);
                     if (act) {
-                        double* p = acc + o * VL + lv[q] * L + j;
-                        atomicAdd(p, yb[o][q] + (j > 0 ? below : 0.0));
-                        if (j == nl - 1) atomicAdd(p + 1, yt[o][q]);
+                        double* ptr = acc + o * VL + lv[p][q] * L + j;
+                        atomicAdd(ptr, yb[o][q] + (j > 0 ? below : 0.0));
+                        if (j == nl - 1) atomicAdd(ptr + 1, yt[o][q]);
                     }
                 }
         }
@@ -228,13 +260,13 @@ __global__ void __launch_bounds__(256) k_staged_p1(const ColArgs a, const TileAr
         const int nvS = T.nv << LS;
         for (int it = threadIdx.x; it < nvS; it += blockDim.x) {
             const int v = it >> LS;
-            const int j = it & (S - 1);
-            if (j < nl) {
-                const int32_t tag = t.verts[T.vb + v];
-                const int64_t d = (int64_t)t.fstart0[eid(tag)] + l0 + j;
+            const int jj = it & (S - 1);
+            if (jj < nl) {
+                const int32_t tag = V.tag[v];
+                const int64_t d = (int64_t)V.fst[v] + l0 + jj;
 #pragma unroll
                 for (int o = 0; o < NOUT; ++o) {
-                    const double s = acc[o * VL + v * L + j];
+                    const double s = acc[o * VL + v * L + jj];
                     if (ATOMIC && eshared(tag))
                         unsafeAtomicAdd(out[o] + d, s);
                     else
@@ -243,12 +275,12 @@ __global__ void __launch_bounds__(256) k_staged_p1(const ColArgs a, const TileAr
             }
             if (!last_chunk)
 #pragma unroll
-                for (int o = 0; o < NOUT; ++o) nxt[o * VL + v * L + j] = j == 0 ? acc[o * VL + v * L + nl] : 0.0;
+                for (int o = 0; o < NOUT; ++o) nxt[o * VL + v * L + jj] = jj == 0 ? acc[o * VL + v * L + nl] : 0.0;
         }
         for (int v = threadIdx.x; v < T.nv; v += blockDim.x) {
             if (last_chunk) {   // the column's top level
-                const int32_t tag = t.verts[T.vb + v];
-                const int64_t d = (int64_t)t.fstart0[eid(tag)] + l0 + nl;
+                const int32_t tag = V.tag[v];
+                const int64_t d = (int64_t)V.fst[v] + l0 + nl;
 #pragma unroll
                 for (int o = 0; o < NOUT; ++o) {
                     const double s = acc[o * VL + v * L + nl];
@@ -263,75 +295,91 @@ __global__ void __launch_bounds__(256) k_staged_p1(const ColArgs a, const TileAr
             }
         }
         if (last_chunk) break;
-        stage<S, NA>(a, t, T, l0 + S, min(S, a.n_layers - l0 - S), src, starts, st, VL);
+        stage<S, NA>(T, V, l0 + S, min(S, a.n_layers - l0 - S), src, st, VL);
         cur ^= 1;
         __syncthreads();
     }
+    (void)lane;
 }
 
 // DG0 x DG0 and DG1 x DG1: only z is staged (two buffers, so the next chunk
 // is copied in while this one is computed); the cell's own DoFs are
 // consecutive in layers and read / written directly.
 template <int NDOF, int S>
-__global__ void __launch_bounds__(256) k_staged_dg(const ColArgs a, const TileArgs t)
+__global__ void __launch_bounds__(kThreads) k_staged_dg(const ColArgs a, const TileArgs t)
 {
     constexpr int L = S + 1;
     constexpr int LS = Log2<S>::v;
+    constexpr int CPP = kThreads >> LS;
     extern __shared__ double lds[];
     const Tile T = tile_of(t);
     const int VL = t.vstride * L;
-    double* xs = lds;
-    double* ys = xs + t.vstride;
-    double* zb[2] = {ys + t.vstride, ys + t.vstride + VL};
+    VertLds V;
+    V.xs = lds;
+    V.ys = V.xs + t.vstride;
+    double* zb[2] = {V.ys + t.vstride, V.ys + t.vstride + VL};
+    V.tag = (int32_t*)(zb[1] + VL);
+    V.xst = V.tag + t.vstride;
+    V.fst = V.xst + t.vstride;
     const double* const src[1] = {a.X + 2 * a.xn};
-    const int32_t* const starts[1] = {t.xstart};
-    stage_xy(a, t, T, xs, ys);
-    stage<S, 1>(a, t, T, 0, min(S, a.n_layers), src, starts, zb[0], VL);
+    const int j = threadIdx.x & (S - 1);
+    int lv[kPasses][3];
+    int64_t d0[kPasses];
+    bool has[kPasses];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        const int c = (threadIdx.x >> LS) + p * CPP;
+        has[p] = c < T.nc;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lv[p][q] = has[p] ? t.lcv[(int64_t)(T.cb + c) * 3 + q] : 0;
+        d0[p] = has[p] ? (int64_t)a.fmap[(int64_t)t.cells[T.cb + c] * NDOF] : 0;
+    }
+    const int npass = (T.nc + CPP - 1) / CPP;
+    load_vertices(a, t, T, V, false);
+    __syncthreads();
+    stage<S, 1>(T, V, 0, min(S, a.n_layers), src, zb[0], VL);
     __syncthreads();
     int cur = 0;
     for (int l0 = 0; l0 < a.n_layers; l0 += S) {
         const int nl = min(S, a.n_layers - l0);
         const bool last_chunk = l0 + nl == a.n_layers;
-        if (!last_chunk) stage<S, 1>(a, t, T, l0 + S, min(S, a.n_layers - l0 - S), src, starts, zb[cur ^ 1], VL);
+        if (!last_chunk) stage<S, 1>(T, V, l0 + S, min(S, a.n_layers - l0 - S), src, zb[cur ^ 1], VL);
         const double* zs = zb[cur];
-        const int nitems = T.nc << LS;
-        for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
-            const int c = it >> LS;
-            const int j = it & (S - 1);
-            if (j >= nl) continue;
+#pragma unroll
+        for (int p = 0; p < kPasses; ++p) {
+            if (p >= npass) break;
+            if (!(has[p] && j < nl)) continue;
             double x[3], y[3], h[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                const int lv = t.lcv[(int64_t)(T.cb + c) * 3 + q];
-                x[q] = xs[lv];
-                y[q] = ys[lv];
-                h[q] = zs[lv * L + j + 1] - zs[lv * L + j];
+                x[q] = V.xs[lv[p][q]];
+                y[q] = V.ys[lv[p][q]];
+                h[q] = zs[lv[p][q] * L + j + 1] - zs[lv[p][q] * L + j];
             }
             const double twoA = twice_area(x, y);
-            const int32_t cell = t.cells[T.cb + c];
-            const int64_t d0 = (int64_t)a.fmap[(int64_t)cell * NDOF] + (int64_t)(l0 + j) * a.off;
+            const int64_t d = d0[p] + (int64_t)(l0 + j) * a.off;
             if constexpr (NDOF == 1) {
-                const double yv = dg0_mass(twoA, h, a.in0[d0]);
+                const double yv = dg0_mass(twoA, h, a.in0[d]);
                 if (a.write)
-                    a.out0[d0] = yv;
+                    a.out0[d] = yv;
                 else
-                    a.out0[d0] += yv;
+                    a.out0[d] += yv;
             } else {
                 double xb[3], xt[3], yb[3], yt[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    xb[q] = a.in0[d0 + 2 * q];
-                    xt[q] = a.in0[d0 + 2 * q + 1];
+                    xb[q] = a.in0[d + 2 * q];
+                    xt[q] = a.in0[d + 2 * q + 1];
                 }
                 p1_mass(twoA, h, xb, xt, yb, yt);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     if (a.write) {
-                        a.out0[d0 + 2 * q] = yb[q];
-                        a.out0[d0 + 2 * q + 1] = yt[q];
+                        a.out0[d + 2 * q] = yb[q];
+                        a.out0[d + 2 * q + 1] = yt[q];
                     } else {
-                        a.out0[d0 + 2 * q] += yb[q];
-                        a.out0[d0 + 2 * q + 1] += yt[q];
+                        a.out0[d + 2 * q] += yb[q];
+                        a.out0[d + 2 * q + 1] += yt[q];
                     }
                 }
             }
@@ -347,15 +395,18 @@ __global__ void __launch_bounds__(256) k_staged_dg(const ColArgs a, const TileAr
 size_t staged_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t S)
 {
     const size_t VL = (size_t)vstride * (S + 1);
-    const size_t xy = 2 * (size_t)vstride;
-    if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1) return sizeof(double) * (xy + 2 * VL);
+    const size_t per_vertex = 2 * sizeof(double) + 3 * sizeof(int32_t);
+    if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1)
+        return sizeof(double) * 2 * VL + per_vertex * vstride;
     if (element != EXM_ELEMENT_P1P1) return 0;
     int nin = 1, nout = 1;
     if (kernel == EXM_K_CUBIC) nin = 2;
     if (kernel == EXM_K_CUBIC_VJP) nin = 2, nout = 2;
     if (kernel == EXM_K_CUBIC_FUSED) nin = 3, nout = 3;
-    return sizeof(double) * (xy + (1 + nin + 2 * nout) * VL);
+    return sizeof(double) * (1 + nin + 2 * nout) * VL + per_vertex * vstride;
 }
+
+int32_t staged_max_tile_cells(int32_t S) { return kPasses * (kThreads / S); }
 
 bool staged_supported(int32_t kernel, int32_t element)
 {
@@ -366,7 +417,7 @@ bool staged_supported(int32_t kernel, int32_t element)
 template <int S>
 static int32_t launch_staged_s(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
 {
-    dim3 grid((unsigned)t.tile_count), block(256);
+    dim3 grid((unsigned)t.tile_count), block(kThreads);
     const bool atomic = P.race == EXM_RACE_ATOMIC;
 #define EXM_SL(K) hipLaunchKernelGGL(K, grid, block, lds, s, a, t)
 #define EXM_SL_RACE(F)                                   \

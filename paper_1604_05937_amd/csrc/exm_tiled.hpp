@@ -48,6 +48,7 @@ ColArgs col_args(const LoopLaunch& P);
 int32_t tiled_max_threads(int32_t kernel, int32_t element);
 size_t staged_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t S);
 bool staged_supported(int32_t kernel, int32_t element);
+int32_t staged_max_tile_cells(int32_t S);
 int32_t launch_staged(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t S, size_t lds, hipStream_t s);
 size_t tiled_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t seg);
 int32_t launch_tiled(const LoopLaunch& P, const TileArgs& t, int32_t threads, size_t lds, hipStream_t s);

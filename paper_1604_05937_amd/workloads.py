@@ -1,0 +1,127 @@
+"""The benchmark workloads as seeded synthetic inputs on the device, and their
+algorithmic byte counts.
+
+Input preparation and bookkeeping only: meshes come from ``meshgen``, the
+numbering and every assembly run in libexm.
+
+Algorithmic bytes of one column loop = the bytes it must move at least once:
+input fields, the output (read and written for INC, written for WRITE), the
+z coordinate of every extruded vertex, (x, y) once per base vertex (columns
+are vertical), and the explicit lists it reads (field lists and the
+coordinate list, int32).  The paper's valuable data volume (input, output and
+the full coordinate field, Section 4.2.1) is reported beside it.
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import (EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_MASS, EXM_READ, EXM_WRITE, Mesh, Space,
+               coordinate_field, par_loop)
+from . import meshgen
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources and the C header (identifies a kernel build)."""
+    h = hashlib.sha256()
+    files = sorted(os.path.join(_PKG, "csrc", f) for f in os.listdir(os.path.join(_PKG, "csrc")))
+    files.append(os.path.join(os.path.dirname(_PKG), "include", "exm.h"))
+    for p in files:
+        with open(p, "rb") as fh:
+            h.update(os.path.basename(p).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+@dataclass
+class Extruded:
+    base: meshgen.BaseMesh
+    n_layers: int
+    mesh: Mesh
+    Vx: Space
+    X: object                         # device coordinates [3, n]
+    spaces: dict = field(default_factory=dict)
+    vc: np.ndarray | None = None      # host vertex coordinates [N0, lambda+1, 3]
+
+    @property
+    def n_prisms(self) -> int:
+        return self.base.n_cells * self.n_layers
+
+    def space(self, name: str) -> Space:
+        if name == "P1":
+            return self.Vx
+        if name not in self.spaces:
+            self.spaces[name] = Space(self.mesh, name)
+        return self.spaces[name]
+
+
+def extruded(n: int, n_layers: int, order: str = "rcm", keep_host_coords: bool = False, terrain: float = 0.0):
+    base = meshgen.tri_square(n, order=order)
+    mesh = Mesh(base, n_layers)
+    Vx = Space(mesh, "P1")
+    vc = meshgen.extruded_vertex_coords(base, n_layers, terrain=terrain)
+    X = coordinate_field(Vx, vc)
+    return Extruded(base, n_layers, mesh, Vx, X, {}, vc if keep_host_coords else None)
+
+
+def device_values(n: int, seed: int):
+    """n FP64 values U[-1, 1] from numpy's seeded PCG64, on the device."""
+    import torch
+    return torch.from_numpy(meshgen.uniform_values(n, seed=seed)).to("cuda")
+
+
+def map_bytes(e: Extruded, name: str) -> int:
+    k = {"P1": 6, "DG0": 1, "DG1": 6, "P2": 18}[name]
+    lists = 4 * e.base.n_cells * k
+    if name != "P1":
+        lists += 4 * e.base.n_cells * 6   # the coordinate list
+    return lists
+
+
+def coord_bytes(e: Extruded) -> int:
+    """z at every extruded vertex + (x, y) per base vertex."""
+    return 8 * e.Vx.n_dofs + 16 * e.base.n_vertices
+
+
+def mass_bytes(e: Extruded, name: str) -> dict:
+    """Byte counts of one y = M x / residual assembly on space `name`."""
+    n = e.space(name).n_dofs
+    inc = name in ("P1", "P2")
+    alg = 8 * n + 8 * n * (2 if inc else 1) + coord_bytes(e) + map_bytes(e, name)
+    valuable = 8 * n * 2 + 24 * e.Vx.n_dofs
+    return dict(algorithmic=alg, valuable=valuable, n_dofs=n)
+
+
+def cubic_bytes(e: Extruded, fused: bool) -> dict:
+    n = e.Vx.n_dofs
+    n_in = 3 if fused else 2
+    n_out = 3 if fused else 1
+    alg = 8 * n * n_in + 16 * n * n_out + coord_bytes(e) + map_bytes(e, "P1")
+    valuable = 8 * n * (n_in + n_out) + 24 * n
+    return dict(algorithmic=alg, valuable=valuable, n_dofs=n)
+
+
+def mass_args(e: Extruded, name: str, x, y):
+    acc = EXM_INC if name in ("P1", "P2") else EXM_WRITE
+    V = e.space(name)
+    return [(x, V, EXM_READ), (y, V, acc)]
+
+
+def run_mass(e: Extruded, name: str, x, y, **opts):
+    par_loop(EXM_K_MASS, e.mesh, e.X, e.Vx, mass_args(e, name, x, y), **opts)
+
+
+def run_cubic(e: Extruded, u, f, F, **opts):
+    V = e.Vx
+    par_loop(EXM_K_CUBIC, e.mesh, e.X, V, [(u, V, EXM_READ), (f, V, EXM_READ), (F, V, EXM_INC)], **opts)
+
+
+def run_fused(e: Extruded, u, f, w, F, gu, gf, **opts):
+    V = e.Vx
+    par_loop(EXM_K_CUBIC_FUSED, e.mesh, e.X, V, [(u, V, EXM_READ), (f, V, EXM_READ), (w, V, EXM_READ),
+                                                (F, V, EXM_INC), (gu, V, EXM_INC), (gf, V, EXM_INC)], **opts)

@@ -1,0 +1,53 @@
+"""The C ABI: the built library exports every entry point include/exm.h
+declares, and host-side validation rejects bad input before any device work
+(these calls never reach the GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1604_05937_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "exm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(exm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert set(_declared()) == set(_abi.EXPORTED)
+
+
+def test_library_exports_every_symbol():
+    lib = _abi.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.exm_abi_version() == 1
+
+
+def test_mesh_validation_errors():
+    lib = _abi.load()
+    h = ctypes.c_void_p()
+    cv = np.array([[0, 1, 2], [0, 2, 5]], dtype=np.int32)   # vertex 5 out of range for 4 vertices
+    st = lib.exm_mesh_create(4, 0, 2, cv.ctypes.data_as(ctypes.c_void_p), None, 3, ctypes.byref(h))
+    assert st == _abi.EXM_ERANGE and "outside" in _abi.last_error()
+    cv = np.array([[0, 1, 2]], dtype=np.int32)
+    assert lib.exm_mesh_create(3, 0, 1, cv.ctypes.data_as(ctypes.c_void_p), None, 0, ctypes.byref(h)) == _abi.EXM_ERANGE
+    cv = np.array([[0, 1, 1]], dtype=np.int32)
+    assert lib.exm_mesh_create(3, 0, 1, cv.ctypes.data_as(ctypes.c_void_p), None, 2, ctypes.byref(h)) == _abi.EXM_EINVAL
+    assert lib.exm_mesh_create(3, 0, 1, None, None, 2, ctypes.byref(h)) == _abi.EXM_EINVAL
+    assert lib.exm_space_create(None, None, 0, None, ctypes.byref(h)) == _abi.EXM_EINVAL
+    assert lib.exm_par_loop(99, None, 0, None, None, None) == _abi.EXM_EINVAL
+    assert lib.exm_stream_triad(None, None, None, 1.0, 10, 256, 0, None) == _abi.EXM_EINVAL
+    assert lib.exm_batch_create(0, None, None, None, ctypes.byref(h)) == _abi.EXM_EINVAL
+
+
+def test_python_wrappers_raise():
+    with pytest.raises(_abi.ExmError) as e:
+        _abi.exm_par_loop(99, None, 0, None, None, None)
+    assert e.value.status == _abi.EXM_EINVAL

@@ -1,0 +1,85 @@
+"""Batched persistent launch (HIP graph): every output equals its single
+par_loop counterpart and the oracle, on every graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1604_05937_amd as exm
+from paper_1604_05937_amd import meshgen
+from tests.gpu_common import assert_close, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n_meshes, scale, n_fields, adjoint, seed=meshgen.SEED_BATCH):
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    items, refs = [], []
+    for it in meshgen.batch_meshes(n_meshes=n_meshes, scale=scale, seed=seed):
+        mesh = exm.Mesh(it.mesh, it.n_layers)
+        Vx = exm.Space(mesh, "P1")
+        V = exm.Space(mesh, it.space) if it.space != "P1" else Vx
+        vc = meshgen.extruded_vertex_coords(it.mesh, it.n_layers)
+        X = exm.coordinate_field(Vx, vc)
+        rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        d = dict(space=V, coord_space=Vx, coords=X, mesh=mesh, base=it,
+                 f=[rnd() for _ in range(n_fields)], b=[V.zeros() for _ in range(n_fields)])
+        if adjoint:
+            d["w"] = [rnd() for _ in range(n_fields)]
+            d["g"] = [V.zeros() for _ in range(n_fields)]
+        items.append(d)
+        refs.append(vc)
+    return items, refs
+
+
+def _single(d, x):
+    y = d["space"].zeros()
+    acc = exm.EXM_INC if d["space"].element == exm.EXM_ELEMENT_P1P1 else exm.EXM_WRITE
+    exm.par_loop(exm.EXM_K_MASS, d["mesh"], d["coords"], d["coord_space"], [(x, d["space"], exm.EXM_READ),
+                                                                             (y, d["space"], acc)])
+    return y
+
+
+@pytest.mark.parametrize("cpw,unit", [(0, 0), (1, 8), (3, 64), (2, 1000)])
+def test_batch_matches_single_launches(cpw, unit):
+    say(f"batch cpw={cpw} unit={unit}")
+    items, _ = _setup(6, 0.01, 3, True)
+    B = exm.Batch(items, cols_per_wave=cpw, unit_cells=unit)
+    n_units, n_blocks = B.info()
+    assert n_units >= len(items) and n_blocks > 0
+    ref = [([_single(d, f) for f in d["f"]], [_single(d, w) for w in d["w"]]) for d in items]
+    torch.cuda.synchronize()
+    for replay in range(3):
+        # eager work between replays: scribble on the outputs
+        for d in items:
+            for t in d["b"] + d["g"]:
+                t.fill_(123.0)
+        torch.cuda.synchronize()
+        B.launch()
+        torch.cuda.synchronize()
+        for d, (rb, rg) in zip(items, ref):
+            for got, want in zip(d["b"] + d["g"], rb + rg):
+                g_, w_ = got.cpu().numpy(), want.cpu().numpy()
+                assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what=f"replay {replay}")
+
+
+def test_batch_matches_oracle():
+    items, vcs = _setup(4, 0.004, 2, True, seed=9)
+    B = exm.Batch(items)
+    B.launch()
+    torch.cuda.synchronize()
+    for d, vc in zip(items, vcs):
+        name = "P1" if d["space"].element == exm.EXM_ELEMENT_P1P1 else "DG0"
+        pr = oracle.Problem(d["base"].mesh, d["base"].n_layers, name, vc)
+        for src, dst in ((d["f"], d["b"]), (d["w"], d["g"])):
+            for x, y in zip(src, dst):
+                xn = x.cpu().numpy()
+                assert_close(y.cpu().numpy(), pr.mass(xn), pr.mass_abs(xn), what=f"batch vs oracle {name}")
+
+
+def test_batch_rejects_bad_items():
+    items, _ = _setup(2, 0.004, 1, False)
+    items[0]["b"] = [items[0]["f"][0]]   # output aliases input
+    with pytest.raises(exm.ExmError):
+        exm.Batch(items)
