@@ -117,7 +117,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["p1", "dg0"], help="launch only this kernel (for profiling)")
+    ap.add_argument("--only", choices=["p1", "dg0", "triad"],
+                    help="launch only this kernel, warmup + steps times, and print nothing (for rocprofv3)")
+    ap.add_argument("--config", default=None,
+                    help="with --only: the launch configuration as JSON (exm_loop_opts fields) instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -133,6 +136,17 @@ def main():
 
     exm.load_library()
     torch.cuda.init()
+    if args.only == "triad":
+        # calibration kernel for the HBM counters: reads 16 n bytes, writes 8 n
+        n = 1 << 26
+        a = torch.empty(n, dtype=torch.float64, device="cuda")
+        b = torch.rand(n, dtype=torch.float64, device="cuda")
+        c = torch.rand(n, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup + args.steps):
+            exm.stream_triad(a, b, c, 3.0)
+        torch.cuda.synchronize()
+        log(f"done: triad n = {n}, {16 * n} bytes read and {8 * n} written per launch")
+        return
     t0 = time.time()
     work = W.extruded(512, 100, keep_host_coords=not args.no_cpu)
     V1, V0 = work.space("P1"), work.space("DG0")
@@ -146,28 +160,29 @@ def main():
     setup_s = time.time() - t0
     log(f"setup {setup_s:.1f}s: {work.base.n_cells} cells x {work.n_layers} layers, P1 {V1.n_dofs} DoFs, DG0 {V0.n_dofs} DoFs")
 
+    by1 = W.mass_bytes(work, "P1")
+    by0 = W.mass_bytes(work, "DG0")
+    if args.only in ("p1", "dg0"):
+        name, f, b = ("P1", f1, b1) if args.only == "p1" else ("DG0", f0, b0)
+        if args.config:
+            cfg = json.loads(args.config)
+        else:
+            cfg = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, name, f, b))
+        torch.cuda.synchronize()
+        for _ in range(args.warmup + args.steps):
+            W.run_mass(work, name, f, b, **cfg)
+        torch.cuda.synchronize()
+        log(f"done: {name} {cfg}, {(by1 if name == 'P1' else by0)['algorithmic']} algorithmic bytes per launch")
+        return
+
     # autotuned launch configurations (the library keeps them for later calls)
     t0 = time.time()
     cfg1 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "P1", f1, b1))
     cfg0 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "DG0", f0, b0))
     log(f"autotune {time.time() - t0:.1f}s: P1 {cfg1}  DG0 {cfg0}")
 
-    by1 = W.mass_bytes(work, "P1")
-    by0 = W.mass_bytes(work, "DG0")
     k1 = lambda: W.run_mass(work, "P1", f1, b1)
     k2 = lambda: W.run_mass(work, "DG0", f0, b0)
-    if args.only == "p1":
-        for _ in range(args.warmup + args.steps):
-            k1()
-        torch.cuda.synchronize()
-        log("done")
-        return
-    if args.only == "dg0":
-        for _ in range(args.warmup + args.steps):
-            k2()
-        torch.cuda.synchronize()
-        log("done")
-        return
 
     # ---- timed region: K steps of (P1 assembly, DG0 assembly) ----
     s = torch.cuda.current_stream()
