@@ -190,6 +190,12 @@ typedef struct {
                               /* once per chunk of chunk_layers layers, loading the next      */
                               /* chunk while it computes the current one; the element kernels */
                               /* read LDS only.  P1xP1, DG0DG0 and DG1DG1 (P2P2 runs TILED)   */
+#define EXM_SCHED_PIPELINED 4 /* like STAGED, but the column segments (coordinates, inputs   */
+                              /* and the INC output) reach LDS through asynchronous           */
+                              /* global-to-LDS copies issued one chunk ahead, so a chunk's    */
+                              /* loads, the previous chunk's stores and the current chunk's   */
+                              /* element kernels overlap.  P1xP1 mass action; other kernels   */
+                              /* fall back to STAGED.  Field pointers must be 16-byte aligned */
 
 typedef struct {
     int32_t race;              /* EXM_RACE_*                                             */
@@ -197,9 +203,11 @@ typedef struct {
     int32_t cols_per_wave;     /* DIRECT, TILED: base cells side by side in one          */
                                /* wavefront, each taking 64 / cols_per_wave lanes =      */
                                /* layers per step: 1..16 (0 = choose)                    */
-    int32_t waves_per_block;   /* DIRECT: 1..4; TILED: 1..8; STAGED: 4 (0 = choose)      */
-    int32_t tile_cells;        /* TILED, STAGED: 8..1024 target cells per tile (0 = choose) */
-    int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64 layers per chunk (0 = choose) */
+    int32_t waves_per_block;   /* DIRECT: 1..4; TILED: 1..8; STAGED, PIPELINED: 4 (0 = choose) */
+    int32_t tile_cells;        /* TILED, STAGED, PIPELINED: 8..1024 target cells per tile */
+                               /* (0 = choose)                                           */
+    int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64; PIPELINED: 8, 16 or 32 layers */
+                               /* per chunk (0 = choose)                                 */
 } exm_loop_opts;
 
 /* opts may be NULL (all defaults). */

@@ -206,7 +206,8 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (opts) {
         EXM_CHECK(opts->race >= 0 && opts->race <= 2, EXM_EINVAL, "unknown race strategy %d", opts->race);
-        EXM_CHECK(opts->schedule >= 0 && opts->schedule <= 3, EXM_EINVAL, "unknown schedule %d", opts->schedule);
+        EXM_CHECK(opts->schedule >= 0 && opts->schedule <= EXM_SCHED_PIPELINED, EXM_EINVAL, "unknown schedule %d",
+                  opts->schedule);
         EXM_CHECK(opts->cols_per_wave >= 0 && opts->cols_per_wave <= 16, EXM_ERANGE,
                   "cols_per_wave = %d outside [0, 16]", opts->cols_per_wave);
         EXM_CHECK(opts->waves_per_block >= 0 && opts->waves_per_block <= 16, EXM_ERANGE,
@@ -231,6 +232,32 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
+    if (d.schedule == EXM_SCHED_PIPELINED && !pipe_supported(P.kernel, P.element)) {
+        d.schedule = EXM_SCHED_STAGED;
+        if (d.chunk_layers > 32) d.chunk_layers = 0;
+    }
+    if (d.schedule == EXM_SCHED_PIPELINED) {
+        d.waves_per_block = 4;
+        d.cols_per_wave = 0;
+        if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 ? 16 : 8;
+        EXM_CHECK(d.chunk_layers <= 32, EXM_ERANGE, "PIPELINED: chunk_layers = %d, use 8, 16 or 32", d.chunk_layers);
+        if (!d.tile_cells) d.tile_cells = std::min(64, pipe_max_tile_cells(P.element, d.chunk_layers));
+        EXM_CHECK(d.tile_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+                  "PIPELINED: tiles of %d cells with %d-layer chunks exceed %d cells", d.tile_cells, d.chunk_layers,
+                  pipe_max_tile_cells(P.element, d.chunk_layers));
+        const TilePlan* plan = nullptr;
+        int32_t s = build_tile_plan(mesh, d.tile_cells, &plan);
+        if (s != EXM_OK) return s;
+        if (P.element == EXM_ELEMENT_P1P1)
+            EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(d.chunk_layers), EXM_EUNSUPPORTED,
+                      "PIPELINED: tiles of %d cells touch up to %d vertices, more than %d with %d-layer chunks",
+                      d.tile_cells, plan->max_verts, pipe_max_tile_verts(d.chunk_layers), d.chunk_layers);
+        EXM_CHECK(pipe_lds_bytes(P.kernel, P.element, plan->max_verts, plan->max_cells, d.chunk_layers) <= kLdsLimit,
+                  EXM_EUNSUPPORTED, "tiles of %d cells with %d-layer chunks do not fit in LDS", d.tile_cells,
+                  d.chunk_layers);
+        ch = d;
+        return EXM_OK;
+    }
     if (d.schedule == EXM_SCHED_STAGED && !staged_supported(P.kernel, P.element)) {
         d.schedule = EXM_SCHED_TILED;
         d.chunk_layers = 0;
@@ -384,9 +411,38 @@ static int32_t run_staged(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_op
     return launch_staged(P, a, t, ch.chunk_layers, lds, stream);
 }
 
+static int32_t run_pipe(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
+{
+    const TilePlan* plan = nullptr;
+    int32_t s = build_tile_plan(mesh, ch.tile_cells, &plan);
+    if (s != EXM_OK) return s;
+    const size_t lds = pipe_lds_bytes(P.kernel, P.element, plan->max_verts, plan->max_cells, ch.chunk_layers);
+    P.race = ch.race;
+    P.shape = make_shape(1, 1);
+    const ColArgs a = col_args(P);
+    TileArgs t;
+    fill_tile_args(plan, P, t);
+    if (ch.race == EXM_RACE_COLOUR && continuous(P.element)) {
+        t.tiles = plan->colour_tiles.p;
+        for (int32_t k = 0; k < plan->n_colours; ++k) {
+            t.tile_begin = (int32_t)plan->colour_off[k];
+            t.tile_count = (int32_t)(plan->colour_off[k + 1] - plan->colour_off[k]);
+            s = launch_pipe(P, a, t, plan->max_cells, ch.chunk_layers, lds, stream);
+            if (s != EXM_OK) return s;
+        }
+        return EXM_OK;
+    }
+    t.tiles = nullptr;
+    t.tile_begin = 0;
+    t.tile_count = plan->n_tiles;
+    if (!continuous(P.element)) P.race = EXM_RACE_ATOMIC;   // nothing is shared
+    return launch_pipe(P, a, t, plan->max_cells, ch.chunk_layers, lds, stream);
+}
+
 static int32_t run_on_mesh(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
 {
     if (ch.schedule == EXM_SCHED_DIRECT) return run_direct(mesh, P, ch, stream);
+    if (ch.schedule == EXM_SCHED_PIPELINED) return run_pipe(mesh, P, ch, stream);
     if (ch.schedule == EXM_SCHED_STAGED) return run_staged(mesh, P, ch, stream);
     return run_tiled(mesh, P, ch, stream);
 }
@@ -452,6 +508,11 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                 for (int32_t S : {8, 16, 32, 64})
                     if (tc <= staged_max_tile_cells(S))
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
+        if (pipe_supported(P.kernel, P.element))
+            for (int32_t tc : {32, 64, 128, 256})
+                for (int32_t S : {8, 16, 32})
+                    if (tc <= pipe_max_tile_cells(P.element, S))
+                        cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
         if (cg)
             for (int32_t t : {32, 64, 128, 256})
                 for (int32_t c : {0, 2, 4})
@@ -532,7 +593,7 @@ int32_t exm_autotune_load(const char* path)
                          o.tile_cells >> o.chunk_layers),
                   EXM_EINVAL, "%s:%d: malformed line", path, ln);
         EXM_CHECK((o.race == EXM_RACE_ATOMIC || o.race == EXM_RACE_COLOUR) &&
-                      o.schedule >= EXM_SCHED_DIRECT && o.schedule <= EXM_SCHED_STAGED && o.cols_per_wave >= 0 &&
+                      o.schedule >= EXM_SCHED_DIRECT && o.schedule <= EXM_SCHED_PIPELINED && o.cols_per_wave >= 0 &&
                       o.cols_per_wave <= 16 && o.waves_per_block >= 1 && o.waves_per_block <= 16 &&
                       o.tile_cells >= 0 && o.tile_cells <= 1024 &&
                       (o.chunk_layers == 0 || o.chunk_layers == 8 || o.chunk_layers == 16 || o.chunk_layers == 32 ||

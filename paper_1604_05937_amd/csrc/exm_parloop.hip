@@ -600,6 +600,7 @@ ColArgs col_args(const LoopLaunch& P)
     a.cpw = P.shape.cpw;
     a.seg = P.shape.seg;
     a.xn = P.xspace->n_dofs;
+    a.fn = P.fspace->n_dofs;
     a.fmap = P.fmap;
     a.xmap = P.xmap;
     a.X = P.X;

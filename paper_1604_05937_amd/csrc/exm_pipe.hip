@@ -1,0 +1,559 @@
+// PIPELINED schedule of the column loop: the tile walk of the STAGED
+// schedule, with every column segment copied into LDS by the asynchronous
+// global-to-LDS loads of gfx950 (16 bytes per lane, no registers involved),
+// issued one chunk of layers ahead of its use.
+//
+// One workgroup owns a compact tile of base cells (the tile plan) and walks
+// its columns in chunks of S layers.  Per chunk and per tile vertex, the
+// segment of levels l0 .. l0 + S of z, of the input field and of the INC
+// output (y) lands in LDS.  The vertical-innermost numbering makes each
+// segment contiguous in HBM, so the copy is a handful of 16-byte transfers per
+// vertex, and every level of every array crosses the memory path once per
+// tile.
+//
+// Per chunk k the workgroup, after one wait for its own copies and one
+// barrier:
+//   1. writes chunk k-1 back: every (vertex, level) sum goes to HBM once, a
+//      plain store for vertices only this tile touches (whose LDS slot
+//      started from the old output value) and an FP64 atomic add for shared
+//      vertices (whose slot started from zero); the chunk's top level carries
+//      into level 0 of chunk k;
+//   2. barrier, then issues the copies of chunk k+1 into the other buffers;
+//   3. computes chunk k from LDS: each thread owns R consecutive layers of a
+//      few cells (fixed for the whole column, with 2A in registers), adds
+//      the top contribution of layer r to the bottom one of layer r + 1 in
+//      registers, and sends each level's sum to LDS with one LDS atomic.
+// The copies of chunk k+1 and the stores of chunk k-1 are in flight while
+// chunk k computes; the wait at the top of the next chunk finds them done.
+//
+// Copies are 16-byte aligned: a vertex's LDS slot starts at the even global
+// index at or below its first level, so the slot holds one extra level below
+// when the column start is odd (the parity is fixed because S is even).
+// Base pointers must be 16-byte aligned; the host checks.
+#include "exm_elements.hpp"
+#include "exm_tiled.hpp"
+
+namespace exm {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPasses = 4;   // cells per thread: tile_cells <= kPasses * 256 * kLayers / S
+constexpr int kLayers = 4;   // consecutive layers of one cell per thread
+constexpr int kCopy = 4;     // 16-byte copy slots per thread and array: verts * (S / 2 + 1) <= 256 * kCopy
+
+__device__ __forceinline__ unsigned xcd_block_p(unsigned b, unsigned G)
+{
+    const unsigned q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Barrier for LDS traffic only: this wave's LDS reads and writes are done
+// before any wave passes.  Asynchronous copies are waited for separately, and
+// outstanding global stores are not waited for.
+__device__ __forceinline__ void lds_barrier()
+{
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    __asm__ __volatile__("" ::: "memory");
+}
+
+// All vector-memory operations of this wave are complete (copies landed in
+// LDS, stores acknowledged).
+__device__ __forceinline__ void wait_copies()
+{
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
+    __asm__ __volatile__("" ::: "memory");
+}
+
+// Copy 16 bytes from src to LDS at wave_base + 16 * (lane id), asynchronously.
+// wave_base must be the same for every lane of the wavefront.
+__device__ __forceinline__ void copy16(const double* src, double* wave_base)
+{
+    __builtin_amdgcn_global_load_lds((const void*)src,
+                                     (__attribute__((address_space(3))) void*)wave_base, 16, 0, 0);
+}
+
+// FP64 add into LDS (no return value).  Written in assembly so that the
+// compiler does not hold it until the asynchronous copies in flight have
+// landed (they target the other buffers); lds_barrier() waits for it.
+__device__ __forceinline__ void lds_add(double* p, double v)
+{
+    const uint32_t a = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) double*)p;
+    __asm__ __volatile__("ds_add_f64 %0, %1" : : "v"(a), "v"(v));
+}
+
+__device__ __forceinline__ int32_t vid(int32_t tagged) { return tagged & 0x7fffffff; }
+__device__ __forceinline__ bool vshared(int32_t tagged) { return tagged < 0; }
+
+template <int S>
+struct Chunk {
+    static constexpr int LS = S == 8 ? 3 : (S == 16 ? 4 : 5);
+    static constexpr int P2 = S + 2;      // doubles per vertex slot (even)
+    static constexpr int PP = P2 / 2;     // 16-byte pairs per vertex slot
+    static constexpr int R = kLayers;     // layers per thread
+    static constexpr int G = S / R;       // threads per cell
+    static constexpr int CPP = kThreads / G;   // cells per pass
+};
+
+}  // namespace
+
+// P1 x P1 mass action / RHS, y += M x (INC).  LDS: Z[2], X[2], Y[2] of
+// vstride * (S + 2) doubles, then x, y (doubles) and tag, column start (ints)
+// per tile vertex.  ATOMIC: shared vertices are added atomically; otherwise
+// one launch holds one colour of tiles and every vertex is read-add-written.
+template <int S, bool ATOMIC>
+__global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const TileArgs t)
+{
+    using C = Chunk<S>;
+    constexpr int P2 = C::P2, PP = C::PP, LS = C::LS, R = C::R, G = C::G, CPP = C::CPP;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int VS = t.vstride * P2;
+    double* const Zs = lds;
+    double* const Xs = lds + 2 * VS;
+    double* const Ys = lds + 4 * VS;
+    double* const Tx = lds + 6 * VS;
+    double* const Ty = Tx + t.vstride;
+    int32_t* const Ttag = (int32_t*)(Ty + t.vstride);
+    int32_t* const Txst = Ttag + t.vstride;
+    const int64_t n = a.xn;
+    const double* const z = a.X + 2 * n;
+    const double* const x = a.in0;
+    double* const y = a.out0;
+    const int lam = a.n_layers;
+
+    // tile vertex table: tag, column start, (x, y) of the column
+    for (int v = tid; v < nv; v += kThreads) {
+        const int32_t tag = t.verts[vb0 + v];
+        const int32_t xs = t.xstart[vid(tag)];
+        Ttag[v] = tag;
+        Txst[v] = xs;
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+    }
+    lds_barrier();
+
+    // this thread's cells: LDS slot start of each vertex (with the parity
+    // shift) and 2A, fixed for the whole column; the thread takes layers
+    // r0 .. r0 + R - 1 of every chunk
+    const int r0 = (tid & (G - 1)) * R;
+    int vb[kPasses][3];
+    double twoA[kPasses];
+    bool has[kPasses];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        const int c = tid / G + p * CPP;
+        has[p] = c < nc;
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            vb[p][q] = lv * P2 + (Txst[lv] & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
+    }
+    const int npass = (nc + CPP - 1) / CPP;
+
+    // this thread's copy slots: pair e = tid + 256 i of the tile's vertex slots
+    int32_t sidx[kCopy], lim[kCopy];
+    bool sh[kCopy];
+#pragma unroll
+    for (int i = 0; i < kCopy; ++i) {
+        const int e = tid + kThreads * i;
+        const int v = e / PP, w = e - (e / PP) * PP;
+        const bool ok = v < nv;
+        const int32_t xs = ok ? Txst[v] : 0;
+        const int sv = xs & 1;
+        sidx[i] = xs - sv + 2 * w;                 // even: 16-byte aligned pair
+        lim[i] = ok ? 2 * w - sv : 0x7fffffff;     // needed iff lim <= levels in the chunk
+        sh[i] = ATOMIC && ok && vshared(Ttag[v]);
+    }
+    const int wave_e = tid & ~63;
+
+    auto issue_copies = [&](int k) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        const int b = k & 1;
+#pragma unroll
+        for (int i = 0; i < kCopy; ++i) {
+            if (lim[i] > nl) continue;
+            const int64_t g = (int64_t)sidx[i] + l0;
+            const int eb = 2 * (kThreads * i + wave_e);   // wave's first double in the slot array
+            const int e2 = 2 * (kThreads * i + tid);
+            if (g + 1 < n) {
+                copy16(z + g, Zs + b * VS + eb);
+                copy16(x + g, Xs + b * VS + eb);
+                if (!sh[i]) copy16(y + g, Ys + b * VS + eb);
+            } else {
+                // the array's last element: keep the read inside the array
+                Zs[b * VS + e2] = z[g];
+                Xs[b * VS + e2] = x[g];
+                if (!sh[i]) Ys[b * VS + e2] = y[g];
+            }
+            if (sh[i]) {   // shared vertices start from zero and are added atomically
+                Ys[b * VS + e2] = 0.0;
+                Ys[b * VS + e2 + 1] = 0.0;
+            }
+        }
+    };
+
+    const int nch = (lam + S - 1) / S;
+    issue_copies(0);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        wait_copies();
+        lds_barrier();
+        // 1. write chunk k-1 back; carry its top level into chunk k
+        if (k > 0) {
+            const double* Yp = Ys + (b ^ 1) * VS;
+            const int l0p = l0 - S;
+            for (int it = tid; it < (nv << LS); it += kThreads) {
+                const int v = it >> LS, jj = it & (S - 1);
+                const int32_t xs = Txst[v];
+                const double s = Yp[v * P2 + (xs & 1) + jj];
+                const int64_t g = (int64_t)xs + l0p + jj;
+                if (ATOMIC && vshared(Ttag[v]))
+                    unsafeAtomicAdd(y + g, s);
+                else
+                    y[g] = s;
+            }
+        }
+        double* const Yb = Ys + b * VS;
+        for (int v = tid; v < nv; v += kThreads) {
+            const int o = v * P2 + (Txst[v] & 1);
+            if (k > 0) Yb[o] += Ys[(b ^ 1) * VS + o + S];
+            if (nl == S && l0 + S < lam) Yb[o + S] = 0.0;   // level l0 + S belongs to chunk k+1
+        }
+        lds_barrier();
+        // 2. copies of chunk k+1
+        if (k + 1 < nch) issue_copies(k + 1);
+        // 3. element kernels of chunk k: R consecutive layers of one cell per
+        // thread; a level's sum over the thread's layers goes to LDS once
+        const double* const Zb = Zs + b * VS;
+        const double* const Xb = Xs + b * VS;
+#pragma unroll
+        for (int p = 0; p < kPasses; ++p) {
+            if (p >= npass) break;
+            if (!has[p] || r0 >= nl) continue;
+            int o[3];
+            double zc[3], xc[3], acc[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                o[q] = vb[p][q] + r0;
+                zc[q] = Zb[o[q]];
+                xc[q] = Xb[o[q]];
+                acc[q] = 0.0;
+            }
+            int r = 0;
+#pragma unroll
+            for (; r < R; ++r) {
+                if (r0 + r >= nl) break;
+                double zn[3], xn[3], h[3], yb[3], yt[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    zn[q] = Zb[o[q] + r + 1];
+                    xn[q] = Xb[o[q] + r + 1];
+                    h[q] = zn[q] - zc[q];
+                }
+                p1_mass(twoA[p], h, xc, xn, yb, yt);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    lds_add(Yb + o[q] + r, acc[q] + yb[q]);
+                    acc[q] = yt[q];
+                    zc[q] = zn[q];
+                    xc[q] = xn[q];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) lds_add(Yb + o[q] + r, acc[q]);
+        }
+    }
+    // write back the last chunk, its top level included
+    lds_barrier();
+    {
+        const int k = nch - 1;
+        const double* Yl = Ys + (k & 1) * VS;
+        const int l0 = k * S, nl = lam - l0;
+        for (int it = tid; it < (nv << LS); it += kThreads) {
+            const int v = it >> LS, jj = it & (S - 1);
+            if (jj >= nl) continue;
+            const int32_t xs = Txst[v];
+            const double s = Yl[v * P2 + (xs & 1) + jj];
+            const int64_t g = (int64_t)xs + l0 + jj;
+            if (ATOMIC && vshared(Ttag[v]))
+                unsafeAtomicAdd(y + g, s);
+            else
+                y[g] = s;
+        }
+        for (int v = tid; v < nv; v += kThreads) {
+            const int32_t xs = Txst[v];
+            const double s = Yl[v * P2 + (xs & 1) + nl];
+            const int64_t g = (int64_t)xs + lam;
+            if (ATOMIC && vshared(Ttag[v]))
+                unsafeAtomicAdd(y + g, s);
+            else
+                y[g] = s;
+        }
+    }
+}
+
+// DG0 x DG0 (NDOF = 1) and DG1 x DG1 (NDOF = 6) mass action / RHS.  A
+// cell's DoFs form one contiguous column of NDOF * lambda values, so per
+// chunk the tile's cells copy NDOF * S values each and its vertices S + 1
+// levels of z.  Outputs belong to one cell: each thread keeps the results of
+// its (cell, layer) pairs in registers and stores them to HBM while the next
+// chunk computes, after that chunk's copies are issued.  LDS: Z[2] of
+// vstride * (S + 2), F[2] of cstride * (NDOF * S + 2) doubles, then x, y
+// (doubles) per tile vertex, column start per vertex and per cell (ints).
+template <int NDOF, int S, int NP>
+__global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const TileArgs t, int32_t cstride)
+{
+    using C = Chunk<S>;
+    constexpr int P2 = C::P2, PP = C::PP, LS = C::LS;
+    constexpr int QF = NDOF * S + 2;      // doubles per cell slot (even)
+    constexpr int QP = QF / 2;
+    constexpr int CPP = kThreads >> LS;   // one layer per thread
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int VS = t.vstride * P2;
+    const int FS = cstride * QF;
+    double* const Zs = lds;
+    double* const Fs = lds + 2 * VS;
+    double* const Tx = Fs + 2 * FS;
+    double* const Ty = Tx + t.vstride;
+    int32_t* const Txst = (int32_t*)(Ty + t.vstride);
+    int32_t* const Tcst = Txst + t.vstride;
+    const int64_t n = a.xn;
+    const double* const z = a.X + 2 * n;
+    const double* const f = a.in0;
+    double* const out = a.out0;
+    const int lam = a.n_layers;
+    const int64_t nf = a.fn;
+
+    for (int v = tid; v < nv; v += kThreads) {
+        const int32_t xs = t.xstart[vid(t.verts[vb0 + v])];
+        Txst[v] = xs;
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+    }
+    for (int c = tid; c < nc; c += kThreads) Tcst[c] = a.fmap[(int64_t)t.cells[cb + c] * NDOF];
+    lds_barrier();
+
+    const int j = tid & (S - 1);
+    int vb[NP][3], fb[NP];
+    int32_t d0[NP];
+    double twoA[NP];
+    bool has[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int c = (tid >> LS) + p * CPP;
+        has[p] = c < nc;
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            vb[p][q] = lv * P2 + (Txst[lv] & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
+        const int32_t cs = has[p] ? Tcst[c] : 0;
+        d0[p] = cs;
+        fb[p] = (has[p] ? c : 0) * QF + (cs & 1);
+    }
+    const int npass = (nc + CPP - 1) / CPP;
+    const int wave_e = tid & ~63;
+
+    auto issue_copies = [&](int k) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        const int b = k & 1;
+        // z: vertex slots, levels l0 .. l0 + nl
+        for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int v = e / PP, w = e - (e / PP) * PP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int sv = xs & 1;
+            if (2 * w - sv > nl) continue;
+            const int64_t g = (int64_t)xs - sv + l0 + 2 * w;
+            if (g + 1 < n)
+                copy16(z + g, Zs + b * VS + 2 * (e0 + wave_e));
+            else
+                Zs[b * VS + 2 * e] = z[g];
+        }
+        // field: cell slots, DoFs of layers l0 .. l0 + nl - 1
+        for (int e0 = 0; e0 < nc * QP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int c = e / QP, w = e - (e / QP) * QP;
+            if (c >= nc) continue;
+            const int32_t cs = Tcst[c];
+            const int sc = cs & 1;
+            if (2 * w - sc >= NDOF * nl) continue;
+            const int64_t g = (int64_t)cs - sc + (int64_t)l0 * NDOF + 2 * w;
+            if (g + 1 < nf)
+                copy16(f + g, Fs + b * FS + 2 * (e0 + wave_e));
+            else
+                Fs[b * FS + 2 * e] = f[g];
+        }
+    };
+
+    // results of the previous chunk, stored after the next chunk's copies are issued
+    double res[NP][NDOF];
+    int prev_l0 = -1, prev_nl = 0;
+    auto store_results = [&]() {
+        if (prev_l0 < 0) return;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass) break;
+            if (!has[p] || j >= prev_nl) continue;
+            const int64_t d = (int64_t)d0[p] + (int64_t)(prev_l0 + j) * NDOF;
+#pragma unroll
+            for (int k = 0; k < NDOF; ++k) {
+                if (a.write)
+                    out[d + k] = res[p][k];
+                else
+                    out[d + k] += res[p][k];
+            }
+        }
+    };
+
+    const int nch = (lam + S - 1) / S;
+    issue_copies(0);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        wait_copies();
+        lds_barrier();
+        if (k + 1 < nch) issue_copies(k + 1);
+        store_results();
+        const double* const Zb = Zs + b * VS;
+        const double* const Fb = Fs + b * FS;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass) break;
+            if (!has[p] || j >= nl) continue;
+            double h[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) h[q] = Zb[vb[p][q] + j + 1] - Zb[vb[p][q] + j];
+            const int o = fb[p] + NDOF * j;
+            if constexpr (NDOF == 1) {
+                res[p][0] = dg0_mass(twoA[p], h, Fb[o]);
+            } else {
+                double xb[3], xt[3], yb[3], yt[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    xb[q] = Fb[o + 2 * q];
+                    xt[q] = Fb[o + 2 * q + 1];
+                }
+                p1_mass(twoA[p], h, xb, xt, yb, yt);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    res[p][2 * q] = yb[q];
+                    res[p][2 * q + 1] = yt[q];
+                }
+            }
+        }
+        prev_l0 = l0;
+        prev_nl = nl;
+    }
+    store_results();
+}
+
+// ---------------------------------------------------------------------------
+
+static int dg_ndof(int32_t element) { return element == EXM_ELEMENT_DG1DG1 ? 6 : 1; }
+
+size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t cstride, int32_t S)
+{
+    if (kernel != EXM_K_MASS) return 0;
+    if (element == EXM_ELEMENT_P1P1)
+        return sizeof(double) * (6 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + 2 * sizeof(int32_t) * vstride;
+    if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1)
+        return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)cstride * (dg_ndof(element) * S + 2) +
+                                 2 * (size_t)vstride) +
+               sizeof(int32_t) * ((size_t)vstride + cstride);
+    return 0;
+}
+
+bool pipe_supported(int32_t kernel, int32_t element)
+{
+    return kernel == EXM_K_MASS &&
+           (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1);
+}
+
+int32_t pipe_max_tile_cells(int32_t element, int32_t S)
+{
+    if (element == EXM_ELEMENT_DG0DG0) return 4 * kThreads / S;
+    if (element == EXM_ELEMENT_DG1DG1) return 2 * kThreads / S;
+    return kPasses * kThreads * kLayers / S;
+}
+
+int32_t pipe_max_tile_verts(int32_t S) { return kThreads * kCopy / (S / 2 + 1); }
+
+template <int S>
+static void launch_pipe_s(bool atomic, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+{
+    if (atomic)
+        hipLaunchKernelGGL((k_pipe_p1<S, true>), dim3((unsigned)t.tile_count), dim3(kThreads), lds, s, a, t);
+    else
+        hipLaunchKernelGGL((k_pipe_p1<S, false>), dim3((unsigned)t.tile_count), dim3(kThreads), lds, s, a, t);
+}
+
+template <int S>
+static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds,
+                           hipStream_t s)
+{
+    const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    if (element == EXM_ELEMENT_DG0DG0)
+        hipLaunchKernelGGL((k_pipe_dg<1, S, 4>), grid, block, lds, s, a, t, cstride);
+    else
+        hipLaunchKernelGGL((k_pipe_dg<6, S, 2>), grid, block, lds, s, a, t, cstride);
+}
+
+int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t cstride, int32_t S, size_t lds,
+                    hipStream_t s)
+{
+    if (t.tile_count <= 0) return EXM_OK;
+    EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
+              "the PIPELINED schedule runs the mass action on P1xP1, DG0xDG0 and DG1xDG1");
+    const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.out0;
+    EXM_CHECK((al & 15) == 0, EXM_EUNSUPPORTED, "the PIPELINED schedule needs 16-byte aligned field pointers");
+    if (P.element != EXM_ELEMENT_P1P1) {
+        switch (S) {
+        case 8: launch_pipe_dg<8>(P.element, a, t, cstride, lds, s); break;
+        case 16: launch_pipe_dg<16>(P.element, a, t, cstride, lds, s); break;
+        case 32: launch_pipe_dg<32>(P.element, a, t, cstride, lds, s); break;
+        default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 16 or 32", S);
+        }
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
+    const bool atomic = P.race != EXM_RACE_COLOUR;
+    switch (S) {
+    case 8: launch_pipe_s<8>(atomic, a, t, lds, s); break;
+    case 16: launch_pipe_s<16>(atomic, a, t, lds, s); break;
+    case 32: launch_pipe_s<32>(atomic, a, t, lds, s); break;
+    default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 16 or 32", S);
+    }
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+}  // namespace exm

@@ -12,6 +12,7 @@ struct ColArgs {
     int32_t cpw, seg;      // columns per wavefront, lanes (layers per step) per column
     int32_t write;         // DG outputs: 1 WRITE, 0 INC
     int64_t xn;            // DoFs of the coordinate space (component stride of X)
+    int64_t fn;            // DoFs of the field space (length of every field array)
     const int32_t* __restrict__ fmap;   // field explicit lists [n_cells * k]
     const int32_t* __restrict__ xmap;   // coordinate explicit lists [n_cells * 6]
     const double* __restrict__ X;       // coordinates, component-major [3 * xn]
@@ -50,6 +51,12 @@ size_t staged_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_
 bool staged_supported(int32_t kernel, int32_t element);
 int32_t staged_max_tile_cells(int32_t S);
 int32_t launch_staged(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t S, size_t lds, hipStream_t s);
+size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t cstride, int32_t S);
+bool pipe_supported(int32_t kernel, int32_t element);
+int32_t pipe_max_tile_cells(int32_t element, int32_t S);
+int32_t pipe_max_tile_verts(int32_t S);
+int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t cstride, int32_t S, size_t lds,
+                    hipStream_t s);
 size_t tiled_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t seg);
 int32_t launch_tiled(const LoopLaunch& P, const TileArgs& t, int32_t threads, size_t lds, hipStream_t s);
 

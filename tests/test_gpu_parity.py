@@ -36,7 +36,7 @@ def test_numbering_bit_exact(space, n, lam, order):
             np.testing.assert_array_equal(starts, ref.column_starts(d1).astype(np.int32))
 
 
-SCHEDULES = [exm.EXM_SCHED_DIRECT, exm.EXM_SCHED_TILED, exm.EXM_SCHED_STAGED]
+SCHEDULES = [exm.EXM_SCHED_DIRECT, exm.EXM_SCHED_TILED, exm.EXM_SCHED_STAGED, exm.EXM_SCHED_PIPELINED]
 RACES = [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR]
 
 
@@ -101,6 +101,57 @@ def test_mass_staged_shapes(space, tile, chunk, race):
             assert e.status == exm._abi.EXM_EUNSUPPORTED and tile * chunk > 1024, str(e)
             return
         assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"staged mass {space} tile={tile} S={chunk} lam={lam}")
+
+
+@pytest.mark.parametrize("space", ["P1", "DG0", "DG1"])
+@pytest.mark.parametrize("tile", [8, 29, 64, 128])
+@pytest.mark.parametrize("chunk", [8, 16, 32])
+@pytest.mark.parametrize("race", RACES)
+def test_mass_pipelined_shapes(space, tile, chunk, race):
+    say(f"pipelined shape {space} tile={tile} chunk={chunk} race={race}")
+    base = meshgen.tri_square(10, order="random" if tile == 29 else "rcm")
+    for lam in (1, chunk - 1, chunk, 2 * chunk + 3):
+        c = Case(base, lam, space, terrain=0.2)
+        x = meshgen.uniform_values(c.n, seed=7)
+        y0 = meshgen.uniform_values(c.n, seed=8)
+        xd, y = c.dev(x), c.dev(y0)
+        try:
+            exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, c.out_access())],
+                         schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=chunk, race=race)
+        except exm.ExmError as e:
+            # tiles too large for the chunk length are refused before any launch
+            assert e.status == exm._abi.EXM_EUNSUPPORTED and "PIPELINED" in str(e), str(e)
+            return
+        if space == "P1":
+            # INC into a non-zero output: the old values pass through the staged copy
+            want, scale = c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0)
+        else:   # WRITE overwrites
+            want, scale = c.ref.mass(x), c.ref.mass_abs(x)
+        assert_close(c.host(y), want, scale, what=f"pipelined mass {space} tile={tile} S={chunk} lam={lam}")
+
+
+@pytest.mark.parametrize("space", ["DG0", "DG1"])
+def test_pipelined_dg_inc(space):
+    base = meshgen.tri_square(7)
+    c = Case(base, 19, space)
+    x = meshgen.uniform_values(c.n, seed=9)
+    y0 = meshgen.uniform_values(c.n, seed=10)
+    xd, y = c.dev(x), c.dev(y0)
+    exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
+                 schedule=exm.EXM_SCHED_PIPELINED, chunk_layers=8)
+    assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what=f"pipelined {space} INC")
+
+
+def test_pipelined_needs_aligned_pointers():
+    base = meshgen.tri_square(6)
+    c = Case(base, 9, "P1", with_oracle=False)
+    buf = c.torch.zeros(c.n + 1, dtype=c.torch.float64, device="cuda")
+    x = buf[1:]   # 8-byte aligned only
+    y = c.V.zeros()
+    with pytest.raises(exm.ExmError) as e:
+        exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(x, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
+                     schedule=exm.EXM_SCHED_PIPELINED)
+    assert e.value.status == exm._abi.EXM_EUNSUPPORTED
 
 
 def test_tiny_config_p1_rhs():
