@@ -172,6 +172,11 @@ typedef struct {
 #define EXM_RACE_ATOMIC 1     /* hardware FP64 atomic adds for DoFs another unit shares  */
 #define EXM_RACE_COLOUR 2     /* units greedily coloured (no shared vertex within one    */
                               /* colour), one launch per colour, plain read-add-write    */
+#define EXM_RACE_OWNER 3      /* owner computes (PIPELINED schedule, P1xP1): base        */
+                              /* vertices are split into tiles, each tile sums and       */
+                              /* stores only the columns it owns, and a cell on a tile   */
+                              /* boundary is computed by every tile owning one of its    */
+                              /* vertices; no atomics and a single launch                */
 
 /* Work schedule of the column loop. */
 #define EXM_SCHED_AUTO 0

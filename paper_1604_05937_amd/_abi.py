@@ -40,6 +40,7 @@ EXM_K_CUBIC_FUSED = 4
 EXM_RACE_AUTO = 0
 EXM_RACE_ATOMIC = 1
 EXM_RACE_COLOUR = 2
+EXM_RACE_OWNER = 3
 
 EXM_SCHED_AUTO = 0
 EXM_SCHED_DIRECT = 1

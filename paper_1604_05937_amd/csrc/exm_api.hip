@@ -205,7 +205,7 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.schedule = EXM_SCHED_DIRECT;
     }
     if (opts) {
-        EXM_CHECK(opts->race >= 0 && opts->race <= 2, EXM_EINVAL, "unknown race strategy %d", opts->race);
+        EXM_CHECK(opts->race >= 0 && opts->race <= EXM_RACE_OWNER, EXM_EINVAL, "unknown race strategy %d", opts->race);
         EXM_CHECK(opts->schedule >= 0 && opts->schedule <= EXM_SCHED_PIPELINED, EXM_EINVAL, "unknown schedule %d",
                   opts->schedule);
         EXM_CHECK(opts->cols_per_wave >= 0 && opts->cols_per_wave <= 16, EXM_ERANGE,
@@ -232,6 +232,16 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
+    if (d.race == EXM_RACE_OWNER) {
+        if (!continuous(P.element)) {
+            d.race = EXM_RACE_ATOMIC;   // DG columns belong to one cell: nothing to own
+        } else {
+            EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
+                      "owner-computes is implemented for the P1xP1 mass action (PIPELINED schedule)");
+            if (d.schedule != EXM_SCHED_PIPELINED) d.cols_per_wave = d.waves_per_block = d.tile_cells = 0;
+            d.schedule = EXM_SCHED_PIPELINED;
+        }
+    }
     if (d.schedule == EXM_SCHED_PIPELINED && !pipe_supported(P.kernel, P.element)) {
         d.schedule = EXM_SCHED_STAGED;
         if (d.chunk_layers > 32) d.chunk_layers = 0;
@@ -246,8 +256,13 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
                   "PIPELINED: tiles of %d cells with %d-layer chunks exceed %d cells", d.tile_cells, d.chunk_layers,
                   pipe_max_tile_cells(P.element, d.chunk_layers));
         const TilePlan* plan = nullptr;
-        int32_t s = build_tile_plan(mesh, d.tile_cells, &plan);
+        const bool owner = d.race == EXM_RACE_OWNER;
+        int32_t s = owner ? build_owner_plan(mesh, d.tile_cells, &plan) : build_tile_plan(mesh, d.tile_cells, &plan);
         if (s != EXM_OK) return s;
+        EXM_CHECK(plan->max_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+                  "PIPELINED: owner tiles of about %d cells reach %d cells with their neighbours, more than %d "
+                  "with %d-layer chunks", d.tile_cells, plan->max_cells, pipe_max_tile_cells(P.element, d.chunk_layers),
+                  d.chunk_layers);
         if (P.element == EXM_ELEMENT_P1P1)
             EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(d.chunk_layers), EXM_EUNSUPPORTED,
                       "PIPELINED: tiles of %d cells touch up to %d vertices, more than %d with %d-layer chunks",
@@ -350,6 +365,7 @@ static void fill_tile_args(const TilePlan* plan, const LoopLaunch& P, TileArgs& 
     t.xstart = P.xspace->d_starts[0].p;
     t.fstart0 = P.fspace->d_starts[0].p;
     t.fstart1 = P.fspace->d_starts[1].p;
+    t.owned = plan->owner ? plan->owned.p : nullptr;
 }
 
 static int32_t run_tiled(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
@@ -414,7 +430,8 @@ static int32_t run_staged(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_op
 static int32_t run_pipe(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
 {
     const TilePlan* plan = nullptr;
-    int32_t s = build_tile_plan(mesh, ch.tile_cells, &plan);
+    const bool owner = ch.race == EXM_RACE_OWNER;
+    int32_t s = owner ? build_owner_plan(mesh, ch.tile_cells, &plan) : build_tile_plan(mesh, ch.tile_cells, &plan);
     if (s != EXM_OK) return s;
     const size_t lds = pipe_lds_bytes(P.kernel, P.element, plan->max_verts, plan->max_cells, ch.chunk_layers);
     P.race = ch.race;
@@ -511,8 +528,10 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
         if (pipe_supported(P.kernel, P.element))
             for (int32_t tc : {32, 64, 128, 256})
                 for (int32_t S : {8, 16, 32})
-                    if (tc <= pipe_max_tile_cells(P.element, S))
+                    if (tc <= pipe_max_tile_cells(P.element, S)) {
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
+                        if (cg && r == 0) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
+                    }
         if (cg)
             for (int32_t t : {32, 64, 128, 256})
                 for (int32_t c : {0, 2, 4})
@@ -592,7 +611,7 @@ int32_t exm_autotune_load(const char* path)
         EXM_CHECK((bool)(is >> k >> e >> l >> b >> o.race >> o.schedule >> o.cols_per_wave >> o.waves_per_block >>
                          o.tile_cells >> o.chunk_layers),
                   EXM_EINVAL, "%s:%d: malformed line", path, ln);
-        EXM_CHECK((o.race == EXM_RACE_ATOMIC || o.race == EXM_RACE_COLOUR) &&
+        EXM_CHECK((o.race == EXM_RACE_ATOMIC || o.race == EXM_RACE_COLOUR || o.race == EXM_RACE_OWNER) &&
                       o.schedule >= EXM_SCHED_DIRECT && o.schedule <= EXM_SCHED_PIPELINED && o.cols_per_wave >= 0 &&
                       o.cols_per_wave <= 16 && o.waves_per_block >= 1 && o.waves_per_block <= 16 &&
                       o.tile_cells >= 0 && o.tile_cells <= 1024 &&

@@ -84,6 +84,7 @@ struct Colouring {
 // Tiles of compact groups of base cells for the LDS-staged column loop.
 struct TilePlan {
     int32_t target = 0;          // requested cells per tile
+    bool owner = false;          // owner plan: tiles own vertices, cells may repeat across tiles
     int32_t n_tiles = 0;
     int32_t max_cells = 0, max_verts = 0, max_edges = 0;
     int64_t n_tile_verts = 0;    // sum over tiles of their vertex counts
@@ -100,6 +101,8 @@ struct TilePlan {
     int32_t n_colours = 0;
     std::vector<int64_t> colour_off;   // [n_colours + 1] into colour_tiles
     DevBuf<int32_t> colour_tiles;      // tiles grouped by colour
+    DevBuf<int32_t> owned;             // owner plan: [n_tiles] vertices owned (the first of each vertex list)
+    int64_t n_cell_entries = 0;        // owner plan: cells summed over tiles (>= n_cells)
 };
 
 }  // namespace exm
@@ -133,6 +136,7 @@ namespace exm {
 
 int32_t build_colouring(const exm_mesh* m, const Colouring** out);
 int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out);
+int32_t build_owner_plan(const exm_mesh* m, int32_t target, const TilePlan** out);
 
 // Work decomposition of the column loop.
 struct LoopShape {

@@ -38,7 +38,7 @@ namespace exm {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPasses = 4;   // cells per thread: tile_cells <= kPasses * 256 * kLayers / S
+constexpr int kPasses = 2;   // cells per thread: tile_cells <= kPasses * 256 * kLayers / S
 constexpr int kLayers = 4;   // consecutive layers of one cell per thread
 constexpr int kCopy = 4;     // 16-byte copy slots per thread and array: verts * (S / 2 + 1) <= 256 * kCopy
 
@@ -102,11 +102,19 @@ struct Chunk {
 
 // P1 x P1 mass action / RHS, y += M x (INC).  LDS: Z[2], X[2], Y[2] of
 // vstride * (S + 2) doubles, then x, y (doubles) and tag, column start (ints)
-// per tile vertex.  ATOMIC: shared vertices are added atomically; otherwise
-// one launch holds one colour of tiles and every vertex is read-add-written.
-template <int S, bool ATOMIC>
+// per tile vertex.  MODE (how vertices shared between tiles are summed):
+//   kPlain  - one launch holds one colour of tiles: every vertex is
+//             read-added-written;
+//   kAtomic - shared vertices start from zero and are added atomically;
+//   kOwner  - owner plan: the tile writes only the vertices it owns (the first
+//             `owned` of its list), with plain stores, and drops the
+//             contributions of its cells to the other vertices.
+constexpr int kPlain = 0, kAtomic = 1, kOwner = 2;
+
+template <int S, int MODE>
 __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const TileArgs t)
 {
+    constexpr bool ATOMIC = MODE == kAtomic;
     using C = Chunk<S>;
     constexpr int P2 = C::P2, PP = C::PP, LS = C::LS, R = C::R, G = C::G, CPP = C::CPP;
     extern __shared__ double lds[];
@@ -115,6 +123,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
     const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
     const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int32_t no = MODE == kOwner ? t.owned[tile] : nv;   // vertices this tile writes
     const int VS = t.vstride * P2;
     double* const Zs = lds;
     double* const Xs = lds + 2 * VS;
@@ -147,17 +156,20 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     int vb[kPasses][3];
     double twoA[kPasses];
     bool has[kPasses];
+    int wmask[kPasses];   // bit q: vertex q of the cell is written by this tile
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
         const int c = tid / G + p * CPP;
         has[p] = c < nc;
         double xq[3], yq[3];
+        wmask[p] = 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int lv = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
             vb[p][q] = lv * P2 + (Txst[lv] & 1);
             xq[q] = Tx[lv];
             yq[q] = Ty[lv];
+            wmask[p] |= (lv < no ? 1 : 0) << q;
         }
         twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
     }
@@ -165,7 +177,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
 
     // this thread's copy slots: pair e = tid + 256 i of the tile's vertex slots
     int32_t sidx[kCopy], lim[kCopy];
-    bool sh[kCopy];
+    bool sh[kCopy], noy[kCopy];
 #pragma unroll
     for (int i = 0; i < kCopy; ++i) {
         const int e = tid + kThreads * i;
@@ -176,6 +188,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
         sidx[i] = xs - sv + 2 * w;                 // even: 16-byte aligned pair
         lim[i] = ok ? 2 * w - sv : 0x7fffffff;     // needed iff lim <= levels in the chunk
         sh[i] = ATOMIC && ok && vshared(Ttag[v]);
+        noy[i] = MODE == kOwner && v >= no;   // read-only vertex: no output slot
     }
     const int wave_e = tid & ~63;
 
@@ -192,12 +205,12 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
             if (g + 1 < n) {
                 copy16(z + g, Zs + b * VS + eb);
                 copy16(x + g, Xs + b * VS + eb);
-                if (!sh[i]) copy16(y + g, Ys + b * VS + eb);
+                if (!sh[i] && !noy[i]) copy16(y + g, Ys + b * VS + eb);
             } else {
                 // the array's last element: keep the read inside the array
                 Zs[b * VS + e2] = z[g];
                 Xs[b * VS + e2] = x[g];
-                if (!sh[i]) Ys[b * VS + e2] = y[g];
+                if (!sh[i] && !noy[i]) Ys[b * VS + e2] = y[g];
             }
             if (sh[i]) {   // shared vertices start from zero and are added atomically
                 Ys[b * VS + e2] = 0.0;
@@ -218,7 +231,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
         if (k > 0) {
             const double* Yp = Ys + (b ^ 1) * VS;
             const int l0p = l0 - S;
-            for (int it = tid; it < (nv << LS); it += kThreads) {
+            for (int it = tid; it < (no << LS); it += kThreads) {
                 const int v = it >> LS, jj = it & (S - 1);
                 const int32_t xs = Txst[v];
                 const double s = Yp[v * P2 + (xs & 1) + jj];
@@ -230,7 +243,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
             }
         }
         double* const Yb = Ys + b * VS;
-        for (int v = tid; v < nv; v += kThreads) {
+        for (int v = tid; v < no; v += kThreads) {
             const int o = v * P2 + (Txst[v] & 1);
             if (k > 0) Yb[o] += Ys[(b ^ 1) * VS + o + S];
             if (nl == S && l0 + S < lam) Yb[o + S] = 0.0;   // level l0 + S belongs to chunk k+1
@@ -269,14 +282,15 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
                 p1_mass(twoA[p], h, xc, xn, yb, yt);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    lds_add(Yb + o[q] + r, acc[q] + yb[q]);
+                    if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(Yb + o[q] + r, acc[q] + yb[q]);
                     acc[q] = yt[q];
                     zc[q] = zn[q];
                     xc[q] = xn[q];
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 3; ++q) lds_add(Yb + o[q] + r, acc[q]);
+            for (int q = 0; q < 3; ++q)
+                if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(Yb + o[q] + r, acc[q]);
         }
     }
     // write back the last chunk, its top level included
@@ -285,7 +299,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
         const int k = nch - 1;
         const double* Yl = Ys + (k & 1) * VS;
         const int l0 = k * S, nl = lam - l0;
-        for (int it = tid; it < (nv << LS); it += kThreads) {
+        for (int it = tid; it < (no << LS); it += kThreads) {
             const int v = it >> LS, jj = it & (S - 1);
             if (jj >= nl) continue;
             const int32_t xs = Txst[v];
@@ -296,7 +310,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
             else
                 y[g] = s;
         }
-        for (int v = tid; v < nv; v += kThreads) {
+        for (int v = tid; v < no; v += kThreads) {
             const int32_t xs = Txst[v];
             const double s = Yl[v * P2 + (xs & 1) + nl];
             const int64_t g = (int64_t)xs + lam;
@@ -308,21 +322,20 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     }
 }
 
-// DG0 x DG0 (NDOF = 1) and DG1 x DG1 (NDOF = 6) mass action / RHS.  A
-// cell's DoFs form one contiguous column of NDOF * lambda values, so per
-// chunk the tile's cells copy NDOF * S values each and its vertices S + 1
-// levels of z.  Outputs belong to one cell: each thread keeps the results of
-// its (cell, layer) pairs in registers and stores them to HBM while the next
-// chunk computes, after that chunk's copies are issued.  LDS: Z[2] of
-// vstride * (S + 2), F[2] of cstride * (NDOF * S + 2) doubles, then x, y
-// (doubles) per tile vertex, column start per vertex and per cell (ints).
+// DG0 x DG0 (NDOF = 1) and DG1 x DG1 (NDOF = 6) mass action / RHS.  Only z
+// is shared between the cells of a tile, so only z goes through LDS (S + 1
+// levels per tile vertex and chunk, copied one chunk ahead).  A cell's DoFs
+// form one contiguous column of NDOF * lambda values that no other cell
+// touches: each thread takes one layer of a few cells, loads that layer's
+// field values into registers one chunk ahead (coalesced along the column),
+// and stores its results while the next chunk computes.  LDS: Z[2] of
+// vstride * (S + 2) doubles, then x, y (doubles) and the column start (int)
+// per tile vertex.
 template <int NDOF, int S, int NP>
-__global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const TileArgs t, int32_t cstride)
+__global__ void __launch_bounds__(kThreads, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
 {
     using C = Chunk<S>;
     constexpr int P2 = C::P2, PP = C::PP, LS = C::LS;
-    constexpr int QF = NDOF * S + 2;      // doubles per cell slot (even)
-    constexpr int QP = QF / 2;
     constexpr int CPP = kThreads >> LS;   // one layer per thread
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -331,19 +344,15 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
     const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
     const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
     const int VS = t.vstride * P2;
-    const int FS = cstride * QF;
     double* const Zs = lds;
-    double* const Fs = lds + 2 * VS;
-    double* const Tx = Fs + 2 * FS;
+    double* const Tx = Zs + 2 * VS;
     double* const Ty = Tx + t.vstride;
     int32_t* const Txst = (int32_t*)(Ty + t.vstride);
-    int32_t* const Tcst = Txst + t.vstride;
     const int64_t n = a.xn;
     const double* const z = a.X + 2 * n;
     const double* const f = a.in0;
     double* const out = a.out0;
     const int lam = a.n_layers;
-    const int64_t nf = a.fn;
 
     for (int v = tid; v < nv; v += kThreads) {
         const int32_t xs = t.xstart[vid(t.verts[vb0 + v])];
@@ -351,11 +360,10 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
         Tx[v] = a.X[xs];
         Ty[v] = a.X[n + xs];
     }
-    for (int c = tid; c < nc; c += kThreads) Tcst[c] = a.fmap[(int64_t)t.cells[cb + c] * NDOF];
     lds_barrier();
 
     const int j = tid & (S - 1);
-    int vb[NP][3], fb[NP];
+    int vb[NP][3];
     int32_t d0[NP];
     double twoA[NP];
     bool has[NP];
@@ -372,9 +380,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
             yq[q] = Ty[lv];
         }
         twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
-        const int32_t cs = has[p] ? Tcst[c] : 0;
-        d0[p] = cs;
-        fb[p] = (has[p] ? c : 0) * QF + (cs & 1);
+        d0[p] = has[p] ? a.fmap[(int64_t)t.cells[cb + c] * NDOF] : 0;
     }
     const int npass = (nc + CPP - 1) / CPP;
     const int wave_e = tid & ~63;
@@ -383,7 +389,6 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
         const int l0 = k * S;
         const int nl = min(S, lam - l0);
         const int b = k & 1;
-        // z: vertex slots, levels l0 .. l0 + nl
         for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
             const int e = e0 + tid;
             const int v = e / PP, w = e - (e / PP) * PP;
@@ -397,24 +402,31 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
             else
                 Zs[b * VS + 2 * e] = z[g];
         }
-        // field: cell slots, DoFs of layers l0 .. l0 + nl - 1
-        for (int e0 = 0; e0 < nc * QP; e0 += kThreads) {
-            const int e = e0 + tid;
-            const int c = e / QP, w = e - (e / QP) * QP;
-            if (c >= nc) continue;
-            const int32_t cs = Tcst[c];
-            const int sc = cs & 1;
-            if (2 * w - sc >= NDOF * nl) continue;
-            const int64_t g = (int64_t)cs - sc + (int64_t)l0 * NDOF + 2 * w;
-            if (g + 1 < nf)
-                copy16(f + g, Fs + b * FS + 2 * (e0 + wave_e));
-            else
-                Fs[b * FS + 2 * e] = f[g];
+    };
+    auto load_field = [&](int k, double (&fv)[NP][NDOF]) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass) break;
+            if (!has[p] || j >= nl) continue;
+            const double* src = f + (int64_t)d0[p] + (int64_t)(l0 + j) * NDOF;
+            if constexpr (NDOF % 2 == 0) {
+                // even column starts and an even stride: 16-byte aligned pairs
+#pragma unroll
+                for (int q = 0; q < NDOF / 2; ++q) {
+                    const double2 v2 = reinterpret_cast<const double2*>(src)[q];
+                    fv[p][2 * q] = v2.x;
+                    fv[p][2 * q + 1] = v2.y;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < NDOF; ++q) fv[p][q] = src[q];
+            }
         }
     };
 
-    // results of the previous chunk, stored after the next chunk's copies are issued
-    double res[NP][NDOF];
+    double fcur[NP][NDOF], fnext[NP][NDOF], res[NP][NDOF];
     int prev_l0 = -1, prev_nl = 0;
     auto store_results = [&]() {
         if (prev_l0 < 0) return;
@@ -422,29 +434,38 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
         for (int p = 0; p < NP; ++p) {
             if (p >= npass) break;
             if (!has[p] || j >= prev_nl) continue;
-            const int64_t d = (int64_t)d0[p] + (int64_t)(prev_l0 + j) * NDOF;
+            double* dst = out + (int64_t)d0[p] + (int64_t)(prev_l0 + j) * NDOF;
+            if (a.write) {
+                if constexpr (NDOF % 2 == 0) {
 #pragma unroll
-            for (int k = 0; k < NDOF; ++k) {
-                if (a.write)
-                    out[d + k] = res[p][k];
-                else
-                    out[d + k] += res[p][k];
+                    for (int q = 0; q < NDOF / 2; ++q)
+                        reinterpret_cast<double2*>(dst)[q] = make_double2(res[p][2 * q], res[p][2 * q + 1]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NDOF; ++q) dst[q] = res[p][q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < NDOF; ++q) dst[q] += res[p][q];
             }
         }
     };
 
     const int nch = (lam + S - 1) / S;
     issue_copies(0);
+    load_field(0, fcur);
     for (int k = 0; k < nch; ++k) {
         const int b = k & 1;
         const int l0 = k * S;
         const int nl = min(S, lam - l0);
         wait_copies();
         lds_barrier();
-        if (k + 1 < nch) issue_copies(k + 1);
+        if (k + 1 < nch) {
+            issue_copies(k + 1);
+            load_field(k + 1, fnext);
+        }
         store_results();
         const double* const Zb = Zs + b * VS;
-        const double* const Fb = Fs + b * FS;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             if (p >= npass) break;
@@ -452,15 +473,14 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
             double h[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) h[q] = Zb[vb[p][q] + j + 1] - Zb[vb[p][q] + j];
-            const int o = fb[p] + NDOF * j;
             if constexpr (NDOF == 1) {
-                res[p][0] = dg0_mass(twoA[p], h, Fb[o]);
+                res[p][0] = dg0_mass(twoA[p], h, fcur[p][0]);
             } else {
                 double xb[3], xt[3], yb[3], yt[3];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    xb[q] = Fb[o + 2 * q];
-                    xt[q] = Fb[o + 2 * q + 1];
+                    xb[q] = fcur[p][2 * q];
+                    xt[q] = fcur[p][2 * q + 1];
                 }
                 p1_mass(twoA[p], h, xb, xt, yb, yt);
 #pragma unroll
@@ -470,6 +490,10 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
                 }
             }
         }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int q = 0; q < NDOF; ++q) fcur[p][q] = fnext[p][q];
         prev_l0 = l0;
         prev_nl = nl;
     }
@@ -478,17 +502,13 @@ __global__ void __launch_bounds__(kThreads) k_pipe_dg(const ColArgs a, const Til
 
 // ---------------------------------------------------------------------------
 
-static int dg_ndof(int32_t element) { return element == EXM_ELEMENT_DG1DG1 ? 6 : 1; }
-
 size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t cstride, int32_t S)
 {
     if (kernel != EXM_K_MASS) return 0;
     if (element == EXM_ELEMENT_P1P1)
         return sizeof(double) * (6 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + 2 * sizeof(int32_t) * vstride;
     if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1)
-        return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)cstride * (dg_ndof(element) * S + 2) +
-                                 2 * (size_t)vstride) +
-               sizeof(int32_t) * ((size_t)vstride + cstride);
+        return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + sizeof(int32_t) * vstride;
     return 0;
 }
 
@@ -500,7 +520,7 @@ bool pipe_supported(int32_t kernel, int32_t element)
 
 int32_t pipe_max_tile_cells(int32_t element, int32_t S)
 {
-    if (element == EXM_ELEMENT_DG0DG0) return 4 * kThreads / S;
+    if (element == EXM_ELEMENT_DG0DG0) return 2 * kThreads / S;
     if (element == EXM_ELEMENT_DG1DG1) return 2 * kThreads / S;
     return kPasses * kThreads * kLayers / S;
 }
@@ -508,12 +528,15 @@ int32_t pipe_max_tile_cells(int32_t element, int32_t S)
 int32_t pipe_max_tile_verts(int32_t S) { return kThreads * kCopy / (S / 2 + 1); }
 
 template <int S>
-static void launch_pipe_s(bool atomic, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
 {
-    if (atomic)
-        hipLaunchKernelGGL((k_pipe_p1<S, true>), dim3((unsigned)t.tile_count), dim3(kThreads), lds, s, a, t);
+    const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    if (race == EXM_RACE_OWNER)
+        hipLaunchKernelGGL((k_pipe_p1<S, kOwner>), grid, block, lds, s, a, t);
+    else if (race == EXM_RACE_COLOUR)
+        hipLaunchKernelGGL((k_pipe_p1<S, kPlain>), grid, block, lds, s, a, t);
     else
-        hipLaunchKernelGGL((k_pipe_p1<S, false>), dim3((unsigned)t.tile_count), dim3(kThreads), lds, s, a, t);
+        hipLaunchKernelGGL((k_pipe_p1<S, kAtomic>), grid, block, lds, s, a, t);
 }
 
 template <int S>
@@ -521,10 +544,11 @@ static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t,
                            hipStream_t s)
 {
     const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    (void)cstride;
     if (element == EXM_ELEMENT_DG0DG0)
-        hipLaunchKernelGGL((k_pipe_dg<1, S, 4>), grid, block, lds, s, a, t, cstride);
+        hipLaunchKernelGGL((k_pipe_dg<1, S, 2>), grid, block, lds, s, a, t);
     else
-        hipLaunchKernelGGL((k_pipe_dg<6, S, 2>), grid, block, lds, s, a, t, cstride);
+        hipLaunchKernelGGL((k_pipe_dg<6, S, 2>), grid, block, lds, s, a, t);
 }
 
 int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t cstride, int32_t S, size_t lds,
@@ -545,11 +569,11 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
         EXM_TRY_HIP(hipGetLastError());
         return EXM_OK;
     }
-    const bool atomic = P.race != EXM_RACE_COLOUR;
+    EXM_CHECK(P.race != EXM_RACE_OWNER || t.owned != nullptr, EXM_EINVAL, "owner-computes needs an owner plan");
     switch (S) {
-    case 8: launch_pipe_s<8>(atomic, a, t, lds, s); break;
-    case 16: launch_pipe_s<16>(atomic, a, t, lds, s); break;
-    case 32: launch_pipe_s<32>(atomic, a, t, lds, s); break;
+    case 8: launch_pipe_s<8>(P.race, a, t, lds, s); break;
+    case 16: launch_pipe_s<16>(P.race, a, t, lds, s); break;
+    case 32: launch_pipe_s<32>(P.race, a, t, lds, s); break;
     default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 16 or 32", S);
     }
     EXM_TRY_HIP(hipGetLastError());

@@ -42,7 +42,7 @@ int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out)
 {
     std::lock_guard<std::mutex> lock(m->mu);
     for (auto& p : m->plans)
-        if (p->target == target) {
+        if (p->target == target && !p->owner) {
             *out = p.get();
             return EXM_OK;
         }
@@ -194,6 +194,131 @@ int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out)
     }
     if ((s = plan->colour_tiles.upload(tiles_by_colour.data(), tiles_by_colour.size())) != EXM_OK) return s;
     plan->has_edges = edges;
+    m->plans.push_back(std::move(plan));
+    *out = m->plans.back().get();
+    return EXM_OK;
+}
+
+// Owner plan: the base vertices are split into compact tiles of about
+// target / 2 vertices (a triangulation has about half as many vertices as
+// cells), grown breadth-first over the vertex graph from the lowest-numbered
+// unassigned vertex.  A tile owns its vertices: it is the only one that sums
+// and writes their columns.  Its cell list holds every cell with an owned
+// vertex, so a cell on a tile boundary appears in each tile that owns one of
+// its vertices and is computed there again; its vertex list holds the owned
+// vertices first, then the other vertices of those cells (read, never
+// written).
+int32_t build_owner_plan(const exm_mesh* m, int32_t target, const TilePlan** out)
+{
+    std::lock_guard<std::mutex> lock(m->mu);
+    for (auto& p : m->plans)
+        if (p->target == target && p->owner) {
+            *out = p.get();
+            return EXM_OK;
+        }
+    const int32_t nv = m->n[0], nc = m->n[2];
+    const int32_t* cv = m->h_cell_vertex.data();
+    Csr vc = vertex_cells(m);
+    const int32_t tv = std::max(1, target / 2);
+
+    // 1. grow vertex tiles over the vertex graph (vertices sharing a cell)
+    std::vector<int32_t> tile_of(nv, -1), vorder;
+    vorder.reserve(nv);
+    std::vector<int64_t> own_off(1, 0);
+    std::deque<int32_t> q;
+    int32_t nt = 0;
+    for (int32_t s0 = 0; s0 < nv; ++s0) {
+        if (tile_of[s0] >= 0) continue;
+        int32_t cnt = 0;
+        q.clear();
+        q.push_back(s0);
+        tile_of[s0] = nt;
+        vorder.push_back(s0);
+        ++cnt;
+        while (!q.empty() && cnt < tv) {
+            const int32_t v = q.front();
+            q.pop_front();
+            for (int64_t jx = vc.start[v]; jx < vc.start[v + 1] && cnt < tv; ++jx) {
+                const int32_t c = vc.items[jx];
+                for (int a = 0; a < 3 && cnt < tv; ++a) {
+                    const int32_t w = cv[(int64_t)c * 3 + a];
+                    if (tile_of[w] >= 0) continue;
+                    tile_of[w] = nt;
+                    vorder.push_back(w);
+                    q.push_back(w);
+                    ++cnt;
+                }
+            }
+        }
+        own_off.push_back((int64_t)vorder.size());
+        ++nt;
+    }
+
+    // 2. per tile: cells touching an owned vertex, vertex list (owned first)
+    auto plan = std::make_unique<TilePlan>();
+    plan->target = target;
+    plan->owner = true;
+    plan->n_tiles = nt;
+    std::vector<int32_t> cstamp(nc, -1), vstamp(nv, -1), local(nv, 0);
+    std::vector<int32_t> cells, verts, owned(nt);
+    std::vector<int64_t> coff(1, 0), voff(1, 0);
+    std::vector<uint16_t> lcv;
+    int32_t maxc = 0, maxv = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+        int32_t nvl = 0;
+        for (int64_t i = own_off[t]; i < own_off[t + 1]; ++i) {
+            const int32_t v = vorder[i];
+            vstamp[v] = t;
+            local[v] = nvl++;
+            verts.push_back(v);
+        }
+        owned[t] = nvl;
+        const int64_t c0 = (int64_t)cells.size();
+        for (int64_t i = own_off[t]; i < own_off[t + 1]; ++i) {
+            const int32_t v = vorder[i];
+            for (int64_t jx = vc.start[v]; jx < vc.start[v + 1]; ++jx) {
+                const int32_t c = vc.items[jx];
+                if (cstamp[c] == t) continue;
+                cstamp[c] = t;
+                cells.push_back(c);
+                for (int a = 0; a < 3; ++a) {
+                    const int32_t w = cv[(int64_t)c * 3 + a];
+                    if (vstamp[w] != t) {
+                        vstamp[w] = t;
+                        local[w] = nvl++;
+                        verts.push_back(w);
+                    }
+                    lcv.push_back((uint16_t)local[w]);
+                }
+            }
+        }
+        EXM_CHECK(nvl < 65535, EXM_ERANGE, "tile too large");
+        maxc = std::max<int32_t>(maxc, (int32_t)((int64_t)cells.size() - c0));
+        maxv = std::max(maxv, nvl);
+        coff.push_back((int64_t)cells.size());
+        voff.push_back((int64_t)verts.size());
+    }
+    plan->max_cells = maxc;
+    plan->max_verts = maxv;
+    plan->max_edges = 0;
+    plan->n_tile_verts = (int64_t)verts.size();
+    plan->n_shared_verts = 0;
+    plan->n_cell_entries = (int64_t)cells.size();
+    plan->n_colours = 1;
+    plan->colour_off = {0, nt};
+
+    EXM_CHECK(coff.back() < INT32_MAX && voff.back() < INT32_MAX, EXM_EOVERFLOW, "plan too large");
+    std::vector<int32_t> co(coff.begin(), coff.end()), vo(voff.begin(), voff.end()), all(nt);
+    for (int32_t t = 0; t < nt; ++t) all[t] = t;
+    int32_t s;
+    if ((s = plan->cell_off.upload(co.data(), co.size())) != EXM_OK) return s;
+    if ((s = plan->cells.upload(cells.data(), cells.size())) != EXM_OK) return s;
+    if ((s = plan->vert_off.upload(vo.data(), vo.size())) != EXM_OK) return s;
+    if ((s = plan->verts.upload(verts.data(), verts.size())) != EXM_OK) return s;
+    if ((s = plan->local_cv.upload(lcv.data(), lcv.size())) != EXM_OK) return s;
+    if ((s = plan->owned.upload(owned.data(), owned.size())) != EXM_OK) return s;
+    if ((s = plan->colour_tiles.upload(all.data(), all.size())) != EXM_OK) return s;
+    plan->has_edges = false;
     m->plans.push_back(std::move(plan));
     *out = m->plans.back().get();
     return EXM_OK;

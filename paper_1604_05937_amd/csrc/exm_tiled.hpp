@@ -43,6 +43,7 @@ struct TileArgs {
     const int32_t* __restrict__ xstart;    // coordinate column start of every base vertex
     const int32_t* __restrict__ fstart0;   // field column start of every base vertex
     const int32_t* __restrict__ fstart1;   // field column start of every base edge
+    const int32_t* __restrict__ owned;     // owner plan: vertices each tile owns (else null)
 };
 
 ColArgs col_args(const LoopLaunch& P);

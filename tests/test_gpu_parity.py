@@ -106,7 +106,7 @@ def test_mass_staged_shapes(space, tile, chunk, race):
 @pytest.mark.parametrize("space", ["P1", "DG0", "DG1"])
 @pytest.mark.parametrize("tile", [8, 29, 64, 128])
 @pytest.mark.parametrize("chunk", [8, 16, 32])
-@pytest.mark.parametrize("race", RACES)
+@pytest.mark.parametrize("race", RACES + [exm.EXM_RACE_OWNER])
 def test_mass_pipelined_shapes(space, tile, chunk, race):
     say(f"pipelined shape {space} tile={tile} chunk={chunk} race={race}")
     base = meshgen.tri_square(10, order="random" if tile == 29 else "rcm")
@@ -140,6 +140,28 @@ def test_pipelined_dg_inc(space):
     exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
                  schedule=exm.EXM_SCHED_PIPELINED, chunk_layers=8)
     assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what=f"pipelined {space} INC")
+
+
+@pytest.mark.parametrize("n,lam", SHAPES)
+def test_owner_computes_matches_oracle(n, lam):
+    say(f"owner computes n={n} lam={lam}")
+    c = Case(meshgen.tri_square(n, order="random"), lam, "P1", terrain=0.3)
+    x = meshgen.uniform_values(c.n, seed=11)
+    got = c.mass(x, race=exm.EXM_RACE_OWNER)
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what="owner-computes P1")
+    cfg = exm.par_loop_config(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(c.dev(x), c.V, exm.EXM_READ),
+                                                                 (c.V.zeros(), c.V, exm.EXM_INC)],
+                              race=exm.EXM_RACE_OWNER)
+    assert cfg["schedule"] == exm.EXM_SCHED_PIPELINED and cfg["race"] == exm.EXM_RACE_OWNER
+
+
+def test_owner_computes_unsupported_on_p2():
+    c = Case(meshgen.tri_square(4), 3, "P2", with_oracle=False)
+    x = c.dev(meshgen.uniform_values(c.n, seed=1))
+    with pytest.raises(exm.ExmError) as e:
+        exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(x, c.V, exm.EXM_READ), (c.V.zeros(), c.V, exm.EXM_INC)],
+                     race=exm.EXM_RACE_OWNER)
+    assert e.value.status == exm._abi.EXM_EUNSUPPORTED
 
 
 def test_pipelined_needs_aligned_pointers():
