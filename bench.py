@@ -63,9 +63,10 @@ def stream_triad(torch, exm):
     return best
 
 
-def read_traffic(kernel_tag: str, src_hash: str):
+def read_traffic(kernel_tag: str, src_hash: str, launch: dict):
     """HBM bytes per launch from the rocprofv3 counter summary of this kernel
-    build (profiles/<tag>.md, a line 'traffic: {json}'), else None."""
+    build and launch configuration (profiles/<tag>.md, a line
+    'traffic: {json}'), else None."""
     p = os.path.join(ROOT, "profiles", f"{kernel_tag}.md")
     if not os.path.exists(p):
         return None
@@ -73,8 +74,8 @@ def read_traffic(kernel_tag: str, src_hash: str):
     if not m:
         return None
     d = json.loads(m.group(1))
-    if d.get("source_hash") != src_hash:
-        return None   # counters were taken on another kernel build
+    if d.get("source_hash") != src_hash or d.get("launch") != launch:
+        return None   # counters were taken on another kernel build or launch configuration
     return d.get("bytes_per_launch")
 
 
@@ -121,7 +122,14 @@ def main():
                     help="launch only this kernel, warmup + steps times, and print nothing (for rocprofv3)")
     ap.add_argument("--config", default=None,
                     help="with --only: the launch configuration as JSON (exm_loop_opts fields) instead of autotuning")
+    ap.add_argument("--launch", default=None,
+                    help='launch configurations as JSON {"p1": {...}, "dg0": {...}} instead of autotuning '
+                         "(the figures of a previous run, for profiling the timed region alone)")
     ap.add_argument("--cpu-seconds", type=float, default=16.0)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line: layer sweep (P1 and DG0 RHS, autotuned) on the fixed "
+                         "512x512 base and at a constant ~52.4M prisms, plus RCM against a random base ordering; "
+                         "one JSON line per point")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -136,6 +144,9 @@ def main():
 
     exm.load_library()
     torch.cuda.init()
+    if args.sweep:
+        sweep(torch, exm)
+        return
     if args.only == "triad":
         # calibration kernel for the HBM counters: reads 16 n bytes, writes 8 n
         n = 1 << 26
@@ -175,14 +186,19 @@ def main():
         log(f"done: {name} {cfg}, {(by1 if name == 'P1' else by0)['algorithmic']} algorithmic bytes per launch")
         return
 
-    # autotuned launch configurations (the library keeps them for later calls)
-    t0 = time.time()
-    cfg1 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "P1", f1, b1))
-    cfg0 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "DG0", f0, b0))
-    log(f"autotune {time.time() - t0:.1f}s: P1 {cfg1}  DG0 {cfg0}")
+    if args.launch:
+        given = json.loads(args.launch)
+        cfg1, cfg0 = given["p1"], given["dg0"]
+        log(f"given launch configurations: P1 {cfg1}  DG0 {cfg0}")
+    else:
+        # autotuned launch configurations (the library keeps them for later calls)
+        t0 = time.time()
+        cfg1 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "P1", f1, b1))
+        cfg0 = exm.autotune(exm.EXM_K_MASS, work.mesh, work.X, work.Vx, W.mass_args(work, "DG0", f0, b0))
+        log(f"autotune {time.time() - t0:.1f}s: P1 {cfg1}  DG0 {cfg0}")
 
-    k1 = lambda: W.run_mass(work, "P1", f1, b1)
-    k2 = lambda: W.run_mass(work, "DG0", f0, b0)
+    k1 = lambda: W.run_mass(work, "P1", f1, b1, **cfg1)
+    k2 = lambda: W.run_mass(work, "DG0", f0, b0, **cfg0)
 
     # ---- timed region: K steps of (P1 assembly, DG0 assembly) ----
     s = torch.cuda.current_stream()
@@ -212,10 +228,10 @@ def main():
 
     k1_gbs = by1["algorithmic"] / (np.mean(t1) * 1e-3) / 1e9
     k2_gbs = by0["algorithmic"] / (np.mean(t2) * 1e-3) / 1e9
-    dominant = ("p1_rhs_512x512x100", by1, t1, k1_gbs) if np.mean(t1) >= np.mean(t2) else \
-               ("dg0_rhs_512x512x100", by0, t2, k2_gbs)
+    dominant = ("p1_rhs_512x512x100", by1, t1, k1_gbs, cfg1) if np.mean(t1) >= np.mean(t2) else \
+               ("dg0_rhs_512x512x100", by0, t2, k2_gbs, cfg0)
     src_hash = W.source_hash()
-    traffic = read_traffic(dominant[0], src_hash)
+    traffic = read_traffic(dominant[0], src_hash, dominant[4])
     roofline = {
         "kernel": dominant[0],
         "bound": "hbm",
@@ -291,6 +307,41 @@ def main():
             "gpu_speedup": round(cpu_step_s / (step_ms * 1e-3), 1),
         }
     print(json.dumps(result), flush=True)
+
+
+def sweep(torch, exm):
+    """Throughput against the layer count (Section 4.2: the base-map load is
+    amortised over the column) and against the base ordering."""
+    import numpy as np
+
+    from paper_1604_05937_amd import meshgen, workloads as W
+
+    def point(n, lam, order):
+        t0 = time.time()
+        e = W.extruded(n, lam, order=order)
+        res = {"base": f"{n}x{n}", "n_layers": lam, "order": order, "n_prisms": e.n_prisms}
+        for name in ("P1", "DG0"):
+            V = e.space(name)
+            x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
+            y = V.zeros()
+            cfg = exm.autotune(exm.EXM_K_MASS, e.mesh, e.X, e.Vx, W.mass_args(e, name, x, y))
+            t, _ = timed(torch, lambda: W.run_mass(e, name, x, y, **cfg), 10)
+            b = W.mass_bytes(e, name)
+            res[name.lower()] = {"ms": round(t, 4), "gbs": round(b["algorithmic"] / t / 1e6, 1),
+                                 "dofs_per_s": round(V.n_dofs / t * 1e3), "launch": cfg}
+            del x, y
+        del e
+        torch.cuda.empty_cache()
+        res["setup_s"] = round(time.time() - t0, 1)
+        print(json.dumps(res), flush=True)
+
+    for lam in (1, 2, 5, 10, 20, 50, 100, 200):
+        point(512, lam, "rcm")
+    # constant work: about 52.4M prisms, the base shrinking as the layers grow
+    for lam in (5, 10, 20, 50, 200):
+        point(int(round(512 * np.sqrt(100.0 / lam))), lam, "rcm")
+    for lam in (1, 10, 100):
+        point(512, lam, "random")
 
 
 def secondary(torch, exm, W, meshgen):

@@ -201,6 +201,12 @@ typedef struct {
                               /* loads, the previous chunk's stores and the current chunk's   */
                               /* element kernels overlap.  P1xP1 mass action; other kernels   */
                               /* fall back to STAGED.  Field pointers must be 16-byte aligned */
+#define EXM_SCHED_CHUNKED 5   /* P1xP1 mass action: one workgroup per (tile, chunk of        */
+                              /* chunk_layers layers); consecutive chunks overlap by one     */
+                              /* layer so that each writes whole levels, the workgroups are  */
+                              /* independent and the grid runs chunk by chunk.  Same race    */
+                              /* strategies and alignment as PIPELINED; other kernels run    */
+                              /* PIPELINED                                                   */
 
 typedef struct {
     int32_t race;              /* EXM_RACE_*                                             */
@@ -211,7 +217,8 @@ typedef struct {
     int32_t waves_per_block;   /* DIRECT: 1..4; TILED: 1..8; STAGED, PIPELINED: 4 (0 = choose) */
     int32_t tile_cells;        /* TILED, STAGED, PIPELINED: 8..1024 target cells per tile */
                                /* (0 = choose)                                           */
-    int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64; PIPELINED: 8, 16 or 32 layers */
+    int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64; PIPELINED, CHUNKED: 8, 16 or  */
+                               /* 32 layers                                              */
                                /* per chunk (0 = choose)                                 */
 } exm_loop_opts;
 

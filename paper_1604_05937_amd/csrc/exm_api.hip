@@ -206,7 +206,7 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (opts) {
         EXM_CHECK(opts->race >= 0 && opts->race <= EXM_RACE_OWNER, EXM_EINVAL, "unknown race strategy %d", opts->race);
-        EXM_CHECK(opts->schedule >= 0 && opts->schedule <= EXM_SCHED_PIPELINED, EXM_EINVAL, "unknown schedule %d",
+        EXM_CHECK(opts->schedule >= 0 && opts->schedule <= EXM_SCHED_CHUNKED, EXM_EINVAL, "unknown schedule %d",
                   opts->schedule);
         EXM_CHECK(opts->cols_per_wave >= 0 && opts->cols_per_wave <= 16, EXM_ERANGE,
                   "cols_per_wave = %d outside [0, 16]", opts->cols_per_wave);
@@ -214,9 +214,10 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
                   "waves_per_block = %d outside [0, 16]", opts->waves_per_block);
         EXM_CHECK(opts->tile_cells == 0 || (opts->tile_cells >= 8 && opts->tile_cells <= 1024), EXM_ERANGE,
                   "tile_cells = %d outside [8, 1024]", opts->tile_cells);
-        EXM_CHECK(opts->chunk_layers == 0 || opts->chunk_layers == 8 || opts->chunk_layers == 16 ||
-                      opts->chunk_layers == 32 || opts->chunk_layers == 64,
-                  EXM_ERANGE, "chunk_layers = %d: use 8, 16, 32 or 64 (0 = choose)", opts->chunk_layers);
+        EXM_CHECK(opts->chunk_layers == 0 || opts->chunk_layers == 8 || opts->chunk_layers == 12 ||
+                      opts->chunk_layers == 16 || opts->chunk_layers == 24 || opts->chunk_layers == 32 ||
+                      opts->chunk_layers == 64,
+                  EXM_ERANGE, "chunk_layers = %d: use 8, 12, 16, 24, 32 or 64 (0 = choose)", opts->chunk_layers);
         if (opts->race) d.race = opts->race;
         if (opts->schedule) {
             if (opts->schedule != d.schedule) {
@@ -238,9 +239,34 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         } else {
             EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
                       "owner-computes is implemented for the P1xP1 mass action (PIPELINED schedule)");
-            if (d.schedule != EXM_SCHED_PIPELINED) d.cols_per_wave = d.waves_per_block = d.tile_cells = 0;
-            d.schedule = EXM_SCHED_PIPELINED;
+            if (d.schedule != EXM_SCHED_PIPELINED && d.schedule != EXM_SCHED_CHUNKED) {
+                d.cols_per_wave = d.waves_per_block = d.tile_cells = 0;
+                d.schedule = EXM_SCHED_PIPELINED;
+            }
         }
+    }
+    if (d.schedule == EXM_SCHED_CHUNKED && !(P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1)) {
+        d.schedule = EXM_SCHED_PIPELINED;
+        d.tile_cells = 0;
+    }
+    if (d.schedule == EXM_SCHED_CHUNKED) {
+        d.waves_per_block = 4;
+        d.cols_per_wave = 0;
+        if (!d.chunk_layers) d.chunk_layers = 16;
+        EXM_CHECK(d.chunk_layers == 8 || d.chunk_layers == 16 || d.chunk_layers == 32, EXM_ERANGE,
+                  "CHUNKED: chunk_layers = %d, use 8, 16 or 32", d.chunk_layers);
+        if (!d.tile_cells) d.tile_cells = 64;
+        const TilePlan* plan = nullptr;
+        const bool owner = d.race == EXM_RACE_OWNER;
+        int32_t s = owner ? build_owner_plan(mesh, d.tile_cells, &plan) : build_tile_plan(mesh, d.tile_cells, &plan);
+        if (s != EXM_OK) return s;
+        EXM_CHECK(plan->max_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+                  "CHUNKED: tiles of about %d cells reach %d cells, more than %d with %d-layer chunks", d.tile_cells,
+                  plan->max_cells, pipe_max_tile_cells(P.element, d.chunk_layers), d.chunk_layers);
+        EXM_CHECK(chunk_lds_bytes(plan->max_verts, d.chunk_layers) <= kLdsLimit, EXM_EUNSUPPORTED,
+                  "CHUNKED: tiles of %d cells with %d-layer chunks do not fit in LDS", d.tile_cells, d.chunk_layers);
+        ch = d;
+        return EXM_OK;
     }
     if (d.schedule == EXM_SCHED_PIPELINED && !pipe_supported(P.kernel, P.element)) {
         d.schedule = EXM_SCHED_STAGED;
@@ -250,7 +276,9 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.waves_per_block = 4;
         d.cols_per_wave = 0;
         if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 ? 16 : 8;
-        EXM_CHECK(d.chunk_layers <= 32, EXM_ERANGE, "PIPELINED: chunk_layers = %d, use 8, 16 or 32", d.chunk_layers);
+        EXM_CHECK(pipe_chunk_ok(P.element, d.chunk_layers), EXM_ERANGE,
+                  "PIPELINED: chunk_layers = %d, use 8, 12, 16, 24 or 32 on P1xP1 and 8, 16 or 32 on DG spaces",
+                  d.chunk_layers);
         if (!d.tile_cells) d.tile_cells = std::min(64, pipe_max_tile_cells(P.element, d.chunk_layers));
         EXM_CHECK(d.tile_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
                   "PIPELINED: tiles of %d cells with %d-layer chunks exceed %d cells", d.tile_cells, d.chunk_layers,
@@ -273,6 +301,9 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         ch = d;
         return EXM_OK;
     }
+    if (d.schedule == EXM_SCHED_STAGED)
+        EXM_CHECK(d.chunk_layers % 8 == 0 && (d.chunk_layers & (d.chunk_layers - 1)) == 0, EXM_ERANGE,
+                  "STAGED: chunk_layers = %d, use 8, 16, 32 or 64", d.chunk_layers);
     if (d.schedule == EXM_SCHED_STAGED && !staged_supported(P.kernel, P.element)) {
         d.schedule = EXM_SCHED_TILED;
         d.chunk_layers = 0;
@@ -456,8 +487,37 @@ static int32_t run_pipe(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts
     return launch_pipe(P, a, t, plan->max_cells, ch.chunk_layers, lds, stream);
 }
 
+static int32_t run_chunked(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
+{
+    const TilePlan* plan = nullptr;
+    const bool owner = ch.race == EXM_RACE_OWNER;
+    int32_t s = owner ? build_owner_plan(mesh, ch.tile_cells, &plan) : build_tile_plan(mesh, ch.tile_cells, &plan);
+    if (s != EXM_OK) return s;
+    const size_t lds = chunk_lds_bytes(plan->max_verts, ch.chunk_layers);
+    P.race = ch.race;
+    P.shape = make_shape(1, 1);
+    const ColArgs a = col_args(P);
+    TileArgs t;
+    fill_tile_args(plan, P, t);
+    if (ch.race == EXM_RACE_COLOUR) {
+        t.tiles = plan->colour_tiles.p;
+        for (int32_t k = 0; k < plan->n_colours; ++k) {
+            t.tile_begin = (int32_t)plan->colour_off[k];
+            t.tile_count = (int32_t)(plan->colour_off[k + 1] - plan->colour_off[k]);
+            s = launch_chunked(P, a, t, ch.chunk_layers, lds, stream);
+            if (s != EXM_OK) return s;
+        }
+        return EXM_OK;
+    }
+    t.tiles = nullptr;
+    t.tile_begin = 0;
+    t.tile_count = plan->n_tiles;
+    return launch_chunked(P, a, t, ch.chunk_layers, lds, stream);
+}
+
 static int32_t run_on_mesh(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
 {
+    if (ch.schedule == EXM_SCHED_CHUNKED) return run_chunked(mesh, P, ch, stream);
     if (ch.schedule == EXM_SCHED_DIRECT) return run_direct(mesh, P, ch, stream);
     if (ch.schedule == EXM_SCHED_PIPELINED) return run_pipe(mesh, P, ch, stream);
     if (ch.schedule == EXM_SCHED_STAGED) return run_staged(mesh, P, ch, stream);
@@ -527,10 +587,14 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
         if (pipe_supported(P.kernel, P.element))
             for (int32_t tc : {32, 64, 128, 256})
-                for (int32_t S : {8, 16, 32})
-                    if (tc <= pipe_max_tile_cells(P.element, S)) {
+                for (int32_t S : {8, 12, 16, 24, 32})
+                    if (pipe_chunk_ok(P.element, S) && tc <= pipe_max_tile_cells(P.element, S)) {
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
                         if (cg && r == 0) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
+                        if (P.element == EXM_ELEMENT_P1P1 && (S & (S - 1)) == 0) {
+                            cand.push_back(exm_loop_opts{races[r], EXM_SCHED_CHUNKED, 0, 4, tc, S});
+                            if (r == 0) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_CHUNKED, 0, 4, tc, S});
+                        }
                     }
         if (cg)
             for (int32_t t : {32, 64, 128, 256})
@@ -612,11 +676,11 @@ int32_t exm_autotune_load(const char* path)
                          o.tile_cells >> o.chunk_layers),
                   EXM_EINVAL, "%s:%d: malformed line", path, ln);
         EXM_CHECK((o.race == EXM_RACE_ATOMIC || o.race == EXM_RACE_COLOUR || o.race == EXM_RACE_OWNER) &&
-                      o.schedule >= EXM_SCHED_DIRECT && o.schedule <= EXM_SCHED_PIPELINED && o.cols_per_wave >= 0 &&
+                      o.schedule >= EXM_SCHED_DIRECT && o.schedule <= EXM_SCHED_CHUNKED && o.cols_per_wave >= 0 &&
                       o.cols_per_wave <= 16 && o.waves_per_block >= 1 && o.waves_per_block <= 16 &&
                       o.tile_cells >= 0 && o.tile_cells <= 1024 &&
-                      (o.chunk_layers == 0 || o.chunk_layers == 8 || o.chunk_layers == 16 || o.chunk_layers == 32 ||
-                       o.chunk_layers == 64),
+                      (o.chunk_layers == 0 || o.chunk_layers == 8 || o.chunk_layers == 12 || o.chunk_layers == 16 ||
+                       o.chunk_layers == 24 || o.chunk_layers == 32 || o.chunk_layers == 64),
                   EXM_ERANGE, "%s:%d: values out of range", path, ln);
         table[TuneKey(k, e, l, b)] = o;
     }

@@ -30,6 +30,8 @@
 // index at or below its first level, so the slot holds one extra level below
 // when the column start is odd (the parity is fixed because S is even).
 // Base pointers must be 16-byte aligned; the host checks.
+#include <algorithm>
+
 #include "exm_elements.hpp"
 #include "exm_tiled.hpp"
 
@@ -40,7 +42,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPasses = 2;   // cells per thread: tile_cells <= kPasses * 256 * kLayers / S
 constexpr int kLayers = 4;   // consecutive layers of one cell per thread
-constexpr int kCopy = 4;     // 16-byte copy slots per thread and array: verts * (S / 2 + 1) <= 256 * kCopy
 
 __device__ __forceinline__ unsigned xcd_block_p(unsigned b, unsigned G)
 {
@@ -100,23 +101,32 @@ struct Chunk {
 
 }  // namespace
 
-// P1 x P1 mass action / RHS, y += M x (INC).  LDS: Z[2], X[2], Y[2] of
-// vstride * (S + 2) doubles, then x, y (doubles) and tag, column start (ints)
-// per tile vertex.  MODE (how vertices shared between tiles are summed):
+// How vertices shared between tiles are summed (MODE):
 //   kPlain  - one launch holds one colour of tiles: every vertex is
 //             read-added-written;
-//   kAtomic - shared vertices start from zero and are added atomically;
+//   kAtomic - shared vertices are added atomically, the others read-added-
+//             written;
 //   kOwner  - owner plan: the tile writes only the vertices it owns (the first
-//             `owned` of its list), with plain stores, and drops the
+//             `owned` of its list), with read-add-write, and drops the
 //             contributions of its cells to the other vertices.
 constexpr int kPlain = 0, kAtomic = 1, kOwner = 2;
 
+// Per-thread output items: item i of thread t is (vertex, level offset)
+// (t + 256 i) / S, (t + 256 i) % S of the chunk.
+constexpr int kItems = 4;
+
+// P1 x P1 mass action / RHS, y += M x (INC).  LDS: Z[2] and X[2] of
+// vstride * (S + 2) doubles (16-byte aligned vertex slots), the accumulator A
+// (same slots, levels l0 .. l0 + S of the chunk, the top one carried into the
+// next chunk), then tag and column start (ints) per tile vertex; (x, y) per
+// vertex only during set-up, inside A.  The old output values of a chunk are
+// loaded into registers while the chunk computes and added when it is written
+// back, during the next chunk.
 template <int S, int MODE>
 __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const TileArgs t)
 {
     constexpr bool ATOMIC = MODE == kAtomic;
-    using C = Chunk<S>;
-    constexpr int P2 = C::P2, PP = C::PP, LS = C::LS, R = C::R, G = C::G, CPP = C::CPP;
+    constexpr int P2 = S + 2, PP = P2 / 2, R = kLayers, G = S / R, CPP = kThreads / G;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
@@ -127,10 +137,10 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     const int VS = t.vstride * P2;
     double* const Zs = lds;
     double* const Xs = lds + 2 * VS;
-    double* const Ys = lds + 4 * VS;
-    double* const Tx = lds + 6 * VS;
-    double* const Ty = Tx + t.vstride;
-    int32_t* const Ttag = (int32_t*)(Ty + t.vstride);
+    double* const A = lds + 4 * VS;
+    double* const Tx = A;                 // set-up only
+    double* const Ty = A + t.vstride;
+    int32_t* const Ttag = (int32_t*)(lds + 5 * VS);
     int32_t* const Txst = Ttag + t.vstride;
     const int64_t n = a.xn;
     const double* const z = a.X + 2 * n;
@@ -150,9 +160,9 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     lds_barrier();
 
     // this thread's cells: LDS slot start of each vertex (with the parity
-    // shift) and 2A, fixed for the whole column; the thread takes layers
-    // r0 .. r0 + R - 1 of every chunk
-    const int r0 = (tid & (G - 1)) * R;
+    // shift) and 2A, fixed for the whole column; layers r0 .. r0 + R - 1 of
+    // every chunk
+    const int r0 = (tid % G) * R;
     int vb[kPasses][3];
     double twoA[kPasses];
     bool has[kPasses];
@@ -160,7 +170,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
         const int c = tid / G + p * CPP;
-        has[p] = c < nc;
+        has[p] = tid < CPP * G && c < nc;
         double xq[3], yq[3];
         wmask[p] = 0;
 #pragma unroll
@@ -175,81 +185,102 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     }
     const int npass = (nc + CPP - 1) / CPP;
 
-    // this thread's copy slots: pair e = tid + 256 i of the tile's vertex slots
-    int32_t sidx[kCopy], lim[kCopy];
-    bool sh[kCopy], noy[kCopy];
+    // this thread's output items: accumulator slot, global index (without
+    // the chunk's first level), kind
+    // ipos: slot (low 30 bits) and kind (top 2 bits: 0 none, 1 read-add-write, 2 atomic)
+    int32_t ipos[kItems], iglb[kItems];
 #pragma unroll
-    for (int i = 0; i < kCopy; ++i) {
-        const int e = tid + kThreads * i;
-        const int v = e / PP, w = e - (e / PP) * PP;
-        const bool ok = v < nv;
+    for (int i = 0; i < kItems; ++i) {
+        const int it = tid + kThreads * i;
+        const int v = it / S, jj = it - (it / S) * S;
+        const bool ok = v < no;
         const int32_t xs = ok ? Txst[v] : 0;
-        const int sv = xs & 1;
-        sidx[i] = xs - sv + 2 * w;                 // even: 16-byte aligned pair
-        lim[i] = ok ? 2 * w - sv : 0x7fffffff;     // needed iff lim <= levels in the chunk
-        sh[i] = ATOMIC && ok && vshared(Ttag[v]);
-        noy[i] = MODE == kOwner && v >= no;   // read-only vertex: no output slot
+        const int kind = !ok ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
+        ipos[i] = (v * P2 + (xs & 1) + jj) | (kind << 30);
+        iglb[i] = xs + jj;
     }
+    lds_barrier();   // (x, y) are no longer needed: the accumulator takes their place
+    for (int i = tid; i < VS; i += kThreads) A[i] = 0.0;
     const int wave_e = tid & ~63;
 
+    // copies: pair e of the tile's vertex slots (vertex e / PP), levels from
+    // the even global index at or below the chunk's first level
     auto issue_copies = [&](int k) {
         const int l0 = k * S;
         const int nl = min(S, lam - l0);
         const int b = k & 1;
-#pragma unroll
-        for (int i = 0; i < kCopy; ++i) {
-            if (lim[i] > nl) continue;
-            const int64_t g = (int64_t)sidx[i] + l0;
-            const int eb = 2 * (kThreads * i + wave_e);   // wave's first double in the slot array
-            const int e2 = 2 * (kThreads * i + tid);
+        for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int v = e / PP, w = e - (e / PP) * PP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int sv = xs & 1;
+            if (2 * w - sv > nl) continue;
+            const int64_t g = (int64_t)xs - sv + l0 + 2 * w;
+            const int eb = 2 * (e0 + wave_e);   // wave's first double in the slot array
+            const int e2 = 2 * e;
             if (g + 1 < n) {
                 copy16(z + g, Zs + b * VS + eb);
                 copy16(x + g, Xs + b * VS + eb);
-                if (!sh[i] && !noy[i]) copy16(y + g, Ys + b * VS + eb);
-            } else {
-                // the array's last element: keep the read inside the array
+            } else {   // the array's last element: keep the read inside the array
                 Zs[b * VS + e2] = z[g];
                 Xs[b * VS + e2] = x[g];
-                if (!sh[i] && !noy[i]) Ys[b * VS + e2] = y[g];
             }
-            if (sh[i]) {   // shared vertices start from zero and are added atomically
-                Ys[b * VS + e2] = 0.0;
-                Ys[b * VS + e2 + 1] = 0.0;
+        }
+    };
+    // old output values of chunk k (levels below its top), into registers
+    auto load_old = [&](int k, double (&dst)[kItems]) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+#pragma unroll
+        for (int i = 0; i < kItems; ++i)
+            dst[i] = (((uint32_t)ipos[i] >> 30) == 1 && (tid + kThreads * i) % S < nl) ? y[(int64_t)iglb[i] + l0] : 0.0;
+    };
+    // write chunk k back (levels l0 .. l0 + nl - 1); with `carry`, move its
+    // top level to level 0 for chunk k + 1
+    auto write_back = [&](int k, const double (&old)[kItems], bool carry) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int jj = (tid + kThreads * i) % S;
+            const int kind = (int)((uint32_t)ipos[i] >> 30);
+            const int pos = ipos[i] & 0x3fffffff;
+            if (kind == 0 || jj >= nl) continue;
+            const double s = A[pos];
+            const int64_t g = (int64_t)iglb[i] + l0;
+            if (kind == 2)
+                unsafeAtomicAdd(y + g, s);
+            else
+                y[g] = old[i] + s;
+            if (carry && jj == 0) {
+                A[pos] = A[pos + S];
+                A[pos + S] = 0.0;
+            } else {
+                A[pos] = 0.0;
             }
         }
     };
 
+    // yA: old values of the next chunk to be written back (loading); yB: of
+    // the chunk written back next
+    double yA[kItems], yB[kItems];
     const int nch = (lam + S - 1) / S;
     issue_copies(0);
+    load_old(0, yA);
     for (int k = 0; k < nch; ++k) {
         const int b = k & 1;
         const int l0 = k * S;
         const int nl = min(S, lam - l0);
         wait_copies();
         lds_barrier();
-        // 1. write chunk k-1 back; carry its top level into chunk k
-        if (k > 0) {
-            const double* Yp = Ys + (b ^ 1) * VS;
-            const int l0p = l0 - S;
-            for (int it = tid; it < (no << LS); it += kThreads) {
-                const int v = it >> LS, jj = it & (S - 1);
-                const int32_t xs = Txst[v];
-                const double s = Yp[v * P2 + (xs & 1) + jj];
-                const int64_t g = (int64_t)xs + l0p + jj;
-                if (ATOMIC && vshared(Ttag[v]))
-                    unsafeAtomicAdd(y + g, s);
-                else
-                    y[g] = s;
-            }
-        }
-        double* const Yb = Ys + b * VS;
-        for (int v = tid; v < no; v += kThreads) {
-            const int o = v * P2 + (Txst[v] & 1);
-            if (k > 0) Yb[o] += Ys[(b ^ 1) * VS + o + S];
-            if (nl == S && l0 + S < lam) Yb[o + S] = 0.0;   // level l0 + S belongs to chunk k+1
-        }
+        // 1. write chunk k-1 back and carry its top level into chunk k
+        if (k > 0) write_back(k - 1, yB, true);
+        // 2. old output values of chunk k+1, then the copies of chunk k+1
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) yB[i] = yA[i];
+        if (k + 1 < nch) load_old(k + 1, yA);
         lds_barrier();
-        // 2. copies of chunk k+1
         if (k + 1 < nch) issue_copies(k + 1);
         // 3. element kernels of chunk k: R consecutive layers of one cell per
         // thread; a level's sum over the thread's layers goes to LDS once
@@ -282,7 +313,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
                 p1_mass(twoA[p], h, xc, xn, yb, yt);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(Yb + o[q] + r, acc[q] + yb[q]);
+                    if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q] + yb[q]);
                     acc[q] = yt[q];
                     zc[q] = zn[q];
                     xc[q] = xn[q];
@@ -290,34 +321,23 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
             }
 #pragma unroll
             for (int q = 0; q < 3; ++q)
-                if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(Yb + o[q] + r, acc[q]);
+                if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q]);
         }
     }
     // write back the last chunk, its top level included
     lds_barrier();
     {
         const int k = nch - 1;
-        const double* Yl = Ys + (k & 1) * VS;
         const int l0 = k * S, nl = lam - l0;
-        for (int it = tid; it < (no << LS); it += kThreads) {
-            const int v = it >> LS, jj = it & (S - 1);
-            if (jj >= nl) continue;
-            const int32_t xs = Txst[v];
-            const double s = Yl[v * P2 + (xs & 1) + jj];
-            const int64_t g = (int64_t)xs + l0 + jj;
-            if (ATOMIC && vshared(Ttag[v]))
-                unsafeAtomicAdd(y + g, s);
-            else
-                y[g] = s;
-        }
+        write_back(k, yB, false);
         for (int v = tid; v < no; v += kThreads) {
             const int32_t xs = Txst[v];
-            const double s = Yl[v * P2 + (xs & 1) + nl];
+            const double s = A[v * P2 + (xs & 1) + nl];
             const int64_t g = (int64_t)xs + lam;
             if (ATOMIC && vshared(Ttag[v]))
                 unsafeAtomicAdd(y + g, s);
             else
-                y[g] = s;
+                y[g] += s;
         }
     }
 }
@@ -500,13 +520,216 @@ __global__ void __launch_bounds__(kThreads, NDOF == 1 ? 8 : 4) k_pipe_dg(const C
     store_results();
 }
 
+// CHUNKED schedule, P1 x P1 mass action / RHS (INC): one workgroup per
+// (tile, chunk).  Chunk c computes the layers c (S - 1) .. c (S - 1) + S - 1
+// and writes the levels whose two neighbouring layers it computed (the
+// chunk's inner levels, plus level 0 in the first chunk and level lambda in
+// the last): consecutive chunks overlap by one layer, so no partial sum
+// crosses a workgroup and every (vertex, level) is written by one workgroup
+// per tile.  Workgroups are independent: each copies its column segments
+// into LDS (asynchronous 16-byte copies), waits once, computes, and writes.
+// The grid is chunk-major, so the workgroups that run together hold
+// neighbouring tiles at the same levels and share their boundary columns in
+// L2.  MODE as for k_pipe_p1 (kOwner with an owner plan, kAtomic, or kPlain
+// for one colour of tiles).  LDS: Z, X, Y of vstride * (S + 2) doubles, then
+// x, y (doubles) and tag, column start (ints) per tile vertex.
+template <int S, int MODE>
+__global__ void __launch_bounds__(kThreads) k_chunk_p1(const ColArgs a, const TileArgs t, int32_t n_chunks)
+{
+    constexpr bool ATOMIC = MODE == kAtomic;
+    using C = Chunk<S>;
+    constexpr int P2 = C::P2, PP = C::PP, R = C::R, G = C::G, CPP = C::CPP;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t chunk = blk / t.tile_count;
+    const int32_t tl = blk - chunk * t.tile_count;
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + tl] : t.tile_begin + tl;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int32_t no = MODE == kOwner ? t.owned[tile] : nv;
+    const int VS = t.vstride * P2;
+    double* const Zs = lds;
+    double* const Xs = lds + VS;
+    double* const Ys = lds + 2 * VS;
+    double* const Tx = lds + 3 * VS;
+    double* const Ty = Tx + t.vstride;
+    int32_t* const Ttag = (int32_t*)(Ty + t.vstride);
+    int32_t* const Txst = Ttag + t.vstride;
+    const int64_t n = a.xn;
+    const double* const z = a.X + 2 * n;
+    const double* const x = a.in0;
+    double* const y = a.out0;
+    const int lam = a.n_layers;
+    const int la = chunk * (S - 1);                // first layer computed
+    const int nlay = min(S, lam - la);             // layers computed
+    const int lw0 = chunk == 0 ? 0 : 1;            // written levels: la + lw0 .. la + lw1
+    const int lw1 = la + nlay == lam ? nlay : nlay - 1;
+    (void)n_chunks;
+
+    for (int v = tid; v < nv; v += kThreads) {
+        const int32_t tag = t.verts[vb0 + v];
+        const int32_t xs = t.xstart[vid(tag)];
+        Ttag[v] = tag;
+        Txst[v] = xs;
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+    }
+    lds_barrier();
+
+    // copies: slot of vertex v holds levels la - s_v .. la - s_v + S + 1, s_v
+    // the parity of its first level (16-byte aligned pairs)
+    const int wave_e = tid & ~63;
+    for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
+        const int e = e0 + tid;
+        const int v = e / PP, w = e - (e / PP) * PP;
+        if (v >= nv) continue;
+        const int32_t xs = Txst[v];
+        const int sv = (xs + la) & 1;
+        if (2 * w - sv > nlay) continue;           // levels la .. la + nlay
+        const int64_t g = (int64_t)xs + la - sv + 2 * w;
+        const bool wr = v < no;                    // a written vertex: its old output values too
+        const bool zero = ATOMIC && vshared(Ttag[v]);
+        if (g + 1 < n) {
+            copy16(z + g, Zs + 2 * (e0 + wave_e));
+            copy16(x + g, Xs + 2 * (e0 + wave_e));
+            if (wr && !zero) copy16(y + g, Ys + 2 * (e0 + wave_e));
+        } else {
+            Zs[2 * e] = z[g];
+            Xs[2 * e] = x[g];
+            if (wr && !zero) Ys[2 * e] = y[g];
+        }
+        if (zero) {
+            Ys[2 * e] = 0.0;
+            Ys[2 * e + 1] = 0.0;
+        }
+    }
+
+    // this thread's cells, layers r0 .. r0 + R - 1 of the chunk
+    const int r0 = (tid & (G - 1)) * R;
+    int vb[kPasses][3];
+    double twoA[kPasses];
+    bool has[kPasses];
+    int wmask[kPasses];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        const int c = tid / G + p * CPP;
+        has[p] = c < nc;
+        double xq[3], yq[3];
+        wmask[p] = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            vb[p][q] = lv * P2 + ((Txst[lv] + la) & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+            wmask[p] |= (lv < no ? 1 : 0) << q;
+        }
+        twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
+    }
+    const int npass = (nc + CPP - 1) / CPP;
+    wait_copies();
+    lds_barrier();
+
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        if (p >= npass) break;
+        if (!has[p] || r0 >= nlay) continue;
+        int o[3];
+        double zc[3], xc[3], acc[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            o[q] = vb[p][q] + r0;
+            zc[q] = Zs[o[q]];
+            xc[q] = Xs[o[q]];
+            acc[q] = 0.0;
+        }
+        int r = 0;
+#pragma unroll
+        for (; r < R; ++r) {
+            if (r0 + r >= nlay) break;
+            double zn[3], xn[3], h[3], yb[3], yt[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                zn[q] = Zs[o[q] + r + 1];
+                xn[q] = Xs[o[q] + r + 1];
+                h[q] = zn[q] - zc[q];
+            }
+            p1_mass(twoA[p], h, xc, xn, yb, yt);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(Ys + o[q] + r, acc[q] + yb[q]);
+                acc[q] = yt[q];
+                zc[q] = zn[q];
+                xc[q] = xn[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(Ys + o[q] + r, acc[q]);
+    }
+    lds_barrier();
+
+    // write the chunk's levels la + lw0 .. la + lw1 of every written vertex
+    const int nw = lw1 - lw0 + 1;
+    for (int it = tid; it < no * nw; it += kThreads) {
+        const int v = it / nw, jj = lw0 + (it - (it / nw) * nw);
+        const int32_t xs = Txst[v];
+        const double s = Ys[v * P2 + ((xs + la) & 1) + jj];
+        const int64_t g = (int64_t)xs + la + jj;
+        if (ATOMIC && vshared(Ttag[v]))
+            unsafeAtomicAdd(y + g, s);
+        else
+            y[g] = s;
+    }
+}
+
+size_t chunk_lds_bytes(int32_t vstride, int32_t S)
+{
+    return sizeof(double) * (3 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + 2 * sizeof(int32_t) * vstride;
+}
+
+int32_t chunk_count(int32_t n_layers, int32_t S) { return n_layers <= S ? 1 : 1 + (n_layers - 2) / (S - 1); }
+
+template <int S>
+static void launch_chunk_s(int32_t race, const ColArgs& a, const TileArgs& t, int32_t nch, size_t lds, hipStream_t s)
+{
+    const dim3 grid((unsigned)((int64_t)t.tile_count * nch)), block(kThreads);
+    if (race == EXM_RACE_OWNER)
+        hipLaunchKernelGGL((k_chunk_p1<S, kOwner>), grid, block, lds, s, a, t, nch);
+    else if (race == EXM_RACE_COLOUR)
+        hipLaunchKernelGGL((k_chunk_p1<S, kPlain>), grid, block, lds, s, a, t, nch);
+    else
+        hipLaunchKernelGGL((k_chunk_p1<S, kAtomic>), grid, block, lds, s, a, t, nch);
+}
+
+int32_t launch_chunked(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t S, size_t lds, hipStream_t s)
+{
+    if (t.tile_count <= 0) return EXM_OK;
+    EXM_CHECK(P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1, EXM_EUNSUPPORTED,
+              "the CHUNKED schedule runs the P1xP1 mass action only");
+    const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.out0;
+    EXM_CHECK((al & 15) == 0, EXM_EUNSUPPORTED, "the CHUNKED schedule needs 16-byte aligned field pointers");
+    EXM_CHECK(P.race != EXM_RACE_OWNER || t.owned != nullptr, EXM_EINVAL, "owner-computes needs an owner plan");
+    const int32_t nch = chunk_count(a.n_layers, S);
+    EXM_CHECK((int64_t)t.tile_count * nch < INT32_MAX, EXM_EOVERFLOW, "too many workgroups");
+    switch (S) {
+    case 8: launch_chunk_s<8>(P.race, a, t, nch, lds, s); break;
+    case 16: launch_chunk_s<16>(P.race, a, t, nch, lds, s); break;
+    case 32: launch_chunk_s<32>(P.race, a, t, nch, lds, s); break;
+    default: return fail(EXM_ERANGE, "chunk_layers = %d: the CHUNKED schedule takes 8, 16 or 32", S);
+    }
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
 // ---------------------------------------------------------------------------
 
 size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t cstride, int32_t S)
 {
     if (kernel != EXM_K_MASS) return 0;
     if (element == EXM_ELEMENT_P1P1)
-        return sizeof(double) * (6 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + 2 * sizeof(int32_t) * vstride;
+        return sizeof(double) * 5 * (size_t)vstride * (S + 2) + 2 * sizeof(int32_t) * vstride;
     if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1)
         return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + sizeof(int32_t) * vstride;
     return 0;
@@ -522,10 +745,16 @@ int32_t pipe_max_tile_cells(int32_t element, int32_t S)
 {
     if (element == EXM_ELEMENT_DG0DG0) return 2 * kThreads / S;
     if (element == EXM_ELEMENT_DG1DG1) return 2 * kThreads / S;
-    return kPasses * kThreads * kLayers / S;
+    return kPasses * (kThreads / (S / kLayers));
 }
 
-int32_t pipe_max_tile_verts(int32_t S) { return kThreads * kCopy / (S / 2 + 1); }
+bool pipe_chunk_ok(int32_t element, int32_t S)
+{
+    if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 24 || S == 32;
+    return S == 8 || S == 16 || S == 32;
+}
+
+int32_t pipe_max_tile_verts(int32_t S) { return kThreads * kItems / S; }
 
 template <int S>
 static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
@@ -572,9 +801,11 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
     EXM_CHECK(P.race != EXM_RACE_OWNER || t.owned != nullptr, EXM_EINVAL, "owner-computes needs an owner plan");
     switch (S) {
     case 8: launch_pipe_s<8>(P.race, a, t, lds, s); break;
+    case 12: launch_pipe_s<12>(P.race, a, t, lds, s); break;
     case 16: launch_pipe_s<16>(P.race, a, t, lds, s); break;
+    case 24: launch_pipe_s<24>(P.race, a, t, lds, s); break;
     case 32: launch_pipe_s<32>(P.race, a, t, lds, s); break;
-    default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 16 or 32", S);
+    default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 12, 16, 24 or 32 on P1xP1", S);
     }
     EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;

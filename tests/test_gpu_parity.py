@@ -36,7 +36,8 @@ def test_numbering_bit_exact(space, n, lam, order):
             np.testing.assert_array_equal(starts, ref.column_starts(d1).astype(np.int32))
 
 
-SCHEDULES = [exm.EXM_SCHED_DIRECT, exm.EXM_SCHED_TILED, exm.EXM_SCHED_STAGED, exm.EXM_SCHED_PIPELINED]
+SCHEDULES = [exm.EXM_SCHED_DIRECT, exm.EXM_SCHED_TILED, exm.EXM_SCHED_STAGED, exm.EXM_SCHED_PIPELINED,
+             exm.EXM_SCHED_CHUNKED]
 RACES = [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR]
 
 
@@ -103,12 +104,13 @@ def test_mass_staged_shapes(space, tile, chunk, race):
         assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"staged mass {space} tile={tile} S={chunk} lam={lam}")
 
 
+@pytest.mark.parametrize("schedule", [exm.EXM_SCHED_PIPELINED, exm.EXM_SCHED_CHUNKED])
 @pytest.mark.parametrize("space", ["P1", "DG0", "DG1"])
 @pytest.mark.parametrize("tile", [8, 29, 64, 128])
-@pytest.mark.parametrize("chunk", [8, 16, 32])
+@pytest.mark.parametrize("chunk", [8, 12, 16, 24, 32])
 @pytest.mark.parametrize("race", RACES + [exm.EXM_RACE_OWNER])
-def test_mass_pipelined_shapes(space, tile, chunk, race):
-    say(f"pipelined shape {space} tile={tile} chunk={chunk} race={race}")
+def test_mass_pipelined_shapes(schedule, space, tile, chunk, race):
+    say(f"pipelined shape {space} schedule={schedule} tile={tile} chunk={chunk} race={race}")
     base = meshgen.tri_square(10, order="random" if tile == 29 else "rcm")
     for lam in (1, chunk - 1, chunk, 2 * chunk + 3):
         c = Case(base, lam, space, terrain=0.2)
@@ -117,10 +119,13 @@ def test_mass_pipelined_shapes(space, tile, chunk, race):
         xd, y = c.dev(x), c.dev(y0)
         try:
             exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, c.out_access())],
-                         schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=chunk, race=race)
+                         schedule=schedule, tile_cells=tile, chunk_layers=chunk, race=race)
         except exm.ExmError as e:
-            # tiles too large for the chunk length are refused before any launch
-            assert e.status == exm._abi.EXM_EUNSUPPORTED and "PIPELINED" in str(e), str(e)
+            # tiles too large for the chunk length, and chunk lengths a schedule or
+            # space does not take, are refused before any launch
+            big = e.status == exm._abi.EXM_EUNSUPPORTED and ("PIPELINED" in str(e) or "CHUNKED" in str(e))
+            odd = e.status == exm._abi.EXM_ERANGE and chunk in (12, 24) and (space != "P1" or schedule != 4)
+            assert big or odd, str(e)
             return
         if space == "P1":
             # INC into a non-zero output: the old values pass through the staged copy
