@@ -112,85 +112,112 @@ __device__ __forceinline__ void p2_mass(double twoA, const double h[3], const do
 // residual (u^3 - f) v det J has degree 5 horizontally and 4 vertically on
 // these prisms, so the 7-point degree-5 triangle rule of Radon (centroid and
 // two three-point orbits built on sqrt(15)) times 3-point Gauss-Legendre in
-// zeta integrates it exactly.
+// zeta integrates it exactly; so does the adjoint integrand 3 u^2 w v det J.
+//
+// The points are visited one at a time and their contributions to the test
+// functions summed as they go, so that no per-point table of the fields is
+// held in registers.
 
-struct CubicRule {
-    // barycentric coordinates and weights (weights sum to 1/2, the reference area)
-    double lam[7][3];
-    double w[7];
-    double z[3];
-    double wz[3];
-};
+namespace cubic {
 
-__device__ __forceinline__ void cubic_rule(CubicRule& r)
+constexpr double kS15 = 3.872983346207416885;   // sqrt(15)
+constexpr double kA1 = (6.0 - kS15) / 21.0, kA2 = (6.0 + kS15) / 21.0;
+constexpr double kB1 = 1.0 - 2.0 * kA1, kB2 = 1.0 - 2.0 * kA2;
+constexpr double kW1 = (155.0 - kS15) / 2400.0, kW2 = (155.0 + kS15) / 2400.0;
+// barycentric coordinates and weights of the triangle rule (weights sum to
+// 1/2, the reference area)
+constexpr double kLam[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {kA1, kA1, kB1}, {kA1, kB1, kA1}, {kB1, kA1, kA1},
+                               {kA2, kA2, kB2}, {kA2, kB2, kA2}, {kB2, kA2, kA2}};
+constexpr double kWt[7] = {9.0 / 80.0, kW1, kW1, kW1, kW2, kW2, kW2};
+// Gauss-Legendre on [0, 1]
+constexpr double kG = 0.5 * 0.774596669241483377;   // sqrt(3/5) / 2
+constexpr double kZ[3] = {0.5 - kG, 0.5, 0.5 + kG};
+constexpr double kWz[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+}  // namespace cubic
+
+// Nonlinear P1 x P1 element forms on one prism (b, t: bottom / top nodal
+// values of each input at the three vertices; yb, yt: outputs likewise).
+//   FORM 1: F = integral (u^3 - f) v             inputs u, f;    output F
+//   FORM 2: g_u = integral 3 u^2 w v, g_f = -M w inputs u, w;    outputs g_u, g_f
+//   FORM 3: F, g_u, g_f together                 inputs u, f, w; outputs F, g_u, g_f
+template <int FORM>
+__device__ __forceinline__ void cubic_element(double twoA, const double h[3], const double b[][3],
+                                              const double t[][3], double yb[][3], double yt[][3])
 {
-    const double s15 = 3.872983346207416885;   // sqrt(15)
-    const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
-    const double w1 = (155.0 - s15) / 2400.0, w2 = (155.0 + s15) / 2400.0;
-    const double b1 = 1.0 - 2.0 * a1, b2 = 1.0 - 2.0 * a2;
-    const double L[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, a1, b1}, {a1, b1, a1}, {b1, a1, a1},
-                            {a2, a2, b2}, {a2, b2, a2}, {b2, a2, a2}};
-    const double W[7] = {9.0 / 80.0, w1, w1, w1, w2, w2, w2};
-#pragma unroll
+    using namespace cubic;
+    constexpr bool F = FORM == 1 || FORM == 3;
+    constexpr bool GU = FORM == 2 || FORM == 3;
+    constexpr int iw = FORM == 2 ? 1 : 2;      // input index of w
+    constexpr int ou = FORM == 2 ? 0 : 1;      // output index of g_u
+    double fb[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0};   // F
+    double gb[3] = {0.0, 0.0, 0.0}, gt[3] = {0.0, 0.0, 0.0};   // g_u
+    // the fused form holds three inputs and two sets of sums: one triangle
+    // point at a time keeps its live set small; the others unroll
+    constexpr int kUnroll = FORM == 3 ? 1 : 7;
+#pragma unroll kUnroll
     for (int i = 0; i < 7; ++i) {
-        r.w[i] = W[i];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) r.lam[i][a] = L[i][a];
-    }
-    const double g = 0.5 * 0.774596669241483377;   // sqrt(3/5) / 2
-    r.z[0] = 0.5 - g;
-    r.z[1] = 0.5;
-    r.z[2] = 0.5 + g;
-    r.wz[0] = 5.0 / 18.0;
-    r.wz[1] = 8.0 / 18.0;
-    r.wz[2] = 5.0 / 18.0;
-}
-
-// Values of a P1 x P1 field at the 21 points: v[i][j] (triangle point i,
-// interval point j).
-__device__ __forceinline__ void p1_at_points(const CubicRule& r, const double xb[3], const double xt[3],
-                                             double v[7][3])
-{
-    double col[3][3];   // column value of vertex a at height z_j
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) col[a][j] = xb[a] + r.z[j] * (xt[a] - xb[a]);
-#pragma unroll
-    for (int i = 0; i < 7; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            v[i][j] = r.lam[i][0] * col[0][j] + r.lam[i][1] * col[1][j] + r.lam[i][2] * col[2][j];
-}
-
-// Test a point-value field s[i][j] (already multiplied by weights and det J)
-// against the P1 x P1 basis: out_b[a] += sum s lambda_a (1 - z), out_t[a] += sum s lambda_a z.
-__device__ __forceinline__ void p1_test(const CubicRule& r, const double s[7][3], double ob[3], double ot[3])
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double tb = 0.0, tt = 0.0;
+        const double dj = twoA * (kLam[i][0] * h[0] + kLam[i][1] * h[1] + kLam[i][2] * h[2]);
+        // each input at the column of point i: bottom value and rise over the layer
+        const double u0 = kLam[i][0] * b[0][0] + kLam[i][1] * b[0][1] + kLam[i][2] * b[0][2];
+        const double u1 = kLam[i][0] * t[0][0] + kLam[i][1] * t[0][1] + kLam[i][2] * t[0][2] - u0;
+        double f0 = 0.0, f1 = 0.0, w0 = 0.0, w1 = 0.0;
+        if constexpr (F) {
+            f0 = kLam[i][0] * b[1][0] + kLam[i][1] * b[1][1] + kLam[i][2] * b[1][2];
+            f1 = kLam[i][0] * t[1][0] + kLam[i][1] * t[1][1] + kLam[i][2] * t[1][2] - f0;
+        }
+        if constexpr (GU) {
+            w0 = kLam[i][0] * b[iw][0] + kLam[i][1] * b[iw][1] + kLam[i][2] * b[iw][2];
+            w1 = kLam[i][0] * t[iw][0] + kLam[i][1] * t[iw][1] + kLam[i][2] * t[iw][2] - w0;
+        }
+        double sfb = 0.0, sft = 0.0, sgb = 0.0, sgt = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            double t = 0.0;
-#pragma unroll
-            for (int i = 0; i < 7; ++i) t += r.lam[i][a] * s[i][j];
-            tb += (1.0 - r.z[j]) * t;
-            tt += r.z[j] * t;
+            const double wq = kWt[i] * kWz[j] * dj;
+            const double u = u0 + kZ[j] * u1;
+            const double u2 = u * u;
+            if constexpr (F) {
+                const double s = wq * (u2 * u - (f0 + kZ[j] * f1));
+                sfb += (1.0 - kZ[j]) * s;
+                sft += kZ[j] * s;
+            }
+            if constexpr (GU) {
+                const double s = 3.0 * wq * u2 * (w0 + kZ[j] * w1);
+                sgb += (1.0 - kZ[j]) * s;
+                sgt += kZ[j] * s;
+            }
         }
-        ob[a] = tb;
-        ot[a] = tt;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if constexpr (F) {
+                fb[a] += kLam[i][a] * sfb;
+                ft[a] += kLam[i][a] * sft;
+            }
+            if constexpr (GU) {
+                gb[a] += kLam[i][a] * sgb;
+                gt[a] += kLam[i][a] * sgt;
+            }
+        }
     }
-}
-
-// det J times the quadrature weight at every point.
-__device__ __forceinline__ void cubic_weights(const CubicRule& r, double twoA, const double h[3], double W[7][3])
-{
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        const double dj = twoA * (r.lam[i][0] * h[0] + r.lam[i][1] * h[1] + r.lam[i][2] * h[2]);
+    for (int a = 0; a < 3; ++a) {
+        if constexpr (F) {
+            yb[0][a] = fb[a];
+            yt[0][a] = ft[a];
+        }
+        if constexpr (GU) {
+            yb[ou][a] = gb[a];
+            yt[ou][a] = gt[a];
+        }
+    }
+    if constexpr (GU) {   // g_f = -M w
+        double mb[3], mt[3];
+        p1_mass(twoA, h, b[iw], t[iw], mb, mt);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) W[i][j] = r.w[i] * r.wz[j] * dj;
+        for (int a = 0; a < 3; ++a) {
+            yb[ou + 1][a] = -mb[a];
+            yt[ou + 1][a] = -mt[a];
+        }
     }
 }
 

@@ -121,41 +121,10 @@ template <int FORM>
 __device__ __forceinline__ void element(double twoA, const double h[3], const double b[][3], const double tp[][3],
                                         double yb[][3], double yt[][3])
 {
-    if constexpr (FORM == 0) {
+    if constexpr (FORM == 0)
         p1_mass(twoA, h, b[0], tp[0], yb[0], yt[0]);
-    } else {
-        CubicRule Q;
-        cubic_rule(Q);
-        double W[7][3], uq[7][3];
-        cubic_weights(Q, twoA, h, W);
-        p1_at_points(Q, b[0], tp[0], uq);
-        if constexpr (FORM == 1 || FORM == 3) {
-            double fq[7][3], s[7][3];
-            p1_at_points(Q, b[1], tp[1], fq);
-#pragma unroll
-            for (int i = 0; i < 7; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) s[i][j] = W[i][j] * (uq[i][j] * uq[i][j] * uq[i][j] - fq[i][j]);
-            p1_test(Q, s, yb[0], yt[0]);
-        }
-        if constexpr (FORM == 2 || FORM == 3) {
-            constexpr int wi = FORM == 2 ? 1 : 2;
-            constexpr int og = FORM == 2 ? 0 : 1;
-            double wq[7][3], s[7][3], mb[3], mt[3];
-            p1_at_points(Q, b[wi], tp[wi], wq);
-#pragma unroll
-            for (int i = 0; i < 7; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) s[i][j] = W[i][j] * 3.0 * uq[i][j] * uq[i][j] * wq[i][j];
-            p1_test(Q, s, yb[og], yt[og]);
-            p1_mass(twoA, h, b[wi], tp[wi], mb, mt);
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                yb[og + 1][q] = -mb[q];
-                yt[og + 1][q] = -mt[q];
-            }
-        }
-    }
+    else
+        cubic_element<FORM>(twoA, h, b, tp, yb, yt);
 }
 
 }  // namespace
