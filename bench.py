@@ -346,6 +346,22 @@ def sweep(torch, exm):
 
 def secondary(torch, exm, W, meshgen):
     out = {}
+    # the RHS on the paper's nine spaces ({CG1, DG0, DG1} horizontally x vertically), 256 x 256 x 64
+    e9 = W.extruded(256, 64)
+    nine = {}
+    for name in ("P1", "CG1xDG0", "CG1xDG1", "DG0xCG1", "DG0", "DG0xDG1", "DG1xCG1", "DG1xDG0", "DG1"):
+        V = e9.space(name)
+        x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
+        y = V.zeros()
+        cfg = exm.autotune(exm.EXM_K_MASS, e9.mesh, e9.X, e9.Vx, W.mass_args(e9, name, x, y))
+        t, _ = timed(torch, lambda: W.run_mass(e9, name, x, y, **cfg), 10)
+        b = W.mass_bytes(e9, name)
+        nine[name] = {"ms": round(t, 4), "gbs": round(b["algorithmic"] / t / 1e6, 1),
+                      "dofs_per_s": round(V.n_dofs / t * 1e3), "schedule": cfg["schedule"]}
+        del x, y
+    out["rhs_nine_spaces_256x256x64"] = nine
+    log("nine spaces: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in nine.items()))
+    del e9
     # higher-order mass actions: 256 x 256 x 64, DG1 x DG1 and P2 x P2
     e3 = W.extruded(256, 64)
     for name in ("DG1", "P2"):

@@ -108,6 +108,14 @@ void exm_mesh_destroy(exm_mesh* mesh);
 #define EXM_ELEMENT_DG0DG0 2   /* DG0 x DG0, delta(2,1) = 1, arity 1            */
 #define EXM_ELEMENT_DG1DG1 3   /* DG1 x DG1, delta(2,1) = 6, arity 6            */
 #define EXM_ELEMENT_P2P2 4     /* CG2 x CG2, delta(0,*) = delta(1,*) = 1, arity 18 */
+/* The other tensor products of {CG1, DG0, DG1} (horizontal x vertical) of
+ * the paper's study (Section 4.1.3); mass action only, DIRECT schedule. */
+#define EXM_ELEMENT_P1DG0 5    /* CG1 x DG0, delta(0,1) = 1, arity 3            */
+#define EXM_ELEMENT_P1DG1 6    /* CG1 x DG1, delta(0,1) = 2, arity 6            */
+#define EXM_ELEMENT_DG0P1 7    /* DG0 x CG1, delta(2,0) = 1, arity 2            */
+#define EXM_ELEMENT_DG0DG1 8   /* DG0 x DG1, delta(2,1) = 2, arity 2            */
+#define EXM_ELEMENT_DG1P1 9    /* DG1 x CG1, delta(2,0) = 3, arity 6            */
+#define EXM_ELEMENT_DG1DG0 10  /* DG1 x DG0, delta(2,1) = 3, arity 3            */
 
 typedef struct exm_space exm_space;
 int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t element,

@@ -331,6 +331,12 @@ SPACES = {
     "DG0": ("DG0", "DG0"),
     "DG1": ("DG1", "DG1"),
     "P2": ("CG2", "CG2"),
+    "CG1xDG0": ("CG1", "DG0"),
+    "CG1xDG1": ("CG1", "DG1"),
+    "DG0xCG1": ("DG0", "CG1"),
+    "DG0xDG1": ("DG0", "DG1"),
+    "DG1xCG1": ("DG1", "CG1"),
+    "DG1xDG0": ("DG1", "DG0"),
 }
 
 

@@ -25,12 +25,25 @@ __all__ = ["Mesh", "Space", "par_loop", "ExmError", "ELEMENTS", "DELTA", "load_l
 
 # delta((d1, d2)) tables, flattened as d1 * 2 + d2 (Section 3.2)
 DELTA = {
+    _abi.EXM_ELEMENT_P1DG0: (0, 1, 0, 0, 0, 0),
+    _abi.EXM_ELEMENT_P1DG1: (0, 2, 0, 0, 0, 0),
+    _abi.EXM_ELEMENT_DG0P1: (0, 0, 0, 0, 1, 0),
+    _abi.EXM_ELEMENT_DG0DG1: (0, 0, 0, 0, 0, 2),
+    _abi.EXM_ELEMENT_DG1P1: (0, 0, 0, 0, 3, 0),
+    _abi.EXM_ELEMENT_DG1DG0: (0, 0, 0, 0, 0, 3),
     EXM_ELEMENT_P1P1: (1, 0, 0, 0, 0, 0),
     EXM_ELEMENT_DG0DG0: (0, 0, 0, 0, 0, 1),
     EXM_ELEMENT_DG1DG1: (0, 0, 0, 0, 0, 6),
     EXM_ELEMENT_P2P2: (1, 1, 1, 1, 0, 0),
 }
-ELEMENTS = {"P1": EXM_ELEMENT_P1P1, "DG0": EXM_ELEMENT_DG0DG0, "DG1": EXM_ELEMENT_DG1DG1, "P2": EXM_ELEMENT_P2P2}
+ELEMENTS = {"P1": EXM_ELEMENT_P1P1, "DG0": EXM_ELEMENT_DG0DG0, "DG1": EXM_ELEMENT_DG1DG1, "P2": EXM_ELEMENT_P2P2,
+            # the other horizontal x vertical products of {CG1, DG0, DG1}
+            "CG1xDG0": _abi.EXM_ELEMENT_P1DG0, "CG1xDG1": _abi.EXM_ELEMENT_P1DG1,
+            "DG0xCG1": _abi.EXM_ELEMENT_DG0P1, "DG0xDG1": _abi.EXM_ELEMENT_DG0DG1,
+            "DG1xCG1": _abi.EXM_ELEMENT_DG1P1, "DG1xDG0": _abi.EXM_ELEMENT_DG1DG0}
+
+# spaces whose DoFs are shared between cells or layers (outputs must be INC)
+CONTINUOUS = {"P1", "P2", "CG1xDG0", "CG1xDG1", "DG0xCG1", "DG1xCG1"}
 
 
 def load_library():

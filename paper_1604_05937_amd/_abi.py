@@ -27,6 +27,12 @@ EXM_ELEMENT_P1P1 = 1
 EXM_ELEMENT_DG0DG0 = 2
 EXM_ELEMENT_DG1DG1 = 3
 EXM_ELEMENT_P2P2 = 4
+EXM_ELEMENT_P1DG0 = 5
+EXM_ELEMENT_P1DG1 = 6
+EXM_ELEMENT_DG0P1 = 7
+EXM_ELEMENT_DG0DG1 = 8
+EXM_ELEMENT_DG1P1 = 9
+EXM_ELEMENT_DG1DG0 = 10
 
 EXM_READ = 1
 EXM_WRITE = 2

@@ -106,7 +106,15 @@ static bool signature(int32_t kernel, Signature& s)
     }
 }
 
-static bool continuous(int32_t element) { return element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2; }
+// DoFs shared between cells (horizontally) or between layers (vertically)
+static bool continuous(int32_t element)
+{
+    return element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2 || element == EXM_ELEMENT_P1DG0 ||
+           element == EXM_ELEMENT_P1DG1 || element == EXM_ELEMENT_DG0P1 || element == EXM_ELEMENT_DG1P1;
+}
+
+// The tensor-product elements that run the generic DIRECT kernel only
+static bool direct_only(int32_t element) { return element >= EXM_ELEMENT_P1DG0 && element <= EXM_ELEMENT_DG1DG0; }
 
 // Validate and fill everything but the schedule.
 static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const exm_arg* args, LoopLaunch& P)
@@ -233,6 +241,13 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
+    if (direct_only(P.element)) {
+        EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED, "owner-computes is not available on element %d",
+                  P.element);
+        if (d.schedule != EXM_SCHED_DIRECT) d.cols_per_wave = d.waves_per_block = 0;
+        d.schedule = EXM_SCHED_DIRECT;
+        d.tile_cells = d.chunk_layers = 0;
+    }
     if (d.race == EXM_RACE_OWNER) {
         if (!continuous(P.element)) {
             d.race = EXM_RACE_ATOMIC;   // DG columns belong to one cell: nothing to own

@@ -208,6 +208,12 @@ static bool element_delta(int32_t element, int32_t d[6])
     case EXM_ELEMENT_DG0DG0: d[5] = 1; return true;
     case EXM_ELEMENT_DG1DG1: d[5] = 6; return true;
     case EXM_ELEMENT_P2P2: d[0] = d[1] = d[2] = d[3] = 1; return true;
+    case EXM_ELEMENT_P1DG0: d[1] = 1; return true;
+    case EXM_ELEMENT_P1DG1: d[1] = 2; return true;
+    case EXM_ELEMENT_DG0P1: d[4] = 1; return true;
+    case EXM_ELEMENT_DG0DG1: d[5] = 2; return true;
+    case EXM_ELEMENT_DG1P1: d[4] = 3; return true;
+    case EXM_ELEMENT_DG1DG0: d[5] = 3; return true;
     default: return false;
     }
 }

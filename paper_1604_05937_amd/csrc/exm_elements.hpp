@@ -56,6 +56,57 @@ __device__ __forceinline__ void p1_mass(double twoA, const double h[3], const do
     }
 }
 
+// Horizontal P1 mass with the column heights as weight, applied to one value
+// per base vertex (a vertically constant field):
+//     y_a = 2A sum_b T_ab(h) x_b = (2A / 120) ((2 h_a + H) x_a + (h_a + H) X + sum_b h_b x_b),
+// X = sum_b x_b (the T of p1_mass).
+__device__ __forceinline__ void tri_mass(double twoA, const double h[3], const double x[3], double y[3])
+{
+    const double s = twoA * (1.0 / 120.0);
+    const double H = h[0] + h[1] + h[2];
+    const double X = x[0] + x[1] + x[2];
+    const double HX = h[0] * x[0] + h[1] * x[1] + h[2] * x[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) y[a] = s * ((2.0 * h[a] + H) * x[a] + (h[a] + H) * X + HX);
+}
+
+// Mass action of the tensor-product element with NH horizontal nodes (3:
+// linear on the triangle, 1: constant) and NV vertical nodes (2: linear,
+// bottom and top; 1: constant) on one prism: x[alpha][beta] -> y[alpha][beta].
+template <int NH, int NV>
+__device__ __forceinline__ void tp_mass(double twoA, const double h[3], const double x[NH][NV], double y[NH][NV])
+{
+    if constexpr (NH == 3 && NV == 2) {
+        double xb[3], xt[3], yb[3], yt[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xb[a] = x[a][0];
+            xt[a] = x[a][1];
+        }
+        p1_mass(twoA, h, xb, xt, yb, yt);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            y[a][0] = yb[a];
+            y[a][1] = yt[a];
+        }
+    } else if constexpr (NH == 3) {
+        double xv[3], yv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xv[a] = x[a][0];
+        tri_mass(twoA, h, xv, yv);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) y[a][0] = yv[a];
+    } else {
+        const double c = twoA * (h[0] + h[1] + h[2]) * (1.0 / 6.0);
+        if constexpr (NV == 2) {
+            y[0][0] = c * (x[0][0] * (1.0 / 3.0) + x[0][1] * (1.0 / 6.0));
+            y[0][1] = c * (x[0][0] * (1.0 / 6.0) + x[0][1] * (1.0 / 3.0));
+        } else {
+            y[0][0] = c * x[0][0];
+        }
+    }
+}
+
 // DG0 x DG0: integral of the prism = 2A * sum_c h_c / 6 (each lambda_c
 // integrates to 1/6 on the reference triangle).
 __device__ __forceinline__ double dg0_mass(double twoA, const double h[3], double x)

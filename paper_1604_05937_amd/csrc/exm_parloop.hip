@@ -259,6 +259,80 @@ __global__ void __launch_bounds__(256) k_direct_dg0(const ColArgs a)
     }
 }
 
+// Mass action of the other tensor-product spaces (the paper's nine spaces
+// are {CG1, DG0, DG1} horizontally x vertically).  NH horizontal nodes x NV
+// vertical nodes; list position of node (alpha, beta): BMAJOR ? NH beta +
+// alpha : NV alpha + beta (the order Algorithm 1's entity layout gives).
+//   HSH   - horizontal nodes sit on base vertices, shared with other cells:
+//           INC updates go through RACE (atomic, or one colour per launch);
+//   VCONT - the vertical nodes are the bottom and top levels, shared with
+//           the layers below and above: the top contribution of layer l - 1
+//           reaches layer l's lane through a shuffle, so every level gets one
+//           update per cell.
+template <int NH, int NV, bool BMAJOR, bool HSH, bool VCONT, int RACE>
+__global__ void __launch_bounds__(256) k_direct_tp(const ColArgs a)
+{
+    constexpr int K = NH * NV;
+    const Lane L = lane_of(a.seg);
+    int32_t cell;
+    bool valid;
+    if (!direct_cell(a, L, cell, valid)) return;
+    int fb[NH][NV], xb[3];
+#pragma unroll
+    for (int al = 0; al < NH; ++al)
+#pragma unroll
+        for (int be = 0; be < NV; ++be) {
+            const int p = BMAJOR ? NH * be + al : NV * al + be;
+            fb[al][be] = valid ? a.fmap[(int64_t)cell * K + p] : 0;
+        }
+#pragma unroll
+    for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+    const BaseXY g = base_xy(a.X, a.xn, xb, valid);
+    auto update = [&](double* p, double v) {
+        if (a.write)
+            *p = v;
+        else if constexpr (HSH)
+            inc<RACE>(p, v);
+        else
+            *p += v;
+    };
+    double carry[NH];
+#pragma unroll
+    for (int al = 0; al < NH; ++al) carry[al] = 0.0;
+    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+        const int l = l0 + L.lsub;
+        const bool act = valid && l < a.n_layers;
+        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        double twoA, h[3];
+        geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
+        const int64_t lo = (int64_t)l * a.off;
+        double x[NH][NV], y[NH][NV];
+#pragma unroll
+        for (int al = 0; al < NH; ++al)
+#pragma unroll
+            for (int be = 0; be < NV; ++be) x[al][be] = act ? a.in0[fb[al][be] + lo] : 0.0;
+        tp_mass<NH, NV>(twoA, h, x, y);
+        if constexpr (VCONT) {
+#pragma unroll
+            for (int al = 0; al < NH; ++al) {
+                const double below = from_below(y[al][1]);
+                const double val = y[al][0] + (L.lsub == 0 ? carry[al] : below);
+                carry[al] = __shfl(y[al][1], min(L.sub * a.seg + a.seg - 1, 63), 64);
+                if (act) {
+                    update(a.out0 + fb[al][0] + lo, val);
+                    if (l == a.n_layers - 1) update(a.out0 + fb[al][1] + lo, y[al][1]);
+                }
+            }
+        } else {
+            if (act)
+#pragma unroll
+                for (int al = 0; al < NH; ++al)
+#pragma unroll
+                    for (int be = 0; be < NV; ++be) update(a.out0 + fb[al][be] + lo, y[al][be]);
+        }
+    }
+}
+
 // DG1 x DG1 mass action: six consecutive DoFs per prism, L(c)[p] + 6 l; position
 // p is horizontal node p / 2 (at vertex p / 2) and vertical node p % 2.
 __global__ void __launch_bounds__(256) k_direct_dg1(const ColArgs a)
@@ -623,6 +697,29 @@ int32_t launch_column_loop(const LoopLaunch& P, hipStream_t stream)
     case EXM_ELEMENT_DG1DG1:
         if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on DG1xDG1", P.kernel);
         EXM_LAUNCH(k_direct_dg1);
+        break;
+    case EXM_ELEMENT_P1DG0:
+    case EXM_ELEMENT_P1DG1:
+    case EXM_ELEMENT_DG0P1:
+    case EXM_ELEMENT_DG0DG1:
+    case EXM_ELEMENT_DG1P1:
+    case EXM_ELEMENT_DG1DG0:
+        if (P.kernel != EXM_K_MASS)
+            return fail(EXM_EUNSUPPORTED, "kernel %d not available on element %d", P.kernel, P.element);
+        switch (P.element) {
+        case EXM_ELEMENT_P1DG0:   // vertex columns, one DoF per layer
+            if (atomic) EXM_LAUNCH((k_direct_tp<3, 1, false, true, false, EXM_RACE_ATOMIC>));
+            else EXM_LAUNCH((k_direct_tp<3, 1, false, true, false, EXM_RACE_COLOUR>));
+            break;
+        case EXM_ELEMENT_P1DG1:   // vertex columns, two DoFs per layer
+            if (atomic) EXM_LAUNCH((k_direct_tp<3, 2, false, true, false, EXM_RACE_ATOMIC>));
+            else EXM_LAUNCH((k_direct_tp<3, 2, false, true, false, EXM_RACE_COLOUR>));
+            break;
+        case EXM_ELEMENT_DG0P1: EXM_LAUNCH((k_direct_tp<1, 2, false, false, true, EXM_RACE_ATOMIC>)); break;
+        case EXM_ELEMENT_DG0DG1: EXM_LAUNCH((k_direct_tp<1, 2, false, false, false, EXM_RACE_ATOMIC>)); break;
+        case EXM_ELEMENT_DG1P1: EXM_LAUNCH((k_direct_tp<3, 2, true, false, true, EXM_RACE_ATOMIC>)); break;
+        default: EXM_LAUNCH((k_direct_tp<3, 1, false, false, false, EXM_RACE_ATOMIC>)); break;
+        }
         break;
     default: return fail(EXM_EUNSUPPORTED, "element %d has no kernels", P.element);
     }

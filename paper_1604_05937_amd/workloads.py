@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import (EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_MASS, EXM_READ, EXM_WRITE, Mesh, Space,
+from . import (CONTINUOUS, EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_MASS, EXM_READ, EXM_WRITE, Mesh, Space,
                coordinate_field, par_loop)
 from . import meshgen
 
@@ -75,9 +75,12 @@ def device_values(n: int, seed: int):
     return torch.from_numpy(meshgen.uniform_values(n, seed=seed)).to("cuda")
 
 
+ARITY = {"P1": 6, "DG0": 1, "DG1": 6, "P2": 18, "CG1xDG0": 3, "CG1xDG1": 6, "DG0xCG1": 2, "DG0xDG1": 2,
+         "DG1xCG1": 6, "DG1xDG0": 3}
+
+
 def map_bytes(e: Extruded, name: str) -> int:
-    k = {"P1": 6, "DG0": 1, "DG1": 6, "P2": 18}[name]
-    lists = 4 * e.base.n_cells * k
+    lists = 4 * e.base.n_cells * ARITY[name]
     if name != "P1":
         lists += 4 * e.base.n_cells * 6   # the coordinate list
     return lists
@@ -91,7 +94,7 @@ def coord_bytes(e: Extruded) -> int:
 def mass_bytes(e: Extruded, name: str) -> dict:
     """Byte counts of one y = M x / residual assembly on space `name`."""
     n = e.space(name).n_dofs
-    inc = name in ("P1", "P2")
+    inc = name in CONTINUOUS
     alg = 8 * n + 8 * n * (2 if inc else 1) + coord_bytes(e) + map_bytes(e, name)
     valuable = 8 * n * 2 + 24 * e.Vx.n_dofs
     return dict(algorithmic=alg, valuable=valuable, n_dofs=n)
@@ -107,7 +110,7 @@ def cubic_bytes(e: Extruded, fused: bool) -> dict:
 
 
 def mass_args(e: Extruded, name: str, x, y):
-    acc = EXM_INC if name in ("P1", "P2") else EXM_WRITE
+    acc = EXM_INC if name in CONTINUOUS else EXM_WRITE
     V = e.space(name)
     return [(x, V, EXM_READ), (y, V, acc)]
 

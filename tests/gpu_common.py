@@ -50,7 +50,7 @@ class Case:
         return t.cpu().numpy()
 
     def out_access(self):
-        return exm.EXM_INC if self.space_name in ("P1", "P2") else exm.EXM_WRITE
+        return exm.EXM_INC if self.space_name in exm.CONTINUOUS else exm.EXM_WRITE
 
     def mass(self, x: np.ndarray, **opts) -> np.ndarray:
         xd = self.dev(x)

@@ -16,7 +16,10 @@ pytestmark = pytest.mark.gpu
 SHAPES = [(16, 10), (5, 1), (7, 63), (6, 65), (3, 130)]
 
 
-@pytest.mark.parametrize("space", ["P1", "DG0", "DG1", "P2"])
+ALL_SPACES = ["P1", "DG0", "DG1", "P2", "CG1xDG0", "CG1xDG1", "DG0xCG1", "DG0xDG1", "DG1xCG1", "DG1xDG0"]
+
+
+@pytest.mark.parametrize("space", ALL_SPACES)
 @pytest.mark.parametrize("n,lam", SHAPES)
 @pytest.mark.parametrize("order", ["rcm", "random"])
 def test_numbering_bit_exact(space, n, lam, order):
@@ -41,7 +44,7 @@ SCHEDULES = [exm.EXM_SCHED_DIRECT, exm.EXM_SCHED_TILED, exm.EXM_SCHED_STAGED, ex
 RACES = [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR]
 
 
-@pytest.mark.parametrize("space", ["P1", "DG0", "DG1", "P2"])
+@pytest.mark.parametrize("space", ALL_SPACES)
 @pytest.mark.parametrize("n,lam", SHAPES)
 @pytest.mark.parametrize("race", RACES)
 @pytest.mark.parametrize("schedule", SCHEDULES)
@@ -158,6 +161,24 @@ def test_owner_computes_matches_oracle(n, lam):
                                                                  (c.V.zeros(), c.V, exm.EXM_INC)],
                               race=exm.EXM_RACE_OWNER)
     assert cfg["schedule"] == exm.EXM_SCHED_PIPELINED and cfg["race"] == exm.EXM_RACE_OWNER
+
+
+@pytest.mark.parametrize("space", ["CG1xDG0", "CG1xDG1", "DG0xCG1", "DG1xCG1"])
+def test_shared_spaces_refuse_write(space):
+    c = Case(meshgen.tri_square(4), 3, space, with_oracle=False)
+    x = c.dev(meshgen.uniform_values(c.n, seed=1))
+    with pytest.raises(exm.ExmError) as e:
+        exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(x, c.V, exm.EXM_READ), (c.V.zeros(), c.V, exm.EXM_WRITE)])
+    assert e.value.status == exm._abi.EXM_EINVAL
+
+
+@pytest.mark.parametrize("space", ["CG1xDG0", "DG1xCG1"])
+def test_tensor_spaces_direct_shapes(space):
+    c = Case(meshgen.tri_square(9), 23, space, terrain=0.3)
+    x = meshgen.uniform_values(c.n, seed=12)
+    for cpw in (1, 2, 3, 5, 16):
+        got = c.mass(x, schedule=exm.EXM_SCHED_DIRECT, cols_per_wave=cpw)
+        assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"{space} cpw={cpw}")
 
 
 def test_owner_computes_unsupported_on_p2():

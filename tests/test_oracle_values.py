@@ -18,7 +18,8 @@ def _rel_close(got, exact, tol=1e-13):
     assert err <= tol, err
 
 
-@pytest.mark.parametrize("space", ["P1", "DG0", "DG1", "P2", ("CG1", "DG0"), ("DG0", "CG1"), ("DG1", "CG1"), ("CG1", "DG1")])
+@pytest.mark.parametrize("space", ["P1", "DG0", "DG1", "P2", ("CG1", "DG0"), ("DG0", "CG1"), ("DG1", "CG1"), ("CG1", "DG1"),
+                                   ("DG0", "DG1"), ("DG1", "DG0")])
 @pytest.mark.parametrize("terrain", [0.0, 0.3])
 def test_mass_matches_exact_rationals(space, terrain):
     mesh = meshgen.tri_square(3, jitter=0.2)
@@ -126,7 +127,7 @@ def test_dg0_closed_form():
             assert abs(b[dof] - f[dof] * A * hts.mean()) < 1e-15
 
 
-@pytest.mark.parametrize("space", ["P1", "DG1", "P2"])
+@pytest.mark.parametrize("space", ["P1", "DG1", "P2", "CG1xDG0", "CG1xDG1", "DG0xCG1", "DG0xDG1", "DG1xCG1", "DG1xDG0"])
 def test_mass_symmetric_and_volume(space):
     mesh = meshgen.tri_square(4)
     lam = 3
