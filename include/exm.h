@@ -225,8 +225,8 @@ typedef struct {
     int32_t waves_per_block;   /* DIRECT: 1..4; TILED: 1..8; STAGED, PIPELINED: 4 (0 = choose) */
     int32_t tile_cells;        /* TILED, STAGED, PIPELINED: 8..1024 target cells per tile */
                                /* (0 = choose)                                           */
-    int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64; PIPELINED, CHUNKED: 8, 16 or  */
-                               /* 32 layers                                              */
+    int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64; PIPELINED: 8, 12, 16, 20, 24  */
+                               /* or 32 on P1xP1, 8, 16 or 32 on DG; CHUNKED: 8, 16 or 32 */
                                /* per chunk (0 = choose)                                 */
 } exm_loop_opts;
 

@@ -223,9 +223,9 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         EXM_CHECK(opts->tile_cells == 0 || (opts->tile_cells >= 8 && opts->tile_cells <= 1024), EXM_ERANGE,
                   "tile_cells = %d outside [8, 1024]", opts->tile_cells);
         EXM_CHECK(opts->chunk_layers == 0 || opts->chunk_layers == 8 || opts->chunk_layers == 12 ||
-                      opts->chunk_layers == 16 || opts->chunk_layers == 24 || opts->chunk_layers == 32 ||
-                      opts->chunk_layers == 64,
-                  EXM_ERANGE, "chunk_layers = %d: use 8, 12, 16, 24, 32 or 64 (0 = choose)", opts->chunk_layers);
+                      opts->chunk_layers == 16 || opts->chunk_layers == 20 || opts->chunk_layers == 24 ||
+                      opts->chunk_layers == 32 || opts->chunk_layers == 64,
+                  EXM_ERANGE, "chunk_layers = %d: use 8, 12, 16, 20, 24, 32 or 64 (0 = choose)", opts->chunk_layers);
         if (opts->race) d.race = opts->race;
         if (opts->schedule) {
             if (opts->schedule != d.schedule) {
@@ -292,7 +292,7 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.cols_per_wave = 0;
         if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 ? 16 : 8;
         EXM_CHECK(pipe_chunk_ok(P.element, d.chunk_layers), EXM_ERANGE,
-                  "PIPELINED: chunk_layers = %d, use 8, 12, 16, 24 or 32 on P1xP1 and 8, 16 or 32 on DG spaces",
+                  "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1 and 8, 16 or 32 on DG spaces",
                   d.chunk_layers);
         if (!d.tile_cells) d.tile_cells = std::min(64, pipe_max_tile_cells(P.element, d.chunk_layers));
         EXM_CHECK(d.tile_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
@@ -601,8 +601,8 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                     if (tc <= staged_max_tile_cells(S))
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
         if (pipe_supported(P.kernel, P.element))
-            for (int32_t tc : {32, 64, 128, 256})
-                for (int32_t S : {8, 12, 16, 24, 32})
+            for (int32_t tc : {32, 48, 64, 96, 128, 256})
+                for (int32_t S : {8, 12, 16, 20, 24, 32})
                     if (pipe_chunk_ok(P.element, S) && tc <= pipe_max_tile_cells(P.element, S)) {
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
                         if (cg && r == 0) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
@@ -695,7 +695,7 @@ int32_t exm_autotune_load(const char* path)
                       o.cols_per_wave <= 16 && o.waves_per_block >= 1 && o.waves_per_block <= 16 &&
                       o.tile_cells >= 0 && o.tile_cells <= 1024 &&
                       (o.chunk_layers == 0 || o.chunk_layers == 8 || o.chunk_layers == 12 || o.chunk_layers == 16 ||
-                       o.chunk_layers == 24 || o.chunk_layers == 32 || o.chunk_layers == 64),
+                       o.chunk_layers == 20 || o.chunk_layers == 24 || o.chunk_layers == 32 || o.chunk_layers == 64),
                   EXM_ERANGE, "%s:%d: values out of range", path, ln);
         table[TuneKey(k, e, l, b)] = o;
     }

@@ -351,12 +351,12 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
 // and stores its results while the next chunk computes.  LDS: Z[2] of
 // vstride * (S + 2) doubles, then x, y (doubles) and the column start (int)
 // per tile vertex.
-template <int NDOF, int S, int NP>
-__global__ void __launch_bounds__(kThreads, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
+template <int NDOF, int S, int NP, int NT>
+__global__ void __launch_bounds__(NT, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
 {
     using C = Chunk<S>;
     constexpr int P2 = C::P2, PP = C::PP, LS = C::LS;
-    constexpr int CPP = kThreads >> LS;   // one layer per thread
+    constexpr int CPP = NT >> LS;   // one layer per thread
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(kThreads, NDOF == 1 ? 8 : 4) k_pipe_dg(const C
     double* const out = a.out0;
     const int lam = a.n_layers;
 
-    for (int v = tid; v < nv; v += kThreads) {
+    for (int v = tid; v < nv; v += NT) {
         const int32_t xs = t.xstart[vid(t.verts[vb0 + v])];
         Txst[v] = xs;
         Tx[v] = a.X[xs];
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(kThreads, NDOF == 1 ? 8 : 4) k_pipe_dg(const C
         const int l0 = k * S;
         const int nl = min(S, lam - l0);
         const int b = k & 1;
-        for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
+        for (int e0 = 0; e0 < nv * PP; e0 += NT) {
             const int e = e0 + tid;
             const int v = e / PP, w = e - (e / PP) * PP;
             if (v >= nv) continue;
@@ -743,14 +743,13 @@ bool pipe_supported(int32_t kernel, int32_t element)
 
 int32_t pipe_max_tile_cells(int32_t element, int32_t S)
 {
-    if (element == EXM_ELEMENT_DG0DG0) return 2 * kThreads / S;
-    if (element == EXM_ELEMENT_DG1DG1) return 2 * kThreads / S;
+    if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1) return 2 * 512 / S;
     return kPasses * (kThreads / (S / kLayers));
 }
 
 bool pipe_chunk_ok(int32_t element, int32_t S)
 {
-    if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 24 || S == 32;
+    if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 20 || S == 24 || S == 32;
     return S == 8 || S == 16 || S == 32;
 }
 
@@ -773,11 +772,19 @@ static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t,
                            hipStream_t s)
 {
     const dim3 grid((unsigned)t.tile_count), block(kThreads);
-    (void)cstride;
-    if (element == EXM_ELEMENT_DG0DG0)
-        hipLaunchKernelGGL((k_pipe_dg<1, S, 2>), grid, block, lds, s, a, t);
-    else
-        hipLaunchKernelGGL((k_pipe_dg<6, S, 2>), grid, block, lds, s, a, t);
+    // tiles beyond two cells per thread of a 256-thread workgroup take 512 threads
+    const bool wide = cstride > 2 * kThreads / S;
+    if (element == EXM_ELEMENT_DG0DG0) {
+        if (wide)
+            hipLaunchKernelGGL((k_pipe_dg<1, S, 2, 512>), grid, dim3(512), lds, s, a, t);
+        else
+            hipLaunchKernelGGL((k_pipe_dg<1, S, 2, 256>), grid, block, lds, s, a, t);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((k_pipe_dg<6, S, 2, 512>), grid, dim3(512), lds, s, a, t);
+        else
+            hipLaunchKernelGGL((k_pipe_dg<6, S, 2, 256>), grid, block, lds, s, a, t);
+    }
 }
 
 int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t cstride, int32_t S, size_t lds,
@@ -803,9 +810,10 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
     case 8: launch_pipe_s<8>(P.race, a, t, lds, s); break;
     case 12: launch_pipe_s<12>(P.race, a, t, lds, s); break;
     case 16: launch_pipe_s<16>(P.race, a, t, lds, s); break;
+    case 20: launch_pipe_s<20>(P.race, a, t, lds, s); break;
     case 24: launch_pipe_s<24>(P.race, a, t, lds, s); break;
     case 32: launch_pipe_s<32>(P.race, a, t, lds, s); break;
-    default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 12, 16, 24 or 32 on P1xP1", S);
+    default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 12, 16, 20, 24 or 32 on P1xP1", S);
     }
     EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;

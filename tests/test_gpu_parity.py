@@ -110,7 +110,7 @@ def test_mass_staged_shapes(space, tile, chunk, race):
 @pytest.mark.parametrize("schedule", [exm.EXM_SCHED_PIPELINED, exm.EXM_SCHED_CHUNKED])
 @pytest.mark.parametrize("space", ["P1", "DG0", "DG1"])
 @pytest.mark.parametrize("tile", [8, 29, 64, 128])
-@pytest.mark.parametrize("chunk", [8, 12, 16, 24, 32])
+@pytest.mark.parametrize("chunk", [8, 12, 16, 20, 24, 32])
 @pytest.mark.parametrize("race", RACES + [exm.EXM_RACE_OWNER])
 def test_mass_pipelined_shapes(schedule, space, tile, chunk, race):
     say(f"pipelined shape {space} schedule={schedule} tile={tile} chunk={chunk} race={race}")
@@ -127,7 +127,7 @@ def test_mass_pipelined_shapes(schedule, space, tile, chunk, race):
             # tiles too large for the chunk length, and chunk lengths a schedule or
             # space does not take, are refused before any launch
             big = e.status == exm._abi.EXM_EUNSUPPORTED and ("PIPELINED" in str(e) or "CHUNKED" in str(e))
-            odd = e.status == exm._abi.EXM_ERANGE and chunk in (12, 24) and (space != "P1" or schedule != 4)
+            odd = e.status == exm._abi.EXM_ERANGE and chunk in (12, 20, 24) and (space != "P1" or schedule != 4)
             assert big or odd, str(e)
             return
         if space == "P1":
