@@ -344,6 +344,12 @@ def sweep(torch, exm):
         point(512, lam, "random")
 
 
+def direct_shapes(exm, name):
+    races = [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR] if name in exm.CONTINUOUS else [exm.EXM_RACE_ATOMIC]
+    return [dict(schedule=exm.EXM_SCHED_DIRECT, race=r, cols_per_wave=c, waves_per_block=w)
+            for r in races for c, w in ((1, 4), (2, 4), (3, 4), (4, 4), (1, 8), (2, 8), (4, 8))]
+
+
 def secondary(torch, exm, W, meshgen):
     out = {}
     # the RHS on the paper's nine spaces ({CG1, DG0, DG1} horizontally x vertically), 256 x 256 x 64
@@ -362,6 +368,30 @@ def secondary(torch, exm, W, meshgen):
     out["rhs_nine_spaces_256x256x64"] = nine
     log("nine spaces: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in nine.items()))
     del e9
+    # columns of different heights: 512 x 512 x 100 with the bottom of every
+    # column following a smooth bump (meshgen.layer_ranges, "bathymetry"),
+    # beside the DIRECT schedule on the uniform mesh of the same sizes
+    var = {}
+    for kind in (None, "bathymetry"):
+        ev = W.extruded(512, 100, layer_kind=kind)
+        for name in ("P1", "DG0"):
+            V = ev.space(name)
+            x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
+            y = V.zeros()
+            if kind:   # the tuner tries DIRECT shapes only on such a mesh
+                cfg = exm.autotune(exm.EXM_K_MASS, ev.mesh, ev.X, ev.Vx, W.mass_args(ev, name, x, y))
+                t, _ = timed(torch, lambda: W.run_mass(ev, name, x, y, **cfg), 10)
+            else:      # the same DIRECT shapes on the uniform mesh
+                t, cfg = min(((timed(torch, lambda: W.run_mass(ev, name, x, y, **c), 10)[0], c)
+                              for c in direct_shapes(exm, name)), key=lambda tc: tc[0])
+            b = W.mass_bytes(ev, name)
+            var[f"{name}_{kind or 'uniform'}"] = {"prisms": ev.n_prisms, "ms": round(t, 4),
+                                                  "gbs": round(b["algorithmic"] / t / 1e6, 1),
+                                                  "prisms_per_s": round(ev.n_prisms / t * 1e3), "launch": cfg}
+            del x, y
+        del ev
+    out["rhs_direct_variable_layers_512x512x100"] = var
+    log("variable layers: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in var.items()))
     # higher-order mass actions: 256 x 256 x 64, DG1 x DG1 and P2 x P2
     e3 = W.extruded(256, 64)
     for name in ("DG1", "P2"):

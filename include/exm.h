@@ -79,6 +79,29 @@ int32_t exm_mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
                         int32_t n_layers, exm_mesh** out);
 void exm_mesh_destroy(exm_mesh* mesh);
 
+/* Extruded mesh with a layer range per cell column.  The constant layer count
+ * of the paper's exposition is a simplification the method does not need
+ * (Section 3.1, footnote; Section 5).
+ * layers: host [n_cells * 2]; cell c carries the prisms of layers
+ *         layers[2c] .. layers[2c+1] - 1, 0 <= layers[2c] < layers[2c+1] <= n_layers.
+ * The column of a vertex or edge spans the union of the ranges of the cells
+ * around it (the levels lo .. hi of exm_mesh_entity_layers); Algorithm 1 then
+ * numbers every entity over its own range, so column starts become a prefix
+ * sum, and a cell's explicit list is the stencil of its bottom prism, so that
+ * L(c) + l * offset addresses layer layers[2c] + l of its column.  Loops on
+ * such a mesh run the DIRECT schedule whatever the options ask, and refuse
+ * EXM_RACE_OWNER (EXM_EUNSUPPORTED); batches take uniform meshes only.
+ * Other arguments and errors as exm_mesh_create; a vertex that belongs to no
+ * cell is rejected (EXM_EINVAL). */
+int32_t exm_mesh_create_var(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
+                            const int32_t* cell_vertex, const int32_t* cell_edge,
+                            int32_t n_layers, const int32_t* layers, exm_mesh** out);
+
+/* Layer range [lo, hi) of the column of every base entity of dimension d1
+ * (0 and n_layers for a uniform mesh).  lo, hi: host [N_d1], either may be
+ * NULL. */
+int32_t exm_mesh_entity_layers(const exm_mesh* mesh, int32_t d1, int32_t* lo, int32_t* hi);
+
 /* ------------------------------------------------------------------------
  * Function space: the vertical-innermost numbering of Algorithm 1 and the
  * explicit lists and offsets of Algorithms 2-3.

@@ -72,8 +72,12 @@ def _lib():
     lib.oracle_alg1_number.argtypes = [P, ctypes.c_int32, P, P, P, P]
     lib.oracle_stencil.restype = ctypes.c_int32
     lib.oracle_stencil.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, P, P]
+    lib.oracle_alg1_number_var.restype = ctypes.c_int64
+    lib.oracle_alg1_number_var.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P]
+    lib.oracle_stencil_var.restype = ctypes.c_int32
+    lib.oracle_stencil_var.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P, P]
     lib.oracle_par_loop.restype = None
-    lib.oracle_par_loop.argtypes = [ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int32,
+    lib.oracle_par_loop.argtypes = [ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int32, P,
                                     P, P, P, ctypes.c_int32, P, P,
                                     P, P, P, P, P, P, ctypes.c_int32,
                                     ctypes.c_int32, P, P, P, P]
@@ -237,9 +241,12 @@ class Numbering:
     delta: np.ndarray           # [3, 2]
     n_dofs: int
     first: list                 # first[d1]: [N_d1, lam+1, 2] int64 (-1 = no entity)
-    lmap: np.ndarray            # [N2, k] int64 explicit list at layer 0
+    lmap: np.ndarray            # [N2, k] int64 explicit list at the column's bottom layer
     offsets: np.ndarray         # [k] int32
     entity_dim: np.ndarray      # [k] int32
+    lo: list = None             # variable layers: first layer of every entity column, per dimension
+    hi: list = None             # ... and one past its last layer
+    cell_lam: np.ndarray = None  # variable layers: layers of every cell column (int32)
 
     @property
     def k(self) -> int:
@@ -247,11 +254,42 @@ class Numbering:
 
     def column_starts(self, d1: int) -> np.ndarray:
         """First DoF of the column of every base entity of dimension d1."""
-        return self.first[d1][:, 0, 0].copy()
+        if self.lo is None:
+            return self.first[d1][:, 0, 0].copy()
+        idx = np.arange(self.first[d1].shape[0])
+        return self.first[d1][idx, self.lo[d1], 0].copy()
 
 
-def number(counts, n_layers: int, delta, cell_vertex, cell_edge=None) -> Numbering:
-    """Algorithm 1 + the explicit lists + Algorithm 2 for one function space."""
+def entity_layers(counts, n_layers: int, cell_vertex, cell_edge, layers):
+    """Layer ranges of every entity column when each cell c carries the prisms
+    of layers[c, 0] .. layers[c, 1] - 1 (reading: a vertex or edge column spans
+    the union of the ranges of the cells around it)."""
+    layers = np.asarray(layers, dtype=np.int32).reshape(-1, 2)
+    n0, n1, n2 = (int(x) for x in counts)
+    assert layers.shape[0] == n2
+    assert np.all(layers[:, 0] >= 0) and np.all(layers[:, 0] < layers[:, 1]) and np.all(layers[:, 1] <= n_layers)
+    lo = [np.full(n0, n_layers, np.int32), np.full(n1, n_layers, np.int32), layers[:, 0].copy()]
+    hi = [np.zeros(n0, np.int32), np.zeros(n1, np.int32), layers[:, 1].copy()]
+    for c in range(n2):
+        for a in range(3):
+            v = cell_vertex[c, a]
+            lo[0][v] = min(lo[0][v], layers[c, 0])
+            hi[0][v] = max(hi[0][v], layers[c, 1])
+            if cell_edge is not None:
+                e = cell_edge[c, a]
+                lo[1][e] = min(lo[1][e], layers[c, 0])
+                hi[1][e] = max(hi[1][e], layers[c, 1])
+    if cell_edge is None:
+        lo[1][:] = 0
+        hi[1][:] = n_layers
+    return lo, hi
+
+
+def number(counts, n_layers: int, delta, cell_vertex, cell_edge=None, layers=None) -> Numbering:
+    """Algorithm 1 + the explicit lists + Algorithm 2 for one function space.
+
+    layers: optional [N2, 2] layer range per cell (variable layers); n_layers
+    is then the largest layer count."""
     lib = _lib()
     counts = np.ascontiguousarray(counts, dtype=np.int32)
     delta = np.ascontiguousarray(np.asarray(delta, dtype=np.int32).reshape(3, 2))
@@ -274,7 +312,22 @@ def number(counts, n_layers: int, delta, cell_vertex, cell_edge=None) -> Numberi
         ce = None
     lib.oracle_stencil(int(counts[2]), n_layers, _ptr(delta), _ptr(cv), _ptr(ce),
                        _ptr(first[0]), _ptr(first[1]), _ptr(first[2]), _ptr(lmap), _ptr(offsets), _ptr(edim))
-    return Numbering(tuple(int(x) for x in counts), n_layers, delta, int(n_dofs), first, lmap, offsets, edim)
+    if layers is None:
+        return Numbering(tuple(int(x) for x in counts), n_layers, delta, int(n_dofs), first, lmap, offsets, edim)
+    # variable layers: number again over every entity's own range
+    lo, hi = entity_layers(counts, n_layers, np.asarray(cell_vertex), None if cell_edge is None else
+                           np.asarray(cell_edge), layers)
+    for d in range(3):
+        if first[d] is not None:
+            first[d][:] = -1
+    n_dofs = lib.oracle_alg1_number_var(_ptr(counts), n_layers, _ptr(delta), _ptr(lo[0]), _ptr(hi[0]), _ptr(lo[1]),
+                                        _ptr(hi[1]), _ptr(lo[2]), _ptr(hi[2]),
+                                        _ptr(first[0]), _ptr(first[1]), _ptr(first[2]))
+    cell_lo = np.ascontiguousarray(lo[2])
+    lib.oracle_stencil_var(int(counts[2]), n_layers, _ptr(delta), _ptr(cv), _ptr(ce), _ptr(cell_lo),
+                           _ptr(first[0]), _ptr(first[1]), _ptr(first[2]), _ptr(lmap))
+    return Numbering(tuple(int(x) for x in counts), n_layers, delta, int(n_dofs), first, lmap, offsets, edim,
+                     lo, hi, np.ascontiguousarray(hi[2] - lo[2], dtype=np.int32))
 
 
 def coordinate_field(num_x: Numbering, vertex_coords: np.ndarray) -> np.ndarray:
@@ -282,8 +335,9 @@ def coordinate_field(num_x: Numbering, vertex_coords: np.ndarray) -> np.ndarray:
     coordinate space: X[dof(v, l), :]."""
     nv, nl, _ = vertex_coords.shape
     X = np.zeros((num_x.n_dofs, 3))
-    dof = num_x.first[0][:, :, 0]          # [N0, lam+1]
-    X[dof.ravel()] = vertex_coords.reshape(-1, 3)
+    dof = num_x.first[0][:, :, 0]          # [N0, lam+1]; -1 at levels outside a column (variable layers)
+    used = dof.ravel() >= 0
+    X[dof.ravel()[used]] = vertex_coords.reshape(-1, 3)[used]
     return X
 
 
@@ -313,7 +367,7 @@ def par_loop(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.
     else:
         cells = np.ascontiguousarray(cells, dtype=np.int64)
         n_iter, cptr = cells.size, _ptr(cells)
-    lib.oracle_par_loop(form, n_iter, cptr, num_v.n_layers,
+    lib.oracle_par_loop(form, n_iter, cptr, num_v.n_layers, _ptr(num_v.cell_lam),
                         _ptr(num_x.lmap), _ptr(num_x.offsets), _ptr(Xc),
                         num_v.k, _ptr(num_v.lmap), _ptr(num_v.offsets),
                         _ptr(ins[0]), _ptr(ins[1]), _ptr(ins[2]),
@@ -347,13 +401,13 @@ def is_continuous(space: tuple) -> bool:
 class Problem:
     """A base mesh extruded to n_layers with its coordinate field and one space."""
 
-    def __init__(self, mesh, n_layers: int, space: str | tuple, vertex_coords: np.ndarray):
+    def __init__(self, mesh, n_layers: int, space: str | tuple, vertex_coords: np.ndarray, layers=None):
         self.mesh = mesh
         self.n_layers = n_layers
         self.space = SPACES.get(space, space) if isinstance(space, str) else space
         counts = mesh.counts
-        self.num_x = number(counts, n_layers, delta_table("CG1", "CG1"), mesh.cell_vertex, mesh.cell_edge)
-        self.num_v = number(counts, n_layers, delta_table(*self.space), mesh.cell_vertex, mesh.cell_edge)
+        self.num_x = number(counts, n_layers, delta_table("CG1", "CG1"), mesh.cell_vertex, mesh.cell_edge, layers)
+        self.num_v = number(counts, n_layers, delta_table(*self.space), mesh.cell_vertex, mesh.cell_edge, layers)
         self.X = coordinate_field(self.num_x, vertex_coords)
 
     @property

@@ -61,6 +61,75 @@ int64_t oracle_alg1_number(const int32_t counts[3], int32_t lam, const int32_t d
 }
 
 /*
+ * Algorithm 1 with a layer range per entity column (the constant layer count
+ * of the paper's exposition relaxed, Section 3.1): entity (d1, i) spans the
+ * layers lo[d1][i] .. hi[d1][i] - 1, i.e. the levels lo .. hi.  The counter
+ * visits, for each entity, its layers in order -- horizontal entity at the
+ * layer's bottom level, then the vertical entity -- and finally its top level.
+ * first_d[d1][(i*(lam_max+1) + l)*2 + d2] as in oracle_alg1_number with the
+ * absolute level l; -1 outside the entity's range.
+ */
+int64_t oracle_alg1_number_var(const int32_t counts[3], int32_t lam_max, const int32_t delta[6],
+                               const int32_t* lo0, const int32_t* hi0, const int32_t* lo1, const int32_t* hi1,
+                               const int32_t* lo2, const int32_t* hi2,
+                               int64_t* first0, int64_t* first1, int64_t* first2)
+{
+    int64_t* first[3] = {first0, first1, first2};
+    const int32_t* lo[3] = {lo0, lo1, lo2};
+    const int32_t* hi[3] = {hi0, hi1, hi2};
+    int64_t c = 0;
+    for (int d1 = 0; d1 < 3; ++d1) {
+        for (int64_t i = 0; i < counts[d1]; ++i) {
+            int64_t* f = first[d1] ? first[d1] + i * (int64_t)(lam_max + 1) * 2 : NULL;
+            const int32_t a = lo[d1] ? lo[d1][i] : 0, b = hi[d1] ? hi[d1][i] : lam_max;
+            for (int32_t l = a; l < b; ++l) {
+                for (int d2 = 0; d2 < 2; ++d2) {
+                    if (f) f[l * 2 + d2] = c;
+                    c += DELTA(delta, d1, d2);
+                }
+            }
+            if (f) f[b * 2 + 0] = c;
+            c += DELTA(delta, d1, 0);
+        }
+    }
+    return c;
+}
+
+/* The explicit lists for a layer range per cell: L(c) is the stencil of the
+ * cell's bottom prism (layer cell_lo[c]); the offsets are those of
+ * oracle_stencil. */
+int32_t oracle_stencil_var(int32_t n_cells, int32_t lam_max, const int32_t delta[6], const int32_t* cell_vertex,
+                           const int32_t* cell_edge, const int32_t* cell_lo,
+                           const int64_t* first0, const int64_t* first1, const int64_t* first2, int64_t* lmap)
+{
+    const int64_t* first[3] = {first0, first1, first2};
+    int32_t k = 0;
+    for (int e = 0; e < 7; ++e) {
+        int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+        k += 2 * DELTA(delta, d, 0) + DELTA(delta, d, 1);
+    }
+    for (int64_t c = 0; c < n_cells; ++c) {
+        int64_t* row = lmap + c * k;
+        int32_t p = 0;
+        const int64_t b = cell_lo[c];
+        for (int e = 0; e < 7; ++e) {
+            int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+            int64_t i;
+            if (d == 0) i = cell_vertex[c * 3 + e];
+            else if (d == 1) i = cell_edge ? cell_edge[c * 3 + (e - 3)] : -1;
+            else i = c;
+            int nh = DELTA(delta, d, 0), nv = DELTA(delta, d, 1);
+            if (nh + nv == 0) continue;
+            const int64_t* f = first[d] + (i * (int64_t)(lam_max + 1) + b) * 2;
+            for (int j = 0; j < nh; ++j) row[p++] = f[0 * 2 + 0] + j;   /* bottom level of the cell's first layer */
+            for (int j = 0; j < nh; ++j) row[p++] = f[1 * 2 + 0] + j;   /* its top level */
+            for (int j = 0; j < nv; ++j) row[p++] = f[0 * 2 + 1] + j;   /* its vertical entity */
+        }
+    }
+    return k;
+}
+
+/*
  * The stencil of a prism (the explicit list L of Section 3.3): the DoFs of
  * all entities in the closure of base cell c extruded over one layer.  The
  * closure entities are taken in the order vertex 0, 1, 2 (cell_vertex order),
@@ -151,9 +220,11 @@ static double det3(const double J[3][3])
  * and |det J| of the full 3x3 Jacobian at every point.
  *
  * cells: the base cells to visit (NULL: all 0..n_iter-1).
+ * cell_lam: layers of each cell's column (NULL: lam for every column); the
+ * lists then hold the DoFs of the column's bottom prism.
  * write_mode: 1 = WRITE (assign), 0 = INC (add) for the outputs.
  */
-void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t lam,
+void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t lam, const int32_t* cell_lam,
                      const int64_t* mapx, const int32_t* offx, const double* X,
                      int32_t k, const int64_t* mapv, const int32_t* offv,
                      const double* in0, const double* in1, const double* in2,
@@ -171,7 +242,8 @@ void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t
         /* (dof_0, ..., dof_{k-1}) <- L(c), for both spaces */
         for (int p = 0; p < 6; ++p) dx[p] = mapx[c * 6 + p];
         for (int p = 0; p < k; ++p) dv[p] = mapv[c * k + p];
-        for (int32_t l = 0; l < lam; ++l) {
+        const int32_t nl = cell_lam ? cell_lam[c] : lam;   /* layers of this column */
+        for (int32_t l = 0; l < nl; ++l) {
             /* S(f(dof_0), ..., f(dof_{k-1})): the element kernel */
             for (int p = 0; p < k; ++p) e0[p] = e1[p] = e2[p] = 0.0;
             for (int q = 0; q < nq; ++q) {

@@ -63,20 +63,33 @@ def _i32(a) -> np.ndarray:
 
 class Mesh:
     """An extruded mesh: triangular base mesh (cell->vertex, cell->edge) and
-    a layer count.  Wraps exm_mesh."""
+    a layer count, or a layer range per cell column (``layers`` [N2, 2]: the
+    prisms of layers layers[c, 0] .. layers[c, 1] - 1).  Wraps exm_mesh."""
 
-    def __init__(self, base, n_layers: int):
+    def __init__(self, base, n_layers: int, layers=None):
         _abi.load()
         self.base = base
         self.n_layers = int(n_layers)
+        self.layers = None if layers is None else _i32(layers).reshape(-1, 2)
         cv = _i32(base.cell_vertex)
         ce = _i32(base.cell_edge) if getattr(base, "cell_edge", None) is not None else None
         h = ctypes.c_void_p()
-        _abi.exm_mesh_create(int(base.n_vertices), int(base.n_edges), int(base.n_cells),
-                             cv.ctypes.data_as(ctypes.c_void_p),
-                             None if ce is None else ce.ctypes.data_as(ctypes.c_void_p),
-                             self.n_layers, ctypes.byref(h))
+        args = (int(base.n_vertices), int(base.n_edges), int(base.n_cells), cv.ctypes.data_as(ctypes.c_void_p),
+                None if ce is None else ce.ctypes.data_as(ctypes.c_void_p), self.n_layers)
+        if self.layers is None:
+            _abi.exm_mesh_create(*args, ctypes.byref(h))
+        else:
+            _abi.exm_mesh_create_var(*args, self.layers.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
         self.handle = h
+
+    def entity_layers(self, d1: int):
+        """Layer range (lo, hi) of the column of every base entity of dimension d1."""
+        n = int(self.base.counts[d1])
+        lo = np.zeros(n, dtype=np.int32)
+        hi = np.zeros(n, dtype=np.int32)
+        _abi.exm_mesh_entity_layers(self.handle, d1, lo.ctypes.data_as(ctypes.c_void_p),
+                                    hi.ctypes.data_as(ctypes.c_void_p))
+        return lo, hi
 
     @property
     def n_cells(self) -> int:
@@ -155,9 +168,12 @@ def coordinate_field(space: Space, vertex_coords: np.ndarray):
     starts = space.column_starts(0).cpu().numpy().astype(np.int64)
     nl = vertex_coords.shape[1]
     host = np.zeros((3, space.n_dofs))
-    idx = (starts[:, None] + np.arange(nl)[None, :]).ravel()
+    lo, hi = space.mesh.entity_layers(0)
+    lev = np.arange(nl)[None, :]
+    used = (lev >= lo[:, None]) & (lev <= hi[:, None])     # levels lo .. hi of every vertex column
+    idx = (starts[:, None] + lev - lo[:, None])[used]
     for i in range(3):
-        host[i, idx] = vertex_coords[:, :, i].ravel()
+        host[i, idx] = vertex_coords[:, :, i][used]
     return torch.from_numpy(host).to("cuda")
 
 

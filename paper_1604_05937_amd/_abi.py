@@ -86,6 +86,9 @@ _PROTOS = {
     "exm_abi_version": (c_int32, []),
     "exm_sync": (c_int32, [c_void_p]),
     "exm_mesh_create": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32, POINTER(c_void_p)]),
+    "exm_mesh_create_var": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                      POINTER(c_void_p)]),
+    "exm_mesh_entity_layers": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "exm_mesh_destroy": (None, [c_void_p]),
     "exm_space_create": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_void_p)]),
     "exm_space_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int32)]),

@@ -168,6 +168,7 @@ static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const e
     P.kernel = kernel;
     P.element = el;
     P.n_layers = m->n_layers;
+    P.cell_lam = m->variable ? m->d_cell_lam.p : nullptr;
     P.field_offset = V->offsets[0];
     P.fmap = V->d_map.p;
     P.xmap = X.space->d_map.p;
@@ -208,7 +209,8 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
 {
     exm_loop_opts d;
     std::memset(&d, 0, sizeof(d));
-    if (!lookup_tuned(P.kernel, P.element, P.n_layers, P.n_cells, &d)) {
+    // meshes with a layer range per column are tuned apart (negative layer key)
+    if (!lookup_tuned(P.kernel, P.element, P.cell_lam ? -P.n_layers : P.n_layers, P.n_cells, &d)) {
         d.race = EXM_RACE_ATOMIC;
         d.schedule = EXM_SCHED_DIRECT;
     }
@@ -241,6 +243,13 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
+    if (mesh->variable) {   // columns of different heights: the DIRECT schedule walks each on its own
+        EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED,
+                  "owner-computes needs columns of one height; this mesh has a layer range per column");
+        if (d.schedule != EXM_SCHED_DIRECT) d.cols_per_wave = d.waves_per_block = 0;
+        d.schedule = EXM_SCHED_DIRECT;
+        d.tile_cells = d.chunk_layers = 0;
+    }
     if (direct_only(P.element)) {
         EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED, "owner-computes is not available on element %d",
                   P.element);
@@ -595,6 +604,10 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     const int32_t races[2] = {EXM_RACE_ATOMIC, EXM_RACE_COLOUR};
     for (int r = 0; r < (cg ? 2 : 1); ++r) {
         for (int32_t c : {1, 2, 3, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 4, 0, 0});
+        if (iterset->variable) {   // columns of different heights run DIRECT only
+            for (int32_t c : {1, 2, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 8, 0, 0});
+            continue;
+        }
         if (staged_supported(P.kernel, P.element))
             for (int32_t tc : {32, 64, 128, 256})
                 for (int32_t S : {8, 16, 32, 64})
@@ -650,7 +663,7 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     EXM_TRY_HIP(hipStreamSynchronize(hs));
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
-        g_tuned[tune_key(P.kernel, P.element, P.n_layers, P.n_cells)] = best_opts;
+        g_tuned[tune_key(P.kernel, P.element, P.cell_lam ? -P.n_layers : P.n_layers, P.n_cells)] = best_opts;
     }
     if (best) *best = best_opts;
     return EXM_OK;

@@ -289,6 +289,8 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         EXM_CHECK(it.space && it.coord_space && it.coords, EXM_EINVAL, "item %d: NULL space, coord_space or coords", m);
         EXM_CHECK(it.space->element == EXM_ELEMENT_P1P1 || it.space->element == EXM_ELEMENT_DG0DG0,
                   EXM_EUNSUPPORTED, "item %d: batched assembly supports P1xP1 and DG0xDG0 spaces", m);
+        EXM_CHECK(!it.space->mesh->variable, EXM_EUNSUPPORTED,
+                  "item %d: batches take meshes with one layer count per column", m);
         EXM_CHECK(it.coord_space->element == EXM_ELEMENT_P1P1 && it.coord_space->mesh == it.space->mesh, EXM_EINVAL,
                   "item %d: coord_space must be a P1xP1 space on the same mesh", m);
         EXM_CHECK(it.n_fields >= 1 && it.n_fields <= 64, EXM_ERANGE, "item %d: n_fields = %d outside [1, 64]", m,

@@ -157,10 +157,9 @@ int32_t exm_sync(void* stream)
     return check_pending();
 }
 
-int32_t exm_mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells, const int32_t* cell_vertex,
-                        const int32_t* cell_edge, int32_t n_layers, exm_mesh** out)
+static int32_t mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells, const int32_t* cell_vertex,
+                           const int32_t* cell_edge, int32_t n_layers, const int32_t* layers, exm_mesh** out)
 {
-    clear_error();
     EXM_CHECK(out != nullptr, EXM_EINVAL, "out is NULL");
     *out = nullptr;
     EXM_CHECK(cell_vertex != nullptr, EXM_EINVAL, "cell_vertex is NULL");
@@ -180,6 +179,11 @@ int32_t exm_mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells, co
         for (int64_t i = 0; i < (int64_t)n_cells * 3; ++i)
             EXM_CHECK(cell_edge[i] >= 0 && cell_edge[i] < n_edges, EXM_ERANGE,
                       "cell_edge[%lld] = %d outside [0, %d)", (long long)i, cell_edge[i], n_edges);
+    if (layers)
+        for (int64_t c = 0; c < n_cells; ++c)
+            EXM_CHECK(layers[2 * c] >= 0 && layers[2 * c] < layers[2 * c + 1] && layers[2 * c + 1] <= n_layers,
+                      EXM_ERANGE, "layers of cell %lld = [%d, %d) not inside [0, %d) or empty", (long long)c,
+                      layers[2 * c], layers[2 * c + 1], n_layers);
     auto m = std::make_unique<exm_mesh>();
     m->n[0] = n_vertices;
     m->n[1] = n_edges;
@@ -194,7 +198,68 @@ int32_t exm_mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells, co
         s = m->d_cell_edge.upload(cell_edge, (size_t)n_cells * 3);
         if (s != EXM_OK) return s;
     }
+    if (layers) {
+        // entity columns: a cell's own range; a vertex or edge column spans
+        // the union of the ranges of the cells around it
+        m->variable = true;
+        for (int d = 0; d < 3; ++d) {
+            m->lo[d].assign(m->n[d], n_layers);
+            m->hi[d].assign(m->n[d], 0);
+        }
+        std::vector<int32_t> lam(n_cells);
+        for (int64_t c = 0; c < n_cells; ++c) {
+            const int32_t b = layers[2 * c], t = layers[2 * c + 1];
+            lam[c] = t - b;
+            m->lo[2][c] = b;
+            m->hi[2][c] = t;
+            for (int a = 0; a < 3; ++a) {
+                const int32_t v = cell_vertex[c * 3 + a];
+                m->lo[0][v] = std::min(m->lo[0][v], b);
+                m->hi[0][v] = std::max(m->hi[0][v], t);
+                if (cell_edge) {
+                    const int32_t e = cell_edge[c * 3 + a];
+                    m->lo[1][e] = std::min(m->lo[1][e], b);
+                    m->hi[1][e] = std::max(m->hi[1][e], t);
+                }
+            }
+        }
+        for (int32_t v = 0; v < n_vertices; ++v)
+            EXM_CHECK(m->lo[0][v] < m->hi[0][v], EXM_EINVAL, "vertex %d belongs to no cell", v);
+        if (!cell_edge) {
+            m->lo[1].assign(m->n[1], 0);
+            m->hi[1].assign(m->n[1], n_layers);
+        }
+        s = m->d_cell_lam.upload(lam.data(), lam.size());
+        if (s != EXM_OK) return s;
+    }
     *out = m.release();
+    return EXM_OK;
+}
+
+int32_t exm_mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells, const int32_t* cell_vertex,
+                        const int32_t* cell_edge, int32_t n_layers, exm_mesh** out)
+{
+    clear_error();
+    return mesh_create(n_vertices, n_edges, n_cells, cell_vertex, cell_edge, n_layers, nullptr, out);
+}
+
+int32_t exm_mesh_create_var(int32_t n_vertices, int32_t n_edges, int32_t n_cells, const int32_t* cell_vertex,
+                            const int32_t* cell_edge, int32_t n_layers, const int32_t* layers, exm_mesh** out)
+{
+    clear_error();
+    EXM_CHECK(layers != nullptr, EXM_EINVAL, "layers is NULL");
+    return mesh_create(n_vertices, n_edges, n_cells, cell_vertex, cell_edge, n_layers, layers, out);
+}
+
+int32_t exm_mesh_entity_layers(const exm_mesh* mesh, int32_t d1, int32_t* lo, int32_t* hi)
+{
+    clear_error();
+    EXM_CHECK(mesh != nullptr, EXM_EINVAL, "mesh is NULL");
+    EXM_CHECK(d1 >= 0 && d1 <= 2, EXM_ERANGE, "d1 = %d outside [0, 2]", d1);
+    for (int32_t i = 0; i < mesh->n[d1]; ++i) {
+        if (lo) lo[i] = mesh->variable ? mesh->lo[d1][i] : 0;
+        if (hi) hi[i] = mesh->variable ? mesh->hi[d1][i] : mesh->n_layers;
+    }
     return EXM_OK;
 }
 
@@ -216,6 +281,77 @@ static bool element_delta(int32_t element, int32_t d[6])
     case EXM_ELEMENT_DG1DG0: d[5] = 3; return true;
     default: return false;
     }
+}
+
+// Algorithm 1 with a layer range per entity column: column sizes differ, so
+// the column starts are a prefix sum over the entities of each dimension (in
+// the order Algorithm 1 visits them); the explicit list of a cell is that of
+// its bottom prism, so that L(c) + l * offset still addresses layer l of the
+// cell's column.  Built on the host (the ranges are host data) and uploaded.
+static int32_t space_create_var(const exm_mesh* mesh, const int32_t* delta, std::unique_ptr<exm_space> s,
+                                exm_space** out)
+{
+    std::vector<int64_t> start[3];
+    int64_t c = 0;
+    for (int d = 0; d < 3; ++d) {
+        s->base[d] = c;
+        s->col_size[d] = -1;   // columns differ in size
+        start[d].resize(mesh->n[d]);
+        for (int32_t i = 0; i < mesh->n[d]; ++i) {
+            start[d][i] = c;
+            const int64_t nl = mesh->hi[d][i] - mesh->lo[d][i];
+            c += (nl + 1) * delta[2 * d] + nl * delta[2 * d + 1];
+        }
+    }
+    s->n_dofs = c;
+    EXM_CHECK(s->n_dofs < (int64_t)INT32_MAX, EXM_EOVERFLOW,
+              "space has %lld DoFs; the int32 numbering allows at most %d", (long long)s->n_dofs, INT32_MAX - 1);
+    // stencil layout and offsets (Algorithm 2), as for uniform columns
+    std::vector<int32_t> row_ent, row_part, row_j;   // per position: closure entity 0..6, part (0 bottom, 1 top, 2 vertical), index
+    for (int e = 0; e < 7; ++e) {
+        const int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+        const int nh = delta[2 * d], nv = delta[2 * d + 1];
+        for (int part = 0; part < 3; ++part) {
+            const int cnt = part < 2 ? nh : nv;
+            for (int j = 0; j < cnt; ++j) {
+                row_ent.push_back(e);
+                row_part.push_back(part);
+                row_j.push_back(j);
+                s->offsets.push_back(nh + nv);
+                s->entity_dim.push_back(d);
+            }
+        }
+    }
+    s->k = (int32_t)s->offsets.size();
+    const int32_t nc = mesh->n[2];
+    std::vector<int32_t> map((size_t)nc * s->k);
+    const int32_t* cv = mesh->h_cell_vertex.data();
+    const int32_t* ce = mesh->h_cell_edge.empty() ? nullptr : mesh->h_cell_edge.data();
+    for (int32_t cell = 0; cell < nc; ++cell) {
+        const int32_t b = mesh->lo[2][cell];   // the cell's first layer
+        for (int32_t p = 0; p < s->k; ++p) {
+            const int e = row_ent[p];
+            const int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+            const int32_t i = d == 0 ? cv[cell * 3 + e] : (d == 1 ? ce[cell * 3 + (e - 3)] : cell);
+            const int nh = delta[2 * d], nv = delta[2 * d + 1];
+            int64_t dof = start[d][i] + (int64_t)(b - mesh->lo[d][i]) * (nh + nv);
+            if (row_part[p] == 1) dof += nh + nv;          // top level: the next level's horizontal DoFs
+            else if (row_part[p] == 2) dof += nh;          // vertical entity of the layer
+            map[(size_t)cell * s->k + p] = (int32_t)(dof + row_j[p]);
+        }
+    }
+    int32_t st = s->d_map.upload(map.data(), map.size());
+    if (st != EXM_OK) return st;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->n[d] == 0) continue;
+        const bool has = delta[2 * d] + delta[2 * d + 1] > 0;
+        std::vector<int32_t> h(mesh->n[d]);
+        for (int32_t i = 0; i < mesh->n[d]; ++i) h[i] = has ? (int32_t)start[d][i] : -1;
+        st = s->d_starts[d].upload(h.data(), h.size());
+        if (st != EXM_OK) return st;
+    }
+    *out = s.release();
+    return EXM_OK;
 }
 
 int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t element, void* stream,
@@ -245,6 +381,7 @@ int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t ele
     s->mesh = mesh;
     s->element = element;
     std::memcpy(s->delta, delta, sizeof(s->delta));
+    if (mesh->variable) return space_create_var(mesh, delta, std::move(s), out);
     int64_t base = 0;
     for (int d = 0; d < 3; ++d) {
         int64_t cs = (lam + 1) * delta[2 * d] + lam * delta[2 * d + 1];
@@ -319,12 +456,11 @@ int32_t exm_space_column_starts(const exm_space* space, int32_t d1, int32_t* dst
     clear_error();
     EXM_CHECK(space != nullptr && dst != nullptr, EXM_EINVAL, "space or dst is NULL");
     EXM_CHECK(d1 >= 0 && d1 <= 2, EXM_ERANGE, "d1 = %d outside [0, 2]", d1);
-    int32_t n = space->mesh->n[d1];
+    const int32_t n = space->mesh->n[d1];
     if (n == 0) return EXM_OK;
-    const int bs = 256;
-    hipLaunchKernelGGL(k_column_starts, dim3((n + bs - 1) / bs), dim3(bs), 0, (hipStream_t)stream, n,
-                       space->base[d1], space->col_size[d1], dst);
-    EXM_TRY_HIP(hipGetLastError());
+    // the starts the space keeps (closed form, or a prefix sum over the ranges of a variable mesh)
+    EXM_TRY_HIP(hipMemcpyAsync(dst, space->d_starts[d1].p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
     return EXM_OK;
 }
 

@@ -109,8 +109,11 @@ struct TilePlan {
 
 struct exm_mesh {
     int32_t n[3] = {0, 0, 0};      // N_0, N_1, N_2
-    int32_t n_layers = 0;
+    int32_t n_layers = 0;          // the largest layer count (all of them unless `variable`)
     int device = 0;
+    bool variable = false;         // each cell column has its own layer range
+    std::vector<int32_t> lo[3], hi[3];   // variable: layer range [lo, hi) of every entity column
+    exm::DevBuf<int32_t> d_cell_lam;     // variable: layers of every cell column
     std::vector<int32_t> h_cell_vertex, h_cell_edge;
     exm::DevBuf<int32_t> d_cell_vertex, d_cell_edge;
     mutable std::mutex mu;
@@ -159,6 +162,7 @@ struct LoopLaunch {
     int32_t race;
     LoopShape shape;
     int32_t n_layers;
+    const int32_t* cell_lam;      // layers of every cell column, or null (all n_layers)
     int32_t field_offset;         // vertical offset of every position of the field space
     const int32_t* fmap;          // field explicit lists [n_cells * k]
     const int32_t* xmap;          // coordinate explicit lists [n_cells * 6]

@@ -178,6 +178,23 @@ __device__ __forceinline__ void p1_lane(const ColArgs& a, const int fb[3], const
 // ---------------------------------------------------------------------------
 // DIRECT schedule.
 
+// Layers of the lane's cell column: the mesh's layer count, or the cell's own
+// range on a mesh with a layer range per column (0 for a lane without a cell).
+__device__ __forceinline__ int column_layers(const ColArgs& a, int32_t cell, bool valid)
+{
+    if (!valid) return 0;
+    return a.cell_lam ? a.cell_lam[cell] : a.n_layers;
+}
+
+// Largest value over the wavefront, so that every lane runs the same steps
+// (the steps exchange values across lanes).
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 __device__ __forceinline__ bool direct_cell(const ColArgs& a, const Lane& L, int32_t& cell, bool& valid)
 {
     const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
@@ -197,6 +214,8 @@ __global__ void __launch_bounds__(256) k_direct_p1(const ColArgs a)
     int32_t cell;
     bool valid;
     if (!direct_cell(a, L, cell, valid)) return;
+    const int lamc = column_layers(a, cell, valid);   // this lane's column
+    const int lamw = wave_max(lamc);                  // loop bound of the whole wavefront
     int fb[3], xb[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -208,10 +227,10 @@ __global__ void __launch_bounds__(256) k_direct_p1(const ColArgs a)
     double carry[NOUT][3];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) carry[o][0] = carry[o][1] = carry[o][2] = 0.0;
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+    for (int l0 = 0; l0 < lamw; l0 += a.seg) {
         const int l = l0 + L.lsub;
-        const bool act = valid && l < a.n_layers;
-        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        const bool act = valid && l < lamc;
+        const bool last = L.lsub == a.seg - 1 || l == lamc - 1;
         double lev[NOUT][3], yt[NOUT][3];
         p1_lane<FORM>(a, fb, xb, g, l, act, last, L.lsub == 0, lev, yt);
         const int lo = l * a.off;
@@ -224,7 +243,7 @@ __global__ void __launch_bounds__(256) k_direct_p1(const ColArgs a)
                 carry[o][v] = __shfl(yt[o][v], min(L.sub * a.seg + a.seg - 1, 63), 64);
                 if (act) {
                     inc<RACE>(out[o] + fb[v] + lo, val);
-                    if (l == a.n_layers - 1) inc<RACE>(out[o] + fb[v] + lo + a.off, yt[o][v]);
+                    if (l == lamc - 1) inc<RACE>(out[o] + fb[v] + lo + a.off, yt[o][v]);
                 }
             }
     }
@@ -237,15 +256,17 @@ __global__ void __launch_bounds__(256) k_direct_dg0(const ColArgs a)
     int32_t cell;
     bool valid;
     if (!direct_cell(a, L, cell, valid)) return;
+    const int lamc = column_layers(a, cell, valid);   // this lane's column
+    const int lamw = wave_max(lamc);                  // loop bound of the whole wavefront
     const int f0 = valid ? a.fmap[cell] : 0;
     int xb[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
     const BaseXY g = base_xy(a.X, a.xn, xb, valid);
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+    for (int l0 = 0; l0 < lamw; l0 += a.seg) {
         const int l = l0 + L.lsub;
-        const bool act = valid && l < a.n_layers;
-        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        const bool act = valid && l < lamc;
+        const bool last = L.lsub == a.seg - 1 || l == lamc - 1;
         double twoA, h[3];
         geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
         if (act) {
@@ -277,6 +298,8 @@ __global__ void __launch_bounds__(256) k_direct_tp(const ColArgs a)
     int32_t cell;
     bool valid;
     if (!direct_cell(a, L, cell, valid)) return;
+    const int lamc = column_layers(a, cell, valid);   // this lane's column
+    const int lamw = wave_max(lamc);                  // loop bound of the whole wavefront
     int fb[NH][NV], xb[3];
 #pragma unroll
     for (int al = 0; al < NH; ++al)
@@ -299,10 +322,10 @@ __global__ void __launch_bounds__(256) k_direct_tp(const ColArgs a)
     double carry[NH];
 #pragma unroll
     for (int al = 0; al < NH; ++al) carry[al] = 0.0;
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+    for (int l0 = 0; l0 < lamw; l0 += a.seg) {
         const int l = l0 + L.lsub;
-        const bool act = valid && l < a.n_layers;
-        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        const bool act = valid && l < lamc;
+        const bool last = L.lsub == a.seg - 1 || l == lamc - 1;
         double twoA, h[3];
         geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
         const int64_t lo = (int64_t)l * a.off;
@@ -320,7 +343,7 @@ __global__ void __launch_bounds__(256) k_direct_tp(const ColArgs a)
                 carry[al] = __shfl(y[al][1], min(L.sub * a.seg + a.seg - 1, 63), 64);
                 if (act) {
                     update(a.out0 + fb[al][0] + lo, val);
-                    if (l == a.n_layers - 1) update(a.out0 + fb[al][1] + lo, y[al][1]);
+                    if (l == lamc - 1) update(a.out0 + fb[al][1] + lo, y[al][1]);
                 }
             }
         } else {
@@ -341,15 +364,17 @@ __global__ void __launch_bounds__(256) k_direct_dg1(const ColArgs a)
     int32_t cell;
     bool valid;
     if (!direct_cell(a, L, cell, valid)) return;
+    const int lamc = column_layers(a, cell, valid);   // this lane's column
+    const int lamw = wave_max(lamc);                  // loop bound of the whole wavefront
     const int f0 = valid ? a.fmap[(int64_t)cell * 6] : 0;
     int xb[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
     const BaseXY g = base_xy(a.X, a.xn, xb, valid);
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+    for (int l0 = 0; l0 < lamw; l0 += a.seg) {
         const int l = l0 + L.lsub;
-        const bool act = valid && l < a.n_layers;
-        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        const bool act = valid && l < lamc;
+        const bool last = L.lsub == a.seg - 1 || l == lamc - 1;
         double twoA, h[3];
         geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
         if (act) {
@@ -413,6 +438,8 @@ __global__ void __launch_bounds__(256) k_direct_p2(const ColArgs a)
     int32_t cell;
     bool valid;
     if (!direct_cell(a, L, cell, valid)) return;
+    const int lamc = column_layers(a, cell, valid);   // this lane's column
+    const int lamw = wave_max(lamc);                  // loop bound of the whole wavefront
     int fb[6], fm[6], xb[3];
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
@@ -423,10 +450,10 @@ __global__ void __launch_bounds__(256) k_direct_p2(const ColArgs a)
     for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
     const BaseXY g = base_xy(a.X, a.xn, xb, valid);
     double carry[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+    for (int l0 = 0; l0 < lamw; l0 += a.seg) {
         const int l = l0 + L.lsub;
-        const bool act = valid && l < a.n_layers;
-        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        const bool act = valid && l < lamc;
+        const bool last = L.lsub == a.seg - 1 || l == lamc - 1;
         double lev[6], yt[6], ym[6];
         p2_lane(a, fb, fm, xb, g, l, act, last, L.lsub == 0, lev, yt, ym);
         const int lo = l * a.off;
@@ -437,7 +464,7 @@ __global__ void __launch_bounds__(256) k_direct_p2(const ColArgs a)
             if (act) {
                 inc<RACE>(a.out0 + fb[e] + lo, val);
                 inc<RACE>(a.out0 + fm[e] + lo, ym[e]);
-                if (l == a.n_layers - 1) inc<RACE>(a.out0 + fb[e] + lo + a.off, yt[e]);
+                if (l == lamc - 1) inc<RACE>(a.out0 + fb[e] + lo + a.off, yt[e]);
             }
         }
     }
@@ -639,6 +666,7 @@ ColArgs col_args(const LoopLaunch& P)
 {
     ColArgs a;
     a.n_layers = P.n_layers;
+    a.cell_lam = P.cell_lam;
     a.off = P.field_offset;
     a.cpw = P.shape.cpw;
     a.seg = P.shape.seg;

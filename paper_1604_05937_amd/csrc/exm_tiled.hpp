@@ -22,6 +22,7 @@ struct ColArgs {
     double* __restrict__ out0;
     double* __restrict__ out1;
     double* __restrict__ out2;
+    const int32_t* __restrict__ cell_lam;   // layers of every cell column (a mesh with a range per column) or null
     const int32_t* __restrict__ cells;  // DIRECT: cell list (one colour) or null
     int64_t cell_begin, cell_count;     // DIRECT: range of the list (or of the cells)
 };

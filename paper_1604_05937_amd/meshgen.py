@@ -222,6 +222,38 @@ def extruded_vertex_coords(mesh: BaseMesh, n_layers: int, height: float = 1.0,
     return out
 
 
+def layer_ranges(mesh: BaseMesh, n_layers: int, kind: str = "bathymetry", depth: float = 0.5,
+                 seed: int = SEED_MESH + 20) -> np.ndarray:
+    """Layer range [b_c, t_c) of every cell column (int32 [n_cells, 2]) for a
+    mesh whose columns differ in height.
+
+    ``bathymetry``: every column reaches the top level; the bottom of column c
+    sits at b_c = floor(depth * n_layers * s(x_c, y_c)), s a smooth bump in
+    [0, 1) over the cell centroid, so neighbouring columns differ by few layers
+    (an ocean over uneven ground).  ``random``: b_c and n_layers - t_c are
+    independent, uniform in 0 .. floor(depth * n_layers) / 2 (ragged at both
+    ends, neighbours unrelated).
+    """
+    cent = mesh.xy[mesh.cell_vertex].mean(axis=1)
+    lo = mesh.xy.min(axis=0)
+    span = np.maximum(mesh.xy.max(axis=0) - lo, 1e-300)
+    u = (cent - lo) / span
+    if kind == "bathymetry":
+        s = 0.5 * (1.0 + np.sin(2.0 * np.pi * u[:, 0]) * np.sin(3.0 * np.pi * u[:, 1])) * (1.0 - 1e-12)
+        b = np.floor(depth * n_layers * s).astype(np.int64)
+        t = np.full(mesh.n_cells, n_layers, np.int64)
+    elif kind == "random":
+        k = int(depth * n_layers) // 2
+        rng = np.random.default_rng(seed)
+        b = rng.integers(0, k + 1, mesh.n_cells)
+        t = n_layers - rng.integers(0, k + 1, mesh.n_cells)
+    else:
+        raise ValueError(f"unknown layer-range kind {kind!r}")
+    b = np.minimum(b, n_layers - 1)
+    t = np.maximum(t, b + 1)
+    return np.stack([b, t], axis=1).astype(np.int32)
+
+
 def uniform_values(n: int, seed: int = SEED_FIELD, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     """n float64 values, U[lo, hi], from numpy's PCG64 with the given seed."""
     return np.random.default_rng(seed).uniform(lo, hi, size=n)

@@ -47,9 +47,12 @@ class Extruded:
     X: object                         # device coordinates [3, n]
     spaces: dict = field(default_factory=dict)
     vc: np.ndarray | None = None      # host vertex coordinates [N0, lambda+1, 3]
+    layers: np.ndarray | None = None  # layer range of every cell column (meshes with columns of different heights)
 
     @property
     def n_prisms(self) -> int:
+        if self.layers is not None:
+            return int((self.layers[:, 1] - self.layers[:, 0]).sum())
         return self.base.n_cells * self.n_layers
 
     def space(self, name: str) -> Space:
@@ -60,13 +63,17 @@ class Extruded:
         return self.spaces[name]
 
 
-def extruded(n: int, n_layers: int, order: str = "rcm", keep_host_coords: bool = False, terrain: float = 0.0):
+def extruded(n: int, n_layers: int, order: str = "rcm", keep_host_coords: bool = False, terrain: float = 0.0,
+             layer_kind: str | None = None):
+    """n x n triangulated square extruded to n_layers; with ``layer_kind`` the
+    cell columns take the layer ranges of meshgen.layer_ranges."""
     base = meshgen.tri_square(n, order=order)
-    mesh = Mesh(base, n_layers)
+    layers = meshgen.layer_ranges(base, n_layers, layer_kind) if layer_kind else None
+    mesh = Mesh(base, n_layers, layers=layers)
     Vx = Space(mesh, "P1")
     vc = meshgen.extruded_vertex_coords(base, n_layers, terrain=terrain)
     X = coordinate_field(Vx, vc)
-    return Extruded(base, n_layers, mesh, Vx, X, {}, vc if keep_host_coords else None)
+    return Extruded(base, n_layers, mesh, Vx, X, {}, vc if keep_host_coords else None, layers)
 
 
 def device_values(n: int, seed: int):

@@ -19,15 +19,17 @@ import numpy as np
 # ---------------------------------------------------------------------------
 # Explicit 3D extruded mesh
 
-def prism_entities(mesh, n_layers):
+def prism_entities(mesh, n_layers, layers=None):
     """Every prism's closure as sets of 3D vertex ids, in the stencil order
     (vertex 0, 1, 2; edge 0, 1, 2 opposite the vertex; cell), each closure
-    entity split into (bottom horizontal, top horizontal, vertical) parts."""
+    entity split into (bottom horizontal, top horizontal, vertical) parts.
+    layers: optional [N2, 2] range of layers present in each cell column."""
     n0 = mesh.n_vertices
     out = {}
     for c in range(mesh.n_cells):
         v = [int(x) for x in mesh.cell_vertex[c]]
-        for l in range(n_layers):
+        l_lo, l_hi = (0, n_layers) if layers is None else (int(layers[c][0]), int(layers[c][1]))
+        for l in range(l_lo, l_hi):
             bot = [x + l * n0 for x in v]
             top = [x + (l + 1) * n0 for x in v]
             closure = []
@@ -58,7 +60,7 @@ def classify(ent: frozenset, mesh, edge_index, cell_index):
     return (d1, d2), i, levels[0]
 
 
-def bruteforce_numbering(mesh, n_layers, delta):
+def bruteforce_numbering(mesh, n_layers, delta, layers=None):
     """Vertical-innermost numbering obtained by sorting all (entity, j) keys
     of the explicit 3D mesh by (d1, i, l, d2, j).
 
@@ -67,7 +69,7 @@ def bruteforce_numbering(mesh, n_layers, delta):
     delta = np.asarray(delta).reshape(3, 2)
     edge_index = {(int(a), int(b)): e for e, (a, b) in enumerate(mesh.edge_vertex)}
     cell_index = {frozenset(int(x) for x in mesh.cell_vertex[c]): c for c in range(mesh.n_cells)}
-    prisms = prism_entities(mesh, n_layers)
+    prisms = prism_entities(mesh, n_layers, layers)
     entities = {}
     for closure in prisms.values():
         for parts in closure:

@@ -25,17 +25,18 @@ class Case:
     """One extruded mesh with the coordinate space, a field space and the
     oracle problem on the same inputs."""
 
-    def __init__(self, base, n_layers, space, terrain=0.0, with_oracle=True):
+    def __init__(self, base, n_layers, space, terrain=0.0, with_oracle=True, layers=None):
         import torch
         self.base = base
         self.n_layers = n_layers
         self.space_name = space
         self.vc = meshgen.extruded_vertex_coords(base, n_layers, terrain=terrain)
-        self.mesh = exm.Mesh(base, n_layers)
+        self.layers = layers
+        self.mesh = exm.Mesh(base, n_layers, layers=layers)
         self.Vx = exm.Space(self.mesh, "P1")
         self.V = exm.Space(self.mesh, space) if space != "P1" else self.Vx
         self.X = exm.coordinate_field(self.Vx, self.vc)
-        self.ref = oracle.Problem(base, n_layers, space, self.vc) if with_oracle else None
+        self.ref = oracle.Problem(base, n_layers, space, self.vc, layers=layers) if with_oracle else None
         self.torch = torch
 
     @property

@@ -102,3 +102,46 @@ def test_p1_row_layout():
     for c in range(mesh.n_cells):
         v = mesh.cell_vertex[c]
         np.testing.assert_array_equal(num.lmap[c], [S[v[0]], S[v[0]] + 1, S[v[1]], S[v[1]] + 1, S[v[2]], S[v[2]] + 1])
+
+
+def _ranges(mesh, lam, seed):
+    """Seeded layer ranges whose columns around any vertex overlap (every
+    range starts at or below 2 and ends at or above lam - 2)."""
+    rng = np.random.default_rng(seed)
+    lo = rng.integers(0, 3, mesh.n_cells)
+    hi = lam - rng.integers(0, 3, mesh.n_cells)
+    return np.stack([lo, hi], axis=1).astype(np.int32)
+
+
+@pytest.mark.parametrize("space", SPACES)
+def test_variable_layers_match_bruteforce(space):
+    mesh = meshgen.tri_square(3, order="random")
+    lam = 6
+    layers = _ranges(mesh, lam, 5)
+    delta = oracle.delta_table(*space)
+    num = oracle.number(mesh.counts, lam, delta, mesh.cell_vertex, mesh.cell_edge, layers=layers)
+    n, first, stencils, entities = bruteforce.bruteforce_numbering(mesh, lam, delta, layers)
+    assert num.n_dofs == n
+    for ((d1, d2), i, l), f in first.items():
+        assert num.first[d1][i, l, d2] == f
+    # direct addressing from the column's bottom prism
+    for (c, l), row in stencils.items():
+        np.testing.assert_array_equal(num.lmap[c] + (l - layers[c, 0]) * num.offsets, row)
+    # bijection onto 0 .. n_dofs - 1 and per-cell layer counts
+    assert sorted({int(x) for row in stencils.values() for x in row}) == list(range(n))
+    np.testing.assert_array_equal(num.cell_lam, layers[:, 1] - layers[:, 0])
+
+
+def test_variable_layers_reduce_to_uniform():
+    mesh = meshgen.tri_square(4)
+    lam = 5
+    full = np.tile(np.array([[0, lam]], np.int32), (mesh.n_cells, 1))
+    for space in SPACES:
+        delta = oracle.delta_table(*space)
+        a = oracle.number(mesh.counts, lam, delta, mesh.cell_vertex, mesh.cell_edge)
+        b = oracle.number(mesh.counts, lam, delta, mesh.cell_vertex, mesh.cell_edge, layers=full)
+        assert a.n_dofs == b.n_dofs
+        np.testing.assert_array_equal(a.lmap, b.lmap)
+        for d in range(3):
+            if a.first[d] is not None:
+                np.testing.assert_array_equal(a.first[d], b.first[d])

@@ -219,3 +219,29 @@ def test_subset_iteration_matches_full():
     part = pr.mass(f, cells=cells)
     S = pr.num_v.column_starts(0)[v]
     np.testing.assert_array_equal(part[S:S + lam + 1], full[S:S + lam + 1])
+
+
+@pytest.mark.parametrize("space", ["P1", "DG0", ("CG1", "DG0"), ("DG1", "CG1"), "P2"])
+def test_variable_layers_mass_matches_exact_rationals(space):
+    mesh = meshgen.tri_square(3, jitter=0.2)
+    lam = 5
+    rng = np.random.default_rng(21)
+    layers = np.stack([rng.integers(0, 3, mesh.n_cells), lam - rng.integers(0, 3, mesh.n_cells)], 1).astype(np.int32)
+    vc = meshgen.extruded_vertex_coords(mesh, lam, terrain=0.3)
+    pr = oracle.Problem(mesh, lam, space, vc, layers=layers)
+    f = meshgen.uniform_values(pr.n_dofs, seed=8)
+    got = pr.mass(f)
+    n, _, stencils, _ = bruteforce.bruteforce_numbering(mesh, lam, oracle.delta_table(*pr.space), layers)
+    exact = bruteforce.exact_mass(mesh, vc, lam, pr.space, stencils, n, f)
+    _rel_close(got, exact)
+    # the sum of the residual of f = 1 is the volume of the prisms present
+    ones = pr.mass(np.ones(pr.n_dofs))
+    xy = mesh.xy
+    vol = 0.0
+    for c in range(mesh.n_cells):
+        a, b, d = mesh.cell_vertex[c]
+        twoA = abs((xy[b, 0] - xy[a, 0]) * (xy[d, 1] - xy[a, 1]) - (xy[d, 0] - xy[a, 0]) * (xy[b, 1] - xy[a, 1]))
+        for l in range(layers[c, 0], layers[c, 1]):
+            h = [vc[v, l + 1, 2] - vc[v, l, 2] for v in (a, b, d)]
+            vol += twoA * sum(h) / 6.0
+    assert abs(ones.sum() - vol) < 1e-13
