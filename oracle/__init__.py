@@ -51,6 +51,12 @@ FORM_MASS_ABS = 6
 FORM_CUBIC_ABS = 7
 FORM_VJP_ABS = 8
 
+# bilinear forms assembled into a matrix (oracle_assemble)
+ASM_MASS = 1          # integral phi_j phi_i
+ASM_CUBIC_JAC = 2     # integral 3 u^2 phi_j phi_i, the Jacobian of integral (u^3 - f) v
+ASM_MASS_ABS = 3
+ASM_CUBIC_JAC_ABS = 4
+
 
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
@@ -80,6 +86,10 @@ def _lib():
     lib.oracle_par_loop.argtypes = [ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int32, P,
                                     P, P, P, ctypes.c_int32, P, P,
                                     P, P, P, P, P, P, ctypes.c_int32,
+                                    ctypes.c_int32, P, P, P, P]
+    lib.oracle_assemble.restype = None
+    lib.oracle_assemble.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P, P,
+                                    ctypes.c_int32, P, P, P, P, P, P,
                                     ctypes.c_int32, P, P, P, P]
     return lib
 
@@ -377,6 +387,39 @@ def par_loop(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.
     return outs
 
 
+def assemble(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray, u=None):
+    """Matrix of a bilinear form on V (ASM_*), as scipy CSR with sorted
+    indices: oracle_assemble's triplets, one per (prism, p, j) in Algorithm 3's
+    order, summed per (row, column) by scipy's COO-to-CSR conversion.  Every
+    pair of DoFs that share a prism is present, even where the sum is zero."""
+    import scipy.sparse as sps
+    h, v = space
+    if num_v.cell_lam is not None:
+        raise ValueError("assembly takes meshes with one layer count")
+    jac = form in (ASM_CUBIC_JAC, ASM_CUBIC_JAC_ABS)
+    pts, wts = rule_for(FORM_CUBIC_JVP if jac else FORM_MASS, h, v)
+    phiv = np.ascontiguousarray(tabulate(h, v, pts))
+    phix, dphix = tabulate_coords(pts)
+    k = num_v.k
+    m = int(num_v.counts[2]) * num_v.n_layers * k * k
+    rows = np.empty(m, np.int64)
+    cols = np.empty(m, np.int64)
+    vals = np.empty(m, np.float64)
+    if jac:
+        assert u is not None and u.dtype == np.float64 and u.size == num_v.n_dofs
+        u = np.ascontiguousarray(u)
+    _lib().oracle_assemble(form, int(num_v.counts[2]), num_v.n_layers, _ptr(num_x.lmap), _ptr(num_x.offsets),
+                           _ptr(np.ascontiguousarray(X, dtype=np.float64)), k, _ptr(num_v.lmap),
+                           _ptr(num_v.offsets), _ptr(u) if jac else None, _ptr(rows), _ptr(cols), _ptr(vals),
+                           int(wts.size), _ptr(np.ascontiguousarray(wts)), _ptr(np.ascontiguousarray(phix)),
+                           _ptr(np.ascontiguousarray(dphix)), _ptr(phiv))
+    n = num_v.n_dofs
+    A = sps.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrappers for the forms of the hot path
 
@@ -436,6 +479,20 @@ class Problem:
         dF = np.zeros(self.n_dofs)
         par_loop(FORM_CUBIC_JVP, self.space, self.num_v, self.num_x, self.X, [u, du, df], [dF], cells=cells)
         return dF
+
+    def mass_matrix(self):
+        """M_ij = integral phi_j phi_i (scipy CSR)."""
+        return assemble(ASM_MASS, self.space, self.num_v, self.num_x, self.X)
+
+    def mass_matrix_abs(self):
+        return assemble(ASM_MASS_ABS, self.space, self.num_v, self.num_x, self.X)
+
+    def cubic_jacobian(self, u):
+        """J_ij = d F_i / d u_j = integral 3 u^2 phi_j phi_i (P1 x P1, scipy CSR)."""
+        return assemble(ASM_CUBIC_JAC, self.space, self.num_v, self.num_x, self.X, u)
+
+    def cubic_jacobian_abs(self, u):
+        return assemble(ASM_CUBIC_JAC_ABS, self.space, self.num_v, self.num_x, self.X, u)
 
     def mass_abs(self, x, cells=None):
         """Integral of |x_h| |v_i| with |.| on every factor: the scale of the

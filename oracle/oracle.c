@@ -301,3 +301,73 @@ void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t
     free(e1);
     free(e2);
 }
+
+/*
+ * Matrix of a bilinear form, assembled by the same column iteration
+ * (Algorithm 3; Section 5 names the assembly of the global system matrix as
+ * the next use of the vertical structure).  For every prism, in Algorithm 3's
+ * order, the element matrix
+ *     A_e[p][j] = integral of s(x) phi_j phi_p |det J|
+ * is computed by quadrature and emitted as k * k triplets (row dof_p,
+ * column dof_j, value A_e[p][j]); the matrix is the sum of the triplets with
+ * equal (row, column).
+ *   form 1: mass, s = 1;
+ *   form 2: Jacobian of the cubic residual integral (u^3 - f) v with respect
+ *           to u, s = 3 u^2 (u = in0 on V);
+ *   form 3, 4: the same with |phi| and |u| (the scales of the rounding error
+ *           of any summation order).
+ * rows, cols, vals: n_cells * lam * k * k entries each.
+ */
+void oracle_assemble(int32_t form, int64_t n_cells, int32_t lam,
+                     const int64_t* mapx, const int32_t* offx, const double* X,
+                     int32_t k, const int64_t* mapv, const int32_t* offv, const double* in0,
+                     int64_t* rows, int64_t* cols, double* vals,
+                     int32_t nq, const double* qw, const double* phix, const double* dphix,
+                     const double* phiv)
+{
+    int64_t dx[6];
+    int64_t* dv = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+    double* Ae = (double*)malloc(sizeof(double) * (size_t)k * (size_t)k);
+    const int absf = form >= 3;
+    const int jac = form == 2 || form == 4;
+    int64_t t = 0;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        for (int p = 0; p < 6; ++p) dx[p] = mapx[c * 6 + p];
+        for (int p = 0; p < k; ++p) dv[p] = mapv[c * k + p];
+        for (int32_t l = 0; l < lam; ++l) {
+            for (int64_t e = 0; e < (int64_t)k * k; ++e) Ae[e] = 0.0;
+            for (int q = 0; q < nq; ++q) {
+                double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                for (int p = 0; p < 6; ++p)
+                    for (int i = 0; i < 3; ++i)
+                        for (int r = 0; r < 3; ++r)
+                            J[i][r] += X[dx[p] * 3 + i] * dphix[(q * 6 + p) * 3 + r];
+                double s = qw[q] * fabs(det3(J));
+                if (jac) {
+                    double u = 0.0;
+                    for (int p = 0; p < k; ++p)
+                        u += (absf ? fabs(in0[dv[p]]) : in0[dv[p]]) * (absf ? fabs(phiv[q * k + p]) : phiv[q * k + p]);
+                    s *= 3.0 * u * u;
+                }
+                for (int p = 0; p < k; ++p) {
+                    double pp = absf ? fabs(phiv[q * k + p]) : phiv[q * k + p];
+                    for (int j = 0; j < k; ++j) {
+                        double pj = absf ? fabs(phiv[q * k + j]) : phiv[q * k + j];
+                        Ae[p * k + j] += s * pj * pp;
+                    }
+                }
+            }
+            for (int p = 0; p < k; ++p)
+                for (int j = 0; j < k; ++j) {
+                    rows[t] = dv[p];
+                    cols[t] = dv[j];
+                    vals[t] = Ae[p * k + j];
+                    ++t;
+                }
+            for (int p = 0; p < 6; ++p) dx[p] += offx[p];
+            for (int p = 0; p < k; ++p) dv[p] += offv[p];
+        }
+    }
+    free(dv);
+    free(Ae);
+}
