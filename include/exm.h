@@ -189,6 +189,10 @@ void exm_space_destroy(exm_space* space);
 #define EXM_K_CUBIC 2
 #define EXM_K_CUBIC_VJP 3
 #define EXM_K_CUBIC_FUSED 4
+/* Matrices only (exm_matrix_assemble; exm_par_loop refuses it):
+ *   EXM_K_CUBIC_JAC  J_ij = dF_i / du_j = integral 3 u^2 phi_j phi_i, the
+ *                    Jacobian of EXM_K_CUBIC's residual (args: X, u READ), P1P1. */
+#define EXM_K_CUBIC_JAC 5
 
 typedef struct {
     void* data;               /* device FP64 [n_dofs * dim]               */
@@ -311,6 +315,51 @@ int32_t exm_batch_launch(exm_batch* batch, void* stream);
 /* Work units (cell groups) and persistent workgroups of the batch. */
 int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_blocks);
 void exm_batch_destroy(exm_batch* batch);
+
+/* ------------------------------------------------------------------------
+ * Matrices of bilinear forms on one space, in a layout that uses the
+ * vertical alignment of the numbering (Section 5 names the sparse system
+ * matrix as the next place to exploit it).
+ *
+ * With Algorithm 1's numbering, node alpha of the column of base entity e
+ * holds the DoFs c0 + s * w, slot s = 0 .. lambda (a node on the levels) or
+ * 0 .. lambda - 1 (a node inside the layers), c0 = S(e) + alpha, w the DoFs
+ * per level of the column (Algorithm 2's offset).  Such a run is a class.
+ * Two DoFs couple iff they share a prism, so the classes a class couples with
+ * are those of the base cells around its entity (the pattern, one per class,
+ * the same at every level) and the slots differ by -1, 0 or +1.  The matrix
+ * is stored as, per pattern entry, band = 3 values per slot (slot distance
+ * -1, 0, +1; band = 1 on spaces with no level nodes, whose couplings stay in
+ * one layer), slot-innermost: no per-entry column index.  Entries at slots
+ * where the two classes share no prism are zero and are not exported.
+ *
+ * exm_matrix_create: builds the pattern of `space` (uniform layer count only:
+ *   EXM_EUNSUPPORTED on a mesh with layer ranges) on the host and allocates
+ *   the values on the device (zero).  The space must outlive the matrix.
+ * exm_matrix_info: n_rows (= n_dofs), nnz (structural entries, the CSR
+ *   count), n_pattern (class pairs), n_stored (values held: n_pattern *
+ *   band * (lambda + 1)).  NULL outputs are skipped.
+ * exm_matrix_assemble(kernel, A, nargs, args, stream): overwrite the values
+ *   with the matrix of
+ *     EXM_K_MASS        M_ij = integral phi_j phi_i (args: X), any element;
+ *     EXM_K_CUBIC_JAC   integral 3 u^2 phi_j phi_i (args: X, u on A's space), P1P1.
+ *   X as for exm_par_loop.  Every value is computed by one thread from the
+ *   prisms that contribute to it (no atomics): the result is bitwise
+ *   reproducible.
+ * exm_matrix_spmv(A, x, y, access, stream): y = A x (EXM_WRITE) or
+ *   y += A x (EXM_INC); x, y device [n_rows], distinct.
+ * exm_matrix_csr(A, rowptr, col, val, stream): the same matrix in CSR,
+ *   device arrays rowptr [n_rows + 1] (int64), col [nnz] (int32, ascending
+ *   within a row), val [nnz], caller-owned.  Allocates scratch and waits for
+ *   `stream` before returning.
+ */
+typedef struct exm_matrix exm_matrix;
+int32_t exm_matrix_create(const exm_space* space, exm_matrix** out);
+int32_t exm_matrix_info(const exm_matrix* A, int64_t* n_rows, int64_t* nnz, int64_t* n_pattern, int64_t* n_stored);
+int32_t exm_matrix_assemble(int32_t kernel, exm_matrix* A, int32_t nargs, const exm_arg* args, void* stream);
+int32_t exm_matrix_spmv(const exm_matrix* A, const double* x, double* y, int32_t access, void* stream);
+int32_t exm_matrix_csr(const exm_matrix* A, int64_t* rowptr, int32_t* col, double* val, void* stream);
+void exm_matrix_destroy(exm_matrix* A);
 
 /* ------------------------------------------------------------------------
  * STREAM triad a_i = b_i + alpha c_i (FP64), the bandwidth yardstick of

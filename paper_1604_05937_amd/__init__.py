@@ -17,11 +17,12 @@ import numpy as np
 
 from . import _abi
 from ._abi import (EXM_ELEMENT_DG0DG0, EXM_ELEMENT_DG1DG1, EXM_ELEMENT_NONE, EXM_ELEMENT_P1P1, EXM_ELEMENT_P2P2,
-                   EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_VJP, EXM_K_MASS, EXM_RACE_ATOMIC,
+                   EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_JAC, EXM_K_CUBIC_VJP, EXM_K_MASS,
+                   EXM_RACE_ATOMIC,
                    EXM_RACE_AUTO, EXM_RACE_COLOUR, EXM_RACE_OWNER, EXM_READ, EXM_SCHED_AUTO, EXM_SCHED_CHUNKED, EXM_SCHED_DIRECT, EXM_SCHED_PIPELINED,
                    EXM_SCHED_STAGED, EXM_SCHED_TILED, EXM_WRITE, ExmError)
 
-__all__ = ["Mesh", "Space", "par_loop", "ExmError", "ELEMENTS", "DELTA", "load_library", "stream_handle"]
+__all__ = ["Mesh", "Space", "Matrix", "par_loop", "ExmError", "ELEMENTS", "DELTA", "load_library", "stream_handle"]
 
 # delta((d1, d2)) tables, flattened as d1 * 2 + d2 (Section 3.2)
 DELTA = {
@@ -235,6 +236,55 @@ def sync(stream=None):
 def stream_triad(a, b, c, alpha: float, block: int = 256, grid: int = 0, stream=None):
     _abi.exm_stream_triad(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
                           float(alpha), a.numel(), block, grid, stream_handle(stream))
+
+
+class Matrix:
+    """exm_matrix: the matrix of a bilinear form on one space in the
+    vertically aligned layout (classes of DoFs at a fixed stride, a pattern
+    over base entities, three values per slot), assembled, applied and
+    exported to CSR on the device."""
+
+    def __init__(self, space: Space):
+        self.space = space
+        h = ctypes.c_void_p()
+        _abi.exm_matrix_create(space.handle, ctypes.byref(h))
+        self.handle = h
+        n, nnz, npat, nst = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _abi.exm_matrix_info(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(npat), ctypes.byref(nst))
+        self.n_rows, self.nnz, self.n_pattern, self.n_stored = n.value, nnz.value, npat.value, nst.value
+
+    def assemble(self, kernel: int, coords, coord_space: Space, u=None, stream=None):
+        """Overwrite the values with the matrix of EXM_K_MASS (no field) or
+        EXM_K_CUBIC_JAC (the Jacobian at u)."""
+        fields = [] if u is None else [(u, self.space, EXM_READ)]
+        args = make_args(coords, coord_space, fields)
+        _abi.exm_matrix_assemble(kernel, self.handle, len(args), args, stream_handle(stream))
+
+    def spmv(self, x, y=None, access: int = EXM_WRITE, stream=None):
+        import torch
+        assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.numel() == self.n_rows
+        if y is None:
+            y = torch.empty_like(x)
+        assert y.dtype == torch.float64 and y.is_cuda and y.is_contiguous() and y.numel() == self.n_rows
+        _abi.exm_matrix_spmv(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), access,
+                             stream_handle(stream))
+        return y
+
+    def csr(self, stream=None):
+        """(rowptr int64 [n + 1], col int32 [nnz], val float64 [nnz]) on the device."""
+        import torch
+        rowptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device="cuda")
+        val = torch.empty(max(self.nnz, 1), dtype=torch.float64, device="cuda")
+        _abi.exm_matrix_csr(self.handle, ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                            ctypes.c_void_p(val.data_ptr()), stream_handle(stream))
+        return rowptr, col[:self.nnz], val[:self.nnz]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _abi is not None and _abi._lib is not None:
+            _abi._lib.exm_matrix_destroy(h)
+        self.handle = None
 
 
 class Batch:

@@ -42,6 +42,7 @@ EXM_K_MASS = 1
 EXM_K_CUBIC = 2
 EXM_K_CUBIC_VJP = 3
 EXM_K_CUBIC_FUSED = 4
+EXM_K_CUBIC_JAC = 5
 
 EXM_RACE_AUTO = 0
 EXM_RACE_ATOMIC = 1
@@ -108,6 +109,12 @@ _PROTOS = {
     "exm_batch_launch": (c_int32, [c_void_p, c_void_p]),
     "exm_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int32)]),
     "exm_batch_destroy": (None, [c_void_p]),
+    "exm_matrix_create": (c_int32, [c_void_p, POINTER(c_void_p)]),
+    "exm_matrix_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
+    "exm_matrix_assemble": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
+    "exm_matrix_spmv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "exm_matrix_csr": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "exm_matrix_destroy": (None, [c_void_p]),
     "exm_stream_triad": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int64, c_int32, c_int32, c_void_p]),
 }
 

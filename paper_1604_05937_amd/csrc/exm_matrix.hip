@@ -1,0 +1,630 @@
+// Matrices of bilinear forms in the extruded layout.
+//
+// The vertical-innermost numbering (Algorithm 1) puts the DoFs of one node of
+// an entity column at a fixed stride: node alpha of entity e sits at
+// c0 + s * w for its slots s = 0, 1, ... (c0 = S(e) + alpha, w = DoFs per level
+// of the column, Algorithm 2's offset).  Call such a run a class.  Two DoFs
+// couple when they share a prism, so a class couples with the classes of the
+// base cells around its entity, and only at slot distance -1, 0 or +1.  The
+// matrix therefore needs no column index per entry: the classes a class
+// couples with (a pattern over base entities, the same at every level) and,
+// per pattern entry, three values per slot (one per slot distance), stored
+// slot-innermost so that a wavefront of consecutive slots reads them in one
+// coalesced sweep.  This is the vertical alignment of the global matrix that
+// Section 5 points to; CSR with per-entry column indices is produced on
+// request.
+//
+// Assembly gathers: one thread per (pattern entry, slot) sums the element
+// matrix entries of every prism that contributes to it (the base cells that
+// hold both classes, layers s - 1 and s) and writes its values once, so no
+// atomics, no colouring and a bitwise reproducible result.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "exm_elements.hpp"
+#include "exm_internal.hpp"
+
+namespace exm {
+namespace {
+
+constexpr int kKindH = 0;   // a node on a level (horizontal DoF): slots 0 .. lambda
+constexpr int kKindV = 1;   // a node inside a layer (vertical DoF): slots 0 .. lambda - 1
+
+// Do a row class of kind kr at slot s and a column class of kind kq at slot
+// s + d share a prism?  A level node belongs to the layers below and above
+// it, a layer node to its own layer.
+__host__ __device__ inline bool pair_valid(int kr, int kq, int d, int s, int lam)
+{
+    const int r0 = kr == kKindV ? s : s - 1, r1 = s;
+    const int t = s + d;
+    const int c0 = kq == kKindV ? t : t - 1, c1 = t;
+    const int lo = std::max(std::max(r0, c0), 0);
+    const int hi = std::min(std::min(r1, c1), lam - 1);
+    return lo <= hi;
+}
+
+// Horizontal and vertical factors of the tensor-product elements: the mass of
+// a prism with vertical columns is 2A * T(h) (x) V exactly (the Jacobian
+// determinant is 2A times the linear interpolant of the column heights).
+//   HK 0: the three P1 barycentric functions, T_ab = (h_a + h_b + H)(1 + [a = b]) / 120
+//   HK 1: the constant, T = H / 6
+//   HK 2: the six P2 functions, T_ab = sum_c h_c K_c[a][b] / 2520
+//   VK 0: linear on [0, 1] (bottom, top), V = [[1/3, 1/6], [1/6, 1/3]]
+//   VK 1: the constant, V = 1
+//   VK 2: quadratic (bottom, top, middle), V = [[4, -1, 2], [-1, 4, 2], [2, 2, 16]] / 30
+struct ElementKinds {
+    int hk, vk;
+};
+
+ElementKinds element_kinds(int32_t el)
+{
+    switch (el) {
+    case EXM_ELEMENT_P1P1: return {0, 0};
+    case EXM_ELEMENT_DG0DG0: return {1, 1};
+    case EXM_ELEMENT_DG1DG1: return {0, 0};
+    case EXM_ELEMENT_P2P2: return {2, 2};
+    case EXM_ELEMENT_P1DG0: return {0, 1};
+    case EXM_ELEMENT_P1DG1: return {0, 0};
+    case EXM_ELEMENT_DG0P1: return {1, 0};
+    case EXM_ELEMENT_DG0DG1: return {1, 0};
+    case EXM_ELEMENT_DG1P1: return {0, 0};
+    default: return {0, 1};   // DG1DG0
+    }
+}
+
+// Horizontal node a and vertical node b of stencil position p (the order of
+// the explicit lists: per closure entity its bottom, top and vertical DoFs).
+void position_nodes(int32_t el, int p, int& a, int& b)
+{
+    switch (el) {
+    case EXM_ELEMENT_P1P1:
+    case EXM_ELEMENT_DG1DG1:
+    case EXM_ELEMENT_P1DG1: a = p / 2; b = p % 2; return;
+    case EXM_ELEMENT_P2P2: a = p / 3; b = p % 3; return;
+    case EXM_ELEMENT_DG0DG0: a = 0; b = 0; return;
+    case EXM_ELEMENT_DG0P1:
+    case EXM_ELEMENT_DG0DG1: a = 0; b = p; return;
+    case EXM_ELEMENT_DG1P1: a = p % 3; b = p / 3; return;
+    default: a = p; b = 0; return;   // P1DG0, DG1DG0
+    }
+}
+
+template <int HK, int VK>
+__device__ __forceinline__ double mass_entry(double twoA, const double h[3], int ai, int aj, int bi, int bj)
+{
+    const double H = h[0] + h[1] + h[2];
+    double T;
+    if constexpr (HK == 0) {
+        // h_a + h_b + H, doubled on the diagonal (selects, not an indexed array)
+        const double s = (ai == 0 || aj == 0 ? h[0] : 0.0) + (ai == 1 || aj == 1 ? h[1] : 0.0) +
+                         (ai == 2 || aj == 2 ? h[2] : 0.0);
+        T = ai == aj ? (2.0 * s + H) * (1.0 / 60.0) : (s + H) * (1.0 / 120.0);
+    } else if constexpr (HK == 1) {
+        T = H * (1.0 / 6.0);
+    } else {
+        constexpr double K[3][6][6] = EXM_P2_K_TABLE;
+        T = (h[0] * K[0][ai][aj] + h[1] * K[1][ai][aj] + h[2] * K[2][ai][aj]) * (1.0 / 2520.0);
+    }
+    double V;
+    if constexpr (VK == 0) {
+        V = bi == bj ? 1.0 / 3.0 : 1.0 / 6.0;
+    } else if constexpr (VK == 1) {
+        V = 1.0;
+    } else {
+        constexpr double V2[3][3] = {{4.0, -1.0, 2.0}, {-1.0, 4.0, 2.0}, {2.0, 2.0, 16.0}};
+        V = V2[bi][bj] * (1.0 / 30.0);
+    }
+    return twoA * T * V;
+}
+
+// Entry (a_i, b_i), (a_j, b_j) of the Jacobian of the cubic residual on a P1
+// prism, integral 3 u^2 phi_j phi_i det J, with the rule of the residual
+// (7-point Radon triangle x 3-point Gauss-Legendre, exact for this degree).
+// ub, ut: u at the bottom and top node of the three vertices.
+__device__ __forceinline__ double cubic_jac_entry(double twoA, const double h[3], const double ub[3],
+                                                  const double ut[3], int ai, int aj, int bi, int bj)
+{
+    using namespace cubic;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+        const double dj = twoA * (kLam[t][0] * h[0] + kLam[t][1] * h[1] + kLam[t][2] * h[2]);
+        const double u0 = kLam[t][0] * ub[0] + kLam[t][1] * ub[1] + kLam[t][2] * ub[2];
+        const double u1 = kLam[t][0] * ut[0] + kLam[t][1] * ut[1] + kLam[t][2] * ut[2] - u0;
+        const double li = ai == 0 ? kLam[t][0] : (ai == 1 ? kLam[t][1] : kLam[t][2]);
+        const double lj = aj == 0 ? kLam[t][0] : (aj == 1 ? kLam[t][1] : kLam[t][2]);
+        double sz = 0.0;
+#pragma unroll
+        for (int z = 0; z < 3; ++z) {
+            const double u = u0 + kZ[z] * u1;
+            const double pi = bi ? kZ[z] : 1.0 - kZ[z];
+            const double pj = bj ? kZ[z] : 1.0 - kZ[z];
+            sz += kWz[z] * u * u * pi * pj;
+        }
+        acc += kWt[t] * dj * li * lj * sz;
+    }
+    return 3.0 * acc;
+}
+
+__device__ __forceinline__ unsigned xcd_block_m(unsigned b, unsigned G)
+{
+    const unsigned q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+struct GatherArgs {
+    int32_t lam, L, band;
+    int64_t n_items;                      // pattern entries x slots
+    const int64_t* __restrict__ pc_ptr;   // [n_pat + 1] contributions of every pattern entry
+    const int32_t* __restrict__ pc_cell;  // base cell of every contribution (ascending within an entry)
+    const int32_t* __restrict__ pc_info;  // a_i | a_j << 3 | b_i << 6 | b_j << 8 | top_i << 10 | top_j << 11
+    const int32_t* __restrict__ xmap;     // coordinate lists [n_cells * 6]
+    const double* __restrict__ X;         // coordinates, component-major
+    int64_t xn;
+    const int32_t* __restrict__ fmap;     // field lists (Jacobian: u's space, P1 x P1)
+    const double* __restrict__ u;
+    double* __restrict__ val;             // [n_pat][band][L]
+};
+
+// One thread per (pattern entry p, slot s); consecutive threads take
+// consecutive slots of one entry, so the contribution list is read once per
+// wavefront and the values are written in one coalesced sweep.
+template <int HK, int VK, bool JAC>
+__global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
+{
+    const int64_t idx = (int64_t)xcd_block_m(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= g.n_items) return;
+    const int64_t p = idx / g.L;
+    const int s = (int)(idx - p * g.L);
+    double acc[3] = {0.0, 0.0, 0.0};
+    int64_t e = g.pc_ptr[p];
+    const int64_t end = g.pc_ptr[p + 1];
+    while (e < end) {
+        const int32_t c = g.pc_cell[e];
+        int xb[3];
+        double x[3], y[3], hlo[3], hhi[3], ul[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xb[a] = g.xmap[(int64_t)c * 6 + 2 * a];
+            x[a] = g.X[xb[a]];
+            y[a] = g.X[g.xn + xb[a]];
+            // z at levels s - 1, s, s + 1 (those inside the column)
+            double z[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int lev = s - 1 + k;
+                z[k] = lev >= 0 && lev <= g.lam ? g.X[2 * g.xn + xb[a] + lev] : 0.0;
+            }
+            hlo[a] = z[1] - z[0];   // layer s - 1
+            hhi[a] = z[2] - z[1];   // layer s
+            if constexpr (JAC) {
+                const int fb = g.fmap[(int64_t)c * 6 + 2 * a];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int lev = s - 1 + k;
+                    ul[a][k] = lev >= 0 && lev <= g.lam ? g.u[fb + lev] : 0.0;
+                }
+            }
+        }
+        const double twoA = twice_area(x, y);
+        for (; e < end && g.pc_cell[e] == c; ++e) {
+            const int info = g.pc_info[e];
+            const int ai = info & 7, aj = (info >> 3) & 7, bi = (info >> 6) & 3, bj = (info >> 8) & 3;
+            const int ti = (info >> 10) & 1, tj = (info >> 11) & 1;
+            const int l = s - ti;   // the prism: the row node is its top (layer s - 1) or bottom / inside (layer s)
+            if (l < 0 || l >= g.lam) continue;
+            double h[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) h[a] = ti ? hlo[a] : hhi[a];
+            double v;
+            if constexpr (JAC) {
+                double ub[3], ut[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    ub[a] = ti ? ul[a][0] : ul[a][1];
+                    ut[a] = ti ? ul[a][1] : ul[a][2];
+                }
+                v = cubic_jac_entry(twoA, h, ub, ut, ai, aj, bi, bj);
+            } else {
+                v = mass_entry<HK, VK>(twoA, h, ai, aj, bi, bj);
+            }
+            const int d = tj - ti;
+            if (d < 0) acc[0] += v;
+            else if (d == 0) acc[1] += v;
+            else acc[2] += v;
+        }
+    }
+    if (g.band == 3) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g.val[(p * 3 + d) * g.L + s] = acc[d];
+    } else {
+        g.val[p * g.L + s] = acc[1];
+    }
+}
+
+struct RowArgs {
+    int32_t lam, L, band, write;
+    int64_t n_items;                      // classes x slots
+    const int32_t* __restrict__ c0;       // [n_classes] DoF at slot 0
+    const int32_t* __restrict__ wk;       // [n_classes] stride | kind << 16
+    const int32_t* __restrict__ pptr;     // [n_classes + 1]
+    const int32_t* __restrict__ pcol;     // [n_pat]
+    const double* __restrict__ val;
+    const double* __restrict__ x;
+    double* __restrict__ y;
+    const int64_t* __restrict__ rowptr;   // CSR export
+    int64_t* __restrict__ cnt;
+    int32_t* __restrict__ ccol;
+    double* __restrict__ cval;
+};
+
+// y = A x, one thread per row (class r, slot s).
+__global__ void __launch_bounds__(256) k_mat_spmv(const RowArgs a)
+{
+    const int64_t idx = (int64_t)xcd_block_m(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= a.n_items) return;
+    const int32_t r = (int32_t)(idx / a.L);
+    const int s = (int)(idx - (int64_t)r * a.L);
+    const int wr = a.wk[r] & 0xffff, kr = a.wk[r] >> 16;
+    if (kr == kKindV && s == a.lam) return;   // no such row
+    double acc = 0.0;
+    for (int32_t p = a.pptr[r]; p < a.pptr[r + 1]; ++p) {
+        const int32_t q = a.pcol[p];
+        const int64_t cq = a.c0[q];
+        const int wq = a.wk[q] & 0xffff, kq = a.wk[q] >> 16;
+        if (a.band == 3) {
+#pragma unroll
+            for (int d = -1; d <= 1; ++d)
+                if (pair_valid(kr, kq, d, s, a.lam))
+                    acc += a.val[((int64_t)p * 3 + d + 1) * a.L + s] * a.x[cq + (int64_t)(s + d) * wq];
+        } else {
+            acc += a.val[(int64_t)p * a.L + s] * a.x[cq + (int64_t)s * wq];
+        }
+    }
+    const int64_t row = a.c0[r] + (int64_t)s * wr;
+    if (a.write)
+        a.y[row] = acc;
+    else
+        a.y[row] += acc;
+}
+
+// CSR export, pass 1: entries of every row.
+__global__ void __launch_bounds__(256) k_csr_count(const RowArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n_items) return;
+    const int32_t r = (int32_t)(idx / a.L);
+    const int s = (int)(idx - (int64_t)r * a.L);
+    const int wr = a.wk[r] & 0xffff, kr = a.wk[r] >> 16;
+    if (kr == kKindV && s == a.lam) return;
+    int64_t n = 0;
+    for (int32_t p = a.pptr[r]; p < a.pptr[r + 1]; ++p) {
+        const int kq = a.wk[a.pcol[p]] >> 16;
+        for (int d = -1; d <= 1; ++d)
+            if ((a.band == 3 || d == 0) && pair_valid(kr, kq, d, s, a.lam)) ++n;
+    }
+    a.cnt[a.c0[r] + (int64_t)s * wr] = n;
+}
+
+// CSR export, pass 2: column indices and values of every row, sorted by column.
+__global__ void __launch_bounds__(256) k_csr_fill(const RowArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n_items) return;
+    const int32_t r = (int32_t)(idx / a.L);
+    const int s = (int)(idx - (int64_t)r * a.L);
+    const int wr = a.wk[r] & 0xffff, kr = a.wk[r] >> 16;
+    if (kr == kKindV && s == a.lam) return;
+    const int64_t row = a.c0[r] + (int64_t)s * wr;
+    const int64_t b = a.rowptr[row];
+    int64_t n = 0;
+    for (int32_t p = a.pptr[r]; p < a.pptr[r + 1]; ++p) {
+        const int32_t q = a.pcol[p];
+        const int64_t cq = a.c0[q];
+        const int wq = a.wk[q] & 0xffff, kq = a.wk[q] >> 16;
+        for (int d = -1; d <= 1; ++d) {
+            if (!((a.band == 3 || d == 0) && pair_valid(kr, kq, d, s, a.lam))) continue;
+            const int32_t col = (int32_t)(cq + (int64_t)(s + d) * wq);
+            const double v = a.val[((int64_t)p * a.band + (a.band == 3 ? d + 1 : 0)) * a.L + s];
+            // insertion into the sorted prefix of the row
+            int64_t j = n;
+            while (j > 0 && a.ccol[b + j - 1] > col) {
+                a.ccol[b + j] = a.ccol[b + j - 1];
+                a.cval[b + j] = a.cval[b + j - 1];
+                --j;
+            }
+            a.ccol[b + j] = col;
+            a.cval[b + j] = v;
+            ++n;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace exm
+
+using namespace exm;
+
+struct exm_matrix {
+    const exm_space* space = nullptr;
+    int32_t element = 0, lam = 0, L = 0, band = 3;
+    int32_t n_classes = 0;
+    int64_t n_pat = 0, n_contrib = 0, nnz = 0;
+    DevBuf<int32_t> c0, wk, pptr, pcol;
+    DevBuf<int64_t> pc_ptr;
+    DevBuf<int32_t> pc_cell, pc_info;
+    DevBuf<double> val;
+};
+
+extern "C" {
+
+int32_t exm_matrix_create(const exm_space* space, exm_matrix** out)
+{
+    clear_error();
+    EXM_CHECK(space != nullptr && out != nullptr, EXM_EINVAL, "space or out is NULL");
+    EXM_CHECK(space->element != EXM_ELEMENT_NONE, EXM_EINVAL, "the space has no element");
+    const exm_mesh* mesh = space->mesh;
+    EXM_CHECK(!mesh->variable, EXM_EUNSUPPORTED, "matrices take meshes with one layer count per column");
+    auto A = std::make_unique<exm_matrix>();
+    A->space = space;
+    A->element = space->element;
+    A->lam = mesh->n_layers;
+    A->L = A->lam + 1;
+    const int32_t* delta = space->delta;
+    bool any_h = false;
+    int64_t cbase[3], nclass = 0;
+    int32_t w[3];
+    for (int d = 0; d < 3; ++d) {
+        w[d] = delta[2 * d] + delta[2 * d + 1];
+        any_h = any_h || delta[2 * d] > 0;
+        cbase[d] = nclass;
+        nclass += (int64_t)mesh->n[d] * w[d];
+    }
+    A->band = any_h ? 3 : 1;   // only layer nodes: couplings stay within one slot
+    EXM_CHECK(nclass < INT32_MAX, EXM_EOVERFLOW, "%lld classes exceed the int32 range", (long long)nclass);
+    A->n_classes = (int32_t)nclass;
+    // classes: node alpha of entity e (dimension d), in Algorithm 1's order
+    std::vector<int32_t> c0(nclass), wk(nclass);
+    for (int d = 0; d < 3; ++d)
+        for (int32_t e = 0; e < mesh->n[d]; ++e)
+            for (int al = 0; al < w[d]; ++al) {
+                const int64_t id = cbase[d] + (int64_t)e * w[d] + al;
+                c0[id] = (int32_t)(space->base[d] + (int64_t)e * space->col_size[d] + al);
+                wk[id] = w[d] | ((al < delta[2 * d] ? kKindH : kKindV) << 16);
+            }
+    // stencil positions: class offset within the entity, top flag, nodes
+    struct Pos {
+        int ent, al, top, a, b;
+    };
+    std::vector<Pos> pos;
+    for (int ent = 0; ent < 7; ++ent) {
+        const int d = ent < 3 ? 0 : (ent < 6 ? 1 : 2);
+        const int nh = delta[2 * d], nv = delta[2 * d + 1];
+        for (int part = 0; part < 3; ++part)
+            for (int j = 0; j < (part < 2 ? nh : nv); ++j)
+                pos.push_back({ent, part == 2 ? nh + j : j, part == 1 ? 1 : 0, 0, 0});
+    }
+    const int k = (int)pos.size();
+    EXM_CHECK(k == space->k, EXM_EINVAL, "stencil layout mismatch (%d vs %d)", k, space->k);
+    for (int p = 0; p < k; ++p) position_nodes(A->element, p, pos[p].a, pos[p].b);
+    const int32_t nc = mesh->n[2];
+    const int32_t* cv = mesh->h_cell_vertex.data();
+    const int32_t* ce = mesh->h_cell_edge.empty() ? nullptr : mesh->h_cell_edge.data();
+    auto cls_of = [&](int32_t cell, int p) -> int32_t {
+        const int ent = pos[p].ent;
+        const int d = ent < 3 ? 0 : (ent < 6 ? 1 : 2);
+        const int32_t i = d == 0 ? cv[cell * 3 + ent] : (d == 1 ? ce[cell * 3 + (ent - 3)] : cell);
+        return (int32_t)(cbase[d] + (int64_t)i * w[d] + pos[p].al);
+    };
+    // pattern: the classes of the cells around each class
+    std::vector<std::vector<int32_t>> rows(nclass);
+    std::vector<int32_t> cc(k);
+    for (int32_t cell = 0; cell < nc; ++cell) {
+        for (int p = 0; p < k; ++p) cc[p] = cls_of(cell, p);
+        for (int p = 0; p < k; ++p)
+            for (int q = 0; q < k; ++q) rows[cc[p]].push_back(cc[q]);
+    }
+    std::vector<int32_t> pptr(nclass + 1, 0), pcol;
+    for (int64_t r = 0; r < nclass; ++r) {
+        auto& v = rows[r];
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        EXM_CHECK((int64_t)pcol.size() + (int64_t)v.size() < INT32_MAX, EXM_EOVERFLOW, "pattern exceeds int32");
+        pptr[r + 1] = pptr[r] + (int32_t)v.size();
+        pcol.insert(pcol.end(), v.begin(), v.end());
+        std::vector<int32_t>().swap(v);
+    }
+    A->n_pat = (int64_t)pcol.size();
+    // contributions (cell, i, j) of every pattern entry, by counting sort
+    const int64_t ncon = (int64_t)nc * k * k;
+    std::vector<int32_t> pidx(ncon);
+    std::vector<int64_t> pc_ptr(A->n_pat + 1, 0);
+    for (int32_t cell = 0; cell < nc; ++cell) {
+        for (int p = 0; p < k; ++p) cc[p] = cls_of(cell, p);
+        for (int i = 0; i < k; ++i) {
+            const int32_t* rb = pcol.data() + pptr[cc[i]];
+            const int32_t* re = pcol.data() + pptr[cc[i] + 1];
+            for (int j = 0; j < k; ++j) {
+                const int32_t pe = (int32_t)(std::lower_bound(rb, re, cc[j]) - pcol.data());
+                pidx[((int64_t)cell * k + i) * k + j] = pe;
+                ++pc_ptr[pe + 1];
+            }
+        }
+    }
+    std::partial_sum(pc_ptr.begin(), pc_ptr.end(), pc_ptr.begin());
+    std::vector<int32_t> pc_cell(ncon), pc_info(ncon);
+    {
+        std::vector<int64_t> fill(pc_ptr.begin(), pc_ptr.end() - 1);
+        for (int32_t cell = 0; cell < nc; ++cell)
+            for (int i = 0; i < k; ++i)
+                for (int j = 0; j < k; ++j) {
+                    const int64_t at = fill[pidx[((int64_t)cell * k + i) * k + j]]++;
+                    pc_cell[at] = cell;
+                    pc_info[at] = pos[i].a | pos[j].a << 3 | pos[i].b << 6 | pos[j].b << 8 | pos[i].top << 10 |
+                                  pos[j].top << 11;
+                }
+    }
+    A->n_contrib = ncon;
+    // structural entries (the CSR count)
+    int64_t cnt[2][2][3] = {};
+    for (int kr = 0; kr < 2; ++kr)
+        for (int kq = 0; kq < 2; ++kq)
+            for (int d = -1; d <= 1; ++d)
+                for (int s = 0; s <= A->lam; ++s)
+                    if ((kr == kKindH || s < A->lam) && (A->band == 3 || d == 0) && pair_valid(kr, kq, d, s, A->lam))
+                        ++cnt[kr][kq][d + 1];
+    int64_t nnz = 0;
+    for (int64_t r = 0; r < nclass; ++r)
+        for (int32_t p = pptr[r]; p < pptr[r + 1]; ++p)
+            for (int d = 0; d < 3; ++d) nnz += cnt[wk[r] >> 16][wk[pcol[p]] >> 16][d];
+    A->nnz = nnz;
+    int32_t st;
+    if ((st = A->c0.upload(c0.data(), c0.size())) != EXM_OK) return st;
+    if ((st = A->wk.upload(wk.data(), wk.size())) != EXM_OK) return st;
+    if ((st = A->pptr.upload(pptr.data(), pptr.size())) != EXM_OK) return st;
+    if ((st = A->pcol.upload(pcol.data(), pcol.size())) != EXM_OK) return st;
+    if ((st = A->pc_ptr.upload(pc_ptr.data(), pc_ptr.size())) != EXM_OK) return st;
+    if ((st = A->pc_cell.upload(pc_cell.data(), pc_cell.size())) != EXM_OK) return st;
+    if ((st = A->pc_info.upload(pc_info.data(), pc_info.size())) != EXM_OK) return st;
+    if ((st = A->val.alloc((size_t)A->n_pat * A->band * A->L)) != EXM_OK) return st;
+    EXM_TRY_HIP(hipMemset(A->val.p, 0, sizeof(double) * A->val.n));
+    *out = A.release();
+    return EXM_OK;
+}
+
+int32_t exm_matrix_info(const exm_matrix* A, int64_t* n_rows, int64_t* nnz, int64_t* n_pattern, int64_t* n_stored)
+{
+    clear_error();
+    EXM_CHECK(A != nullptr, EXM_EINVAL, "matrix is NULL");
+    if (n_rows) *n_rows = A->space->n_dofs;
+    if (nnz) *nnz = A->nnz;
+    if (n_pattern) *n_pattern = A->n_pat;
+    if (n_stored) *n_stored = A->n_pat * A->band * A->L;
+    return EXM_OK;
+}
+
+int32_t exm_matrix_assemble(int32_t kernel, exm_matrix* A, int32_t nargs, const exm_arg* args, void* stream)
+{
+    clear_error();
+    EXM_CHECK(A != nullptr && args != nullptr, EXM_EINVAL, "matrix or args is NULL");
+    EXM_CHECK(kernel == EXM_K_MASS || kernel == EXM_K_CUBIC_JAC, EXM_EINVAL,
+              "kernel %d has no matrix (EXM_K_MASS or EXM_K_CUBIC_JAC)", kernel);
+    const bool jac = kernel == EXM_K_CUBIC_JAC;
+    EXM_CHECK(nargs == (jac ? 2 : 1), EXM_EINVAL, "kernel %d takes %d args, got %d", kernel, jac ? 2 : 1, nargs);
+    const exm_mesh* m = A->space->mesh;
+    const exm_arg& X = args[0];
+    EXM_CHECK(X.space != nullptr && X.data != nullptr, EXM_EINVAL, "args[0] (coordinates) has a NULL space or data");
+    EXM_CHECK(X.space->mesh == m, EXM_EINVAL, "coordinate space is on another mesh");
+    EXM_CHECK(X.space->element == EXM_ELEMENT_P1P1 && X.dim == 3 && X.access == EXM_READ, EXM_EINVAL,
+              "coordinates must be an EXM_READ P1xP1 field of dim 3");
+    if (jac) {
+        EXM_CHECK(A->element == EXM_ELEMENT_P1P1, EXM_EUNSUPPORTED, "the cubic Jacobian is implemented for P1xP1");
+        EXM_CHECK(args[1].data != nullptr && args[1].space == A->space && args[1].dim == 1 &&
+                      args[1].access == EXM_READ,
+                  EXM_EINVAL, "args[1] (u) must be an EXM_READ scalar field on the matrix's space");
+    }
+    if (A->n_pat == 0) return EXM_OK;
+    GatherArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.lam = A->lam;
+    g.L = A->L;
+    g.band = A->band;
+    g.n_items = A->n_pat * A->L;
+    g.pc_ptr = A->pc_ptr.p;
+    g.pc_cell = A->pc_cell.p;
+    g.pc_info = A->pc_info.p;
+    g.xmap = X.space->d_map.p;
+    g.X = (const double*)X.data;
+    g.xn = X.space->n_dofs;
+    g.fmap = A->space->d_map.p;
+    g.u = jac ? (const double*)args[1].data : nullptr;
+    g.val = A->val.p;
+    const int bs = 256;
+    const int64_t nb = (g.n_items + bs - 1) / bs;
+    EXM_CHECK(nb < INT32_MAX, EXM_EOVERFLOW, "grid too large");
+    hipStream_t hs = (hipStream_t)stream;
+    const ElementKinds ek = element_kinds(A->element);
+#define EXM_GATHER(HK, VK, J) hipLaunchKernelGGL((k_mat_gather<HK, VK, J>), dim3((unsigned)nb), dim3(bs), 0, hs, g)
+    if (jac) EXM_GATHER(0, 0, true);
+    else if (ek.hk == 0 && ek.vk == 0) EXM_GATHER(0, 0, false);
+    else if (ek.hk == 0) EXM_GATHER(0, 1, false);
+    else if (ek.hk == 1 && ek.vk == 0) EXM_GATHER(1, 0, false);
+    else if (ek.hk == 1) EXM_GATHER(1, 1, false);
+    else EXM_GATHER(2, 2, false);
+#undef EXM_GATHER
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+static RowArgs row_args(const exm_matrix* A)
+{
+    RowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.lam = A->lam;
+    a.L = A->L;
+    a.band = A->band;
+    a.n_items = (int64_t)A->n_classes * A->L;
+    a.c0 = A->c0.p;
+    a.wk = A->wk.p;
+    a.pptr = A->pptr.p;
+    a.pcol = A->pcol.p;
+    a.val = A->val.p;
+    return a;
+}
+
+int32_t exm_matrix_spmv(const exm_matrix* A, const double* x, double* y, int32_t access, void* stream)
+{
+    clear_error();
+    EXM_CHECK(A != nullptr && x != nullptr && y != nullptr, EXM_EINVAL, "matrix, x or y is NULL");
+    EXM_CHECK(x != y, EXM_EINVAL, "y aliases x");
+    EXM_CHECK(access == EXM_WRITE || access == EXM_INC, EXM_EINVAL, "access must be EXM_WRITE or EXM_INC");
+    RowArgs a = row_args(A);
+    if (a.n_items == 0) return EXM_OK;
+    a.write = access == EXM_WRITE;
+    a.x = x;
+    a.y = y;
+    const int bs = 256;
+    const int64_t nb = (a.n_items + bs - 1) / bs;
+    hipLaunchKernelGGL(k_mat_spmv, dim3((unsigned)nb), dim3(bs), 0, (hipStream_t)stream, a);
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+int32_t exm_matrix_csr(const exm_matrix* A, int64_t* rowptr, int32_t* col, double* val, void* stream)
+{
+    clear_error();
+    EXM_CHECK(A != nullptr && rowptr != nullptr, EXM_EINVAL, "matrix or rowptr is NULL");
+    EXM_CHECK(A->nnz == 0 || (col != nullptr && val != nullptr), EXM_EINVAL, "col or val is NULL");
+    const int64_t n = A->space->n_dofs;
+    hipStream_t hs = (hipStream_t)stream;
+    RowArgs a = row_args(A);
+    DevBuf<int64_t> cnt;
+    int32_t st;
+    if ((st = cnt.alloc((size_t)n + 1)) != EXM_OK) return st;
+    EXM_TRY_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int64_t) * (size_t)(n + 1), hs));
+    a.cnt = cnt.p;
+    const int bs = 256;
+    const int64_t nb = (a.n_items + bs - 1) / bs;
+    if (a.n_items) hipLaunchKernelGGL(k_csr_count, dim3((unsigned)nb), dim3(bs), 0, hs, a);
+    EXM_TRY_HIP(hipGetLastError());
+    size_t tmp_bytes = 0;
+    EXM_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt.p, rowptr, (int)(n + 1), hs));
+    DevBuf<unsigned char> tmp;
+    if ((st = tmp.alloc(tmp_bytes)) != EXM_OK) return st;
+    EXM_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tmp_bytes, cnt.p, rowptr, (int)(n + 1), hs));
+    a.rowptr = rowptr;
+    a.ccol = col;
+    a.cval = val;
+    if (a.n_items) hipLaunchKernelGGL(k_csr_fill, dim3((unsigned)nb), dim3(bs), 0, hs, a);
+    EXM_TRY_HIP(hipGetLastError());
+    // cnt and tmp are freed on return: wait for the kernels that use them
+    EXM_TRY_HIP(hipStreamSynchronize(hs));
+    return EXM_OK;
+}
+
+void exm_matrix_destroy(exm_matrix* A) { delete A; }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""Parity of the matrix assembly in the vertically aligned layout with the
+oracle's triplet assembly: CSR structure bit-exact, values to the
+componentwise FP64 tolerance, products with the matrix, and the cubic
+Jacobian."""
+import numpy as np
+import pytest
+
+import paper_1604_05937_amd as exm
+from paper_1604_05937_amd import meshgen
+from tests.gpu_common import RTOL, Case, assert_close, say
+
+pytestmark = pytest.mark.gpu
+
+ALL_SPACES = ["P1", "DG0", "DG1", "P2", "CG1xDG0", "CG1xDG1", "DG0xCG1", "DG0xDG1", "DG1xCG1", "DG1xDG0"]
+# lambda = 1; slots spanning several wavefronts with a ragged tail; a square
+# base that is not a tile multiple
+SHAPES = [(4, 3), (5, 1), (3, 70), (7, 9)]
+
+
+def _csr(c, M):
+    rowptr, col, val = M.csr()
+    return c.host(rowptr), c.host(col), c.host(val)
+
+
+def _check_csr(c, M, ref, ref_abs, what):
+    rowptr, col, val = _csr(c, M)
+    assert M.nnz == ref.nnz, f"{what}: nnz {M.nnz} vs {ref.nnz}"
+    np.testing.assert_array_equal(rowptr, ref.indptr.astype(np.int64))
+    np.testing.assert_array_equal(col.astype(np.int64), ref.indices.astype(np.int64))
+    assert_close(val, ref.data, ref_abs.data, what=what)
+
+
+@pytest.mark.parametrize("space", ALL_SPACES)
+@pytest.mark.parametrize("n,lam", SHAPES)
+def test_mass_matrix_matches_oracle(space, n, lam):
+    say(f"matrix mass {space} n={n} lam={lam}")
+    c = Case(meshgen.tri_square(n), lam, space, terrain=0.25)
+    M = exm.Matrix(c.V)
+    M.assemble(exm.EXM_K_MASS, c.X, c.Vx)
+    ref = c.ref.mass_matrix()
+    ref_abs = c.ref.mass_matrix_abs()
+    _check_csr(c, M, ref, ref_abs, f"mass matrix {space}")
+    # the product with the stored layout, against the oracle's matrix and the
+    # matrix-free mass action of the column loop
+    x = meshgen.uniform_values(c.n, seed=21)
+    y = c.host(M.spmv(c.dev(x)))
+    scale = ref_abs @ np.abs(x)
+    assert_close(y, ref @ x, scale, what=f"spmv {space}")
+    assert_close(y, c.mass(x), scale, what=f"spmv vs matrix-free {space}")
+
+
+@pytest.mark.parametrize("n,lam,terrain", [(4, 3, 0.0), (5, 1, 0.2), (3, 70, 0.1), (6, 10, 0.3)])
+def test_cubic_jacobian_matches_oracle(n, lam, terrain):
+    say(f"matrix cubic jacobian n={n} lam={lam}")
+    c = Case(meshgen.tri_square(n), lam, "P1", terrain=terrain)
+    u = meshgen.uniform_values(c.n, seed=22)
+    J = exm.Matrix(c.V)
+    J.assemble(exm.EXM_K_CUBIC_JAC, c.X, c.Vx, u=c.dev(u))
+    _check_csr(c, J, c.ref.cubic_jacobian(u), c.ref.cubic_jacobian_abs(u), "cubic Jacobian")
+    du = meshgen.uniform_values(c.n, seed=23)
+    y = c.host(J.spmv(c.dev(du)))
+    ref = c.ref.cubic_jvp(u, du, np.zeros(c.n))
+    assert_close(y, ref, c.ref.cubic_jacobian_abs(u) @ np.abs(du), what="J du")
+
+
+def test_assembly_is_bitwise_reproducible_and_overwrites():
+    c = Case(meshgen.tri_square(8), 12, "P1", terrain=0.2)
+    u = c.dev(meshgen.uniform_values(c.n, seed=24))
+    M = exm.Matrix(c.V)
+    M.assemble(exm.EXM_K_CUBIC_JAC, c.X, c.Vx, u=u)
+    a = _csr(c, M)[2]
+    M.assemble(exm.EXM_K_MASS, c.X, c.Vx)       # overwrite with another form ...
+    M.assemble(exm.EXM_K_CUBIC_JAC, c.X, c.Vx, u=u)   # ... and back
+    b = _csr(c, M)[2]
+    assert np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+def test_spmv_inc_accumulates():
+    c = Case(meshgen.tri_square(5), 6, "P2")
+    M = exm.Matrix(c.V)
+    M.assemble(exm.EXM_K_MASS, c.X, c.Vx)
+    x = meshgen.uniform_values(c.n, seed=25)
+    y = c.dev(np.full(c.n, 3.0))
+    M.spmv(c.dev(x), y, access=exm.EXM_INC)
+    ref = c.ref.mass_matrix()
+    assert_close(c.host(y), ref @ x + 3.0, c.ref.mass_matrix_abs() @ np.abs(x) + 3.0, what="INC spmv")
+
+
+def test_matrix_errors():
+    base = meshgen.tri_square(4)
+    layers = meshgen.layer_ranges(base, 5, "random")
+    cv = Case(base, 5, "P1", layers=layers, with_oracle=False)
+    with pytest.raises(exm.ExmError) as e:
+        exm.Matrix(cv.V)
+    assert e.value.status == exm._abi.EXM_EUNSUPPORTED
+    c = Case(base, 5, "DG1", with_oracle=False)
+    M = exm.Matrix(c.V)
+    with pytest.raises(exm.ExmError) as e:
+        M.assemble(exm.EXM_K_CUBIC_JAC, c.X, c.Vx, u=c.V.zeros())
+    assert e.value.status == exm._abi.EXM_EUNSUPPORTED
+    # the Jacobian kernel is for matrices only
+    x = c.V.zeros()
+    with pytest.raises(exm.ExmError) as e:
+        exm.par_loop(exm.EXM_K_CUBIC_JAC, c.mesh, c.X, c.Vx, [(x, c.V, exm.EXM_READ), (x, c.V, exm.EXM_INC)])
+    assert e.value.status == exm._abi.EXM_EINVAL
