@@ -392,6 +392,7 @@ def secondary(torch, exm, W, meshgen):
         del ev
     out["rhs_direct_variable_layers_512x512x100"] = var
     log("variable layers: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in var.items()))
+    out["matrix_p1_512x512x100"] = matrix_figures(torch, exm, W, meshgen)
     # higher-order mass actions: 256 x 256 x 64, DG1 x DG1 and P2 x P2
     e3 = W.extruded(256, 64)
     for name in ("DG1", "P2"):
@@ -430,6 +431,42 @@ def secondary(torch, exm, W, meshgen):
     torch.cuda.empty_cache()
     out["batch"] = batch_vs_plain(torch, exm, W, meshgen)
     return out
+
+
+def matrix_figures(torch, exm, W, meshgen):
+    """Mass matrix and cubic Jacobian of P1 x P1 on 512 x 512 x 100 in the
+    vertically aligned layout: assembly, product with the matrix, and the
+    matrix-free action of the column loop beside it."""
+    em = W.extruded(512, 100)
+    V = em.Vx
+    M = exm.Matrix(V)
+    n = V.n_dofs
+    t_asm, _ = timed(torch, lambda: M.assemble(exm.EXM_K_MASS, em.X, V), 5)
+    x = W.device_values(n, meshgen.SEED_FIELD)
+    y = V.zeros()
+    t_mv, _ = timed(torch, lambda: M.spmv(x, y), 10)
+    cfg = exm.autotune(exm.EXM_K_MASS, em.mesh, em.X, V, W.mass_args(em, "P1", x, y))
+    t_mf, _ = timed(torch, lambda: W.run_mass(em, "P1", x, y, **cfg), 10)
+    u = W.device_values(n, 31)
+    t_jac, _ = timed(torch, lambda: M.assemble(exm.EXM_K_CUBIC_JAC, em.X, V, u=u), 3)
+    n_classes = em.base.n_vertices
+    stored = 8 * M.n_stored
+    pattern = 4 * M.n_pattern + 12 * n_classes
+    spmv_bytes = stored + pattern + 16 * n               # values, pattern, x, y
+    csr_bytes = 12 * M.nnz + 8 * (n + 1) + 16 * n         # what a CSR product moves
+    # values written once, coordinates, the contribution lists (cell, nodes: 8 B per element-matrix entry)
+    asm_bytes = stored + W.coord_bytes(em) + 8 * 36 * em.base.n_cells + 8 * (M.n_pattern + 1)
+    r = {"nnz": M.nnz, "stored_values": M.n_stored, "pattern": M.n_pattern,
+         "assemble_mass_ms": round(t_asm, 3), "assemble_gbs": round(asm_bytes / t_asm / 1e6, 1),
+         "assemble_cubic_jacobian_ms": round(t_jac, 3),
+         "spmv_ms": round(t_mv, 4), "spmv_gbs": round(spmv_bytes / t_mv / 1e6, 1),
+         "spmv_bytes_vs_csr": round(spmv_bytes / csr_bytes, 3),
+         "matrix_free_ms": round(t_mf, 4), "matrix_free_launch": cfg}
+    log(f"matrix: assemble {t_asm:.2f} ms, jacobian {t_jac:.2f} ms, spmv {t_mv:.3f} ms "
+        f"({r['spmv_gbs']} GB/s), matrix-free {t_mf:.3f} ms")
+    del M, x, y, u, em
+    torch.cuda.empty_cache()
+    return r
 
 
 def batch_vs_plain(torch, exm, W, meshgen):

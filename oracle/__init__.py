@@ -87,6 +87,9 @@ def _lib():
                                     P, P, P, ctypes.c_int32, P, P,
                                     P, P, P, P, P, P, ctypes.c_int32,
                                     ctypes.c_int32, P, P, P, P]
+    lib.oracle_facet_loop.restype = None
+    lib.oracle_facet_loop.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P,
+                                      ctypes.c_int32, ctypes.c_int32, P, P, P, P, P]
     lib.oracle_assemble.restype = None
     lib.oracle_assemble.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P, P,
                                     ctypes.c_int32, P, P, P, P, P, P,
@@ -420,6 +423,34 @@ def assemble(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.
     return A
 
 
+def facet_loop(space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray, x: np.ndarray,
+               absf: bool = False) -> np.ndarray:
+    """Algorithm 3 over the horizontal facets (lambda + 1 per column):
+    y_i = sum over facets of the integral of [x][v_i] dS, [w] the value below
+    minus the value above (zero outside the domain).  The triangle rule is
+    exact for the product of two horizontal basis functions (the surface
+    element of a facet is constant: the map of each level is affine)."""
+    h, v = space
+    if num_v.cell_lam is not None:
+        raise ValueError("the facet loop takes meshes with one layer count")
+    n_tri = max(1, (2 * _DEG_H[h] + 2) // 2)
+    tp, tw = triangle_rule(n_tri)
+    nq = tp.shape[0]
+    psix = np.stack([1.0 - tp[:, 0] - tp[:, 1], tp[:, 0], tp[:, 1]], axis=1)
+    dpsix = np.tile(np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]]), (nq, 1, 1))
+    lo = np.ascontiguousarray(tabulate(h, v, np.column_stack([tp, np.ones(nq)])))
+    hi = np.ascontiguousarray(tabulate(h, v, np.column_stack([tp, np.zeros(nq)])))
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.size == num_v.n_dofs
+    y = np.zeros(num_v.n_dofs)
+    _lib().oracle_facet_loop(int(num_v.counts[2]), num_v.n_layers, _ptr(num_x.lmap), _ptr(num_x.offsets),
+                             _ptr(np.ascontiguousarray(X, dtype=np.float64)), num_v.k, _ptr(num_v.lmap),
+                             _ptr(num_v.offsets), _ptr(x), _ptr(y), 1 if absf else 0, nq,
+                             _ptr(np.ascontiguousarray(tw)), _ptr(np.ascontiguousarray(psix)),
+                             _ptr(np.ascontiguousarray(dpsix)), _ptr(lo), _ptr(hi))
+    return y
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrappers for the forms of the hot path
 
@@ -479,6 +510,14 @@ class Problem:
         dF = np.zeros(self.n_dofs)
         par_loop(FORM_CUBIC_JVP, self.space, self.num_v, self.num_x, self.X, [u, du, df], [dF], cells=cells)
         return dF
+
+    def facet_jump(self, x):
+        """y_i = sum over horizontal facets of integral [x][v_i] dS (the
+        facet loop, lambda + 1 facets per column)."""
+        return facet_loop(self.space, self.num_v, self.num_x, self.X, x)
+
+    def facet_jump_abs(self, x):
+        return facet_loop(self.space, self.num_v, self.num_x, self.X, x, absf=True)
 
     def mass_matrix(self):
         """M_ij = integral phi_j phi_i (scipy CSR)."""

@@ -371,3 +371,75 @@ void oracle_assemble(int32_t form, int64_t n_cells, int32_t lam,
     free(dv);
     free(Ae);
 }
+
+/*
+ * Algorithm 3 over the horizontal facets (d2 = 0): lambda + 1 facets per
+ * column, level l = 0 .. lambda, with the loop bound lambda - d2 inclusive.
+ * Facet l lies between the prism of layer l - 1 (below; absent for l = 0)
+ * and that of layer l (above; absent for l = lambda).  Its stencil is the
+ * lists of both prisms, advanced by the offsets as in the cell loop.
+ *
+ * Form (the interior-penalty jump term of a field discontinuous across
+ * levels, with zero outside the domain on the bottom and top facets):
+ *     out_i += integral over the facet of [x] [v_i] dS,  [w] = w_below - w_above.
+ * The facet integral uses the coordinate field's restriction to the level
+ * (the vertices of the facet at their own heights, so a tilted facet has its
+ * true area): dS = |t_xi x t_eta| w_q, t the tangents of the map.
+ *   qw[nq]: triangle rule; psix[q*3 + a], dpsix[(q*3 + a)*2 + r]: the
+ *   barycentric functions and their derivatives; phi_lo[q*k + p] /
+ *   phi_hi[q*k + p]: the basis of V at zeta = 1 (below) / zeta = 0 (above).
+ * absf: the same sum with every factor replaced by its absolute value.
+ * out0 is incremented (the caller zeroes it for WRITE).
+ */
+void oracle_facet_loop(int64_t n_cells, int32_t lam, const int64_t* mapx, const int32_t* offx, const double* X,
+                       int32_t k, const int64_t* mapv, const int32_t* offv, const double* in0, double* out0,
+                       int32_t absf, int32_t nq, const double* qw, const double* psix, const double* dpsix,
+                       const double* phi_lo, const double* phi_hi)
+{
+    int64_t* dv = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+    for (int64_t c = 0; c < n_cells; ++c) {
+        for (int p = 0; p < k; ++p) dv[p] = mapv[c * k + p];   /* layer 0 */
+        for (int32_t l = 0; l <= lam; ++l) {
+            const int below = l >= 1, above = l < lam;
+            /* coordinate DoFs of the facet's three vertices at level l */
+            int64_t fx[3];
+            for (int a = 0; a < 3; ++a)
+                fx[a] = above ? mapx[c * 6 + 2 * a] + (int64_t)l * offx[2 * a]
+                              : mapx[c * 6 + 2 * a + 1] + (int64_t)(l - 1) * offx[2 * a + 1];
+            for (int q = 0; q < nq; ++q) {
+                double t[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                for (int a = 0; a < 3; ++a)
+                    for (int r = 0; r < 2; ++r)
+                        for (int i = 0; i < 3; ++i) t[r][i] += X[fx[a] * 3 + i] * dpsix[(q * 3 + a) * 2 + r];
+                const double n0 = t[0][1] * t[1][2] - t[0][2] * t[1][1];
+                const double n1 = t[0][2] * t[1][0] - t[0][0] * t[1][2];
+                const double n2 = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+                const double dS = qw[q] * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+                double ulo = 0.0, uhi = 0.0;
+                for (int p = 0; p < k; ++p) {
+                    const double plo = absf ? fabs(phi_lo[q * k + p]) : phi_lo[q * k + p];
+                    const double phi = absf ? fabs(phi_hi[q * k + p]) : phi_hi[q * k + p];
+                    if (below) {
+                        const double x = in0[dv[p] - offv[p]];   /* the prism below: one offset down */
+                        ulo += (absf ? fabs(x) : x) * plo;
+                    }
+                    if (above) {
+                        const double x = in0[dv[p]];
+                        uhi += (absf ? fabs(x) : x) * phi;
+                    }
+                }
+                const double jump = absf ? ulo + uhi : ulo - uhi;
+                for (int p = 0; p < k; ++p) {
+                    const double plo = absf ? fabs(phi_lo[q * k + p]) : phi_lo[q * k + p];
+                    const double phi = absf ? fabs(phi_hi[q * k + p]) : phi_hi[q * k + p];
+                    if (below) out0[dv[p] - offv[p]] += dS * jump * plo;
+                    if (above) out0[dv[p]] += (absf ? 1.0 : -1.0) * dS * jump * phi;
+                }
+            }
+            /* the prism above facet l is the prism below facet l + 1 */
+            if (above)
+                for (int p = 0; p < k; ++p) dv[p] += offv[p];
+        }
+    }
+    free(dv);
+}
