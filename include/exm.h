@@ -193,6 +193,16 @@ void exm_space_destroy(exm_space* space);
  *   EXM_K_CUBIC_JAC  J_ij = dF_i / du_j = integral 3 u^2 phi_j phi_i, the
  *                    Jacobian of EXM_K_CUBIC's residual (args: X, u READ), P1P1. */
 #define EXM_K_CUBIC_JAC 5
+/*   EXM_K_FACET_JUMP  the loop over horizontal facets (Algorithm 3 with d2 = 0:
+ *                    lambda + 1 facets per column, level 0 .. lambda):
+ *                    y_i = sum over facets of integral [x][v_i] dS, [w] the
+ *                    value below the facet minus the value above, zero
+ *                    outside the domain (the interior-penalty jump term of a
+ *                    field discontinuous across levels) (args: X, x READ, y).
+ *                    Spaces discontinuous across levels: DG0DG0, DG1DG1,
+ *                    DG0DG1, DG1DG0 (y WRITE or INC), P1DG0, P1DG1 (y INC);
+ *                    DIRECT schedule, uniform layer count. */
+#define EXM_K_FACET_JUMP 6
 
 typedef struct {
     void* data;               /* device FP64 [n_dofs * dim]               */

@@ -17,7 +17,8 @@ import numpy as np
 
 from . import _abi
 from ._abi import (EXM_ELEMENT_DG0DG0, EXM_ELEMENT_DG1DG1, EXM_ELEMENT_NONE, EXM_ELEMENT_P1P1, EXM_ELEMENT_P2P2,
-                   EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_JAC, EXM_K_CUBIC_VJP, EXM_K_MASS,
+                   EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_JAC, EXM_K_CUBIC_VJP, EXM_K_FACET_JUMP,
+                   EXM_K_MASS,
                    EXM_RACE_ATOMIC,
                    EXM_RACE_AUTO, EXM_RACE_COLOUR, EXM_RACE_OWNER, EXM_READ, EXM_SCHED_AUTO, EXM_SCHED_CHUNKED, EXM_SCHED_DIRECT, EXM_SCHED_PIPELINED,
                    EXM_SCHED_STAGED, EXM_SCHED_TILED, EXM_WRITE, ExmError)

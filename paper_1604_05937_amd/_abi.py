@@ -43,6 +43,7 @@ EXM_K_CUBIC = 2
 EXM_K_CUBIC_VJP = 3
 EXM_K_CUBIC_FUSED = 4
 EXM_K_CUBIC_JAC = 5
+EXM_K_FACET_JUMP = 6
 
 EXM_RACE_AUTO = 0
 EXM_RACE_ATOMIC = 1

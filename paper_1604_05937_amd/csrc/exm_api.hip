@@ -102,6 +102,7 @@ static bool signature(int32_t kernel, Signature& s)
     case EXM_K_CUBIC: s = {2, 1}; return true;
     case EXM_K_CUBIC_VJP: s = {2, 2}; return true;
     case EXM_K_CUBIC_FUSED: s = {3, 3}; return true;
+    case EXM_K_FACET_JUMP: s = {1, 1}; return true;
     default: return false;
     }
 }
@@ -136,8 +137,14 @@ static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const e
     EXM_CHECK(V->mesh == m, EXM_EINVAL, "field space is on another mesh");
     const int32_t el = V->element;
     EXM_CHECK(el != EXM_ELEMENT_NONE, EXM_EINVAL, "field space has no element");
-    if (kernel != EXM_K_MASS)
+    if (kernel == EXM_K_FACET_JUMP) {
+        EXM_CHECK(el == EXM_ELEMENT_DG0DG0 || el == EXM_ELEMENT_DG1DG1 || el == EXM_ELEMENT_DG0DG1 ||
+                      el == EXM_ELEMENT_DG1DG0 || el == EXM_ELEMENT_P1DG0 || el == EXM_ELEMENT_P1DG1,
+                  EXM_EUNSUPPORTED, "the facet jump needs a space discontinuous across levels (element %d)", el);
+        EXM_CHECK(!m->variable, EXM_EUNSUPPORTED, "the facet loop takes meshes with one layer count per column");
+    } else if (kernel != EXM_K_MASS) {
         EXM_CHECK(el == EXM_ELEMENT_P1P1, EXM_EUNSUPPORTED, "kernel %d is implemented for P1xP1 only", kernel);
+    }
     int32_t write = -1;
     for (int i = 1; i < nargs; ++i) {
         const exm_arg& A = args[i];
@@ -250,9 +257,9 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.schedule = EXM_SCHED_DIRECT;
         d.tile_cells = d.chunk_layers = 0;
     }
-    if (direct_only(P.element)) {
-        EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED, "owner-computes is not available on element %d",
-                  P.element);
+    if (direct_only(P.element) || P.kernel == EXM_K_FACET_JUMP) {   // the generic DIRECT kernels
+        EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED,
+                  "owner-computes is not available for kernel %d on element %d", P.kernel, P.element);
         if (d.schedule != EXM_SCHED_DIRECT) d.cols_per_wave = d.waves_per_block = 0;
         d.schedule = EXM_SCHED_DIRECT;
         d.tile_cells = d.chunk_layers = 0;

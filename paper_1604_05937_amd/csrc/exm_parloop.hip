@@ -660,6 +660,95 @@ __global__ void __launch_bounds__(512) k_tiled_p2(const ColArgs a, const TileArg
 }
 
 // ---------------------------------------------------------------------------
+// Horizontal facets: Algorithm 3 with d2 = 0, lambda + 1 facets per column
+// (levels l = 0 .. lambda).  Lane = facet.  Facet l lies between the prism of
+// layer l - 1 (below) and that of layer l (above); it integrates [x][v] dS with
+// [x] = x_below - x_above, zero outside the domain on the bottom and top
+// facets.  The facet is the flat triangle through the column vertices at
+// level l, so dS = |n| dxi deta (n the cross product of two edges) and the
+// facet mass of the horizontal basis is |n| (1 + [a = b]) / 24 for the P1
+// functions, |n| / 2 for the constant.  NH horizontal x NV vertical nodes,
+// list position NV a + b; only vertically discontinuous spaces (the jump of a
+// continuous field vanishes).
+//   NV = 2: the top nodes of the prism below and the bottom nodes of the
+//           prism above are distinct DoFs, each touched by one facet;
+//   NV = 1: the one DoF of prism l - 1 takes shares from facets l - 1 and l:
+//           lane l adds the share of facet l - 1 (shuffled up from the lane
+//           below, or carried from the previous step) and updates it once.
+template <int NH, int NV, bool HSH, int RACE>
+__global__ void __launch_bounds__(256) k_direct_facet(const ColArgs a)
+{
+    constexpr int K = NH * NV;
+    const Lane L = lane_of(a.seg);
+    int32_t cell;
+    bool valid;
+    if (!direct_cell(a, L, cell, valid)) return;
+    const int lam = a.n_layers;
+    int fb[NH][NV], xb[3];
+#pragma unroll
+    for (int al = 0; al < NH; ++al)
+#pragma unroll
+        for (int be = 0; be < NV; ++be) fb[al][be] = valid ? a.fmap[(int64_t)cell * K + NV * al + be] : 0;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+    const BaseXY g = base_xy(a.X, a.xn, xb, valid);
+    auto update = [&](double* p, double v) {
+        if (a.write)
+            *p = v;
+        else if constexpr (HSH)
+            inc<RACE>(p, v);
+        else
+            *p += v;
+    };
+    double carry[NH];
+#pragma unroll
+    for (int al = 0; al < NH; ++al) carry[al] = 0.0;
+    for (int l0 = 0; l0 <= lam; l0 += a.seg) {
+        const int l = l0 + L.lsub;
+        const bool act = valid && l <= lam;
+        const bool below = act && l >= 1, above = act && l < lam;
+        double z[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) z[v] = act ? a.X[2 * a.xn + (int64_t)xb[v] + l] : 0.0;
+        const double ex0 = g.x[1] - g.x[0], ey0 = g.y[1] - g.y[0], ez0 = z[1] - z[0];
+        const double ex1 = g.x[2] - g.x[0], ey1 = g.y[2] - g.y[0], ez1 = z[2] - z[0];
+        const double nx = ey0 * ez1 - ez0 * ey1, ny = ez0 * ex1 - ex0 * ez1, nz = ex0 * ey1 - ey0 * ex1;
+        const double n = sqrt(nx * nx + ny * ny + nz * nz);
+        const int64_t lb = (int64_t)(l - 1) * a.off, la = (int64_t)l * a.off;
+        double j[NH];
+#pragma unroll
+        for (int al = 0; al < NH; ++al) {
+            const double lo = below ? a.in0[fb[al][NV - 1] + lb] : 0.0;   // top node of the prism below
+            const double hi = above ? a.in0[fb[al][0] + la] : 0.0;        // bottom node of the prism above
+            j[al] = lo - hi;
+        }
+        double r[NH];
+        if constexpr (NH == 3) {
+            const double J = j[0] + j[1] + j[2];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) r[al] = n * (j[al] + J) * (1.0 / 24.0);
+        } else {
+            r[0] = n * j[0] * 0.5;
+        }
+        if constexpr (NV == 2) {
+#pragma unroll
+            for (int al = 0; al < NH; ++al) {
+                if (below) update(a.out0 + fb[al][1] + lb, r[al]);
+                if (above) update(a.out0 + fb[al][0] + la, -r[al]);
+            }
+        } else {
+#pragma unroll
+            for (int al = 0; al < NH; ++al) {
+                const double prev = from_below(-r[al]);
+                const double share = L.lsub == 0 ? carry[al] : prev;
+                carry[al] = __shfl(-r[al], min(L.sub * a.seg + a.seg - 1, 63), 64);
+                if (below) update(a.out0 + fb[al][0] + lb, r[al] + share);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch.
 
 ColArgs col_args(const LoopLaunch& P)
@@ -703,6 +792,25 @@ int32_t launch_column_loop(const LoopLaunch& P, hipStream_t stream)
         if (atomic) EXM_LAUNCH((k_direct_p1<F, EXM_RACE_ATOMIC>));                   \
         else EXM_LAUNCH((k_direct_p1<F, EXM_RACE_COLOUR>));                          \
     } while (0)
+    if (P.kernel == EXM_K_FACET_JUMP) {
+        switch (P.element) {
+        case EXM_ELEMENT_DG0DG0: EXM_LAUNCH((k_direct_facet<1, 1, false, EXM_RACE_ATOMIC>)); break;
+        case EXM_ELEMENT_DG1DG1: EXM_LAUNCH((k_direct_facet<3, 2, false, EXM_RACE_ATOMIC>)); break;
+        case EXM_ELEMENT_DG0DG1: EXM_LAUNCH((k_direct_facet<1, 2, false, EXM_RACE_ATOMIC>)); break;
+        case EXM_ELEMENT_DG1DG0: EXM_LAUNCH((k_direct_facet<3, 1, false, EXM_RACE_ATOMIC>)); break;
+        case EXM_ELEMENT_P1DG0:
+            if (atomic) EXM_LAUNCH((k_direct_facet<3, 1, true, EXM_RACE_ATOMIC>));
+            else EXM_LAUNCH((k_direct_facet<3, 1, true, EXM_RACE_COLOUR>));
+            break;
+        case EXM_ELEMENT_P1DG1:
+            if (atomic) EXM_LAUNCH((k_direct_facet<3, 2, true, EXM_RACE_ATOMIC>));
+            else EXM_LAUNCH((k_direct_facet<3, 2, true, EXM_RACE_COLOUR>));
+            break;
+        default: return fail(EXM_EUNSUPPORTED, "no facet kernel on element %d", P.element);
+        }
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
     switch (P.element) {
     case EXM_ELEMENT_P1P1:
         switch (P.kernel) {

@@ -379,8 +379,8 @@ int32_t staged_max_tile_cells(int32_t S) { return kPasses * (kThreads / S); }
 
 bool staged_supported(int32_t kernel, int32_t element)
 {
-    (void)kernel;
-    return element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1;
+    return kernel != EXM_K_FACET_JUMP &&
+           (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1);
 }
 
 template <int S>
