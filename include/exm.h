@@ -252,6 +252,14 @@ typedef struct {
                               /* independent and the grid runs chunk by chunk.  Same race    */
                               /* strategies and alignment as PIPELINED; other kernels run    */
                               /* PIPELINED                                                   */
+#define EXM_SCHED_GATHER 6    /* P1xP1 mass action: the loop turned to the output columns    */
+                              /* (owner computes).  A wavefront owns a base vertex and 62    */
+                              /* levels of its column, walks the fan of cells around it      */
+                              /* (each neighbouring column read once) and sums the rows of   */
+                              /* that vertex of the prisms around each level: every output   */
+                              /* DoF is written once, no atomics, colours, LDS or barriers.  */
+                              /* waves_per_block 1..4; the race is reported as               */
+                              /* EXM_RACE_OWNER; other kernels run DIRECT                    */
 
 typedef struct {
     int32_t race;              /* EXM_RACE_*                                             */

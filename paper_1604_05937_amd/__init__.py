@@ -20,7 +20,7 @@ from ._abi import (EXM_ELEMENT_DG0DG0, EXM_ELEMENT_DG1DG1, EXM_ELEMENT_NONE, EXM
                    EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_JAC, EXM_K_CUBIC_VJP, EXM_K_FACET_JUMP,
                    EXM_K_MASS,
                    EXM_RACE_ATOMIC,
-                   EXM_RACE_AUTO, EXM_RACE_COLOUR, EXM_RACE_OWNER, EXM_READ, EXM_SCHED_AUTO, EXM_SCHED_CHUNKED, EXM_SCHED_DIRECT, EXM_SCHED_PIPELINED,
+                   EXM_RACE_AUTO, EXM_RACE_COLOUR, EXM_RACE_OWNER, EXM_READ, EXM_SCHED_AUTO, EXM_SCHED_CHUNKED, EXM_SCHED_DIRECT, EXM_SCHED_GATHER, EXM_SCHED_PIPELINED,
                    EXM_SCHED_STAGED, EXM_SCHED_TILED, EXM_WRITE, ExmError)
 
 __all__ = ["Mesh", "Space", "Matrix", "par_loop", "ExmError", "ELEMENTS", "DELTA", "load_library", "stream_handle"]
@@ -228,6 +228,17 @@ def autotune(kernel: int, mesh: Mesh, coords, coord_space: Space, fields, stream
     best = _abi.exm_loop_opts()
     _abi.exm_autotune(kernel, mesh.handle, len(args), args, stream_handle(stream), ctypes.byref(best))
     return _opts_dict(best)
+
+
+def autotune_save(path: str):
+    """Write the launches the autotuner has chosen (a text table)."""
+    _abi.exm_autotune_save(path.encode())
+
+
+def autotune_load(path: str):
+    """Read a table written by autotune_save: loops without explicit options
+    take its launches."""
+    _abi.exm_autotune_load(path.encode())
 
 
 def sync(stream=None):

@@ -56,6 +56,7 @@ EXM_SCHED_TILED = 2
 EXM_SCHED_STAGED = 3
 EXM_SCHED_PIPELINED = 4
 EXM_SCHED_CHUNKED = 5
+EXM_SCHED_GATHER = 6
 
 STATUS_NAMES = {0: "EXM_OK", -1: "EXM_EINVAL", -2: "EXM_ERANGE", -3: "EXM_EOVERFLOW", -4: "EXM_ENOMEM",
                 -5: "EXM_EHIP", -6: "EXM_EUNSUPPORTED"}

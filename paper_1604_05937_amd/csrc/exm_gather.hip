@@ -1,0 +1,257 @@
+// GATHER schedule of the P1 x P1 mass action: the column loop turned around
+// to iterate the vertex columns of the output (owner computes).
+//
+// A wavefront owns one base vertex v and 62 consecutive levels of its column
+// (lanes hold levels l0 - 1 .. l0 + 62; the two end lanes are halo).  It walks
+// the fan of base cells around v in cyclic order, so that every neighbouring
+// vertex column is loaded once for the two cells that share it, and sums the
+// row of v of every prism around its levels: lane l evaluates prism (c, l)
+// for node v at the bottom and at the top, keeps the bottom row and passes
+// the top row one lane up (it is level l + 1's share).  Every output DoF is
+// written once by its owner: no atomics, no colours, no LDS and no barriers;
+// the neighbouring columns come from L2, since the fans of consecutive
+// vertices (in the RCM order) overlap.
+#include <algorithm>
+#include <cstring>
+
+#include "exm_elements.hpp"
+#include "exm_internal.hpp"
+#include "exm_tiled.hpp"
+
+namespace exm {
+namespace {
+
+constexpr int kOwned = 62;   // levels written per wavefront step (64 lanes, one halo lane each side)
+
+__device__ __forceinline__ unsigned xcd_block_g(unsigned b, unsigned G)
+{
+    const unsigned q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+struct GatherP1Args {
+    int32_t n_vertices, lam, n_steps, write;
+    int64_t fbase, xbase;          // column start of vertex w: base + w * (lam + 1)
+    const int32_t* __restrict__ fan_off;   // [n_vertices + 1]
+    const int32_t* __restrict__ fan;       // neighbour ids; bit 31: the entry starts a fan (no cell with the previous)
+    const double* __restrict__ X;          // coordinates, component-major
+    int64_t xn;
+    const double* __restrict__ f;
+    double* __restrict__ y;
+};
+
+// Row of node v (index 0) of the P1 x P1 mass action on one prism (the
+// sum-factorised form of p1_mass restricted to one vertex):
+//   y_v = (2A / 120) ((2 h_v + H) g_v + (h_v + H) G + sum_a h_a g_a),
+// g = V x per vertex at the bottom and at the top.
+__device__ __forceinline__ void p1_row(double s, const double h[3], const double xb[3], const double xt[3],
+                                       double& yb, double& yt)
+{
+    constexpr double sixth = 1.0 / 6.0;
+    const double H = h[0] + h[1] + h[2];
+    double gb[3], gt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gb[a] = (2.0 * xb[a] + xt[a]) * sixth;
+        gt[a] = (xb[a] + 2.0 * xt[a]) * sixth;
+    }
+    const double Gb = gb[0] + gb[1] + gb[2], Gt = gt[0] + gt[1] + gt[2];
+    const double HGb = h[0] * gb[0] + h[1] * gb[1] + h[2] * gb[2];
+    const double HGt = h[0] * gt[0] + h[1] * gt[1] + h[2] * gt[2];
+    const double d = 2.0 * h[0] + H, o = h[0] + H;
+    yb = s * (d * gb[0] + o * Gb + HGb);
+    yt = s * (d * gt[0] + o * Gt + HGt);
+}
+
+__global__ void __launch_bounds__(256) k_gather_p1(const GatherP1Args g)
+{
+    const int lane = threadIdx.x & 63;
+    // the wavefront's work item, made visibly uniform so that its indices live in scalar registers
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_g(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t v = wid / g.n_steps;
+    if (v >= g.n_vertices) return;   // uniform over the wavefront
+    const int l0 = (int)(wid - v * g.n_steps) * kOwned;
+    const int lev = l0 - 1 + lane;
+    const bool in = lev >= 0 && lev <= g.lam;   // a level of the column
+    const bool prism = lev >= 0 && lev < g.lam; // the prism above this level exists
+    const int64_t lamp = (int64_t)g.lam + 1;
+    const double* __restrict__ Z = g.X + 2 * g.xn;
+    // own column: f and z at this level and the next (the next lane's)
+    const int64_t fv = g.fbase + v * lamp, xv = g.xbase + v * lamp;
+    const double f0 = in ? g.f[fv + lev] : 0.0;
+    const double z0 = in ? Z[xv + lev] : 0.0;
+    const double f0n = __shfl_down(f0, 1, 64), z0n = __shfl_down(z0, 1, 64);
+    const double px0 = g.X[xv], py0 = g.X[g.xn + xv];
+    double acc_b = 0.0, acc_t = 0.0;
+    double fp = 0.0, fpn = 0.0, zp = 0.0, zpn = 0.0, pxp = 0.0, pyp = 0.0;   // previous neighbour
+    const int32_t e0 = g.fan_off[v], e1 = g.fan_off[v + 1];
+    // blocks of kBlk fan entries: every load of a block is issued before the
+    // first of its cells is evaluated, so the wavefront waits once per block
+    constexpr int kBlk = 4;
+    for (int32_t e = e0; e < e1; e += kBlk) {
+        int32_t ent[kBlk];
+        double f1[kBlk], z1[kBlk], px1[kBlk], py1[kBlk];
+#pragma unroll
+        for (int k = 0; k < kBlk; ++k) {
+            const bool has = e + k < e1;   // uniform over the wavefront
+            ent[k] = has ? g.fan[e + k] : 0;
+            const int64_t w = ent[k] & 0x7fffffff;
+            const int64_t fw = g.fbase + w * lamp, xw = g.xbase + w * lamp;
+            f1[k] = has && in ? g.f[fw + lev] : 0.0;
+            z1[k] = has && in ? Z[xw + lev] : 0.0;
+            px1[k] = has ? g.X[xw] : 0.0;
+            py1[k] = has ? g.X[g.xn + xw] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kBlk; ++k) {
+            if (e + k >= e1) break;
+            const double f1n = __shfl_down(f1[k], 1, 64), z1n = __shfl_down(z1[k], 1, 64);
+            if (ent[k] >= 0 && prism) {   // cell (v, previous, w)
+                const double twoA = fabs((pxp - px0) * (py1[k] - py0) - (px1[k] - px0) * (pyp - py0));
+                const double h[3] = {z0n - z0, zpn - zp, z1n - z1[k]};
+                const double xb[3] = {f0, fp, f1[k]};
+                const double xt[3] = {f0n, fpn, f1n};
+                double yb, yt;
+                p1_row(twoA * (1.0 / 120.0), h, xb, xt, yb, yt);
+                acc_b += yb;
+                acc_t += yt;
+            }
+            fp = f1[k];
+            fpn = f1n;
+            zp = z1[k];
+            zpn = z1n;
+            pxp = px1[k];
+            pyp = py1[k];
+        }
+    }
+    // level lev takes the bottom rows of the prisms above it and the top rows
+    // of the prisms below it (computed by the lane below)
+    const double below = __shfl_up(acc_t, 1, 64);
+    if (lane >= 1 && lane <= kOwned && in) {
+        const double val = acc_b + below;
+        if (g.write)
+            g.y[fv + lev] = val;
+        else
+            g.y[fv + lev] += val;
+    }
+}
+
+}  // namespace
+
+// Fans of base cells around every vertex, in cyclic order: for vertex v the
+// list n_0, n_1, ..., n_k of neighbouring vertices such that (v, n_i, n_i+1)
+// is a cell; a fan starts at a spoke with one cell (the boundary) where there
+// is one, and an interior fan repeats its first neighbour at the end.  A
+// vertex whose cells do not form one fan gets several, each entry that
+// starts a fan flagged with bit 31.
+int32_t build_vertex_fans(const exm_mesh* m, const VertexFans** out)
+{
+    std::lock_guard<std::mutex> lock(m->mu);
+    if (m->fans) {
+        *out = m->fans.get();
+        return EXM_OK;
+    }
+    const int32_t nv = m->n[0], nc = m->n[2];
+    const int32_t* cv = m->h_cell_vertex.data();
+    std::vector<int64_t> vstart(nv + 1, 0);
+    for (int64_t i = 0; i < (int64_t)nc * 3; ++i) vstart[cv[i] + 1]++;
+    for (int32_t v = 0; v < nv; ++v) vstart[v + 1] += vstart[v];
+    std::vector<int32_t> vcells(vstart[nv]);
+    {
+        std::vector<int64_t> fill(vstart.begin(), vstart.end() - 1);
+        for (int32_t c = 0; c < nc; ++c)
+            for (int a = 0; a < 3; ++a) vcells[fill[cv[c * 3 + a]]++] = c;
+    }
+    std::vector<int32_t> off(nv + 1, 0), fan;
+    fan.reserve((size_t)nc * 4);
+    std::vector<int32_t> na, nb;   // the two other vertices of every cell of the star
+    std::vector<char> used;
+    for (int32_t v = 0; v < nv; ++v) {
+        const int64_t b = vstart[v], n = vstart[v + 1] - b;
+        na.assign(n, 0);
+        nb.assign(n, 0);
+        used.assign(n, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t c = vcells[b + i];
+            int k = 0;
+            int32_t o[2] = {0, 0};
+            for (int a = 0; a < 3; ++a)
+                if (cv[c * 3 + a] != v && k < 2) o[k++] = cv[c * 3 + a];
+            na[i] = o[0];
+            nb[i] = o[1];
+        }
+        auto spokes = [&](int32_t w) {   // cells of the star that contain w
+            int cnt = 0;
+            for (int64_t i = 0; i < n; ++i) cnt += (na[i] == w) + (nb[i] == w);
+            return cnt;
+        };
+        int64_t left = n;
+        while (left > 0) {
+            // start at a boundary spoke if an unused cell has one
+            int64_t s = -1;
+            int32_t entry = 0;
+            for (int64_t i = 0; i < n && s < 0; ++i) {
+                if (used[i]) continue;
+                if (spokes(na[i]) == 1) { s = i; entry = na[i]; }
+                else if (spokes(nb[i]) == 1) { s = i; entry = nb[i]; }
+            }
+            if (s < 0) {
+                for (int64_t i = 0; i < n && s < 0; ++i)
+                    if (!used[i]) { s = i; entry = na[i]; }
+            }
+            fan.push_back(entry | (int32_t)0x80000000);
+            int64_t cur = s;
+            int32_t from = entry;
+            while (cur >= 0) {
+                used[cur] = 1;
+                --left;
+                const int32_t exit = na[cur] == from ? nb[cur] : na[cur];
+                fan.push_back(exit);
+                int64_t next = -1;
+                for (int64_t i = 0; i < n && next < 0; ++i)
+                    if (!used[i] && (na[i] == exit || nb[i] == exit)) next = i;
+                cur = next;
+                from = exit;
+            }
+        }
+        off[v + 1] = (int32_t)fan.size();
+    }
+    auto F = std::make_unique<VertexFans>();
+    int32_t st;
+    if ((st = F->off.upload(off.data(), off.size())) != EXM_OK) return st;
+    if ((st = F->fan.upload(fan.data(), fan.size())) != EXM_OK) return st;
+    F->n_entries = (int64_t)fan.size();
+    m->fans = std::move(F);
+    *out = m->fans.get();
+    return EXM_OK;
+}
+
+bool gather_supported(int32_t kernel, int32_t element) { return kernel == EXM_K_MASS && element == EXM_ELEMENT_P1P1; }
+
+int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, hipStream_t s)
+{
+    GatherP1Args g;
+    std::memset(&g, 0, sizeof(g));
+    g.n_vertices = P.fspace->mesh->n[0];
+    g.lam = P.n_layers;
+    g.n_steps = (P.n_layers + 1 + kOwned - 1) / kOwned;
+    g.write = P.write;
+    g.fbase = P.fspace->base[0];
+    g.xbase = P.xspace->base[0];
+    g.fan_off = fans->off.p;
+    g.fan = fans->fan.p;
+    g.X = P.X;
+    g.xn = P.xspace->n_dofs;
+    g.f = P.in[0];
+    g.y = P.out[0];
+    if (g.n_vertices == 0) return EXM_OK;
+    const int64_t waves = (int64_t)g.n_vertices * g.n_steps;
+    const int64_t blocks = (waves + wpb - 1) / wpb;
+    if (blocks * wpb > INT32_MAX) return fail(EXM_ERANGE, "grid too large");
+    hipLaunchKernelGGL(k_gather_p1, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+}  // namespace exm

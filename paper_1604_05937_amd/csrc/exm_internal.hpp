@@ -105,6 +105,13 @@ struct TilePlan {
     int64_t n_cell_entries = 0;        // owner plan: cells summed over tiles (>= n_cells)
 };
 
+// Fans of base cells around every vertex (the GATHER schedule).
+struct VertexFans {
+    DevBuf<int32_t> off;   // [n_vertices + 1]
+    DevBuf<int32_t> fan;   // neighbouring vertices in fan order; bit 31 flags the start of a fan
+    int64_t n_entries = 0;
+};
+
 }  // namespace exm
 
 struct exm_mesh {
@@ -119,6 +126,7 @@ struct exm_mesh {
     mutable std::mutex mu;
     mutable std::unique_ptr<exm::Colouring> colouring;   // built on first use
     mutable std::vector<std::unique_ptr<exm::TilePlan>> plans;
+    mutable std::unique_ptr<exm::VertexFans> fans;        // built on first use
 };
 
 struct exm_space {
@@ -140,6 +148,7 @@ namespace exm {
 int32_t build_colouring(const exm_mesh* m, const Colouring** out);
 int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out);
 int32_t build_owner_plan(const exm_mesh* m, int32_t target, const TilePlan** out);
+int32_t build_vertex_fans(const exm_mesh* m, const VertexFans** out);
 
 // Work decomposition of the column loop.
 struct LoopShape {

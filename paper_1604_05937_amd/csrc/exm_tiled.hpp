@@ -63,6 +63,8 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
 size_t chunk_lds_bytes(int32_t vstride, int32_t S);
 int32_t chunk_count(int32_t n_layers, int32_t S);
 int32_t launch_chunked(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t S, size_t lds, hipStream_t s);
+bool gather_supported(int32_t kernel, int32_t element);
+int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, hipStream_t s);
 size_t tiled_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t seg);
 int32_t launch_tiled(const LoopLaunch& P, const TileArgs& t, int32_t threads, size_t lds, hipStream_t s);
 

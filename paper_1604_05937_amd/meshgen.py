@@ -195,6 +195,16 @@ def tri_rectangle(nx: int, ny: int, h: float, jitter: float = 0.2, seed: int = S
     return _assemble(xy, cells, order, seed_order, meta)
 
 
+def tri_checkerboard(n: int, order: str = "rcm", seed_order: int = SEED_ORDER) -> BaseMesh:
+    """The n x n square with every other quad removed (a checkerboard): the
+    cells around an interior vertex form two fans that meet only at it."""
+    xy, cells, _ = _structured_rectangle(n, n, 1.0 / n)
+    q = np.arange(cells.shape[0]) // 2
+    keep = ((q % n) + (q // n)) % 2 == 0
+    meta = dict(nx=n, ny=n, h=1.0 / n, jitter=0.0, checkerboard=True)
+    return _assemble(xy, cells[keep], order, seed_order, meta)
+
+
 def level_heights(n_layers: int, height: float = 1.0) -> np.ndarray:
     """z of the n_layers+1 levels of a flat extrusion: l * height / n_layers."""
     return np.arange(n_layers + 1, dtype=np.float64) * (height / n_layers)
