@@ -51,3 +51,26 @@ def test_python_wrappers_raise():
     with pytest.raises(_abi.ExmError) as e:
         _abi.exm_par_loop(99, None, 0, None, None, None)
     assert e.value.status == _abi.EXM_EINVAL
+
+
+def test_new_entry_points_validate_on_the_host():
+    lib = _abi.load()
+    h = ctypes.c_void_p()
+    cv = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    # layer ranges: empty, reversed and beyond n_layers are refused before any device work
+    for bad in ([[0, 0], [0, 3]], [[2, 1], [0, 3]], [[0, 4], [0, 3]], [[-1, 2], [0, 3]]):
+        lay = np.array(bad, dtype=np.int32)
+        st = lib.exm_mesh_create_var(4, 0, 2, cv.ctypes.data_as(ctypes.c_void_p), None, 3,
+                                     lay.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+        assert st == _abi.EXM_ERANGE, (bad, st)
+    assert lib.exm_mesh_create_var(4, 0, 2, cv.ctypes.data_as(ctypes.c_void_p), None, 3, None,
+                                   ctypes.byref(h)) == _abi.EXM_EINVAL
+    assert lib.exm_mesh_entity_layers(None, 0, None, None) == _abi.EXM_EINVAL
+    assert lib.exm_matrix_create(None, ctypes.byref(h)) == _abi.EXM_EINVAL
+    assert lib.exm_matrix_info(None, None, None, None, None) == _abi.EXM_EINVAL
+    assert lib.exm_matrix_assemble(_abi.EXM_K_MASS, None, 0, None, None) == _abi.EXM_EINVAL
+    assert lib.exm_matrix_spmv(None, None, None, _abi.EXM_WRITE, None) == _abi.EXM_EINVAL
+    assert lib.exm_matrix_csr(None, None, None, None, None) == _abi.EXM_EINVAL
+    # the Jacobian and the facet loop are kernels of their own entry points only
+    assert lib.exm_par_loop(_abi.EXM_K_CUBIC_JAC, None, 0, None, None, None) == _abi.EXM_EINVAL
+    assert lib.exm_par_loop(_abi.EXM_K_FACET_JUMP, None, 0, None, None, None) == _abi.EXM_EINVAL
