@@ -120,33 +120,52 @@ __device__ __forceinline__ double mass_entry(double twoA, const double h[3], int
     return twoA * T * V;
 }
 
-// Entry (a_i, b_i), (a_j, b_j) of the Jacobian of the cubic residual on a P1
-// prism, integral 3 u^2 phi_j phi_i det J, with the rule of the residual
-// (7-point Radon triangle x 3-point Gauss-Legendre, exact for this degree).
-// ub, ut: u at the bottom and top node of the three vertices.
-__device__ __forceinline__ double cubic_jac_entry(double twoA, const double h[3], const double ub[3],
-                                                  const double ut[3], int ai, int aj, int bi, int bj)
+// Jacobian of the cubic residual on a P1 prism, integral 3 u^2 phi_j phi_i
+// det J, with the rule of the residual (7-point Radon triangle x 3-point
+// Gauss-Legendre, exact for this degree).  Per prism, the vertical moments
+// of 3 u^2 det J at every triangle point,
+//     m[t][k] = 3 w_t dj_t sum_z w_z u(t, z)^2 (1 - z)^(2 - k) z^k,  k = 0, 1, 2,
+// serve all its entries: entry (a_i, b_i), (a_j, b_j) = sum_t lambda_ai
+// lambda_aj m[t][b_i + b_j].  ub, ut: u at the bottom and top node of the
+// three vertices.
+__device__ __forceinline__ void cubic_jac_moments(double twoA, const double h[3], const double ub[3],
+                                                  const double ut[3], double m[7][3])
 {
     using namespace cubic;
-    double acc = 0.0;
 #pragma unroll
     for (int t = 0; t < 7; ++t) {
         const double dj = twoA * (kLam[t][0] * h[0] + kLam[t][1] * h[1] + kLam[t][2] * h[2]);
         const double u0 = kLam[t][0] * ub[0] + kLam[t][1] * ub[1] + kLam[t][2] * ub[2];
         const double u1 = kLam[t][0] * ut[0] + kLam[t][1] * ut[1] + kLam[t][2] * ut[2] - u0;
-        const double li = ai == 0 ? kLam[t][0] : (ai == 1 ? kLam[t][1] : kLam[t][2]);
-        const double lj = aj == 0 ? kLam[t][0] : (aj == 1 ? kLam[t][1] : kLam[t][2]);
-        double sz = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
         for (int z = 0; z < 3; ++z) {
             const double u = u0 + kZ[z] * u1;
-            const double pi = bi ? kZ[z] : 1.0 - kZ[z];
-            const double pj = bj ? kZ[z] : 1.0 - kZ[z];
-            sz += kWz[z] * u * u * pi * pj;
+            const double g = kWz[z] * u * u;
+            s0 += g * (1.0 - kZ[z]) * (1.0 - kZ[z]);
+            s1 += g * (1.0 - kZ[z]) * kZ[z];
+            s2 += g * kZ[z] * kZ[z];
         }
-        acc += kWt[t] * dj * li * lj * sz;
+        const double c = 3.0 * kWt[t] * dj;
+        m[t][0] = c * s0;
+        m[t][1] = c * s1;
+        m[t][2] = c * s2;
     }
-    return 3.0 * acc;
+}
+
+__device__ __forceinline__ double cubic_jac_entry(const double m[7][3], int ai, int aj, int bb)
+{
+    using namespace cubic;
+    // weights instead of an index, so that the moments stay in registers
+    const double w0 = bb == 0 ? 1.0 : 0.0, w1 = bb == 1 ? 1.0 : 0.0, w2 = bb == 2 ? 1.0 : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) {
+        const double li = ai == 0 ? kLam[t][0] : (ai == 1 ? kLam[t][1] : kLam[t][2]);
+        const double lj = aj == 0 ? kLam[t][0] : (aj == 1 ? kLam[t][1] : kLam[t][2]);
+        acc += li * lj * (w0 * m[t][0] + w1 * m[t][1] + w2 * m[t][2]);
+    }
+    return acc;
 }
 
 __device__ __forceinline__ unsigned xcd_block_m(unsigned b, unsigned G)
@@ -157,7 +176,7 @@ __device__ __forceinline__ unsigned xcd_block_m(unsigned b, unsigned G)
 
 struct GatherArgs {
     int32_t lam, L, band;
-    int64_t n_items;                      // pattern entries x slots
+    int64_t n_pat;                        // pattern entries
     const int64_t* __restrict__ pc_ptr;   // [n_pat + 1] contributions of every pattern entry
     const int32_t* __restrict__ pc_cell;  // base cell of every contribution (ascending within an entry)
     const int32_t* __restrict__ pc_info;  // a_i | a_j << 3 | b_i << 6 | b_j << 8 | top_i << 10 | top_j << 11
@@ -169,34 +188,42 @@ struct GatherArgs {
     double* __restrict__ val;             // [n_pat][band][L]
 };
 
-// One thread per (pattern entry p, slot s); consecutive threads take
-// consecutive slots of one entry, so the contribution list is read once per
-// wavefront and the values are written in one coalesced sweep.
+// One wavefront per (pattern entry p, 64 consecutive slots): the entry, its
+// contribution list, the cells and their base geometry are the same for
+// every lane (scalar loads); the lanes read z (and u) of their own levels,
+// contiguous along the columns, and write their values in one coalesced
+// sweep.  (Issuing the next cell's loads before the current cell's entries
+// measured slower: the registers it takes cost more occupancy than the
+// latency it hides.)
 template <int HK, int VK, bool JAC>
 __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
 {
-    const int64_t idx = (int64_t)xcd_block_m(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (idx >= g.n_items) return;
-    const int64_t p = idx / g.L;
-    const int s = (int)(idx - p * g.L);
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_m(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int nsteps = (g.L + 63) >> 6;
+    const int64_t p = wid / nsteps;
+    if (p >= g.n_pat) return;   // uniform over the wavefront
+    const int s = (int)(wid - p * nsteps) * 64 + lane;
+    const bool act = s < g.L;
     double acc[3] = {0.0, 0.0, 0.0};
     int64_t e = g.pc_ptr[p];
     const int64_t end = g.pc_ptr[p + 1];
+    const double* __restrict__ Z = g.X + 2 * g.xn;
     while (e < end) {
         const int32_t c = g.pc_cell[e];
-        int xb[3];
         double x[3], y[3], hlo[3], hhi[3], ul[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            xb[a] = g.xmap[(int64_t)c * 6 + 2 * a];
-            x[a] = g.X[xb[a]];
-            y[a] = g.X[g.xn + xb[a]];
+            const int xb = g.xmap[(int64_t)c * 6 + 2 * a];
+            x[a] = g.X[xb];
+            y[a] = g.X[g.xn + xb];
             // z at levels s - 1, s, s + 1 (those inside the column)
             double z[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const int lev = s - 1 + k;
-                z[k] = lev >= 0 && lev <= g.lam ? g.X[2 * g.xn + xb[a] + lev] : 0.0;
+                z[k] = act && lev >= 0 && lev <= g.lam ? Z[xb + lev] : 0.0;
             }
             hlo[a] = z[1] - z[0];   // layer s - 1
             hhi[a] = z[2] - z[1];   // layer s
@@ -205,30 +232,42 @@ __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const int lev = s - 1 + k;
-                    ul[a][k] = lev >= 0 && lev <= g.lam ? g.u[fb + lev] : 0.0;
+                    ul[a][k] = act && lev >= 0 && lev <= g.lam ? g.u[fb + lev] : 0.0;
                 }
             }
         }
         const double twoA = twice_area(x, y);
+        double mlo[7][3], mhi[7][3];   // Jacobian: moments of the prisms of layers s - 1 and s
+        if constexpr (JAC) {
+            double ub[3], ut[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ub[a] = ul[a][0];
+                ut[a] = ul[a][1];
+            }
+            cubic_jac_moments(twoA, hlo, ub, ut, mlo);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ub[a] = ul[a][1];
+                ut[a] = ul[a][2];
+            }
+            cubic_jac_moments(twoA, hhi, ub, ut, mhi);
+        }
         for (; e < end && g.pc_cell[e] == c; ++e) {
             const int info = g.pc_info[e];
             const int ai = info & 7, aj = (info >> 3) & 7, bi = (info >> 6) & 3, bj = (info >> 8) & 3;
             const int ti = (info >> 10) & 1, tj = (info >> 11) & 1;
             const int l = s - ti;   // the prism: the row node is its top (layer s - 1) or bottom / inside (layer s)
             if (l < 0 || l >= g.lam) continue;
-            double h[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) h[a] = ti ? hlo[a] : hhi[a];
             double v;
             if constexpr (JAC) {
-                double ub[3], ut[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    ub[a] = ti ? ul[a][0] : ul[a][1];
-                    ut[a] = ti ? ul[a][1] : ul[a][2];
-                }
-                v = cubic_jac_entry(twoA, h, ub, ut, ai, aj, bi, bj);
+                const double vlo = cubic_jac_entry(mlo, ai, aj, bi + bj);
+                const double vhi = cubic_jac_entry(mhi, ai, aj, bi + bj);
+                v = ti ? vlo : vhi;
             } else {
+                double h[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) h[a] = ti ? hlo[a] : hhi[a];
                 v = mass_entry<HK, VK>(twoA, h, ai, aj, bi, bj);
             }
             const int d = tj - ti;
@@ -237,6 +276,7 @@ __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
             else acc[2] += v;
         }
     }
+    if (!act) return;
     if (g.band == 3) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) g.val[(p * 3 + d) * g.L + s] = acc[d];
@@ -247,6 +287,7 @@ __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
 
 struct RowArgs {
     int32_t lam, L, band, write;
+    int32_t n_classes;
     int64_t n_items;                      // classes x slots
     const int32_t* __restrict__ c0;       // [n_classes] DoF at slot 0
     const int32_t* __restrict__ wk;       // [n_classes] stride | kind << 16
@@ -261,15 +302,21 @@ struct RowArgs {
     double* __restrict__ cval;
 };
 
-// y = A x, one thread per row (class r, slot s).
+// y = A x, one wavefront per (class r, 64 consecutive slots): the pattern
+// row and the coupled classes are the same for every lane (scalar loads);
+// each lane reads its slot's values (coalesced across the lanes) and x at the
+// neighbouring slots of the coupled class.
 __global__ void __launch_bounds__(256) k_mat_spmv(const RowArgs a)
 {
-    const int64_t idx = (int64_t)xcd_block_m(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (idx >= a.n_items) return;
-    const int32_t r = (int32_t)(idx / a.L);
-    const int s = (int)(idx - (int64_t)r * a.L);
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_m(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int nsteps = (a.L + 63) >> 6;
+    const int32_t r = (int32_t)(wid / nsteps);
+    if (r >= a.n_classes) return;   // uniform over the wavefront
+    const int s = (int)(wid - (int64_t)r * nsteps) * 64 + lane;
     const int wr = a.wk[r] & 0xffff, kr = a.wk[r] >> 16;
-    if (kr == kKindV && s == a.lam) return;   // no such row
+    if (s >= a.L || (kr == kKindV && s == a.lam)) return;   // no such row
     double acc = 0.0;
     for (int32_t p = a.pptr[r]; p < a.pptr[r + 1]; ++p) {
         const int32_t q = a.pcol[p];
@@ -532,7 +579,7 @@ int32_t exm_matrix_assemble(int32_t kernel, exm_matrix* A, int32_t nargs, const 
     g.lam = A->lam;
     g.L = A->L;
     g.band = A->band;
-    g.n_items = A->n_pat * A->L;
+    g.n_pat = A->n_pat;
     g.pc_ptr = A->pc_ptr.p;
     g.pc_cell = A->pc_cell.p;
     g.pc_info = A->pc_info.p;
@@ -542,9 +589,10 @@ int32_t exm_matrix_assemble(int32_t kernel, exm_matrix* A, int32_t nargs, const 
     g.fmap = A->space->d_map.p;
     g.u = jac ? (const double*)args[1].data : nullptr;
     g.val = A->val.p;
-    const int bs = 256;
-    const int64_t nb = (g.n_items + bs - 1) / bs;
-    EXM_CHECK(nb < INT32_MAX, EXM_EOVERFLOW, "grid too large");
+    const int bs = 256;   // four wavefronts, each one (pattern entry, 64 slots)
+    const int64_t waves = A->n_pat * ((A->L + 63) / 64);
+    EXM_CHECK(waves < INT32_MAX, EXM_EOVERFLOW, "grid too large");
+    const int64_t nb = (waves + 3) / 4;
     hipStream_t hs = (hipStream_t)stream;
     const ElementKinds ek = element_kinds(A->element);
 #define EXM_GATHER(HK, VK, J) hipLaunchKernelGGL((k_mat_gather<HK, VK, J>), dim3((unsigned)nb), dim3(bs), 0, hs, g)
@@ -566,6 +614,7 @@ static RowArgs row_args(const exm_matrix* A)
     a.lam = A->lam;
     a.L = A->L;
     a.band = A->band;
+    a.n_classes = A->n_classes;
     a.n_items = (int64_t)A->n_classes * A->L;
     a.c0 = A->c0.p;
     a.wk = A->wk.p;
@@ -586,8 +635,10 @@ int32_t exm_matrix_spmv(const exm_matrix* A, const double* x, double* y, int32_t
     a.write = access == EXM_WRITE;
     a.x = x;
     a.y = y;
-    const int bs = 256;
-    const int64_t nb = (a.n_items + bs - 1) / bs;
+    const int bs = 256;   // four wavefronts, each one (class, 64 slots)
+    const int64_t waves = (int64_t)A->n_classes * ((A->L + 63) / 64);
+    EXM_CHECK(waves < INT32_MAX, EXM_EOVERFLOW, "grid too large");
+    const int64_t nb = (waves + 3) / 4;
     hipLaunchKernelGGL(k_mat_spmv, dim3((unsigned)nb), dim3(bs), 0, (hipStream_t)stream, a);
     EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;
