@@ -87,6 +87,10 @@ def _lib():
                                     P, P, P, ctypes.c_int32, P, P,
                                     P, P, P, P, P, P, ctypes.c_int32,
                                     ctypes.c_int32, P, P, P, P]
+    lib.oracle_alg1_number_mixed.restype = ctypes.c_int64
+    lib.oracle_alg1_number_mixed.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P]
+    lib.oracle_stencil_mixed.restype = ctypes.c_int64
+    lib.oracle_stencil_mixed.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P]
     lib.oracle_facet_loop.restype = None
     lib.oracle_facet_loop.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P,
                                       ctypes.c_int32, ctypes.c_int32, P, P, P, P, P]
@@ -341,6 +345,72 @@ def number(counts, n_layers: int, delta, cell_vertex, cell_edge=None, layers=Non
                            _ptr(first[0]), _ptr(first[1]), _ptr(first[2]), _ptr(lmap))
     return Numbering(tuple(int(x) for x in counts), n_layers, delta, int(n_dofs), first, lmap, offsets, edim,
                      lo, hi, np.ascontiguousarray(hi[2] - lo[2], dtype=np.int32))
+
+
+@dataclass
+class MixedNumbering:
+    """Algorithm 1 with a DoF count per entity: dofs[d1] is [N_d1, 2]
+    (horizontal, vertical DoFs of every base entity of dimension d1)."""
+    counts: tuple
+    n_layers: int
+    dofs: list
+    n_dofs: int
+    first: list                 # first[d1]: [N_d1, lam+1, 2] int64
+    list_off: np.ndarray        # [N2 + 1] int64
+    lmap: np.ndarray            # [list_off[-1]] int64, bottom-layer lists
+    offsets: np.ndarray         # [list_off[-1]] int32, vertical offset of every entry
+
+    def column_starts(self, d1: int) -> np.ndarray:
+        return self.first[d1][:, 0, 0].copy()
+
+
+def number_mixed(counts, n_layers: int, dofs, cell_vertex, cell_edge=None) -> MixedNumbering:
+    lib = _lib()
+    dofs = [np.ascontiguousarray(np.asarray(d, dtype=np.int32).reshape(int(counts[k]), 2)) for k, d in enumerate(dofs)]
+    first = [np.full((int(counts[d]), n_layers + 1, 2), -1, dtype=np.int64) for d in range(3)]
+    cnt = np.asarray(counts, dtype=np.int32)
+    n_dofs = lib.oracle_alg1_number_mixed(_ptr(cnt), n_layers, _ptr(dofs[0]), _ptr(dofs[1]), _ptr(dofs[2]),
+                                          _ptr(first[0]), _ptr(first[1]), _ptr(first[2]))
+    cv = np.ascontiguousarray(cell_vertex, dtype=np.int32)
+    ce = None if cell_edge is None else np.ascontiguousarray(cell_edge, dtype=np.int32)
+    n2 = int(counts[2])
+    off = np.zeros(n2 + 1, dtype=np.int64)
+    total = lib.oracle_stencil_mixed(n2, n_layers, _ptr(dofs[0]), _ptr(dofs[1]), _ptr(dofs[2]), _ptr(cv), _ptr(ce),
+                                     _ptr(first[0]), _ptr(first[1]), _ptr(first[2]), _ptr(off), None, None)
+    lmap = np.zeros(total, dtype=np.int64)
+    offsets = np.zeros(total, dtype=np.int32)
+    lib.oracle_stencil_mixed(n2, n_layers, _ptr(dofs[0]), _ptr(dofs[1]), _ptr(dofs[2]), _ptr(cv), _ptr(ce),
+                             _ptr(first[0]), _ptr(first[1]), _ptr(first[2]), _ptr(off), _ptr(lmap), _ptr(offsets))
+    return MixedNumbering(tuple(int(x) for x in counts), n_layers, dofs, int(n_dofs), first, off, lmap, offsets)
+
+
+def mixed_dg_mass(mesh, n_layers: int, vertex_coords: np.ndarray, cell_ndof, x: np.ndarray, absf: bool = False):
+    """y = M x on the mixed-degree DG space whose cell c carries DG0 x DG0
+    (cell_ndof[c] = 1) or DG1 x DG1 (6), numbered by number_mixed.  DG columns
+    are independent, so on the DG0 cells y is the DG0 mass action of those
+    cells and on the DG1 cells the DG1 one: par_loop over each cell subset on
+    the uniform space of that degree, carried between the two numberings DoF
+    by DoF.  Returns (y, numbering)."""
+    cell_ndof = np.asarray(cell_ndof, dtype=np.int32)
+    dofs = [np.zeros((mesh.n_vertices, 2), np.int32), np.zeros((mesh.n_edges, 2), np.int32),
+            np.stack([np.zeros_like(cell_ndof), cell_ndof], axis=1)]
+    num = number_mixed(mesh.counts, n_layers, dofs, mesh.cell_vertex, mesh.cell_edge)
+    y = np.zeros(num.n_dofs)
+    x = np.asarray(x, dtype=np.float64)
+    lay = np.arange(n_layers)
+    for name, k in (("DG0", 1), ("DG1", 6)):
+        cells = np.nonzero(cell_ndof == k)[0]
+        if cells.size == 0:
+            continue
+        pr = Problem(mesh, n_layers, name, vertex_coords)
+        pos = lay[None, :, None] * k + np.arange(k)[None, None, :]
+        mix = (num.lmap[num.list_off[cells]][:, None, None] + pos).ravel()
+        uni = (pr.num_v.lmap[cells, 0][:, None, None] + pos).ravel()
+        xu = np.zeros(pr.n_dofs)
+        xu[uni] = x[mix]
+        yu = pr.mass_abs(xu, cells=cells) if absf else pr.mass(xu, cells=cells)
+        y[mix] = yu[uni]
+    return y, num
 
 
 def coordinate_field(num_x: Numbering, vertex_coords: np.ndarray) -> np.ndarray:

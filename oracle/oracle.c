@@ -443,3 +443,76 @@ void oracle_facet_loop(int64_t n_cells, int32_t lam, const int64_t* mapx, const 
     }
     free(dv);
 }
+
+/*
+ * Algorithm 1 with a DoF count per entity: the paper fixes the count per
+ * entity type for its exposition and notes that the algorithm does not need
+ * it (Section 5).  Base entity (d1, i) carries dofs_d1[2i] DoFs on each of
+ * its horizontal entities and dofs_d1[2i + 1] on each vertical one; the
+ * counter visits the entities exactly as oracle_alg1_number does.  first_d
+ * as there (an entity without DoFs still records the counter).
+ */
+int64_t oracle_alg1_number_mixed(const int32_t counts[3], int32_t lam, const int32_t* dofs0, const int32_t* dofs1,
+                                 const int32_t* dofs2, int64_t* first0, int64_t* first1, int64_t* first2)
+{
+    int64_t* first[3] = {first0, first1, first2};
+    const int32_t* dofs[3] = {dofs0, dofs1, dofs2};
+    int64_t c = 0;
+    for (int d1 = 0; d1 < 3; ++d1) {
+        for (int64_t i = 0; i < counts[d1]; ++i) {
+            int64_t* f = first[d1] + i * (int64_t)(lam + 1) * 2;
+            const int32_t nh = dofs[d1][2 * i], nv = dofs[d1][2 * i + 1];
+            for (int32_t l = 0; l < lam; ++l) {
+                f[l * 2 + 0] = c;
+                c += nh;
+                f[l * 2 + 1] = c;
+                c += nv;
+            }
+            f[lam * 2 + 0] = c;
+            c += nh;
+            f[lam * 2 + 1] = -1;
+        }
+    }
+    return c;
+}
+
+/*
+ * Explicit lists of a space with a DoF count per entity: the list of cell c
+ * has its own length (list_off[c] .. list_off[c + 1]); entries in the order
+ * of oracle_stencil (closure entities vertex 0, 1, 2, edge 0, 1, 2, cell; per
+ * entity its bottom, top and vertical DoFs), for the bottom layer; the
+ * vertical offset of every entry is the entity's DoFs per level (Algorithm 2
+ * per entity).  With lmap NULL only list_off is filled.  Returns the total
+ * length.
+ */
+int64_t oracle_stencil_mixed(int64_t n_cells, int32_t lam, const int32_t* dofs0, const int32_t* dofs1,
+                             const int32_t* dofs2, const int32_t* cell_vertex, const int32_t* cell_edge,
+                             const int64_t* first0, const int64_t* first1, const int64_t* first2,
+                             int64_t* list_off, int64_t* lmap, int32_t* offsets)
+{
+    const int64_t* first[3] = {first0, first1, first2};
+    const int32_t* dofs[3] = {dofs0, dofs1, dofs2};
+    int64_t p = 0;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        list_off[c] = p;
+        for (int e = 0; e < 7; ++e) {
+            const int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
+            int64_t i;
+            if (d == 0) i = cell_vertex[c * 3 + e];
+            else if (d == 1) i = cell_edge ? cell_edge[c * 3 + (e - 3)] : -1;
+            else i = c;
+            if (i < 0) continue;
+            const int32_t nh = dofs[d][2 * i], nv = dofs[d][2 * i + 1];
+            if (!lmap) {
+                p += 2 * nh + nv;
+                continue;
+            }
+            const int64_t* f = first[d] + i * (int64_t)(lam + 1) * 2;
+            for (int j = 0; j < nh; ++j) { lmap[p] = f[0] + j; offsets[p++] = nh + nv; }       /* bottom, level 0 */
+            for (int j = 0; j < nh; ++j) { lmap[p] = f[2] + j; offsets[p++] = nh + nv; }       /* top, level 1 */
+            for (int j = 0; j < nv; ++j) { lmap[p] = f[1] + j; offsets[p++] = nh + nv; }       /* vertical, interval 0 */
+        }
+    }
+    list_off[n_cells] = p;
+    return p;
+}

@@ -264,6 +264,21 @@ def layer_ranges(mesh: BaseMesh, n_layers: int, kind: str = "bathymetry", depth:
     return np.stack([b, t], axis=1).astype(np.int32)
 
 
+def cell_degrees(mesh: BaseMesh, frac_dg1: float = 0.5, seed: int = SEED_MESH + 30) -> np.ndarray:
+    """DoFs per layer of every cell of a mixed-degree DG space: 6 (DG1 x DG1)
+    on a seeded random fraction frac_dg1 of the cells, 1 (DG0 x DG0) on the
+    rest."""
+    rng = np.random.default_rng(seed)
+    return np.where(rng.random(mesh.n_cells) < frac_dg1, 6, 1).astype(np.int32)
+
+
+def entity_dofs(mesh: BaseMesh, hi: int = 3, seed: int = SEED_MESH + 31) -> list:
+    """A DoF count per entity, uniform in 0 .. hi - 1 for the horizontal and the
+    vertical entities of every base vertex, edge and cell: [N_d, 2] each."""
+    rng = np.random.default_rng(seed)
+    return [rng.integers(0, hi, (n, 2)).astype(np.int32) for n in mesh.counts]
+
+
 def uniform_values(n: int, seed: int = SEED_FIELD, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     """n float64 values, U[lo, hi], from numpy's PCG64 with the given seed."""
     return np.random.default_rng(seed).uniform(lo, hi, size=n)

@@ -60,13 +60,20 @@ def classify(ent: frozenset, mesh, edge_index, cell_index):
     return (d1, d2), i, levels[0]
 
 
-def bruteforce_numbering(mesh, n_layers, delta, layers=None):
+def bruteforce_numbering(mesh, n_layers, delta, layers=None, dofs=None):
     """Vertical-innermost numbering obtained by sorting all (entity, j) keys
     of the explicit 3D mesh by (d1, i, l, d2, j).
+
+    dofs: optional per-entity counts, dofs[d1][i] = (horizontal, vertical),
+    in place of the per-type table delta.
 
     Returns (numbers, stencils): numbers[((d1, d2), i, l)] = first DoF,
     stencils[(c, l)] = the DoF list of that prism in stencil order."""
     delta = np.asarray(delta).reshape(3, 2)
+
+    def count(d1, i, d2):
+        return int(dofs[d1][i][d2]) if dofs is not None else int(delta[d1, d2])
+
     edge_index = {(int(a), int(b)): e for e, (a, b) in enumerate(mesh.edge_vertex)}
     cell_index = {frozenset(int(x) for x in mesh.cell_vertex[c]): c for c in range(mesh.n_cells)}
     prisms = prism_entities(mesh, n_layers, layers)
@@ -78,7 +85,7 @@ def bruteforce_numbering(mesh, n_layers, delta, layers=None):
                     entities[ent] = classify(ent, mesh, edge_index, cell_index)
     keys = []
     for ent, ((d1, d2), i, l) in entities.items():
-        for j in range(int(delta[d1, d2])):
+        for j in range(count(d1, i, d2)):
             keys.append((d1, i, l, d2, j))
     keys.sort()
     first = {}
@@ -90,8 +97,8 @@ def bruteforce_numbering(mesh, n_layers, delta, layers=None):
         row = []
         for bot, top, vert in closure:
             (d1, _), ib, lb = entities[bot]
-            nh = int(delta[d1, 0])
-            nv = int(delta[d1, 1])
+            nh = count(d1, ib, 0)
+            nv = count(d1, ib, 1)
             row += [first[((d1, 0), ib, lb)] + j for j in range(nh)]
             (_, _), it, lt = entities[top]
             row += [first[((d1, 0), it, lt)] + j for j in range(nh)]

@@ -145,3 +145,53 @@ def test_variable_layers_reduce_to_uniform():
         for d in range(3):
             if a.first[d] is not None:
                 np.testing.assert_array_equal(a.first[d], b.first[d])
+
+
+def _random_entity_dofs(mesh, seed, hi=3):
+    rng = np.random.default_rng(seed)
+    return [rng.integers(0, hi, (n, 2)).astype(np.int32) for n in mesh.counts]
+
+
+@pytest.mark.parametrize("lam", [1, 3, 4])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_entity_dofs_match_bruteforce(lam, seed):
+    # a DoF count per entity (the per-type constant of the exposition relaxed):
+    # the counter loop against sorting every (entity, j) key of the explicit mesh
+    mesh = meshgen.tri_square(3, jitter=0.2, order="random")
+    dofs = _random_entity_dofs(mesh, seed)
+    num = oracle.number_mixed(mesh.counts, lam, dofs, mesh.cell_vertex, mesh.cell_edge)
+    n, first, stencils, _ = bruteforce.bruteforce_numbering(mesh, lam, np.zeros((3, 2)), dofs=dofs)
+    assert num.n_dofs == n
+    for ((d1, d2), i, l), f in first.items():
+        assert num.first[d1][i, l, d2] == f
+    for (c, l), row in stencils.items():
+        a, b = num.list_off[c], num.list_off[c + 1]
+        got = num.lmap[a:b] + l * num.offsets[a:b].astype(np.int64)
+        assert got.tolist() == row, (c, l)
+
+
+def test_entity_dofs_reduce_to_the_type_table():
+    mesh = meshgen.tri_square(4)
+    lam = 5
+    for space in ("P1", "P2", "DG1", "DG1xCG1", "CG1xDG1"):
+        delta = oracle.delta_table(*oracle.SPACES[space])
+        dofs = [np.tile(delta[d], (mesh.counts[d], 1)) for d in range(3)]
+        mix = oracle.number_mixed(mesh.counts, lam, dofs, mesh.cell_vertex, mesh.cell_edge)
+        uni = oracle.number(mesh.counts, lam, delta, mesh.cell_vertex, mesh.cell_edge)
+        assert mix.n_dofs == uni.n_dofs
+        k = uni.k
+        np.testing.assert_array_equal(mix.list_off, np.arange(mesh.n_cells + 1) * k)
+        np.testing.assert_array_equal(mix.lmap.reshape(-1, k), uni.lmap)
+        np.testing.assert_array_equal(mix.offsets.reshape(-1, k), np.tile(uni.offsets, (mesh.n_cells, 1)))
+        for d in range(3):
+            if uni.first[d] is not None:
+                np.testing.assert_array_equal(mix.column_starts(d), uni.column_starts(d))
+
+
+def test_entity_dofs_count_formula():
+    # n_dofs = sum over entities of (lam + 1) n_h + lam n_v
+    mesh = meshgen.tri_square(5)
+    lam = 7
+    dofs = _random_entity_dofs(mesh, 9, hi=5)
+    num = oracle.number_mixed(mesh.counts, lam, dofs, mesh.cell_vertex, mesh.cell_edge)
+    assert num.n_dofs == sum(int(((lam + 1) * d[:, 0] + lam * d[:, 1]).sum()) for d in dofs)
