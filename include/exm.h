@@ -139,6 +139,11 @@ int32_t exm_mesh_entity_layers(const exm_mesh* mesh, int32_t d1, int32_t* lo, in
 #define EXM_ELEMENT_DG0DG1 8   /* DG0 x DG1, delta(2,1) = 2, arity 2            */
 #define EXM_ELEMENT_DG1P1 9    /* DG1 x CG1, delta(2,0) = 3, arity 6            */
 #define EXM_ELEMENT_DG1DG0 10  /* DG1 x DG0, delta(2,1) = 3, arity 3            */
+/* A space with a DoF count per entity (exm_space_create_mixed) whose cells
+ * each carry DG0 x DG0 (1 DoF per layer) or DG1 x DG1 (6 DoFs per layer) and
+ * no other entity carries DoFs: a mixed-degree DG space, mass action only,
+ * DIRECT schedule. */
+#define EXM_ELEMENT_DGMIX 11
 
 typedef struct exm_space exm_space;
 int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t element,
@@ -150,9 +155,37 @@ int32_t exm_space_offsets(const exm_space* space, int32_t* offsets);
 /* dst: device [N_d1], first DoF of the column of every base entity of
  * dimension d1 (-1 where the space has no DoFs on that column). */
 int32_t exm_space_column_starts(const exm_space* space, int32_t d1, int32_t* dst, void* stream);
-/* dst: device [n_cells * k], the explicit lists L(c) of layer 0, row-major. */
+/* dst: device [n_cells * k], the explicit lists L(c) of layer 0, row-major.
+ * A space made by exm_space_create_mixed has lists of different lengths:
+ * EXM_EUNSUPPORTED here and in exm_space_offsets; use exm_space_lists. */
 int32_t exm_space_bottom_map(const exm_space* space, int32_t* dst, void* stream);
 void exm_space_destroy(exm_space* space);
+
+/* Function space with a DoF count per entity.  The paper fixes the count per
+ * entity type for its exposition and notes that neither the numbering nor
+ * its performance depends on it (Section 5).
+ * dofs_v, dofs_e, dofs_c: host [N_d * 2]; entity i of dimension d carries
+ *   dofs_d[2i] DoFs on each of its horizontal entities (levels) and
+ *   dofs_d[2i + 1] on each vertical one (layers), 0 .. 64 each.  dofs_e may be
+ *   NULL when no edge carries DoFs (required when the mesh has no cell_edge).
+ * Algorithm 1 numbers the entities in the same order as exm_space_create, so
+ * column starts are a prefix sum of the column sizes (lambda + 1) n_h +
+ * lambda n_v; an entity without DoFs gets the start of the next column.  The
+ * list of cell c holds, per closure entity in the order of exm_space_create,
+ * its bottom, top and vertical DoFs of layer 0: its length varies by cell,
+ * and the vertical offset of every entry is its entity's DoFs per level
+ * (Algorithm 2 per entity).  Uniform layer count only (EXM_EUNSUPPORTED on a
+ * mesh with layer ranges).  element: EXM_ELEMENT_NONE (numbering only) or
+ * EXM_ELEMENT_DGMIX (checked: every cell (0, 1) or (0, 6), nothing else). */
+int32_t exm_space_create_mixed(const exm_mesh* mesh, const int32_t* dofs_v, const int32_t* dofs_e,
+                               const int32_t* dofs_c, int32_t element, void* stream, exm_space** out);
+/* Total length of the explicit lists (n_cells * k for a uniform space). */
+int32_t exm_space_list_size(const exm_space* space, int64_t* total);
+/* The explicit lists of any space: list_off device [n_cells + 1] (the list of
+ * cell c is lists[list_off[c] .. list_off[c + 1] - 1]), lists device [total],
+ * entry_offsets device [total] (the vertical offset of every entry). */
+int32_t exm_space_lists(const exm_space* space, int32_t* list_off, int32_t* lists, int32_t* entry_offsets,
+                        void* stream);
 
 /* ------------------------------------------------------------------------
  * Parallel loop over the prisms of an extruded mesh (Algorithm 3) applying a

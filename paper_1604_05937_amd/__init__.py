@@ -16,7 +16,7 @@ import ctypes
 import numpy as np
 
 from . import _abi
-from ._abi import (EXM_ELEMENT_DG0DG0, EXM_ELEMENT_DG1DG1, EXM_ELEMENT_NONE, EXM_ELEMENT_P1P1, EXM_ELEMENT_P2P2,
+from ._abi import (EXM_ELEMENT_DG0DG0, EXM_ELEMENT_DG1DG1, EXM_ELEMENT_DGMIX, EXM_ELEMENT_NONE, EXM_ELEMENT_P1P1, EXM_ELEMENT_P2P2,
                    EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_JAC, EXM_K_CUBIC_VJP, EXM_K_FACET_JUMP,
                    EXM_K_MASS,
                    EXM_RACE_ATOMIC,
@@ -129,6 +129,41 @@ class Space:
         _abi.exm_space_info(h, ctypes.byref(n), ctypes.byref(k))
         self.n_dofs = n.value
         self.arity = k.value
+
+    @classmethod
+    def mixed(cls, mesh: Mesh, dofs, element: int = EXM_ELEMENT_NONE, stream=None):
+        """A space with a DoF count per entity: dofs[d] is [N_d, 2] (DoFs on
+        every horizontal and vertical entity of each base entity of dimension
+        d), or None for none."""
+        self = cls.__new__(cls)
+        self.mesh = mesh
+        self.element = element
+        self.delta = None
+        arrs = [None if d is None else np.ascontiguousarray(np.asarray(d, dtype=np.int32).reshape(-1, 2))
+                for d in dofs]
+        ptrs = [None if a is None else a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        h = ctypes.c_void_p()
+        _abi.exm_space_create_mixed(mesh.handle, ptrs[0], ptrs[1], ptrs[2], int(element), stream_handle(stream),
+                                    ctypes.byref(h))
+        self.handle = h
+        n = ctypes.c_int64()
+        k = ctypes.c_int32()
+        _abi.exm_space_info(h, ctypes.byref(n), ctypes.byref(k))
+        self.n_dofs = n.value
+        self.arity = k.value
+        return self
+
+    def lists(self, stream=None):
+        """(list_off [n_cells + 1], lists [total], entry_offsets [total]), int32 device tensors."""
+        import torch
+        total = ctypes.c_int64()
+        _abi.exm_space_list_size(self.handle, ctypes.byref(total))
+        off = torch.empty(self.mesh.n_cells + 1, dtype=torch.int32, device="cuda")
+        lst = torch.empty(max(total.value, 1), dtype=torch.int32, device="cuda")
+        eo = torch.empty(max(total.value, 1), dtype=torch.int32, device="cuda")
+        _abi.exm_space_lists(self.handle, ctypes.c_void_p(off.data_ptr()), ctypes.c_void_p(lst.data_ptr()),
+                             ctypes.c_void_p(eo.data_ptr()), stream_handle(stream))
+        return off, lst[:total.value], eo[:total.value]
 
     def offsets(self) -> np.ndarray:
         out = np.zeros(self.arity, dtype=np.int32)

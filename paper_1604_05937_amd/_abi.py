@@ -33,6 +33,7 @@ EXM_ELEMENT_DG0P1 = 7
 EXM_ELEMENT_DG0DG1 = 8
 EXM_ELEMENT_DG1P1 = 9
 EXM_ELEMENT_DG1DG0 = 10
+EXM_ELEMENT_DGMIX = 11
 
 EXM_READ = 1
 EXM_WRITE = 2
@@ -111,6 +112,10 @@ _PROTOS = {
     "exm_batch_launch": (c_int32, [c_void_p, c_void_p]),
     "exm_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int32)]),
     "exm_batch_destroy": (None, [c_void_p]),
+    "exm_space_create_mixed": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                         POINTER(c_void_p)]),
+    "exm_space_list_size": (c_int32, [c_void_p, POINTER(c_int64)]),
+    "exm_space_lists": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "exm_matrix_create": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "exm_matrix_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "exm_matrix_assemble": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p]),

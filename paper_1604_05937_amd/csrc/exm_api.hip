@@ -115,7 +115,7 @@ static bool continuous(int32_t element)
 }
 
 // The tensor-product elements that run the generic DIRECT kernel only
-static bool direct_only(int32_t element) { return element >= EXM_ELEMENT_P1DG0 && element <= EXM_ELEMENT_DG1DG0; }
+static bool direct_only(int32_t element) { return element >= EXM_ELEMENT_P1DG0 && element <= EXM_ELEMENT_DGMIX; }
 
 // Validate and fill everything but the schedule.
 static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const exm_arg* args, LoopLaunch& P)
@@ -176,7 +176,8 @@ static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const e
     P.element = el;
     P.n_layers = m->n_layers;
     P.cell_lam = m->variable ? m->d_cell_lam.p : nullptr;
-    P.field_offset = V->offsets[0];
+    P.field_offset = V->offsets.empty() ? 0 : V->offsets[0];   // a mixed space has an offset per list entry
+    P.list_off = V->mixed ? V->d_list_off.p : nullptr;
     P.fmap = V->d_map.p;
     P.xmap = X.space->d_map.p;
     P.X = (const double*)X.data;

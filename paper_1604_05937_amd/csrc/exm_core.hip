@@ -443,10 +443,149 @@ int32_t exm_space_info(const exm_space* space, int64_t* n_dofs, int32_t* arity)
     return EXM_OK;
 }
 
+int32_t exm_space_create_mixed(const exm_mesh* mesh, const int32_t* dofs_v, const int32_t* dofs_e,
+                               const int32_t* dofs_c, int32_t element, void* stream, exm_space** out)
+{
+    clear_error();
+    EXM_CHECK(mesh != nullptr && out != nullptr, EXM_EINVAL, "mesh or out is NULL");
+    EXM_CHECK(dofs_v != nullptr && dofs_c != nullptr, EXM_EINVAL, "dofs_v or dofs_c is NULL");
+    EXM_CHECK(!mesh->variable, EXM_EUNSUPPORTED, "a DoF count per entity takes meshes with one layer count");
+    EXM_CHECK(element == EXM_ELEMENT_NONE || element == EXM_ELEMENT_DGMIX, EXM_EINVAL,
+              "element %d: a space with a DoF count per entity is EXM_ELEMENT_NONE or EXM_ELEMENT_DGMIX", element);
+    const int32_t* dofs[3] = {dofs_v, dofs_e, dofs_c};
+    for (int d = 0; d < 3; ++d) {
+        if (!dofs[d]) continue;
+        for (int64_t i = 0; i < 2 * (int64_t)mesh->n[d]; ++i)
+            EXM_CHECK(dofs[d][i] >= 0 && dofs[d][i] <= 64, EXM_ERANGE, "dofs of entity %lld (dimension %d) = %d "
+                      "outside [0, 64]", (long long)(i / 2), d, dofs[d][i]);
+    }
+    bool edge_dofs = false;
+    if (dofs_e)
+        for (int64_t i = 0; i < 2 * (int64_t)mesh->n[1] && !edge_dofs; ++i) edge_dofs = dofs_e[i] > 0;
+    EXM_CHECK(!edge_dofs || !mesh->h_cell_edge.empty(), EXM_EINVAL,
+              "edges carry DoFs but the mesh has no cell_edge map");
+    if (element == EXM_ELEMENT_DGMIX) {
+        for (int64_t i = 0; i < 2 * (int64_t)mesh->n[0]; ++i)
+            EXM_CHECK(dofs_v[i] == 0, EXM_EINVAL, "EXM_ELEMENT_DGMIX: vertex DoFs must be 0");
+        EXM_CHECK(!edge_dofs, EXM_EINVAL, "EXM_ELEMENT_DGMIX: edge DoFs must be 0");
+        for (int32_t c = 0; c < mesh->n[2]; ++c)
+            EXM_CHECK(dofs_c[2 * c] == 0 && (dofs_c[2 * c + 1] == 1 || dofs_c[2 * c + 1] == 6), EXM_EINVAL,
+                      "EXM_ELEMENT_DGMIX: cell %d carries (%d, %d); use (0, 1) or (0, 6)", c, dofs_c[2 * c],
+                      dofs_c[2 * c + 1]);
+    }
+    const int64_t lam = mesh->n_layers;
+    auto s = std::make_unique<exm_space>();
+    s->mesh = mesh;
+    s->element = element;
+    s->mixed = true;
+    auto nh = [&](int d, int64_t i) { return dofs[d] ? dofs[d][2 * i] : 0; };
+    auto nv = [&](int d, int64_t i) { return dofs[d] ? dofs[d][2 * i + 1] : 0; };
+    // Algorithm 1: column starts as a prefix sum over the entities in visiting order
+    std::vector<int64_t> start[3];
+    int64_t c = 0;
+    for (int d = 0; d < 3; ++d) {
+        s->base[d] = c;
+        s->col_size[d] = -1;   // columns differ in size
+        start[d].resize(mesh->n[d]);
+        for (int32_t i = 0; i < mesh->n[d]; ++i) {
+            start[d][i] = c;
+            c += (lam + 1) * nh(d, i) + lam * nv(d, i);
+        }
+    }
+    s->n_dofs = c;
+    EXM_CHECK(s->n_dofs < (int64_t)INT32_MAX, EXM_EOVERFLOW,
+              "space has %lld DoFs; the int32 numbering allows at most %d", (long long)s->n_dofs, INT32_MAX - 1);
+    // lists of layer 0, cell by cell, with the vertical offset of every entry
+    const int32_t ncell = mesh->n[2];
+    const int32_t* cv = mesh->h_cell_vertex.data();
+    const int32_t* ce = mesh->h_cell_edge.empty() ? nullptr : mesh->h_cell_edge.data();
+    std::vector<int32_t> off(ncell + 1, 0), map, eoff;
+    int32_t kmax = 0;
+    for (int32_t cell = 0; cell < ncell; ++cell) {
+        for (int ent = 0; ent < 7; ++ent) {
+            const int d = ent < 3 ? 0 : (ent < 6 ? 1 : 2);
+            if (d == 1 && !ce) continue;
+            const int32_t i = d == 0 ? cv[cell * 3 + ent] : (d == 1 ? ce[cell * 3 + (ent - 3)] : cell);
+            const int h = nh(d, i), v = nv(d, i);
+            const int64_t S = start[d][i];
+            for (int j = 0; j < h; ++j) { map.push_back((int32_t)(S + j)); eoff.push_back(h + v); }           // bottom
+            for (int j = 0; j < h; ++j) { map.push_back((int32_t)(S + h + v + j)); eoff.push_back(h + v); }   // top
+            for (int j = 0; j < v; ++j) { map.push_back((int32_t)(S + h + j)); eoff.push_back(h + v); }       // vertical
+        }
+        EXM_CHECK(map.size() < (size_t)INT32_MAX, EXM_EOVERFLOW, "lists exceed the int32 range");
+        off[cell + 1] = (int32_t)map.size();
+        kmax = std::max(kmax, off[cell + 1] - off[cell]);
+    }
+    s->k = kmax;
+    s->list_total = (int64_t)map.size();
+    int32_t st;
+    if ((st = s->d_map.upload(map.data(), map.size())) != EXM_OK) return st;
+    if ((st = s->d_list_off.upload(off.data(), off.size())) != EXM_OK) return st;
+    if ((st = s->d_entry_off.upload(eoff.data(), eoff.size())) != EXM_OK) return st;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->n[d] == 0) continue;
+        std::vector<int32_t> h(mesh->n[d]);
+        for (int32_t i = 0; i < mesh->n[d]; ++i) h[i] = (int32_t)start[d][i];
+        if ((st = s->d_starts[d].upload(h.data(), h.size())) != EXM_OK) return st;
+    }
+    (void)stream;
+    *out = s.release();
+    return EXM_OK;
+}
+
+int32_t exm_space_list_size(const exm_space* space, int64_t* total)
+{
+    clear_error();
+    EXM_CHECK(space != nullptr && total != nullptr, EXM_EINVAL, "space or total is NULL");
+    *total = space->mixed ? space->list_total : (int64_t)space->mesh->n[2] * space->k;
+    return EXM_OK;
+}
+
+__global__ void k_uniform_lists(int32_t n_cells, int32_t k, const int32_t* __restrict__ offsets, int32_t* list_off,
+                                int32_t* entry_off)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n_cells) list_off[i] = (int32_t)(i * k);
+    if (i < (int64_t)n_cells * k) entry_off[i] = offsets[i % k];
+}
+
+int32_t exm_space_lists(const exm_space* space, int32_t* list_off, int32_t* lists, int32_t* entry_offsets,
+                        void* stream)
+{
+    clear_error();
+    EXM_CHECK(space != nullptr && list_off != nullptr, EXM_EINVAL, "space or list_off is NULL");
+    int64_t total = 0;
+    int32_t st = exm_space_list_size(space, &total);
+    if (st != EXM_OK) return st;
+    EXM_CHECK(total == 0 || (lists != nullptr && entry_offsets != nullptr), EXM_EINVAL, "lists or entry_offsets is NULL");
+    hipStream_t hs = (hipStream_t)stream;
+    const int32_t nc = space->mesh->n[2];
+    if (total) EXM_TRY_HIP(hipMemcpyAsync(lists, space->d_map.p, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToDevice, hs));
+    if (space->mixed) {
+        EXM_TRY_HIP(hipMemcpyAsync(list_off, space->d_list_off.p, sizeof(int32_t) * (size_t)(nc + 1),
+                                   hipMemcpyDeviceToDevice, hs));
+        if (total)
+            EXM_TRY_HIP(hipMemcpyAsync(entry_offsets, space->d_entry_off.p, sizeof(int32_t) * (size_t)total,
+                                       hipMemcpyDeviceToDevice, hs));
+        return EXM_OK;
+    }
+    DevBuf<int32_t> offs;
+    if ((st = offs.upload(space->offsets.data(), space->offsets.size())) != EXM_OK) return st;
+    const int64_t n = std::max<int64_t>(nc + 1, total);
+    const int bs = 256;
+    hipLaunchKernelGGL(k_uniform_lists, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, hs, nc, space->k,
+                       offs.p, list_off, entry_offsets);
+    EXM_TRY_HIP(hipGetLastError());
+    // offs is freed on return: wait for the kernel that reads it
+    EXM_TRY_HIP(hipStreamSynchronize(hs));
+    return EXM_OK;
+}
+
 int32_t exm_space_offsets(const exm_space* space, int32_t* offsets)
 {
     clear_error();
     EXM_CHECK(space != nullptr && offsets != nullptr, EXM_EINVAL, "space or offsets is NULL");
+    EXM_CHECK(!space->mixed, EXM_EUNSUPPORTED, "the space has a DoF count per entity: use exm_space_lists");
     std::memcpy(offsets, space->offsets.data(), sizeof(int32_t) * space->offsets.size());
     return EXM_OK;
 }
@@ -468,6 +607,7 @@ int32_t exm_space_bottom_map(const exm_space* space, int32_t* dst, void* stream)
 {
     clear_error();
     EXM_CHECK(space != nullptr && dst != nullptr, EXM_EINVAL, "space or dst is NULL");
+    EXM_CHECK(!space->mixed, EXM_EUNSUPPORTED, "the space has a DoF count per entity: use exm_space_lists");
     size_t bytes = sizeof(int32_t) * space->d_map.n;
     if (bytes)
         EXM_TRY_HIP(hipMemcpyAsync(dst, space->d_map.p, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));

@@ -141,6 +141,13 @@ struct exm_space {
     std::vector<int32_t> entity_dim;   // [k]
     exm::DevBuf<int32_t> d_map;        // [n_cells * k], explicit lists of layer 0
     exm::DevBuf<int32_t> d_starts[3];  // column start of every base entity (-1: no column)
+    // a DoF count per entity: lists of different lengths (d_map holds them
+    // back to back), the start of every cell's list and the vertical offset
+    // of every entry
+    bool mixed = false;
+    int64_t list_total = 0;
+    exm::DevBuf<int32_t> d_list_off;   // [n_cells + 1]
+    exm::DevBuf<int32_t> d_entry_off;  // [list_total]
 };
 
 namespace exm {
@@ -172,6 +179,7 @@ struct LoopLaunch {
     LoopShape shape;
     int32_t n_layers;
     const int32_t* cell_lam;      // layers of every cell column, or null (all n_layers)
+    const int32_t* list_off;      // a space with a DoF count per entity: start of every cell's list, else null
     int32_t field_offset;         // vertical offset of every position of the field space
     const int32_t* fmap;          // field explicit lists [n_cells * k]
     const int32_t* xmap;          // coordinate explicit lists [n_cells * 6]

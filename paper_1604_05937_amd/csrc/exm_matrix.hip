@@ -415,6 +415,7 @@ int32_t exm_matrix_create(const exm_space* space, exm_matrix** out)
     EXM_CHECK(space->element != EXM_ELEMENT_NONE, EXM_EINVAL, "the space has no element");
     const exm_mesh* mesh = space->mesh;
     EXM_CHECK(!mesh->variable, EXM_EUNSUPPORTED, "matrices take meshes with one layer count per column");
+    EXM_CHECK(!space->mixed, EXM_EUNSUPPORTED, "matrices take spaces with one DoF count per entity type");
     auto A = std::make_unique<exm_matrix>();
     A->space = space;
     A->element = space->element;

@@ -659,6 +659,59 @@ __global__ void __launch_bounds__(512) k_tiled_p2(const ColArgs a, const TileArg
     }
 }
 
+// Mixed-degree DG mass action (a space with a DoF count per entity whose
+// cells carry DG0 x DG0 or DG1 x DG1): the length of a cell's list is its DoF
+// count per layer nd (1 or 6), and its DoFs are the contiguous column
+// L(c)[0] + nd l + p, position p = 2a + b for DG1 (vertex a, bottom / top b).
+__global__ void __launch_bounds__(256) k_direct_dgmix(const ColArgs a)
+{
+    const Lane L = lane_of(a.seg);
+    int32_t cell;
+    bool valid;
+    if (!direct_cell(a, L, cell, valid)) return;
+    const int32_t lo = valid ? a.list_off[cell] : 0;
+    const int nd = valid ? a.list_off[cell + 1] - lo : 0;
+    const int f0 = valid ? a.fmap[lo] : 0;
+    int xb[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) xb[v] = valid ? a.xmap[(int64_t)cell * 6 + 2 * v] : 0;
+    const BaseXY g = base_xy(a.X, a.xn, xb, valid);
+    for (int l0 = 0; l0 < a.n_layers; l0 += a.seg) {
+        const int l = l0 + L.lsub;
+        const bool act = valid && l < a.n_layers;
+        const bool last = L.lsub == a.seg - 1 || l == a.n_layers - 1;
+        double twoA, h[3];
+        geometry(a.X, a.xn, xb, g, l, act, last, twoA, h);
+        if (!act) continue;
+        const int64_t d = f0 + (int64_t)l * nd;
+        if (nd == 1) {
+            const double y = dg0_mass(twoA, h, a.in0[d]);
+            if (a.write)
+                a.out0[d] = y;
+            else
+                a.out0[d] += y;
+        } else {
+            double xb6[3], xt6[3], yb[3], yt[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                xb6[q] = a.in0[d + 2 * q];
+                xt6[q] = a.in0[d + 2 * q + 1];
+            }
+            p1_mass(twoA, h, xb6, xt6, yb, yt);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (a.write) {
+                    a.out0[d + 2 * q] = yb[q];
+                    a.out0[d + 2 * q + 1] = yt[q];
+                } else {
+                    a.out0[d + 2 * q] += yb[q];
+                    a.out0[d + 2 * q + 1] += yt[q];
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Horizontal facets: Algorithm 3 with d2 = 0, lambda + 1 facets per column
 // (levels l = 0 .. lambda).  Lane = facet.  Facet l lies between the prism of
@@ -756,6 +809,7 @@ ColArgs col_args(const LoopLaunch& P)
     ColArgs a;
     a.n_layers = P.n_layers;
     a.cell_lam = P.cell_lam;
+    a.list_off = P.list_off;
     a.off = P.field_offset;
     a.cpw = P.shape.cpw;
     a.seg = P.shape.seg;
@@ -833,6 +887,10 @@ int32_t launch_column_loop(const LoopLaunch& P, hipStream_t stream)
     case EXM_ELEMENT_DG1DG1:
         if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on DG1xDG1", P.kernel);
         EXM_LAUNCH(k_direct_dg1);
+        break;
+    case EXM_ELEMENT_DGMIX:
+        if (P.kernel != EXM_K_MASS) return fail(EXM_EUNSUPPORTED, "kernel %d not available on EXM_ELEMENT_DGMIX", P.kernel);
+        EXM_LAUNCH(k_direct_dgmix);
         break;
     case EXM_ELEMENT_P1DG0:
     case EXM_ELEMENT_P1DG1:

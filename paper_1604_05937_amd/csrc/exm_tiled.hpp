@@ -23,6 +23,7 @@ struct ColArgs {
     double* __restrict__ out1;
     double* __restrict__ out2;
     const int32_t* __restrict__ cell_lam;   // layers of every cell column (a mesh with a range per column) or null
+    const int32_t* __restrict__ list_off;   // start of every cell's list (a DoF count per entity) or null
     const int32_t* __restrict__ cells;  // DIRECT: cell list (one colour) or null
     int64_t cell_begin, cell_count;     // DIRECT: range of the list (or of the cells)
 };
