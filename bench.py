@@ -375,6 +375,7 @@ def direct_shapes(exm, name):
 
 
 def secondary(torch, exm, W, meshgen):
+    import numpy as np
     out = {}
     # the RHS on the paper's nine spaces ({CG1, DG0, DG1} horizontally x vertically), 256 x 256 x 64
     e9 = W.extruded(256, 64)
@@ -417,6 +418,21 @@ def secondary(torch, exm, W, meshgen):
     out["rhs_direct_variable_layers_512x512x100"] = var
     log("variable layers: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in var.items()))
     out["matrix_p1_512x512x100"] = matrix_figures(torch, exm, W, meshgen)
+    # mixed-degree DG (a DoF count per entity): half the cells DG1, half DG0, 256 x 256 x 64
+    em = W.extruded(256, 64)
+    nd = meshgen.cell_degrees(em.base, frac_dg1=0.5)
+    dofs = [np.zeros((em.base.n_vertices, 2), np.int32), None, np.stack([np.zeros_like(nd), nd], 1)]
+    Vm = exm.Space.mixed(em.mesh, dofs, element=exm.EXM_ELEMENT_DGMIX)
+    x = W.device_values(Vm.n_dofs, meshgen.SEED_FIELD)
+    y = Vm.zeros()
+    margs = [(x, Vm, exm.EXM_READ), (y, Vm, exm.EXM_WRITE)]
+    cfg = exm.autotune(exm.EXM_K_MASS, em.mesh, em.X, em.Vx, margs)
+    t, _ = timed(torch, lambda: exm.par_loop(exm.EXM_K_MASS, em.mesh, em.X, em.Vx, margs, **cfg), 10)
+    mbytes = 16 * Vm.n_dofs + W.coord_bytes(em) + 4 * (em.base.n_cells + 1) + 4 * int(nd.sum()) + 24 * em.base.n_cells
+    out["mass_dg_mixed_degree_256x256x64"] = {"dofs": Vm.n_dofs, "ms": round(t, 4),
+                                              "gbs": round(mbytes / t / 1e6, 1), "launch": cfg}
+    log(f"mixed-degree DG mass {t:.3f} ms")
+    del x, y, Vm, em
     # horizontal facets (lambda + 1 per column), the jump form: DG0 on 512 x 512 x 100, DG1 on 256 x 256 x 64
     fac = {}
     for name, (nb, lam) in (("DG0", (512, 100)), ("DG1", (256, 64))):

@@ -95,8 +95,10 @@ def test_mixed_space_refusals():
     with pytest.raises(exm.ExmError) as e:
         V.bottom_map()
     assert e.value.status == exm._abi.EXM_EUNSUPPORTED
+    D = exm.Space.mixed(mesh, [np.zeros((base.n_vertices, 2)), None, np.stack([np.zeros_like(nd), nd], 1)],
+                        element=exm.EXM_ELEMENT_DGMIX)
     with pytest.raises(exm.ExmError) as e:
-        exm.Matrix(V)
+        exm.Matrix(D)
     assert e.value.status == exm._abi.EXM_EUNSUPPORTED
     vmesh = exm.Mesh(base, 5, layers=meshgen.layer_ranges(base, 5, "random"))
     with pytest.raises(exm.ExmError) as e:
