@@ -92,10 +92,10 @@ def _lib():
     lib.oracle_stencil_mixed.restype = ctypes.c_int64
     lib.oracle_stencil_mixed.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P]
     lib.oracle_facet_loop.restype = None
-    lib.oracle_facet_loop.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P,
+    lib.oracle_facet_loop.argtypes = [ctypes.c_int64, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P,
                                       ctypes.c_int32, ctypes.c_int32, P, P, P, P, P]
     lib.oracle_assemble.restype = None
-    lib.oracle_assemble.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P, P, P,
+    lib.oracle_assemble.argtypes = [ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int32, P, P, P,
                                     ctypes.c_int32, P, P, P, P, P, P,
                                     ctypes.c_int32, P, P, P, P]
     return lib
@@ -460,7 +460,14 @@ def par_loop(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.
     return outs
 
 
-def assemble(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray, u=None):
+def _cell_subset(num_v, cells):
+    if cells is None:
+        return int(num_v.counts[2]), None, None
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    return cells.size, cells, _ptr(cells)
+
+
+def assemble(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray, u=None, cells=None):
     """Matrix of a bilinear form on V (ASM_*), as scipy CSR with sorted
     indices: oracle_assemble's triplets, one per (prism, p, j) in Algorithm 3's
     order, summed per (row, column) by scipy's COO-to-CSR conversion.  Every
@@ -474,14 +481,15 @@ def assemble(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.
     phiv = np.ascontiguousarray(tabulate(h, v, pts))
     phix, dphix = tabulate_coords(pts)
     k = num_v.k
-    m = int(num_v.counts[2]) * num_v.n_layers * k * k
+    n_iter, cells, cptr = _cell_subset(num_v, cells)
+    m = n_iter * num_v.n_layers * k * k
     rows = np.empty(m, np.int64)
     cols = np.empty(m, np.int64)
     vals = np.empty(m, np.float64)
     if jac:
         assert u is not None and u.dtype == np.float64 and u.size == num_v.n_dofs
         u = np.ascontiguousarray(u)
-    _lib().oracle_assemble(form, int(num_v.counts[2]), num_v.n_layers, _ptr(num_x.lmap), _ptr(num_x.offsets),
+    _lib().oracle_assemble(form, n_iter, cptr, num_v.n_layers, _ptr(num_x.lmap), _ptr(num_x.offsets),
                            _ptr(np.ascontiguousarray(X, dtype=np.float64)), k, _ptr(num_v.lmap),
                            _ptr(num_v.offsets), _ptr(u) if jac else None, _ptr(rows), _ptr(cols), _ptr(vals),
                            int(wts.size), _ptr(np.ascontiguousarray(wts)), _ptr(np.ascontiguousarray(phix)),
@@ -494,7 +502,7 @@ def assemble(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.
 
 
 def facet_loop(space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray, x: np.ndarray,
-               absf: bool = False) -> np.ndarray:
+               absf: bool = False, cells=None) -> np.ndarray:
     """Algorithm 3 over the horizontal facets (lambda + 1 per column):
     y_i = sum over facets of the integral of [x][v_i] dS, [w] the value below
     minus the value above (zero outside the domain).  The triangle rule is
@@ -513,7 +521,8 @@ def facet_loop(space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray, 
     x = np.ascontiguousarray(x, dtype=np.float64)
     assert x.size == num_v.n_dofs
     y = np.zeros(num_v.n_dofs)
-    _lib().oracle_facet_loop(int(num_v.counts[2]), num_v.n_layers, _ptr(num_x.lmap), _ptr(num_x.offsets),
+    n_iter, cells, cptr = _cell_subset(num_v, cells)
+    _lib().oracle_facet_loop(n_iter, cptr, num_v.n_layers, _ptr(num_x.lmap), _ptr(num_x.offsets),
                              _ptr(np.ascontiguousarray(X, dtype=np.float64)), num_v.k, _ptr(num_v.lmap),
                              _ptr(num_v.offsets), _ptr(x), _ptr(y), 1 if absf else 0, nq,
                              _ptr(np.ascontiguousarray(tw)), _ptr(np.ascontiguousarray(psix)),
@@ -581,20 +590,21 @@ class Problem:
         par_loop(FORM_CUBIC_JVP, self.space, self.num_v, self.num_x, self.X, [u, du, df], [dF], cells=cells)
         return dF
 
-    def facet_jump(self, x):
+    def facet_jump(self, x, cells=None):
         """y_i = sum over horizontal facets of integral [x][v_i] dS (the
         facet loop, lambda + 1 facets per column)."""
-        return facet_loop(self.space, self.num_v, self.num_x, self.X, x)
+        return facet_loop(self.space, self.num_v, self.num_x, self.X, x, cells=cells)
 
-    def facet_jump_abs(self, x):
-        return facet_loop(self.space, self.num_v, self.num_x, self.X, x, absf=True)
+    def facet_jump_abs(self, x, cells=None):
+        return facet_loop(self.space, self.num_v, self.num_x, self.X, x, absf=True, cells=cells)
 
-    def mass_matrix(self):
-        """M_ij = integral phi_j phi_i (scipy CSR)."""
-        return assemble(ASM_MASS, self.space, self.num_v, self.num_x, self.X)
+    def mass_matrix(self, cells=None):
+        """M_ij = integral phi_j phi_i (scipy CSR), from the prisms of all
+        base cells or of the given ones."""
+        return assemble(ASM_MASS, self.space, self.num_v, self.num_x, self.X, cells=cells)
 
-    def mass_matrix_abs(self):
-        return assemble(ASM_MASS_ABS, self.space, self.num_v, self.num_x, self.X)
+    def mass_matrix_abs(self, cells=None):
+        return assemble(ASM_MASS_ABS, self.space, self.num_v, self.num_x, self.X, cells=cells)
 
     def cubic_jacobian(self, u):
         """J_ij = d F_i / d u_j = integral 3 u^2 phi_j phi_i (P1 x P1, scipy CSR)."""

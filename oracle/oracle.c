@@ -316,9 +316,10 @@ void oracle_par_loop(int32_t form, int64_t n_iter, const int64_t* cells, int32_t
  *           to u, s = 3 u^2 (u = in0 on V);
  *   form 3, 4: the same with |phi| and |u| (the scales of the rounding error
  *           of any summation order).
- * rows, cols, vals: n_cells * lam * k * k entries each.
+ * cells: the base cells to visit (NULL: all 0 .. n_iter - 1).
+ * rows, cols, vals: n_iter * lam * k * k entries each.
  */
-void oracle_assemble(int32_t form, int64_t n_cells, int32_t lam,
+void oracle_assemble(int32_t form, int64_t n_iter, const int64_t* cells, int32_t lam,
                      const int64_t* mapx, const int32_t* offx, const double* X,
                      int32_t k, const int64_t* mapv, const int32_t* offv, const double* in0,
                      int64_t* rows, int64_t* cols, double* vals,
@@ -331,7 +332,8 @@ void oracle_assemble(int32_t form, int64_t n_cells, int32_t lam,
     const int absf = form >= 3;
     const int jac = form == 2 || form == 4;
     int64_t t = 0;
-    for (int64_t c = 0; c < n_cells; ++c) {
+    for (int64_t it = 0; it < n_iter; ++it) {
+        const int64_t c = cells ? cells[it] : it;
         for (int p = 0; p < 6; ++p) dx[p] = mapx[c * 6 + p];
         for (int p = 0; p < k; ++p) dv[p] = mapv[c * k + p];
         for (int32_t l = 0; l < lam; ++l) {
@@ -389,15 +391,17 @@ void oracle_assemble(int32_t form, int64_t n_cells, int32_t lam,
  *   barycentric functions and their derivatives; phi_lo[q*k + p] /
  *   phi_hi[q*k + p]: the basis of V at zeta = 1 (below) / zeta = 0 (above).
  * absf: the same sum with every factor replaced by its absolute value.
+ * cells: the base cells to visit (NULL: all 0 .. n_iter - 1).
  * out0 is incremented (the caller zeroes it for WRITE).
  */
-void oracle_facet_loop(int64_t n_cells, int32_t lam, const int64_t* mapx, const int32_t* offx, const double* X,
-                       int32_t k, const int64_t* mapv, const int32_t* offv, const double* in0, double* out0,
-                       int32_t absf, int32_t nq, const double* qw, const double* psix, const double* dpsix,
-                       const double* phi_lo, const double* phi_hi)
+void oracle_facet_loop(int64_t n_iter, const int64_t* cells, int32_t lam, const int64_t* mapx, const int32_t* offx,
+                       const double* X, int32_t k, const int64_t* mapv, const int32_t* offv, const double* in0,
+                       double* out0, int32_t absf, int32_t nq, const double* qw, const double* psix,
+                       const double* dpsix, const double* phi_lo, const double* phi_hi)
 {
     int64_t* dv = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
-    for (int64_t c = 0; c < n_cells; ++c) {
+    for (int64_t it = 0; it < n_iter; ++it) {
+        const int64_t c = cells ? cells[it] : it;
         for (int p = 0; p < k; ++p) dv[p] = mapv[c * k + p];   /* layer 0 */
         for (int32_t l = 0; l <= lam; ++l) {
             const int below = l >= 1, above = l < lam;

@@ -110,3 +110,85 @@ def test_config4_sampled():
     _check_columns(c.host(F), Fr, Fs, S, verts, lam + 1, "fused F")
     _check_columns(c.host(gu), gur, gus, S, verts, lam + 1, "fused g_u")
     _check_columns(c.host(gf), gfr, gfs, S, verts, lam + 1, "fused g_f")
+
+
+def _ranges_columns(starts, lo, hi, ids, extra):
+    """Indices of the columns of entities ids: start + 0 .. (hi - lo - 1 + extra)."""
+    return np.concatenate([starts[i] + np.arange(hi[i] - lo[i] + extra) for i in ids])
+
+
+@pytest.mark.parametrize("space", ["P1", "DG0"])
+def test_variable_layers_config2_sampled(space):
+    # columns of different heights (bathymetry ranges) on 512 x 512 x 100,
+    # in the launch the autotuner picks (DIRECT): sampled columns
+    say(f"full size variable layers 512x512x100 {space}")
+    base = meshgen.tri_square(512)
+    lam = 100
+    layers = meshgen.layer_ranges(base, lam, "bathymetry")
+    c = Case(base, lam, space, layers=layers)
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    got, cfg = _tuned_mass(c, x)
+    say(f"  launch {cfg}")
+    rng = np.random.default_rng(79)
+    if space == "P1":
+        verts = rng.choice(base.n_vertices, 64, replace=False)
+        cells = _cells_around_vertices(base, verts)
+        lo, hi = c.ref.num_v.lo[0], c.ref.num_v.hi[0]
+        idx = _ranges_columns(c.ref.num_v.column_starts(0), lo, hi, verts, 1)
+    else:
+        cells = rng.choice(base.n_cells, 256, replace=False)
+        lo, hi = layers[:, 0], layers[:, 1]
+        idx = _ranges_columns(c.ref.num_v.column_starts(2), lo, hi, cells, 0)
+    ref = c.ref.mass(x, cells=cells)
+    scale = c.ref.mass_abs(x, cells=cells)
+    assert_close(got[idx], ref[idx], scale[idx], what=f"variable {space} columns")
+
+
+def test_facets_config2_sampled():
+    # the facet loop (lambda + 1 facets per column) on DG0, 512 x 512 x 100
+    say("full size facets 512x512x100 DG0")
+    base = meshgen.tri_square(512)
+    lam = 100
+    c = Case(base, lam, "DG0")
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    xd = c.dev(x)
+    y = c.V.zeros()
+    fields = [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_WRITE)]
+    cfg = exm.autotune(exm.EXM_K_FACET_JUMP, c.mesh, c.X, c.Vx, fields)
+    say(f"  launch {cfg}")
+    exm.par_loop(exm.EXM_K_FACET_JUMP, c.mesh, c.X, c.Vx, fields)
+    got = c.host(y)
+    cells = np.random.default_rng(80).choice(base.n_cells, 256, replace=False)
+    ref = c.ref.facet_jump(x, cells=cells)
+    scale = c.ref.facet_jump_abs(x, cells=cells)
+    _check_columns(got, ref, scale, c.ref.num_v.column_starts(2), cells, lam, "DG0 facet columns")
+
+
+def test_matrix_config2_sampled():
+    # the P1 mass matrix of 512 x 512 x 100: the product and the CSR rows of
+    # sampled vertex columns against the oracle on the cells around them
+    say("full size matrix 512x512x100 P1")
+    base = meshgen.tri_square(512)
+    lam = 100
+    c = Case(base, lam, "P1")
+    M = exm.Matrix(c.V)
+    M.assemble(exm.EXM_K_MASS, c.X, c.Vx)
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    y = c.host(M.spmv(c.dev(x)))
+    verts = np.random.default_rng(81).choice(base.n_vertices, 32, replace=False)
+    cells = _cells_around_vertices(base, verts)
+    starts = c.ref.num_v.column_starts(0)
+    ref = c.ref.mass(x, cells=cells)
+    scale = c.ref.mass_abs(x, cells=cells)
+    _check_columns(y, ref, scale, starts, verts, lam + 1, "matrix product rows")
+    rowptr, col, val = M.csr()
+    rp = c.host(rowptr)
+    A = c.ref.mass_matrix(cells=cells)
+    S = c.ref.mass_matrix_abs(cells=cells)
+    rows = (starts[verts][:, None] + np.arange(lam + 1)[None, :]).ravel()
+    for r in rows[::7]:
+        a, b = int(rp[r]), int(rp[r + 1])
+        gc = col[a:b].cpu().numpy()
+        gv = val[a:b].cpu().numpy()
+        np.testing.assert_array_equal(gc.astype(np.int64), A.indices[A.indptr[r]:A.indptr[r + 1]].astype(np.int64))
+        assert_close(gv, A.data[A.indptr[r]:A.indptr[r + 1]], S.data[S.indptr[r]:S.indptr[r + 1]], what=f"CSR row {r}")
