@@ -198,9 +198,12 @@ int32_t exm_space_lists(const exm_space* space, int32_t* list_off, int32_t* list
  * exactly under that assumption and do not check it.
  *
  *   EXM_K_MASS       y = M x, i.e. y_i = integral of x_h v_i, the residual of
- *                    Section 4.1.1 (args: X, x READ, y).  Elements P1P1,
- *                    DG0DG0, DG1DG1, P2P2.  y is EXM_INC for continuous
- *                    spaces, EXM_WRITE or EXM_INC for DG spaces.  The adjoint
+ *                    Section 4.1.1 (args: X, x READ, y).  Every element: the
+ *                    paper's nine {CG1, DG0, DG1} x {CG1, DG0, DG1} spaces,
+ *                    P2P2 and DGMIX.  y is EXM_INC for spaces with DoFs
+ *                    shared between cells or layers (P1P1, P2P2, P1DG0,
+ *                    P1DG1, DG0P1, DG1P1), EXM_WRITE or EXM_INC for the
+ *                    others.  The adjoint
  *                    of this linear residual with respect to x is the same
  *                    call with the cotangent as x (M is symmetric).
  *   EXM_K_CUBIC      F_i = integral (u^3 - f) v_i  (args: X, u, f READ, F INC), P1P1.
@@ -254,7 +257,9 @@ typedef struct {
                               /* vertices are split into tiles, each tile sums and       */
                               /* stores only the columns it owns, and a cell on a tile   */
                               /* boundary is computed by every tile owning one of its    */
-                              /* vertices; no atomics and a single launch                */
+                              /* vertices; no atomics and a single launch.  The GATHER   */
+                              /* schedule reports this race too (each vertex column owns */
+                              /* its outputs)                                            */
 
 /* Work schedule of the column loop. */
 #define EXM_SCHED_AUTO 0
