@@ -658,8 +658,8 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                         }
                     }
         if (cg)
-            for (int32_t t : {32, 64, 128, 256})
-                for (int32_t c : {0, 2, 4})
+            for (int32_t t : {8, 16, 24, 32, 64, 128, 256})
+                for (int32_t c : {0, 1, 2, 4})
                     for (int32_t w : {4, 8}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_TILED, c, w, t, 0});
     }
     hipEvent_t e0, e1;
