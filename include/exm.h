@@ -290,7 +290,8 @@ typedef struct {
                               /* independent and the grid runs chunk by chunk.  Same race    */
                               /* strategies and alignment as PIPELINED; other kernels run    */
                               /* PIPELINED                                                   */
-#define EXM_SCHED_GATHER 6    /* P1xP1 mass action: the loop turned to the output columns    */
+#define EXM_SCHED_GATHER 6    /* mass action of P1xP1, CG1xDG0 and CG1xDG1: the loop turned  */
+                              /* to the output columns                                       */
                               /* (owner computes).  A wavefront owns a base vertex and 62    */
                               /* levels of its column, walks the fan of cells around it      */
                               /* (each neighbouring column read once) and sums the rows of   */

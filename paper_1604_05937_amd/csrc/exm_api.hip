@@ -258,7 +258,8 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.schedule = EXM_SCHED_DIRECT;
         d.tile_cells = d.chunk_layers = 0;
     }
-    if (direct_only(P.element) || P.kernel == EXM_K_FACET_JUMP) {   // the generic DIRECT kernels
+    const bool gather = d.schedule == EXM_SCHED_GATHER && gather_supported(P.kernel, P.element);
+    if ((direct_only(P.element) || P.kernel == EXM_K_FACET_JUMP) && !gather) {   // the generic DIRECT kernels
         EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED,
                   "owner-computes is not available for kernel %d on element %d", P.kernel, P.element);
         if (d.schedule != EXM_SCHED_DIRECT) d.cols_per_wave = d.waves_per_block = 0;

@@ -137,6 +137,102 @@ __global__ void __launch_bounds__(256) k_gather_p1(const GatherP1Args g)
     }
 }
 
+// The same owner-computes walk for the spaces whose vertex columns are
+// discontinuous across levels: CG1 x DG0 (NV = 1, one DoF per layer) and
+// CG1 x DG1 (NV = 2, bottom and top node per layer).  There is no vertical
+// coupling, so a lane owns one layer (no halo lanes): it reads z at both
+// levels of its layer and the field at its layer for v and the fan, and
+// writes the row of v of every prism of that layer around v:
+//   y_(v, b) = (2A / 120) ((2 h_v + H) g_v + (h_v + H) G + sum_a h_a g_a),
+// g = V x per vertex (V the vertical mass of the layer's nodes).
+template <int NV>
+__global__ void __launch_bounds__(256) k_gather_p1dg(const GatherP1Args g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_g(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t v = wid / g.n_steps;
+    if (v >= g.n_vertices) return;   // uniform over the wavefront
+    const int l = (int)(wid - v * g.n_steps) * 64 + lane;
+    const bool act = l < g.lam;
+    const int64_t col = (int64_t)NV * g.lam;          // DoFs of a vertex column
+    const int64_t lamp = (int64_t)g.lam + 1;          // levels of a coordinate column
+    const double* __restrict__ Z = g.X + 2 * g.xn;
+    const int64_t fv = g.fbase + v * col, xv = g.xbase + v * lamp;
+    double x0[NV];
+#pragma unroll
+    for (int b = 0; b < NV; ++b) x0[b] = act ? g.f[fv + NV * l + b] : 0.0;
+    const double z0 = act ? Z[xv + l] : 0.0, z0n = act ? Z[xv + l + 1] : 0.0;
+    const double px0 = g.X[xv], py0 = g.X[g.xn + xv];
+    double acc[NV];
+#pragma unroll
+    for (int b = 0; b < NV; ++b) acc[b] = 0.0;
+    double xp[NV], zp = 0.0, zpn = 0.0, pxp = 0.0, pyp = 0.0;   // previous neighbour
+#pragma unroll
+    for (int b = 0; b < NV; ++b) xp[b] = 0.0;
+    const int32_t e0 = g.fan_off[v], e1 = g.fan_off[v + 1];
+    constexpr int kBlk = 4;
+    for (int32_t e = e0; e < e1; e += kBlk) {
+        int32_t ent[kBlk];
+        double x1[kBlk][NV], z1[kBlk], z1n[kBlk], px1[kBlk], py1[kBlk];
+#pragma unroll
+        for (int k = 0; k < kBlk; ++k) {
+            const bool has = e + k < e1;   // uniform over the wavefront
+            ent[k] = has ? g.fan[e + k] : 0;
+            const int64_t w = ent[k] & 0x7fffffff;
+            const int64_t fw = g.fbase + w * col, xw = g.xbase + w * lamp;
+#pragma unroll
+            for (int b = 0; b < NV; ++b) x1[k][b] = has && act ? g.f[fw + NV * l + b] : 0.0;
+            z1[k] = has && act ? Z[xw + l] : 0.0;
+            z1n[k] = has && act ? Z[xw + l + 1] : 0.0;
+            px1[k] = has ? g.X[xw] : 0.0;
+            py1[k] = has ? g.X[g.xn + xw] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kBlk; ++k) {
+            if (e + k >= e1) break;
+            if (ent[k] >= 0 && act) {   // cell (v, previous, w)
+                const double twoA = fabs((pxp - px0) * (py1[k] - py0) - (px1[k] - px0) * (pyp - py0));
+                const double h[3] = {z0n - z0, zpn - zp, z1n[k] - z1[k]};
+                const double H = h[0] + h[1] + h[2];
+                const double s = twoA * (1.0 / 120.0);
+#pragma unroll
+                for (int b = 0; b < NV; ++b) {
+                    // vertical mass of the layer's nodes, then the horizontal row of v
+                    double gv, gp, gw;
+                    if constexpr (NV == 1) {
+                        gv = x0[0];
+                        gp = xp[0];
+                        gw = x1[k][0];
+                    } else {
+                        const double cs = b == 0 ? 1.0 / 3.0 : 1.0 / 6.0, ct = b == 0 ? 1.0 / 6.0 : 1.0 / 3.0;
+                        gv = cs * x0[0] + ct * x0[1];
+                        gp = cs * xp[0] + ct * xp[1];
+                        gw = cs * x1[k][0] + ct * x1[k][1];
+                    }
+                    const double G = gv + gp + gw;
+                    const double HG = h[0] * gv + h[1] * gp + h[2] * gw;
+                    acc[b] += s * ((2.0 * h[0] + H) * gv + (h[0] + H) * G + HG);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NV; ++b) xp[b] = x1[k][b];
+            zp = z1[k];
+            zpn = z1n[k];
+            pxp = px1[k];
+            pyp = py1[k];
+        }
+    }
+    if (!act) return;
+#pragma unroll
+    for (int b = 0; b < NV; ++b) {
+        if (g.write)
+            g.y[fv + NV * l + b] = acc[b];
+        else
+            g.y[fv + NV * l + b] += acc[b];
+    }
+}
+
 }  // namespace
 
 // Fans of base cells around every vertex, in cyclic order: for vertex v the
@@ -227,7 +323,11 @@ int32_t build_vertex_fans(const exm_mesh* m, const VertexFans** out)
     return EXM_OK;
 }
 
-bool gather_supported(int32_t kernel, int32_t element) { return kernel == EXM_K_MASS && element == EXM_ELEMENT_P1P1; }
+bool gather_supported(int32_t kernel, int32_t element)
+{
+    return kernel == EXM_K_MASS &&
+           (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P1DG0 || element == EXM_ELEMENT_P1DG1);
+}
 
 int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, hipStream_t s)
 {
@@ -235,7 +335,8 @@ int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, 
     std::memset(&g, 0, sizeof(g));
     g.n_vertices = P.fspace->mesh->n[0];
     g.lam = P.n_layers;
-    g.n_steps = (P.n_layers + 1 + kOwned - 1) / kOwned;
+    const bool levels = P.element == EXM_ELEMENT_P1P1;   // DoFs on the levels, else inside the layers
+    g.n_steps = levels ? (P.n_layers + 1 + kOwned - 1) / kOwned : (P.n_layers + 63) / 64;
     g.write = P.write;
     g.fbase = P.fspace->base[0];
     g.xbase = P.xspace->base[0];
@@ -249,7 +350,12 @@ int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, 
     const int64_t waves = (int64_t)g.n_vertices * g.n_steps;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     if (blocks * wpb > INT32_MAX) return fail(EXM_ERANGE, "grid too large");
-    hipLaunchKernelGGL(k_gather_p1, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+    if (levels)
+        hipLaunchKernelGGL(k_gather_p1, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+    else if (P.element == EXM_ELEMENT_P1DG0)
+        hipLaunchKernelGGL(k_gather_p1dg<1>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+    else
+        hipLaunchKernelGGL(k_gather_p1dg<2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
     EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;
 }

@@ -202,36 +202,38 @@ def test_pipelined_needs_aligned_pointers():
     assert e.value.status == exm._abi.EXM_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("lam", [1, 2, 10, 60, 61, 62, 63, 64, 123, 124, 125, 130])
+@pytest.mark.parametrize("space", ["P1", "CG1xDG0", "CG1xDG1"])
+@pytest.mark.parametrize("lam", [1, 2, 10, 60, 61, 62, 63, 64, 65, 123, 124, 125, 130])
 @pytest.mark.parametrize("order", ["rcm", "random"])
 @pytest.mark.parametrize("wpb", [1, 2, 4])
-def test_gather_schedule_shapes(lam, order, wpb):
-    # the vertex-column schedule: steps of 62 owned levels, so lambda + 1
-    # around multiples of 62 exercises the halo lanes of both ends
-    say(f"gather lam={lam} order={order} wpb={wpb}")
-    c = Case(meshgen.tri_square(7, order=order), lam, "P1", terrain=0.3)
+def test_gather_schedule_shapes(space, lam, order, wpb):
+    # the vertex-column schedule: steps of 62 owned levels (P1), of 64 layers
+    # (CG1 x DG*), so lambda around multiples of 62 and 64 exercises the ends
+    say(f"gather {space} lam={lam} order={order} wpb={wpb}")
+    c = Case(meshgen.tri_square(7, order=order), lam, space, terrain=0.3)
     x = meshgen.uniform_values(c.n, seed=51)
     cfg = exm.par_loop_config(exm.EXM_K_MASS, c.mesh, c.X, c.Vx,
                               [(c.dev(x), c.V, exm.EXM_READ), (c.V.zeros(), c.V, exm.EXM_INC)],
                               schedule=exm.EXM_SCHED_GATHER, waves_per_block=wpb)
     assert cfg["schedule"] == exm.EXM_SCHED_GATHER and cfg["race"] == exm.EXM_RACE_OWNER
     got = c.mass(x, schedule=exm.EXM_SCHED_GATHER, waves_per_block=wpb)
-    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what="gather P1")
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"gather {space}")
 
 
+@pytest.mark.parametrize("space", ["P1", "CG1xDG0", "CG1xDG1"])
 @pytest.mark.parametrize("n", [4, 5, 7])
 @pytest.mark.parametrize("schedule", [exm.EXM_SCHED_GATHER, exm.EXM_SCHED_PIPELINED, exm.EXM_SCHED_DIRECT])
-def test_checkerboard_mesh(n, schedule):
+def test_checkerboard_mesh(space, n, schedule):
     # every other quad removed: interior vertices carry two fans that touch only
     # at the vertex, and (n even) some vertices belong to no cell
-    c = Case(meshgen.tri_checkerboard(n), 9, "P1", terrain=0.2)
+    c = Case(meshgen.tri_checkerboard(n), 9, space, terrain=0.2)
     x = meshgen.uniform_values(c.n, seed=52)
     y0 = meshgen.uniform_values(c.n, seed=53)
     xd = c.dev(x)
     y = c.dev(y0)
     exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
                  schedule=schedule)
-    assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what="checkerboard P1")
+    assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what=f"checkerboard {space}")
 
 
 def test_tiny_config_p1_rhs():
