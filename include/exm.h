@@ -132,7 +132,8 @@ int32_t exm_mesh_entity_layers(const exm_mesh* mesh, int32_t d1, int32_t* lo, in
 #define EXM_ELEMENT_DG1DG1 3   /* DG1 x DG1, delta(2,1) = 6, arity 6            */
 #define EXM_ELEMENT_P2P2 4     /* CG2 x CG2, delta(0,*) = delta(1,*) = 1, arity 18 */
 /* The other tensor products of {CG1, DG0, DG1} (horizontal x vertical) of
- * the paper's study (Section 4.1.3); mass action only, DIRECT schedule. */
+ * the paper's study (Section 4.1.3); mass action only, DIRECT schedule (and
+ * GATHER for CG1 x DG0 and CG1 x DG1). */
 #define EXM_ELEMENT_P1DG0 5    /* CG1 x DG0, delta(0,1) = 1, arity 3            */
 #define EXM_ELEMENT_P1DG1 6    /* CG1 x DG1, delta(0,1) = 2, arity 6            */
 #define EXM_ELEMENT_DG0P1 7    /* DG0 x CG1, delta(2,0) = 1, arity 2            */
