@@ -137,6 +137,101 @@ __global__ void __launch_bounds__(256) k_gather_p1(const GatherP1Args g)
     }
 }
 
+// Two levels per lane: lanes hold levels b = l0 - 1 + 2 i and b + 1, so a
+// wavefront covers 126 owned levels (the first level of lane 0 and the second
+// of lane 63 are halo) and a 101-level column needs one wavefront instead of
+// two.  A lane evaluates prisms (c, b) and (c, b + 1) for node v; level b
+// takes the bottom row of prism b and the top row of prism b - 1 (the lane
+// below), level b + 1 the bottom row of prism b + 1 and the top row of
+// prism b.
+constexpr int kOwned2 = 126;
+
+__global__ void __launch_bounds__(256) k_gather_p1x2(const GatherP1Args g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_g(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t v = wid / g.n_steps;
+    if (v >= g.n_vertices) return;   // uniform over the wavefront
+    const int l0 = (int)(wid - v * g.n_steps) * kOwned2;
+    const int b = l0 - 1 + 2 * lane;
+    const bool in0 = b >= 0 && b <= g.lam, in1 = b + 1 >= 0 && b + 1 <= g.lam;
+    const bool pr0 = b >= 0 && b < g.lam, pr1 = b + 1 >= 0 && b + 1 < g.lam;   // prisms above b and b + 1
+    const int64_t lamp = (int64_t)g.lam + 1;
+    const double* __restrict__ Z = g.X + 2 * g.xn;
+    const int64_t fv = g.fbase + v * lamp, xv = g.xbase + v * lamp;
+    // own column at levels b, b + 1 and (from the next lane) b + 2
+    const double f0a = in0 ? g.f[fv + b] : 0.0, f0b = in1 ? g.f[fv + b + 1] : 0.0;
+    const double z0a = in0 ? Z[xv + b] : 0.0, z0b = in1 ? Z[xv + b + 1] : 0.0;
+    const double f0c = __shfl_down(f0a, 1, 64), z0c = __shfl_down(z0a, 1, 64);
+    const double px0 = g.X[xv], py0 = g.X[g.xn + xv];
+    double yb0 = 0.0, yt0 = 0.0, yb1 = 0.0, yt1 = 0.0;
+    double fpa = 0.0, fpb = 0.0, fpc = 0.0, zpa = 0.0, zpb = 0.0, zpc = 0.0, pxp = 0.0, pyp = 0.0;
+    const int32_t e0 = g.fan_off[v], e1 = g.fan_off[v + 1];
+    constexpr int kBlk = 4;
+    for (int32_t e = e0; e < e1; e += kBlk) {
+        int32_t ent[kBlk];
+        double fa[kBlk], fb[kBlk], za[kBlk], zb[kBlk], px1[kBlk], py1[kBlk];
+#pragma unroll
+        for (int k = 0; k < kBlk; ++k) {
+            const bool has = e + k < e1;   // uniform over the wavefront
+            ent[k] = has ? g.fan[e + k] : 0;
+            const int64_t w = ent[k] & 0x7fffffff;
+            const int64_t fw = g.fbase + w * lamp, xw = g.xbase + w * lamp;
+            fa[k] = has && in0 ? g.f[fw + b] : 0.0;
+            fb[k] = has && in1 ? g.f[fw + b + 1] : 0.0;
+            za[k] = has && in0 ? Z[xw + b] : 0.0;
+            zb[k] = has && in1 ? Z[xw + b + 1] : 0.0;
+            px1[k] = has ? g.X[xw] : 0.0;
+            py1[k] = has ? g.X[g.xn + xw] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kBlk; ++k) {
+            if (e + k >= e1) break;
+            const double fc = __shfl_down(fa[k], 1, 64), zc = __shfl_down(za[k], 1, 64);
+            if (ent[k] >= 0) {   // cell (v, previous, w)
+                const double twoA = fabs((pxp - px0) * (py1[k] - py0) - (px1[k] - px0) * (pyp - py0));
+                const double s = twoA * (1.0 / 120.0);
+                if (pr0) {
+                    const double h[3] = {z0b - z0a, zpb - zpa, zb[k] - za[k]};
+                    const double xb[3] = {f0a, fpa, fa[k]};
+                    const double xt[3] = {f0b, fpb, fb[k]};
+                    double r0, r1;
+                    p1_row(s, h, xb, xt, r0, r1);
+                    yb0 += r0;
+                    yt0 += r1;
+                }
+                if (pr1) {
+                    const double h[3] = {z0c - z0b, zpc - zpb, zc - zb[k]};
+                    const double xb[3] = {f0b, fpb, fb[k]};
+                    const double xt[3] = {f0c, fpc, fc};
+                    double r0, r1;
+                    p1_row(s, h, xb, xt, r0, r1);
+                    yb1 += r0;
+                    yt1 += r1;
+                }
+            }
+            fpa = fa[k];
+            fpb = fb[k];
+            fpc = fc;
+            zpa = za[k];
+            zpb = zb[k];
+            zpc = zc;
+            pxp = px1[k];
+            pyp = py1[k];
+        }
+    }
+    const double below = __shfl_up(yt1, 1, 64);   // top row of prism b - 1
+    const auto put = [&](int lev, double val) {
+        if (g.write)
+            g.y[fv + lev] = val;
+        else
+            g.y[fv + lev] += val;
+    };
+    if (lane >= 1 && in0) put(b, yb0 + below);
+    if (lane <= 62 && in1) put(b + 1, yb1 + yt0);
+}
+
 // The same owner-computes walk for the spaces whose vertex columns are
 // discontinuous across levels: CG1 x DG0 (NV = 1, one DoF per layer) and
 // CG1 x DG1 (NV = 2, bottom and top node per layer).  There is no vertical
@@ -336,7 +431,9 @@ int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, 
     g.n_vertices = P.fspace->mesh->n[0];
     g.lam = P.n_layers;
     const bool levels = P.element == EXM_ELEMENT_P1P1;   // DoFs on the levels, else inside the layers
-    g.n_steps = levels ? (P.n_layers + 1 + kOwned - 1) / kOwned : (P.n_layers + 63) / 64;
+    const bool two = levels && P.n_layers + 1 > kOwned;   // columns longer than one 62-level step
+    g.n_steps = levels ? (two ? (P.n_layers + 1 + kOwned2 - 1) / kOwned2 : (P.n_layers + 1 + kOwned - 1) / kOwned)
+                       : (P.n_layers + 63) / 64;
     g.write = P.write;
     g.fbase = P.fspace->base[0];
     g.xbase = P.xspace->base[0];
@@ -350,7 +447,9 @@ int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, 
     const int64_t waves = (int64_t)g.n_vertices * g.n_steps;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     if (blocks * wpb > INT32_MAX) return fail(EXM_ERANGE, "grid too large");
-    if (levels)
+    if (levels && two)
+        hipLaunchKernelGGL(k_gather_p1x2, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+    else if (levels)
         hipLaunchKernelGGL(k_gather_p1, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
     else if (P.element == EXM_ELEMENT_P1DG0)
         hipLaunchKernelGGL(k_gather_p1dg<1>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
