@@ -311,7 +311,7 @@ def main():
 
     if not args.quick:
         try:
-            result["secondary"] = secondary(torch, exm, W, meshgen)
+            result["secondary"] = add_roofline(secondary(torch, exm, W, meshgen), stream_gbs)
         except Exception as e:   # secondary figures never hide the main line
             log(f"secondary measurements failed: {e!r}")
             result["secondary"] = {"error": repr(e)}
@@ -372,6 +372,19 @@ def direct_shapes(exm, name):
     races = [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR] if name in exm.CONTINUOUS else [exm.EXM_RACE_ATOMIC]
     return [dict(schedule=exm.EXM_SCHED_DIRECT, race=r, cols_per_wave=c, waves_per_block=w)
             for r in races for c, w in ((1, 4), (2, 4), (3, 4), (4, 4), (1, 2), (2, 2), (4, 2))]
+
+
+def add_roofline(tree, stream_gbs):
+    """Every secondary figure with an algorithmic GB/s gets its fraction of the
+    HBM peak and of the measured STREAM triad (these kernels are HBM-bound)."""
+    if isinstance(tree, dict):
+        out = {k: add_roofline(v, stream_gbs) for k, v in tree.items()}
+        for key in ("gbs", "spmv_gbs", "assemble_gbs", "batched_gbs"):
+            if isinstance(tree.get(key), (int, float)):
+                out[key.replace("gbs", "frac_hbm")] = round(tree[key] / HBM_PEAK_GBS, 4)
+                out[key.replace("gbs", "frac_stream")] = round(tree[key] / stream_gbs, 4)
+        return out
+    return tree
 
 
 def secondary(torch, exm, W, meshgen):
