@@ -408,7 +408,7 @@ def secondary(torch, exm, W, meshgen):
     del e9
     # columns of different heights: 512 x 512 x 100 with the bottom of every
     # column following a smooth bump (meshgen.layer_ranges, "bathymetry"),
-    # beside the DIRECT schedule on the uniform mesh of the same sizes
+    # beside the uniform mesh of the same sizes, with the schedules both run
     var = {}
     for kind in (None, "bathymetry"):
         ev = W.extruded(512, 100, layer_kind=kind)
@@ -416,19 +416,23 @@ def secondary(torch, exm, W, meshgen):
             V = ev.space(name)
             x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
             y = V.zeros()
-            if kind:   # the tuner tries DIRECT shapes only on such a mesh
-                cfg = exm.autotune(exm.EXM_K_MASS, ev.mesh, ev.X, ev.Vx, W.mass_args(ev, name, x, y))
-                t, _ = timed(torch, lambda: W.run_mass(ev, name, x, y, **cfg), 10)
-            else:      # the same DIRECT shapes on the uniform mesh
-                t, cfg = min(((timed(torch, lambda: W.run_mass(ev, name, x, y, **c), 10)[0], c)
-                              for c in direct_shapes(exm, name)), key=lambda tc: tc[0])
+            # the DIRECT shapes (the tuner's candidates on such a mesh), and GATHER for P1
+            shapes = direct_shapes(exm, name)
+            if name == "P1":
+                shapes += [dict(schedule=exm.EXM_SCHED_GATHER, waves_per_block=w) for w in (1, 2, 4)]
             b = W.mass_bytes(ev, name)
-            var[f"{name}_{kind or 'uniform'}"] = {"prisms": ev.n_prisms, "ms": round(t, 4),
-                                                  "gbs": round(b["algorithmic"] / t / 1e6, 1),
-                                                  "prisms_per_s": round(ev.n_prisms / t * 1e3), "launch": cfg}
+            for label, group in (("direct", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_DIRECT]),
+                                 ("gather", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_GATHER])):
+                if not group:
+                    continue
+                t, cfg = min(((timed(torch, lambda: W.run_mass(ev, name, x, y, **c), 10)[0], c) for c in group),
+                             key=lambda tc: tc[0])
+                var[f"{name}_{kind or 'uniform'}_{label}"] = {
+                    "prisms": ev.n_prisms, "ms": round(t, 4), "gbs": round(b["algorithmic"] / t / 1e6, 1),
+                    "prisms_per_s": round(ev.n_prisms / t * 1e3), "launch": cfg}
             del x, y
         del ev
-    out["rhs_direct_variable_layers_512x512x100"] = var
+    out["rhs_variable_layers_512x512x100"] = var
     log("variable layers: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in var.items()))
     out["matrix_p1_512x512x100"] = matrix_figures(torch, exm, W, meshgen)
     # mixed-degree DG (a DoF count per entity): half the cells DG1, half DG0, 256 x 256 x 64

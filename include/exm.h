@@ -89,8 +89,10 @@ void exm_mesh_destroy(exm_mesh* mesh);
  * numbers every entity over its own range, so column starts become a prefix
  * sum, and a cell's explicit list is the stencil of its bottom prism, so that
  * L(c) + l * offset addresses layer layers[2c] + l of its column.  Loops on
- * such a mesh run the DIRECT schedule whatever the options ask, and refuse
- * EXM_RACE_OWNER (EXM_EUNSUPPORTED); batches take uniform meshes only.
+ * such a mesh run the DIRECT schedule whatever the options ask (or GATHER,
+ * when asked for, on the mass of P1P1, CG1xDG0 and CG1xDG1), and refuse
+ * EXM_RACE_OWNER with the tiled schedules (EXM_EUNSUPPORTED); batches take
+ * uniform meshes only.
  * Other arguments and errors as exm_mesh_create; a vertex that belongs to no
  * cell is rejected (EXM_EINVAL). */
 int32_t exm_mesh_create_var(int32_t n_vertices, int32_t n_edges, int32_t n_cells,

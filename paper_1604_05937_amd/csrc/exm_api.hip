@@ -251,9 +251,10 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
-    if (mesh->variable) {   // columns of different heights: the DIRECT schedule walks each on its own
+    if (mesh->variable && !(d.schedule == EXM_SCHED_GATHER && gather_supported(P.kernel, P.element))) {
+        // columns of different heights: the DIRECT schedule walks each on its own (or GATHER)
         EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED,
-                  "owner-computes needs columns of one height; this mesh has a layer range per column");
+                  "owner-computes tiles need columns of one height; this mesh has a layer range per column");
         if (d.schedule != EXM_SCHED_DIRECT) d.cols_per_wave = d.waves_per_block = 0;
         d.schedule = EXM_SCHED_DIRECT;
         d.tile_cells = d.chunk_layers = 0;
@@ -636,8 +637,10 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     const int32_t races[2] = {EXM_RACE_ATOMIC, EXM_RACE_COLOUR};
     for (int r = 0; r < (cg ? 2 : 1); ++r) {
         for (int32_t c : {1, 2, 3, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 4, 0, 0});
-        if (iterset->variable) {   // columns of different heights run DIRECT only
+        if (iterset->variable) {   // columns of different heights run DIRECT (or GATHER)
             for (int32_t c : {1, 2, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 2, 0, 0});
+            if (r == 0 && gather_supported(P.kernel, P.element))
+                for (int32_t w : {1, 2, 4}) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_GATHER, 0, w, 0, 0});
             continue;
         }
         if (r == 0 && gather_supported(P.kernel, P.element))

@@ -231,6 +231,9 @@ static int32_t mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
         }
         s = m->d_cell_lam.upload(lam.data(), lam.size());
         if (s != EXM_OK) return s;
+        if ((s = m->d_cell_lo.upload(m->lo[2].data(), m->lo[2].size())) != EXM_OK) return s;
+        if ((s = m->d_vert_lo.upload(m->lo[0].data(), m->lo[0].size())) != EXM_OK) return s;
+        if ((s = m->d_vert_hi.upload(m->hi[0].data(), m->hi[0].size())) != EXM_OK) return s;
     }
     *out = m.release();
     return EXM_OK;

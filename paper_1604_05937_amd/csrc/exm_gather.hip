@@ -38,6 +38,14 @@ struct GatherP1Args {
     int64_t xn;
     const double* __restrict__ f;
     double* __restrict__ y;
+    // columns of different heights
+    const int32_t* __restrict__ fstart;    // column start of every vertex in the field space
+    const int32_t* __restrict__ xstart;    // ... in the coordinate space
+    const int32_t* __restrict__ vlo;       // level range lo .. hi of every vertex column
+    const int32_t* __restrict__ vhi;
+    const int32_t* __restrict__ cell_lo;   // layers cell_lo .. cell_lo + cell_lam - 1 of every cell
+    const int32_t* __restrict__ cell_lam;
+    const int32_t* __restrict__ fan_cell;  // the cell of every fan entry (-1 at the start of a fan)
 };
 
 // Row of node v (index 0) of the P1 x P1 mass action on one prism (the
@@ -328,6 +336,157 @@ __global__ void __launch_bounds__(256) k_gather_p1dg(const GatherP1Args g)
     }
 }
 
+// GATHER on a mesh whose columns differ in height (P1 x P1).  The wavefront
+// walks its vertex column from the column's own bottom level; a neighbour's
+// values come from its own column at the same absolute level, and the
+// prisms of a cell of the fan count only within the cell's layer range (the
+// columns of its three vertices span that range, so the levels it needs are
+// present).
+__global__ void __launch_bounds__(256) k_gather_p1_var(const GatherP1Args g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_g(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t v = wid / g.n_steps;
+    if (v >= g.n_vertices) return;   // uniform over the wavefront
+    const int lo_v = g.vlo[v], nlev = g.vhi[v] - lo_v + 1;
+    const int q0 = (int)(wid - v * g.n_steps) * kOwned;
+    if (q0 >= nlev) return;          // beyond this column (uniform)
+    const int q = q0 - 1 + lane;     // level of the column, from its bottom
+    const int lev = lo_v + q;        // absolute level
+    const bool in = q >= 0 && q < nlev;
+    const double* __restrict__ Z = g.X + 2 * g.xn;
+    const int64_t fv = g.fstart[v], xv = g.xstart[v];
+    const double f0 = in ? g.f[fv + q] : 0.0;
+    const double z0 = in ? Z[xv + q] : 0.0;
+    const double f0n = __shfl_down(f0, 1, 64), z0n = __shfl_down(z0, 1, 64);
+    const double px0 = g.X[xv], py0 = g.X[g.xn + xv];
+    double acc_b = 0.0, acc_t = 0.0;
+    double fp = 0.0, fpn = 0.0, zp = 0.0, zpn = 0.0, pxp = 0.0, pyp = 0.0;
+    const int32_t e0 = g.fan_off[v], e1 = g.fan_off[v + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t ent = g.fan[e];
+        const int32_t w = ent & 0x7fffffff;
+        const int32_t c = g.fan_cell[e];
+        const int lo_w = g.vlo[w], hi_w = g.vhi[w];
+        const int64_t fw = g.fstart[w], xw = g.xstart[w];
+        const bool inw = in && lev >= lo_w && lev <= hi_w;
+        const double f1 = inw ? g.f[fw + (lev - lo_w)] : 0.0;
+        const double z1 = inw ? Z[xw + (lev - lo_w)] : 0.0;
+        const double f1n = __shfl_down(f1, 1, 64), z1n = __shfl_down(z1, 1, 64);
+        const double px1 = g.X[xw], py1 = g.X[g.xn + xw];
+        if (c >= 0) {
+            const int cb = g.cell_lo[c], ct = cb + g.cell_lam[c];
+            if (in && lev >= cb && lev < ct) {   // prism (c, lev) of cell (v, previous, w)
+                const double twoA = fabs((pxp - px0) * (py1 - py0) - (px1 - px0) * (pyp - py0));
+                const double h[3] = {z0n - z0, zpn - zp, z1n - z1};
+                const double xb[3] = {f0, fp, f1};
+                const double xt[3] = {f0n, fpn, f1n};
+                double yb, yt;
+                p1_row(twoA * (1.0 / 120.0), h, xb, xt, yb, yt);
+                acc_b += yb;
+                acc_t += yt;
+            }
+        }
+        fp = f1;
+        fpn = f1n;
+        zp = z1;
+        zpn = z1n;
+        pxp = px1;
+        pyp = py1;
+    }
+    const double below = __shfl_up(acc_t, 1, 64);
+    if (lane >= 1 && lane <= kOwned && in) {
+        const double val = acc_b + below;
+        if (g.write)
+            g.y[fv + q] = val;
+        else
+            g.y[fv + q] += val;
+    }
+}
+
+// GATHER on a mesh whose columns differ in height, CG1 x DG0 (NV = 1) and
+// CG1 x DG1 (NV = 2): one lane per layer of the vertex column.
+template <int NV>
+__global__ void __launch_bounds__(256) k_gather_p1dg_var(const GatherP1Args g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_g(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int64_t v = wid / g.n_steps;
+    if (v >= g.n_vertices) return;   // uniform over the wavefront
+    const int lo_v = g.vlo[v], nl = g.vhi[v] - lo_v;
+    const int q0 = (int)(wid - v * g.n_steps) * 64;
+    if (q0 >= nl) return;            // beyond this column (uniform)
+    const int q = q0 + lane;         // layer of the column, from its bottom
+    const int lev = lo_v + q;
+    const bool act = q < nl;
+    const double* __restrict__ Z = g.X + 2 * g.xn;
+    const int64_t fv = g.fstart[v], xv = g.xstart[v];
+    double x0[NV];
+#pragma unroll
+    for (int b = 0; b < NV; ++b) x0[b] = act ? g.f[fv + NV * q + b] : 0.0;
+    const double z0 = act ? Z[xv + q] : 0.0, z0n = act ? Z[xv + q + 1] : 0.0;
+    const double px0 = g.X[xv], py0 = g.X[g.xn + xv];
+    double acc[NV], xp[NV];
+#pragma unroll
+    for (int b = 0; b < NV; ++b) acc[b] = xp[b] = 0.0;
+    double zp = 0.0, zpn = 0.0, pxp = 0.0, pyp = 0.0;
+    const int32_t e0 = g.fan_off[v], e1 = g.fan_off[v + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t w = g.fan[e] & 0x7fffffff;
+        const int32_t c = g.fan_cell[e];
+        const int lo_w = g.vlo[w], hi_w = g.vhi[w];
+        const int64_t fw = g.fstart[w], xw = g.xstart[w];
+        const bool inw = act && lev >= lo_w && lev < hi_w;
+        double x1[NV];
+#pragma unroll
+        for (int b = 0; b < NV; ++b) x1[b] = inw ? g.f[fw + NV * (lev - lo_w) + b] : 0.0;
+        const double z1 = inw ? Z[xw + (lev - lo_w)] : 0.0, z1n = inw ? Z[xw + (lev - lo_w) + 1] : 0.0;
+        const double px1 = g.X[xw], py1 = g.X[g.xn + xw];
+        if (c >= 0) {
+            const int cb = g.cell_lo[c], ct = cb + g.cell_lam[c];
+            if (act && lev >= cb && lev < ct) {
+                const double twoA = fabs((pxp - px0) * (py1 - py0) - (px1 - px0) * (pyp - py0));
+                const double h[3] = {z0n - z0, zpn - zp, z1n - z1};
+                const double H = h[0] + h[1] + h[2];
+                const double s = twoA * (1.0 / 120.0);
+#pragma unroll
+                for (int b = 0; b < NV; ++b) {
+                    double gv, gp, gw;
+                    if constexpr (NV == 1) {
+                        gv = x0[0];
+                        gp = xp[0];
+                        gw = x1[0];
+                    } else {
+                        const double cs = b == 0 ? 1.0 / 3.0 : 1.0 / 6.0, ct2 = b == 0 ? 1.0 / 6.0 : 1.0 / 3.0;
+                        gv = cs * x0[0] + ct2 * x0[1];
+                        gp = cs * xp[0] + ct2 * xp[1];
+                        gw = cs * x1[0] + ct2 * x1[1];
+                    }
+                    const double G = gv + gp + gw;
+                    const double HG = h[0] * gv + h[1] * gp + h[2] * gw;
+                    acc[b] += s * ((2.0 * h[0] + H) * gv + (h[0] + H) * G + HG);
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NV; ++b) xp[b] = x1[b];
+        zp = z1;
+        zpn = z1n;
+        pxp = px1;
+        pyp = py1;
+    }
+    if (!act) return;
+#pragma unroll
+    for (int b = 0; b < NV; ++b) {
+        if (g.write)
+            g.y[fv + NV * q + b] = acc[b];
+        else
+            g.y[fv + NV * q + b] += acc[b];
+    }
+}
+
 }  // namespace
 
 // Fans of base cells around every vertex, in cyclic order: for vertex v the
@@ -354,8 +513,9 @@ int32_t build_vertex_fans(const exm_mesh* m, const VertexFans** out)
         for (int32_t c = 0; c < nc; ++c)
             for (int a = 0; a < 3; ++a) vcells[fill[cv[c * 3 + a]]++] = c;
     }
-    std::vector<int32_t> off(nv + 1, 0), fan;
+    std::vector<int32_t> off(nv + 1, 0), fan, fcell;
     fan.reserve((size_t)nc * 4);
+    fcell.reserve((size_t)nc * 4);
     std::vector<int32_t> na, nb;   // the two other vertices of every cell of the star
     std::vector<char> used;
     for (int32_t v = 0; v < nv; ++v) {
@@ -392,6 +552,7 @@ int32_t build_vertex_fans(const exm_mesh* m, const VertexFans** out)
                     if (!used[i]) { s = i; entry = na[i]; }
             }
             fan.push_back(entry | (int32_t)0x80000000);
+            fcell.push_back(-1);
             int64_t cur = s;
             int32_t from = entry;
             while (cur >= 0) {
@@ -399,6 +560,7 @@ int32_t build_vertex_fans(const exm_mesh* m, const VertexFans** out)
                 --left;
                 const int32_t exit = na[cur] == from ? nb[cur] : na[cur];
                 fan.push_back(exit);
+                fcell.push_back(vcells[b + cur]);
                 int64_t next = -1;
                 for (int64_t i = 0; i < n && next < 0; ++i)
                     if (!used[i] && (na[i] == exit || nb[i] == exit)) next = i;
@@ -412,6 +574,7 @@ int32_t build_vertex_fans(const exm_mesh* m, const VertexFans** out)
     int32_t st;
     if ((st = F->off.upload(off.data(), off.size())) != EXM_OK) return st;
     if ((st = F->fan.upload(fan.data(), fan.size())) != EXM_OK) return st;
+    if ((st = F->cell.upload(fcell.data(), fcell.size())) != EXM_OK) return st;
     F->n_entries = (int64_t)fan.size();
     m->fans = std::move(F);
     *out = m->fans.get();
@@ -444,6 +607,28 @@ int32_t launch_gather(const LoopLaunch& P, const VertexFans* fans, int32_t wpb, 
     g.f = P.in[0];
     g.y = P.out[0];
     if (g.n_vertices == 0) return EXM_OK;
+    const exm_mesh* m = P.fspace->mesh;
+    if (m->variable) {   // columns of different heights: starts and ranges from the mesh and the spaces
+        g.fstart = P.fspace->d_starts[0].p;
+        g.xstart = P.xspace->d_starts[0].p;
+        g.vlo = m->d_vert_lo.p;
+        g.vhi = m->d_vert_hi.p;
+        g.cell_lo = m->d_cell_lo.p;
+        g.cell_lam = m->d_cell_lam.p;
+        g.fan_cell = fans->cell.p;
+        g.n_steps = levels ? (P.n_layers + 1 + kOwned - 1) / kOwned : (P.n_layers + 63) / 64;
+        const int64_t waves = (int64_t)g.n_vertices * g.n_steps;
+        const int64_t blocks = (waves + wpb - 1) / wpb;
+        if (blocks * wpb > INT32_MAX) return fail(EXM_ERANGE, "grid too large");
+        if (levels)
+            hipLaunchKernelGGL(k_gather_p1_var, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+        else if (P.element == EXM_ELEMENT_P1DG0)
+            hipLaunchKernelGGL(k_gather_p1dg_var<1>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+        else
+            hipLaunchKernelGGL(k_gather_p1dg_var<2>, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, g);
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
     const int64_t waves = (int64_t)g.n_vertices * g.n_steps;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     if (blocks * wpb > INT32_MAX) return fail(EXM_ERANGE, "grid too large");

@@ -109,6 +109,7 @@ struct TilePlan {
 struct VertexFans {
     DevBuf<int32_t> off;   // [n_vertices + 1]
     DevBuf<int32_t> fan;   // neighbouring vertices in fan order; bit 31 flags the start of a fan
+    DevBuf<int32_t> cell;  // the cell between an entry and the one before it (-1 at the start of a fan)
     int64_t n_entries = 0;
 };
 
@@ -121,6 +122,8 @@ struct exm_mesh {
     bool variable = false;         // each cell column has its own layer range
     std::vector<int32_t> lo[3], hi[3];   // variable: layer range [lo, hi) of every entity column
     exm::DevBuf<int32_t> d_cell_lam;     // variable: layers of every cell column
+    exm::DevBuf<int32_t> d_cell_lo;      // variable: first layer of every cell column
+    exm::DevBuf<int32_t> d_vert_lo, d_vert_hi;   // variable: level range of every vertex column
     std::vector<int32_t> h_cell_vertex, h_cell_edge;
     exm::DevBuf<int32_t> d_cell_vertex, d_cell_edge;
     mutable std::mutex mu;

@@ -129,3 +129,31 @@ def test_variable_mesh_refuses_owner_computes():
         exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(x, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
                      race=exm.EXM_RACE_OWNER)
     assert e.value.status == exm._abi.EXM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("space", ["P1", "CG1xDG0", "CG1xDG1"])
+@pytest.mark.parametrize("n,lam,kind", SHAPES + [(6, 62, "random"), (5, 125, "bathymetry")])
+@pytest.mark.parametrize("wpb", [1, 4])
+def test_variable_gather(space, n, lam, kind, wpb):
+    # the vertex-column schedule on columns of different heights: every
+    # neighbour read at the same absolute level, prisms only inside the cell's range
+    say(f"variable gather {space} n={n} lam={lam} {kind} wpb={wpb}")
+    c = _case(n, lam, kind, space)
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    cfg = exm.par_loop_config(exm.EXM_K_MASS, c.mesh, c.X, c.Vx,
+                              [(c.dev(x), c.V, exm.EXM_READ), (c.V.zeros(), c.V, exm.EXM_INC)],
+                              schedule=exm.EXM_SCHED_GATHER, waves_per_block=wpb)
+    assert cfg["schedule"] == exm.EXM_SCHED_GATHER
+    got = c.mass(x, schedule=exm.EXM_SCHED_GATHER, waves_per_block=wpb)
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"variable gather {space}")
+
+
+@pytest.mark.parametrize("space", ["P1", "CG1xDG1"])
+def test_variable_gather_checkerboard(space):
+    base = meshgen.tri_checkerboard(5)
+    lam = 9
+    layers = meshgen.layer_ranges(base, lam, "random")
+    c = Case(base, lam, space, terrain=0.2, layers=layers)
+    x = meshgen.uniform_values(c.n, seed=63)
+    got = c.mass(x, schedule=exm.EXM_SCHED_GATHER)
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"variable gather checkerboard {space}")
