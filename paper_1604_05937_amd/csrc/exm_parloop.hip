@@ -753,9 +753,9 @@ __global__ void __launch_bounds__(256) k_direct_facet(const ColArgs a)
         else
             *p += v;
     };
-    double carry[NH];
+    double carry[NH], xcarry[NH];   // shares of facet l - 1 and (NV = 1) the field value below, per step
 #pragma unroll
-    for (int al = 0; al < NH; ++al) carry[al] = 0.0;
+    for (int al = 0; al < NH; ++al) carry[al] = xcarry[al] = 0.0;
     for (int l0 = 0; l0 <= lam; l0 += a.seg) {
         const int l = l0 + L.lsub;
         const bool act = valid && l <= lam;
@@ -771,8 +771,16 @@ __global__ void __launch_bounds__(256) k_direct_facet(const ColArgs a)
         double j[NH];
 #pragma unroll
         for (int al = 0; al < NH; ++al) {
-            const double lo = below ? a.in0[fb[al][NV - 1] + lb] : 0.0;   // top node of the prism below
             const double hi = above ? a.in0[fb[al][0] + la] : 0.0;        // bottom node of the prism above
+            double lo;                                                    // top node of the prism below
+            if constexpr (NV == 1) {
+                // one DoF per prism: the value below is the lane below's value above
+                const double up = from_below(hi);
+                lo = below ? (L.lsub == 0 ? xcarry[al] : up) : 0.0;
+                xcarry[al] = __shfl(hi, min(L.sub * a.seg + a.seg - 1, 63), 64);
+            } else {
+                lo = below ? a.in0[fb[al][NV - 1] + lb] : 0.0;
+            }
             j[al] = lo - hi;
         }
         double r[NH];
