@@ -1,6 +1,10 @@
-// GATHER schedule of the P1 x P1 mass action: the column loop turned around
-// to iterate the vertex columns of the output (owner computes).
+// GATHER schedule of the mass action on the spaces whose DoFs sit on vertex
+// columns (P1 x P1, CG1 x DG0, CG1 x DG1): the column loop turned around to
+// iterate the vertex columns of the output (owner computes).  Variants: two
+// levels per lane for long P1 columns, one lane per layer for the spaces
+// discontinuous across levels, and columns of different heights.
 //
+// P1 x P1:
 // A wavefront owns one base vertex v and 62 consecutive levels of its column
 // (lanes hold levels l0 - 1 .. l0 + 62; the two end lanes are halo).  It walks
 // the fan of base cells around v in cyclic order, so that every neighbouring
