@@ -284,7 +284,7 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         if (!continuous(P.element)) {
             d.race = EXM_RACE_ATOMIC;   // DG columns belong to one cell: nothing to own
         } else {
-            EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
+            EXM_CHECK(P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1, EXM_EUNSUPPORTED,
                       "owner-computes is implemented for the P1xP1 mass action (PIPELINED schedule)");
             if (d.schedule != EXM_SCHED_PIPELINED && d.schedule != EXM_SCHED_CHUNKED) {
                 d.cols_per_wave = d.waves_per_block = d.tile_cells = 0;
@@ -322,11 +322,13 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     if (d.schedule == EXM_SCHED_PIPELINED) {
         d.waves_per_block = 4;
         d.cols_per_wave = 0;
-        if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 ? 16 : 8;
+        const bool p2 = P.element == EXM_ELEMENT_P2P2;
+        if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 && !p2 ? 16 : 8;
         EXM_CHECK(pipe_chunk_ok(P.element, d.chunk_layers), EXM_ERANGE,
-                  "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1 and 8, 16 or 32 on DG spaces",
+                  "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1, 8 or 16 on P2xP2 and 8, 16 "
+                  "or 32 on DG spaces",
                   d.chunk_layers);
-        if (!d.tile_cells) d.tile_cells = std::min(64, pipe_max_tile_cells(P.element, d.chunk_layers));
+        if (!d.tile_cells) d.tile_cells = std::min(p2 ? 32 : 64, pipe_max_tile_cells(P.element, d.chunk_layers));
         EXM_CHECK(d.tile_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
                   "PIPELINED: tiles of %d cells with %d-layer chunks exceed %d cells", d.tile_cells, d.chunk_layers,
                   pipe_max_tile_cells(P.element, d.chunk_layers));
@@ -342,7 +344,16 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
             EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(d.chunk_layers), EXM_EUNSUPPORTED,
                       "PIPELINED: tiles of %d cells touch up to %d vertices, more than %d with %d-layer chunks",
                       d.tile_cells, plan->max_verts, pipe_max_tile_verts(d.chunk_layers), d.chunk_layers);
-        EXM_CHECK(pipe_lds_bytes(P.kernel, P.element, plan->max_verts, plan->max_cells, d.chunk_layers) <= kLdsLimit,
+        if (p2) {
+            EXM_CHECK(plan->has_edges, EXM_EINVAL, "P2 needs the mesh's cell_edge map");
+            EXM_CHECK(plan->max_verts + plan->max_edges <= pipe_max_tile_entities(d.chunk_layers), EXM_EUNSUPPORTED,
+                      "PIPELINED: tiles of %d cells touch up to %d vertices and %d edges, more than %d entities with "
+                      "%d-layer chunks",
+                      d.tile_cells, plan->max_verts, plan->max_edges, pipe_max_tile_entities(d.chunk_layers),
+                      d.chunk_layers);
+        }
+        EXM_CHECK(pipe_lds_bytes(P.kernel, P.element, plan->max_verts, plan->has_edges ? plan->max_edges : 0,
+                                 plan->max_cells, d.chunk_layers) <= kLdsLimit,
                   EXM_EUNSUPPORTED, "tiles of %d cells with %d-layer chunks do not fit in LDS", d.tile_cells,
                   d.chunk_layers);
         ch = d;
@@ -511,7 +522,8 @@ static int32_t run_pipe(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts
     const bool owner = ch.race == EXM_RACE_OWNER;
     int32_t s = owner ? build_owner_plan(mesh, ch.tile_cells, &plan) : build_tile_plan(mesh, ch.tile_cells, &plan);
     if (s != EXM_OK) return s;
-    const size_t lds = pipe_lds_bytes(P.kernel, P.element, plan->max_verts, plan->max_cells, ch.chunk_layers);
+    const size_t lds = pipe_lds_bytes(P.kernel, P.element, plan->max_verts, plan->has_edges ? plan->max_edges : 0,
+                                      plan->max_cells, ch.chunk_layers);
     P.race = ch.race;
     P.shape = make_shape(1, 1);
     const ColArgs a = col_args(P);
@@ -651,11 +663,13 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                     if (tc <= staged_max_tile_cells(S))
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
         if (pipe_supported(P.kernel, P.element))
-            for (int32_t tc : {32, 48, 64, 96, 128, 256})
+            for (int32_t tc : {16, 24, 32, 48, 64, 96, 128, 256})
                 for (int32_t S : {8, 12, 16, 20, 24, 32})
-                    if (pipe_chunk_ok(P.element, S) && tc <= pipe_max_tile_cells(P.element, S)) {
+                    if (pipe_chunk_ok(P.element, S) && tc <= pipe_max_tile_cells(P.element, S) &&
+                        (tc >= 32 || P.element == EXM_ELEMENT_P2P2)) {
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
-                        if (cg && r == 0) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
+                        if (r == 0 && P.element == EXM_ELEMENT_P1P1)
+                            cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
                         if (P.element == EXM_ELEMENT_P1P1 && (S & (S - 1)) == 0) {
                             cand.push_back(exm_loop_opts{races[r], EXM_SCHED_CHUNKED, 0, 4, tc, S});
                             if (r == 0) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_CHUNKED, 0, 4, tc, S});

@@ -129,33 +129,46 @@ __device__ __forceinline__ double dg0_mass(double twoA, const double h[3], doubl
      {{6, 1, -4, -12, -8, -4}, {1, 6, -4, -8, -12, -4}, {-4, -4, 30, 12, 12, -4},               \
       {-12, -8, 12, 96, 48, 32}, {-8, -12, 12, 48, 96, 32}, {-4, -4, -4, 32, 32, 32}}}
 
-// x[e][beta], y[e][beta]: e = horizontal node 0..5, beta = bottom, top, middle.
-__device__ __forceinline__ void p2_mass(double twoA, const double h[3], const double x[6][3], double y[6][3])
+// Vertical factor of the P2 mass action, 30 V2 x per horizontal node:
+// x[e][beta], g[e][beta], e = horizontal node 0..5, beta = bottom, top, middle.
+__device__ __forceinline__ void p2_vertical(const double x[6][3], double g[6][3])
 {
-    // vertical factor, scaled by 2A / (2520 * 30)
-    constexpr double K[3][6][6] = EXM_P2_K_TABLE;
-    const double s = twoA * (1.0 / (2520.0 * 30.0));
-    double g[6][3];
 #pragma unroll
     for (int e = 0; e < 6; ++e) {
         g[e][0] = 4.0 * x[e][0] - x[e][1] + 2.0 * x[e][2];
         g[e][1] = -x[e][0] + 4.0 * x[e][1] + 2.0 * x[e][2];
         g[e][2] = 2.0 * (x[e][0] + x[e][1]) + 16.0 * x[e][2];
     }
+}
+
+// Row i (horizontal node i, all three vertical nodes) of the P2 mass action
+// from the vertical factors: yi[beta] = 2A / (2520 * 30) sum_j (sum_c h_c
+// K_c[i][j]) g[j][beta].
+__device__ __forceinline__ void p2_mass_row(double twoA, const double h[3], const double g[6][3], int i,
+                                            double yi[3])
+{
+    constexpr double K[3][6][6] = EXM_P2_K_TABLE;
+    const double s = twoA * (1.0 / (2520.0 * 30.0));
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const double t = h[0] * K[0][i][j] + h[1] * K[1][i][j] + h[2] * K[2][i][j];
-            acc0 += t * g[j][0];
-            acc1 += t * g[j][1];
-            acc2 += t * g[j][2];
-        }
-        y[i][0] = s * acc0;
-        y[i][1] = s * acc1;
-        y[i][2] = s * acc2;
+    for (int j = 0; j < 6; ++j) {
+        const double t = h[0] * K[0][i][j] + h[1] * K[1][i][j] + h[2] * K[2][i][j];
+        acc0 += t * g[j][0];
+        acc1 += t * g[j][1];
+        acc2 += t * g[j][2];
     }
+    yi[0] = s * acc0;
+    yi[1] = s * acc1;
+    yi[2] = s * acc2;
+}
+
+// x[e][beta], y[e][beta]: e = horizontal node 0..5, beta = bottom, top, middle.
+__device__ __forceinline__ void p2_mass(double twoA, const double h[3], const double x[6][3], double y[6][3])
+{
+    double g[6][3];
+    p2_vertical(x, g);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p2_mass_row(twoA, h, g, i, y[i]);
 }
 
 // ---------------------------------------------------------------------------

@@ -520,6 +520,251 @@ __global__ void __launch_bounds__(NT, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs
     store_results();
 }
 
+// P2 x P2 mass action, y += M x (INC).  The tile walk of k_pipe_p1 with the
+// P2 columns: every base vertex and edge of the tile owns a field column of
+// 2 lambda + 1 nodes (level l at 2 l, the middle of layer l at 2 l + 1), and
+// per chunk of S layers its 2 S + 1 nodes land in LDS next to the S + 1 levels
+// of z of every tile vertex.  Entity slots: the tile's vertices first, then
+// its edges.  LDS: Z[2] of vstride * (S + 2) doubles, X[2] and the
+// accumulator A of estride2 * (2 S + 2) doubles (estride2 = vstride +
+// estride), then tag and field column start per entity and the coordinate
+// column start per vertex (ints); (x, y) per vertex only during set-up,
+// inside A.  Each thread takes one layer of one cell and adds each row of
+// the element to LDS as soon as it is computed (one layer per thread keeps
+// the element's registers within three wavefronts per SIMD).  Old output
+// values of a chunk are loaded into registers right after the previous chunk
+// is written back and added when this one is, one step later.
+constexpr int kLayers2 = 1;   // consecutive layers of one cell per thread: tile_cells <= 256 * kLayers2 / S
+constexpr int kItems2 = 8;    // output items per thread: (vertices + edges) * 2 S <= 256 * kItems2
+
+template <int S, int MODE>
+__global__ void __launch_bounds__(kThreads) k_pipe_p2(const ColArgs a, const TileArgs t)
+{
+    static_assert(MODE != kOwner, "no owner plan for edges");
+    constexpr bool ATOMIC = MODE == kAtomic;
+    constexpr int PZ = S + 2, PZP = PZ / 2;        // z slot (doubles, 16-byte pairs)
+    constexpr int PX = 2 * S + 2, PXP = PX / 2;    // field / accumulator slot
+    constexpr int W = 2 * S;                       // nodes a chunk writes per entity (the top one carries)
+    constexpr int R = kLayers2, G = S / R;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int32_t eb0 = t.edge_off[tile], ne = t.edge_off[tile + 1] - eb0;
+    const int32_t nent = nv + ne;
+    const int ES = t.vstride + t.estride;
+    const int VZ = t.vstride * PZ;
+    const int VX = ES * PX;
+    double* const Zs = lds;
+    double* const Xs = lds + 2 * VZ;
+    double* const A = Xs + 2 * VX;
+    double* const Tx = A;                 // set-up only
+    double* const Ty = A + t.vstride;
+    int32_t* const Ttag = (int32_t*)(A + VX);
+    int32_t* const Tfst = Ttag + ES;
+    int32_t* const Txst = Tfst + ES;
+    const int64_t n = a.xn, fn = a.fn;
+    const double* const z = a.X + 2 * n;
+    const double* const x = a.in0;
+    double* const y = a.out0;
+    const int lam = a.n_layers;
+
+    // entity table: tag, field column start; per vertex the coordinate column
+    // start and (x, y) of the column
+    for (int e = tid; e < nent; e += kThreads) {
+        const bool vert = e < nv;
+        const int32_t tag = vert ? t.verts[vb0 + e] : t.edges[eb0 + e - nv];
+        Ttag[e] = tag;
+        Tfst[e] = vert ? t.fstart0[vid(tag)] : t.fstart1[vid(tag)];
+        if (vert) {
+            const int32_t xs = t.xstart[vid(tag)];
+            Txst[e] = xs;
+            Tx[e] = a.X[xs];
+            Ty[e] = a.X[n + xs];
+        }
+    }
+    lds_barrier();
+
+    // this thread's cell: z slot of each vertex, field slot of each of the
+    // six horizontal nodes (vertices 0, 1, 2, then the edges opposite them),
+    // with the parity shifts, and 2A; layers r0 .. r0 + R - 1 of every chunk
+    const int r0 = (tid % G) * R;
+    int zb[3], xb[6];
+    double twoA;
+    const bool has = tid / G < nc;
+    {
+        const int c = tid / G;
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = has ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            const int le = has ? nv + (int)t.lce[(int64_t)(cb + c) * 3 + q] : 0;
+            zb[q] = lv * PZ + (Txst[lv] & 1);
+            xb[q] = lv * PX + (Tfst[lv] & 1);
+            xb[3 + q] = le * PX + (Tfst[le] & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA = has ? twice_area(xq, yq) : 0.0;
+    }
+
+    lds_barrier();   // (x, y) are no longer needed: the accumulator takes their place
+    for (int i = tid; i < VX; i += kThreads) A[i] = 0.0;
+    const int wave_e = tid & ~63;
+
+    // copies of chunk k: z pairs of every vertex (levels from the even global
+    // index at or below l0), field pairs of every entity (nodes from the even
+    // global index at or below 2 l0)
+    auto issue_copies = [&](int k) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        const int b = k & 1;
+        for (int e0 = 0; e0 < nv * PZP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int v = e / PZP, w = e - (e / PZP) * PZP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int sv = xs & 1;
+            if (2 * w - sv > nl) continue;
+            const int64_t g = (int64_t)xs - sv + l0 + 2 * w;
+            if (g + 1 < n)
+                copy16(z + g, Zs + b * VZ + 2 * (e0 + wave_e));
+            else   // the array's last element: keep the read inside the array
+                Zs[b * VZ + 2 * e] = z[g];
+        }
+        for (int e0 = 0; e0 < nent * PXP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int s = e / PXP, w = e - (e / PXP) * PXP;
+            if (s >= nent) continue;
+            const int32_t fs = Tfst[s];
+            const int sv = fs & 1;
+            if (2 * w - sv > 2 * nl) continue;
+            const int64_t g = (int64_t)fs - sv + 2 * l0 + 2 * w;
+            if (g + 1 < fn)
+                copy16(x + g, Xs + b * VX + 2 * (e0 + wave_e));
+            else
+                Xs[b * VX + 2 * e] = x[g];
+        }
+    };
+    // output items: item i of this thread is (entity, node) (tid + 256 i) / W,
+    // (tid + 256 i) % W of the chunk; its kind is 0 (none), 1 (read-add-write)
+    // or 2 (atomic)
+    auto item_kind = [&](int i) {
+        const int e = (tid + kThreads * i) / W;
+        return e >= nent ? 0 : ((ATOMIC && vshared(Ttag[e])) ? 2 : 1);
+    };
+    auto load_old = [&](int k, double (&dst)[kItems2]) {
+        const int nl = min(S, lam - k * S);
+#pragma unroll
+        for (int i = 0; i < kItems2; ++i) {
+            const int it = tid + kThreads * i;
+            const int e = it / W, jj = it % W;
+            dst[i] = (item_kind(i) == 1 && jj < 2 * nl) ? y[(int64_t)Tfst[e] + 2 * k * S + jj] : 0.0;
+        }
+    };
+    auto write_back = [&](int k, const double (&old)[kItems2], bool carry) {
+        const int nl = min(S, lam - k * S);
+#pragma unroll
+        for (int i = 0; i < kItems2; ++i) {
+            const int it = tid + kThreads * i;
+            const int e = it / W, jj = it % W;
+            const int kind = item_kind(i);
+            if (kind == 0 || jj >= 2 * nl) continue;
+            const int32_t fs = Tfst[e];
+            const int pos = e * PX + (fs & 1) + jj;
+            const double s = A[pos];
+            const int64_t g = (int64_t)fs + 2 * k * S + jj;
+            if (kind == 2)
+                unsafeAtomicAdd(y + g, s);
+            else
+                y[g] = old[i] + s;
+            if (carry && jj == 0) {
+                A[pos] = A[pos + W];
+                A[pos + W] = 0.0;
+            } else {
+                A[pos] = 0.0;
+            }
+        }
+    };
+
+    // yO: old output values of the chunk written back next
+    double yO[kItems2];
+    const int nch = (lam + S - 1) / S;
+    issue_copies(0);
+    load_old(0, yO);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int nl = min(S, lam - k * S);
+        wait_copies();
+        lds_barrier();
+        if (k > 0) {
+            write_back(k - 1, yO, true);
+            load_old(k, yO);
+        }
+        lds_barrier();
+        if (k + 1 < nch) issue_copies(k + 1);
+        if (!has || r0 >= nl) continue;
+        const double* const Zb = Zs + b * VZ;
+        const double* const Xb = Xs + b * VX;
+        double zc[3], xv[6][3], acc[6];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) zc[q] = Zb[zb[q] + r0];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            xv[e][0] = Xb[xb[e] + 2 * r0];
+            acc[e] = 0.0;
+        }
+        int r = 0;
+#pragma unroll
+        for (; r < R; ++r) {
+            if (r0 + r >= nl) break;
+            const int o = 2 * (r0 + r);
+            double h[3], g[6][3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double zn = Zb[zb[q] + r0 + r + 1];
+                h[q] = zn - zc[q];
+                zc[q] = zn;
+            }
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                xv[e][2] = Xb[xb[e] + o + 1];
+                xv[e][1] = Xb[xb[e] + o + 2];
+            }
+            p2_vertical(xv, g);
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                double yi[3];
+                p2_mass_row(twoA, h, g, e, yi);
+                lds_add(A + xb[e] + o, acc[e] + yi[0]);
+                lds_add(A + xb[e] + o + 1, yi[2]);
+                acc[e] = yi[1];
+                xv[e][0] = xv[e][1];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) lds_add(A + xb[e] + 2 * (r0 + r), acc[e]);
+    }
+    // write back the last chunk, its top node included
+    lds_barrier();
+    {
+        const int k = nch - 1;
+        const int nl = lam - k * S;
+        write_back(k, yO, false);
+        for (int e = tid; e < nent; e += kThreads) {
+            const int32_t fs = Tfst[e];
+            const double s = A[e * PX + (fs & 1) + 2 * nl];
+            const int64_t g = (int64_t)fs + 2 * lam;
+            if (ATOMIC && vshared(Ttag[e]))
+                unsafeAtomicAdd(y + g, s);
+            else
+                y[g] += s;
+        }
+    }
+}
+
 // CHUNKED schedule, P1 x P1 mass action / RHS (INC): one workgroup per
 // (tile, chunk).  Chunk c computes the layers c (S - 1) .. c (S - 1) + S - 1
 // and writes the levels whose two neighbouring layers it computed (the
@@ -725,11 +970,16 @@ int32_t launch_chunked(const LoopLaunch& P, const ColArgs& a, const TileArgs& t,
 
 // ---------------------------------------------------------------------------
 
-size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t cstride, int32_t S)
+size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t cstride, int32_t S)
 {
     if (kernel != EXM_K_MASS) return 0;
     if (element == EXM_ELEMENT_P1P1)
         return sizeof(double) * 5 * (size_t)vstride * (S + 2) + 2 * sizeof(int32_t) * vstride;
+    if (element == EXM_ELEMENT_P2P2) {
+        const size_t es = (size_t)vstride + (size_t)estride;
+        return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 3 * es * (2 * S + 2)) +
+               sizeof(int32_t) * (2 * es + (size_t)vstride);
+    }
     if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1)
         return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + sizeof(int32_t) * vstride;
     return 0;
@@ -737,23 +987,27 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
 
 bool pipe_supported(int32_t kernel, int32_t element)
 {
-    return kernel == EXM_K_MASS &&
-           (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1);
+    return kernel == EXM_K_MASS && (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2 ||
+                                    element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1);
 }
 
 int32_t pipe_max_tile_cells(int32_t element, int32_t S)
 {
     if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1) return 2 * 512 / S;
+    if (element == EXM_ELEMENT_P2P2) return kThreads / (S / kLayers2);
     return kPasses * (kThreads / (S / kLayers));
 }
 
 bool pipe_chunk_ok(int32_t element, int32_t S)
 {
     if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 20 || S == 24 || S == 32;
+    if (element == EXM_ELEMENT_P2P2) return S == 8 || S == 16;
     return S == 8 || S == 16 || S == 32;
 }
 
 int32_t pipe_max_tile_verts(int32_t S) { return kThreads * kItems / S; }
+
+int32_t pipe_max_tile_entities(int32_t S) { return kThreads * kItems2 / (2 * S); }
 
 template <int S>
 static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
@@ -765,6 +1019,16 @@ static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, siz
         hipLaunchKernelGGL((k_pipe_p1<S, kPlain>), grid, block, lds, s, a, t);
     else
         hipLaunchKernelGGL((k_pipe_p1<S, kAtomic>), grid, block, lds, s, a, t);
+}
+
+template <int S>
+static void launch_pipe_p2(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+{
+    const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    if (race == EXM_RACE_COLOUR)
+        hipLaunchKernelGGL((k_pipe_p2<S, kPlain>), grid, block, lds, s, a, t);
+    else
+        hipLaunchKernelGGL((k_pipe_p2<S, kAtomic>), grid, block, lds, s, a, t);
 }
 
 template <int S>
@@ -792,9 +1056,20 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
 {
     if (t.tile_count <= 0) return EXM_OK;
     EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
-              "the PIPELINED schedule runs the mass action on P1xP1, DG0xDG0 and DG1xDG1");
+              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2, DG0xDG0 and DG1xDG1");
     const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.out0;
     EXM_CHECK((al & 15) == 0, EXM_EUNSUPPORTED, "the PIPELINED schedule needs 16-byte aligned field pointers");
+    if (P.element == EXM_ELEMENT_P2P2) {
+        EXM_CHECK(P.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED, "owner-computes is not available on P2xP2");
+        EXM_CHECK(t.edge_off != nullptr, EXM_EINVAL, "P2 needs the mesh's cell_edge map");
+        switch (S) {
+        case 8: launch_pipe_p2<8>(P.race, a, t, lds, s); break;
+        case 16: launch_pipe_p2<16>(P.race, a, t, lds, s); break;
+        default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8 or 16 on P2xP2", S);
+        }
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
     if (P.element != EXM_ELEMENT_P1P1) {
         switch (S) {
         case 8: launch_pipe_dg<8>(P.element, a, t, cstride, lds, s); break;
