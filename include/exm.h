@@ -345,14 +345,17 @@ int32_t exm_autotune_load(const char* path);
 
 /* ------------------------------------------------------------------------
  * Batched assembly: many extruded meshes, several fields per mesh, forward
- * residual (EXM_K_MASS) plus its adjoint, in one persistent launch captured
- * in a HIP graph.
+ * residual (EXM_K_MASS) plus its adjoint, in persistent launches (one over
+ * the P1 x P1 items, one over the DG0 x DG0 items) captured in a HIP graph.
+ * The fields of a mesh share its lists and geometry (end of Section 3.3).
  *
  * Item m: a space (EXM_ELEMENT_P1P1 or EXM_ELEMENT_DG0DG0) and its coordinate
  * field on the same mesh; n_fields inputs f[j] with outputs b[j] = M f[j], and
  * optionally cotangents w[j] with adjoint outputs g[j] = M^T w[j] = M w[j].
  * Pointer arrays are host arrays of device pointers (copied at create).
- * Outputs are overwritten (the launch zeroes continuous-space outputs itself).
+ * Outputs are overwritten: every output DoF is written once (P1 x P1 items
+ * run vertex-column owner-computes, as EXM_SCHED_GATHER; no atomics), so
+ * the result does not depend on the order in which units run.
  * The meshes, spaces and buffers must outlive the batch.
  */
 typedef struct {
@@ -367,12 +370,14 @@ typedef struct {
 } exm_batch_item;
 
 typedef struct exm_batch exm_batch;
-/* opts may be NULL; opts->cols_per_wave applies to every item when set. */
+/* opts may be NULL; opts->cols_per_wave applies to every DG0 x DG0 item when
+ * set, opts->tile_cells sets the work-unit size (base cells of DG0 items,
+ * base vertices of P1 items, scaled by 64 / layers; 0 = timed choice). */
 int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm_loop_opts* opts,
                          void* stream, exm_batch** out);
 /* Replay the captured graph on `stream`. */
 int32_t exm_batch_launch(exm_batch* batch, void* stream);
-/* Work units (cell groups) and persistent workgroups of the batch. */
+/* Work units (cell or vertex groups) and persistent workgroups per kernel of the batch. */
 int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_blocks);
 void exm_batch_destroy(exm_batch* batch);
 

@@ -2,19 +2,23 @@
 // residual b = M f plus its adjoint g = M^T w = M w, in one persistent kernel
 // launch captured in a HIP graph.
 //
-// Work list.  Every mesh is cut into units of about unit_cells consecutive
-// base cells; a fixed grid of workgroups pulls units from a device counter
-// until the list is exhausted, so meshes of very different sizes and layer
-// counts balance across the GPU.  Within a unit the wavefronts walk columns as
-// in the DIRECT schedule (cols_per_wave cells side by side, one layer per
-// lane).  All fields of a mesh live on one space and share its explicit lists
-// (end of Section 3.3 of the paper): the lists and the prism geometry are read
-// once per column step and reused by every field and by the adjoint.
+// Work list.  Every mesh is cut into units of consecutive base entities; a
+// fixed grid of workgroups pulls units from a device counter until the list is
+// exhausted, so meshes of very different sizes and layer counts balance across
+// the GPU.  All fields of a mesh live on one space and share its explicit
+// lists (end of Section 3.3 of the paper), so the geometry read for a column
+// serves several fields.
 //
-// Continuous (P1 x P1) outputs are summed with FP64 atomic adds; a step adds
-// its top level directly (no carry between steps), so a level shared by two
-// steps receives two adds.  DG0 outputs are written.  The graph first resets
-// the work counter and zeroes the continuous outputs with small kernels.
+// DG0 x DG0 units are base cells: the wavefronts walk their columns as in the
+// DIRECT schedule (cols_per_wave cells side by side, one layer per lane) and
+// write every field's output.  P1 x P1 units are base vertices, each owned by
+// one wavefront (the GATHER form of the loop): it walks the fan of cells
+// around its vertex column, 62 levels per step, for four fields at a time,
+// and writes every output DoF of its column once.  So no output needs
+// zeroing and no atomics are needed.  The two kinds of unit run in two
+// persistent kernels with a work list each (the P1 path's registers would
+// otherwise lower the occupancy of the DG0 path); the graph first resets
+// the two work counters with a one-thread kernel.
 #include <algorithm>
 #include <cstring>
 
@@ -32,6 +36,9 @@ struct BatchItemDev {
     int32_t adjoint;
     int32_t pad;
     int64_t xn;
+    int64_t fbase, xbase;     // P1: column start of vertex w is base + w (lambda + 1)
+    const int32_t* fan_off;   // P1: fans of cells around every vertex (see exm_gather.hip)
+    const int32_t* fan;
     const int32_t* fmap;
     const int32_t* xmap;
     const double* X;
@@ -48,58 +55,101 @@ struct Unit {
     int32_t pad;
 };
 
-struct ZeroSeg {
-    double* p;
-    int64_t n;
-};
-
-__global__ void k_batch_reset(int32_t* counter) { *counter = 0; }
-
-__global__ void k_batch_zero(const ZeroSeg* __restrict__ segs)
+__global__ void k_batch_reset(int32_t* counter)
 {
-    const ZeroSeg s = segs[blockIdx.y];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n; i += stride) s.p[i] = 0.0;
+    counter[0] = 0;
+    counter[1] = 0;
 }
 
 __device__ __forceinline__ double next_lane(double v) { return __shfl_down(v, 1, 64); }
 
-// One step of a P1 x P1 column walk for every field of the item.
-__device__ __forceinline__ void batch_p1_step(const BatchItemDev& I, const int fb[3], const int xb[3],
-                                              const double gx[3], const double gy[3], int lsub, int seg, int l,
-                                              bool act, bool last)
+constexpr int kVOwned = 62;   // P1: levels a wavefront writes per step (one halo lane at each end)
+constexpr int kVGroup = 4;    // P1: fields (forward and adjoint counted apart) per walk of the fan
+constexpr int kVBlk = 2;      // P1: fan entries whose loads are issued together
+
+// P1 x P1: the column of base vertex v, every field and its adjoint.  Lane
+// `lane` of a step holds level lev = l0 - 1 + lane; it evaluates the row of v
+// of prism (c, lev) for every cell c of the fan (bottom and top), keeps the
+// bottom row and passes the top row one lane up, where it belongs to level
+// lev + 1.  The fan lists the neighbouring vertices in cyclic order, so each
+// neighbouring column is loaded once for the two cells that share it.
+__device__ void batch_p1_vertex(const BatchItemDev& I, int32_t v, int lane)
 {
-    double zb[3], h[3];
+    const int64_t lamp = (int64_t)I.n_layers + 1;
+    const double* __restrict__ Z = I.X + 2 * I.xn;
+    const int64_t fv = I.fbase + (int64_t)v * lamp, xv = I.xbase + (int64_t)v * lamp;
+    const double px0 = I.X[xv], py0 = I.X[I.xn + xv];
+    const int32_t e0 = I.fan_off[v], e1 = I.fan_off[v + 1];
+    const int nfp = I.adjoint ? 2 * I.n_fields : I.n_fields;   // forward fields, then adjoint ones
+    for (int l0 = 0; l0 <= I.n_layers; l0 += kVOwned) {
+        const int lev = l0 - 1 + lane;
+        const bool in = lev >= 0 && lev <= I.n_layers;   // a level of the column
+        const bool prism = lev >= 0 && lev < I.n_layers;  // the prism above it exists
+        const double z0 = in ? Z[xv + lev] : 0.0;
+        const double z0n = next_lane(z0);
+        for (int k0 = 0; k0 < nfp; k0 += kVGroup) {
+            const double* src[kVGroup];
+            double f0[kVGroup], f0n[kVGroup], fp[kVGroup], fpn[kVGroup], ab[kVGroup], at[kVGroup];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) zb[a] = act ? I.X[2 * I.xn + (int64_t)xb[a] + l] : 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double zt = next_lane(zb[a]);
-        if (act && last) zt = I.X[2 * I.xn + (int64_t)xb[a] + l + 1];
-        h[a] = zt - zb[a];
-    }
-    const double twoA = twice_area(gx, gy);
-    const int lo = l * I.off;
-    const int passes = I.adjoint ? 2 : 1;
-    for (int pass = 0; pass < passes; ++pass) {
-        for (int k = 0; k < I.n_fields; ++k) {
-            const double* src = pass == 0 ? I.f[k] : I.w[k];
-            double* dst = pass == 0 ? I.b[k] : I.g[k];
-            double xbv[3], xtv[3], yb[3] = {0.0, 0.0, 0.0}, yt[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) xbv[a] = act ? src[fb[a] + lo] : 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                xtv[a] = next_lane(xbv[a]);
-                if (act && last) xtv[a] = src[fb[a] + lo + I.off];
+            for (int j = 0; j < kVGroup; ++j) {
+                const int k = k0 + j;   // uniform
+                src[j] = k < I.n_fields ? I.f[k] : (k < nfp ? I.w[k - I.n_fields] : nullptr);
+                f0[j] = k < nfp && in ? src[j][fv + lev] : 0.0;
+                f0n[j] = next_lane(f0[j]);
+                fp[j] = fpn[j] = ab[j] = at[j] = 0.0;
             }
-            if (act) p1_mass(twoA, h, xbv, xtv, yb, yt);
+            double zp = 0.0, zpn = 0.0, pxp = 0.0, pyp = 0.0;   // the previous neighbour
+            for (int32_t eb = e0; eb < e1; eb += kVBlk) {
+                // the loads of kVBlk fan entries are in flight before the first is used
+                int32_t ent[kVBlk];
+                double z1[kVBlk], px1[kVBlk], py1[kVBlk], f1[kVBlk][kVGroup];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double below = __shfl_up(yt[a], 1, 64);
-                if (act) {
-                    unsafeAtomicAdd(dst + fb[a] + lo, yb[a] + (lsub > 0 ? below : 0.0));
-                    if (last) unsafeAtomicAdd(dst + fb[a] + lo + I.off, yt[a]);
+                for (int q = 0; q < kVBlk; ++q) {
+                    const bool has = eb + q < e1;   // uniform
+                    ent[q] = has ? I.fan[eb + q] : 0;
+                    const int64_t w = ent[q] & 0x7fffffff;
+                    const int64_t fw = I.fbase + w * lamp, xw = I.xbase + w * lamp;
+                    z1[q] = has && in ? Z[xw + lev] : 0.0;
+                    px1[q] = has ? I.X[xw] : 0.0;
+                    py1[q] = has ? I.X[I.xn + xw] : 0.0;
+#pragma unroll
+                    for (int j = 0; j < kVGroup; ++j) f1[q][j] = has && k0 + j < nfp && in ? src[j][fw + lev] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < kVBlk; ++q) {
+                    if (eb + q >= e1) break;   // uniform
+                    const double z1n = next_lane(z1[q]);
+                    const bool cell = ent[q] >= 0 && prism;   // cell (v, previous, w)
+                    const double s =
+                        fabs((pxp - px0) * (py1[q] - py0) - (px1[q] - px0) * (pyp - py0)) * (1.0 / 120.0);
+                    const double h[3] = {z0n - z0, zpn - zp, z1n - z1[q]};
+#pragma unroll
+                    for (int j = 0; j < kVGroup; ++j) {
+                        const double f1n = next_lane(f1[q][j]);
+                        if (cell && k0 + j < nfp) {
+                            const double xb[3] = {f0[j], fp[j], f1[q][j]};
+                            const double xt[3] = {f0n[j], fpn[j], f1n};
+                            double yb, yt;
+                            p1_row(s, h, xb, xt, yb, yt);
+                            ab[j] += yb;
+                            at[j] += yt;
+                        }
+                        fp[j] = f1[q][j];
+                        fpn[j] = f1n;
+                    }
+                    zp = z1[q];
+                    zpn = z1n;
+                    pxp = px1[q];
+                    pyp = py1[q];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kVGroup; ++j) {
+                const int k = k0 + j;
+                const double below = __shfl_up(at[j], 1, 64);
+                if (k < nfp && lane >= 1 && lane <= kVOwned && in) {
+                    double* dst = k < I.n_fields ? I.b[k] : I.g[k - I.n_fields];
+                    dst[fv + lev] = ab[j] + below;
                 }
             }
         }
@@ -126,6 +176,9 @@ __device__ __forceinline__ void batch_dg0_step(const BatchItemDev& I, int f0, co
         for (int k = 0; k < I.n_fields; ++k) I.g[k][d] = I.w[k][d] * vol;
 }
 
+// The persistent kernel over the units of one kind: P1 (base vertices) or
+// DG0 (base cells).
+template <bool P1>
 __global__ void __launch_bounds__(256) k_batch(const BatchItemDev* __restrict__ items, const Unit* __restrict__ units,
                                                int32_t n_units, int32_t* counter)
 {
@@ -141,6 +194,10 @@ __global__ void __launch_bounds__(256) k_batch(const BatchItemDev* __restrict__ 
         if (u >= n_units) break;   // every wave of the workgroup leaves together
         const Unit U = units[u];
         const BatchItemDev& I = items[U.item];
+        if constexpr (P1) {   // a range of base vertices, one per wavefront
+            for (int i = wave; i < U.cell_count; i += nwaves) batch_p1_vertex(I, U.cell_begin + i, lane);
+            continue;
+        }
         const int sub = lane / I.seg;
         const int lsub = lane - sub * I.seg;
         for (int grp = wave; grp * I.cpw < U.cell_count; grp += nwaves) {   // uniform over the wavefront
@@ -155,24 +212,12 @@ __global__ void __launch_bounds__(256) k_batch(const BatchItemDev* __restrict__ 
                 gx[a] = valid ? I.X[xb[a]] : 0.0;
                 gy[a] = valid ? I.X[I.xn + xb[a]] : 0.0;
             }
-            if (I.element == EXM_ELEMENT_P1P1) {
-                int fb[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) fb[a] = valid ? I.fmap[(int64_t)cell * 6 + 2 * a] : 0;
-                for (int l0 = 0; l0 < I.n_layers; l0 += I.seg) {
-                    const int l = l0 + lsub;
-                    const bool act = valid && l < I.n_layers;
-                    const bool last = lsub == I.seg - 1 || l == I.n_layers - 1;
-                    batch_p1_step(I, fb, xb, gx, gy, lsub, I.seg, l, act, last);
-                }
-            } else {
-                const int f0 = valid ? I.fmap[cell] : 0;
-                for (int l0 = 0; l0 < I.n_layers; l0 += I.seg) {
-                    const int l = l0 + lsub;
-                    const bool act = valid && l < I.n_layers;
-                    const bool last = lsub == I.seg - 1 || l == I.n_layers - 1;
-                    batch_dg0_step(I, f0, xb, gx, gy, l, act, last);
-                }
+            const int f0 = valid ? I.fmap[cell] : 0;
+            for (int l0 = 0; l0 < I.n_layers; l0 += I.seg) {
+                const int l = l0 + lsub;
+                const bool act = valid && l < I.n_layers;
+                const bool last = lsub == I.seg - 1 || l == I.n_layers - 1;
+                batch_dg0_step(I, f0, xb, gx, gy, l, act, last);
             }
         }
     }
@@ -189,14 +234,14 @@ struct exm_batch {
     hipGraphExec_t exec = nullptr;
     DevBuf<BatchItemDev> items;
     DevBuf<Unit> units;
-    DevBuf<ZeroSeg> zsegs;
     DevBuf<int32_t> counter;
     DevBuf<const double*> ptrs;   // all field pointer arrays, item by item
     int64_t n_units = 0;
-    int32_t n_zero = 0;
+    int64_t n_units_p1 = 0;       // the P1 units come first in `units`
     int32_t n_blocks = 0;
     int32_t unit_cells = 0;
     std::vector<int32_t> cpw;     // per item
+    std::vector<bool> p1;         // per item: P1 x P1 (vertex units), else DG0 x DG0 (cell units)
     ~exm_batch()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -228,35 +273,45 @@ int32_t enqueue(exm_batch* B, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->counter.p);
     EXM_TRY_HIP(hipGetLastError());
-    if (B->n_zero > 0) {
-        hipLaunchKernelGGL(k_batch_zero, dim3(256, (unsigned)B->n_zero), dim3(256), 0, s, B->zsegs.p);
+    const int32_t n1 = (int32_t)B->n_units_p1, n0 = (int32_t)(B->n_units - B->n_units_p1);
+    if (n1 > 0) {
+        hipLaunchKernelGGL(k_batch<true>, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p, B->units.p, n1,
+                           B->counter.p);
         EXM_TRY_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_batch, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p, B->units.p,
-                       (int32_t)B->n_units, B->counter.p);
-    EXM_TRY_HIP(hipGetLastError());
+    if (n0 > 0) {
+        hipLaunchKernelGGL(k_batch<false>, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p,
+                           B->units.p + n1, n0, B->counter.p + 1);
+        EXM_TRY_HIP(hipGetLastError());
+    }
     return EXM_OK;
 }
 
 int32_t build_units(exm_batch* B, const std::vector<int32_t>& n_cells, const std::vector<int32_t>& n_layers,
                     int32_t unit_cells)
 {
-    // units of about unit_cells cells, scaled so that every unit holds a
-    // similar number of prisms (cells x layers)
-    std::vector<Unit> units;
+    // units of about unit_cells entities (cells, or vertices for P1 items),
+    // scaled so that every unit holds a similar number of layers in total
+    // two lists, P1 units then DG0 units, each sorted largest first (that
+    // keeps the tail of its kernel short)
+    std::vector<Unit> lists[2];
     int64_t ref_layers = 64;
     for (size_t m = 0; m < n_cells.size(); ++m) {
         int64_t uc = std::max<int64_t>(1, unit_cells * ref_layers / std::max(1, n_layers[m]));
         uc = std::max<int64_t>(uc, B->cpw[m]);
+        std::vector<Unit>& units = lists[B->p1[m] ? 0 : 1];
         for (int64_t c = 0; c < n_cells[m]; c += uc)
             units.push_back(Unit{(int32_t)m, (int32_t)c, (int32_t)std::min<int64_t>(uc, n_cells[m] - c), 0});
     }
-    // largest units first keeps the tail short
-    std::stable_sort(units.begin(), units.end(), [&](const Unit& a, const Unit& b) {
-        return (int64_t)a.cell_count * n_layers[a.item] > (int64_t)b.cell_count * n_layers[b.item];
-    });
+    for (std::vector<Unit>& units : lists)
+        std::stable_sort(units.begin(), units.end(), [&](const Unit& a, const Unit& b) {
+            return (int64_t)a.cell_count * n_layers[a.item] > (int64_t)b.cell_count * n_layers[b.item];
+        });
+    std::vector<Unit> units = lists[0];
+    units.insert(units.end(), lists[1].begin(), lists[1].end());
     EXM_CHECK(units.size() < (size_t)INT32_MAX, EXM_EOVERFLOW, "too many work units");
     B->n_units = (int64_t)units.size();
+    B->n_units_p1 = (int64_t)lists[0].size();
     B->unit_cells = unit_cells;
     return B->units.upload(units.data(), units.size());
 }
@@ -280,10 +335,10 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
     EXM_TRY_HIP(hipGetDevice(&B->device));
     std::vector<BatchItemDev> dev(n_items);
     std::vector<const double*> ptrs;
-    std::vector<ZeroSeg> zero;
-    std::vector<int32_t> n_cells(n_items), n_layers(n_items);
+    std::vector<int32_t> n_ent(n_items), n_layers(n_items);   // work entities (cells, or vertices for P1) per item
     std::vector<size_t> ptr_base(n_items);
     B->cpw.resize(n_items);
+    B->p1.resize(n_items);
     for (int32_t m = 0; m < n_items; ++m) {
         const exm_batch_item& it = items[m];
         EXM_CHECK(it.space && it.coord_space && it.coords, EXM_EINVAL, "item %d: NULL space, coord_space or coords", m);
@@ -298,7 +353,6 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         EXM_CHECK(it.f && it.b, EXM_EINVAL, "item %d: NULL f or b", m);
         EXM_CHECK((it.w == nullptr) == (it.g == nullptr), EXM_EINVAL, "item %d: w and g must both be given or both NULL",
                   m);
-        const int64_t n = it.space->n_dofs;
         for (int32_t k = 0; k < it.n_fields; ++k) {
             EXM_CHECK(it.f[k] && it.b[k], EXM_EINVAL, "item %d field %d: NULL pointer", m, k);
             EXM_CHECK(it.f[k] != it.b[k], EXM_EINVAL, "item %d field %d: b aliases f", m, k);
@@ -309,7 +363,9 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
             }
         }
         const exm_mesh* mesh = it.space->mesh;
-        n_cells[m] = mesh->n[2];
+        const bool p1 = it.space->element == EXM_ELEMENT_P1P1;
+        B->p1[m] = p1;
+        n_ent[m] = p1 ? mesh->n[0] : mesh->n[2];
         n_layers[m] = mesh->n_layers;
         B->cpw[m] = opts && opts->cols_per_wave ? opts->cols_per_wave : batch_cpw(mesh->n_layers);
         BatchItemDev& d = dev[m];
@@ -322,6 +378,15 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         d.n_fields = it.n_fields;
         d.adjoint = it.w ? 1 : 0;
         d.xn = it.coord_space->n_dofs;
+        if (p1) {
+            const VertexFans* fans = nullptr;
+            int32_t st = build_vertex_fans(mesh, &fans);
+            if (st != EXM_OK) return st;
+            d.fan_off = fans->off.p;
+            d.fan = fans->fan.p;
+            d.fbase = it.space->base[0];
+            d.xbase = it.coord_space->base[0];
+        }
         d.fmap = it.space->d_map.p;
         d.xmap = it.coord_space->d_map.p;
         d.X = it.coords;
@@ -332,13 +397,7 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
             for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.w[k]);
             for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.g[k]);
         }
-        if (d.element == EXM_ELEMENT_P1P1) {
-            for (int32_t k = 0; k < it.n_fields; ++k) zero.push_back(ZeroSeg{it.b[k], n});
-            if (it.w)
-                for (int32_t k = 0; k < it.n_fields; ++k) zero.push_back(ZeroSeg{it.g[k], n});
-        }
     }
-    EXM_CHECK(zero.size() <= 65535, EXM_ERANGE, "too many continuous outputs (%zu)", zero.size());
     int32_t s = B->ptrs.upload(ptrs.data(), ptrs.size());
     if (s != EXM_OK) return s;
     for (int32_t m = 0; m < n_items; ++m) {
@@ -352,15 +411,13 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         }
     }
     if ((s = B->items.upload(dev.data(), dev.size())) != EXM_OK) return s;
-    if ((s = B->zsegs.upload(zero.data(), zero.size())) != EXM_OK) return s;
-    B->n_zero = (int32_t)zero.size();
-    if ((s = B->counter.alloc(1)) != EXM_OK) return s;
+    if ((s = B->counter.alloc(2)) != EXM_OK) return s;
     int cus = 0;
     EXM_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
     B->n_blocks = std::max(1, cus) * 8;
     hipStream_t hs = (hipStream_t)stream;
     if (opts && opts->tile_cells) {
-        if ((s = build_units(B.get(), n_cells, n_layers, opts->tile_cells)) != EXM_OK) return s;
+        if ((s = build_units(B.get(), n_ent, n_layers, opts->tile_cells)) != EXM_OK) return s;
     } else {
         // project autotuner: time the candidate unit sizes on these buffers
         // (the launch overwrites every output, so timing runs are harmless)
@@ -370,7 +427,7 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         float best = 1e30f;
         int32_t best_uc = 64;
         for (int32_t uc : {16, 64, 256}) {
-            if ((s = build_units(B.get(), n_cells, n_layers, uc)) != EXM_OK) break;
+            if ((s = build_units(B.get(), n_ent, n_layers, uc)) != EXM_OK) break;
             if ((s = enqueue(B.get(), hs)) != EXM_OK) break;
             EXM_TRY_HIP(hipEventRecord(e0, hs));
             if ((s = enqueue(B.get(), hs)) != EXM_OK) break;
@@ -386,9 +443,9 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (s != EXM_OK) return s;
-        if ((s = build_units(B.get(), n_cells, n_layers, best_uc)) != EXM_OK) return s;
+        if ((s = build_units(B.get(), n_ent, n_layers, best_uc)) != EXM_OK) return s;
     }
-    // capture reset + zero + persistent kernel into a graph on a private stream
+    // capture the counter reset and the persistent kernel into a graph on a private stream
     EXM_TRY_HIP(hipStreamSynchronize(hs));
     EXM_TRY_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     EXM_TRY_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));

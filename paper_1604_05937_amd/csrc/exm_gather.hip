@@ -52,29 +52,6 @@ struct GatherP1Args {
     const int32_t* __restrict__ fan_cell;  // the cell of every fan entry (-1 at the start of a fan)
 };
 
-// Row of node v (index 0) of the P1 x P1 mass action on one prism (the
-// sum-factorised form of p1_mass restricted to one vertex):
-//   y_v = (2A / 120) ((2 h_v + H) g_v + (h_v + H) G + sum_a h_a g_a),
-// g = V x per vertex at the bottom and at the top.
-__device__ __forceinline__ void p1_row(double s, const double h[3], const double xb[3], const double xt[3],
-                                       double& yb, double& yt)
-{
-    constexpr double sixth = 1.0 / 6.0;
-    const double H = h[0] + h[1] + h[2];
-    double gb[3], gt[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        gb[a] = (2.0 * xb[a] + xt[a]) * sixth;
-        gt[a] = (xb[a] + 2.0 * xt[a]) * sixth;
-    }
-    const double Gb = gb[0] + gb[1] + gb[2], Gt = gt[0] + gt[1] + gt[2];
-    const double HGb = h[0] * gb[0] + h[1] * gb[1] + h[2] * gb[2];
-    const double HGt = h[0] * gt[0] + h[1] * gt[1] + h[2] * gt[2];
-    const double d = 2.0 * h[0] + H, o = h[0] + H;
-    yb = s * (d * gb[0] + o * Gb + HGb);
-    yt = s * (d * gt[0] + o * Gt + HGt);
-}
-
 __global__ void __launch_bounds__(256) k_gather_p1(const GatherP1Args g)
 {
     const int lane = threadIdx.x & 63;

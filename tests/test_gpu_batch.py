@@ -83,3 +83,33 @@ def test_batch_rejects_bad_items():
     items[0]["b"] = [items[0]["f"][0]]   # output aliases input
     with pytest.raises(exm.ExmError):
         exm.Batch(items)
+
+
+def test_batch_short_columns_odd_field_count():
+    # P1 columns shorter than one 62-level step, and 5 fields (a partial group
+    # of the P1 path's four fields per walk of the fan); no adjoint
+    say("batch short columns, 5 fields")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(21)
+    items = []
+    for space, n, lam in (("P1", 9, 7), ("DG0", 8, 5), ("P1", 6, 61), ("P1", 5, 1)):
+        base = meshgen.tri_square(n)
+        mesh = exm.Mesh(base, lam)
+        Vx = exm.Space(mesh, "P1")
+        V = exm.Space(mesh, space) if space != "P1" else Vx
+        X = exm.coordinate_field(Vx, meshgen.extruded_vertex_coords(base, lam))
+        rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        items.append(dict(space=V, coord_space=Vx, coords=X, mesh=mesh,
+                          f=[rnd() for _ in range(5)], b=[V.zeros() for _ in range(5)]))
+    B = exm.Batch(items)
+    ref = [[_single(d, f) for f in d["f"]] for d in items]
+    for d in items:
+        for t in d["b"]:
+            t.fill_(-7.0)
+    torch.cuda.synchronize()
+    B.launch()
+    torch.cuda.synchronize()
+    for d, rb in zip(items, ref):
+        for got, want in zip(d["b"], rb):
+            g_, w_ = got.cpu().numpy(), want.cpu().numpy()
+            assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what="short columns")
