@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 TUNED_TABLE = os.path.join(ROOT, "paper_1604_05937_amd", "tuned_mi355x.txt")
 
 
@@ -379,7 +380,7 @@ def add_roofline(tree, stream_gbs):
     HBM peak and of the measured STREAM triad (these kernels are HBM-bound)."""
     if isinstance(tree, dict):
         out = {k: add_roofline(v, stream_gbs) for k, v in tree.items()}
-        for key in ("gbs", "spmv_gbs", "assemble_gbs", "batched_gbs"):
+        for key in ("gbs", "spmv_gbs", "assemble_gbs", "batched_gbs", "forward_gbs", "fused_gbs"):
             if isinstance(tree.get(key), (int, float)):
                 out[key.replace("gbs", "frac_hbm")] = round(tree[key] / HBM_PEAK_GBS, 4)
                 out[key.replace("gbs", "frac_stream")] = round(tree[key] / stream_gbs, 4)
@@ -495,10 +496,16 @@ def secondary(torch, exm, W, meshgen):
     c_fu = exm.autotune(exm.EXM_K_CUBIC_FUSED, e4.mesh, e4.X, V, fu)
     t_fw, _ = timed(torch, lambda: W.run_cubic(e4, u, f, F), 10)
     t_fu, _ = timed(torch, lambda: W.run_fused(e4, u, f, w, F, gu, gf), 10)
+    fl_fw, fl_fu = W.cubic_flops(e4, False), W.cubic_flops(e4, True)
     out["cubic_256x256x50"] = {"forward_ms": round(t_fw, 4), "fused_fwd_adj_ms": round(t_fu, 4),
                                "fused_over_forward": round(t_fu / t_fw, 3), "launch_forward": c_fw,
                                "launch_fused": c_fu,
-                               "forward_gflops_est": None}
+                               "forward_tflops": round(fl_fw / t_fw / 1e9, 2),
+                               "forward_frac_fp64_peak": round(fl_fw / t_fw / 1e9 / FP64_PEAK_TFLOPS, 4),
+                               "fused_tflops": round(fl_fu / t_fu / 1e9, 2),
+                               "fused_frac_fp64_peak": round(fl_fu / t_fu / 1e9 / FP64_PEAK_TFLOPS, 4),
+                               "forward_gbs": round(W.cubic_bytes(e4, False)["algorithmic"] / t_fw / 1e6, 1),
+                               "fused_gbs": round(W.cubic_bytes(e4, True)["algorithmic"] / t_fu / 1e6, 1)}
     log(f"cubic forward {t_fw:.3f} ms, fused {t_fu:.3f} ms")
     del e4, u, f, w, F, gu, gf
     torch.cuda.empty_cache()

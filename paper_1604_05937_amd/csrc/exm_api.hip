@@ -307,9 +307,9 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         const bool owner = d.race == EXM_RACE_OWNER;
         int32_t s = owner ? build_owner_plan(mesh, d.tile_cells, &plan) : build_tile_plan(mesh, d.tile_cells, &plan);
         if (s != EXM_OK) return s;
-        EXM_CHECK(plan->max_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+        EXM_CHECK(plan->max_cells <= pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers), EXM_EUNSUPPORTED,
                   "CHUNKED: tiles of about %d cells reach %d cells, more than %d with %d-layer chunks", d.tile_cells,
-                  plan->max_cells, pipe_max_tile_cells(P.element, d.chunk_layers), d.chunk_layers);
+                  plan->max_cells, pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers), d.chunk_layers);
         EXM_CHECK(chunk_lds_bytes(plan->max_verts, d.chunk_layers) <= kLdsLimit, EXM_EUNSUPPORTED,
                   "CHUNKED: tiles of %d cells with %d-layer chunks do not fit in LDS", d.tile_cells, d.chunk_layers);
         ch = d;
@@ -323,27 +323,29 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.waves_per_block = 4;
         d.cols_per_wave = 0;
         const bool p2 = P.element == EXM_ELEMENT_P2P2;
-        if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 && !p2 ? 16 : 8;
-        EXM_CHECK(pipe_chunk_ok(P.element, d.chunk_layers), EXM_ERANGE,
+        const bool one_layer = p2 || P.kernel != EXM_K_MASS;   // one layer of one cell per thread
+        if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 && !one_layer ? 16 : 8;
+        EXM_CHECK(pipe_chunk_ok(P.kernel, P.element, d.chunk_layers), EXM_ERANGE,
                   "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1, 8 or 16 on P2xP2 and 8, 16 "
                   "or 32 on DG spaces",
                   d.chunk_layers);
-        if (!d.tile_cells) d.tile_cells = std::min(p2 ? 32 : 64, pipe_max_tile_cells(P.element, d.chunk_layers));
-        EXM_CHECK(d.tile_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+        if (!d.tile_cells)
+            d.tile_cells = std::min(one_layer ? 32 : 64, pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers));
+        EXM_CHECK(d.tile_cells <= pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers), EXM_EUNSUPPORTED,
                   "PIPELINED: tiles of %d cells with %d-layer chunks exceed %d cells", d.tile_cells, d.chunk_layers,
-                  pipe_max_tile_cells(P.element, d.chunk_layers));
+                  pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers));
         const TilePlan* plan = nullptr;
         const bool owner = d.race == EXM_RACE_OWNER;
         int32_t s = owner ? build_owner_plan(mesh, d.tile_cells, &plan) : build_tile_plan(mesh, d.tile_cells, &plan);
         if (s != EXM_OK) return s;
-        EXM_CHECK(plan->max_cells <= pipe_max_tile_cells(P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+        EXM_CHECK(plan->max_cells <= pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers), EXM_EUNSUPPORTED,
                   "PIPELINED: owner tiles of about %d cells reach %d cells with their neighbours, more than %d "
-                  "with %d-layer chunks", d.tile_cells, plan->max_cells, pipe_max_tile_cells(P.element, d.chunk_layers),
+                  "with %d-layer chunks", d.tile_cells, plan->max_cells, pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers),
                   d.chunk_layers);
         if (P.element == EXM_ELEMENT_P1P1)
-            EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(d.chunk_layers), EXM_EUNSUPPORTED,
+            EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(P.kernel, d.chunk_layers), EXM_EUNSUPPORTED,
                       "PIPELINED: tiles of %d cells touch up to %d vertices, more than %d with %d-layer chunks",
-                      d.tile_cells, plan->max_verts, pipe_max_tile_verts(d.chunk_layers), d.chunk_layers);
+                      d.tile_cells, plan->max_verts, pipe_max_tile_verts(P.kernel, d.chunk_layers), d.chunk_layers);
         if (p2) {
             EXM_CHECK(plan->has_edges, EXM_EINVAL, "P2 needs the mesh's cell_edge map");
             EXM_CHECK(plan->max_verts + plan->max_edges <= pipe_max_tile_entities(d.chunk_layers), EXM_EUNSUPPORTED,
@@ -665,10 +667,10 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
         if (pipe_supported(P.kernel, P.element))
             for (int32_t tc : {16, 24, 32, 48, 64, 96, 128, 256})
                 for (int32_t S : {8, 12, 16, 20, 24, 32})
-                    if (pipe_chunk_ok(P.element, S) && tc <= pipe_max_tile_cells(P.element, S) &&
-                        (tc >= 32 || P.element == EXM_ELEMENT_P2P2)) {
+                    if (pipe_chunk_ok(P.kernel, P.element, S) && tc <= pipe_max_tile_cells(P.kernel, P.element, S) &&
+                        (tc >= 32 || P.element == EXM_ELEMENT_P2P2 || P.kernel != EXM_K_MASS)) {
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
-                        if (r == 0 && P.element == EXM_ELEMENT_P1P1)
+                        if (r == 0 && P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1)
                             cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
                         if (P.element == EXM_ELEMENT_P1P1 && (S & (S - 1)) == 0) {
                             cand.push_back(exm_loop_opts{races[r], EXM_SCHED_CHUNKED, 0, 4, tc, S});

@@ -765,6 +765,213 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p2(const ColArgs a, const Til
     }
 }
 
+// Cubic forms of P1 x P1 (FORM 1: F = integral (u^3 - f) v; 2: its adjoint
+// g_u, g_f; 3: both in one sweep; inputs and outputs as in cubic_element),
+// all INC.  The tile walk of k_pipe_p1 with NIN input columns and NOUT
+// accumulators per tile vertex: z and every input land in LDS one chunk
+// ahead, one thread takes one layer of one cell and adds the bottom and top
+// rows of every output to LDS, and chunk k - 1 is written back while chunk k
+// computes.  LDS: Z[2], X[2][NIN], A[NOUT] of vstride * (S + 2) doubles, then
+// tag and column start per tile vertex (ints); (x, y) per vertex only during
+// set-up, inside A.  Old output values of a chunk are loaded into registers
+// right after the previous chunk is written back (item indices come from the
+// LDS tables, not from registers).  Tiles of up to 256 / S cells: larger
+// tiles in 512-thread workgroups measured slower.
+constexpr int kItemsC = 4;   // output items per thread: vertices * S <= 256 * kItemsC
+
+template <int FORM>
+struct CubicIO {
+    static constexpr int NIN = FORM == 3 ? 3 : 2;
+    static constexpr int NOUT = FORM == 1 ? 1 : (FORM == 2 ? 2 : 3);
+};
+
+template <int FORM, int S, int MODE>
+__global__ void __launch_bounds__(kThreads) k_pipe_cubic(const ColArgs a, const TileArgs t)
+{
+    static_assert(MODE != kOwner, "owner-computes is for the mass action");
+    constexpr int NIN = CubicIO<FORM>::NIN, NOUT = CubicIO<FORM>::NOUT;
+    constexpr bool ATOMIC = MODE == kAtomic;
+    constexpr int P2 = S + 2, PP = P2 / 2;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int VS = t.vstride * P2;
+    double* const Zs = lds;                        // [2][VS]
+    double* const Xs = lds + 2 * VS;               // [2][NIN][VS]
+    double* const A = lds + (2 + 2 * NIN) * VS;    // [NOUT][VS]
+    double* const Tx = A;                          // set-up only
+    double* const Ty = A + t.vstride;
+    int32_t* const Ttag = (int32_t*)(lds + (2 + 2 * NIN + NOUT) * VS);
+    int32_t* const Txst = Ttag + t.vstride;
+    const int64_t n = a.xn;
+    const double* const z = a.X + 2 * n;
+    const double* const in[3] = {a.in0, a.in1, a.in2};
+    double* const out[3] = {a.out0, a.out1, a.out2};
+    const int lam = a.n_layers;
+
+    for (int v = tid; v < nv; v += kThreads) {
+        const int32_t tag = t.verts[vb0 + v];
+        const int32_t xs = t.xstart[vid(tag)];
+        Ttag[v] = tag;
+        Txst[v] = xs;
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+    }
+    lds_barrier();
+
+    // this thread's cell and its layer r of every chunk
+    const int r = tid % S;
+    const int c = tid / S;
+    const bool has = c < nc;
+    int vb[3];
+    double twoA;
+    {
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = has ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            vb[q] = lv * P2 + (Txst[lv] & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA = has ? twice_area(xq, yq) : 0.0;
+    }
+    lds_barrier();   // (x, y) are no longer needed: the accumulators take their place
+    for (int i = tid; i < NOUT * VS; i += kThreads) A[i] = 0.0;
+    const int wave_e = tid & ~63;
+
+    auto issue_copies = [&](int k) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        const int b = k & 1;
+        for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int v = e / PP, w = e - (e / PP) * PP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int sv = xs & 1;
+            if (2 * w - sv > nl) continue;
+            const int64_t g = (int64_t)xs - sv + l0 + 2 * w;
+            if (g + 1 < n) {
+                copy16(z + g, Zs + b * VS + 2 * (e0 + wave_e));
+#pragma unroll
+                for (int i = 0; i < NIN; ++i) copy16(in[i] + g, Xs + (b * NIN + i) * VS + 2 * (e0 + wave_e));
+            } else {   // the array's last element: keep the read inside the array
+                Zs[b * VS + 2 * e] = z[g];
+#pragma unroll
+                for (int i = 0; i < NIN; ++i) Xs[(b * NIN + i) * VS + 2 * e] = in[i][g];
+            }
+        }
+    };
+    // item i of this thread: (vertex, level of the chunk) (tid + 256 i) / S,
+    // (tid + 256 i) % S; kind 0 none, 1 read-add-write, 2 atomic
+    auto item_kind = [&](int i) {
+        const int v = (tid + kThreads * i) / S;
+        return v >= nv ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
+    };
+    auto load_old = [&](int k, double (&dst)[NOUT][kItemsC]) {
+        const int nl = min(S, lam - k * S);
+#pragma unroll
+        for (int i = 0; i < kItemsC; ++i) {
+            const int it = tid + kThreads * i;
+            const int v = it / S, jj = it % S;
+            const bool ld = item_kind(i) == 1 && jj < nl;
+            const int64_t g = ld ? (int64_t)Txst[v] + k * S + jj : 0;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) dst[o][i] = ld ? out[o][g] : 0.0;
+        }
+    };
+    auto write_back = [&](int k, const double (&old)[NOUT][kItemsC], bool carry) {
+        const int nl = min(S, lam - k * S);
+#pragma unroll
+        for (int i = 0; i < kItemsC; ++i) {
+            const int it = tid + kThreads * i;
+            const int v = it / S, jj = it % S;
+            const int kind = item_kind(i);
+            if (kind == 0 || jj >= nl) continue;
+            const int32_t xs = Txst[v];
+            const int pos = v * P2 + (xs & 1) + jj;
+            const int64_t g = (int64_t)xs + k * S + jj;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) {
+                double* const Ao = A + o * VS;
+                const double s = Ao[pos];
+                if (kind == 2)
+                    unsafeAtomicAdd(out[o] + g, s);
+                else
+                    out[o][g] = old[o][i] + s;
+                if (carry && jj == 0) {
+                    Ao[pos] = Ao[pos + S];
+                    Ao[pos + S] = 0.0;
+                } else {
+                    Ao[pos] = 0.0;
+                }
+            }
+        }
+    };
+
+    double yO[NOUT][kItemsC];   // old output values of the chunk written back next
+    const int nch = (lam + S - 1) / S;
+    issue_copies(0);
+    load_old(0, yO);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int nl = min(S, lam - k * S);
+        wait_copies();
+        lds_barrier();
+        if (k > 0) {
+            write_back(k - 1, yO, true);
+            load_old(k, yO);
+        }
+        lds_barrier();
+        if (k + 1 < nch) issue_copies(k + 1);
+        if (!has || r >= nl) continue;
+        const double* const Zb = Zs + b * VS;
+        double h[3], vbot[NIN][3], vtop[NIN][3], yb[NOUT][3], yt[NOUT][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) h[q] = Zb[vb[q] + r + 1] - Zb[vb[q] + r];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            const double* const Xb = Xs + (b * NIN + i) * VS;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                vbot[i][q] = Xb[vb[q] + r];
+                vtop[i][q] = Xb[vb[q] + r + 1];
+            }
+        }
+        cubic_element<FORM>(twoA, h, vbot, vtop, yb, yt);
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                lds_add(A + o * VS + vb[q] + r, yb[o][q]);
+                lds_add(A + o * VS + vb[q] + r + 1, yt[o][q]);
+            }
+    }
+    // write back the last chunk, its top level included
+    lds_barrier();
+    {
+        const int k = nch - 1;
+        const int nl = lam - k * S;
+        write_back(k, yO, false);
+        for (int v = tid; v < nv; v += kThreads) {
+            const int32_t xs = Txst[v];
+            const int64_t g = (int64_t)xs + lam;
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) {
+                const double s = A[o * VS + v * P2 + (xs & 1) + nl];
+                if (ATOMIC && vshared(Ttag[v]))
+                    unsafeAtomicAdd(out[o] + g, s);
+                else
+                    out[o][g] += s;
+            }
+        }
+    }
+}
+
 // CHUNKED schedule, P1 x P1 mass action / RHS (INC): one workgroup per
 // (tile, chunk).  Chunk c computes the layers c (S - 1) .. c (S - 1) + S - 1
 // and writes the levels whose two neighbouring layers it computed (the
@@ -970,8 +1177,19 @@ int32_t launch_chunked(const LoopLaunch& P, const ColArgs& a, const TileArgs& t,
 
 // ---------------------------------------------------------------------------
 
+static bool cubic_kernel(int32_t kernel)
+{
+    return kernel == EXM_K_CUBIC || kernel == EXM_K_CUBIC_VJP || kernel == EXM_K_CUBIC_FUSED;
+}
+
 size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t cstride, int32_t S)
 {
+    if (cubic_kernel(kernel) && element == EXM_ELEMENT_P1P1) {
+        const int nin = kernel == EXM_K_CUBIC_FUSED ? 3 : 2;
+        const int nout = kernel == EXM_K_CUBIC ? 1 : (kernel == EXM_K_CUBIC_VJP ? 2 : 3);
+        return sizeof(double) * (size_t)(2 + 2 * nin + nout) * (size_t)vstride * (S + 2) +
+               2 * sizeof(int32_t) * vstride;
+    }
     if (kernel != EXM_K_MASS) return 0;
     if (element == EXM_ELEMENT_P1P1)
         return sizeof(double) * 5 * (size_t)vstride * (S + 2) + 2 * sizeof(int32_t) * vstride;
@@ -987,25 +1205,31 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
 
 bool pipe_supported(int32_t kernel, int32_t element)
 {
+    if (cubic_kernel(kernel)) return element == EXM_ELEMENT_P1P1;
     return kernel == EXM_K_MASS && (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2 ||
                                     element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1);
 }
 
-int32_t pipe_max_tile_cells(int32_t element, int32_t S)
+int32_t pipe_max_tile_cells(int32_t kernel, int32_t element, int32_t S)
 {
+    if (cubic_kernel(kernel)) return kThreads / S;   // one layer of one cell per thread
     if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1) return 2 * 512 / S;
     if (element == EXM_ELEMENT_P2P2) return kThreads / (S / kLayers2);
     return kPasses * (kThreads / (S / kLayers));
 }
 
-bool pipe_chunk_ok(int32_t element, int32_t S)
+bool pipe_chunk_ok(int32_t kernel, int32_t element, int32_t S)
 {
+    if (cubic_kernel(kernel)) return S == 8 || S == 16;
     if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 20 || S == 24 || S == 32;
     if (element == EXM_ELEMENT_P2P2) return S == 8 || S == 16;
     return S == 8 || S == 16 || S == 32;
 }
 
-int32_t pipe_max_tile_verts(int32_t S) { return kThreads * kItems / S; }
+int32_t pipe_max_tile_verts(int32_t kernel, int32_t S)
+{
+    return kThreads * (cubic_kernel(kernel) ? kItemsC : kItems) / S;
+}
 
 int32_t pipe_max_tile_entities(int32_t S) { return kThreads * kItems2 / (2 * S); }
 
@@ -1019,6 +1243,28 @@ static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, siz
         hipLaunchKernelGGL((k_pipe_p1<S, kPlain>), grid, block, lds, s, a, t);
     else
         hipLaunchKernelGGL((k_pipe_p1<S, kAtomic>), grid, block, lds, s, a, t);
+}
+
+template <int FORM, int S>
+static void launch_pipe_cubic_f(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+{
+    const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    if (race == EXM_RACE_COLOUR)
+        hipLaunchKernelGGL((k_pipe_cubic<FORM, S, kPlain>), grid, block, lds, s, a, t);
+    else
+        hipLaunchKernelGGL((k_pipe_cubic<FORM, S, kAtomic>), grid, block, lds, s, a, t);
+}
+
+template <int S>
+static void launch_pipe_cubic(int32_t kernel, int32_t race, const ColArgs& a, const TileArgs& t, size_t lds,
+                              hipStream_t s)
+{
+    if (kernel == EXM_K_CUBIC)
+        launch_pipe_cubic_f<1, S>(race, a, t, lds, s);
+    else if (kernel == EXM_K_CUBIC_VJP)
+        launch_pipe_cubic_f<2, S>(race, a, t, lds, s);
+    else
+        launch_pipe_cubic_f<3, S>(race, a, t, lds, s);
 }
 
 template <int S>
@@ -1056,9 +1302,20 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
 {
     if (t.tile_count <= 0) return EXM_OK;
     EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
-              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2, DG0xDG0 and DG1xDG1");
-    const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.out0;
+              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2, DG0xDG0 and DG1xDG1 and the cubic forms "
+              "on P1xP1");
+    const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.in1 | (uintptr_t)a.in2 | (uintptr_t)a.out0;
     EXM_CHECK((al & 15) == 0, EXM_EUNSUPPORTED, "the PIPELINED schedule needs 16-byte aligned field pointers");
+    if (cubic_kernel(P.kernel)) {
+        EXM_CHECK(P.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED, "owner-computes is for the mass action");
+        switch (S) {
+        case 8: launch_pipe_cubic<8>(P.kernel, P.race, a, t, lds, s); break;
+        case 16: launch_pipe_cubic<16>(P.kernel, P.race, a, t, lds, s); break;
+        default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8 or 16 on the cubic forms", S);
+        }
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
     if (P.element == EXM_ELEMENT_P2P2) {
         EXM_CHECK(P.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED, "owner-computes is not available on P2xP2");
         EXM_CHECK(t.edge_off != nullptr, EXM_EINVAL, "P2 needs the mesh's cell_edge map");

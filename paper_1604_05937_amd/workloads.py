@@ -116,6 +116,21 @@ def cubic_bytes(e: Extruded, fused: bool) -> dict:
     return dict(algorithmic=alg, valuable=valuable, n_dofs=n)
 
 
+# Algorithmic FP64 operations per prism of the cubic forms, as the quadrature
+# is written (an add, a subtract or a multiply counts one): the layer heights
+# (3), then per triangle point (7) the interpolation of each input at the
+# point's column (11 per input: bottom value and rise) and the weight (6), per
+# Gauss point (3) the point value, u^2 and the weighted integrand (forward 13,
+# with the adjoint 22), and the sums into the test functions (12 per output
+# pair); the fused form adds -M w (74).  Forward: 3 + 7 (6 + 22 + 39 + 12) =
+# 556; fused: 3 + 7 (6 + 33 + 66 + 24) + 74 = 980.
+CUBIC_FLOPS_PER_PRISM = {"forward": 556, "fused": 980}
+
+
+def cubic_flops(e: Extruded, fused: bool) -> int:
+    return CUBIC_FLOPS_PER_PRISM["fused" if fused else "forward"] * e.base.n_cells * e.n_layers
+
+
 def mass_args(e: Extruded, name: str, x, y):
     acc = EXM_INC if name in CONTINUOUS else EXM_WRITE
     V = e.space(name)

@@ -14,7 +14,10 @@ OPTS = [dict(schedule=exm.EXM_SCHED_DIRECT, race=exm.EXM_RACE_ATOMIC),
         dict(schedule=exm.EXM_SCHED_TILED, race=exm.EXM_RACE_ATOMIC),
         dict(schedule=exm.EXM_SCHED_TILED, race=exm.EXM_RACE_COLOUR, tile_cells=24, cols_per_wave=3),
         dict(schedule=exm.EXM_SCHED_STAGED, race=exm.EXM_RACE_ATOMIC, tile_cells=40, chunk_layers=16),
-        dict(schedule=exm.EXM_SCHED_STAGED, race=exm.EXM_RACE_COLOUR, tile_cells=16, chunk_layers=8)]
+        dict(schedule=exm.EXM_SCHED_STAGED, race=exm.EXM_RACE_COLOUR, tile_cells=16, chunk_layers=8),
+        dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC),
+        dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_COLOUR, tile_cells=16, chunk_layers=16),
+        dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=8, chunk_layers=8)]
 
 
 def _run(c, kernel, ins, nout, **opts):
@@ -47,3 +50,38 @@ def test_cubic_forward_vjp_fused(opts, n, lam, terrain):
     assert_close(F2, F_ref, F_scale, what="fused F")
     assert_close(gu2, gu_ref, gu_scale, what="fused g_u")
     assert_close(gf2, gf_ref, gf_scale, what="fused g_f")
+
+
+@pytest.mark.parametrize("race", [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR])
+@pytest.mark.parametrize("chunk", [8, 16])
+def test_cubic_pipelined_inc_into_nonzero(race, chunk):
+    # INC: the pipelined write-back adds the old output values it loaded one
+    # chunk ahead; outputs start from random values here
+    say(f"cubic pipelined INC race={race} chunk={chunk}")
+    base = meshgen.tri_square(9, order="random")
+    c = Case(base, 2 * chunk + 5, "P1", terrain=0.2)
+    u = meshgen.uniform_values(c.n, seed=41)
+    f = meshgen.uniform_values(c.n, seed=42)
+    w = meshgen.uniform_values(c.n, seed=43)
+    y0 = [meshgen.uniform_values(c.n, seed=50 + i) for i in range(3)]
+    outs = [c.dev(y) for y in y0]
+    fields = [(c.dev(x), c.V, exm.EXM_READ) for x in (u, f, w)] + [(o, c.V, exm.EXM_INC) for o in outs]
+    exm.par_loop(exm.EXM_K_CUBIC_FUSED, c.mesh, c.X, c.Vx, fields, schedule=exm.EXM_SCHED_PIPELINED, race=race,
+                 chunk_layers=chunk, tile_cells=256 // chunk)
+    F_ref, gu_ref, gf_ref = c.ref.cubic(u, f), *c.ref.cubic_vjp(u, w)
+    F_scale, (gu_scale, gf_scale) = c.ref.cubic_abs(u, f), c.ref.vjp_abs(u, w)
+    for got, ref, scale, y, what in ((outs[0], F_ref, F_scale, y0[0], "F"), (outs[1], gu_ref, gu_scale, y0[1], "g_u"),
+                                     (outs[2], gf_ref, gf_scale, y0[2], "g_f")):
+        assert_close(c.host(got), ref + y, scale + np.abs(y), what=f"pipelined INC {what}")
+
+
+def test_cubic_pipelined_refuses_owner_and_bad_chunks():
+    c = Case(meshgen.tri_square(5), 9, "P1", with_oracle=False)
+    x = c.dev(meshgen.uniform_values(c.n, seed=1))
+    fields = [(x, c.V, exm.EXM_READ), (x, c.V, exm.EXM_READ), (c.V.zeros(), c.V, exm.EXM_INC)]
+    with pytest.raises(exm.ExmError) as e:
+        exm.par_loop(exm.EXM_K_CUBIC, c.mesh, c.X, c.Vx, fields, race=exm.EXM_RACE_OWNER)
+    assert e.value.status == exm._abi.EXM_EUNSUPPORTED
+    with pytest.raises(exm.ExmError) as e:
+        exm.par_loop(exm.EXM_K_CUBIC, c.mesh, c.X, c.Vx, fields, schedule=exm.EXM_SCHED_PIPELINED, chunk_layers=32)
+    assert e.value.status == exm._abi.EXM_ERANGE
