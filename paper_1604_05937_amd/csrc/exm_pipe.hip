@@ -148,6 +148,17 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     double* const y = a.out0;
     const int lam = a.n_layers;
 
+    // this thread's cells (tile-local vertices), loaded before the tile's
+    // vertex table so that the two loads overlap
+    bool has[kPasses];
+    int lvq[kPasses][3];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        const int c = tid / G + p * CPP;
+        has[p] = tid < CPP * G && c < nc;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+    }
     // tile vertex table: tag, column start, (x, y) of the column
     for (int v = tid; v < nv; v += kThreads) {
         const int32_t tag = t.verts[vb0 + v];
@@ -165,17 +176,14 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     const int r0 = (tid % G) * R;
     int vb[kPasses][3];
     double twoA[kPasses];
-    bool has[kPasses];
     int wmask[kPasses];   // bit q: vertex q of the cell is written by this tile
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
-        const int c = tid / G + p * CPP;
-        has[p] = tid < CPP * G && c < nc;
         double xq[3], yq[3];
         wmask[p] = 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int lv = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            const int lv = lvq[p][q];
             vb[p][q] = lv * P2 + (Txst[lv] & 1);
             xq[q] = Tx[lv];
             yq[q] = Ty[lv];
@@ -374,6 +382,19 @@ __global__ void __launch_bounds__(NT, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs
     double* const out = a.out0;
     const int lam = a.n_layers;
 
+    // this thread's cells (tile-local vertices, field column), loaded before
+    // the tile's vertex table so that the loads overlap
+    bool has[NP];
+    int lvq[NP][3];
+    int32_t d0[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int c = (tid >> LS) + p * CPP;
+        has[p] = c < nc;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+        d0[p] = has[p] ? a.fmap[(int64_t)t.cells[cb + c] * NDOF] : 0;
+    }
     for (int v = tid; v < nv; v += NT) {
         const int32_t xs = t.xstart[vid(t.verts[vb0 + v])];
         Txst[v] = xs;
@@ -384,23 +405,18 @@ __global__ void __launch_bounds__(NT, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs
 
     const int j = tid & (S - 1);
     int vb[NP][3];
-    int32_t d0[NP];
     double twoA[NP];
-    bool has[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const int c = (tid >> LS) + p * CPP;
-        has[p] = c < nc;
         double xq[3], yq[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int lv = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            const int lv = lvq[p][q];
             vb[p][q] = lv * P2 + (Txst[lv] & 1);
             xq[q] = Tx[lv];
             yq[q] = Ty[lv];
         }
         twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
-        d0[p] = has[p] ? a.fmap[(int64_t)t.cells[cb + c] * NDOF] : 0;
     }
     const int npass = (nc + CPP - 1) / CPP;
     const int wave_e = tid & ~63;
@@ -571,6 +587,15 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p2(const ColArgs a, const Til
     double* const y = a.out0;
     const int lam = a.n_layers;
 
+    // this thread's cell (tile-local vertices and edges), loaded before the
+    // entity table so that the loads overlap
+    const bool has = tid / G < nc;
+    int lvq[3], leq[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        lvq[q] = has ? (int)t.lcv[(int64_t)(cb + tid / G) * 3 + q] : 0;
+        leq[q] = has ? nv + (int)t.lce[(int64_t)(cb + tid / G) * 3 + q] : 0;
+    }
     // entity table: tag, field column start; per vertex the coordinate column
     // start and (x, y) of the column
     for (int e = tid; e < nent; e += kThreads) {
@@ -593,14 +618,12 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p2(const ColArgs a, const Til
     const int r0 = (tid % G) * R;
     int zb[3], xb[6];
     double twoA;
-    const bool has = tid / G < nc;
     {
-        const int c = tid / G;
         double xq[3], yq[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int lv = has ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
-            const int le = has ? nv + (int)t.lce[(int64_t)(cb + c) * 3 + q] : 0;
+            const int lv = lvq[q];
+            const int le = leq[q];
             zb[q] = lv * PZ + (Txst[lv] & 1);
             xb[q] = lv * PX + (Tfst[lv] & 1);
             xb[3 + q] = le * PX + (Tfst[le] & 1);
@@ -786,7 +809,7 @@ struct CubicIO {
 };
 
 template <int FORM, int S, int MODE>
-__global__ void __launch_bounds__(kThreads) k_pipe_cubic(const ColArgs a, const TileArgs t)
+__global__ void __launch_bounds__(kThreads, 3) k_pipe_cubic(const ColArgs a, const TileArgs t)
 {
     static_assert(MODE != kOwner, "owner-computes is for the mass action");
     constexpr int NIN = CubicIO<FORM>::NIN, NOUT = CubicIO<FORM>::NOUT;
@@ -812,6 +835,14 @@ __global__ void __launch_bounds__(kThreads) k_pipe_cubic(const ColArgs a, const 
     double* const out[3] = {a.out0, a.out1, a.out2};
     const int lam = a.n_layers;
 
+    // this thread's cell and its layer r of every chunk; the cell's tile-local
+    // vertices are loaded before the vertex table so that the loads overlap
+    const int r = tid % S;
+    const int c = tid / S;
+    const bool has = c < nc;
+    int lvq[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) lvq[q] = has ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
     for (int v = tid; v < nv; v += kThreads) {
         const int32_t tag = t.verts[vb0 + v];
         const int32_t xs = t.xstart[vid(tag)];
@@ -822,17 +853,13 @@ __global__ void __launch_bounds__(kThreads) k_pipe_cubic(const ColArgs a, const 
     }
     lds_barrier();
 
-    // this thread's cell and its layer r of every chunk
-    const int r = tid % S;
-    const int c = tid / S;
-    const bool has = c < nc;
     int vb[3];
     double twoA;
     {
         double xq[3], yq[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int lv = has ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+            const int lv = lvq[q];
             vb[q] = lv * P2 + (Txst[lv] & 1);
             xq[q] = Tx[lv];
             yq[q] = Ty[lv];
