@@ -457,6 +457,17 @@ static void fill_tile_args(const TilePlan* plan, const LoopLaunch& P, TileArgs& 
     t.fstart0 = P.fspace->d_starts[0].p;
     t.fstart1 = P.fspace->d_starts[1].p;
     t.owned = plan->owner ? plan->owned.p : nullptr;
+    // closed-form column starts where Algorithm 1 gives one: one layer count
+    // and one DoF count per entity type
+    const bool uniform = !P.fspace->mesh->variable;
+    const bool xok = uniform && !P.xspace->mixed && P.xspace->col_size[0] > 0;
+    const bool fok = uniform && !P.fspace->mixed;
+    t.xbase = P.xspace->base[0];
+    t.xstep = xok ? P.xspace->col_size[0] : 0;
+    t.fbase0 = P.fspace->base[0];
+    t.fstep0 = fok && P.fspace->col_size[0] > 0 ? P.fspace->col_size[0] : 0;
+    t.fbase1 = P.fspace->base[1];
+    t.fstep1 = fok && P.fspace->col_size[1] > 0 ? P.fspace->col_size[1] : 0;
 }
 
 static int32_t run_tiled(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)

@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     // tile vertex table: tag, column start, (x, y) of the column
     for (int v = tid; v < nv; v += kThreads) {
         const int32_t tag = t.verts[vb0 + v];
-        const int32_t xs = t.xstart[vid(tag)];
+        const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(tag));
         Ttag[v] = tag;
         Txst[v] = xs;
         Tx[v] = a.X[xs];
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(NT, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs
         d0[p] = has[p] ? a.fmap[(int64_t)t.cells[cb + c] * NDOF] : 0;
     }
     for (int v = tid; v < nv; v += NT) {
-        const int32_t xs = t.xstart[vid(t.verts[vb0 + v])];
+        const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(t.verts[vb0 + v]));
         Txst[v] = xs;
         Tx[v] = a.X[xs];
         Ty[v] = a.X[n + xs];
@@ -602,9 +602,10 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p2(const ColArgs a, const Til
         const bool vert = e < nv;
         const int32_t tag = vert ? t.verts[vb0 + e] : t.edges[eb0 + e - nv];
         Ttag[e] = tag;
-        Tfst[e] = vert ? t.fstart0[vid(tag)] : t.fstart1[vid(tag)];
+        Tfst[e] = vert ? column_start(t.fstart0, t.fbase0, t.fstep0, vid(tag))
+                       : column_start(t.fstart1, t.fbase1, t.fstep1, vid(tag));
         if (vert) {
-            const int32_t xs = t.xstart[vid(tag)];
+            const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(tag));
             Txst[e] = xs;
             Tx[e] = a.X[xs];
             Ty[e] = a.X[n + xs];
@@ -845,7 +846,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_pipe_cubic(const ColArgs a, con
     for (int q = 0; q < 3; ++q) lvq[q] = has ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
     for (int v = tid; v < nv; v += kThreads) {
         const int32_t tag = t.verts[vb0 + v];
-        const int32_t xs = t.xstart[vid(tag)];
+        const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(tag));
         Ttag[v] = tag;
         Txst[v] = xs;
         Tx[v] = a.X[xs];
@@ -1048,7 +1049,7 @@ __global__ void __launch_bounds__(kThreads) k_chunk_p1(const ColArgs a, const Ti
 
     for (int v = tid; v < nv; v += kThreads) {
         const int32_t tag = t.verts[vb0 + v];
-        const int32_t xs = t.xstart[vid(tag)];
+        const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(tag));
         Ttag[v] = tag;
         Txst[v] = xs;
         Tx[v] = a.X[xs];

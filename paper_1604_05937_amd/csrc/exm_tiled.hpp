@@ -46,7 +46,19 @@ struct TileArgs {
     const int32_t* __restrict__ fstart0;   // field column start of every base vertex
     const int32_t* __restrict__ fstart1;   // field column start of every base edge
     const int32_t* __restrict__ owned;     // owner plan: vertices each tile owns (else null)
+    // Uniform meshes: the column starts in the closed form of Algorithm 1,
+    // base + id * step, so that a kernel need not read the tables above
+    // (step 0: read them).  Coordinate vertex columns, field vertex and edge columns.
+    int64_t xbase, fbase0, fbase1;
+    int32_t xstep, fstep0, fstep1;
 };
+
+// Column start of entity `id` from its table or, on uniform meshes, in closed form.
+__device__ __forceinline__ int32_t column_start(const int32_t* __restrict__ table, int64_t base, int32_t step,
+                                                int32_t id)
+{
+    return step > 0 ? (int32_t)(base + (int64_t)id * step) : table[id];
+}
 
 ColArgs col_args(const LoopLaunch& P);
 int32_t tiled_max_threads(int32_t kernel, int32_t element);
