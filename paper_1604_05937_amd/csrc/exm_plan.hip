@@ -1,7 +1,7 @@
 // Tile plans for the LDS-staged column loop (host code).
 //
 // A tile is a compact group of base cells grown by breadth-first search over
-// the cells sharing an edge, seeded at the lowest-numbered unassigned cell, so
+// the cells sharing a vertex, seeded at the lowest-numbered unassigned cell, so
 // it follows the locality of the base ordering.  For every tile the plan lists
 // the base vertices (and, if asked, edges) its cells touch; each is flagged
 // when another tile touches it too.  Tiles are also greedily coloured so that
@@ -72,14 +72,16 @@ int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out)
         while (!q.empty() && cnt < target) {
             const int32_t c = q.front();
             q.pop_front();
-            // edge neighbours: cells holding two vertices of c
+            // vertex neighbours: cells sharing a vertex with c.  Growing over
+            // edge neighbours only leaves pockets between earlier tiles that
+            // later tiles cannot fill: on triangulated squares that gives
+            // tiles of about 40 cells for a target of 64, with more vertices
+            // per cell; over vertex neighbours the tiles fill.
             for (int a = 0; a < 3 && cnt < target; ++a) {
-                const int32_t p = cv[c * 3 + (a + 1) % 3], r = cv[c * 3 + (a + 2) % 3];
+                const int32_t p = cv[c * 3 + a];
                 for (int64_t j = vc.start[p]; j < vc.start[p + 1] && cnt < target; ++j) {
                     const int32_t o = vc.items[j];
                     if (tile_of[o] >= 0) continue;
-                    const int32_t* w = cv + (int64_t)o * 3;
-                    if (w[0] != r && w[1] != r && w[2] != r) continue;
                     tile_of[o] = nt;
                     order.push_back(o);
                     q.push_back(o);
