@@ -260,7 +260,10 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.tile_cells = d.chunk_layers = 0;
     }
     const bool gather = d.schedule == EXM_SCHED_GATHER && gather_supported(P.kernel, P.element);
-    if ((direct_only(P.element) || P.kernel == EXM_K_FACET_JUMP) && !gather) {   // the generic DIRECT kernels
+    // the generic DIRECT kernels (tensor spaces the PIPELINED schedule also runs may ask for it)
+    const bool pipe_ok = (d.schedule == EXM_SCHED_PIPELINED || d.schedule == EXM_SCHED_CHUNKED) &&
+                         pipe_supported(P.kernel, P.element);   // CHUNKED runs PIPELINED off P1
+    if ((direct_only(P.element) || P.kernel == EXM_K_FACET_JUMP) && !gather && !pipe_ok) {
         EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED,
                   "owner-computes is not available for kernel %d on element %d", P.kernel, P.element);
         if (d.schedule != EXM_SCHED_DIRECT) d.cols_per_wave = d.waves_per_block = 0;

@@ -350,7 +350,10 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     }
 }
 
-// DG0 x DG0 (NDOF = 1) and DG1 x DG1 (NDOF = 6) mass action / RHS.  Only z
+// Mass action / RHS on the spaces discontinuous horizontally and vertically:
+// NH horizontal by NV vertical nodes per layer (DG0 x DG0 1 x 1, DG1 x DG1
+// 3 x 2, DG0 x DG1 1 x 2, DG1 x DG0 3 x 1; node (a, b) at NV a + b of the
+// layer, NDOF = NH NV values).  Only z
 // is shared between the cells of a tile, so only z goes through LDS (S + 1
 // levels per tile vertex and chunk, copied one chunk ahead).  A cell's DoFs
 // form one contiguous column of NDOF * lambda values that no other cell
@@ -359,9 +362,10 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
 // and stores its results while the next chunk computes.  LDS: Z[2] of
 // vstride * (S + 2) doubles, then x, y (doubles) and the column start (int)
 // per tile vertex.
-template <int NDOF, int S, int NP, int NT>
-__global__ void __launch_bounds__(NT, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
+template <int NH, int NV, int S, int NP, int NT>
+__global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
 {
+    constexpr int NDOF = NH * NV;
     using C = Chunk<S>;
     constexpr int P2 = C::P2, PP = C::PP, LS = C::LS;
     constexpr int CPP = NT >> LS;   // one layer per thread
@@ -511,6 +515,13 @@ __global__ void __launch_bounds__(NT, NDOF == 1 ? 8 : 4) k_pipe_dg(const ColArgs
             for (int q = 0; q < 3; ++q) h[q] = Zb[vb[p][q] + j + 1] - Zb[vb[p][q] + j];
             if constexpr (NDOF == 1) {
                 res[p][0] = dg0_mass(twoA[p], h, fcur[p][0]);
+            } else if constexpr (NH != 3 || NV != 2) {   // DG0 x DG1, DG1 x DG0: node (a, b) at NV a + b
+                double x[NH][NV], y[NH][NV];
+#pragma unroll
+                for (int q = 0; q < NDOF; ++q) x[q / NV][q % NV] = fcur[p][q];
+                tp_mass<NH, NV>(twoA[p], h, x, y);
+#pragma unroll
+                for (int q = 0; q < NDOF; ++q) res[p][q] = y[q / NV][q % NV];
             } else {
                 double xb[3], xt[3], yb[3], yt[3];
 #pragma unroll
@@ -1210,6 +1221,14 @@ static bool cubic_kernel(int32_t kernel)
     return kernel == EXM_K_CUBIC || kernel == EXM_K_CUBIC_VJP || kernel == EXM_K_CUBIC_FUSED;
 }
 
+// Spaces discontinuous horizontally and vertically: a cell's DoFs of a layer
+// belong to that (cell, layer) alone, so only z goes through LDS.
+static bool dg_element(int32_t element)
+{
+    return element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1 || element == EXM_ELEMENT_DG0DG1 ||
+           element == EXM_ELEMENT_DG1DG0;
+}
+
 size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t cstride, int32_t S)
 {
     if (cubic_kernel(kernel) && element == EXM_ELEMENT_P1P1) {
@@ -1226,7 +1245,7 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
         return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 3 * es * (2 * S + 2)) +
                sizeof(int32_t) * (2 * es + (size_t)vstride);
     }
-    if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1)
+    if (dg_element(element))
         return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + sizeof(int32_t) * vstride;
     return 0;
 }
@@ -1234,14 +1253,14 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
 bool pipe_supported(int32_t kernel, int32_t element)
 {
     if (cubic_kernel(kernel)) return element == EXM_ELEMENT_P1P1;
-    return kernel == EXM_K_MASS && (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2 ||
-                                    element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1);
+    return kernel == EXM_K_MASS &&
+           (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2 || dg_element(element));
 }
 
 int32_t pipe_max_tile_cells(int32_t kernel, int32_t element, int32_t S)
 {
     if (cubic_kernel(kernel)) return kThreads / S;   // one layer of one cell per thread
-    if (element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1) return 2 * 512 / S;
+    if (dg_element(element)) return 2 * 512 / S;
     if (element == EXM_ELEMENT_P2P2) return kThreads / (S / kLayers2);
     return kPasses * (kThreads / (S / kLayers));
 }
@@ -1305,23 +1324,26 @@ static void launch_pipe_p2(int32_t race, const ColArgs& a, const TileArgs& t, si
         hipLaunchKernelGGL((k_pipe_p2<S, kAtomic>), grid, block, lds, s, a, t);
 }
 
+template <int NH, int NV, int S>
+static void launch_pipe_dg_e(const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds, hipStream_t s)
+{
+    const dim3 grid((unsigned)t.tile_count);
+    // tiles beyond two cells per thread of a 256-thread workgroup take 512 threads
+    if (cstride > 2 * kThreads / S)
+        hipLaunchKernelGGL((k_pipe_dg<NH, NV, S, 2, 512>), grid, dim3(512), lds, s, a, t);
+    else
+        hipLaunchKernelGGL((k_pipe_dg<NH, NV, S, 2, 256>), grid, dim3(kThreads), lds, s, a, t);
+}
+
 template <int S>
 static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds,
                            hipStream_t s)
 {
-    const dim3 grid((unsigned)t.tile_count), block(kThreads);
-    // tiles beyond two cells per thread of a 256-thread workgroup take 512 threads
-    const bool wide = cstride > 2 * kThreads / S;
-    if (element == EXM_ELEMENT_DG0DG0) {
-        if (wide)
-            hipLaunchKernelGGL((k_pipe_dg<1, S, 2, 512>), grid, dim3(512), lds, s, a, t);
-        else
-            hipLaunchKernelGGL((k_pipe_dg<1, S, 2, 256>), grid, block, lds, s, a, t);
-    } else {
-        if (wide)
-            hipLaunchKernelGGL((k_pipe_dg<6, S, 2, 512>), grid, dim3(512), lds, s, a, t);
-        else
-            hipLaunchKernelGGL((k_pipe_dg<6, S, 2, 256>), grid, block, lds, s, a, t);
+    switch (element) {
+    case EXM_ELEMENT_DG0DG0: launch_pipe_dg_e<1, 1, S>(a, t, cstride, lds, s); break;
+    case EXM_ELEMENT_DG0DG1: launch_pipe_dg_e<1, 2, S>(a, t, cstride, lds, s); break;
+    case EXM_ELEMENT_DG1DG0: launch_pipe_dg_e<3, 1, S>(a, t, cstride, lds, s); break;
+    default: launch_pipe_dg_e<3, 2, S>(a, t, cstride, lds, s); break;   // DG1 x DG1
     }
 }
 
@@ -1330,8 +1352,8 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
 {
     if (t.tile_count <= 0) return EXM_OK;
     EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
-              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2, DG0xDG0 and DG1xDG1 and the cubic forms "
-              "on P1xP1");
+              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2, DG0xDG0, DG1xDG1, DG0xDG1 and DG1xDG0 "
+              "and the cubic forms on P1xP1");
     const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.in1 | (uintptr_t)a.in2 | (uintptr_t)a.out0;
     EXM_CHECK((al & 15) == 0, EXM_EUNSUPPORTED, "the PIPELINED schedule needs 16-byte aligned field pointers");
     if (cubic_kernel(P.kernel)) {
