@@ -547,6 +547,196 @@ __global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColA
     store_results();
 }
 
+// Mass action / RHS on the spaces discontinuous horizontally and continuous
+// vertically (DG0 x CG1: NH = 1, DG1 x CG1: NH = 3 values per level): a
+// cell's column holds NH values on each of its lambda + 1 levels, level l at
+// column start + NH l, and no other cell touches it.  As k_pipe_dg (z
+// through LDS, the cell's own column through registers, one layer per
+// thread), and, as in the DIRECT schedule, the layers of a cell sit on
+// consecutive lanes: a lane takes the top values of its layer from the lane
+// above (or loads them at the chunk's last layer), and adds the top row of
+// the layer below (the lane below, or the carry from the previous chunk) to
+// its bottom row, so every level is written once (INC, no atomics).
+template <int NH, int S, int NP, int NT>
+__global__ void __launch_bounds__(NT) k_pipe_dgv(const ColArgs a, const TileArgs t)
+{
+    using C = Chunk<S>;
+    constexpr int P2 = C::P2, PP = C::PP, LS = C::LS;
+    constexpr int CPP = NT >> LS;   // one layer per thread
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int VS = t.vstride * P2;
+    double* const Zs = lds;
+    double* const Tx = Zs + 2 * VS;
+    double* const Ty = Tx + t.vstride;
+    int32_t* const Txst = (int32_t*)(Ty + t.vstride);
+    const int64_t n = a.xn;
+    const double* const z = a.X + 2 * n;
+    const double* const f = a.in0;
+    double* const out = a.out0;
+    const int lam = a.n_layers;
+
+    // this thread's cells (tile-local vertices, field column), loaded before
+    // the tile's vertex table so that the loads overlap
+    bool has[NP];
+    int lvq[NP][3];
+    int32_t d0[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int c = (tid >> LS) + p * CPP;
+        has[p] = c < nc;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+        d0[p] = has[p] ? a.fmap[(int64_t)t.cells[cb + c] * (2 * NH)] : 0;
+    }
+    for (int v = tid; v < nv; v += NT) {
+        const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(t.verts[vb0 + v]));
+        Txst[v] = xs;
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+    }
+    lds_barrier();
+
+    const int j = tid & (S - 1);
+    const int top_lane = (lane & ~(S - 1)) + S - 1;   // the lane of this cell's last layer in the chunk
+    int vb[NP][3];
+    double twoA[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = lvq[p][q];
+            vb[p][q] = lv * P2 + (Txst[lv] & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
+    }
+    const int npass = (nc + CPP - 1) / CPP;
+    const int wave_e = tid & ~63;
+
+    auto issue_copies = [&](int k) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        const int b = k & 1;
+        for (int e0 = 0; e0 < nv * PP; e0 += NT) {
+            const int e = e0 + tid;
+            const int v = e / PP, w = e - (e / PP) * PP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int sv = xs & 1;
+            if (2 * w - sv > nl) continue;
+            const int64_t g = (int64_t)xs - sv + l0 + 2 * w;
+            if (g + 1 < n)
+                copy16(z + g, Zs + b * VS + 2 * (e0 + wave_e));
+            else
+                Zs[b * VS + 2 * e] = z[g];
+        }
+    };
+    // the values of level l0 + j and, at the chunk's (or column's) last
+    // layer, of level l0 + j + 1
+    auto load_field = [&](int k, double (&fv)[NP][NH], double (&ft)[NP][NH]) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass) break;
+            const bool act = has[p] && j < nl;
+            const bool edge = act && j == nl - 1;
+            const double* src = f + (int64_t)d0[p] + (int64_t)(l0 + j) * NH;
+#pragma unroll
+            for (int q = 0; q < NH; ++q) {
+                fv[p][q] = act ? src[q] : 0.0;
+                ft[p][q] = edge ? src[NH + q] : 0.0;
+            }
+        }
+    };
+
+    double fcur[NP][NH], tcur[NP][NH], fnext[NP][NH], tnext[NP][NH], res[NP][NH], carry[NP][NH];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < NH; ++q) carry[p][q] = 0.0;
+    int prev_l0 = -1, prev_nl = 0;
+    auto store_results = [&]() {
+        if (prev_l0 < 0) return;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass) break;
+            if (!has[p] || j >= prev_nl) continue;
+            double* dst = out + (int64_t)d0[p] + (int64_t)(prev_l0 + j) * NH;
+#pragma unroll
+            for (int q = 0; q < NH; ++q) dst[q] += res[p][q];
+        }
+    };
+
+    const int nch = (lam + S - 1) / S;
+    issue_copies(0);
+    load_field(0, fcur, tcur);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        wait_copies();
+        lds_barrier();
+        if (k + 1 < nch) {
+            issue_copies(k + 1);
+            load_field(k + 1, fnext, tnext);
+        }
+        store_results();
+        const double* const Zb = Zs + b * VS;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass) break;   // uniform: every lane takes part in the shuffles below
+            const bool act = has[p] && j < nl;
+            double h[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) h[q] = act ? Zb[vb[p][q] + j + 1] - Zb[vb[p][q] + j] : 0.0;
+            double x[NH][2], y[NH][2];
+#pragma unroll
+            for (int q = 0; q < NH; ++q) {
+                const double above = __shfl_down(fcur[p][q], 1, 64);   // level l0 + j + 1 from the lane above
+                x[q][0] = fcur[p][q];
+                x[q][1] = j == nl - 1 ? tcur[p][q] : above;
+            }
+            if (act) {
+                tp_mass<NH, 2>(twoA[p], h, x, y);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NH; ++q) y[q][0] = y[q][1] = 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < NH; ++q) {
+                const double below = __shfl_up(y[q][1], 1, 64);   // top row of the layer below
+                res[p][q] = y[q][0] + (j == 0 ? carry[p][q] : below);
+                carry[p][q] = __shfl(y[q][1], top_lane, 64);      // into level 0 of the next chunk
+            }
+            // the column's top level: the top row of its last layer
+            if (act && l0 + j == lam - 1) {
+                double* dst = out + (int64_t)d0[p] + (int64_t)lam * NH;
+#pragma unroll
+                for (int q = 0; q < NH; ++q) dst[q] += y[q][1];
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int q = 0; q < NH; ++q) {
+                fcur[p][q] = fnext[p][q];
+                tcur[p][q] = tnext[p][q];
+            }
+        prev_l0 = l0;
+        prev_nl = nl;
+    }
+    store_results();
+}
+
 // P2 x P2 mass action, y += M x (INC).  The tile walk of k_pipe_p1 with the
 // P2 columns: every base vertex and edge of the tile owns a field column of
 // 2 lambda + 1 nodes (level l at 2 l, the middle of layer l at 2 l + 1), and
@@ -1221,12 +1411,13 @@ static bool cubic_kernel(int32_t kernel)
     return kernel == EXM_K_CUBIC || kernel == EXM_K_CUBIC_VJP || kernel == EXM_K_CUBIC_FUSED;
 }
 
-// Spaces discontinuous horizontally and vertically: a cell's DoFs of a layer
-// belong to that (cell, layer) alone, so only z goes through LDS.
+// Spaces discontinuous horizontally: a cell's column belongs to that cell
+// alone, so only z goes through LDS (the first four are discontinuous
+// vertically too, the last two continuous).
 static bool dg_element(int32_t element)
 {
     return element == EXM_ELEMENT_DG0DG0 || element == EXM_ELEMENT_DG1DG1 || element == EXM_ELEMENT_DG0DG1 ||
-           element == EXM_ELEMENT_DG1DG0;
+           element == EXM_ELEMENT_DG1DG0 || element == EXM_ELEMENT_DG0P1 || element == EXM_ELEMENT_DG1P1;
 }
 
 size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t cstride, int32_t S)
@@ -1335,11 +1526,23 @@ static void launch_pipe_dg_e(const ColArgs& a, const TileArgs& t, int32_t cstrid
         hipLaunchKernelGGL((k_pipe_dg<NH, NV, S, 2, 256>), grid, dim3(kThreads), lds, s, a, t);
 }
 
+template <int NH, int S>
+static void launch_pipe_dgv_e(const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds, hipStream_t s)
+{
+    const dim3 grid((unsigned)t.tile_count);
+    if (cstride > 2 * kThreads / S)
+        hipLaunchKernelGGL((k_pipe_dgv<NH, S, 2, 512>), grid, dim3(512), lds, s, a, t);
+    else
+        hipLaunchKernelGGL((k_pipe_dgv<NH, S, 2, 256>), grid, dim3(kThreads), lds, s, a, t);
+}
+
 template <int S>
 static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds,
                            hipStream_t s)
 {
     switch (element) {
+    case EXM_ELEMENT_DG0P1: launch_pipe_dgv_e<1, S>(a, t, cstride, lds, s); break;
+    case EXM_ELEMENT_DG1P1: launch_pipe_dgv_e<3, S>(a, t, cstride, lds, s); break;
     case EXM_ELEMENT_DG0DG0: launch_pipe_dg_e<1, 1, S>(a, t, cstride, lds, s); break;
     case EXM_ELEMENT_DG0DG1: launch_pipe_dg_e<1, 2, S>(a, t, cstride, lds, s); break;
     case EXM_ELEMENT_DG1DG0: launch_pipe_dg_e<3, 1, S>(a, t, cstride, lds, s); break;
@@ -1352,8 +1555,8 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
 {
     if (t.tile_count <= 0) return EXM_OK;
     EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
-              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2, DG0xDG0, DG1xDG1, DG0xDG1 and DG1xDG0 "
-              "and the cubic forms on P1xP1");
+              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2 and the spaces discontinuous "
+              "horizontally, and the cubic forms on P1xP1");
     const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.in1 | (uintptr_t)a.in2 | (uintptr_t)a.out0;
     EXM_CHECK((al & 15) == 0, EXM_EUNSUPPORTED, "the PIPELINED schedule needs 16-byte aligned field pointers");
     if (cubic_kernel(P.kernel)) {

@@ -108,7 +108,7 @@ def test_mass_staged_shapes(space, tile, chunk, race):
 
 
 @pytest.mark.parametrize("schedule", [exm.EXM_SCHED_PIPELINED, exm.EXM_SCHED_CHUNKED])
-@pytest.mark.parametrize("space", ["P1", "P2", "DG0", "DG1", "DG0xDG1", "DG1xDG0"])
+@pytest.mark.parametrize("space", ["P1", "P2", "DG0", "DG1", "DG0xDG1", "DG1xDG0", "DG0xCG1", "DG1xCG1"])
 @pytest.mark.parametrize("tile", [8, 29, 64, 128])
 @pytest.mark.parametrize("chunk", [8, 12, 16, 20, 24, 32])
 @pytest.mark.parametrize("race", RACES + [exm.EXM_RACE_OWNER])
@@ -131,7 +131,7 @@ def test_mass_pipelined_shapes(schedule, space, tile, chunk, race):
                 (chunk in (12, 20, 24) and (space != "P1" or schedule != 4)) or (chunk == 32 and space == "P2"))
             assert big or odd, str(e)
             return
-        if space in ("P1", "P2"):
+        if c.out_access() == exm.EXM_INC:
             # INC into a non-zero output: the old values pass through the staged copy
             want, scale = c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0)
         else:   # WRITE overwrites
@@ -139,7 +139,7 @@ def test_mass_pipelined_shapes(schedule, space, tile, chunk, race):
         assert_close(c.host(y), want, scale, what=f"pipelined mass {space} tile={tile} S={chunk} lam={lam}")
 
 
-@pytest.mark.parametrize("space", ["DG0", "DG1", "DG0xDG1", "DG1xDG0"])
+@pytest.mark.parametrize("space", ["DG0", "DG1", "DG0xDG1", "DG1xDG0", "DG0xCG1", "DG1xCG1"])
 def test_pipelined_dg_inc(space):
     base = meshgen.tri_square(7)
     c = Case(base, 19, space)
