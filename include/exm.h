@@ -271,7 +271,8 @@ typedef struct {
                               /* gathering straight from HBM; the unit of colouring is the   */
                               /* base cell                                                  */
 #define EXM_SCHED_TILED 2     /* one workgroup takes a compact tile of about tile_cells base  */
-                              /* cells (grown breadth-first from the base ordering); its      */
+                              /* cells (grown breadth-first over cells sharing a vertex,      */
+                              /* seeded in the base ordering); its                            */
                               /* wavefronts walk the tile's cells like DIRECT but sum every   */
                               /* update in LDS, and the workgroup adds each (vertex or edge,  */
                               /* level) sum to the output once; the unit of colouring is the  */
@@ -281,12 +282,14 @@ typedef struct {
                               /* once per chunk of chunk_layers layers, loading the next      */
                               /* chunk while it computes the current one; the element kernels */
                               /* read LDS only.  P1xP1, DG0DG0 and DG1DG1 (P2P2 runs TILED)   */
-#define EXM_SCHED_PIPELINED 4 /* like STAGED, but the column segments (coordinates, inputs   */
-                              /* and the INC output) reach LDS through asynchronous           */
-                              /* global-to-LDS copies issued one chunk ahead, so a chunk's    */
-                              /* loads, the previous chunk's stores and the current chunk's   */
-                              /* element kernels overlap.  P1xP1 mass action; other kernels   */
-                              /* fall back to STAGED.  Field pointers must be 16-byte aligned */
+#define EXM_SCHED_PIPELINED 4 /* like STAGED, but the column segments (coordinates, inputs)   */
+                              /* reach LDS through asynchronous global-to-LDS copies issued   */
+                              /* one chunk ahead, so a chunk's loads, the previous chunk's    */
+                              /* stores and the current chunk's element kernels overlap.      */
+                              /* Mass action of P1xP1, P2xP2 and the six spaces               */
+                              /* discontinuous horizontally (there only z goes through LDS),  */
+                              /* and the cubic forms on P1xP1; other kernels fall back to     */
+                              /* STAGED.  Field pointers must be 16-byte aligned.             */
 #define EXM_SCHED_CHUNKED 5   /* P1xP1 mass action: one workgroup per (tile, chunk of        */
                               /* chunk_layers layers); consecutive chunks overlap by one     */
                               /* layer so that each writes whole levels, the workgroups are  */
