@@ -326,11 +326,12 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         d.waves_per_block = 4;
         d.cols_per_wave = 0;
         const bool p2 = P.element == EXM_ELEMENT_P2P2;
-        const bool one_layer = p2 || P.kernel != EXM_K_MASS;   // one layer of one cell per thread
+        const bool one_layer = p2 || P.kernel != EXM_K_MASS || P.element == EXM_ELEMENT_P1DG0 ||
+                               P.element == EXM_ELEMENT_P1DG1;   // one layer of one cell per thread
         if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 && !one_layer ? 16 : 8;
         EXM_CHECK(pipe_chunk_ok(P.kernel, P.element, d.chunk_layers), EXM_ERANGE,
-                  "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1, 8 or 16 on P2xP2 and 8, 16 "
-                  "or 32 on DG spaces",
+                  "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1, 8 or 16 on P2xP2, CG1xDG* "
+                  "and the cubic forms, and 8, 16 or 32 on the spaces discontinuous horizontally",
                   d.chunk_layers);
         if (!d.tile_cells)
             d.tile_cells = std::min(one_layer ? 32 : 64, pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers));
@@ -345,10 +346,11 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
                   "PIPELINED: owner tiles of about %d cells reach %d cells with their neighbours, more than %d "
                   "with %d-layer chunks", d.tile_cells, plan->max_cells, pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers),
                   d.chunk_layers);
-        if (P.element == EXM_ELEMENT_P1P1)
-            EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(P.kernel, d.chunk_layers), EXM_EUNSUPPORTED,
+        if (P.element == EXM_ELEMENT_P1P1 || P.element == EXM_ELEMENT_P1DG0 || P.element == EXM_ELEMENT_P1DG1)
+            EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(P.kernel, P.element, d.chunk_layers), EXM_EUNSUPPORTED,
                       "PIPELINED: tiles of %d cells touch up to %d vertices, more than %d with %d-layer chunks",
-                      d.tile_cells, plan->max_verts, pipe_max_tile_verts(P.kernel, d.chunk_layers), d.chunk_layers);
+                      d.tile_cells, plan->max_verts, pipe_max_tile_verts(P.kernel, P.element, d.chunk_layers),
+                      d.chunk_layers);
         if (p2) {
             EXM_CHECK(plan->has_edges, EXM_EINVAL, "P2 needs the mesh's cell_edge map");
             EXM_CHECK(plan->max_verts + plan->max_edges <= pipe_max_tile_entities(d.chunk_layers), EXM_EUNSUPPORTED,

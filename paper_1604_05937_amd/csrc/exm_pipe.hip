@@ -737,6 +737,189 @@ __global__ void __launch_bounds__(NT) k_pipe_dgv(const ColArgs a, const TileArgs
     store_results();
 }
 
+// Mass action / RHS (INC) on the spaces continuous horizontally and
+// discontinuous vertically (CG1 x DG0: NV = 1, CG1 x DG1: NV = 2 values per
+// layer of a vertex column, layer l at column start + NV l).  The tile walk
+// of k_pipe_p1 without the vertical carry: per chunk of S layers the NV S
+// values of every tile vertex land in LDS beside z, one thread takes one
+// layer of one cell and adds its element rows to the LDS accumulator, and
+// chunk k - 1 is written back while chunk k computes (shared vertices
+// atomically).  LDS: Z[2] of vstride * (S + 2) doubles, X[2] and A of
+// vstride * (NV S + 2) doubles, then tag, coordinate and field column start
+// per tile vertex (ints); (x, y) only during set-up, inside A.
+constexpr int kItemsD = 8;   // output items per thread: vertices * NV * S <= 256 * kItemsD
+
+template <int NV, int S, int MODE>
+__global__ void __launch_bounds__(kThreads) k_pipe_cgdg(const ColArgs a, const TileArgs t)
+{
+    static_assert(MODE != kOwner, "owner-computes is for the P1 x P1 mass action");
+    constexpr bool ATOMIC = MODE == kAtomic;
+    constexpr int PZ = S + 2, PZP = PZ / 2;          // z slot
+    constexpr int W = NV * S;                        // field values of a vertex per chunk
+    constexpr int PX = W + 2, PXP = PX / 2;          // field / accumulator slot (parity shift, even)
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int VZ = t.vstride * PZ;
+    const int VX = t.vstride * PX;
+    double* const Zs = lds;                          // [2][VZ]
+    double* const Xs = lds + 2 * VZ;                 // [2][VX]
+    double* const A = Xs + 2 * VX;                   // [VX]
+    double* const Tx = A;                            // set-up only
+    double* const Ty = A + t.vstride;
+    int32_t* const Ttag = (int32_t*)(A + VX);
+    int32_t* const Txst = Ttag + t.vstride;
+    int32_t* const Tfst = Txst + t.vstride;
+    const int64_t n = a.xn, fn = a.fn;
+    const double* const z = a.X + 2 * n;
+    const double* const x = a.in0;
+    double* const y = a.out0;
+    const int lam = a.n_layers;
+
+    // this thread's cell (tile-local vertices) and its layer r of every
+    // chunk, loaded before the vertex table so that the loads overlap
+    const int r = tid % S;
+    const int c = tid / S;
+    const bool has = c < nc;
+    int lvq[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) lvq[q] = has ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+    for (int v = tid; v < nv; v += kThreads) {
+        const int32_t tag = t.verts[vb0 + v];
+        const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(tag));
+        Ttag[v] = tag;
+        Txst[v] = xs;
+        Tfst[v] = column_start(t.fstart0, t.fbase0, t.fstep0, vid(tag));
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+    }
+    lds_barrier();
+
+    int zb[3], xb[3];
+    double twoA;
+    {
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = lvq[q];
+            zb[q] = lv * PZ + (Txst[lv] & 1);
+            xb[q] = lv * PX + (Tfst[lv] & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA = has ? twice_area(xq, yq) : 0.0;
+    }
+    lds_barrier();   // (x, y) are no longer needed: the accumulator takes their place
+    for (int i = tid; i < VX; i += kThreads) A[i] = 0.0;
+    const int wave_e = tid & ~63;
+
+    // copies of chunk k: z levels l0 .. l0 + nl and field values
+    // NV l0 .. NV (l0 + nl) - 1 of every tile vertex, in 16-byte pairs from the
+    // even global index at or below the first
+    auto issue_copies = [&](int k) {
+        const int l0 = k * S;
+        const int nl = min(S, lam - l0);
+        const int b = k & 1;
+        for (int e0 = 0; e0 < nv * PZP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int v = e / PZP, w = e - (e / PZP) * PZP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int sv = xs & 1;
+            if (2 * w - sv > nl) continue;
+            const int64_t g = (int64_t)xs - sv + l0 + 2 * w;
+            if (g + 1 < n)
+                copy16(z + g, Zs + b * VZ + 2 * (e0 + wave_e));
+            else   // the array's last element: keep the read inside the array
+                Zs[b * VZ + 2 * e] = z[g];
+        }
+        for (int e0 = 0; e0 < nv * PXP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int v = e / PXP, w = e - (e / PXP) * PXP;
+            if (v >= nv) continue;
+            const int32_t fs = Tfst[v];
+            const int sv = fs & 1;
+            if (2 * w - sv >= NV * nl) continue;
+            const int64_t g = (int64_t)fs - sv + (int64_t)NV * l0 + 2 * w;
+            if (g + 1 < fn)
+                copy16(x + g, Xs + b * VX + 2 * (e0 + wave_e));
+            else
+                Xs[b * VX + 2 * e] = x[g];
+        }
+    };
+    // item i of this thread: (vertex, value of the chunk) (tid + 256 i) / W,
+    // (tid + 256 i) % W; kind 0 none, 1 read-add-write, 2 atomic
+    auto item_kind = [&](int i) {
+        const int v = (tid + kThreads * i) / W;
+        return v >= nv ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
+    };
+    auto load_old = [&](int k, double (&dst)[kItemsD]) {
+        const int nl = min(S, lam - k * S);
+#pragma unroll
+        for (int i = 0; i < kItemsD; ++i) {
+            const int it = tid + kThreads * i;
+            const int v = it / W, jj = it % W;
+            dst[i] = (item_kind(i) == 1 && jj < NV * nl) ? y[(int64_t)Tfst[v] + (int64_t)NV * k * S + jj] : 0.0;
+        }
+    };
+    auto write_back = [&](int k, const double (&old)[kItemsD]) {
+        const int nl = min(S, lam - k * S);
+#pragma unroll
+        for (int i = 0; i < kItemsD; ++i) {
+            const int it = tid + kThreads * i;
+            const int v = it / W, jj = it % W;
+            const int kind = item_kind(i);
+            if (kind == 0 || jj >= NV * nl) continue;
+            const int32_t fs = Tfst[v];
+            const int pos = v * PX + (fs & 1) + jj;
+            const double s = A[pos];
+            const int64_t g = (int64_t)fs + (int64_t)NV * k * S + jj;
+            if (kind == 2)
+                unsafeAtomicAdd(y + g, s);
+            else
+                y[g] = old[i] + s;
+            A[pos] = 0.0;
+        }
+    };
+
+    double yO[kItemsD];   // old output values of the chunk written back next
+    const int nch = (lam + S - 1) / S;
+    issue_copies(0);
+    load_old(0, yO);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int nl = min(S, lam - k * S);
+        wait_copies();
+        lds_barrier();
+        if (k > 0) {
+            write_back(k - 1, yO);
+            load_old(k, yO);
+        }
+        lds_barrier();
+        if (k + 1 < nch) issue_copies(k + 1);
+        if (!has || r >= nl) continue;
+        const double* const Zb = Zs + b * VZ;
+        const double* const Xb = Xs + b * VX;
+        double h[3], xv[3][NV], yv[3][NV];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            h[q] = Zb[zb[q] + r + 1] - Zb[zb[q] + r];
+#pragma unroll
+            for (int be = 0; be < NV; ++be) xv[q][be] = Xb[xb[q] + NV * r + be];
+        }
+        tp_mass<3, NV>(twoA, h, xv, yv);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int be = 0; be < NV; ++be) lds_add(A + xb[q] + NV * r + be, yv[q][be]);
+    }
+    lds_barrier();
+    write_back(nch - 1, yO);
+}
+
 // P2 x P2 mass action, y += M x (INC).  The tile walk of k_pipe_p1 with the
 // P2 columns: every base vertex and edge of the tile owns a field column of
 // 2 lambda + 1 nodes (level l at 2 l, the middle of layer l at 2 l + 1), and
@@ -1420,8 +1603,15 @@ static bool dg_element(int32_t element)
            element == EXM_ELEMENT_DG1DG0 || element == EXM_ELEMENT_DG0P1 || element == EXM_ELEMENT_DG1P1;
 }
 
+static bool cgdg_element(int32_t element) { return element == EXM_ELEMENT_P1DG0 || element == EXM_ELEMENT_P1DG1; }
+
 size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t estride, int32_t cstride, int32_t S)
 {
+    if (kernel == EXM_K_MASS && cgdg_element(element)) {
+        const int nv = element == EXM_ELEMENT_P1DG0 ? 1 : 2;
+        return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 3 * (size_t)vstride * (nv * S + 2)) +
+               3 * sizeof(int32_t) * vstride;
+    }
     if (cubic_kernel(kernel) && element == EXM_ELEMENT_P1P1) {
         const int nin = kernel == EXM_K_CUBIC_FUSED ? 3 : 2;
         const int nout = kernel == EXM_K_CUBIC ? 1 : (kernel == EXM_K_CUBIC_VJP ? 2 : 3);
@@ -1444,13 +1634,13 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
 bool pipe_supported(int32_t kernel, int32_t element)
 {
     if (cubic_kernel(kernel)) return element == EXM_ELEMENT_P1P1;
-    return kernel == EXM_K_MASS &&
-           (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2 || dg_element(element));
+    return kernel == EXM_K_MASS && (element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_P2P2 ||
+                                    cgdg_element(element) || dg_element(element));
 }
 
 int32_t pipe_max_tile_cells(int32_t kernel, int32_t element, int32_t S)
 {
-    if (cubic_kernel(kernel)) return kThreads / S;   // one layer of one cell per thread
+    if (cubic_kernel(kernel) || cgdg_element(element)) return kThreads / S;   // one layer of one cell per thread
     if (dg_element(element)) return 2 * 512 / S;
     if (element == EXM_ELEMENT_P2P2) return kThreads / (S / kLayers2);
     return kPasses * (kThreads / (S / kLayers));
@@ -1458,14 +1648,15 @@ int32_t pipe_max_tile_cells(int32_t kernel, int32_t element, int32_t S)
 
 bool pipe_chunk_ok(int32_t kernel, int32_t element, int32_t S)
 {
-    if (cubic_kernel(kernel)) return S == 8 || S == 16;
+    if (cubic_kernel(kernel) || cgdg_element(element)) return S == 8 || S == 16;
     if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 20 || S == 24 || S == 32;
     if (element == EXM_ELEMENT_P2P2) return S == 8 || S == 16;
     return S == 8 || S == 16 || S == 32;
 }
 
-int32_t pipe_max_tile_verts(int32_t kernel, int32_t S)
+int32_t pipe_max_tile_verts(int32_t kernel, int32_t element, int32_t S)
 {
+    if (cgdg_element(element)) return kThreads * kItemsD / ((element == EXM_ELEMENT_P1DG0 ? 1 : 2) * S);
     return kThreads * (cubic_kernel(kernel) ? kItemsC : kItems) / S;
 }
 
@@ -1503,6 +1694,16 @@ static void launch_pipe_cubic(int32_t kernel, int32_t race, const ColArgs& a, co
         launch_pipe_cubic_f<2, S>(race, a, t, lds, s);
     else
         launch_pipe_cubic_f<3, S>(race, a, t, lds, s);
+}
+
+template <int NV, int S>
+static void launch_pipe_cgdg(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+{
+    const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    if (race == EXM_RACE_COLOUR)
+        hipLaunchKernelGGL((k_pipe_cgdg<NV, S, kPlain>), grid, block, lds, s, a, t);
+    else
+        hipLaunchKernelGGL((k_pipe_cgdg<NV, S, kAtomic>), grid, block, lds, s, a, t);
 }
 
 template <int S>
@@ -1555,8 +1756,8 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
 {
     if (t.tile_count <= 0) return EXM_OK;
     EXM_CHECK(pipe_supported(P.kernel, P.element), EXM_EUNSUPPORTED,
-              "the PIPELINED schedule runs the mass action on P1xP1, P2xP2 and the spaces discontinuous "
-              "horizontally, and the cubic forms on P1xP1");
+              "the PIPELINED schedule runs the mass action on every space but the mixed-degree one, and the "
+              "cubic forms on P1xP1");
     const uintptr_t al = (uintptr_t)a.X | (uintptr_t)a.in0 | (uintptr_t)a.in1 | (uintptr_t)a.in2 | (uintptr_t)a.out0;
     EXM_CHECK((al & 15) == 0, EXM_EUNSUPPORTED, "the PIPELINED schedule needs 16-byte aligned field pointers");
     if (cubic_kernel(P.kernel)) {
@@ -1565,6 +1766,19 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
         case 8: launch_pipe_cubic<8>(P.kernel, P.race, a, t, lds, s); break;
         case 16: launch_pipe_cubic<16>(P.kernel, P.race, a, t, lds, s); break;
         default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8 or 16 on the cubic forms", S);
+        }
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
+    if (cgdg_element(P.element)) {
+        EXM_CHECK(P.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED, "owner-computes is for the P1xP1 mass action");
+        const bool dg1 = P.element == EXM_ELEMENT_P1DG1;
+        switch (S) {
+        case 8: dg1 ? launch_pipe_cgdg<2, 8>(P.race, a, t, lds, s) : launch_pipe_cgdg<1, 8>(P.race, a, t, lds, s); break;
+        case 16:
+            dg1 ? launch_pipe_cgdg<2, 16>(P.race, a, t, lds, s) : launch_pipe_cgdg<1, 16>(P.race, a, t, lds, s);
+            break;
+        default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8 or 16 on CG1xDG*", S);
         }
         EXM_TRY_HIP(hipGetLastError());
         return EXM_OK;

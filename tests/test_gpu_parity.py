@@ -108,7 +108,8 @@ def test_mass_staged_shapes(space, tile, chunk, race):
 
 
 @pytest.mark.parametrize("schedule", [exm.EXM_SCHED_PIPELINED, exm.EXM_SCHED_CHUNKED])
-@pytest.mark.parametrize("space", ["P1", "P2", "DG0", "DG1", "DG0xDG1", "DG1xDG0", "DG0xCG1", "DG1xCG1"])
+@pytest.mark.parametrize("space", ["P1", "P2", "DG0", "DG1", "DG0xDG1", "DG1xDG0", "DG0xCG1", "DG1xCG1", "CG1xDG0",
+                                   "CG1xDG1"])
 @pytest.mark.parametrize("tile", [8, 29, 64, 128])
 @pytest.mark.parametrize("chunk", [8, 12, 16, 20, 24, 32])
 @pytest.mark.parametrize("race", RACES + [exm.EXM_RACE_OWNER])
@@ -128,7 +129,7 @@ def test_mass_pipelined_shapes(schedule, space, tile, chunk, race):
             # space does not take, are refused before any launch
             big = e.status == exm._abi.EXM_EUNSUPPORTED and ("PIPELINED" in str(e) or "CHUNKED" in str(e))
             odd = e.status == exm._abi.EXM_ERANGE and (
-                (chunk in (12, 20, 24) and (space != "P1" or schedule != 4)) or (chunk == 32 and space == "P2"))
+                (chunk in (12, 20, 24) and (space != "P1" or schedule != 4)) or (chunk == 32 and space in ("P2", "CG1xDG0", "CG1xDG1")))
             assert big or odd, str(e)
             return
         if c.out_access() == exm.EXM_INC:
