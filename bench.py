@@ -417,13 +417,16 @@ def secondary(torch, exm, W, meshgen):
             V = ev.space(name)
             x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
             y = V.zeros()
-            # the DIRECT shapes (the tuner's candidates on such a mesh), and GATHER for P1
+            # the DIRECT shapes (the tuner's candidates on such a mesh), and GATHER and PIPELINED for P1
             shapes = direct_shapes(exm, name)
             if name == "P1":
                 shapes += [dict(schedule=exm.EXM_SCHED_GATHER, waves_per_block=w) for w in (1, 2, 4)]
+                shapes += [dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=t, chunk_layers=c)
+                           for (t, c) in ((64, 16), (48, 16), (64, 12))]
             b = W.mass_bytes(ev, name)
             for label, group in (("direct", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_DIRECT]),
-                                 ("gather", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_GATHER])):
+                                 ("gather", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_GATHER]),
+                                 ("pipelined", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_PIPELINED])):
                 if not group:
                     continue
                 t, cfg = min(((timed(torch, lambda: W.run_mass(ev, name, x, y, **c), 10)[0], c) for c in group),

@@ -251,10 +251,12 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
-    if (mesh->variable && !(d.schedule == EXM_SCHED_GATHER && gather_supported(P.kernel, P.element))) {
+    // the P1xP1 mass action has a PIPELINED kernel for columns of different heights
+    const bool var_pipe = d.schedule == EXM_SCHED_PIPELINED && P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1;
+    EXM_CHECK(!mesh->variable || d.race != EXM_RACE_OWNER || d.schedule == EXM_SCHED_GATHER, EXM_EUNSUPPORTED,
+              "owner-computes tiles need columns of one height; this mesh has a layer range per column");
+    if (mesh->variable && !(d.schedule == EXM_SCHED_GATHER && gather_supported(P.kernel, P.element)) && !var_pipe) {
         // columns of different heights: the DIRECT schedule walks each on its own (or GATHER)
-        EXM_CHECK(d.race != EXM_RACE_OWNER, EXM_EUNSUPPORTED,
-                  "owner-computes tiles need columns of one height; this mesh has a layer range per column");
         if (d.schedule != EXM_SCHED_DIRECT) d.cols_per_wave = d.waves_per_block = 0;
         d.schedule = EXM_SCHED_DIRECT;
         d.tile_cells = d.chunk_layers = 0;
@@ -473,6 +475,10 @@ static void fill_tile_args(const TilePlan* plan, const LoopLaunch& P, TileArgs& 
     t.fstep0 = fok && P.fspace->col_size[0] > 0 ? P.fspace->col_size[0] : 0;
     t.fbase1 = P.fspace->base[1];
     t.fstep1 = fok && P.fspace->col_size[1] > 0 ? P.fspace->col_size[1] : 0;
+    const exm_mesh* m = P.fspace->mesh;
+    t.vlo = m->variable ? m->d_vert_lo.p : nullptr;
+    t.vhi = m->variable ? m->d_vert_hi.p : nullptr;
+    t.clo = m->variable ? m->d_cell_lo.p : nullptr;
 }
 
 static int32_t run_tiled(const exm_mesh* mesh, LoopLaunch& P, const exm_loop_opts& ch, hipStream_t stream)
@@ -667,10 +673,13 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     const int32_t races[2] = {EXM_RACE_ATOMIC, EXM_RACE_COLOUR};
     for (int r = 0; r < (cg ? 2 : 1); ++r) {
         for (int32_t c : {1, 2, 3, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 4, 0, 0});
-        if (iterset->variable) {   // columns of different heights run DIRECT (or GATHER)
+        if (iterset->variable) {   // columns of different heights run DIRECT, GATHER or (P1 mass) PIPELINED
             for (int32_t c : {1, 2, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 2, 0, 0});
             if (r == 0 && gather_supported(P.kernel, P.element))
                 for (int32_t w : {1, 2, 4}) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_GATHER, 0, w, 0, 0});
+            if (P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1)
+                for (int32_t tc : {32, 48, 64})
+                    for (int32_t S : {8, 16}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
             continue;
         }
         if (r == 0 && gather_supported(P.kernel, P.element))

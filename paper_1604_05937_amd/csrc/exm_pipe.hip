@@ -350,6 +350,264 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     }
 }
 
+// P1 x P1 mass action / RHS (INC) on a mesh whose cell columns have layer
+// ranges of their own (cell c: layers lo_c .. lo_c + lam_c - 1; vertex v:
+// levels lo_v .. hi_v, the union of its cells' ranges, level L at column
+// start + L - lo_v).  k_pipe_p1 on absolute levels: a tile walks the chunks
+// of S levels that cover its own window (the lowest and highest level of its
+// vertices, from an even level), copies of a vertex stay inside its column
+// (a 16-byte pair half outside it is loaded element by element), a thread
+// evaluates its layers of a cell only inside the cell's range, and a
+// (vertex, level) outside the vertex's range is neither read nor written.
+template <int S, int MODE>
+__global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const TileArgs t)
+{
+    static_assert(MODE != kOwner, "owner tiles need columns of one height");
+    constexpr bool ATOMIC = MODE == kAtomic;
+    constexpr int P2 = S + 2, PP = P2 / 2, R = kLayers, G = S / R, CPP = kThreads / G;
+    extern __shared__ double lds[];
+    __shared__ int32_t s_lo, s_hi;   // the tile's level window
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int VS = t.vstride * P2;
+    double* const Zs = lds;
+    double* const Xs = lds + 2 * VS;
+    double* const A = lds + 4 * VS;
+    double* const Tx = A;                 // set-up only
+    double* const Ty = A + t.vstride;
+    int32_t* const Ttag = (int32_t*)(lds + 5 * VS);
+    int32_t* const Txst = Ttag + t.vstride;
+    int32_t* const Tlo = Txst + t.vstride;
+    int32_t* const Thi = Tlo + t.vstride;
+    const int64_t n = a.xn;
+    const double* const z = a.X + 2 * n;
+    const double* const x = a.in0;
+    double* const y = a.out0;
+
+    // this thread's cells: tile-local vertices and layer range
+    bool has[kPasses];
+    int lvq[kPasses][3], clo[kPasses], chi[kPasses];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        const int c = tid / G + p * CPP;
+        has[p] = tid < CPP * G && c < nc;
+        const int32_t cell = has[p] ? t.cells[cb + c] : 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+        clo[p] = has[p] ? t.clo[cell] : 0;
+        chi[p] = has[p] ? clo[p] + a.cell_lam[cell] : 0;
+    }
+    if (tid == 0) {
+        s_lo = INT32_MAX;
+        s_hi = -1;
+    }
+    lds_barrier();
+    // tile vertex table: tag, column start, level range, (x, y) of the column
+    int my_lo = INT32_MAX, my_hi = -1;
+    for (int v = tid; v < nv; v += kThreads) {
+        const int32_t tag = t.verts[vb0 + v];
+        const int32_t xs = t.xstart[vid(tag)];
+        const int32_t lo = t.vlo[vid(tag)], hi = t.vhi[vid(tag)];
+        Ttag[v] = tag;
+        Txst[v] = xs;
+        Tlo[v] = lo;
+        Thi[v] = hi;
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+        my_lo = min(my_lo, lo);
+        my_hi = max(my_hi, hi);
+    }
+    if (my_hi >= 0) {
+        atomicMin(&s_lo, my_lo);
+        atomicMax(&s_hi, my_hi);
+    }
+    lds_barrier();
+    const int L0b = s_lo & ~1;   // first level of the first chunk (even, so that each vertex's parity is fixed)
+    const int thi = s_hi;        // the tile's top level
+    const int nch = (thi - L0b + S - 1) / S;
+
+    // slot start of each vertex of this thread's cells (with the parity
+    // shift of its column) and 2A; layers r0 .. r0 + R - 1 of every chunk
+    const int r0 = (tid % G) * R;
+    int vb[kPasses][3];
+    double twoA[kPasses];
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p) {
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = lvq[p][q];
+            vb[p][q] = lv * P2 + ((Txst[lv] - Tlo[lv] + L0b) & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
+    }
+    const int npass = (nc + CPP - 1) / CPP;
+
+    // item i of this thread: (vertex, level L0 + jj of the chunk),
+    // (tid + 256 i) / S, (tid + 256 i) % S; kind -1 no vertex, 0 a level
+    // outside the vertex's column, 1 read-add-write, 2 atomic
+    auto item = [&](int i, int L0, int& v, int& jj, int& pos, int64_t& g, int& kind) {
+        const int it = tid + kThreads * i;
+        v = it / S;
+        jj = it % S;
+        kind = -1;
+        if (v >= nv) return;
+        const int lo = Tlo[v], hi = Thi[v], L = L0 + jj;
+        const int32_t xs = Txst[v];
+        pos = v * P2 + ((xs - lo + L0b) & 1) + jj;
+        g = (int64_t)xs + (L - lo);
+        kind = L < lo || L > hi ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
+    };
+    const int wave_e = tid & ~63;
+    auto issue_copies = [&](int k) {
+        const int L0 = L0b + k * S;
+        const int nl = min(S, thi - L0);
+        const int b = k & 1;
+        for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
+            const int e = e0 + tid;
+            const int v = e / PP, w = e - (e / PP) * PP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int lo = Tlo[v], hi = Thi[v];
+            const int sv = (xs - lo + L0b) & 1;
+            const int La = L0 - sv + 2 * w;   // the pair's levels La, La + 1
+            if (2 * w - sv > nl || La + 1 < lo || La > hi) continue;
+            const int64_t g = (int64_t)xs + (La - lo);
+            const int e2 = 2 * e;
+            if (La >= lo && La + 1 <= hi) {
+                copy16(z + g, Zs + b * VS + 2 * (e0 + wave_e));
+                copy16(x + g, Xs + b * VS + 2 * (e0 + wave_e));
+            } else if (La >= lo) {   // only the pair's first level is in the column
+                Zs[b * VS + e2] = z[g];
+                Xs[b * VS + e2] = x[g];
+            } else {                 // only its second
+                Zs[b * VS + e2 + 1] = z[g + 1];
+                Xs[b * VS + e2 + 1] = x[g + 1];
+            }
+        }
+    };
+    auto load_old = [&](int k, double (&dst)[kItems]) {
+        const int L0 = L0b + k * S;
+        const int nl = min(S, thi - L0);
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            int v, jj, pos, kind;
+            int64_t g;
+            item(i, L0, v, jj, pos, g, kind);
+            dst[i] = kind == 1 && jj < nl ? y[g] : 0.0;   // g is inside the column only for kind >= 1
+        }
+    };
+    auto write_back = [&](int k, const double (&old)[kItems], bool carry) {
+        const int L0 = L0b + k * S;
+        const int nl = min(S, thi - L0);
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            int v, jj, pos, kind;
+            int64_t g;
+            item(i, L0, v, jj, pos, g, kind);
+            if (kind < 0 || jj >= nl) continue;
+            if (kind > 0) {
+                const double s = A[pos];
+                if (kind == 2)
+                    unsafeAtomicAdd(y + g, s);
+                else
+                    y[g] = old[i] + s;
+            }
+            // the chunk's top level moves to level 0 of the next chunk even
+            // where the old level 0 lies below the column
+            if (carry && jj == 0) {
+                A[pos] = A[pos + S];
+                A[pos + S] = 0.0;
+            } else {
+                A[pos] = 0.0;
+            }
+        }
+    };
+
+    lds_barrier();   // (x, y) are no longer needed: the accumulator takes their place
+    for (int i = tid; i < VS; i += kThreads) A[i] = 0.0;
+    double yA[kItems], yB[kItems];
+    issue_copies(0);
+    load_old(0, yA);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int L0 = L0b + k * S;
+        const int nl = min(S, thi - L0);
+        wait_copies();
+        lds_barrier();
+        if (k > 0) write_back(k - 1, yB, true);
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) yB[i] = yA[i];
+        if (k + 1 < nch) load_old(k + 1, yA);
+        lds_barrier();
+        if (k + 1 < nch) issue_copies(k + 1);
+        const double* const Zb = Zs + b * VS;
+        const double* const Xb = Xs + b * VS;
+#pragma unroll
+        for (int p = 0; p < kPasses; ++p) {
+            if (p >= npass) break;
+            if (!has[p] || r0 >= nl || L0 + r0 >= chi[p] || L0 + r0 + R <= clo[p]) continue;
+            int o[3];
+            double zc[3], xc[3], acc[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                o[q] = vb[p][q] + r0;
+                zc[q] = Zb[o[q]];
+                xc[q] = Xb[o[q]];
+                acc[q] = 0.0;
+            }
+            int r = 0;
+#pragma unroll
+            for (; r < R; ++r) {
+                if (r0 + r >= nl) break;
+                const int L = L0 + r0 + r;
+                const bool in = L >= clo[p] && L < chi[p];   // a prism of this cell
+                double zn[3], xn[3], h[3], yb[3] = {0.0, 0.0, 0.0}, yt[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    zn[q] = Zb[o[q] + r + 1];
+                    xn[q] = Xb[o[q] + r + 1];
+                    h[q] = zn[q] - zc[q];
+                }
+                if (in) p1_mass(twoA[p], h, xc, xn, yb, yt);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (in || acc[q] != 0.0) lds_add(A + o[q] + r, acc[q] + yb[q]);
+                    acc[q] = yt[q];
+                    zc[q] = zn[q];
+                    xc[q] = xn[q];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (acc[q] != 0.0) lds_add(A + o[q] + r, acc[q]);
+        }
+    }
+    // write back the last chunk, and the tile's top level for the vertices that reach it
+    lds_barrier();
+    {
+        const int k = nch - 1;
+        const int L0 = L0b + k * S, nl = thi - L0;
+        write_back(k, yB, false);
+        for (int v = tid; v < nv; v += kThreads) {
+            if (Thi[v] != thi) continue;
+            const int32_t xs = Txst[v];
+            const int lo = Tlo[v];
+            const double s = A[v * P2 + ((xs - lo + L0b) & 1) + nl];
+            const int64_t g = (int64_t)xs + (thi - lo);
+            if (ATOMIC && vshared(Ttag[v]))
+                unsafeAtomicAdd(y + g, s);
+            else
+                y[g] += s;
+        }
+    }
+}
+
 // Mass action / RHS on the spaces discontinuous horizontally and vertically:
 // NH horizontal by NV vertical nodes per layer (DG0 x DG0 1 x 1, DG1 x DG1
 // 3 x 2, DG0 x DG1 1 x 2, DG1 x DG0 3 x 1; node (a, b) at NV a + b of the
@@ -1619,8 +1877,8 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
                2 * sizeof(int32_t) * vstride;
     }
     if (kernel != EXM_K_MASS) return 0;
-    if (element == EXM_ELEMENT_P1P1)
-        return sizeof(double) * 5 * (size_t)vstride * (S + 2) + 2 * sizeof(int32_t) * vstride;
+    if (element == EXM_ELEMENT_P1P1)   // tag, column start, and a level range for columns of different heights
+        return sizeof(double) * 5 * (size_t)vstride * (S + 2) + 4 * sizeof(int32_t) * vstride;
     if (element == EXM_ELEMENT_P2P2) {
         const size_t es = (size_t)vstride + (size_t)estride;
         return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 3 * es * (2 * S + 2)) +
@@ -1666,6 +1924,13 @@ template <int S>
 static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
 {
     const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    if (t.vlo) {   // columns of different heights
+        if (race == EXM_RACE_COLOUR)
+            hipLaunchKernelGGL((k_pipe_p1_var<S, kPlain>), grid, block, lds, s, a, t);
+        else
+            hipLaunchKernelGGL((k_pipe_p1_var<S, kAtomic>), grid, block, lds, s, a, t);
+        return;
+    }
     if (race == EXM_RACE_OWNER)
         hipLaunchKernelGGL((k_pipe_p1<S, kOwner>), grid, block, lds, s, a, t);
     else if (race == EXM_RACE_COLOUR)

@@ -51,6 +51,11 @@ struct TileArgs {
     // (step 0: read them).  Coordinate vertex columns, field vertex and edge columns.
     int64_t xbase, fbase0, fbase1;
     int32_t xstep, fstep0, fstep1;
+    // a mesh with a layer range per cell column (else null): level range of
+    // every base vertex, first layer of every base cell
+    const int32_t* __restrict__ vlo;
+    const int32_t* __restrict__ vhi;
+    const int32_t* __restrict__ clo;
 };
 
 // Column start of entity `id` from its table or, on uniform meshes, in closed form.

@@ -114,11 +114,37 @@ def test_full_ranges_match_the_uniform_mesh(space):
 
 
 @pytest.mark.parametrize("schedule", [exm.EXM_SCHED_TILED, exm.EXM_SCHED_STAGED, exm.EXM_SCHED_PIPELINED])
-def test_variable_mesh_runs_direct_whatever_the_schedule(schedule):
+def test_variable_mesh_any_schedule(schedule):
+    # TILED and STAGED fall back to DIRECT; PIPELINED has a kernel of its own for P1
     c = _case(8, 10, "bathymetry", "P1")
     x = meshgen.uniform_values(c.n, seed=6)
     got = c.mass(x, schedule=schedule, tile_cells=64, chunk_layers=16)
-    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what="variable P1, schedule falls back")
+    assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"variable P1, schedule {schedule}")
+
+
+@pytest.mark.parametrize("n,lam,kind", SHAPES + [(6, 62, "random"), (5, 33, "bathymetry"), (9, 16, "random")])
+@pytest.mark.parametrize("race", RACES)
+@pytest.mark.parametrize("tile,chunk", [(64, 16), (29, 8), (8, 32), (32, 12)])
+def test_variable_pipelined_p1(n, lam, kind, race, tile, chunk):
+    # the tile pipeline on absolute levels: a window per tile, copies inside
+    # each vertex's column, prisms only inside each cell's range; INC into
+    # non-zero outputs exercises the old values loaded one chunk ahead
+    say(f"variable pipelined P1 n={n} lam={lam} {kind} race={race} tile={tile} chunk={chunk}")
+    c = _case(n, lam, kind, "P1", order="random" if tile == 29 else "rcm")
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    y0 = meshgen.uniform_values(c.n, seed=71)
+    xd, y = c.dev(x), c.dev(y0)
+    fields = [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)]
+    opts = dict(schedule=exm.EXM_SCHED_PIPELINED, race=race, tile_cells=tile, chunk_layers=chunk)
+    try:
+        cfg = exm.par_loop_config(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, fields, **opts)
+        exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, fields, **opts)
+    except exm.ExmError as e:
+        # tiles too large for the chunk length are refused before any launch
+        assert e.status == exm._abi.EXM_EUNSUPPORTED and "PIPELINED" in str(e), str(e)
+        return
+    assert cfg["schedule"] == exm.EXM_SCHED_PIPELINED
+    assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what="variable pipelined P1")
 
 
 def test_variable_mesh_refuses_owner_computes():
