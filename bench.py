@@ -422,7 +422,7 @@ def secondary(torch, exm, W, meshgen):
             if name == "P1":
                 shapes += [dict(schedule=exm.EXM_SCHED_GATHER, waves_per_block=w) for w in (1, 2, 4)]
                 shapes += [dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=t, chunk_layers=c)
-                           for (t, c) in ((64, 16), (48, 16), (64, 12))]
+                           for (t, c) in ((64, 16), (48, 16), (96, 8))]
             b = W.mass_bytes(ev, name)
             for label, group in (("direct", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_DIRECT]),
                                  ("gather", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_GATHER]),

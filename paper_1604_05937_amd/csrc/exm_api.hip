@@ -252,7 +252,8 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
     // the P1xP1 mass action has a PIPELINED kernel for columns of different heights
-    const bool var_pipe = d.schedule == EXM_SCHED_PIPELINED && P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1;
+    const bool var_pipe = d.schedule == EXM_SCHED_PIPELINED && P.kernel == EXM_K_MASS &&
+                          P.element == EXM_ELEMENT_P1P1 && mesh->n_layers <= 2000;
     EXM_CHECK(!mesh->variable || d.race != EXM_RACE_OWNER || d.schedule == EXM_SCHED_GATHER, EXM_EUNSUPPORTED,
               "owner-computes tiles need columns of one height; this mesh has a layer range per column");
     if (mesh->variable && !(d.schedule == EXM_SCHED_GATHER && gather_supported(P.kernel, P.element)) && !var_pipe) {

@@ -359,8 +359,16 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
 // (a 16-byte pair half outside it is loaded element by element), a thread
 // evaluates its layers of a cell only inside the cell's range, and a
 // (vertex, level) outside the vertex's range is neither read nor written.
+// Chunk indices are kept in 8 bits: the host allows at most 2000 layers.
+// Four workgroups per CU as for k_pipe_p1 where S is a power of two (at most
+// 128 VGPRs, which the range bookkeeping fits only with the item fields
+// packed as below; unbounded it took 154 VGPRs, three workgroups, and 40 %
+// more time on full columns).  Other chunk lengths need a few more
+// registers for the level offsets and keep three workgroups rather than
+// spill.
 template <int S, int MODE>
-__global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const TileArgs t)
+__global__ void __launch_bounds__(kThreads, (S & (S - 1)) == 0 ? 4 : 3) k_pipe_p1_var(const ColArgs a,
+                                                                                        const TileArgs t)
 {
     static_assert(MODE != kOwner, "owner tiles need columns of one height");
     constexpr bool ATOMIC = MODE == kAtomic;
@@ -389,7 +397,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const
 
     // this thread's cells: tile-local vertices and layer range
     bool has[kPasses];
-    int lvq[kPasses][3], clo[kPasses], chi[kPasses];
+    int lvq[kPasses][3], crng[kPasses];   // crng: first layer | (last layer + 1) << 16
 #pragma unroll
     for (int p = 0; p < kPasses; ++p) {
         const int c = tid / G + p * CPP;
@@ -397,8 +405,8 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const
         const int32_t cell = has[p] ? t.cells[cb + c] : 0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
-        clo[p] = has[p] ? t.clo[cell] : 0;
-        chi[p] = has[p] ? clo[p] + a.cell_lam[cell] : 0;
+        const int cl = has[p] ? t.clo[cell] : 0;
+        crng[p] = has[p] ? cl | ((cl + a.cell_lam[cell]) << 16) : 0;
     }
     if (tid == 0) {
         s_lo = INT32_MAX;
@@ -425,8 +433,10 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const
         atomicMax(&s_hi, my_hi);
     }
     lds_barrier();
-    const int L0b = s_lo & ~1;   // first level of the first chunk (even, so that each vertex's parity is fixed)
-    const int thi = s_hi;        // the tile's top level
+    // first level of the first chunk (even, so that each vertex's parity is
+    // fixed) and the tile's top level, the same in every lane
+    const int L0b = __builtin_amdgcn_readfirstlane(s_lo & ~1);
+    const int thi = __builtin_amdgcn_readfirstlane(s_hi);
     const int nch = (thi - L0b + S - 1) / S;
 
     // slot start of each vertex of this thread's cells (with the parity
@@ -448,21 +458,34 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const
     }
     const int npass = (nc + CPP - 1) / CPP;
 
-    // item i of this thread: (vertex, level L0 + jj of the chunk),
-    // (tid + 256 i) / S, (tid + 256 i) % S; kind -1 no vertex, 0 a level
-    // outside the vertex's column, 1 read-add-write, 2 atomic
-    auto item = [&](int i, int L0, int& v, int& jj, int& pos, int64_t& g, int& kind) {
+    // item i of this thread: (vertex, level L0b + k S + jj of chunk k),
+    // (tid + 256 i) / S, (tid + 256 i) % S, fixed for the whole column.
+    // ipos: accumulator slot (bits 0-13: LDS holds at most 4096 slots per
+    // array), kind (bits 14-15: 0 no vertex, 1 read-add-write, 2 atomic) and
+    // the first and last chunk at which the level is inside the vertex's
+    // column (bits 16-23, 24-31: the host allows at most 2000 layers, 250
+    // chunks of 8); iglb: global index at chunk 0 (used only inside).
+    uint32_t ipos[kItems];
+    int32_t iglb[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
         const int it = tid + kThreads * i;
-        v = it / S;
-        jj = it % S;
-        kind = -1;
-        if (v >= nv) return;
-        const int lo = Tlo[v], hi = Thi[v], L = L0 + jj;
-        const int32_t xs = Txst[v];
-        pos = v * P2 + ((xs - lo + L0b) & 1) + jj;
-        g = (int64_t)xs + (L - lo);
-        kind = L < lo || L > hi ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
-    };
+        const int v = it / S, jj = it - (it / S) * S;
+        const bool ok = v < nv;
+        const int32_t xs = ok ? Txst[v] : 0;
+        const int lo = ok ? Tlo[v] : 0, hi = ok ? Thi[v] : 0;
+        const int kind = !ok ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
+        const int nlo = lo - L0b - jj, nhi = hi - L0b - jj;   // inside: nlo <= k S <= nhi
+        const int klo = nlo > 0 ? (nlo + S - 1) / S : 0;
+        const int khi = nhi >= 0 ? nhi / S : -1;
+        const bool any = khi >= klo;
+        ipos[i] = (uint32_t)(v * P2 + ((xs - lo + L0b) & 1) + jj) | ((uint32_t)kind << 14) |
+                  ((uint32_t)(any ? klo : 1) << 16) | ((uint32_t)(any ? khi : 0) << 24);
+        iglb[i] = xs - lo + L0b + jj;
+    }
+    auto kind_of = [&](int i) { return (int)((ipos[i] >> 14) & 3u); };
+    auto slot_of = [&](int i) { return (int)(ipos[i] & 0x3fffu); };
+    auto inside = [&](int i, int k) { return k >= (int)((ipos[i] >> 16) & 0xffu) && k <= (int)(ipos[i] >> 24); };
     const int wave_e = tid & ~63;
     auto issue_copies = [&](int k) {
         const int L0 = L0b + k * S;
@@ -492,27 +515,25 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const
         }
     };
     auto load_old = [&](int k, double (&dst)[kItems]) {
-        const int L0 = L0b + k * S;
-        const int nl = min(S, thi - L0);
+        const int nl = min(S, thi - (L0b + k * S));
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            int v, jj, pos, kind;
-            int64_t g;
-            item(i, L0, v, jj, pos, g, kind);
-            dst[i] = kind == 1 && jj < nl ? y[g] : 0.0;   // g is inside the column only for kind >= 1
+            const int jj = (tid + kThreads * i) % S;
+            const bool rd = kind_of(i) == 1 && jj < nl && inside(i, k);
+            dst[i] = rd ? y[(int64_t)iglb[i] + k * S] : 0.0;
         }
     };
     auto write_back = [&](int k, const double (&old)[kItems], bool carry) {
-        const int L0 = L0b + k * S;
-        const int nl = min(S, thi - L0);
+        const int nl = min(S, thi - (L0b + k * S));
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            int v, jj, pos, kind;
-            int64_t g;
-            item(i, L0, v, jj, pos, g, kind);
-            if (kind < 0 || jj >= nl) continue;
-            if (kind > 0) {
+            const int jj = (tid + kThreads * i) % S;
+            const int kind = kind_of(i);
+            const int pos = slot_of(i);
+            if (kind == 0 || jj >= nl) continue;
+            if (inside(i, k)) {
                 const double s = A[pos];
+                const int64_t g = (int64_t)iglb[i] + k * S;
                 if (kind == 2)
                     unsafeAtomicAdd(y + g, s);
                 else
@@ -551,7 +572,8 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const
 #pragma unroll
         for (int p = 0; p < kPasses; ++p) {
             if (p >= npass) break;
-            if (!has[p] || r0 >= nl || L0 + r0 >= chi[p] || L0 + r0 + R <= clo[p]) continue;
+            const int clo = crng[p] & 0xffff, chi = crng[p] >> 16;
+            if (!has[p] || r0 >= nl || L0 + r0 >= chi || L0 + r0 + R <= clo) continue;
             int o[3];
             double zc[3], xc[3], acc[3];
 #pragma unroll
@@ -566,7 +588,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1_var(const ColArgs a, const
             for (; r < R; ++r) {
                 if (r0 + r >= nl) break;
                 const int L = L0 + r0 + r;
-                const bool in = L >= clo[p] && L < chi[p];   // a prism of this cell
+                const bool in = L >= clo && L < chi;   // a prism of this cell
                 double zn[3], xn[3], h[3], yb[3] = {0.0, 0.0, 0.0}, yt[3] = {0.0, 0.0, 0.0};
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {

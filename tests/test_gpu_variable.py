@@ -147,6 +147,23 @@ def test_variable_pipelined_p1(n, lam, kind, race, tile, chunk):
     assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what="variable pipelined P1")
 
 
+@pytest.mark.parametrize("lam,expect", [(2000, "pipelined"), (2001, "direct")])
+def test_variable_pipelined_layer_limit(lam, expect):
+    # the pipelined kernel keeps chunk indices in 8 bits: up to 2000 layers it
+    # runs, above that the loop falls back to DIRECT; both match the oracle
+    say(f"variable pipelined P1 layer limit lam={lam}")
+    c = _case(2, lam, "bathymetry", "P1")
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    xd, y = c.dev(x), c.V.zeros()
+    fields = [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)]
+    opts = dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=8, chunk_layers=8)
+    cfg = exm.par_loop_config(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, fields, **opts)
+    want = exm.EXM_SCHED_PIPELINED if expect == "pipelined" else exm.EXM_SCHED_DIRECT
+    assert cfg["schedule"] == want
+    exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, fields, **opts)
+    assert_close(c.host(y), c.ref.mass(x), c.ref.mass_abs(x), what=f"variable P1, {lam} layers")
+
+
 def test_variable_mesh_refuses_owner_computes():
     c = _case(6, 10, "random", "P1", terrain=0.0)
     x = c.dev(np.ones(c.n))
