@@ -556,7 +556,8 @@ def batch_vs_plain(torch, exm, W, meshgen):
     """64 meshes (half P1, half DG0), 8 fields each: the batched forward +
     adjoint graph against the 1024 individual launches, same GPU, with the
     library's default launch and with the fastest single-launch schedule of
-    each space at these layer counts (GATHER for P1, PIPELINED for DG0)."""
+    each space at these layer counts (PIPELINED for both: ATOMIC 64-cell tiles
+    of 16-layer chunks for P1, 32-cell tiles for DG0)."""
     gen = torch.Generator(device="cuda")
     gen.manual_seed(meshgen.SEED_BATCH)
     t0 = time.time()
@@ -581,13 +582,14 @@ def batch_vs_plain(torch, exm, W, meshgen):
     log(f"batch setup {time.time() - t0:.1f}s")
     t0 = time.time()
     B = exm.Batch(items)
-    log(f"batch create (autotuned, captured) {time.time() - t0:.1f}s, units/blocks {B.info()}")
+    log(f"batch create (autotuned, captured) {time.time() - t0:.1f}s, units/blocks {B.info()}, P1 tiles {B.p1_tiles()}")
     t_batch, _ = timed(torch, B.launch, 5)
 
     def plain(best):
         for d in items:
             if best:
-                opts = dict(schedule=exm.EXM_SCHED_GATHER) if d["name"] == "P1" else \
+                opts = dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=64,
+                            chunk_layers=16) if d["name"] == "P1" else \
                     dict(schedule=exm.EXM_SCHED_PIPELINED, tile_cells=32, chunk_layers=16)
             else:
                 opts = {}
@@ -606,7 +608,7 @@ def batch_vs_plain(torch, exm, W, meshgen):
     res = {"meshes": len(items), "fields_per_mesh": 8, "batched_ms": round(t_batch, 3),
            "individual_launches_ms": round(t_plain, 3), "batched_speedup": round(t_plain / t_batch, 3),
            "individual_best_schedule_ms": round(t_best, 3), "batched_speedup_vs_best": round(t_best / t_batch, 3),
-           "batched_gbs": round(total_bytes / t_batch / 1e6, 1)}
+           "batched_gbs": round(total_bytes / t_batch / 1e6, 1), "p1_tiles": list(B.p1_tiles())}
     del items, B
     torch.cuda.empty_cache()
     return res

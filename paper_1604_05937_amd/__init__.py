@@ -341,7 +341,8 @@ class Batch:
     items: list of dicts with keys space, coord_space, coords, f, b and
     optionally w, g (lists of device FP64 tensors on `space`)."""
 
-    def __init__(self, items, cols_per_wave: int = 0, unit_cells: int = 0, stream=None):
+    def __init__(self, items, cols_per_wave: int = 0, unit_cells: int = 0, schedule: int = 0,
+                 chunk_layers: int = 0, stream=None):
         _abi.load()
         self._keep = []
         arr = (_abi.exm_batch_item * len(items))()
@@ -369,7 +370,8 @@ class Batch:
                                          ctypes.cast(g, P) if g is not None else None)
         self._keep.append(arr)
         self.items = items
-        opts = loop_opts(cols_per_wave=cols_per_wave, tile_cells=unit_cells)
+        opts = loop_opts(cols_per_wave=cols_per_wave, tile_cells=unit_cells, schedule=schedule,
+                         chunk_layers=chunk_layers)
         h = ctypes.c_void_p()
         _abi.exm_batch_create(len(items), arr, ctypes.byref(opts), stream_handle(stream), ctypes.byref(h))
         self.handle = h
@@ -382,6 +384,13 @@ class Batch:
         b = ctypes.c_int32()
         _abi.exm_batch_info(self.handle, ctypes.byref(n), ctypes.byref(b))
         return n.value, b.value
+
+    def p1_tiles(self):
+        """(tile_cells, chunk_layers) of the P1 items' owner tiles; (0, 0) on vertex units."""
+        t = ctypes.c_int32()
+        c = ctypes.c_int32()
+        _abi.exm_batch_p1_tiles(self.handle, ctypes.byref(t), ctypes.byref(c))
+        return t.value, c.value
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -11,19 +11,24 @@
 //
 // DG0 x DG0 units are base cells: the wavefronts walk their columns as in the
 // DIRECT schedule (cols_per_wave cells side by side, one layer per lane) and
-// write every field's output.  P1 x P1 units are base vertices, each owned by
-// one wavefront (the GATHER form of the loop): it walks the fan of cells
-// around its vertex column, 62 levels per step, for four fields at a time,
-// and writes every output DoF of its column once.  So no output needs
-// zeroing and no atomics are needed.  The two kinds of unit run in two
-// persistent kernels with a work list each (the P1 path's registers would
-// otherwise lower the occupancy of the DG0 path); the graph first resets
-// the two work counters with a one-thread kernel.
+// write every field's output.  P1 x P1 items run on owner tiles (the
+// PIPELINED tile walk, exm_pipe.hip): one workgroup per (item, tile) runs
+// every field and adjoint of its item through the tile's set-up once and
+// overwrites the outputs of the vertices it owns, and the tiles of all P1
+// items share one launch.  Where no owner tiling fits the kernel (or on
+// request), P1 units are base vertices instead, each owned by one wavefront
+// (the GATHER form of the loop): it walks the fan of cells around its vertex
+// column, 62 levels per step, for four fields at a time.  Either way every
+// output DoF is written once, so no output needs zeroing and no atomics are
+// needed.  Vertex units and cell units run in two persistent kernels with a
+// work list each (the P1 path's registers would otherwise lower the
+// occupancy of the DG0 path); the graph first resets the two work counters
+// with a one-thread kernel.
 #include <algorithm>
 #include <cstring>
 
 #include "exm_elements.hpp"
-#include "exm_internal.hpp"
+#include "exm_tiled.hpp"
 
 namespace exm {
 
@@ -237,7 +242,14 @@ struct exm_batch {
     DevBuf<int32_t> counter;
     DevBuf<const double*> ptrs;   // all field pointer arrays, item by item
     int64_t n_units = 0;
-    int64_t n_units_p1 = 0;       // the P1 units come first in `units`
+    int64_t n_units_p1 = 0;       // the P1 units come first in `units` (none with p1_tiles)
+    bool p1_tiles = false;        // P1 items on owner tiles (else vertex units)
+    DevBuf<BatchPipeItem> pitems; // p1_tiles: P1 items, largest columns first
+    DevBuf<int32_t> punits;       // p1_tiles: (item, tile) pairs in whole groups
+    DevBuf<const double*> pptrs;  // p1_tiles: per item, inputs (f, w) then outputs (b, g)
+    int32_t n_punits = 0;
+    int32_t pipe_tile = 0, pipe_S = 0;
+    size_t pipe_lds = 0;
     int32_t n_blocks = 0;
     int32_t unit_cells = 0;
     std::vector<int32_t> cpw;     // per item
@@ -269,10 +281,109 @@ int32_t batch_cpw(int32_t n_layers)
     return best;
 }
 
+// P1 items on owner tiles of about T cells with S-layer chunks: the item
+// table, the units and the pass pointers.  *fits stays false (and the batch
+// is left as it was) when some item's tiles exceed the kernel's limits or its
+// pointers are not 16-byte aligned.
+int32_t build_pipe(exm_batch* B, int32_t n_items, const exm_batch_item* items, int32_t T, int32_t S, bool* fits)
+{
+    constexpr size_t kLds = 160 * 1024;
+    *fits = false;
+    std::vector<int32_t> order;   // P1 items, largest columns first
+    for (int32_t m = 0; m < n_items; ++m)
+        if (B->p1[m]) order.push_back(m);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return items[a].space->mesh->n_layers > items[b].space->mesh->n_layers;
+    });
+    std::vector<const TilePlan*> plans;
+    size_t lds = 0;
+    for (int32_t m : order) {
+        const exm_batch_item& it = items[m];
+        uintptr_t al = (uintptr_t)it.coords;
+        for (int32_t k = 0; k < it.n_fields; ++k) al |= (uintptr_t)it.f[k] | (it.w ? (uintptr_t)it.w[k] : 0);
+        // the tile walk reads fields at the coordinate field's column starts
+        const bool same = !it.space->mixed && !it.coord_space->mixed && it.space->base[0] == it.coord_space->base[0] &&
+                          it.space->col_size[0] == it.coord_space->col_size[0];
+        if ((al & 15) != 0 || !same) return EXM_OK;
+        const TilePlan* plan = nullptr;
+        int32_t s = build_owner_plan(it.space->mesh, T, &plan);
+        if (s != EXM_OK) return s;
+        const size_t l = pipe_lds_bytes(EXM_K_MASS, EXM_ELEMENT_P1P1, plan->max_verts, 0, plan->max_cells, S);
+        if (plan->max_cells > pipe_max_tile_cells(EXM_K_MASS, EXM_ELEMENT_P1P1, S) ||
+            plan->max_verts > pipe_max_tile_verts(EXM_K_MASS, EXM_ELEMENT_P1P1, S) || l > kLds)
+            return EXM_OK;
+        lds = std::max(lds, l);
+        plans.push_back(plan);
+    }
+    std::vector<const double*> ptrs;
+    std::vector<size_t> pbase;
+    std::vector<int32_t> units;
+    for (size_t i = 0; i < order.size(); ++i) {
+        const exm_batch_item& it = items[order[i]];
+        pbase.push_back(ptrs.size());
+        for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.f[k]);
+        if (it.w)
+            for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.w[k]);
+        for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.b[k]);
+        if (it.g)
+            for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.g[k]);
+        for (int32_t k = 0; k < plans[i]->n_tiles; ++k) {
+            units.push_back((int32_t)i);
+            units.push_back(k);
+        }
+    }
+    while ((units.size() / 2) % kBatchPipeGroup) {
+        units.push_back(-1);
+        units.push_back(0);
+    }
+    EXM_CHECK(units.size() / 2 < (size_t)INT32_MAX, EXM_EOVERFLOW, "too many P1 tiles in the batch");
+    int32_t s = B->pptrs.upload(ptrs.data(), ptrs.size());
+    if (s != EXM_OK) return s;
+    std::vector<BatchPipeItem> dev(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+        const exm_batch_item& it = items[order[i]];
+        const TilePlan* plan = plans[i];
+        BatchPipeItem& d = dev[i];
+        std::memset(&d, 0, sizeof(d));
+        d.a.n_layers = it.space->mesh->n_layers;
+        d.a.off = 1;
+        d.a.xn = it.coord_space->n_dofs;
+        d.a.fn = it.space->n_dofs;
+        d.a.X = it.coords;
+        d.t.vstride = plan->max_verts;
+        d.t.tile_count = plan->n_tiles;
+        d.t.cell_off = plan->cell_off.p;
+        d.t.cells = plan->cells.p;
+        d.t.vert_off = plan->vert_off.p;
+        d.t.verts = plan->verts.p;
+        d.t.lcv = plan->local_cv.p;
+        d.t.owned = plan->owned.p;
+        d.t.xstart = it.coord_space->d_starts[0].p;
+        d.t.xbase = it.coord_space->base[0];
+        d.t.xstep = it.coord_space->col_size[0];   // closed-form column starts: one layer count per mesh
+        const int32_t np = it.w ? 2 * it.n_fields : it.n_fields;
+        d.src = B->pptrs.p + pbase[i];
+        d.dst = (double* const*)(B->pptrs.p + pbase[i] + np);
+        d.n_pass = np;
+    }
+    if ((s = B->pitems.upload(dev.data(), dev.size())) != EXM_OK) return s;
+    if ((s = B->punits.upload(units.data(), units.size())) != EXM_OK) return s;
+    B->n_punits = (int32_t)(units.size() / 2);
+    B->pipe_tile = T;
+    B->pipe_S = S;
+    B->pipe_lds = lds;
+    *fits = true;
+    return EXM_OK;
+}
+
 int32_t enqueue(exm_batch* B, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->counter.p);
     EXM_TRY_HIP(hipGetLastError());
+    if (B->p1_tiles) {
+        const int32_t st = launch_batch_pipe_p1(B->pitems.p, B->punits.p, B->n_punits, B->pipe_S, B->pipe_lds, s);
+        if (st != EXM_OK) return st;
+    }
     const int32_t n1 = (int32_t)B->n_units_p1, n0 = (int32_t)(B->n_units - B->n_units_p1);
     if (n1 > 0) {
         hipLaunchKernelGGL(k_batch<true>, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p, B->units.p, n1,
@@ -299,6 +410,7 @@ int32_t build_units(exm_batch* B, const std::vector<int32_t>& n_cells, const std
     for (size_t m = 0; m < n_cells.size(); ++m) {
         int64_t uc = std::max<int64_t>(1, unit_cells * ref_layers / std::max(1, n_layers[m]));
         uc = std::max<int64_t>(uc, B->cpw[m]);
+        if (B->p1[m] && B->p1_tiles) continue;   // on owner tiles
         std::vector<Unit>& units = lists[B->p1[m] ? 0 : 1];
         for (int64_t c = 0; c < n_cells[m]; c += uc)
             units.push_back(Unit{(int32_t)m, (int32_t)c, (int32_t)std::min<int64_t>(uc, n_cells[m] - c), 0});
@@ -416,6 +528,58 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
     EXM_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
     B->n_blocks = std::max(1, cus) * 8;
     hipStream_t hs = (hipStream_t)stream;
+    // P1 items on owner tiles unless GATHER is asked for: tile size and chunk
+    // length timed on these buffers (the first that fits when the unit size
+    // is given); vertex units where none fits
+    const bool any_p1 = std::find(B->p1.begin(), B->p1.end(), true) != B->p1.end();
+    if (any_p1 && !(opts && opts->schedule == EXM_SCHED_GATHER)) {
+        static const int32_t cand[][2] = {{64, 16}, {32, 16}, {64, 8}, {128, 8}};
+        const bool tune = !(opts && opts->tile_cells);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tune) {
+            EXM_TRY_HIP(hipEventCreate(&e0));
+            EXM_TRY_HIP(hipEventCreate(&e1));
+        }
+        auto time_one = [&](int32_t S, float* ms) -> int32_t {   // one warm launch, one timed
+            int32_t st = launch_batch_pipe_p1(B->pitems.p, B->punits.p, B->n_punits, S, B->pipe_lds, hs);
+            if (st != EXM_OK) return st;
+            EXM_TRY_HIP(hipEventRecord(e0, hs));
+            st = launch_batch_pipe_p1(B->pitems.p, B->punits.p, B->n_punits, S, B->pipe_lds, hs);
+            if (st != EXM_OK) return st;
+            EXM_TRY_HIP(hipEventRecord(e1, hs));
+            EXM_TRY_HIP(hipEventSynchronize(e1));
+            EXM_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+            return EXM_OK;
+        };
+        float best = 1e30f;
+        int32_t bt = 0, bs = 0;
+        for (const auto& c : cand) {
+            if (opts && opts->chunk_layers && opts->chunk_layers != c[1]) continue;
+            bool fits = false;
+            if ((s = build_pipe(B.get(), n_items, items, c[0], c[1], &fits)) != EXM_OK) break;
+            if (!fits) continue;
+            if (!tune) {
+                bt = c[0];
+                bs = c[1];
+                break;
+            }
+            float ms = 0.f;
+            if ((s = time_one(c[1], &ms)) != EXM_OK) break;
+            if (ms < best) {
+                best = ms;
+                bt = c[0];
+                bs = c[1];
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s != EXM_OK) return s;
+        if (bt) {
+            bool fits = false;
+            if ((s = build_pipe(B.get(), n_items, items, bt, bs, &fits)) != EXM_OK) return s;
+            B->p1_tiles = fits;
+        }
+    }
     if (opts && opts->tile_cells) {
         if ((s = build_units(B.get(), n_ent, n_layers, opts->tile_cells)) != EXM_OK) return s;
     } else {
@@ -479,6 +643,15 @@ int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_bloc
     EXM_CHECK(batch != nullptr, EXM_EINVAL, "batch is NULL");
     if (n_units) *n_units = batch->n_units;
     if (n_blocks) *n_blocks = batch->n_blocks;
+    return EXM_OK;
+}
+
+int32_t exm_batch_p1_tiles(const exm_batch* batch, int32_t* tile_cells, int32_t* chunk_layers)
+{
+    clear_error();
+    EXM_CHECK(batch != nullptr, EXM_EINVAL, "batch is NULL");
+    if (tile_cells) *tile_cells = batch->p1_tiles ? batch->pipe_tile : 0;
+    if (chunk_layers) *chunk_layers = batch->p1_tiles ? batch->pipe_S : 0;
     return EXM_OK;
 }
 

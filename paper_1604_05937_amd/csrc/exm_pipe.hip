@@ -115,22 +115,42 @@ constexpr int kPlain = 0, kAtomic = 1, kOwner = 2;
 // (t + 256 i) / S, (t + 256 i) % S of the chunk.
 constexpr int kItems = 4;
 
-// P1 x P1 mass action / RHS, y += M x (INC).  LDS: Z[2] and X[2] of
-// vstride * (S + 2) doubles (16-byte aligned vertex slots), the accumulator A
-// (same slots, levels l0 .. l0 + S of the chunk, the top one carried into the
-// next chunk), then tag and column start (ints) per tile vertex; (x, y) per
-// vertex only during set-up, inside A.  The old output values of a chunk are
-// loaded into registers while the chunk computes and added when it is written
-// back, during the next chunk.
-template <int S, int MODE>
-__global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const TileArgs t)
+// The (input, output) pairs a tile walk computes, one pass each, over one set
+// of tile tables: the single pair of a column-loop launch, or every field of
+// a batch item.
+struct OneField {
+    const double* x;
+    double* y;
+    __device__ int count() const { return 1; }
+    __device__ const double* src(int) const { return x; }
+    __device__ double* dst(int) const { return y; }
+};
+struct ManyFields {
+    const double* const* xs;
+    double* const* ys;
+    int n;
+    __device__ int count() const { return n; }
+    __device__ const double* src(int k) const { return xs[k]; }
+    __device__ double* dst(int k) const { return ys[k]; }
+};
+
+// P1 x P1 mass action / RHS of one tile, y += M x (INC), or y = M x
+// (OVERWRITE: owner tiles only, every vertex a tile writes is its own), for
+// every (x, y) pair of F in turn; the tile tables, 2A and the output items are
+// set up once.  LDS: Z[2] and X[2] of vstride * (S + 2) doubles (16-byte
+// aligned vertex slots), the accumulator A (same slots, levels l0 .. l0 + S of
+// the chunk, the top one carried into the next chunk), then tag and column
+// start (ints) per tile vertex; (x, y) per vertex only during set-up, inside
+// A.  The old output values of a chunk are loaded into registers while the
+// chunk computes and added when it is written back, during the next chunk.
+template <int S, int MODE, bool OVERWRITE, class Fields>
+__device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t, const int32_t tile, const Fields& F)
 {
+    static_assert(!OVERWRITE || MODE == kOwner, "overwriting needs one writer per vertex");
     constexpr bool ATOMIC = MODE == kAtomic;
     constexpr int P2 = S + 2, PP = P2 / 2, R = kLayers, G = S / R, CPP = kThreads / G;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
-    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
-    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
     const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
     const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
     const int32_t no = MODE == kOwner ? t.owned[tile] : nv;   // vertices this tile writes
@@ -144,8 +164,8 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
     int32_t* const Txst = Ttag + t.vstride;
     const int64_t n = a.xn;
     const double* const z = a.X + 2 * n;
-    const double* const x = a.in0;
-    double* const y = a.out0;
+    const double* x = F.src(0);   // the pass's input and output
+    double* y = F.dst(0);
     const int lam = a.n_layers;
 
     // this thread's cells (tile-local vertices), loaded before the tile's
@@ -208,7 +228,6 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
         iglb[i] = xs + jj;
     }
     lds_barrier();   // (x, y) are no longer needed: the accumulator takes their place
-    for (int i = tid; i < VS; i += kThreads) A[i] = 0.0;
     const int wave_e = tid & ~63;
 
     // copies: pair e of the tile's vertex slots (vertex e / PP), levels from
@@ -260,7 +279,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
             if (kind == 2)
                 unsafeAtomicAdd(y + g, s);
             else
-                y[g] = old[i] + s;
+                y[g] = OVERWRITE ? s : old[i] + s;
             if (carry && jj == 0) {
                 A[pos] = A[pos + S];
                 A[pos + S] = 0.0;
@@ -270,84 +289,122 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
         }
     };
 
-    // yA: old values of the next chunk to be written back (loading); yB: of
-    // the chunk written back next
-    double yA[kItems], yB[kItems];
     const int nch = (lam + S - 1) / S;
-    issue_copies(0);
-    load_old(0, yA);
-    for (int k = 0; k < nch; ++k) {
-        const int b = k & 1;
-        const int l0 = k * S;
-        const int nl = min(S, lam - l0);
-        wait_copies();
-        lds_barrier();
-        // 1. write chunk k-1 back and carry its top level into chunk k
-        if (k > 0) write_back(k - 1, yB, true);
-        // 2. old output values of chunk k+1, then the copies of chunk k+1
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) yB[i] = yA[i];
-        if (k + 1 < nch) load_old(k + 1, yA);
-        lds_barrier();
-        if (k + 1 < nch) issue_copies(k + 1);
-        // 3. element kernels of chunk k: R consecutive layers of one cell per
-        // thread; a level's sum over the thread's layers goes to LDS once
-        const double* const Zb = Zs + b * VS;
-        const double* const Xb = Xs + b * VS;
-#pragma unroll
-        for (int p = 0; p < kPasses; ++p) {
-            if (p >= npass) break;
-            if (!has[p] || r0 >= nl) continue;
-            int o[3];
-            double zc[3], xc[3], acc[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                o[q] = vb[p][q] + r0;
-                zc[q] = Zb[o[q]];
-                xc[q] = Xb[o[q]];
-                acc[q] = 0.0;
-            }
-            int r = 0;
-#pragma unroll
-            for (; r < R; ++r) {
-                if (r0 + r >= nl) break;
-                double zn[3], xn[3], h[3], yb[3], yt[3];
-#pragma unroll
+    for (int pass = 0; pass < F.count(); ++pass) {
+        if (pass > 0) {   // the previous pass's last write-back has read A
+            x = F.src(pass);
+            y = F.dst(pass);
+            lds_barrier();
+        }
+        for (int i = tid; i < VS; i += kThreads) A[i] = 0.0;
+        // yA: old values of the next chunk to be written back (loading); yB: of
+        // the chunk written back next
+        double yA[kItems], yB[kItems];
+        issue_copies(0);
+        if (!OVERWRITE) load_old(0, yA);
+        for (int k = 0; k < nch; ++k) {
+            const int b = k & 1;
+            const int l0 = k * S;
+            const int nl = min(S, lam - l0);
+            wait_copies();
+            lds_barrier();
+            // 1. write chunk k-1 back and carry its top level into chunk k
+            if (k > 0) write_back(k - 1, yB, true);
+            // 2. old output values of chunk k+1, then the copies of chunk k+1
+    #pragma unroll
+            for (int i = 0; i < kItems; ++i) yB[i] = yA[i];
+            if (!OVERWRITE && k + 1 < nch) load_old(k + 1, yA);
+            lds_barrier();
+            if (k + 1 < nch) issue_copies(k + 1);
+            // 3. element kernels of chunk k: R consecutive layers of one cell per
+            // thread; a level's sum over the thread's layers goes to LDS once
+            const double* const Zb = Zs + b * VS;
+            const double* const Xb = Xs + b * VS;
+    #pragma unroll
+            for (int p = 0; p < kPasses; ++p) {
+                if (p >= npass) break;
+                if (!has[p] || r0 >= nl) continue;
+                int o[3];
+                double zc[3], xc[3], acc[3];
+    #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    zn[q] = Zb[o[q] + r + 1];
-                    xn[q] = Xb[o[q] + r + 1];
-                    h[q] = zn[q] - zc[q];
+                    o[q] = vb[p][q] + r0;
+                    zc[q] = Zb[o[q]];
+                    xc[q] = Xb[o[q]];
+                    acc[q] = 0.0;
                 }
-                p1_mass(twoA[p], h, xc, xn, yb, yt);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q] + yb[q]);
-                    acc[q] = yt[q];
-                    zc[q] = zn[q];
-                    xc[q] = xn[q];
+                int r = 0;
+    #pragma unroll
+                for (; r < R; ++r) {
+                    if (r0 + r >= nl) break;
+                    double zn[3], xn[3], h[3], yb[3], yt[3];
+    #pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        zn[q] = Zb[o[q] + r + 1];
+                        xn[q] = Xb[o[q] + r + 1];
+                        h[q] = zn[q] - zc[q];
+                    }
+                    p1_mass(twoA[p], h, xc, xn, yb, yt);
+    #pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q] + yb[q]);
+                        acc[q] = yt[q];
+                        zc[q] = zn[q];
+                        xc[q] = xn[q];
+                    }
                 }
+    #pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q]);
             }
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q]);
+        }
+        // write back the last chunk, its top level included
+        lds_barrier();
+        {
+            const int k = nch - 1;
+            const int l0 = k * S, nl = lam - l0;
+            write_back(k, yB, false);
+            for (int v = tid; v < no; v += kThreads) {
+                const int32_t xs = Txst[v];
+                const double s = A[v * P2 + (xs & 1) + nl];
+                const int64_t g = (int64_t)xs + lam;
+                if (ATOMIC && vshared(Ttag[v]))
+                    unsafeAtomicAdd(y + g, s);
+                else if (OVERWRITE)
+                    y[g] = s;
+                else
+                    y[g] += s;
+            }
         }
     }
-    // write back the last chunk, its top level included
-    lds_barrier();
-    {
-        const int k = nch - 1;
-        const int l0 = k * S, nl = lam - l0;
-        write_back(k, yB, false);
-        for (int v = tid; v < no; v += kThreads) {
-            const int32_t xs = Txst[v];
-            const double s = A[v * P2 + (xs & 1) + nl];
-            const int64_t g = (int64_t)xs + lam;
-            if (ATOMIC && vshared(Ttag[v]))
-                unsafeAtomicAdd(y + g, s);
-            else
-                y[g] += s;
-        }
-    }
+}
+
+template <int S, int MODE>
+__global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const TileArgs t)
+{
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    pipe_p1_tile<S, MODE, false>(a, t, tile, OneField{a.in0, a.out0});
+}
+
+// The P1 x P1 items of a batch, b = M f and g = M w for every field: one
+// workgroup per (item, owner tile) unit runs every field of its item through
+// the tile walk, overwriting the outputs of the vertices the tile owns.  In
+// each group of kBatchPipeGroup units every XCD takes kBatchPipeGroup / 8
+// consecutive units (neighbouring tiles of one mesh, which share boundary
+// columns, meet in one L2), and the groups follow the list (largest columns
+// first); units with item -1 pad the list to whole groups.
+template <int S>
+__global__ void __launch_bounds__(kThreads) k_batch_pipe_p1(const BatchPipeItem* __restrict__ items,
+                                                            const int32_t* __restrict__ units)
+{
+    constexpr unsigned GX = kBatchPipeGroup / 8;
+    const unsigned b = blockIdx.x, r = b % kBatchPipeGroup;
+    const int32_t u = (int32_t)(b - r + (r & 7u) * GX + (r >> 3));
+    const int32_t item = units[2 * u];
+    if (item < 0) return;   // the whole workgroup
+    const BatchPipeItem& I = items[item];
+    pipe_p1_tile<S, kOwner, true>(I.a, I.t, units[2 * u + 1], ManyFields{I.src, I.dst, I.n_pass});
 }
 
 // P1 x P1 mass action / RHS (INC) on a mesh whose cell columns have layer
@@ -1959,6 +2016,21 @@ static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, siz
         hipLaunchKernelGGL((k_pipe_p1<S, kPlain>), grid, block, lds, s, a, t);
     else
         hipLaunchKernelGGL((k_pipe_p1<S, kAtomic>), grid, block, lds, s, a, t);
+}
+
+int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
+                             size_t lds, hipStream_t s)
+{
+    if (n_units <= 0) return EXM_OK;
+    EXM_CHECK(n_units % kBatchPipeGroup == 0, EXM_EINVAL, "batch units must fill groups of %d", kBatchPipeGroup);
+    const dim3 grid((unsigned)n_units), block(kThreads);
+    switch (S) {
+    case 8: hipLaunchKernelGGL(k_batch_pipe_p1<8>, grid, block, lds, s, items, units); break;
+    case 16: hipLaunchKernelGGL(k_batch_pipe_p1<16>, grid, block, lds, s, items, units); break;
+    default: return fail(EXM_ERANGE, "chunk_layers = %d: batched P1 tiles take 8 or 16", S);
+    }
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
 }
 
 template <int FORM, int S>

@@ -65,6 +65,21 @@ __device__ __forceinline__ int32_t column_start(const int32_t* __restrict__ tabl
     return step > 0 ? (int32_t)(base + (int64_t)id * step) : table[id];
 }
 
+// One P1 x P1 item of a batch on owner tiles: coordinates and layer count
+// (a), its owner tile plan (t), and the input and output of every pass
+// (forward fields, then adjoint ones).
+struct BatchPipeItem {
+    ColArgs a;
+    TileArgs t;
+    const double* const* src;
+    double* const* dst;
+    int32_t n_pass;
+};
+// Units (item, tile) of the batched P1 launch come in whole groups of this many.
+constexpr int32_t kBatchPipeGroup = 128;
+int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
+                             size_t lds, hipStream_t s);
+
 ColArgs col_args(const LoopLaunch& P);
 int32_t tiled_max_threads(int32_t kernel, int32_t element);
 size_t staged_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t S);

@@ -41,13 +41,25 @@ def _single(d, x):
     return y
 
 
-@pytest.mark.parametrize("cpw,unit", [(0, 0), (1, 8), (3, 64), (2, 1000)])
-def test_batch_matches_single_launches(cpw, unit):
-    say(f"batch cpw={cpw} unit={unit}")
+# P1 items on owner tiles (default: timed tile size; a fixed unit size takes
+# the first tiling that fits; chunk_layers fixes the chunk) or on vertex
+# units (GATHER)
+@pytest.mark.parametrize("cpw,unit,sched,chunk", [(0, 0, 0, 0), (1, 8, 0, 0), (3, 64, 0, 8), (2, 1000, 0, 16),
+                                                  (0, 0, "gather", 0), (3, 64, "gather", 0)])
+def test_batch_matches_single_launches(cpw, unit, sched, chunk):
+    say(f"batch cpw={cpw} unit={unit} sched={sched} chunk={chunk}")
     items, _ = _setup(6, 0.01, 3, True)
-    B = exm.Batch(items, cols_per_wave=cpw, unit_cells=unit)
+    schedule = exm.EXM_SCHED_GATHER if sched == "gather" else 0
+    B = exm.Batch(items, cols_per_wave=cpw, unit_cells=unit, schedule=schedule, chunk_layers=chunk)
     n_units, n_blocks = B.info()
-    assert n_units >= len(items) and n_blocks > 0
+    tiles = B.p1_tiles()
+    if sched == "gather":
+        assert tiles == (0, 0)
+        assert n_units >= len(items) and n_blocks > 0
+    else:
+        assert tiles[0] > 0 and tiles[1] == (chunk or tiles[1]) and tiles[1] in (8, 16)
+        n_dg0 = sum(d["space"].element != exm.EXM_ELEMENT_P1P1 for d in items)
+        assert n_units >= n_dg0 and n_blocks > 0
     ref = [([_single(d, f) for f in d["f"]], [_single(d, w) for w in d["w"]]) for d in items]
     torch.cuda.synchronize()
     for replay in range(3):
@@ -64,9 +76,10 @@ def test_batch_matches_single_launches(cpw, unit):
                 assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what=f"replay {replay}")
 
 
-def test_batch_matches_oracle():
+@pytest.mark.parametrize("sched", [0, "gather"])
+def test_batch_matches_oracle(sched):
     items, vcs = _setup(4, 0.004, 2, True, seed=9)
-    B = exm.Batch(items)
+    B = exm.Batch(items, schedule=exm.EXM_SCHED_GATHER if sched == "gather" else 0)
     B.launch()
     torch.cuda.synchronize()
     for d, vc in zip(items, vcs):
@@ -85,10 +98,12 @@ def test_batch_rejects_bad_items():
         exm.Batch(items)
 
 
-def test_batch_short_columns_odd_field_count():
-    # P1 columns shorter than one 62-level step, and 5 fields (a partial group
-    # of the P1 path's four fields per walk of the fan); no adjoint
-    say("batch short columns, 5 fields")
+@pytest.mark.parametrize("sched", [0, "gather"])
+def test_batch_short_columns_odd_field_count(sched):
+    # P1 columns shorter than one chunk, or than one 62-level step of the
+    # vertex units, and 5 fields (a partial group of the vertex units' four
+    # fields per walk of the fan); no adjoint
+    say(f"batch short columns, 5 fields, sched={sched}")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(21)
     items = []
@@ -101,7 +116,8 @@ def test_batch_short_columns_odd_field_count():
         rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
         items.append(dict(space=V, coord_space=Vx, coords=X, mesh=mesh,
                           f=[rnd() for _ in range(5)], b=[V.zeros() for _ in range(5)]))
-    B = exm.Batch(items)
+    B = exm.Batch(items, schedule=exm.EXM_SCHED_GATHER if sched == "gather" else 0)
+    assert (B.p1_tiles() == (0, 0)) == (sched == "gather")
     ref = [[_single(d, f) for f in d["f"]] for d in items]
     for d in items:
         for t in d["b"]:
