@@ -582,7 +582,7 @@ def batch_vs_plain(torch, exm, W, meshgen):
     log(f"batch setup {time.time() - t0:.1f}s")
     t0 = time.time()
     B = exm.Batch(items)
-    log(f"batch create (autotuned, captured) {time.time() - t0:.1f}s, units/blocks {B.info()}, P1 tiles {B.p1_tiles()}")
+    log(f"batch create (autotuned, captured) {time.time() - t0:.1f}s, units/blocks {B.info()}, tiles P1 {B.tiles('P1')} DG0 {B.tiles('DG0')}")
     t_batch, _ = timed(torch, B.launch, 5)
 
     def plain(best):
@@ -608,7 +608,8 @@ def batch_vs_plain(torch, exm, W, meshgen):
     res = {"meshes": len(items), "fields_per_mesh": 8, "batched_ms": round(t_batch, 3),
            "individual_launches_ms": round(t_plain, 3), "batched_speedup": round(t_plain / t_batch, 3),
            "individual_best_schedule_ms": round(t_best, 3), "batched_speedup_vs_best": round(t_best / t_batch, 3),
-           "batched_gbs": round(total_bytes / t_batch / 1e6, 1), "p1_tiles": list(B.p1_tiles())}
+           "batched_gbs": round(total_bytes / t_batch / 1e6, 1), "tiles_p1": list(B.tiles("P1")),
+           "tiles_dg0": list(B.tiles("DG0"))}
     del items, B
     torch.cuda.empty_cache()
     return res

@@ -349,10 +349,12 @@ int32_t exm_autotune_load(const char* path);
 /* ------------------------------------------------------------------------
  * Batched assembly: many extruded meshes, several fields per mesh, forward
  * residual (EXM_K_MASS) plus its adjoint, in two launches captured in a HIP
- * graph: the P1 x P1 items on owner tiles (the PIPELINED tile walk, one
- * workgroup per tile of any P1 item, every field of the item through one
- * tile set-up) and a persistent kernel over the DG0 x DG0 items.  The fields
- * of a mesh share its lists and geometry (end of Section 3.3).
+ * graph, one per kind of item: the P1 x P1 items on owner tiles and the
+ * DG0 x DG0 items on tiles (the PIPELINED tile walk, one workgroup per tile
+ * of any item of the kind, every field of the item through one tile
+ * set-up), or, where no tiling fits or on request, persistent kernels over
+ * work units of base vertices (P1) or base cells (DG0).  The fields of a
+ * mesh share its lists and geometry (end of Section 3.3).
  *
  * Item m: a space (EXM_ELEMENT_P1P1 or EXM_ELEMENT_DG0DG0) and its coordinate
  * field on the same mesh; n_fields inputs f[j] with outputs b[j] = M f[j], and
@@ -361,8 +363,8 @@ int32_t exm_autotune_load(const char* path);
  * Outputs are overwritten: every output DoF is written once (each P1 vertex
  * column by the one tile that owns it, or, on vertex units, by its own
  * wavefront as in EXM_SCHED_GATHER; no atomics), so the result does not
- * depend on the order in which work runs.  P1 fields and coordinates must be
- * 16-byte aligned for the tiles; otherwise P1 items run as vertex units.
+ * depend on the order in which work runs.  Tiles need 16-byte aligned
+ * coordinates (and P1 fields); otherwise the kind runs on work units.
  * The meshes, spaces and buffers must outlive the batch.
  */
 typedef struct {
@@ -377,22 +379,24 @@ typedef struct {
 } exm_batch_item;
 
 typedef struct exm_batch exm_batch;
-/* opts may be NULL; opts->cols_per_wave applies to every DG0 x DG0 item when
- * set, opts->tile_cells sets the work-unit size (base cells of DG0 items,
- * base vertices of P1 vertex units, scaled by 64 / layers; 0 = timed choice,
- * which also times the P1 tile sizes), opts->schedule = EXM_SCHED_GATHER
- * puts the P1 items on vertex units, opts->chunk_layers (8 or 16) fixes the
- * chunk length of the P1 tiles. */
+/* opts may be NULL; opts->schedule = EXM_SCHED_GATHER puts both kinds on
+ * work units; opts->cols_per_wave applies to DG0 work units when set;
+ * opts->tile_cells sets the work-unit size (base cells of DG0 units, base
+ * vertices of P1 units, scaled by 64 / layers) and makes each kind take the
+ * first tiling that fits; 0 = timed choice of unit size and tilings;
+ * opts->chunk_layers fixes the tiles' chunk length (8 or 16 for P1, 8, 16
+ * or 32 for DG0). */
 int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm_loop_opts* opts,
                          void* stream, exm_batch** out);
 /* Replay the captured graph on `stream`. */
 int32_t exm_batch_launch(exm_batch* batch, void* stream);
 /* Work units (cell or vertex groups) and persistent workgroups per kernel of the batch. */
 int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_blocks);
-/* Tile size (cells about which owner tiles grow) and chunk length of the P1
- * items' tiles; both 0 when the P1 items run as vertex units or there are
+/* Tile size (target cells per tile) and chunk length of the tiles of one
+ * kind of item (element EXM_ELEMENT_P1P1 or EXM_ELEMENT_DG0DG0, else
+ * EXM_EINVAL); both 0 when that kind runs on work units or the batch has
  * none.  Either pointer may be NULL. */
-int32_t exm_batch_p1_tiles(const exm_batch* batch, int32_t* tile_cells, int32_t* chunk_layers);
+int32_t exm_batch_tiles(const exm_batch* batch, int32_t element, int32_t* tile_cells, int32_t* chunk_layers);
 void exm_batch_destroy(exm_batch* batch);
 
 /* ------------------------------------------------------------------------

@@ -385,11 +385,13 @@ class Batch:
         _abi.exm_batch_info(self.handle, ctypes.byref(n), ctypes.byref(b))
         return n.value, b.value
 
-    def p1_tiles(self):
-        """(tile_cells, chunk_layers) of the P1 items' owner tiles; (0, 0) on vertex units."""
+    def tiles(self, name: str):
+        """(tile_cells, chunk_layers) of the tiles of the "P1" or "DG0" items;
+        (0, 0) when that kind runs on work units."""
         t = ctypes.c_int32()
         c = ctypes.c_int32()
-        _abi.exm_batch_p1_tiles(self.handle, ctypes.byref(t), ctypes.byref(c))
+        el = {"P1": EXM_ELEMENT_P1P1, "DG0": EXM_ELEMENT_DG0DG0}[name]
+        _abi.exm_batch_tiles(self.handle, el, ctypes.byref(t), ctypes.byref(c))
         return t.value, c.value
 
     def __del__(self):

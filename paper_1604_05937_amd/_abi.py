@@ -111,7 +111,7 @@ _PROTOS = {
                                    POINTER(c_void_p)]),
     "exm_batch_launch": (c_int32, [c_void_p, c_void_p]),
     "exm_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int32)]),
-    "exm_batch_p1_tiles": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "exm_batch_tiles": (c_int32, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "exm_batch_destroy": (None, [c_void_p]),
     "exm_space_create_mixed": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                                          POINTER(c_void_p)]),

@@ -228,6 +228,17 @@ __global__ void __launch_bounds__(256) k_batch(const BatchItemDev* __restrict__ 
     }
 }
 
+// The items of one kind on tiles (P1: owner tiles, DG0: tiles), one
+// workgroup per (item, tile), every field of the item through one set-up.
+struct TileSet {
+    bool on = false;
+    DevBuf<BatchPipeItem> items;   // the kind's items, largest columns first
+    DevBuf<int32_t> units;         // (item, tile) pairs in whole groups
+    DevBuf<const double*> ptrs;    // per item, inputs (f, w) then outputs (b, g)
+    int32_t n_units = 0, tile = 0, S = 0, cstride = 0;
+    size_t lds = 0;
+};
+
 }  // namespace exm
 
 using namespace exm;
@@ -242,14 +253,8 @@ struct exm_batch {
     DevBuf<int32_t> counter;
     DevBuf<const double*> ptrs;   // all field pointer arrays, item by item
     int64_t n_units = 0;
-    int64_t n_units_p1 = 0;       // the P1 units come first in `units` (none with p1_tiles)
-    bool p1_tiles = false;        // P1 items on owner tiles (else vertex units)
-    DevBuf<BatchPipeItem> pitems; // p1_tiles: P1 items, largest columns first
-    DevBuf<int32_t> punits;       // p1_tiles: (item, tile) pairs in whole groups
-    DevBuf<const double*> pptrs;  // p1_tiles: per item, inputs (f, w) then outputs (b, g)
-    int32_t n_punits = 0;
-    int32_t pipe_tile = 0, pipe_S = 0;
-    size_t pipe_lds = 0;
+    int64_t n_units_p1 = 0;       // the P1 units come first in `units` (none when P1 is on tiles)
+    TileSet tiles[2];             // P1 items, DG0 items on tiles (else work units)
     int32_t n_blocks = 0;
     int32_t unit_cells = 0;
     std::vector<int32_t> cpw;     // per item
@@ -281,38 +286,45 @@ int32_t batch_cpw(int32_t n_layers)
     return best;
 }
 
-// P1 items on owner tiles of about T cells with S-layer chunks: the item
-// table, the units and the pass pointers.  *fits stays false (and the batch
-// is left as it was) when some item's tiles exceed the kernel's limits or its
-// pointers are not 16-byte aligned.
-int32_t build_pipe(exm_batch* B, int32_t n_items, const exm_batch_item* items, int32_t T, int32_t S, bool* fits)
+// The items of one kind (P1: owner tiles, DG0: tiles) on tiles of about T
+// cells with S-layer chunks: the item table, the units and the pass
+// pointers.  *fits stays false (and the set is left as it was) when some
+// item's tiles exceed the kernel's limits or its pointers are not 16-byte
+// aligned where the tile walk copies 16 bytes at a time.
+int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item* items, int32_t T, int32_t S,
+                    bool* fits)
 {
     constexpr size_t kLds = 160 * 1024;
+    const int32_t element = p1 ? EXM_ELEMENT_P1P1 : EXM_ELEMENT_DG0DG0;
+    TileSet& ts = B->tiles[p1 ? 0 : 1];
     *fits = false;
-    std::vector<int32_t> order;   // P1 items, largest columns first
+    std::vector<int32_t> order;   // the kind's items, largest columns first
     for (int32_t m = 0; m < n_items; ++m)
-        if (B->p1[m]) order.push_back(m);
+        if (B->p1[m] == p1) order.push_back(m);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return items[a].space->mesh->n_layers > items[b].space->mesh->n_layers;
     });
     std::vector<const TilePlan*> plans;
     size_t lds = 0;
+    int32_t cstride = 0;
     for (int32_t m : order) {
         const exm_batch_item& it = items[m];
         uintptr_t al = (uintptr_t)it.coords;
-        for (int32_t k = 0; k < it.n_fields; ++k) al |= (uintptr_t)it.f[k] | (it.w ? (uintptr_t)it.w[k] : 0);
-        // the tile walk reads fields at the coordinate field's column starts
-        const bool same = !it.space->mixed && !it.coord_space->mixed && it.space->base[0] == it.coord_space->base[0] &&
-                          it.space->col_size[0] == it.coord_space->col_size[0];
+        if (p1)   // P1 fields are copied 16 bytes at a time too, at the coordinate field's column starts
+            for (int32_t k = 0; k < it.n_fields; ++k) al |= (uintptr_t)it.f[k] | (it.w ? (uintptr_t)it.w[k] : 0);
+        const bool same = !p1 || (!it.space->mixed && !it.coord_space->mixed &&
+                                  it.space->base[0] == it.coord_space->base[0] &&
+                                  it.space->col_size[0] == it.coord_space->col_size[0]);
         if ((al & 15) != 0 || !same) return EXM_OK;
         const TilePlan* plan = nullptr;
-        int32_t s = build_owner_plan(it.space->mesh, T, &plan);
+        int32_t s = p1 ? build_owner_plan(it.space->mesh, T, &plan) : build_tile_plan(it.space->mesh, T, &plan);
         if (s != EXM_OK) return s;
-        const size_t l = pipe_lds_bytes(EXM_K_MASS, EXM_ELEMENT_P1P1, plan->max_verts, 0, plan->max_cells, S);
-        if (plan->max_cells > pipe_max_tile_cells(EXM_K_MASS, EXM_ELEMENT_P1P1, S) ||
-            plan->max_verts > pipe_max_tile_verts(EXM_K_MASS, EXM_ELEMENT_P1P1, S) || l > kLds)
+        const size_t l = pipe_lds_bytes(EXM_K_MASS, element, plan->max_verts, 0, plan->max_cells, S);
+        if (plan->max_cells > pipe_max_tile_cells(EXM_K_MASS, element, S) ||
+            (p1 && plan->max_verts > pipe_max_tile_verts(EXM_K_MASS, element, S)) || l > kLds)
             return EXM_OK;
         lds = std::max(lds, l);
+        cstride = std::max(cstride, plan->max_cells);
         plans.push_back(plan);
     }
     std::vector<const double*> ptrs;
@@ -336,8 +348,8 @@ int32_t build_pipe(exm_batch* B, int32_t n_items, const exm_batch_item* items, i
         units.push_back(-1);
         units.push_back(0);
     }
-    EXM_CHECK(units.size() / 2 < (size_t)INT32_MAX, EXM_EOVERFLOW, "too many P1 tiles in the batch");
-    int32_t s = B->pptrs.upload(ptrs.data(), ptrs.size());
+    EXM_CHECK(units.size() / 2 < (size_t)INT32_MAX, EXM_EOVERFLOW, "too many tiles in the batch");
+    int32_t s = ts.ptrs.upload(ptrs.data(), ptrs.size());
     if (s != EXM_OK) return s;
     std::vector<BatchPipeItem> dev(order.size());
     for (size_t i = 0; i < order.size(); ++i) {
@@ -346,9 +358,11 @@ int32_t build_pipe(exm_batch* B, int32_t n_items, const exm_batch_item* items, i
         BatchPipeItem& d = dev[i];
         std::memset(&d, 0, sizeof(d));
         d.a.n_layers = it.space->mesh->n_layers;
-        d.a.off = 1;
+        d.a.off = it.space->offsets[0];
+        d.a.write = 1;
         d.a.xn = it.coord_space->n_dofs;
         d.a.fn = it.space->n_dofs;
+        d.a.fmap = it.space->d_map.p;
         d.a.X = it.coords;
         d.t.vstride = plan->max_verts;
         d.t.tile_count = plan->n_tiles;
@@ -357,33 +371,41 @@ int32_t build_pipe(exm_batch* B, int32_t n_items, const exm_batch_item* items, i
         d.t.vert_off = plan->vert_off.p;
         d.t.verts = plan->verts.p;
         d.t.lcv = plan->local_cv.p;
-        d.t.owned = plan->owned.p;
+        d.t.owned = p1 ? plan->owned.p : nullptr;
         d.t.xstart = it.coord_space->d_starts[0].p;
         d.t.xbase = it.coord_space->base[0];
         d.t.xstep = it.coord_space->col_size[0];   // closed-form column starts: one layer count per mesh
         const int32_t np = it.w ? 2 * it.n_fields : it.n_fields;
-        d.src = B->pptrs.p + pbase[i];
-        d.dst = (double* const*)(B->pptrs.p + pbase[i] + np);
+        d.src = ts.ptrs.p + pbase[i];
+        d.dst = (double* const*)(ts.ptrs.p + pbase[i] + np);
         d.n_pass = np;
     }
-    if ((s = B->pitems.upload(dev.data(), dev.size())) != EXM_OK) return s;
-    if ((s = B->punits.upload(units.data(), units.size())) != EXM_OK) return s;
-    B->n_punits = (int32_t)(units.size() / 2);
-    B->pipe_tile = T;
-    B->pipe_S = S;
-    B->pipe_lds = lds;
+    if ((s = ts.items.upload(dev.data(), dev.size())) != EXM_OK) return s;
+    if ((s = ts.units.upload(units.data(), units.size())) != EXM_OK) return s;
+    ts.n_units = (int32_t)(units.size() / 2);
+    ts.tile = T;
+    ts.S = S;
+    ts.cstride = cstride;
+    ts.lds = lds;
     *fits = true;
     return EXM_OK;
+}
+
+int32_t launch_tiles(const TileSet& ts, bool p1, hipStream_t s)
+{
+    return p1 ? launch_batch_pipe_p1(ts.items.p, ts.units.p, ts.n_units, ts.S, ts.lds, s)
+              : launch_batch_pipe_dg0(ts.items.p, ts.units.p, ts.n_units, ts.S, ts.cstride, ts.lds, s);
 }
 
 int32_t enqueue(exm_batch* B, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->counter.p);
     EXM_TRY_HIP(hipGetLastError());
-    if (B->p1_tiles) {
-        const int32_t st = launch_batch_pipe_p1(B->pitems.p, B->punits.p, B->n_punits, B->pipe_S, B->pipe_lds, s);
-        if (st != EXM_OK) return st;
-    }
+    for (int kind = 0; kind < 2; ++kind)
+        if (B->tiles[kind].on) {
+            const int32_t st = launch_tiles(B->tiles[kind], kind == 0, s);
+            if (st != EXM_OK) return st;
+        }
     const int32_t n1 = (int32_t)B->n_units_p1, n0 = (int32_t)(B->n_units - B->n_units_p1);
     if (n1 > 0) {
         hipLaunchKernelGGL(k_batch<true>, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p, B->units.p, n1,
@@ -410,7 +432,7 @@ int32_t build_units(exm_batch* B, const std::vector<int32_t>& n_cells, const std
     for (size_t m = 0; m < n_cells.size(); ++m) {
         int64_t uc = std::max<int64_t>(1, unit_cells * ref_layers / std::max(1, n_layers[m]));
         uc = std::max<int64_t>(uc, B->cpw[m]);
-        if (B->p1[m] && B->p1_tiles) continue;   // on owner tiles
+        if (B->tiles[B->p1[m] ? 0 : 1].on) continue;   // on tiles
         std::vector<Unit>& units = lists[B->p1[m] ? 0 : 1];
         for (int64_t c = 0; c < n_cells[m]; c += uc)
             units.push_back(Unit{(int32_t)m, (int32_t)c, (int32_t)std::min<int64_t>(uc, n_cells[m] - c), 0});
@@ -528,24 +550,26 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
     EXM_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
     B->n_blocks = std::max(1, cus) * 8;
     hipStream_t hs = (hipStream_t)stream;
-    // P1 items on owner tiles unless GATHER is asked for: tile size and chunk
+    // each kind on tiles unless GATHER is asked for: tile size and chunk
     // length timed on these buffers (the first that fits when the unit size
-    // is given); vertex units where none fits
-    const bool any_p1 = std::find(B->p1.begin(), B->p1.end(), true) != B->p1.end();
-    if (any_p1 && !(opts && opts->schedule == EXM_SCHED_GATHER)) {
-        static const int32_t cand[][2] = {{64, 16}, {32, 16}, {64, 8}, {128, 8}};
+    // is given); work units where none fits
+    for (int kind = 0; kind < 2 && !(opts && opts->schedule == EXM_SCHED_GATHER); ++kind) {
+        const bool p1 = kind == 0;
+        if (std::find(B->p1.begin(), B->p1.end(), p1) == B->p1.end()) continue;
+        static const int32_t cand_p1[][2] = {{64, 16}, {32, 16}, {64, 8}, {128, 8}};
+        static const int32_t cand_dg0[][2] = {{32, 32}, {32, 16}, {64, 16}, {64, 8}};
+        const auto& cand = p1 ? cand_p1 : cand_dg0;
         const bool tune = !(opts && opts->tile_cells);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tune) {
             EXM_TRY_HIP(hipEventCreate(&e0));
             EXM_TRY_HIP(hipEventCreate(&e1));
         }
-        auto time_one = [&](int32_t S, float* ms) -> int32_t {   // one warm launch, one timed
-            int32_t st = launch_batch_pipe_p1(B->pitems.p, B->punits.p, B->n_punits, S, B->pipe_lds, hs);
+        auto time_one = [&](float* ms) -> int32_t {   // one warm launch, one timed
+            int32_t st = launch_tiles(B->tiles[kind], p1, hs);
             if (st != EXM_OK) return st;
             EXM_TRY_HIP(hipEventRecord(e0, hs));
-            st = launch_batch_pipe_p1(B->pitems.p, B->punits.p, B->n_punits, S, B->pipe_lds, hs);
-            if (st != EXM_OK) return st;
+            if ((st = launch_tiles(B->tiles[kind], p1, hs)) != EXM_OK) return st;
             EXM_TRY_HIP(hipEventRecord(e1, hs));
             EXM_TRY_HIP(hipEventSynchronize(e1));
             EXM_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
@@ -556,7 +580,7 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         for (const auto& c : cand) {
             if (opts && opts->chunk_layers && opts->chunk_layers != c[1]) continue;
             bool fits = false;
-            if ((s = build_pipe(B.get(), n_items, items, c[0], c[1], &fits)) != EXM_OK) break;
+            if ((s = build_tiles(B.get(), p1, n_items, items, c[0], c[1], &fits)) != EXM_OK) break;
             if (!fits) continue;
             if (!tune) {
                 bt = c[0];
@@ -564,7 +588,7 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
                 break;
             }
             float ms = 0.f;
-            if ((s = time_one(c[1], &ms)) != EXM_OK) break;
+            if ((s = time_one(&ms)) != EXM_OK) break;
             if (ms < best) {
                 best = ms;
                 bt = c[0];
@@ -576,8 +600,8 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         if (s != EXM_OK) return s;
         if (bt) {
             bool fits = false;
-            if ((s = build_pipe(B.get(), n_items, items, bt, bs, &fits)) != EXM_OK) return s;
-            B->p1_tiles = fits;
+            if ((s = build_tiles(B.get(), p1, n_items, items, bt, bs, &fits)) != EXM_OK) return s;
+            B->tiles[kind].on = fits;
         }
     }
     if (opts && opts->tile_cells) {
@@ -646,12 +670,15 @@ int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_bloc
     return EXM_OK;
 }
 
-int32_t exm_batch_p1_tiles(const exm_batch* batch, int32_t* tile_cells, int32_t* chunk_layers)
+int32_t exm_batch_tiles(const exm_batch* batch, int32_t element, int32_t* tile_cells, int32_t* chunk_layers)
 {
     clear_error();
     EXM_CHECK(batch != nullptr, EXM_EINVAL, "batch is NULL");
-    if (tile_cells) *tile_cells = batch->p1_tiles ? batch->pipe_tile : 0;
-    if (chunk_layers) *chunk_layers = batch->p1_tiles ? batch->pipe_S : 0;
+    EXM_CHECK(element == EXM_ELEMENT_P1P1 || element == EXM_ELEMENT_DG0DG0, EXM_EINVAL,
+              "element must be EXM_ELEMENT_P1P1 or EXM_ELEMENT_DG0DG0");
+    const TileSet& ts = batch->tiles[element == EXM_ELEMENT_P1P1 ? 0 : 1];
+    if (tile_cells) *tile_cells = ts.on ? ts.tile : 0;
+    if (chunk_layers) *chunk_layers = ts.on ? ts.S : 0;
     return EXM_OK;
 }
 

@@ -311,7 +311,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
             // 1. write chunk k-1 back and carry its top level into chunk k
             if (k > 0) write_back(k - 1, yB, true);
             // 2. old output values of chunk k+1, then the copies of chunk k+1
-    #pragma unroll
+#pragma unroll
             for (int i = 0; i < kItems; ++i) yB[i] = yA[i];
             if (!OVERWRITE && k + 1 < nch) load_old(k + 1, yA);
             lds_barrier();
@@ -320,13 +320,13 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
             // thread; a level's sum over the thread's layers goes to LDS once
             const double* const Zb = Zs + b * VS;
             const double* const Xb = Xs + b * VS;
-    #pragma unroll
+#pragma unroll
             for (int p = 0; p < kPasses; ++p) {
                 if (p >= npass) break;
                 if (!has[p] || r0 >= nl) continue;
                 int o[3];
                 double zc[3], xc[3], acc[3];
-    #pragma unroll
+#pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     o[q] = vb[p][q] + r0;
                     zc[q] = Zb[o[q]];
@@ -334,18 +334,18 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
                     acc[q] = 0.0;
                 }
                 int r = 0;
-    #pragma unroll
+#pragma unroll
                 for (; r < R; ++r) {
                     if (r0 + r >= nl) break;
                     double zn[3], xn[3], h[3], yb[3], yt[3];
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         zn[q] = Zb[o[q] + r + 1];
                         xn[q] = Xb[o[q] + r + 1];
                         h[q] = zn[q] - zc[q];
                     }
                     p1_mass(twoA[p], h, xc, xn, yb, yt);
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q] + yb[q]);
                         acc[q] = yt[q];
@@ -353,7 +353,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
                         xc[q] = xn[q];
                     }
                 }
-    #pragma unroll
+#pragma unroll
                 for (int q = 0; q < 3; ++q)
                     if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q]);
             }
@@ -696,11 +696,12 @@ __global__ void __launch_bounds__(kThreads, (S & (S - 1)) == 0 ? 4 : 3) k_pipe_p
 // form one contiguous column of NDOF * lambda values that no other cell
 // touches: each thread takes one layer of a few cells, loads that layer's
 // field values into registers one chunk ahead (coalesced along the column),
-// and stores its results while the next chunk computes.  LDS: Z[2] of
+// and stores its results while the next chunk computes.  Every (x, y) pair
+// of F runs in turn over one set-up of the tile.  LDS: Z[2] of
 // vstride * (S + 2) doubles, then x, y (doubles) and the column start (int)
 // per tile vertex.
-template <int NH, int NV, int S, int NP, int NT>
-__global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
+template <int NH, int NV, int S, int NP, int NT, class Fields>
+__device__ __forceinline__ void pipe_dg_tile(const ColArgs& a, const TileArgs& t, const int32_t tile, const Fields& F)
 {
     constexpr int NDOF = NH * NV;
     using C = Chunk<S>;
@@ -708,8 +709,6 @@ __global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColA
     constexpr int CPP = NT >> LS;   // one layer per thread
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
-    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
-    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
     const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
     const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
     const int VS = t.vstride * P2;
@@ -719,8 +718,8 @@ __global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColA
     int32_t* const Txst = (int32_t*)(Ty + t.vstride);
     const int64_t n = a.xn;
     const double* const z = a.X + 2 * n;
-    const double* const f = a.in0;
-    double* const out = a.out0;
+    const double* f = F.src(0);   // the pass's input and output
+    double* out = F.dst(0);
     const int lam = a.n_layers;
 
     // this thread's cells (tile-local vertices, field column), loaded before
@@ -829,59 +828,91 @@ __global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColA
     };
 
     const int nch = (lam + S - 1) / S;
-    issue_copies(0);
-    load_field(0, fcur);
-    for (int k = 0; k < nch; ++k) {
-        const int b = k & 1;
-        const int l0 = k * S;
-        const int nl = min(S, lam - l0);
-        wait_copies();
-        lds_barrier();
-        if (k + 1 < nch) {
-            issue_copies(k + 1);
-            load_field(k + 1, fnext);
+    for (int pass = 0; pass < F.count(); ++pass) {
+        if (pass > 0) {   // every thread is done with the previous pass's buffers
+            f = F.src(pass);
+            out = F.dst(pass);
+            prev_l0 = -1;
+            lds_barrier();
         }
-        store_results();
-        const double* const Zb = Zs + b * VS;
+        issue_copies(0);
+        load_field(0, fcur);
+        for (int k = 0; k < nch; ++k) {
+            const int b = k & 1;
+            const int l0 = k * S;
+            const int nl = min(S, lam - l0);
+            wait_copies();
+            lds_barrier();
+            if (k + 1 < nch) {
+                issue_copies(k + 1);
+                load_field(k + 1, fnext);
+            }
+            store_results();
+            const double* const Zb = Zs + b * VS;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (p >= npass) break;
-            if (!has[p] || j >= nl) continue;
-            double h[3];
+            for (int p = 0; p < NP; ++p) {
+                if (p >= npass) break;
+                if (!has[p] || j >= nl) continue;
+                double h[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) h[q] = Zb[vb[p][q] + j + 1] - Zb[vb[p][q] + j];
-            if constexpr (NDOF == 1) {
-                res[p][0] = dg0_mass(twoA[p], h, fcur[p][0]);
-            } else if constexpr (NH != 3 || NV != 2) {   // DG0 x DG1, DG1 x DG0: node (a, b) at NV a + b
-                double x[NH][NV], y[NH][NV];
+                for (int q = 0; q < 3; ++q) h[q] = Zb[vb[p][q] + j + 1] - Zb[vb[p][q] + j];
+                if constexpr (NDOF == 1) {
+                    res[p][0] = dg0_mass(twoA[p], h, fcur[p][0]);
+                } else if constexpr (NH != 3 || NV != 2) {   // DG0 x DG1, DG1 x DG0: node (a, b) at NV a + b
+                    double x[NH][NV], y[NH][NV];
 #pragma unroll
-                for (int q = 0; q < NDOF; ++q) x[q / NV][q % NV] = fcur[p][q];
-                tp_mass<NH, NV>(twoA[p], h, x, y);
+                    for (int q = 0; q < NDOF; ++q) x[q / NV][q % NV] = fcur[p][q];
+                    tp_mass<NH, NV>(twoA[p], h, x, y);
 #pragma unroll
-                for (int q = 0; q < NDOF; ++q) res[p][q] = y[q / NV][q % NV];
-            } else {
-                double xb[3], xt[3], yb[3], yt[3];
+                    for (int q = 0; q < NDOF; ++q) res[p][q] = y[q / NV][q % NV];
+                } else {
+                    double xb[3], xt[3], yb[3], yt[3];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    xb[q] = fcur[p][2 * q];
-                    xt[q] = fcur[p][2 * q + 1];
-                }
-                p1_mass(twoA[p], h, xb, xt, yb, yt);
+                    for (int q = 0; q < 3; ++q) {
+                        xb[q] = fcur[p][2 * q];
+                        xt[q] = fcur[p][2 * q + 1];
+                    }
+                    p1_mass(twoA[p], h, xb, xt, yb, yt);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    res[p][2 * q] = yb[q];
-                    res[p][2 * q + 1] = yt[q];
+                    for (int q = 0; q < 3; ++q) {
+                        res[p][2 * q] = yb[q];
+                        res[p][2 * q + 1] = yt[q];
+                    }
                 }
             }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int q = 0; q < NDOF; ++q) fcur[p][q] = fnext[p][q];
+            prev_l0 = l0;
+            prev_nl = nl;
         }
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int q = 0; q < NDOF; ++q) fcur[p][q] = fnext[p][q];
-        prev_l0 = l0;
-        prev_nl = nl;
+        store_results();
     }
-    store_results();
+}
+
+template <int NH, int NV, int S, int NP, int NT>
+__global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
+{
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    pipe_dg_tile<NH, NV, S, NP, NT>(a, t, tile, OneField{a.in0, a.out0});
+}
+
+// The DG0 x DG0 items of a batch: one workgroup per (item, tile) unit runs
+// every field of its item through the DG tile walk (outputs written), units
+// in groups as for k_batch_pipe_p1.
+template <int S, int NP, int NT>
+__global__ void __launch_bounds__(NT, 7) k_batch_pipe_dg0(const BatchPipeItem* __restrict__ items,
+                                                          const int32_t* __restrict__ units)
+{
+    constexpr unsigned GX = kBatchPipeGroup / 8;
+    const unsigned b = blockIdx.x, r = b % kBatchPipeGroup;
+    const int32_t u = (int32_t)(b - r + (r & 7u) * GX + (r >> 3));
+    const int32_t item = units[2 * u];
+    if (item < 0) return;   // the whole workgroup
+    const BatchPipeItem& I = items[item];
+    pipe_dg_tile<1, 1, S, NP, NT>(I.a, I.t, units[2 * u + 1], ManyFields{I.src, I.dst, I.n_pass});
 }
 
 // Mass action / RHS on the spaces discontinuous horizontally and continuous
@@ -2016,6 +2047,39 @@ static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, siz
         hipLaunchKernelGGL((k_pipe_p1<S, kPlain>), grid, block, lds, s, a, t);
     else
         hipLaunchKernelGGL((k_pipe_p1<S, kAtomic>), grid, block, lds, s, a, t);
+}
+
+int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
+                              int32_t cstride, size_t lds, hipStream_t s)
+{
+    if (n_units <= 0) return EXM_OK;
+    EXM_CHECK(n_units % kBatchPipeGroup == 0, EXM_EINVAL, "batch units must fill groups of %d", kBatchPipeGroup);
+    const dim3 grid((unsigned)n_units);
+    // tiles beyond two cells per thread of a 256-thread workgroup take 512 threads
+    const bool wide = cstride > 2 * kThreads / S;
+    switch (S) {
+    case 8:
+        if (wide)
+            hipLaunchKernelGGL((k_batch_pipe_dg0<8, 2, 512>), grid, dim3(512), lds, s, items, units);
+        else
+            hipLaunchKernelGGL((k_batch_pipe_dg0<8, 2, 256>), grid, dim3(256), lds, s, items, units);
+        break;
+    case 16:
+        if (wide)
+            hipLaunchKernelGGL((k_batch_pipe_dg0<16, 2, 512>), grid, dim3(512), lds, s, items, units);
+        else
+            hipLaunchKernelGGL((k_batch_pipe_dg0<16, 2, 256>), grid, dim3(256), lds, s, items, units);
+        break;
+    case 32:
+        if (wide)
+            hipLaunchKernelGGL((k_batch_pipe_dg0<32, 2, 512>), grid, dim3(512), lds, s, items, units);
+        else
+            hipLaunchKernelGGL((k_batch_pipe_dg0<32, 2, 256>), grid, dim3(256), lds, s, items, units);
+        break;
+    default: return fail(EXM_ERANGE, "chunk_layers = %d: batched DG0 tiles take 8, 16 or 32", S);
+    }
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
 }
 
 int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,

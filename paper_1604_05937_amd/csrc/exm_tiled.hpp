@@ -65,9 +65,9 @@ __device__ __forceinline__ int32_t column_start(const int32_t* __restrict__ tabl
     return step > 0 ? (int32_t)(base + (int64_t)id * step) : table[id];
 }
 
-// One P1 x P1 item of a batch on owner tiles: coordinates and layer count
-// (a), its owner tile plan (t), and the input and output of every pass
-// (forward fields, then adjoint ones).
+// One item of a batch on tiles (P1 x P1: owner tiles; DG0 x DG0): lists,
+// coordinates and layer count (a), its tile plan (t), and the input and
+// output of every pass (forward fields, then adjoint ones).
 struct BatchPipeItem {
     ColArgs a;
     TileArgs t;
@@ -79,6 +79,9 @@ struct BatchPipeItem {
 constexpr int32_t kBatchPipeGroup = 128;
 int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
                              size_t lds, hipStream_t s);
+// cstride: the largest tile of the DG0 items (cells).
+int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
+                              int32_t cstride, size_t lds, hipStream_t s);
 
 ColArgs col_args(const LoopLaunch& P);
 int32_t tiled_max_threads(int32_t kernel, int32_t element);

@@ -45,7 +45,7 @@ def test_mesh_validation_errors():
     assert lib.exm_par_loop(99, None, 0, None, None, None) == _abi.EXM_EINVAL
     assert lib.exm_stream_triad(None, None, None, 1.0, 10, 256, 0, None) == _abi.EXM_EINVAL
     assert lib.exm_batch_create(0, None, None, None, ctypes.byref(h)) == _abi.EXM_EINVAL
-    assert lib.exm_batch_p1_tiles(None, None, None) == _abi.EXM_EINVAL
+    assert lib.exm_batch_tiles(None, _abi.EXM_ELEMENT_P1P1, None, None) == _abi.EXM_EINVAL
 
 
 def test_python_wrappers_raise():

@@ -41,25 +41,27 @@ def _single(d, x):
     return y
 
 
-# P1 items on owner tiles (default: timed tile size; a fixed unit size takes
-# the first tiling that fits; chunk_layers fixes the chunk) or on vertex
-# units (GATHER)
+# items on tiles (default: timed tile sizes; a fixed unit size takes the
+# first tiling that fits; chunk_layers fixes the chunk: 8 and 16 tile both
+# kinds, 32 only DG0) or on work units (GATHER)
 @pytest.mark.parametrize("cpw,unit,sched,chunk", [(0, 0, 0, 0), (1, 8, 0, 0), (3, 64, 0, 8), (2, 1000, 0, 16),
-                                                  (0, 0, "gather", 0), (3, 64, "gather", 0)])
+                                                  (0, 0, 0, 32), (0, 0, "gather", 0), (3, 64, "gather", 0)])
 def test_batch_matches_single_launches(cpw, unit, sched, chunk):
     say(f"batch cpw={cpw} unit={unit} sched={sched} chunk={chunk}")
     items, _ = _setup(6, 0.01, 3, True)
     schedule = exm.EXM_SCHED_GATHER if sched == "gather" else 0
     B = exm.Batch(items, cols_per_wave=cpw, unit_cells=unit, schedule=schedule, chunk_layers=chunk)
     n_units, n_blocks = B.info()
-    tiles = B.p1_tiles()
+    t1, t0 = B.tiles("P1"), B.tiles("DG0")
     if sched == "gather":
-        assert tiles == (0, 0)
+        assert t1 == (0, 0) and t0 == (0, 0)
         assert n_units >= len(items) and n_blocks > 0
     else:
-        assert tiles[0] > 0 and tiles[1] == (chunk or tiles[1]) and tiles[1] in (8, 16)
-        n_dg0 = sum(d["space"].element != exm.EXM_ELEMENT_P1P1 for d in items)
-        assert n_units >= n_dg0 and n_blocks > 0
+        if chunk == 32:   # P1 tiles take 8 or 16: the P1 items run on vertex units
+            assert t1 == (0, 0) and n_units > 0
+        else:
+            assert t1[0] > 0 and t1[1] == (chunk or t1[1]) and t1[1] in (8, 16)
+        assert t0[0] > 0 and t0[1] == (chunk or t0[1]) and t0[1] in (8, 16, 32)
     ref = [([_single(d, f) for f in d["f"]], [_single(d, w) for w in d["w"]]) for d in items]
     torch.cuda.synchronize()
     for replay in range(3):
@@ -80,6 +82,8 @@ def test_batch_matches_single_launches(cpw, unit, sched, chunk):
 def test_batch_matches_oracle(sched):
     items, vcs = _setup(4, 0.004, 2, True, seed=9)
     B = exm.Batch(items, schedule=exm.EXM_SCHED_GATHER if sched == "gather" else 0)
+    with pytest.raises(exm.ExmError):
+        exm._abi.exm_batch_tiles(B.handle, exm.EXM_ELEMENT_P2P2, None, None)
     B.launch()
     torch.cuda.synchronize()
     for d, vc in zip(items, vcs):
@@ -117,7 +121,8 @@ def test_batch_short_columns_odd_field_count(sched):
         items.append(dict(space=V, coord_space=Vx, coords=X, mesh=mesh,
                           f=[rnd() for _ in range(5)], b=[V.zeros() for _ in range(5)]))
     B = exm.Batch(items, schedule=exm.EXM_SCHED_GATHER if sched == "gather" else 0)
-    assert (B.p1_tiles() == (0, 0)) == (sched == "gather")
+    assert (B.tiles("P1") == (0, 0)) == (sched == "gather")
+    assert (B.tiles("DG0") == (0, 0)) == (sched == "gather")
     ref = [[_single(d, f) for f in d["f"]] for d in items]
     for d in items:
         for t in d["b"]:
