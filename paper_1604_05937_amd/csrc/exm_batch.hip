@@ -246,6 +246,8 @@ using namespace exm;
 struct exm_batch {
     int device = 0;
     hipStream_t cap = nullptr;
+    hipStream_t side = nullptr;     // the DG0 items' branch
+    hipEvent_t fork = nullptr, join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     DevBuf<BatchItemDev> items;
@@ -263,6 +265,9 @@ struct exm_batch {
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -397,27 +402,38 @@ int32_t launch_tiles(const TileSet& ts, bool p1, hipStream_t s)
               : launch_batch_pipe_dg0(ts.items.p, ts.units.p, ts.n_units, ts.S, ts.cstride, ts.lds, s);
 }
 
-int32_t enqueue(exm_batch* B, hipStream_t s)
+// The items of one kind: on tiles, or the persistent kernel over its units.
+int32_t enqueue_kind(exm_batch* B, bool p1, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->counter.p);
-    EXM_TRY_HIP(hipGetLastError());
-    for (int kind = 0; kind < 2; ++kind)
-        if (B->tiles[kind].on) {
-            const int32_t st = launch_tiles(B->tiles[kind], kind == 0, s);
-            if (st != EXM_OK) return st;
-        }
+    if (B->tiles[p1 ? 0 : 1].on) return launch_tiles(B->tiles[p1 ? 0 : 1], p1, s);
     const int32_t n1 = (int32_t)B->n_units_p1, n0 = (int32_t)(B->n_units - B->n_units_p1);
-    if (n1 > 0) {
+    if (p1 && n1 > 0) {
         hipLaunchKernelGGL(k_batch<true>, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p, B->units.p, n1,
                            B->counter.p);
         EXM_TRY_HIP(hipGetLastError());
     }
-    if (n0 > 0) {
+    if (!p1 && n0 > 0) {
         hipLaunchKernelGGL(k_batch<false>, dim3((unsigned)B->n_blocks), dim3(256), 0, s, B->items.p,
                            B->units.p + n1, n0, B->counter.p + 1);
         EXM_TRY_HIP(hipGetLastError());
     }
     return EXM_OK;
+}
+
+// The counter reset, then the P1 items on s and the DG0 items on a side
+// stream forked after the reset and joined at the end (two branches of the
+// graph), so that each kind's tail overlaps the other's work.
+int32_t enqueue(exm_batch* B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, B->counter.p);
+    EXM_TRY_HIP(hipGetLastError());
+    EXM_TRY_HIP(hipEventRecord(B->fork, s));
+    EXM_TRY_HIP(hipStreamWaitEvent(B->side, B->fork, 0));
+    int32_t st = enqueue_kind(B, true, s);
+    if (st == EXM_OK) st = enqueue_kind(B, false, B->side);
+    EXM_TRY_HIP(hipEventRecord(B->join, B->side));   // joined whatever happened, so a capture stays whole
+    EXM_TRY_HIP(hipStreamWaitEvent(s, B->join, 0));
+    return st;
 }
 
 int32_t build_units(exm_batch* B, const std::vector<int32_t>& n_cells, const std::vector<int32_t>& n_layers,
@@ -550,6 +566,9 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
     EXM_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->device));
     B->n_blocks = std::max(1, cus) * 8;
     hipStream_t hs = (hipStream_t)stream;
+    EXM_TRY_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    EXM_TRY_HIP(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
+    EXM_TRY_HIP(hipEventCreateWithFlags(&B->join, hipEventDisableTiming));
     // each kind on tiles unless GATHER is asked for: tile size and chunk
     // length timed on these buffers (the first that fits when the unit size
     // is given); work units where none fits
