@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) k_batch(const BatchItemDev* __restrict__ 
 struct TileSet {
     bool on = false;
     DevBuf<BatchPipeItem> items;   // the kind's items, largest columns first
-    DevBuf<int32_t> units;         // (item, tile) pairs in whole groups
+    DevBuf<int32_t> units;         // (item, tile) pairs
     DevBuf<const double*> ptrs;    // per item, inputs (f, w) then outputs (b, g)
     int32_t n_units = 0, tile = 0, S = 0, cstride = 0;
     size_t lds = 0;
@@ -348,10 +348,6 @@ int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item
             units.push_back((int32_t)i);
             units.push_back(k);
         }
-    }
-    while ((units.size() / 2) % kBatchPipeGroup) {
-        units.push_back(-1);
-        units.push_back(0);
     }
     EXM_CHECK(units.size() / 2 < (size_t)INT32_MAX, EXM_EOVERFLOW, "too many tiles in the batch");
     int32_t s = ts.ptrs.upload(ptrs.data(), ptrs.size());

@@ -388,22 +388,15 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const Til
 }
 
 // The P1 x P1 items of a batch, b = M f and g = M w for every field: one
-// workgroup per (item, owner tile) unit runs every field of its item through
-// the tile walk, overwriting the outputs of the vertices the tile owns.  In
-// each group of kBatchPipeGroup units every XCD takes kBatchPipeGroup / 8
-// consecutive units (neighbouring tiles of one mesh, which share boundary
-// columns, meet in one L2), and the groups follow the list (largest columns
-// first); units with item -1 pad the list to whole groups.
+// workgroup per (item, owner tile) unit, in list order (largest columns
+// first), runs every field of its item through the tile walk, overwriting the
+// outputs of the vertices the tile owns.
 template <int S>
 __global__ void __launch_bounds__(kThreads) k_batch_pipe_p1(const BatchPipeItem* __restrict__ items,
                                                             const int32_t* __restrict__ units)
 {
-    constexpr unsigned GX = kBatchPipeGroup / 8;
-    const unsigned b = blockIdx.x, r = b % kBatchPipeGroup;
-    const int32_t u = (int32_t)(b - r + (r & 7u) * GX + (r >> 3));
-    const int32_t item = units[2 * u];
-    if (item < 0) return;   // the whole workgroup
-    const BatchPipeItem& I = items[item];
+    const int32_t u = (int32_t)blockIdx.x;
+    const BatchPipeItem& I = items[units[2 * u]];
     pipe_p1_tile<S, kOwner, true>(I.a, I.t, units[2 * u + 1], ManyFields{I.src, I.dst, I.n_pass});
 }
 
@@ -899,19 +892,15 @@ __global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColA
     pipe_dg_tile<NH, NV, S, NP, NT>(a, t, tile, OneField{a.in0, a.out0});
 }
 
-// The DG0 x DG0 items of a batch: one workgroup per (item, tile) unit runs
-// every field of its item through the DG tile walk (outputs written), units
-// in groups as for k_batch_pipe_p1.
+// The DG0 x DG0 items of a batch: one workgroup per (item, tile) unit, in
+// list order, runs every field of its item through the DG tile walk (outputs
+// written).
 template <int S, int NP, int NT>
 __global__ void __launch_bounds__(NT, 7) k_batch_pipe_dg0(const BatchPipeItem* __restrict__ items,
                                                           const int32_t* __restrict__ units)
 {
-    constexpr unsigned GX = kBatchPipeGroup / 8;
-    const unsigned b = blockIdx.x, r = b % kBatchPipeGroup;
-    const int32_t u = (int32_t)(b - r + (r & 7u) * GX + (r >> 3));
-    const int32_t item = units[2 * u];
-    if (item < 0) return;   // the whole workgroup
-    const BatchPipeItem& I = items[item];
+    const int32_t u = (int32_t)blockIdx.x;
+    const BatchPipeItem& I = items[units[2 * u]];
     pipe_dg_tile<1, 1, S, NP, NT>(I.a, I.t, units[2 * u + 1], ManyFields{I.src, I.dst, I.n_pass});
 }
 
@@ -2053,7 +2042,6 @@ int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, 
                               int32_t cstride, size_t lds, hipStream_t s)
 {
     if (n_units <= 0) return EXM_OK;
-    EXM_CHECK(n_units % kBatchPipeGroup == 0, EXM_EINVAL, "batch units must fill groups of %d", kBatchPipeGroup);
     const dim3 grid((unsigned)n_units);
     // tiles beyond two cells per thread of a 256-thread workgroup take 512 threads
     const bool wide = cstride > 2 * kThreads / S;
@@ -2086,7 +2074,6 @@ int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, i
                              size_t lds, hipStream_t s)
 {
     if (n_units <= 0) return EXM_OK;
-    EXM_CHECK(n_units % kBatchPipeGroup == 0, EXM_EINVAL, "batch units must fill groups of %d", kBatchPipeGroup);
     const dim3 grid((unsigned)n_units), block(kThreads);
     switch (S) {
     case 8: hipLaunchKernelGGL(k_batch_pipe_p1<8>, grid, block, lds, s, items, units); break;

@@ -75,8 +75,6 @@ struct BatchPipeItem {
     double* const* dst;
     int32_t n_pass;
 };
-// Units (item, tile) of the batched P1 launch come in whole groups of this many.
-constexpr int32_t kBatchPipeGroup = 128;
 int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
                              size_t lds, hipStream_t s);
 // cstride: the largest tile of the DG0 items (cells).
