@@ -134,3 +134,27 @@ def test_batch_short_columns_odd_field_count(sched):
         for got, want in zip(d["b"], rb):
             g_, w_ = got.cpu().numpy(), want.cpu().numpy()
             assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what="short columns")
+
+
+def test_batch_misaligned_p1_field_runs_on_units():
+    # the tile walk copies P1 fields 16 bytes at a time: a field that starts
+    # 8 bytes into its allocation puts the P1 items on vertex units, the DG0
+    # items stay on tiles, and every output still matches
+    say("batch, misaligned P1 field")
+    items, _ = _setup(4, 0.004, 2, True, seed=13)
+    p1 = next(d for d in items if d["space"].element == exm.EXM_ELEMENT_P1P1)
+    n = p1["space"].n_dofs
+    store = torch.empty(n + 1, dtype=torch.float64, device="cuda")
+    store[1:] = p1["f"][0]
+    p1["f"][0] = store[1:]
+    assert p1["f"][0].data_ptr() % 16 == 8
+    B = exm.Batch(items)
+    assert B.tiles("P1") == (0, 0) and B.tiles("DG0") != (0, 0)
+    # references from aligned copies (the single launch may take a tiled schedule)
+    ref = [([_single(d, f.clone()) for f in d["f"]], [_single(d, w) for w in d["w"]]) for d in items]
+    B.launch()
+    torch.cuda.synchronize()
+    for d, (rb, rg) in zip(items, ref):
+        for got, want in zip(d["b"] + d["g"], rb + rg):
+            g_, w_ = got.cpu().numpy(), want.cpu().numpy()
+            assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what="misaligned P1 field")
