@@ -26,6 +26,8 @@
 // with a one-thread kernel.
 #include <algorithm>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "exm_elements.hpp"
 #include "exm_tiled.hpp"
@@ -571,9 +573,10 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
     for (int kind = 0; kind < 2 && !(opts && opts->schedule == EXM_SCHED_GATHER); ++kind) {
         const bool p1 = kind == 0;
         if (std::find(B->p1.begin(), B->p1.end(), p1) == B->p1.end()) continue;
-        static const int32_t cand_p1[][2] = {{64, 16}, {32, 16}, {64, 8}, {128, 8}};
-        static const int32_t cand_dg0[][2] = {{32, 32}, {32, 16}, {64, 16}, {64, 8}};
-        const auto& cand = p1 ? cand_p1 : cand_dg0;
+        // (tile cells, chunk layers)
+        const std::vector<std::pair<int32_t, int32_t>> cand =
+            p1 ? std::vector<std::pair<int32_t, int32_t>>{{64, 16}, {32, 16}, {64, 8}, {128, 8}}
+               : std::vector<std::pair<int32_t, int32_t>>{{32, 32}, {32, 16}, {64, 16}, {64, 8}};
         const bool tune = !(opts && opts->tile_cells);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tune) {
@@ -593,21 +596,21 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         float best = 1e30f;
         int32_t bt = 0, bs = 0;
         for (const auto& c : cand) {
-            if (opts && opts->chunk_layers && opts->chunk_layers != c[1]) continue;
+            if (opts && opts->chunk_layers && opts->chunk_layers != c.second) continue;
             bool fits = false;
-            if ((s = build_tiles(B.get(), p1, n_items, items, c[0], c[1], &fits)) != EXM_OK) break;
+            if ((s = build_tiles(B.get(), p1, n_items, items, c.first, c.second, &fits)) != EXM_OK) break;
             if (!fits) continue;
             if (!tune) {
-                bt = c[0];
-                bs = c[1];
+                bt = c.first;
+                bs = c.second;
                 break;
             }
             float ms = 0.f;
             if ((s = time_one(&ms)) != EXM_OK) break;
             if (ms < best) {
                 best = ms;
-                bt = c[0];
-                bs = c[1];
+                bt = c.first;
+                bs = c.second;
             }
         }
         if (e0) (void)hipEventDestroy(e0);
