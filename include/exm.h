@@ -390,7 +390,8 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
                          void* stream, exm_batch** out);
 /* Replay the captured graph on `stream`. */
 int32_t exm_batch_launch(exm_batch* batch, void* stream);
-/* Work units (cell or vertex groups) and persistent workgroups per kernel of the batch. */
+/* Work units (cell or vertex groups) of the kinds that run on work units
+ * (0 when both run on tiles) and persistent workgroups per work-unit kernel. */
 int32_t exm_batch_info(const exm_batch* batch, int64_t* n_units, int32_t* n_blocks);
 /* Tile size (target cells per tile) and chunk length of the tiles of one
  * kind of item (element EXM_ELEMENT_P1P1 or EXM_ELEMENT_DG0DG0, else

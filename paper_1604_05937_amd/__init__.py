@@ -336,7 +336,8 @@ class Matrix:
 
 class Batch:
     """exm_batch: forward residual b = M f and adjoint g = M w for several
-    fields on many extruded meshes, one persistent kernel in a HIP graph.
+    fields on many extruded meshes, one launch per kind of item (P1, DG0) in
+    a HIP graph.
 
     items: list of dicts with keys space, coord_space, coords, f, b and
     optionally w, g (lists of device FP64 tensors on `space`)."""

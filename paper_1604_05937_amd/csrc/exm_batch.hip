@@ -1,29 +1,32 @@
 // Batched assembly: many extruded meshes, several fields per mesh, forward
-// residual b = M f plus its adjoint g = M^T w = M w, in one persistent kernel
-// launch captured in a HIP graph.
+// residual b = M f plus its adjoint g = M^T w = M w, in two launches (one
+// per kind of item, on parallel branches) captured in a HIP graph.  All
+// fields of a mesh live on one space and share its explicit lists (end of
+// Section 3.3 of the paper), so the geometry read for a column serves
+// several fields.
 //
-// Work list.  Every mesh is cut into units of consecutive base entities; a
-// fixed grid of workgroups pulls units from a device counter until the list is
-// exhausted, so meshes of very different sizes and layer counts balance across
-// the GPU.  All fields of a mesh live on one space and share its explicit
-// lists (end of Section 3.3 of the paper), so the geometry read for a column
-// serves several fields.
+// Tiles.  Each kind normally runs on the PIPELINED tile walk (exm_pipe.hip):
+// one workgroup per (item, tile) of every item of the kind runs all fields
+// and adjoints of its item through one set-up of the tile.  P1 x P1 items use
+// owner tiles, each overwriting the outputs of the vertices it owns; a
+// DG0 x DG0 output belongs to one cell.  Tile size and chunk length are timed
+// at creation.
 //
-// DG0 x DG0 units are base cells: the wavefronts walk their columns as in the
-// DIRECT schedule (cols_per_wave cells side by side, one layer per lane) and
-// write every field's output.  P1 x P1 items run on owner tiles (the
-// PIPELINED tile walk, exm_pipe.hip): one workgroup per (item, tile) runs
-// every field and adjoint of its item through the tile's set-up once and
-// overwrites the outputs of the vertices it owns, and the tiles of all P1
-// items share one launch.  Where no owner tiling fits the kernel (or on
-// request), P1 units are base vertices instead, each owned by one wavefront
-// (the GATHER form of the loop): it walks the fan of cells around its vertex
-// column, 62 levels per step, for four fields at a time.  Either way every
-// output DoF is written once, so no output needs zeroing and no atomics are
-// needed.  Vertex units and cell units run in two persistent kernels with a
-// work list each (the P1 path's registers would otherwise lower the
+// Work units.  Where no tiling fits a kind (or on request), its items are cut
+// into units of consecutive base entities, and a fixed grid of workgroups
+// pulls units from a device counter until the list is exhausted, so meshes
+// of very different sizes and layer counts balance across the GPU.  DG0
+// units are base cells, their columns walked as in the DIRECT schedule
+// (cols_per_wave cells side by side, one layer per lane).  P1 units are base
+// vertices, each owned by one wavefront (the GATHER form of the loop) that
+// walks the fan of cells around its vertex column, 62 levels per step, four
+// fields at a time.  Vertex and cell units run in two persistent kernels
+// with a work list each (the P1 path's registers would otherwise lower the
 // occupancy of the DG0 path); the graph first resets the two work counters
 // with a one-thread kernel.
+//
+// Either way every output DoF is written once, so no output needs zeroing and
+// no atomics are needed.
 #include <algorithm>
 #include <cstring>
 #include <utility>
@@ -651,7 +654,7 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         if (s != EXM_OK) return s;
         if ((s = build_units(B.get(), n_ent, n_layers, best_uc)) != EXM_OK) return s;
     }
-    // capture the counter reset and the persistent kernel into a graph on a private stream
+    // capture the counter reset and the two kinds' launches into a graph on a private stream
     EXM_TRY_HIP(hipStreamSynchronize(hs));
     EXM_TRY_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     EXM_TRY_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
