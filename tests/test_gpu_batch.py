@@ -158,3 +158,35 @@ def test_batch_misaligned_p1_field_runs_on_units():
         for got, want in zip(d["b"] + d["g"], rb + rg):
             g_, w_ = got.cpu().numpy(), want.cpu().numpy()
             assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what="misaligned P1 field")
+
+
+@pytest.mark.parametrize("kind", ["P1", "DG0"])
+def test_batch_single_kind(kind):
+    # a batch of one kind of item: the other branch of the graph is empty
+    say(f"batch of {kind} items only")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(31)
+    items = []
+    for n, lam in ((7, 9), (5, 33)):
+        base = meshgen.tri_square(n)
+        mesh = exm.Mesh(base, lam)
+        Vx = exm.Space(mesh, "P1")
+        V = exm.Space(mesh, kind) if kind != "P1" else Vx
+        X = exm.coordinate_field(Vx, meshgen.extruded_vertex_coords(base, lam))
+        rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        items.append(dict(space=V, coord_space=Vx, coords=X, mesh=mesh, f=[rnd() for _ in range(3)],
+                          b=[V.zeros() for _ in range(3)], w=[rnd() for _ in range(3)], g=[V.zeros() for _ in range(3)]))
+    B = exm.Batch(items)
+    assert B.tiles(kind) != (0, 0) and B.tiles("DG0" if kind == "P1" else "P1") == (0, 0)
+    ref = [([_single(d, f) for f in d["f"]], [_single(d, w) for w in d["w"]]) for d in items]
+    for replay in range(2):
+        for d in items:
+            for t in d["b"] + d["g"]:
+                t.fill_(5.0)
+        torch.cuda.synchronize()
+        B.launch()
+        torch.cuda.synchronize()
+        for d, (rb, rg) in zip(items, ref):
+            for got, want in zip(d["b"] + d["g"], rb + rg):
+                g_, w_ = got.cpu().numpy(), want.cpu().numpy()
+                assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what=f"{kind} only, replay {replay}")
