@@ -417,12 +417,13 @@ def secondary(torch, exm, W, meshgen):
             V = ev.space(name)
             x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
             y = V.zeros()
-            # the DIRECT shapes (the tuner's candidates on such a mesh), and GATHER and PIPELINED for P1
+            # the DIRECT shapes (the tuner's candidates on such a mesh), GATHER for P1, PIPELINED for both
             shapes = direct_shapes(exm, name)
             if name == "P1":
                 shapes += [dict(schedule=exm.EXM_SCHED_GATHER, waves_per_block=w) for w in (1, 2, 4)]
-                shapes += [dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=t, chunk_layers=c)
-                           for (t, c) in ((64, 16), (48, 16), (96, 8))]
+            pipe_shapes = ((64, 16), (48, 16), (96, 8)) if name == "P1" else ((32, 32), (64, 16), (32, 16))
+            shapes += [dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=t, chunk_layers=c)
+                       for (t, c) in pipe_shapes]
             b = W.mass_bytes(ev, name)
             for label, group in (("direct", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_DIRECT]),
                                  ("gather", [c for c in shapes if c["schedule"] == exm.EXM_SCHED_GATHER]),

@@ -251,9 +251,10 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
     }
     if (!d.race) d.race = EXM_RACE_ATOMIC;
     if (!d.schedule) d.schedule = EXM_SCHED_DIRECT;
-    // the P1xP1 mass action has a PIPELINED kernel for columns of different heights
+    // the P1xP1 and DG0xDG0 mass actions have PIPELINED kernels for columns of different heights
     const bool var_pipe = d.schedule == EXM_SCHED_PIPELINED && P.kernel == EXM_K_MASS &&
-                          P.element == EXM_ELEMENT_P1P1 && mesh->n_layers <= 2000;
+                          (P.element == EXM_ELEMENT_P1P1 || P.element == EXM_ELEMENT_DG0DG0) &&
+                          mesh->n_layers <= 2000;
     EXM_CHECK(!mesh->variable || d.race != EXM_RACE_OWNER || d.schedule == EXM_SCHED_GATHER, EXM_EUNSUPPORTED,
               "owner-computes tiles need columns of one height; this mesh has a layer range per column");
     if (mesh->variable && !(d.schedule == EXM_SCHED_GATHER && gather_supported(P.kernel, P.element)) && !var_pipe) {
@@ -674,13 +675,18 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     const int32_t races[2] = {EXM_RACE_ATOMIC, EXM_RACE_COLOUR};
     for (int r = 0; r < (cg ? 2 : 1); ++r) {
         for (int32_t c : {1, 2, 3, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 4, 0, 0});
-        if (iterset->variable) {   // columns of different heights run DIRECT, GATHER or (P1 mass) PIPELINED
+        if (iterset->variable) {   // columns of different heights run DIRECT, GATHER or (P1, DG0 mass) PIPELINED
             for (int32_t c : {1, 2, 4}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_DIRECT, c, 2, 0, 0});
             if (r == 0 && gather_supported(P.kernel, P.element))
                 for (int32_t w : {1, 2, 4}) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_GATHER, 0, w, 0, 0});
             if (P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1)
                 for (int32_t tc : {32, 48, 64})
                     for (int32_t S : {8, 16}) cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
+            if (P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_DG0DG0)
+                for (int32_t tc : {32, 64})
+                    for (int32_t S : {16, 32})
+                        if (tc <= pipe_max_tile_cells(P.kernel, P.element, S))
+                            cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
             continue;
         }
         if (r == 0 && gather_supported(P.kernel, P.element))

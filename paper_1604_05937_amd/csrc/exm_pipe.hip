@@ -884,6 +884,182 @@ __device__ __forceinline__ void pipe_dg_tile(const ColArgs& a, const TileArgs& t
     }
 }
 
+// DG0 x DG0 mass action / RHS on a mesh whose cell columns have layer ranges
+// of their own (cell c: layers lo_c .. lo_c + lam_c - 1, its list entry the
+// DoF of layer lo_c; vertex v: levels lo_v .. hi_v).  The DG0 walk of
+// pipe_dg_tile on absolute levels, with the level window and the clipped z
+// copies of k_pipe_p1_var: a tile walks the chunks of S layers from an even
+// level at or below its lowest vertex level up to its top level, and a
+// thread's layer of a cell is loaded, evaluated and stored only inside the
+// cell's range.  LDS as pipe_dg_tile, plus the level range (ints) per tile
+// vertex.
+template <int S, int NP, int NT>
+__global__ void __launch_bounds__(NT, 7) k_pipe_dg0_var(const ColArgs a, const TileArgs t)
+{
+    using C = Chunk<S>;
+    constexpr int P2 = C::P2, PP = C::PP, LS = C::LS;
+    constexpr int CPP = NT >> LS;   // one layer per thread
+    extern __shared__ double lds[];
+    __shared__ int32_t s_lo, s_hi;   // the tile's level window
+    const int tid = threadIdx.x;
+    const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
+    const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
+    const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
+    const int32_t vb0 = t.vert_off[tile], nv = t.vert_off[tile + 1] - vb0;
+    const int VS = t.vstride * P2;
+    double* const Zs = lds;
+    double* const Tx = Zs + 2 * VS;
+    double* const Ty = Tx + t.vstride;
+    int32_t* const Txst = (int32_t*)(Ty + t.vstride);
+    int32_t* const Tlo = Txst + t.vstride;
+    int32_t* const Thi = Tlo + t.vstride;
+    const int64_t n = a.xn;
+    const double* const z = a.X + 2 * n;
+    const double* const f = a.in0;
+    double* const out = a.out0;
+
+    // this thread's cells: tile-local vertices, list entry, layer range
+    bool has[NP];
+    int lvq[NP][3];
+    int32_t d0[NP];
+    int crng[NP];   // first layer | (last layer + 1) << 16
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int c = (tid >> LS) + p * CPP;
+        has[p] = c < nc;
+        const int32_t cell = has[p] ? t.cells[cb + c] : 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
+        d0[p] = has[p] ? a.fmap[cell] : 0;
+        const int cl = has[p] ? t.clo[cell] : 0;
+        crng[p] = has[p] ? cl | ((cl + a.cell_lam[cell]) << 16) : 0;
+    }
+    if (tid == 0) {
+        s_lo = INT32_MAX;
+        s_hi = -1;
+    }
+    lds_barrier();
+    int my_lo = INT32_MAX, my_hi = -1;
+    for (int v = tid; v < nv; v += NT) {
+        const int32_t id = vid(t.verts[vb0 + v]);
+        const int32_t xs = t.xstart[id];
+        const int32_t lo = t.vlo[id], hi = t.vhi[id];
+        Txst[v] = xs;
+        Tlo[v] = lo;
+        Thi[v] = hi;
+        Tx[v] = a.X[xs];
+        Ty[v] = a.X[n + xs];
+        my_lo = min(my_lo, lo);
+        my_hi = max(my_hi, hi);
+    }
+    if (my_hi >= 0) {
+        atomicMin(&s_lo, my_lo);
+        atomicMax(&s_hi, my_hi);
+    }
+    lds_barrier();
+    const int L0b = __builtin_amdgcn_readfirstlane(s_lo & ~1);   // even: each vertex's parity is fixed
+    const int thi = __builtin_amdgcn_readfirstlane(s_hi);        // the tile's top level
+
+    const int j = tid & (S - 1);
+    int vb[NP][3];
+    double twoA[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        double xq[3], yq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int lv = lvq[p][q];
+            vb[p][q] = lv * P2 + ((Txst[lv] - Tlo[lv] + L0b) & 1);
+            xq[q] = Tx[lv];
+            yq[q] = Ty[lv];
+        }
+        twoA[p] = has[p] ? twice_area(xq, yq) : 0.0;
+    }
+    const int npass = (nc + CPP - 1) / CPP;
+    const int wave_e = tid & ~63;
+
+    // z of chunk k: levels L0 .. L0 + nl of every tile vertex, inside its column
+    auto issue_copies = [&](int k) {
+        const int L0 = L0b + k * S;
+        const int nl = min(S, thi - L0);
+        const int b = k & 1;
+        for (int e0 = 0; e0 < nv * PP; e0 += NT) {
+            const int e = e0 + tid;
+            const int v = e / PP, w = e - (e / PP) * PP;
+            if (v >= nv) continue;
+            const int32_t xs = Txst[v];
+            const int lo = Tlo[v], hi = Thi[v];
+            const int sv = (xs - lo + L0b) & 1;
+            const int La = L0 - sv + 2 * w;   // the pair's levels La, La + 1
+            if (2 * w - sv > nl || La + 1 < lo || La > hi) continue;
+            const int64_t g = (int64_t)xs + (La - lo);
+            if (La >= lo && La + 1 <= hi)
+                copy16(z + g, Zs + b * VS + 2 * (e0 + wave_e));
+            else if (La >= lo)   // only the pair's first level is in the column
+                Zs[b * VS + 2 * e] = z[g];
+            else                 // only its second
+                Zs[b * VS + 2 * e + 1] = z[g + 1];
+        }
+    };
+    // this thread's layer L0 + j of cell p, if the cell has it
+    auto inside = [&](int p, int L) { return L >= (crng[p] & 0xffff) && L < (crng[p] >> 16); };
+    auto load_field = [&](int k, double (&fv)[NP]) {
+        const int L0 = L0b + k * S;
+        const int nl = min(S, thi - L0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            fv[p] = 0.0;
+            if (p >= npass || !has[p] || j >= nl || !inside(p, L0 + j)) continue;
+            fv[p] = f[(int64_t)d0[p] + (L0 + j - (crng[p] & 0xffff))];
+        }
+    };
+
+    double fcur[NP], fnext[NP], res[NP];
+    int prev_L0 = -1, prev_nl = 0;
+    auto store_results = [&]() {
+        if (prev_L0 < 0) return;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass || !has[p] || j >= prev_nl || !inside(p, prev_L0 + j)) continue;
+            double* dst = out + (int64_t)d0[p] + (prev_L0 + j - (crng[p] & 0xffff));
+            if (a.write)
+                *dst = res[p];
+            else
+                *dst += res[p];
+        }
+    };
+
+    const int nch = (thi - L0b + S - 1) / S;
+    issue_copies(0);
+    load_field(0, fcur);
+    for (int k = 0; k < nch; ++k) {
+        const int b = k & 1;
+        const int L0 = L0b + k * S;
+        const int nl = min(S, thi - L0);
+        wait_copies();
+        lds_barrier();
+        if (k + 1 < nch) {
+            issue_copies(k + 1);
+            load_field(k + 1, fnext);
+        }
+        store_results();
+        const double* const Zb = Zs + b * VS;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p >= npass || !has[p] || j >= nl || !inside(p, L0 + j)) continue;
+            double h[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) h[q] = Zb[vb[p][q] + j + 1] - Zb[vb[p][q] + j];
+            res[p] = dg0_mass(twoA[p], h, fcur[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) fcur[p] = fnext[p];
+        prev_L0 = L0;
+        prev_nl = nl;
+    }
+    store_results();
+}
+
 template <int NH, int NV, int S, int NP, int NT>
 __global__ void __launch_bounds__(NT, NH * NV == 1 ? 8 : 4) k_pipe_dg(const ColArgs a, const TileArgs t)
 {
@@ -1983,8 +2159,8 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
         return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 3 * es * (2 * S + 2)) +
                sizeof(int32_t) * (2 * es + (size_t)vstride);
     }
-    if (dg_element(element))
-        return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + sizeof(int32_t) * vstride;
+    if (dg_element(element))   // column start, and a level range for columns of different heights
+        return sizeof(double) * (2 * (size_t)vstride * (S + 2) + 2 * (size_t)vstride) + 3 * sizeof(int32_t) * vstride;
     return 0;
 }
 
@@ -2151,6 +2327,14 @@ template <int S>
 static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds,
                            hipStream_t s)
 {
+    if (t.vlo) {   // columns of different heights (DG0 x DG0 only)
+        const dim3 grid((unsigned)t.tile_count);
+        if (cstride > 2 * kThreads / S)
+            hipLaunchKernelGGL((k_pipe_dg0_var<S, 2, 512>), grid, dim3(512), lds, s, a, t);
+        else
+            hipLaunchKernelGGL((k_pipe_dg0_var<S, 2, 256>), grid, dim3(kThreads), lds, s, a, t);
+        return;
+    }
     switch (element) {
     case EXM_ELEMENT_DG0P1: launch_pipe_dgv_e<1, S>(a, t, cstride, lds, s); break;
     case EXM_ELEMENT_DG1P1: launch_pipe_dgv_e<3, S>(a, t, cstride, lds, s); break;
@@ -2205,6 +2389,8 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
         return EXM_OK;
     }
     if (P.element != EXM_ELEMENT_P1P1) {
+        EXM_CHECK(!t.vlo || P.element == EXM_ELEMENT_DG0DG0, EXM_EUNSUPPORTED,
+                  "the PIPELINED schedule runs P1xP1 and DG0xDG0 on columns of different heights");
         switch (S) {
         case 8: launch_pipe_dg<8>(P.element, a, t, cstride, lds, s); break;
         case 16: launch_pipe_dg<16>(P.element, a, t, cstride, lds, s); break;

@@ -147,6 +147,33 @@ def test_variable_pipelined_p1(n, lam, kind, race, tile, chunk):
     assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what="variable pipelined P1")
 
 
+@pytest.mark.parametrize("n,lam,kind", SHAPES + [(6, 62, "random"), (5, 33, "bathymetry")])
+@pytest.mark.parametrize("acc", ["write", "inc"])
+@pytest.mark.parametrize("tile,chunk", [(32, 32), (64, 16), (29, 8), (8, 32)])
+def test_variable_pipelined_dg0(n, lam, kind, acc, tile, chunk):
+    # the DG0 tile pipeline on absolute levels: z copies inside each vertex's
+    # column, each cell's layers loaded, evaluated and stored only inside its
+    # range; outputs start non-zero, so WRITE must overwrite and INC add
+    say(f"variable pipelined DG0 n={n} lam={lam} {kind} {acc} tile={tile} chunk={chunk}")
+    c = _case(n, lam, kind, "DG0", order="random" if tile == 29 else "rcm")
+    x = meshgen.uniform_values(c.n, seed=meshgen.SEED_FIELD)
+    y0 = meshgen.uniform_values(c.n, seed=71)
+    xd, y = c.dev(x), c.dev(y0)
+    mode = exm.EXM_WRITE if acc == "write" else exm.EXM_INC
+    fields = [(xd, c.V, exm.EXM_READ), (y, c.V, mode)]
+    opts = dict(schedule=exm.EXM_SCHED_PIPELINED, race=exm.EXM_RACE_ATOMIC, tile_cells=tile, chunk_layers=chunk)
+    try:
+        cfg = exm.par_loop_config(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, fields, **opts)
+        exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, fields, **opts)
+    except exm.ExmError as e:
+        # tiles too large for the chunk length are refused before any launch
+        assert e.status == exm._abi.EXM_EUNSUPPORTED and "PIPELINED" in str(e), str(e)
+        return
+    assert cfg["schedule"] == exm.EXM_SCHED_PIPELINED
+    want = c.ref.mass(x) + (y0 if acc == "inc" else 0.0)
+    assert_close(c.host(y), want, c.ref.mass_abs(x) + np.abs(y0), what=f"variable pipelined DG0 {acc}")
+
+
 @pytest.mark.parametrize("lam,expect", [(2000, "pipelined"), (2001, "direct")])
 def test_variable_pipelined_layer_limit(lam, expect):
     # the pipelined kernel keeps chunk indices in 8 bits: up to 2000 layers it
