@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_1604_05937_amd as exm
 from paper_1604_05937_amd import meshgen
 from tests.gpu_common import Case, assert_close, say
@@ -120,7 +121,7 @@ def _ranges_columns(starts, lo, hi, ids, extra):
 @pytest.mark.parametrize("space", ["P1", "DG0"])
 def test_variable_layers_config2_sampled(space):
     # columns of different heights (bathymetry ranges) on 512 x 512 x 100,
-    # in the launch the autotuner picks (DIRECT): sampled columns
+    # in the launch the autotuner picks: sampled columns
     say(f"full size variable layers 512x512x100 {space}")
     base = meshgen.tri_square(512)
     lam = 100
@@ -192,3 +193,46 @@ def test_matrix_config2_sampled():
         gv = val[a:b].cpu().numpy()
         np.testing.assert_array_equal(gc.astype(np.int64), A.indices[A.indptr[r]:A.indptr[r + 1]].astype(np.int64))
         assert_close(gv, A.data[A.indptr[r]:A.indptr[r + 1]], S.data[S.indptr[r]:S.indptr[r + 1]], what=f"CSR row {r}")
+
+
+def test_batch_config5():
+    # the benchmark's batch (64 meshes, 8 fields and 8 adjoints each, seeded
+    # as bench.py seeds it, tilings timed as there): every output of the
+    # graph against its single launch, and one field and one adjoint of the
+    # smallest P1 and DG0 meshes against the oracle
+    say("full size batch, 64 meshes x 8 fields + adjoints")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(meshgen.SEED_BATCH)
+    items = []
+    for it in meshgen.batch_meshes(n_meshes=64):
+        mesh = exm.Mesh(it.mesh, it.n_layers)
+        Vx = exm.Space(mesh, "P1")
+        V = exm.Space(mesh, it.space) if it.space != "P1" else Vx
+        vc = meshgen.extruded_vertex_coords(it.mesh, it.n_layers)
+        X = exm.coordinate_field(Vx, vc)
+        rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        items.append(dict(space=V, coord_space=Vx, coords=X, mesh=mesh, base=it, vc=vc, name=it.space,
+                          f=[rnd() for _ in range(8)], b=[V.zeros() for _ in range(8)],
+                          w=[rnd() for _ in range(8)], g=[V.zeros() for _ in range(8)]))
+    B = exm.Batch(items)
+    say(f"  tiles P1 {B.tiles('P1')} DG0 {B.tiles('DG0')}")
+    B.launch()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for d in items:
+        acc = exm.EXM_INC if d["name"] == "P1" else exm.EXM_WRITE
+        for src, dst in ((d["f"], d["b"]), (d["w"], d["g"])):
+            for x, y in zip(src, dst):
+                ref = d["space"].zeros()
+                exm.par_loop(exm.EXM_K_MASS, d["mesh"], d["coords"], d["coord_space"],
+                             [(x, d["space"], exm.EXM_READ), (ref, d["space"], acc)])
+                bound = 1e-13 * (ref.abs() + 1e-3 * ref.abs().max())
+                excess = ((y - ref).abs() - bound).max().item()
+                worst = max(worst, excess)
+    assert worst <= 0.0, f"batch output off its single launch by {worst:.3e} beyond the bound"
+    for name in ("P1", "DG0"):
+        d = min((d for d in items if d["name"] == name), key=lambda d: d["space"].n_dofs)
+        pr = oracle.Problem(d["base"].mesh, d["base"].n_layers, name, d["vc"])
+        for x, y in ((d["f"][0], d["b"][0]), (d["w"][0], d["g"][0])):
+            xn = x.cpu().numpy()
+            assert_close(y.cpu().numpy(), pr.mass(xn), pr.mass_abs(xn), what=f"full batch vs oracle {name}")
