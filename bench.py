@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["p1", "dg0", "triad"],
+    ap.add_argument("--only", choices=["p1", "dg0", "triad", "batch"],
                     help="launch only this kernel, warmup + steps times, and print nothing (for rocprofv3)")
     ap.add_argument("--config", default=None,
                     help="with --only: the launch configuration as JSON (exm_loop_opts fields) instead of autotuning")
@@ -166,6 +166,17 @@ def main():
             exm.stream_triad(a, b, c, 3.0)
         torch.cuda.synchronize()
         log(f"done: triad n = {n}, {16 * n} bytes read and {8 * n} written per launch")
+        return
+    if args.only == "batch":
+        # the 64-mesh batch, its tilings timed at creation, then warmup + steps graph replays
+        items, bytes_p1, bytes_dg0 = batch_items(torch, exm, W, meshgen)
+        B = exm.Batch(items)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup + args.steps):
+            B.launch()
+        torch.cuda.synchronize()
+        log(f"done: batch, tiles P1 {B.tiles('P1')} DG0 {B.tiles('DG0')}, algorithmic bytes per replay "
+            f"P1 {bytes_p1} DG0 {bytes_dg0}")
         return
     t0 = time.time()
     work = W.extruded(512, 100, keep_host_coords=not args.no_cpu)
@@ -553,33 +564,41 @@ def matrix_figures(torch, exm, W, meshgen):
     return r
 
 
-def batch_vs_plain(torch, exm, W, meshgen):
-    """64 meshes (half P1, half DG0), 8 fields each: the batched forward +
-    adjoint graph against the 1024 individual launches, same GPU, with the
-    library's default launch and with the fastest single-launch schedule of
-    each space at these layer counts (PIPELINED for both: ATOMIC 64-cell tiles
-    of 16-layer chunks for P1, 32-cell tiles for DG0)."""
+def batch_items(torch, exm, W, meshgen):
+    """The batch workload: 64 meshes (half P1, half DG0), 8 fields and 8
+    cotangents each, seeded; with the algorithmic bytes of one replay for
+    the P1 and the DG0 items: 8 fields x (forward + adjoint), input read and
+    output written once, z and (x, y) once, and the P1 fans (vertex offsets
+    and neighbours) or the DG0 lists once."""
     gen = torch.Generator(device="cuda")
     gen.manual_seed(meshgen.SEED_BATCH)
-    t0 = time.time()
     items = []
-    total_bytes = 0
+    by = {True: 0, False: 0}
     for it in meshgen.batch_meshes(n_meshes=64):
         mesh = exm.Mesh(it.mesh, it.n_layers)
         Vx = exm.Space(mesh, "P1")
         V = exm.Space(mesh, it.space) if it.space != "P1" else Vx
         X = exm.coordinate_field(Vx, meshgen.extruded_vertex_coords(it.mesh, it.n_layers))
         rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
-        d = dict(space=V, coord_space=Vx, coords=X, mesh=mesh, name=it.space,
-                 f=[rnd() for _ in range(8)], b=[V.zeros() for _ in range(8)],
-                 w=[rnd() for _ in range(8)], g=[V.zeros() for _ in range(8)])
-        items.append(d)
+        items.append(dict(space=V, coord_space=Vx, coords=X, mesh=mesh, name=it.space,
+                          f=[rnd() for _ in range(8)], b=[V.zeros() for _ in range(8)],
+                          w=[rnd() for _ in range(8)], g=[V.zeros() for _ in range(8)]))
         n = V.n_dofs
         p1 = it.space == "P1"
-        # 8 fields x (forward + adjoint): input read, output written once; z, (x, y) and the
-        # P1 fans (vertex offsets and neighbours) or the DG0 lists once
-        total_bytes += 16 * (8 * n + 8 * n) + 8 * Vx.n_dofs + 16 * it.mesh.n_vertices \
+        by[p1] += 16 * (8 * n + 8 * n) + 8 * Vx.n_dofs + 16 * it.mesh.n_vertices \
             + (4 * (it.mesh.n_vertices + 1) + 8 * it.mesh.n_edges if p1 else 28 * it.mesh.n_cells)
+    return items, by[True], by[False]
+
+
+def batch_vs_plain(torch, exm, W, meshgen):
+    """64 meshes (half P1, half DG0), 8 fields each: the batched forward +
+    adjoint graph against the 1024 individual launches, same GPU, with the
+    library's default launch and with the fastest single-launch schedule of
+    each space at these layer counts (PIPELINED for both: ATOMIC 64-cell tiles
+    of 16-layer chunks for P1, 32-cell tiles for DG0)."""
+    t0 = time.time()
+    items, bytes_p1, bytes_dg0 = batch_items(torch, exm, W, meshgen)
+    total_bytes = bytes_p1 + bytes_dg0
     log(f"batch setup {time.time() - t0:.1f}s")
     t0 = time.time()
     B = exm.Batch(items)
