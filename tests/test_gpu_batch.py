@@ -190,3 +190,18 @@ def test_batch_single_kind(kind):
             for got, want in zip(d["b"] + d["g"], rb + rg):
                 g_, w_ = got.cpu().numpy(), want.cpu().numpy()
                 assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what=f"{kind} only, replay {replay}")
+
+
+def test_batch_refuses_columns_of_different_heights():
+    # batch items take meshes with one layer count: a mesh with a layer range
+    # per column is refused at creation, before any launch
+    base = meshgen.tri_square(5)
+    layers = meshgen.layer_ranges(base, 12, "bathymetry")
+    mesh = exm.Mesh(base, 12, layers=layers)
+    Vx = exm.Space(mesh, "P1")
+    X = exm.coordinate_field(Vx, meshgen.extruded_vertex_coords(base, 12))
+    f = [torch.ones(Vx.n_dofs, dtype=torch.float64, device="cuda")]
+    b = [Vx.zeros()]
+    with pytest.raises(exm.ExmError) as e:
+        exm.Batch([dict(space=Vx, coord_space=Vx, coords=X, mesh=mesh, f=f, b=b)])
+    assert e.value.status == exm._abi.EXM_EUNSUPPORTED and "layer count" in str(e.value)
