@@ -270,3 +270,27 @@ def exact_cubic(mesh, vcoords, n_layers, stencils, n_dofs, u, f):
                 s += hts[cc] * acc
             F[row[p]] += twoA * s
     return F
+
+
+def exact_cubic_vjp(mesh, vcoords, n_layers, stencils, n_dofs, u, w):
+    """g_i = integral of 3 u_h^2 w_h v_i exactly, P1 x P1 (the derivative of
+    the cubic residual's u^3 term applied to w)."""
+    R4, k = reference_tensors("CG1", "CG1", 4)
+    uq = [Fraction(float(x)) for x in u]
+    wq = [Fraction(float(x)) for x in w]
+    g = [Fraction(0)] * n_dofs
+    for (c, l), row in stencils.items():
+        twoA, hts = prism_geometry(mesh.xy, vcoords, mesh.cell_vertex, c, l)
+        ul = [uq[r] for r in row]
+        wl = [wq[r] for r in row]
+        for p in range(k):
+            s = Fraction(0)
+            for cc in range(3):
+                acc = Fraction(0)
+                for q in range(k):
+                    for r in range(k):
+                        for t in range(k):
+                            acc += _lookup(R4[cc], (p, q, r, t)) * ul[q] * ul[r] * wl[t]
+                s += hts[cc] * 3 * acc
+            g[row[p]] += twoA * s
+    return g
