@@ -99,6 +99,16 @@ int32_t exm_mesh_create_var(int32_t n_vertices, int32_t n_edges, int32_t n_cells
                             const int32_t* cell_vertex, const int32_t* cell_edge,
                             int32_t n_layers, const int32_t* layers, exm_mesh** out);
 
+/* The same meshes from device-resident adjacency: cell_vertex, cell_edge
+ * (or NULL) and layers (or NULL for n_layers everywhere) are HIP device
+ * arrays of the sizes above (EXM_EINVAL if any is not device memory).  They
+ * are copied back to the host once, because the race-resolution plans are
+ * built there, then treated exactly as by exm_mesh_create and
+ * exm_mesh_create_var; the caller may free them on return.  Synchronous. */
+int32_t exm_mesh_create_device(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
+                               const int32_t* cell_vertex, const int32_t* cell_edge,
+                               int32_t n_layers, const int32_t* layers, exm_mesh** out);
+
 /* Layer range [lo, hi) of the column of every base entity of dimension d1
  * (0 and n_layers for a uniform mesh).  lo, hi: host [N_d1], either may be
  * NULL. */
@@ -191,14 +201,44 @@ int32_t exm_space_lists(const exm_space* space, int32_t* list_off, int32_t* list
                         void* stream);
 
 /* ------------------------------------------------------------------------
+ * The coordinate field (Section 4.1.1: the geometry is a vector-valued
+ * P1 x P1 field, a d-vector at every extruded vertex).
+ *
+ * The element kernels read (x, y) once per vertex column and z at every
+ * level, so they need vertical columns: the (x, y) of a base vertex is the
+ * same at every level of its column (z is free: terrain-following layers are
+ * allowed).  Columns that lean are refused, never integrated wrongly.
+ *
+ * exm_space_coordinates: fills X, device FP64 [3 * n_dofs] component-major,
+ *   the coordinate field of the P1 x P1 `space`, from xyz [N_0 * (lambda + 1)
+ *   * 3]: the (x, y, z) of level l of base vertex v at xyz[3 * (v * (lambda +
+ *   1) + l)] (levels outside a vertex column of a mesh with layer ranges are
+ *   ignored).  xyz is host memory (xyz_on_device = 0: checked on the host, then
+ *   staged; the call waits for `stream`) or device memory (1: checked on the
+ *   device, synchronising `stream`).  EXM_EUNSUPPORTED, with X untouched, when
+ *   the x or y of a vertex changes between two levels of its column.  The
+ *   address X is remembered as checked (below).
+ * exm_coordinates_verify: checks an existing coordinate field X of `space`
+ *   (device) for vertical columns on `stream` and waits for the answer:
+ *   EXM_OK, or EXM_EUNSUPPORTED naming a leaning vertex.  The address is
+ *   remembered (or forgotten) accordingly.
+ * A loop, matrix assembly or batch given a coordinate address its space has
+ * not seen checked runs the same check first (synchronising its stream; or
+ * EXM_EINVAL while the stream is being captured).  After changing a checked
+ * field in place, or reusing its memory for another, call
+ * exm_coordinates_verify again.
+ */
+int32_t exm_space_coordinates(const exm_space* space, const double* xyz, int32_t xyz_on_device, double* X,
+                              void* stream);
+int32_t exm_coordinates_verify(const exm_space* space, const double* X, void* stream);
+
+/* ------------------------------------------------------------------------
  * Parallel loop over the prisms of an extruded mesh (Algorithm 3) applying a
  * local element kernel.
  *
  * Every kernel takes as args[0] the coordinate field: a P1 x P1 space
- * (EXM_ELEMENT_P1P1) on the same mesh, dim 3, EXM_READ.  Prisms must have
- * vertical columns: the (x, y) of a base vertex is the same at every level
- * (z is free, so terrain-following layers are allowed); the kernels integrate
- * exactly under that assumption and do not check it.
+ * (EXM_ELEMENT_P1P1) on the same mesh, dim 3, EXM_READ, with vertical columns
+ * (checked once per address, as described above).
  *
  *   EXM_K_MASS       y = M x, i.e. y_i = integral of x_h v_i, the residual of
  *                    Section 4.1.1 (args: X, x READ, y).  Every element: the
@@ -332,6 +372,65 @@ int32_t exm_par_loop_config(int32_t kernel, const exm_mesh* iterset, int32_t nar
 /* Number of colours of the base-cell colouring used by EXM_RACE_COLOUR for
  * this space (builds it if needed). */
 int32_t exm_mesh_colours(const exm_mesh* mesh, int32_t* n_colours);
+
+/* ------------------------------------------------------------------------
+ * Read-out of the race-resolution plans a loop uses (built on first use, as
+ * a loop would), so that they can be checked.  The paper's CPU runs need no
+ * such plan (flat MPI, one process per core); on a GPU, increments into DoF
+ * columns shared between base cells race, and these plans are what resolve
+ * it (the reuse between neighbouring cells is the subject of Section 4.3).
+ *
+ *   EXM_PLAN_CELL_COLOURS  units = base cells; the greedy colouring of
+ *                          EXM_RACE_COLOUR under DIRECT (target ignored):
+ *                          no two cells of one colour share a vertex.
+ *   EXM_PLAN_TILES         units = tiles of about `target` base cells (TILED,
+ *                          STAGED, PIPELINED, CHUNKED with EXM_RACE_ATOMIC or
+ *                          EXM_RACE_COLOUR): every cell in one tile; per tile
+ *                          its vertices (bit 31 set when another tile also
+ *                          touches the vertex) and, when the mesh has
+ *                          cell_edge, its edges likewise; tile colours with no
+ *                          shared vertex within a colour.
+ *   EXM_PLAN_OWNER         units = owner tiles of about target / 2 base
+ *                          vertices (EXM_RACE_OWNER): the first owned[t]
+ *                          vertices of tile t are its own (every vertex owned
+ *                          by one tile), its cells are all cells with an
+ *                          owned vertex, its other vertices are read only;
+ *                          one colour.
+ *
+ * exm_mesh_plan_info gives the sizes; exm_mesh_plan_read copies the arrays
+ * into caller-owned host memory (each pointer may be NULL to skip it):
+ * colour [n_units]; cell_off, vert_off, edge_off [n_units + 1] into cells
+ * [n_cell_entries], verts [n_vert_entries], edges [n_edge_entries];
+ * local_cv, local_ce [n_cell_entries * 3]: the unit-local index of each
+ * vertex (edge) of each listed cell; owned [n_units].  Synchronous.
+ */
+#define EXM_PLAN_CELL_COLOURS 1
+#define EXM_PLAN_TILES 2
+#define EXM_PLAN_OWNER 3
+
+typedef struct {
+    int32_t n_units;
+    int32_t n_colours;
+    int64_t n_cell_entries;
+    int64_t n_vert_entries;
+    int64_t n_edge_entries;
+} exm_plan_info;
+
+typedef struct {
+    int32_t* colour;
+    int32_t* cell_off;
+    int32_t* cells;
+    int32_t* vert_off;
+    int32_t* verts;
+    int32_t* owned;
+    int32_t* edge_off;
+    int32_t* edges;
+    uint16_t* local_cv;
+    uint16_t* local_ce;
+} exm_plan_arrays;
+
+int32_t exm_mesh_plan_info(const exm_mesh* mesh, int32_t kind, int32_t target, exm_plan_info* info);
+int32_t exm_mesh_plan_read(const exm_mesh* mesh, int32_t kind, int32_t target, const exm_plan_arrays* out);
 
 /* ------------------------------------------------------------------------
  * Autotuner: times the candidate launch configurations of `kernel` on these

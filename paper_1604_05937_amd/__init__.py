@@ -84,6 +84,25 @@ class Mesh:
             _abi.exm_mesh_create_var(*args, self.layers.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
         self.handle = h
 
+    @classmethod
+    def from_device(cls, base, n_layers: int, cell_vertex, cell_edge=None, layers=None):
+        """The same mesh from device-resident int32 adjacency tensors
+        (exm_mesh_create_device); `base` supplies the entity counts."""
+        import torch
+        _abi.load()
+        self = cls.__new__(cls)
+        self.base = base
+        self.n_layers = int(n_layers)
+        for t in (cell_vertex, cell_edge, layers):
+            assert t is None or (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous())
+        self.layers = None if layers is None else layers.cpu().numpy().reshape(-1, 2)
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        h = ctypes.c_void_p()
+        _abi.exm_mesh_create_device(int(base.n_vertices), int(base.n_edges), int(base.n_cells), ptr(cell_vertex),
+                                    ptr(cell_edge), self.n_layers, ptr(layers), ctypes.byref(h))
+        self.handle = h
+        return self
+
     def entity_layers(self, d1: int):
         """Layer range (lo, hi) of the column of every base entity of dimension d1."""
         n = int(self.base.counts[d1])
@@ -101,6 +120,28 @@ class Mesh:
         n = ctypes.c_int32()
         _abi.exm_mesh_colours(self.handle, ctypes.byref(n))
         return n.value
+
+    def plan(self, kind: str, target: int = 0) -> dict:
+        """A race-resolution plan as host arrays (exm_mesh_plan_read): kind
+        "colours" (base cells), "tiles" or "owner" (tiles of about `target`
+        cells)."""
+        k = {"colours": _abi.EXM_PLAN_CELL_COLOURS, "tiles": _abi.EXM_PLAN_TILES, "owner": _abi.EXM_PLAN_OWNER}[kind]
+        info = _abi.exm_plan_info()
+        _abi.exm_mesh_plan_info(self.handle, k, int(target), ctypes.byref(info))
+        nu = info.n_units
+        edges = info.n_edge_entries > 0
+        out = {"n_colours": info.n_colours,
+               "colour": np.zeros(nu, np.int32), "cell_off": np.zeros(nu + 1, np.int32),
+               "cells": np.zeros(info.n_cell_entries, np.int32), "vert_off": np.zeros(nu + 1, np.int32),
+               "verts": np.zeros(info.n_vert_entries, np.int32), "owned": np.zeros(nu, np.int32),
+               "local_cv": np.zeros(info.n_cell_entries * 3, np.uint16)}
+        if edges:
+            out.update(edge_off=np.zeros(nu + 1, np.int32), edges=np.zeros(info.n_edge_entries, np.int32),
+                       local_ce=np.zeros(info.n_cell_entries * 3, np.uint16))
+        arr = _abi.exm_plan_arrays(*[out[n].ctypes.data if n in out else None
+                                     for n, _ in _abi.exm_plan_arrays._fields_])
+        _abi.exm_mesh_plan_read(self.handle, k, int(target), ctypes.byref(arr))
+        return out
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -195,23 +236,29 @@ class Space:
         self.handle = None
 
 
-def coordinate_field(space: Space, vertex_coords: np.ndarray):
+def coordinate_field(space: Space, vertex_coords, stream=None):
     """Coordinate field (FP64, device, component-major [3, n_dofs]) of a P1 x P1
-    space from per-vertex, per-level coordinates [N0, lambda+1, 3]: component i
-    of extruded vertex (v, l) goes to X[i, S(v) + l], S the column starts the
-    library built."""
+    space from per-vertex, per-level coordinates [N0, lambda+1, 3] (a numpy
+    array or a device tensor), placed by the library (exm_space_coordinates),
+    which refuses columns whose x or y changes with the level."""
     import torch
-    assert space.element == EXM_ELEMENT_P1P1
-    starts = space.column_starts(0).cpu().numpy().astype(np.int64)
-    nl = vertex_coords.shape[1]
-    host = np.zeros((3, space.n_dofs))
-    lo, hi = space.mesh.entity_layers(0)
-    lev = np.arange(nl)[None, :]
-    used = (lev >= lo[:, None]) & (lev <= hi[:, None])     # levels lo .. hi of every vertex column
-    idx = (starts[:, None] + lev - lo[:, None])[used]
-    for i in range(3):
-        host[i, idx] = vertex_coords[:, :, i][used]
-    return torch.from_numpy(host).to("cuda")
+    out = torch.empty(3 * space.n_dofs, dtype=torch.float64, device="cuda")
+    if isinstance(vertex_coords, torch.Tensor):
+        src = vertex_coords.detach().to(dtype=torch.float64).contiguous()
+        assert src.is_cuda and src.numel() == space.mesh.base.n_vertices * (space.mesh.n_layers + 1) * 3
+        _abi.exm_space_coordinates(space.handle, ctypes.c_void_p(src.data_ptr()), 1, ctypes.c_void_p(out.data_ptr()),
+                                   stream_handle(stream))
+    else:
+        src = np.ascontiguousarray(vertex_coords, dtype=np.float64)
+        assert src.size == space.mesh.base.n_vertices * (space.mesh.n_layers + 1) * 3
+        _abi.exm_space_coordinates(space.handle, src.ctypes.data_as(ctypes.c_void_p), 0,
+                                   ctypes.c_void_p(out.data_ptr()), stream_handle(stream))
+    return out.view(3, space.n_dofs)
+
+
+def verify_coordinates(space: Space, X, stream=None):
+    """Check a coordinate field for vertical columns (exm_coordinates_verify)."""
+    _abi.exm_coordinates_verify(space.handle, ctypes.c_void_p(X.data_ptr()), stream_handle(stream))
 
 
 def _arg(t, space: Space, access: int, dim: int = 1) -> _abi.exm_arg:

@@ -84,6 +84,21 @@ class exm_batch_item(ctypes.Structure):
                 ("g", POINTER(c_void_p))]
 
 
+EXM_PLAN_CELL_COLOURS = 1
+EXM_PLAN_TILES = 2
+EXM_PLAN_OWNER = 3
+
+
+class exm_plan_info(ctypes.Structure):
+    _fields_ = [("n_units", c_int32), ("n_colours", c_int32), ("n_cell_entries", c_int64),
+                ("n_vert_entries", c_int64), ("n_edge_entries", c_int64)]
+
+
+class exm_plan_arrays(ctypes.Structure):
+    _fields_ = [(n, c_void_p) for n in ("colour", "cell_off", "cells", "vert_off", "verts", "owned", "edge_off",
+                                        "edges", "local_cv", "local_ce")]
+
+
 # name -> (restype, argtypes); status-returning functions raise ExmError
 _PROTOS = {
     "exm_last_error": (c_char_p, []),
@@ -92,6 +107,8 @@ _PROTOS = {
     "exm_mesh_create": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32, POINTER(c_void_p)]),
     "exm_mesh_create_var": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
                                       POINTER(c_void_p)]),
+    "exm_mesh_create_device": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                         POINTER(c_void_p)]),
     "exm_mesh_entity_layers": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "exm_mesh_destroy": (None, [c_void_p]),
     "exm_space_create": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, POINTER(c_void_p)]),
@@ -100,10 +117,14 @@ _PROTOS = {
     "exm_space_column_starts": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "exm_space_bottom_map": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "exm_space_destroy": (None, [c_void_p]),
+    "exm_space_coordinates": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "exm_coordinates_verify": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "exm_par_loop": (c_int32, [c_int32, c_void_p, c_int32, POINTER(exm_arg), POINTER(exm_loop_opts), c_void_p]),
     "exm_par_loop_config": (c_int32, [c_int32, c_void_p, c_int32, POINTER(exm_arg), POINTER(exm_loop_opts),
                                       POINTER(exm_loop_opts)]),
     "exm_mesh_colours": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "exm_mesh_plan_info": (c_int32, [c_void_p, c_int32, c_int32, POINTER(exm_plan_info)]),
+    "exm_mesh_plan_read": (c_int32, [c_void_p, c_int32, c_int32, POINTER(exm_plan_arrays)]),
     "exm_autotune": (c_int32, [c_int32, c_void_p, c_int32, POINTER(exm_arg), c_void_p, POINTER(exm_loop_opts)]),
     "exm_autotune_save": (c_int32, [c_char_p]),
     "exm_autotune_load": (c_int32, [c_char_p]),

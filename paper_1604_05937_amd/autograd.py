@@ -10,8 +10,11 @@ from __future__ import annotations
 
 import torch
 
-from . import (EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_VJP, EXM_K_MASS, EXM_READ, EXM_WRITE, Mesh,
-               Space, par_loop)
+from . import (CONTINUOUS, ELEMENTS, EXM_INC, EXM_K_CUBIC, EXM_K_CUBIC_FUSED, EXM_K_CUBIC_VJP, EXM_K_MASS, EXM_READ,
+               EXM_WRITE, Mesh, Space, par_loop)
+
+# elements whose DoFs are shared between cells or layers: their outputs are INC
+_SHARED = frozenset(ELEMENTS[name] for name in CONTINUOUS)
 
 
 class Extruded:
@@ -25,7 +28,7 @@ class Extruded:
         self.opts = opts
 
     def _out_access(self):
-        return EXM_INC if self.space.element in (1, 4) else EXM_WRITE
+        return EXM_INC if self.space.element in _SHARED else EXM_WRITE
 
     def mass(self, x):
         y = self.space.zeros()

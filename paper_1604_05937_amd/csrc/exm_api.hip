@@ -637,6 +637,8 @@ int32_t exm_par_loop(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     if (s != EXM_OK) return s;
     s = check_pending();
     if (s != EXM_OK) return s;
+    s = ensure_vertical(P.xspace, P.X, (hipStream_t)stream);
+    if (s != EXM_OK) return s;
     return run_on_mesh(iterset, P, ch, (hipStream_t)stream);
 }
 
@@ -659,6 +661,8 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
     int32_t s = prepare(kernel, iterset, nargs, args, P);
     if (s != EXM_OK) return s;
     hipStream_t hs = (hipStream_t)stream;
+    s = ensure_vertical(P.xspace, P.X, hs);
+    if (s != EXM_OK) return s;
     // Scratch outputs so the caller's buffers stay untouched.
     Signature sig;
     signature(kernel, sig);

@@ -29,6 +29,7 @@
 // no atomics are needed.
 #include <algorithm>
 #include <cstring>
+#include <iterator>
 #include <utility>
 #include <vector>
 
@@ -513,6 +514,8 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
                           "item %d field %d: g aliases another field", m, k);
             }
         }
+        int32_t vs = ensure_vertical(it.coord_space, it.coords, (hipStream_t)stream);
+        if (vs != EXM_OK) return vs;
         const exm_mesh* mesh = it.space->mesh;
         const bool p1 = it.space->element == EXM_ELEMENT_P1P1;
         B->p1[m] = p1;
@@ -547,6 +550,44 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         if (it.w) {
             for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.w[k]);
             for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.g[k]);
+        }
+    }
+    // Every output must be its own memory: no two outputs of any items may
+    // overlap, and no output may overlap any input (fields, cotangents or
+    // coordinates of any item), since tiles read neighbouring input columns
+    // while other tiles store outputs.
+    {
+        struct Range { uintptr_t lo, hi; int32_t item; };
+        std::vector<Range> outs, ins;
+        for (int32_t m = 0; m < n_items; ++m) {
+            const exm_batch_item& it = items[m];
+            const uintptr_t bytes = (uintptr_t)it.space->n_dofs * sizeof(double);
+            for (int32_t k = 0; k < it.n_fields; ++k) {
+                outs.push_back({(uintptr_t)it.b[k], (uintptr_t)it.b[k] + bytes, m});
+                ins.push_back({(uintptr_t)it.f[k], (uintptr_t)it.f[k] + bytes, m});
+                if (it.w) {
+                    outs.push_back({(uintptr_t)it.g[k], (uintptr_t)it.g[k] + bytes, m});
+                    ins.push_back({(uintptr_t)it.w[k], (uintptr_t)it.w[k] + bytes, m});
+                }
+            }
+            const uintptr_t xb = (uintptr_t)it.coord_space->n_dofs * 3 * sizeof(double);
+            ins.push_back({(uintptr_t)it.coords, (uintptr_t)it.coords + xb, m});
+        }
+        std::sort(outs.begin(), outs.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+        for (size_t i = 1; i < outs.size(); ++i)
+            EXM_CHECK(outs[i].lo >= outs[i - 1].hi, EXM_EINVAL, "outputs of items %d and %d overlap",
+                      outs[i - 1].item, outs[i].item);
+        for (const Range& r : ins) {
+            // the first output ending after r.lo is the only candidate that can overlap r
+            auto it = std::upper_bound(outs.begin(), outs.end(), r.lo,
+                                       [](uintptr_t v, const Range& o) { return v < o.lo; });
+            if (it != outs.begin()) {
+                auto prev = std::prev(it);
+                EXM_CHECK(prev->hi <= r.lo, EXM_EINVAL, "an output of item %d overlaps an input of item %d",
+                          prev->item, r.item);
+            }
+            EXM_CHECK(it == outs.end() || it->lo >= r.hi, EXM_EINVAL,
+                      "an output of item %d overlaps an input of item %d", it->item, r.item);
         }
     }
     int32_t s = B->ptrs.upload(ptrs.data(), ptrs.size());

@@ -254,6 +254,37 @@ int32_t exm_mesh_create_var(int32_t n_vertices, int32_t n_edges, int32_t n_cells
     return mesh_create(n_vertices, n_edges, n_cells, cell_vertex, cell_edge, n_layers, layers, out);
 }
 
+int32_t exm_mesh_create_device(int32_t n_vertices, int32_t n_edges, int32_t n_cells, const int32_t* cell_vertex,
+                               const int32_t* cell_edge, int32_t n_layers, const int32_t* layers, exm_mesh** out)
+{
+    clear_error();
+    EXM_CHECK(out != nullptr, EXM_EINVAL, "out is NULL");
+    *out = nullptr;
+    EXM_CHECK(cell_vertex != nullptr, EXM_EINVAL, "cell_vertex is NULL");
+    EXM_CHECK(n_vertices >= 3 && n_cells >= 1 && n_edges >= 0, EXM_ERANGE,
+              "need n_vertices >= 3, n_cells >= 1, n_edges >= 0 (got %d, %d, %d)", n_vertices, n_cells, n_edges);
+    int32_t s = check_pending();
+    if (s != EXM_OK) return s;
+    // The plans (colouring, tiles, fans) are built on the host, so the
+    // adjacency comes back once; every array must be device memory.
+    const int32_t* arrays[3] = {cell_vertex, cell_edge, layers};
+    const char* names[3] = {"cell_vertex", "cell_edge", "layers"};
+    const size_t counts[3] = {(size_t)n_cells * 3, (size_t)n_cells * 3, (size_t)n_cells * 2};
+    std::vector<int32_t> host[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!arrays[a]) continue;
+        hipPointerAttribute_t attr;
+        hipError_t e = hipPointerGetAttributes(&attr, arrays[a]);
+        (void)hipGetLastError();   // an unknown (host) pointer leaves an error behind
+        EXM_CHECK(e == hipSuccess && (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged),
+                  EXM_EINVAL, "%s is not device memory", names[a]);
+        host[a].resize(counts[a]);
+        EXM_TRY_HIP(hipMemcpy(host[a].data(), arrays[a], counts[a] * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    return mesh_create(n_vertices, n_edges, n_cells, host[0].data(), cell_edge ? host[1].data() : nullptr, n_layers,
+                       layers ? host[2].data() : nullptr, out);
+}
+
 int32_t exm_mesh_entity_layers(const exm_mesh* mesh, int32_t d1, int32_t* lo, int32_t* hi)
 {
     clear_error();

@@ -151,6 +151,11 @@ struct exm_space {
     int64_t list_total = 0;
     exm::DevBuf<int32_t> d_list_off;   // [n_cells + 1]
     exm::DevBuf<int32_t> d_entry_off;  // [list_total]
+    // a coordinate (P1xP1) space: addresses of fields found to have vertical
+    // columns, and the device flag of that check
+    mutable std::mutex coords_mu;
+    mutable std::vector<const void*> coords_ok;
+    mutable exm::DevBuf<int32_t> coords_flag;
 };
 
 namespace exm {
@@ -195,5 +200,12 @@ struct LoopLaunch {
     int64_t cell_begin, cell_count;  // range of the list (or of cells) handled by this launch
 };
 int32_t launch_column_loop(const LoopLaunch& L, hipStream_t stream);
+
+// EXM_OK when the coordinate field X on `space` is known to have vertical
+// columns (x, y constant along every vertex column); otherwise checks it on
+// `stream` (synchronising it) and remembers the address if it passes.
+// EXM_EUNSUPPORTED for a leaning column; EXM_EINVAL if the check would be
+// needed while `stream` is being captured.
+int32_t ensure_vertical(const exm_space* space, const void* X, hipStream_t stream);
 
 }  // namespace exm

@@ -575,6 +575,8 @@ int32_t exm_matrix_assemble(int32_t kernel, exm_matrix* A, int32_t nargs, const 
                   EXM_EINVAL, "args[1] (u) must be an EXM_READ scalar field on the matrix's space");
     }
     if (A->n_pat == 0) return EXM_OK;
+    int32_t vs = ensure_vertical(X.space, X.data, (hipStream_t)stream);
+    if (vs != EXM_OK) return vs;
     GatherArgs g;
     std::memset(&g, 0, sizeof(g));
     g.lam = A->lam;

@@ -327,3 +327,125 @@ int32_t build_owner_plan(const exm_mesh* m, int32_t target, const TilePlan** out
 }
 
 }  // namespace exm
+
+// ---------------------------------------------------------------------------
+// Read-out of the plans, so that callers and tests can check them.
+
+using namespace exm;
+
+namespace {
+
+template <class T>
+int32_t copy_back(T* dst, const DevBuf<T>& src, size_t count)
+{
+    if (!dst || count == 0) return EXM_OK;
+    EXM_CHECK(src.p != nullptr && src.n >= count, EXM_EINVAL, "plan array missing");
+    EXM_TRY_HIP(hipMemcpy(dst, src.p, count * sizeof(T), hipMemcpyDeviceToHost));
+    return EXM_OK;
+}
+
+int32_t find_plan(const exm_mesh* m, int32_t kind, int32_t target, const Colouring** col, const TilePlan** plan)
+{
+    *col = nullptr;
+    *plan = nullptr;
+    EXM_CHECK(m != nullptr, EXM_EINVAL, "mesh is NULL");
+    switch (kind) {
+    case EXM_PLAN_CELL_COLOURS: return build_colouring(m, col);
+    case EXM_PLAN_TILES:
+        EXM_CHECK(target >= 1 && target <= 65536, EXM_ERANGE, "target = %d outside [1, 65536]", target);
+        return build_tile_plan(m, target, plan);
+    case EXM_PLAN_OWNER:
+        EXM_CHECK(target >= 2 && target <= 65536, EXM_ERANGE, "target = %d outside [2, 65536]", target);
+        return build_owner_plan(m, target, plan);
+    default: return fail(EXM_EINVAL, "unknown plan kind %d", kind);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t exm_mesh_plan_info(const exm_mesh* mesh, int32_t kind, int32_t target, exm_plan_info* info)
+{
+    clear_error();
+    EXM_CHECK(info != nullptr, EXM_EINVAL, "info is NULL");
+    const Colouring* col;
+    const TilePlan* plan;
+    int32_t s = find_plan(mesh, kind, target, &col, &plan);
+    if (s != EXM_OK) return s;
+    std::memset(info, 0, sizeof(*info));
+    if (col) {
+        info->n_units = mesh->n[2];
+        info->n_colours = col->n_colours;
+        info->n_cell_entries = mesh->n[2];
+        info->n_vert_entries = (int64_t)mesh->n[2] * 3;
+        return EXM_OK;
+    }
+    info->n_units = plan->n_tiles;
+    info->n_colours = plan->n_colours;
+    info->n_cell_entries = (int64_t)plan->cells.n;
+    info->n_vert_entries = plan->n_tile_verts;
+    info->n_edge_entries = plan->has_edges ? (int64_t)plan->edges.n : 0;
+    return EXM_OK;
+}
+
+int32_t exm_mesh_plan_read(const exm_mesh* mesh, int32_t kind, int32_t target, const exm_plan_arrays* out)
+{
+    clear_error();
+    EXM_CHECK(out != nullptr, EXM_EINVAL, "out is NULL");
+    int32_t s = check_pending();
+    if (s != EXM_OK) return s;
+    const Colouring* col;
+    const TilePlan* plan;
+    if ((s = find_plan(mesh, kind, target, &col, &plan)) != EXM_OK) return s;
+    const int32_t nc = mesh->n[2];
+    const int32_t* cv = mesh->h_cell_vertex.data();
+    if (col) {
+        // units are single cells, in base order
+        for (int32_t k = 0; k < col->n_colours; ++k)
+            for (int64_t i = col->offsets[k]; i < col->offsets[k + 1]; ++i)
+                if (out->colour) out->colour[col->host_cells[i]] = k;
+        for (int32_t c = 0; c < nc; ++c) {
+            if (out->cell_off) out->cell_off[c] = c;
+            if (out->cells) out->cells[c] = c;
+            if (out->vert_off) out->vert_off[c] = 3 * c;
+            for (int a = 0; a < 3; ++a) {
+                if (out->verts) out->verts[3 * (int64_t)c + a] = cv[3 * (int64_t)c + a];
+                if (out->local_cv) out->local_cv[3 * (int64_t)c + a] = (uint16_t)a;
+            }
+            if (out->owned) out->owned[c] = 0;
+        }
+        if (out->cell_off) out->cell_off[nc] = nc;
+        if (out->vert_off) out->vert_off[nc] = 3 * nc;
+        EXM_CHECK(!out->edge_off && !out->edges && !out->local_ce, EXM_EINVAL, "the cell colouring lists no edges");
+        return EXM_OK;
+    }
+    const int32_t nt = plan->n_tiles;
+    if (out->colour) {
+        std::vector<int32_t> by_colour(nt);
+        if ((s = copy_back(by_colour.data(), plan->colour_tiles, (size_t)nt)) != EXM_OK) return s;
+        for (int32_t k = 0; k < plan->n_colours; ++k)
+            for (int64_t i = plan->colour_off[k]; i < plan->colour_off[k + 1]; ++i) out->colour[by_colour[i]] = k;
+    }
+    if ((s = copy_back(out->cell_off, plan->cell_off, (size_t)nt + 1)) != EXM_OK) return s;
+    if ((s = copy_back(out->cells, plan->cells, plan->cells.n)) != EXM_OK) return s;
+    if ((s = copy_back(out->vert_off, plan->vert_off, (size_t)nt + 1)) != EXM_OK) return s;
+    if ((s = copy_back(out->verts, plan->verts, plan->verts.n)) != EXM_OK) return s;
+    if ((s = copy_back(out->local_cv, plan->local_cv, plan->local_cv.n)) != EXM_OK) return s;
+    if (out->owned) {
+        if (plan->owner) {
+            if ((s = copy_back(out->owned, plan->owned, (size_t)nt)) != EXM_OK) return s;
+        } else {
+            for (int32_t t = 0; t < nt; ++t) out->owned[t] = 0;
+        }
+    }
+    if (out->edge_off || out->edges || out->local_ce) {
+        EXM_CHECK(plan->has_edges, EXM_EINVAL, "this plan lists no edges (the mesh has no cell_edge, or owner plan)");
+        if ((s = copy_back(out->edge_off, plan->edge_off, (size_t)nt + 1)) != EXM_OK) return s;
+        if ((s = copy_back(out->edges, plan->edges, plan->edges.n)) != EXM_OK) return s;
+        if ((s = copy_back(out->local_ce, plan->local_ce, plan->local_ce.n)) != EXM_OK) return s;
+    }
+    return EXM_OK;
+}
+
+}  // extern "C"

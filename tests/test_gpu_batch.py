@@ -102,6 +102,34 @@ def test_batch_rejects_bad_items():
         exm.Batch(items)
 
 
+@pytest.mark.parametrize("case", ["out_is_other_input", "two_equal_outputs", "out_is_other_cotangent",
+                                  "out_is_coords", "out_overlaps_output"])
+def test_batch_rejects_aliases_across_items(case):
+    items, _ = _setup(2, 0.004, 2, True)
+    a, b = items
+    if case == "out_is_other_input":
+        na, nb = a["space"].n_dofs, b["space"].n_dofs
+        big = torch.rand(max(na, nb), dtype=torch.float64, device="cuda")
+        b["f"][0] = big[:nb]
+        a["b"][1] = big[:na]
+    elif case == "two_equal_outputs":
+        a["g"][0] = a["b"][1]
+    elif case == "out_is_other_cotangent":
+        a["g"][1] = a["w"][0]
+    elif case == "out_is_coords":
+        a["b"][0] = a["coords"].view(-1)[:a["space"].n_dofs]
+    else:
+        # an output that starts inside another item's output
+        big = torch.zeros(a["space"].n_dofs + b["space"].n_dofs, dtype=torch.float64, device="cuda")
+        a["b"][0] = big[:a["space"].n_dofs]
+        b["b"][0] = big[a["space"].n_dofs - 1:a["space"].n_dofs - 1 + b["space"].n_dofs]
+    with pytest.raises(exm.ExmError, match="overlap"):
+        exm.Batch(items)
+    # the same items with their own outputs are accepted
+    items2, _ = _setup(2, 0.004, 2, True)
+    exm.Batch(items2)
+
+
 @pytest.mark.parametrize("sched", [0, "gather"])
 def test_batch_short_columns_odd_field_count(sched):
     # P1 columns shorter than one chunk, or than one 62-level step of the
