@@ -544,6 +544,18 @@ int32_t exm_matrix_spmv(const exm_matrix* A, const double* x, double* y, int32_t
 int32_t exm_matrix_csr(const exm_matrix* A, int64_t* rowptr, int32_t* col, double* val, void* stream);
 void exm_matrix_destroy(exm_matrix* A);
 
+/* exm_matrix_csr without allocating, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same rowptr, col and val as exm_matrix_csr.  The row counts
+ * go straight into rowptr, which is scanned in place; the scan's segment
+ * totals live in a workspace the library holds on each GPU for the life of
+ * the process (512 KiB), so n_rows is limited to 65536 * 8192 = 536,870,912
+ * (EXM_ERANGE beyond).  Asynchronous on `stream`; it calls no hipMalloc,
+ * hipFree, memset or synchronisation.  Every call on one GPU shares that
+ * workspace: calls that overlap on one GPU (other streams, other threads)
+ * race and must be ordered by the caller. */
+int32_t exm_matrix_csr_noalloc(const exm_matrix* A, int64_t* rowptr, int32_t* col, double* val, void* stream);
+
 /* ------------------------------------------------------------------------
  * STREAM triad a_i = b_i + alpha c_i (FP64), the bandwidth yardstick of
  * Section 4.2.1.  block: threads per workgroup (64..1024, multiple of 64);

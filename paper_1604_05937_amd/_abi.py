@@ -143,6 +143,7 @@ _PROTOS = {
     "exm_matrix_assemble": (c_int32, [c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
     "exm_matrix_spmv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "exm_matrix_csr": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "exm_matrix_csr_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "exm_matrix_destroy": (None, [c_void_p]),
     "exm_stream_triad": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int64, c_int32, c_int32, c_void_p]),
 }

@@ -390,7 +390,124 @@ __global__ void __launch_bounds__(256) k_csr_fill(const RowArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// In-place inclusive scan of int64 values for the CSR export without
+// allocation: segments of kScanSeg values per workgroup, the segment totals
+// in `scratch`, then one workgroup scans the totals and every segment adds its
+// offset.
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+constexpr int64_t kScanSeg = (int64_t)kScanThreads * kScanPer;
+constexpr int64_t kScanMaxSegs = 65536;
+
+__device__ __forceinline__ int64_t wave_inclusive(int64_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive prefix over the workgroup of one value per thread; *total gets
+// the workgroup's sum.
+__device__ __forceinline__ int64_t block_exclusive(int64_t v, int64_t* total)
+{
+    __shared__ int64_t wsum[kScanThreads / 64 + 1];   // per-wave offsets, then the total
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t inc = wave_inclusive(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        const int64_t x = lane < kScanThreads / 64 ? wsum[lane] : 0;
+        const int64_t xi = wave_inclusive(x);
+        if (lane < kScanThreads / 64) wsum[lane] = xi - x;
+        if (lane == kScanThreads / 64 - 1) wsum[kScanThreads / 64] = xi;
+    }
+    __syncthreads();
+    const int64_t r = wsum[w] + inc - v;
+    *total = wsum[kScanThreads / 64];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_segments(int64_t* __restrict__ a, int64_t n,
+                                                                int64_t* __restrict__ seg_total)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanSeg + (int64_t)threadIdx.x * kScanPer;
+    int64_t v[kScanPer];
+    int64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < n ? a[base + k] : 0;
+        run += v[k];
+        v[k] = run;
+    }
+    int64_t total;
+    const int64_t off = block_exclusive(run, &total);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n) a[base + k] = v[k] + off;
+    if (threadIdx.x == 0) seg_total[blockIdx.x] = total;
+}
+
+// Exclusive scan of the nseg segment totals, in place, by one workgroup.
+__global__ void __launch_bounds__(kScanThreads) k_scan_totals(int64_t* __restrict__ t, int64_t nseg)
+{
+    const int64_t per = (nseg + kScanThreads - 1) / kScanThreads;
+    const int64_t b = (int64_t)threadIdx.x * per;
+    int64_t run = 0;
+    for (int64_t i = b; i < b + per && i < nseg; ++i) run += t[i];
+    int64_t total;
+    int64_t off = block_exclusive(run, &total);
+    for (int64_t i = b; i < b + per && i < nseg; ++i) {
+        const int64_t x = t[i];
+        t[i] = off;
+        off += x;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_add(int64_t* __restrict__ a, int64_t n,
+                                                           const int64_t* __restrict__ seg_off)
+{
+    const int64_t add = seg_off[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kScanSeg;
+    for (int k = threadIdx.x; k < kScanSeg; k += kScanThreads)
+        if (base + k < n) a[base + k] += add;
+}
+
+// The CSR export's first pass writing its counts straight into the row
+// pointers: rowptr[row + 1] = entries of the row, rowptr[0] = 0.
+__global__ void __launch_bounds__(256) k_csr_count_rowptr(const RowArgs a, int64_t* __restrict__ rowptr)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0) rowptr[0] = 0;
+    if (idx >= a.n_items) return;
+    const int32_t r = (int32_t)(idx / a.L);
+    const int s = (int)(idx - (int64_t)r * a.L);
+    const int wr = a.wk[r] & 0xffff, kr = a.wk[r] >> 16;
+    if (kr == kKindV && s == a.lam) return;
+    int64_t n = 0;
+    for (int32_t p = a.pptr[r]; p < a.pptr[r + 1]; ++p) {
+        const int kq = a.wk[a.pcol[p]] >> 16;
+        for (int d = -1; d <= 1; ++d)
+            if ((a.band == 3 || d == 0) && pair_valid(kr, kq, d, s, a.lam)) ++n;
+    }
+    rowptr[a.c0[r] + (int64_t)s * wr + 1] = n;
+}
+
 }  // namespace
+
+// Workspace of exm_matrix_csr_noalloc: the segment totals of the scan of the
+// row pointers (at most kScanMaxSegs segments of kScanSeg rows, 512 KiB).
+// Every GPU the library runs on holds its own copy for the life of the
+// process; host code reaches it only through the address hipGetSymbolAddress
+// gives on that device.
+static __device__ __align__(256) int64_t scratch[kScanMaxSegs];
+
 }  // namespace exm
 
 using namespace exm;
@@ -676,6 +793,56 @@ int32_t exm_matrix_csr(const exm_matrix* A, int64_t* rowptr, int32_t* col, doubl
     EXM_TRY_HIP(hipGetLastError());
     // cnt and tmp are freed on return: wait for the kernels that use them
     EXM_TRY_HIP(hipStreamSynchronize(hs));
+    return EXM_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per device.
+static int32_t scratch_address(int64_t** out)
+{
+    static std::mutex mu;
+    static std::vector<int64_t*> addr;
+    int dev = 0;
+    EXM_TRY_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        EXM_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        addr[dev] = (int64_t*)p;
+    }
+    *out = addr[dev];
+    return EXM_OK;
+}
+
+int32_t exm_matrix_csr_noalloc(const exm_matrix* A, int64_t* rowptr, int32_t* col, double* val, void* stream)
+{
+    clear_error();
+    EXM_CHECK(A != nullptr && rowptr != nullptr, EXM_EINVAL, "matrix or rowptr is NULL");
+    EXM_CHECK(A->nnz == 0 || (col != nullptr && val != nullptr), EXM_EINVAL, "col or val is NULL");
+    const int64_t n = A->space->n_dofs;
+    const int64_t nseg = (n + kScanSeg - 1) / kScanSeg;
+    EXM_CHECK(nseg <= kScanMaxSegs, EXM_ERANGE, "%lld rows exceed the %lld this call can scan without allocating",
+              (long long)n, (long long)(kScanMaxSegs * kScanSeg));
+    int64_t* seg = nullptr;
+    int32_t st = scratch_address(&seg);
+    if (st != EXM_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    RowArgs a = row_args(A);
+    const int bs = 256;
+    const int64_t nb = std::max<int64_t>(1, (a.n_items + bs - 1) / bs);
+    hipLaunchKernelGGL(k_csr_count_rowptr, dim3((unsigned)nb), dim3(bs), 0, hs, a, rowptr);
+    EXM_TRY_HIP(hipGetLastError());
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scan_segments, dim3((unsigned)nseg), dim3(kScanThreads), 0, hs, rowptr + 1, n, seg);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, hs, seg, nseg);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nseg), dim3(kScanThreads), 0, hs, rowptr + 1, n, seg);
+        EXM_TRY_HIP(hipGetLastError());
+    }
+    a.rowptr = rowptr;
+    a.ccol = col;
+    a.cval = val;
+    if (a.n_items) hipLaunchKernelGGL(k_csr_fill, dim3((unsigned)nb), dim3(bs), 0, hs, a);
+    EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;
 }
 
