@@ -50,6 +50,26 @@ def timed(torch, fn, reps):
     return min(ts), sum(ts) / len(ts)
 
 
+def timed_flushed(torch, fn, reps, flush):
+    """min and mean time (ms) of fn over reps runs, with the 256 MB
+    Infinity Cache (MALL) and the L2s flushed before each run by writing
+    `flush` (>= 1 GiB) outside the timed events."""
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ts = []
+    for r in range(reps):
+        flush.fill_(float(r))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return min(ts), sum(ts) / len(ts)
+
+
 def stream_triad(torch, exm):
     n = 1 << 28   # 3 arrays of 2 GiB
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -81,18 +101,44 @@ def read_traffic(kernel_tag: str, src_hash: str, launch: dict):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(work, f1_host, f0_host, budget_s: float):
-    """The oracle (plain C, one thread) on a bounded sample of the same
-    workload: the first base cells of the RCM order, all layers, P1 and DG0.
-    The per-prism time is extrapolated to the whole step."""
+def host_threads() -> int:
+    """Host threads the all-core baseline uses: OMP_NUM_THREADS when set (the
+    machine's CPU share), else the CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "cpus_allowed": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(base, lam, vc, f1_host, f0_host, budget_s: float, runs: int = 10, all_core_budget_s: float = 30.0):
+    """The oracle (plain C) on the host, two ways:
+    - one thread, on a bounded sample of the same workload (the first base
+      cells of the RCM order, all layers, P1 and DG0), the per-prism time
+      extrapolated to the whole step;
+    - every host thread (host_threads()) over the whole step, P1 colour by
+      colour of the oracle's own greedy colouring, DG0 split over the
+      threads; the minimum of `runs` runs (fewer if they exceed
+      all_core_budget_s), as the paper takes the minimum of ten."""
     import numpy as np
 
     import oracle
-    base, lam = work.base, work.n_layers
     t0 = time.time()
     num_x = oracle.number(base.counts, lam, oracle.delta_table("CG1", "CG1"), base.cell_vertex, base.cell_edge)
     num_0 = oracle.number(base.counts, lam, oracle.delta_table("DG0", "DG0"), base.cell_vertex, base.cell_edge)
-    X = oracle.coordinate_field(num_x, work.vc)
+    X = oracle.coordinate_field(num_x, vc)
     log(f"cpu baseline: oracle numbering {time.time() - t0:.1f}s")
     out1 = np.zeros(num_x.n_dofs)
     out0 = np.zeros(num_0.n_dofs)
@@ -110,7 +156,53 @@ def cpu_baseline(work, f1_host, f0_host, budget_s: float):
             n = min(base.n_cells, int(n * max(2.0, budget_s / 2 / max(dt, 1e-3))))
         per[name] = (dt / (n * lam), n)
         log(f"cpu baseline {name}: {n} cells x {lam} layers in {dt:.2f}s")
-    return per
+    threads = host_threads()
+    colour, n_colours = oracle.greedy_colour(base.cell_vertex, base.n_vertices)
+    times = []
+    t_all = time.perf_counter()
+    for r in range(runs):
+        out1[:] = 0.0
+        t = time.perf_counter()
+        oracle.par_loop_threaded(oracle.FORM_MASS, ("CG1", "CG1"), num_x, num_x, X, [f1_host], [out1],
+                                 threads=threads, colour=colour)
+        oracle.par_loop_threaded(oracle.FORM_MASS, ("DG0", "DG0"), num_0, num_x, X, [f0_host], [out0],
+                                 write=True, threads=threads)
+        times.append(time.perf_counter() - t)
+        if time.perf_counter() - t_all > all_core_budget_s:
+            break
+    log(f"cpu baseline all cores: {threads} threads, {n_colours} colours, {len(times)} runs, "
+        f"min {min(times):.2f}s per step")
+    return per, {"threads": threads, "n_colours": n_colours, "runs": len(times), "min_s": min(times),
+                 "median_s": float(np.median(times))}
+
+
+def cpu_baseline_json(per, allc, step_bytes: float, n_prisms: int, gpu_step_ms: float | None) -> dict:
+    cpu_step_s = (per["P1"][0] + per["DG0"][0]) * n_prisms
+    res = {
+        "value": round(step_bytes / allc["min_s"] / 1e9, 4),
+        "unit": "GB/s",
+        "cores": allc["threads"],
+        "kind": "oracle",
+        "sample": f"the whole step (P1xP1 INC + DG0xDG0 WRITE oracle assembly, 512x512x100) on "
+                  f"{allc['threads']} host threads, P1 colour by colour of the oracle's own greedy colouring "
+                  f"({allc['n_colours']} colours), DG0 split over the threads; minimum of {allc['runs']} runs",
+        "step_s": round(allc["min_s"], 3),
+        "step_s_median": round(allc["median_s"], 3),
+        "single_core": {
+            "value": round(step_bytes / cpu_step_s / 1e9, 4),
+            "unit": "GB/s",
+            "cores": 1,
+            "sample": f"P1xP1 and DG0xDG0 oracle assembly of the first {per['P1'][1]} and {per['DG0'][1]} base "
+                      f"cells (RCM order) x 100 layers, one thread, one run, per-prism time extrapolated to the "
+                      f"{n_prisms}-prism step",
+            "step_s_extrapolated": round(cpu_step_s, 2),
+        },
+        "host_cpu": host_cpu(),
+    }
+    if gpu_step_ms:
+        res["gpu_speedup"] = round(allc["min_s"] / (gpu_step_ms * 1e-3), 1)
+        res["single_core"]["gpu_speedup"] = round(cpu_step_s / (gpu_step_ms * 1e-3), 1)
+    return res
 
 
 def main():
@@ -120,7 +212,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["p1", "dg0", "triad", "batch"],
+    ap.add_argument("--only", choices=["p1", "dg0", "triad", "batch", "cpu"],
                     help="launch only this kernel, warmup + steps times, and print nothing (for rocprofv3)")
     ap.add_argument("--config", default=None,
                     help="with --only: the launch configuration as JSON (exm_loop_opts fields) instead of autotuning")
@@ -140,6 +232,9 @@ def main():
                          "512x512 base and at a constant ~52.4M prisms, plus RCM against a random base ordering; "
                          "one JSON line per point")
     args = ap.parse_args()
+    if args.only == "cpu":
+        cpu_only(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
@@ -279,6 +374,15 @@ def main():
         "traffic": traffic,
         "algorithmic_bytes_per_launch": dominant[1]["algorithmic"],
         "avg_launch_ms": round(float(np.mean(dominant[2])), 4),
+        # the same time on the byte count that reads all three coordinate
+        # components at every extruded vertex (the kernel reads z per level
+        # and (x, y) once per vertical column)
+        "full_coordinate_field": {
+            "algorithmic_bytes_per_launch": dominant[1]["algorithmic_full_coords"],
+            "achieved": round(dominant[1]["algorithmic_full_coords"] / (np.mean(dominant[2]) * 1e-3) / 1e9, 1),
+            "frac": round(dominant[1]["algorithmic_full_coords"] / (np.mean(dominant[2]) * 1e-3) / 1e9
+                          / HBM_PEAK_GBS, 4),
+        },
     }
 
     result = {
@@ -329,20 +433,26 @@ def main():
             result["secondary"] = {"error": repr(e)}
 
     if not args.no_cpu:
-        per = cpu_baseline(work, f1_host, f0_host, args.cpu_seconds)
-        cpu_step_s = (per["P1"][0] + per["DG0"][0]) * work.n_prisms
-        result["cpu_baseline"] = {
-            "value": round(step_bytes / cpu_step_s / 1e9, 4),
-            "unit": "GB/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"P1xP1 and DG0xDG0 oracle assembly of the first {per['P1'][1]} and {per['DG0'][1]} base "
-                      f"cells (RCM order) x 100 layers, single thread, per-prism time extrapolated to the "
-                      f"{work.n_prisms}-prism step",
-            "step_s_extrapolated": round(cpu_step_s, 2),
-            "gpu_speedup": round(cpu_step_s / (step_ms * 1e-3), 1),
-        }
+        per, allc = cpu_baseline(work.base, work.n_layers, work.vc, f1_host, f0_host, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline_json(per, allc, step_bytes, work.n_prisms, step_ms)
     print(json.dumps(result), flush=True)
+
+
+def cpu_only(args):
+    """The CPU baseline alone (no GPU): the oracle on the step's workload."""
+    from paper_1604_05937_amd import meshgen, workloads as W
+    base = meshgen.tri_square(512)
+    lam = 100
+    vc = meshgen.extruded_vertex_coords(base, lam)
+    n1 = base.n_vertices * (lam + 1)
+    n0 = base.n_cells * lam
+    f1 = meshgen.uniform_values(n1, seed=meshgen.SEED_FIELD)
+    f0 = meshgen.uniform_values(n0, seed=meshgen.SEED_FIELD)
+    step_bytes = W.mass_bytes_counts(base, lam, "P1")["algorithmic"] + \
+        W.mass_bytes_counts(base, lam, "DG0")["algorithmic"]
+    per, allc = cpu_baseline(base, lam, vc, f1, f0, args.cpu_seconds)
+    print(json.dumps({"cpu_baseline": cpu_baseline_json(per, allc, step_bytes, base.n_cells * lam, None)}),
+          flush=True)
 
 
 def sweep(torch, exm):
@@ -450,6 +560,8 @@ def secondary(torch, exm, W, meshgen):
         del ev
     out["rhs_variable_layers_512x512x100"] = var
     log("variable layers: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in var.items()))
+    out["race_resolution"] = race_figures(torch, exm, W, meshgen)
+    out["layers_constant_work"] = layer_points(torch, exm, W, meshgen)
     out["matrix_p1_512x512x100"] = matrix_figures(torch, exm, W, meshgen)
     # mixed-degree DG (a DoF count per entity): half the cells DG1, half DG0, 256 x 256 x 64
     em = W.extruded(256, 64)
@@ -509,11 +621,23 @@ def secondary(torch, exm, W, meshgen):
           (gu, V, exm.EXM_INC), (gf, V, exm.EXM_INC)]
     c_fw = exm.autotune(exm.EXM_K_CUBIC, e4.mesh, e4.X, V, fw)
     c_fu = exm.autotune(exm.EXM_K_CUBIC_FUSED, e4.mesh, e4.X, V, fu)
-    t_fw, _ = timed(torch, lambda: W.run_cubic(e4, u, f, F), 10)
-    t_fu, _ = timed(torch, lambda: W.run_fused(e4, u, f, w, F, gu, gf), 10)
+    t_fw, t_fw_mean = timed(torch, lambda: W.run_cubic(e4, u, f, F), 10)
+    t_fu, t_fu_mean = timed(torch, lambda: W.run_fused(e4, u, f, w, F, gu, gf), 10)
+    # the working set (~160 / 240 MB) fits in the 256 MB MALL: also timed
+    # with the caches flushed before every launch
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    tf_fw, tf_fw_mean = timed_flushed(torch, lambda: W.run_cubic(e4, u, f, F), 10, flush)
+    tf_fu, tf_fu_mean = timed_flushed(torch, lambda: W.run_fused(e4, u, f, w, F, gu, gf), 10, flush)
+    del flush
     fl_fw, fl_fu = W.cubic_flops(e4, False), W.cubic_flops(e4, True)
     out["cubic_256x256x50"] = {"forward_ms": round(t_fw, 4), "fused_fwd_adj_ms": round(t_fu, 4),
-                               "fused_over_forward": round(t_fu / t_fw, 3), "launch_forward": c_fw,
+                               "fused_over_forward": round(t_fu / t_fw, 3),
+                               "forward_mean_ms": round(t_fw_mean, 4), "fused_mean_ms": round(t_fu_mean, 4),
+                               "flushed": {"forward_ms": round(tf_fw, 4), "fused_fwd_adj_ms": round(tf_fu, 4),
+                                           "fused_over_forward": round(tf_fu / tf_fw, 3),
+                                           "forward_mean_ms": round(tf_fw_mean, 4),
+                                           "fused_mean_ms": round(tf_fu_mean, 4)},
+                               "launch_forward": c_fw,
                                "launch_fused": c_fu,
                                "forward_tflops": round(fl_fw / t_fw / 1e9, 2),
                                "forward_frac_fp64_peak": round(fl_fw / t_fw / 1e9 / FP64_PEAK_TFLOPS, 4),
@@ -521,10 +645,83 @@ def secondary(torch, exm, W, meshgen):
                                "fused_frac_fp64_peak": round(fl_fu / t_fu / 1e9 / FP64_PEAK_TFLOPS, 4),
                                "forward_gbs": round(W.cubic_bytes(e4, False)["algorithmic"] / t_fw / 1e6, 1),
                                "fused_gbs": round(W.cubic_bytes(e4, True)["algorithmic"] / t_fu / 1e6, 1)}
-    log(f"cubic forward {t_fw:.3f} ms, fused {t_fu:.3f} ms")
+    log(f"cubic forward {t_fw:.3f} ms, fused {t_fu:.3f} ms; flushed {tf_fw:.3f} / {tf_fu:.3f} ms")
     del e4, u, f, w, F, gu, gf
     torch.cuda.empty_cache()
     out["batch"] = batch_vs_plain(torch, exm, W, meshgen)
+    return out
+
+
+def race_figures(torch, exm, W, meshgen):
+    """The race resolutions of CG increments side by side, same run: K1 (P1
+    RHS) on 512 x 512 x 100 and the P2 mass action on 256 x 256 x 64, each
+    schedule under FP64 atomics, colouring and (P1) owner computes."""
+    out = {}
+    A, C, O = exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR, exm.EXM_RACE_OWNER
+    P, T, D, G = exm.EXM_SCHED_PIPELINED, exm.EXM_SCHED_TILED, exm.EXM_SCHED_DIRECT, exm.EXM_SCHED_GATHER
+    for name, (nb, lam), cases in (
+            ("P1", (512, 100), [("pipelined_atomic", dict(schedule=P, race=A, tile_cells=64, chunk_layers=16)),
+                                ("pipelined_colour", dict(schedule=P, race=C, tile_cells=64, chunk_layers=16)),
+                                ("pipelined_owner", dict(schedule=P, race=O, tile_cells=64, chunk_layers=16)),
+                                ("direct_atomic", dict(schedule=D, race=A, cols_per_wave=1, waves_per_block=4)),
+                                ("direct_colour", dict(schedule=D, race=C, cols_per_wave=1, waves_per_block=4)),
+                                ("gather_owner", dict(schedule=G, waves_per_block=4))]),
+            ("P2", (256, 64), [("pipelined_atomic", dict(schedule=P, race=A, tile_cells=32, chunk_layers=8)),
+                               ("pipelined_colour", dict(schedule=P, race=C, tile_cells=32, chunk_layers=8)),
+                               ("tiled_atomic", dict(schedule=T, race=A, tile_cells=8, cols_per_wave=1)),
+                               ("tiled_colour", dict(schedule=T, race=C, tile_cells=8, cols_per_wave=1)),
+                               ("direct_atomic", dict(schedule=D, race=A, cols_per_wave=1, waves_per_block=4)),
+                               ("direct_colour", dict(schedule=D, race=C, cols_per_wave=1, waves_per_block=4))])):
+        e = W.extruded(nb, lam)
+        V = e.space(name)
+        x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
+        y = V.zeros()
+        b = W.mass_bytes(e, name)
+        res = {"colours_cells": e.mesh.colours()}
+        for label, opts in cases:
+            t, tm = timed(torch, lambda: W.run_mass(e, name, x, y, **opts), 10)
+            res[label] = {"ms": round(t, 4), "mean_ms": round(tm, 4), "gbs": round(b["algorithmic"] / t / 1e6, 1),
+                          "launch": exm.par_loop_config(exm.EXM_K_MASS, e.mesh, e.X, e.Vx,
+                                                        W.mass_args(e, name, x, y), **opts)}
+        res["owner"] = "P1 only: there is no owner plan over edges" if name == "P2" else "vertex tiles"
+        out[f"{name}_{nb}x{nb}x{lam}"] = res
+        log(f"races {name}: " + ", ".join(f"{k} {v['ms']:.3f}" for k, v in res.items() if isinstance(v, dict)))
+        del x, y, e
+        torch.cuda.empty_cache()
+    return out
+
+
+def layer_points(torch, exm, W, meshgen):
+    """Throughput against the layer count at a constant ~52.4 M prisms (the
+    base shrinking as the columns grow: n = 512 sqrt(100 / lambda)) and
+    against a random base ordering at 100 layers, P1 and DG0 RHS, each the
+    fastest of a fixed set of PIPELINED launches (the full sweep with the
+    autotuner is ``bench.py --sweep``)."""
+    import numpy as np
+    out = {}
+    A = exm.EXM_RACE_ATOMIC
+    shapes = {"P1": [(64, 16), (64, 8), (128, 8)], "DG0": [(32, 32), (32, 16), (64, 16)]}
+    for lam, order in ((20, "rcm"), (50, "rcm"), (200, "rcm"), (100, "random")):
+        n = 512 if order == "random" else int(round(512 * np.sqrt(100.0 / lam)))
+        t0 = time.time()
+        e = W.extruded(n, lam, order=order)
+        pt = {"base": f"{n}x{n}", "n_layers": lam, "order": order, "n_prisms": e.n_prisms}
+        for name in ("P1", "DG0"):
+            V = e.space(name)
+            x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
+            y = V.zeros()
+            b = W.mass_bytes(e, name)
+            best = min((timed(torch, lambda: W.run_mass(e, name, x, y, schedule=exm.EXM_SCHED_PIPELINED, race=A,
+                                                       tile_cells=tc, chunk_layers=S), 10)[0], tc, S)
+                       for tc, S in shapes[name])
+            pt[name] = {"ms": round(best[0], 4), "gbs": round(b["algorithmic"] / best[0] / 1e6, 1),
+                        "tile_cells": best[1], "chunk_layers": best[2]}
+            del x, y
+        pt["setup_s"] = round(time.time() - t0, 1)
+        out[f"lambda{lam}_{order}"] = pt
+        log(f"layer point {n}x{n}x{lam} {order}: P1 {pt['P1']['gbs']:.0f} GB/s, DG0 {pt['DG0']['gbs']:.0f} GB/s")
+        del e
+        torch.cuda.empty_cache()
     return out
 
 

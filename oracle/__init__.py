@@ -70,9 +70,14 @@ def build(force: bool = True) -> str:
 
 @lru_cache(maxsize=1)
 def _lib():
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    # ORACLE_LIB names another build of oracle.c (the sanitizer build of the
+    # tests); by default the plain build next to the source
+    path = os.environ.get("ORACLE_LIB", "")
+    if not path:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        path = _LIB
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     lib.oracle_alg1_number.restype = ctypes.c_int64
     lib.oracle_alg1_number.argtypes = [P, ctypes.c_int32, P, P, P, P]
@@ -94,6 +99,8 @@ def _lib():
     lib.oracle_facet_loop.restype = None
     lib.oracle_facet_loop.argtypes = [ctypes.c_int64, P, ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P,
                                       ctypes.c_int32, ctypes.c_int32, P, P, P, P, P]
+    lib.oracle_greedy_colour.restype = ctypes.c_int32
+    lib.oracle_greedy_colour.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P]
     lib.oracle_assemble.restype = None
     lib.oracle_assemble.argtypes = [ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int32, P, P, P,
                                     ctypes.c_int32, P, P, P, P, P, P,
@@ -457,6 +464,60 @@ def par_loop(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.
                         _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), 1 if write else 0,
                         int(wts.size), _ptr(np.ascontiguousarray(wts)), _ptr(np.ascontiguousarray(phix)),
                         _ptr(np.ascontiguousarray(dphix)), _ptr(phiv))
+    return outs
+
+
+def greedy_colour(cell_vertex: np.ndarray, n_vertices: int):
+    """The oracle's own greedy base-cell colouring (for timing it on several
+    threads): colour [n_cells] and the number of colours; cells of one colour
+    share no vertex."""
+    cv = np.ascontiguousarray(cell_vertex, dtype=np.int32)
+    colour = np.zeros(cv.shape[0], dtype=np.int32)
+    n = _lib().oracle_greedy_colour(cv.shape[0], int(n_vertices), _ptr(cv), _ptr(colour))
+    if n < 0:
+        raise MemoryError("oracle_greedy_colour")
+    return colour, n
+
+
+def par_loop_threaded(form: int, space: tuple, num_v: Numbering, num_x: Numbering, X: np.ndarray, ins, outs,
+                      write: bool = False, threads: int = 1, colour=None):
+    """par_loop on several host threads, for timing the oracle on all cores:
+    the same C routine on disjoint cell subsets at once (ctypes releases the
+    GIL).  DG outputs (``write``) belong to one cell each, so the cells are
+    simply split; increments into shared columns go colour by colour
+    (``colour`` from greedy_colour), each colour's cells split over the
+    threads.  The values equal par_loop's up to the order of summation."""
+    from concurrent.futures import ThreadPoolExecutor
+    h, v = space
+    lib = _lib()
+    pts, wts = rule_for(form, h, v)
+    phiv = np.ascontiguousarray(tabulate(h, v, pts))
+    phix, dphix = tabulate_coords(pts)
+    wts, phix, dphix = (np.ascontiguousarray(a) for a in (wts, phix, dphix))
+    ins = list(ins) + [None] * (3 - len(ins))
+    outs = list(outs) + [None] * (3 - len(outs))
+    Xc = np.ascontiguousarray(X, dtype=np.float64)
+    n_cells = int(num_v.counts[2])
+    if write:
+        groups = [np.arange(n_cells, dtype=np.int64)]
+    else:
+        assert colour is not None and colour.size == n_cells
+        order = np.argsort(colour, kind="stable").astype(np.int64)
+        bounds = np.searchsorted(colour[order], np.arange(int(colour.max()) + 2))
+        groups = [order[bounds[k]:bounds[k + 1]] for k in range(bounds.size - 1)]
+
+    def run(cells):
+        lib.oracle_par_loop(form, cells.size, _ptr(cells), num_v.n_layers, _ptr(num_v.cell_lam),
+                            _ptr(num_x.lmap), _ptr(num_x.offsets), _ptr(Xc),
+                            num_v.k, _ptr(num_v.lmap), _ptr(num_v.offsets),
+                            _ptr(ins[0]), _ptr(ins[1]), _ptr(ins[2]),
+                            _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), 1 if write else 0,
+                            int(wts.size), _ptr(wts), _ptr(phix), _ptr(dphix), _ptr(phiv))
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for g in groups:
+            parts = [np.ascontiguousarray(p) for p in np.array_split(g, threads) if p.size]
+            list(ex.map(run, parts))   # one colour at a time
     return outs
 
 

@@ -520,3 +520,47 @@ int64_t oracle_stencil_mixed(int64_t n_cells, int32_t lam, const int32_t* dofs0,
     list_off[n_cells] = p;
     return p;
 }
+
+/*
+ * Greedy colouring of the base cells, used only to time the oracle on several
+ * host threads (it is not a step of the method): cells in base order take the
+ * smallest colour that no earlier cell sharing a vertex with them holds.  The
+ * cells of one colour then share no vertex (hence no edge), so no DoF column
+ * of a vertex or edge, and their increments cannot collide.  Writes colour[c]
+ * and returns the number of colours (-1 if memory runs out).
+ */
+int32_t oracle_greedy_colour(int32_t n_cells, int32_t n_vertices, const int32_t* cell_vertex, int32_t* colour)
+{
+    int64_t* start = (int64_t*)calloc((size_t)n_vertices + 1, sizeof(int64_t));
+    int32_t* around = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_cells * 3 + 1);
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_vertices + 1));
+    int32_t* taken = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n_cells * 3 + 1));
+    if (!start || !around || !fill || !taken) {
+        free(start); free(around); free(fill); free(taken);
+        return -1;
+    }
+    for (int64_t i = 0; i < (int64_t)n_cells * 3; ++i) start[cell_vertex[i] + 1]++;
+    for (int32_t v = 0; v < n_vertices; ++v) start[v + 1] += start[v];
+    for (int32_t v = 0; v <= n_vertices; ++v) fill[v] = start[v];
+    for (int32_t c = 0; c < n_cells; ++c)
+        for (int a = 0; a < 3; ++a) around[fill[cell_vertex[c * 3 + a]]++] = c;
+    /* taken[k] == c marks colour k as held by a neighbour of cell c */
+    for (int64_t k = 0; k < (int64_t)n_cells * 3 + 1; ++k) taken[k] = -1;
+    int32_t n_colours = 0;
+    for (int32_t c = 0; c < n_cells; ++c) colour[c] = -1;
+    for (int32_t c = 0; c < n_cells; ++c) {
+        for (int a = 0; a < 3; ++a) {
+            const int32_t v = cell_vertex[c * 3 + a];
+            for (int64_t j = start[v]; j < start[v + 1]; ++j) {
+                const int32_t o = colour[around[j]];
+                if (o >= 0) taken[o] = c;
+            }
+        }
+        int32_t k = 0;
+        while (taken[k] == c) ++k;
+        colour[c] = k;
+        if (k + 1 > n_colours) n_colours = k + 1;
+    }
+    free(start); free(around); free(fill); free(taken);
+    return n_colours;
+}

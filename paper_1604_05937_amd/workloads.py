@@ -98,13 +98,31 @@ def coord_bytes(e: Extruded) -> int:
     return 8 * e.Vx.n_dofs + 16 * e.base.n_vertices
 
 
+def mass_bytes_counts(base, n_layers: int, name: str) -> dict:
+    """mass_bytes of a uniform extruded mesh from the entity counts alone
+    (n_dofs = sum over d of N_d ((lambda + 1) delta(d, 0) + lambda delta(d, 1)))."""
+    from . import DELTA, ELEMENTS
+    d = DELTA[ELEMENTS[name]]
+    counts = (base.n_vertices, base.n_edges, base.n_cells)
+    n = sum(counts[k] * ((n_layers + 1) * d[2 * k] + n_layers * d[2 * k + 1]) for k in range(3))
+    nx = base.n_vertices * (n_layers + 1)
+    lists = 4 * base.n_cells * ARITY[name] + (4 * base.n_cells * 6 if name != "P1" else 0)
+    inc = name in CONTINUOUS
+    alg = 8 * n + 8 * n * (2 if inc else 1) + 8 * nx + 16 * base.n_vertices + lists
+    return dict(algorithmic=alg, valuable=8 * n * 2 + 24 * nx, n_dofs=n)
+
+
 def mass_bytes(e: Extruded, name: str) -> dict:
-    """Byte counts of one y = M x / residual assembly on space `name`."""
+    """Byte counts of one y = M x / residual assembly on space `name`:
+    ``algorithmic`` (what the loop must move, with (x, y) once per vertex
+    column, since columns are vertical), ``algorithmic_full_coords`` (the
+    same with all three coordinate components at every extruded vertex, as
+    if the field were read whole), and the paper's ``valuable`` volume."""
     n = e.space(name).n_dofs
     inc = name in CONTINUOUS
-    alg = 8 * n + 8 * n * (2 if inc else 1) + coord_bytes(e) + map_bytes(e, name)
-    valuable = 8 * n * 2 + 24 * e.Vx.n_dofs
-    return dict(algorithmic=alg, valuable=valuable, n_dofs=n)
+    io = 8 * n + 8 * n * (2 if inc else 1) + map_bytes(e, name)
+    return dict(algorithmic=io + coord_bytes(e), algorithmic_full_coords=io + 24 * e.Vx.n_dofs,
+                valuable=8 * n * 2 + 24 * e.Vx.n_dofs, n_dofs=n)
 
 
 def cubic_bytes(e: Extruded, fused: bool) -> dict:

@@ -46,3 +46,15 @@ def test_batch_shapes():
     for it in items:
         assert 10 <= it.n_layers <= 150
         assert it.mesh.n_cells >= 2
+
+
+def test_byte_counts_from_entity_counts():
+    # the closed-form DoF counts of the byte model (no device needed)
+    from paper_1604_05937_amd import workloads as W
+    base = meshgen.tri_square(512)
+    p1 = W.mass_bytes_counts(base, 100, "P1")
+    d0 = W.mass_bytes_counts(base, 100, "DG0")
+    assert p1["n_dofs"] == 26580069 and d0["n_dofs"] == 52428800
+    # K1: f + b (read and written) + z + (x, y) per base vertex + the 6-entry lists
+    assert p1["algorithmic"] == 867355824
+    assert p1["valuable"] == 8 * 26580069 * 2 + 24 * 26580069
