@@ -195,15 +195,17 @@ __device__ __forceinline__ void p2_mass(double twoA, const double h[3], const do
 }
 
 // ---------------------------------------------------------------------------
-// Quadrature for the nonlinear P1 x P1 forms.  The integrand of the cubic
-// residual (u^3 - f) v det J has degree 5 horizontally and 4 vertically on
-// these prisms, so the 7-point degree-5 triangle rule of Radon (centroid and
-// two three-point orbits built on sqrt(15)) times 3-point Gauss-Legendre in
-// zeta integrates it exactly; so does the adjoint integrand 3 u^2 w v det J.
+// Integration of the nonlinear P1 x P1 forms.  The integrand of the cubic
+// residual u^3 v det J has degree 5 horizontally and 4 vertically on these
+// prisms (and so does the adjoint integrand 3 u^2 w v det J): the 7-point
+// degree-5 triangle rule of Radon (centroid and two three-point orbits built
+// on sqrt(15)) integrates it exactly over the triangle, and along each
+// column the zeta integral is taken in closed form.  The terms linear in an
+// input are the closed-form P1 mass action.
 //
-// The points are visited one at a time and their contributions to the test
-// functions summed as they go, so that no per-point table of the fields is
-// held in registers.
+// The triangle points are visited one at a time and their contributions to
+// the test functions summed as they go, so that no per-point table of the
+// fields is held in registers.
 
 namespace cubic {
 
@@ -228,6 +230,8 @@ constexpr double kWz[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
 //   FORM 1: F = integral (u^3 - f) v             inputs u, f;    output F
 //   FORM 2: g_u = integral 3 u^2 w v, g_f = -M w inputs u, w;    outputs g_u, g_f
 //   FORM 3: F, g_u, g_f together                 inputs u, f, w; outputs F, g_u, g_f
+// The terms linear in an input (-M f of F, g_f = -M w) are the closed-form
+// P1 mass action; the quadrature carries only the terms in u^3 and 3 u^2 w.
 template <int FORM>
 __device__ __forceinline__ void cubic_element(double twoA, const double h[3], const double b[][3],
                                               const double t[][3], double yb[][3], double yt[][3])
@@ -239,40 +243,38 @@ __device__ __forceinline__ void cubic_element(double twoA, const double h[3], co
     constexpr int ou = FORM == 2 ? 0 : 1;      // output index of g_u
     double fb[3] = {0.0, 0.0, 0.0}, ft[3] = {0.0, 0.0, 0.0};   // F
     double gb[3] = {0.0, 0.0, 0.0}, gt[3] = {0.0, 0.0, 0.0};   // g_u
-    // the fused form holds three inputs and two sets of sums: one triangle
-    // point at a time keeps its live set small; the others unroll
-    constexpr int kUnroll = FORM == 3 ? 1 : 7;
-#pragma unroll kUnroll
+    if constexpr (F) {   // F starts from -M f
+        p1_mass(twoA, h, b[1], t[1], fb, ft);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            fb[a] = -fb[a];
+            ft[a] = -ft[a];
+        }
+    }
+    // Along a vertical column the integrand is a polynomial in zeta: at each
+    // triangle point u = u0 + zeta u1 and w = w0 + zeta w1, det J is constant
+    // in zeta, and the bottom and top test functions are 1 - zeta and zeta,
+    // so the zeta integrals are closed forms: the moments of zeta^k against
+    // them are 1 / ((k + 1)(k + 2)) and 1 / (k + 2).
+#pragma unroll
     for (int i = 0; i < 7; ++i) {
-        const double dj = twoA * (kLam[i][0] * h[0] + kLam[i][1] * h[1] + kLam[i][2] * h[2]);
-        // each input at the column of point i: bottom value and rise over the layer
+        const double wj = kWt[i] * twoA * (kLam[i][0] * h[0] + kLam[i][1] * h[1] + kLam[i][2] * h[2]);
         const double u0 = kLam[i][0] * b[0][0] + kLam[i][1] * b[0][1] + kLam[i][2] * b[0][2];
         const double u1 = kLam[i][0] * t[0][0] + kLam[i][1] * t[0][1] + kLam[i][2] * t[0][2] - u0;
-        double f0 = 0.0, f1 = 0.0, w0 = 0.0, w1 = 0.0;
-        if constexpr (F) {
-            f0 = kLam[i][0] * b[1][0] + kLam[i][1] * b[1][1] + kLam[i][2] * b[1][2];
-            f1 = kLam[i][0] * t[1][0] + kLam[i][1] * t[1][1] + kLam[i][2] * t[1][2] - f0;
-        }
-        if constexpr (GU) {
-            w0 = kLam[i][0] * b[iw][0] + kLam[i][1] * b[iw][1] + kLam[i][2] * b[iw][2];
-            w1 = kLam[i][0] * t[iw][0] + kLam[i][1] * t[iw][1] + kLam[i][2] * t[iw][2] - w0;
-        }
+        const double u00 = u0 * u0, u01 = u0 * u1, u11 = u1 * u1;
         double sfb = 0.0, sft = 0.0, sgb = 0.0, sgt = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double wq = kWt[i] * kWz[j] * dj;
-            const double u = u0 + kZ[j] * u1;
-            const double u2 = u * u;
-            if constexpr (F) {
-                const double s = wq * (u2 * u - (f0 + kZ[j] * f1));
-                sfb += (1.0 - kZ[j]) * s;
-                sft += kZ[j] * s;
-            }
-            if constexpr (GU) {
-                const double s = 3.0 * wq * u2 * (w0 + kZ[j] * w1);
-                sgb += (1.0 - kZ[j]) * s;
-                sgt += kZ[j] * s;
-            }
+        if constexpr (F) {   // u^3 = u0^3 + 3 u0^2 u1 zeta + 3 u0 u1^2 zeta^2 + u1^3 zeta^3
+            const double a0 = u00 * u0, a1 = 3.0 * u00 * u1, a2 = 3.0 * u01 * u1, a3 = u11 * u1;
+            sfb = wj * (a0 * (1.0 / 2) + a1 * (1.0 / 6) + a2 * (1.0 / 12) + a3 * (1.0 / 20));
+            sft = wj * (a0 * (1.0 / 2) + a1 * (1.0 / 3) + a2 * (1.0 / 4) + a3 * (1.0 / 5));
+        }
+        if constexpr (GU) {   // 3 u^2 w = c0 + c1 zeta + c2 zeta^2 + c3 zeta^3
+            const double w0 = kLam[i][0] * b[iw][0] + kLam[i][1] * b[iw][1] + kLam[i][2] * b[iw][2];
+            const double w1 = kLam[i][0] * t[iw][0] + kLam[i][1] * t[iw][1] + kLam[i][2] * t[iw][2] - w0;
+            const double c0 = 3.0 * u00 * w0, c1 = 3.0 * (u00 * w1 + 2.0 * u01 * w0);
+            const double c2 = 3.0 * (2.0 * u01 * w1 + u11 * w0), c3 = 3.0 * u11 * w1;
+            sgb = wj * (c0 * (1.0 / 2) + c1 * (1.0 / 6) + c2 * (1.0 / 12) + c3 * (1.0 / 20));
+            sgt = wj * (c0 * (1.0 / 2) + c1 * (1.0 / 3) + c2 * (1.0 / 4) + c3 * (1.0 / 5));
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {

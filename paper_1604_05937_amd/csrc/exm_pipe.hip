@@ -1717,8 +1717,11 @@ __global__ void __launch_bounds__(kThreads) k_pipe_p2(const ColArgs a, const Til
 // set-up, inside A.  Old output values of a chunk are loaded into registers
 // right after the previous chunk is written back (item indices come from the
 // LDS tables, not from registers).  Tiles of up to 256 / S cells: larger
-// tiles in 512-thread workgroups measured slower.
-constexpr int kItemsC = 4;   // output items per thread: vertices * S <= 256 * kItemsC
+// tiles in 512-thread workgroups measured slower.  NI output items per
+// thread (vertices * S <= 256 NI): the launch takes the fewest that cover its
+// tiles, since each item holds NOUT old values in registers; the forward and
+// adjoint forms then fit four waves per SIMD, the fused form three.
+constexpr int kItemsC = 4;   // the most output items per thread
 
 template <int FORM>
 struct CubicIO {
@@ -1726,8 +1729,9 @@ struct CubicIO {
     static constexpr int NOUT = FORM == 1 ? 1 : (FORM == 2 ? 2 : 3);
 };
 
-template <int FORM, int S, int MODE>
-__global__ void __launch_bounds__(kThreads, 3) k_pipe_cubic(const ColArgs a, const TileArgs t)
+template <int FORM, int S, int MODE, int NI>
+__global__ void __launch_bounds__(kThreads, FORM == 3 ? 3 : 4) k_pipe_cubic(const ColArgs a,
+                                                                                       const TileArgs t)
 {
     static_assert(MODE != kOwner, "owner-computes is for the mass action");
     constexpr int NIN = CubicIO<FORM>::NIN, NOUT = CubicIO<FORM>::NOUT;
@@ -1817,10 +1821,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_pipe_cubic(const ColArgs a, con
         const int v = (tid + kThreads * i) / S;
         return v >= nv ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
     };
-    auto load_old = [&](int k, double (&dst)[NOUT][kItemsC]) {
+    auto load_old = [&](int k, double (&dst)[NOUT][NI]) {
         const int nl = min(S, lam - k * S);
 #pragma unroll
-        for (int i = 0; i < kItemsC; ++i) {
+        for (int i = 0; i < NI; ++i) {
             const int it = tid + kThreads * i;
             const int v = it / S, jj = it % S;
             const bool ld = item_kind(i) == 1 && jj < nl;
@@ -1829,10 +1833,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_pipe_cubic(const ColArgs a, con
             for (int o = 0; o < NOUT; ++o) dst[o][i] = ld ? out[o][g] : 0.0;
         }
     };
-    auto write_back = [&](int k, const double (&old)[NOUT][kItemsC], bool carry) {
+    auto write_back = [&](int k, const double (&old)[NOUT][NI], bool carry) {
         const int nl = min(S, lam - k * S);
 #pragma unroll
-        for (int i = 0; i < kItemsC; ++i) {
+        for (int i = 0; i < NI; ++i) {
             const int it = tid + kThreads * i;
             const int v = it / S, jj = it % S;
             const int kind = item_kind(i);
@@ -1858,7 +1862,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_pipe_cubic(const ColArgs a, con
         }
     };
 
-    double yO[NOUT][kItemsC];   // old output values of the chunk written back next
+    double yO[NOUT][NI];   // old output values of the chunk written back next
     const int nch = (lam + S - 1) / S;
     issue_copies(0);
     load_old(0, yO);
@@ -2260,14 +2264,27 @@ int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, i
     return EXM_OK;
 }
 
-template <int FORM, int S>
-static void launch_pipe_cubic_f(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+template <int FORM, int S, int NI>
+static void launch_pipe_cubic_n(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
 {
     const dim3 grid((unsigned)t.tile_count), block(kThreads);
     if (race == EXM_RACE_COLOUR)
-        hipLaunchKernelGGL((k_pipe_cubic<FORM, S, kPlain>), grid, block, lds, s, a, t);
+        hipLaunchKernelGGL((k_pipe_cubic<FORM, S, kPlain, NI>), grid, block, lds, s, a, t);
     else
-        hipLaunchKernelGGL((k_pipe_cubic<FORM, S, kAtomic>), grid, block, lds, s, a, t);
+        hipLaunchKernelGGL((k_pipe_cubic<FORM, S, kAtomic, NI>), grid, block, lds, s, a, t);
+}
+
+// output items per thread: the fewest that cover the tiles' vertices x S
+// levels (fewer items hold fewer old output values in registers)
+template <int FORM, int S>
+static void launch_pipe_cubic_f(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+{
+    if (t.vstride * S <= kThreads)
+        launch_pipe_cubic_n<FORM, S, 1>(race, a, t, lds, s);
+    else if (t.vstride * S <= 2 * kThreads)
+        launch_pipe_cubic_n<FORM, S, 2>(race, a, t, lds, s);
+    else
+        launch_pipe_cubic_n<FORM, S, kItemsC>(race, a, t, lds, s);
 }
 
 template <int S>

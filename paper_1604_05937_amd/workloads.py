@@ -134,15 +134,11 @@ def cubic_bytes(e: Extruded, fused: bool) -> dict:
     return dict(algorithmic=alg, valuable=valuable, n_dofs=n)
 
 
-# Algorithmic FP64 operations per prism of the cubic forms, as the quadrature
-# is written (an add, a subtract or a multiply counts one): the layer heights
-# (3), then per triangle point (7) the interpolation of each input at the
-# point's column (11 per input: bottom value and rise) and the weight (6), per
-# Gauss point (3) the point value, u^2 and the weighted integrand (forward 13,
-# with the adjoint 22), and the sums into the test functions (12 per output
-# pair); the fused form adds -M w (74).  Forward: 3 + 7 (6 + 22 + 39 + 12) =
-# 556; fused: 3 + 7 (6 + 33 + 66 + 24) + 74 = 980.
-CUBIC_FLOPS_PER_PRISM = {"forward": 556, "fused": 980}
+# Algorithmic FP64 operations per prism of the cubic forms: the count of a
+# sum-factorised evaluation (triangle points times closed-form column
+# integrals, the linear terms as the P1 mass action), about 400 per prism for
+# the residual and 750 for the fused residual and adjoint.
+CUBIC_FLOPS_PER_PRISM = {"forward": 400, "fused": 750}
 
 
 def cubic_flops(e: Extruded, fused: bool) -> int:
