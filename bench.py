@@ -212,7 +212,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["p1", "dg0", "triad", "batch", "cpu"],
+    ap.add_argument("--only", choices=["p1", "dg0", "triad", "batch", "cpu", "cubic", "fused"],
                     help="launch only this kernel, warmup + steps times, and print nothing (for rocprofv3)")
     ap.add_argument("--config", default=None,
                     help="with --only: the launch configuration as JSON (exm_loop_opts fields) instead of autotuning")
@@ -272,6 +272,28 @@ def main():
         torch.cuda.synchronize()
         log(f"done: batch, tiles P1 {B.tiles('P1')} DG0 {B.tiles('DG0')}, algorithmic bytes per replay "
             f"P1 {bytes_p1} DG0 {bytes_dg0}")
+        return
+    if args.only in ("cubic", "fused"):
+        # the cubic residual (or its fused residual + adjoint) on 256 x 256 x 50, autotuned
+        e4 = W.extruded(256, 50)
+        V = e4.Vx
+        u = W.device_values(V.n_dofs, 31)
+        f = W.device_values(V.n_dofs, 32)
+        w = W.device_values(V.n_dofs, meshgen.SEED_COTAN)
+        F, gu, gf = V.zeros(), V.zeros(), V.zeros()
+        R, I = exm.EXM_READ, exm.EXM_INC
+        if args.only == "cubic":
+            k, fields = exm.EXM_K_CUBIC, [(u, V, R), (f, V, R), (F, V, I)]
+        else:
+            k, fields = exm.EXM_K_CUBIC_FUSED, [(u, V, R), (f, V, R), (w, V, R), (F, V, I), (gu, V, I), (gf, V, I)]
+        cfg = json.loads(args.config) if args.config else exm.autotune(k, e4.mesh, e4.X, V, fields)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup + args.steps):
+            exm.par_loop(k, e4.mesh, e4.X, V, fields, **cfg)
+        torch.cuda.synchronize()
+        by = W.cubic_bytes(e4, args.only == "fused")["algorithmic"]
+        log(f"done: {args.only} {cfg}, {by} algorithmic bytes and {W.cubic_flops(e4, args.only == 'fused')} "
+            f"algorithmic FP64 operations per launch")
         return
     t0 = time.time()
     work = W.extruded(512, 100, keep_host_coords=not args.no_cpu)

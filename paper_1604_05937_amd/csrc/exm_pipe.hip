@@ -31,6 +31,7 @@
 // when the column start is odd (the parity is fixed because S is even).
 // Base pointers must be 16-byte aligned; the host checks.
 #include <algorithm>
+#include <type_traits>
 
 #include "exm_elements.hpp"
 #include "exm_tiled.hpp"
@@ -1730,7 +1731,7 @@ struct CubicIO {
 };
 
 template <int FORM, int S, int MODE, int NI>
-__global__ void __launch_bounds__(kThreads, FORM == 3 ? 3 : 4) k_pipe_cubic(const ColArgs a,
+__global__ void __launch_bounds__(kThreads, FORM == 3 && NI > 1 ? 3 : 4) k_pipe_cubic(const ColArgs a,
                                                                                        const TileArgs t)
 {
     static_assert(MODE != kOwner, "owner-computes is for the mass action");
@@ -1879,26 +1880,37 @@ __global__ void __launch_bounds__(kThreads, FORM == 3 ? 3 : 4) k_pipe_cubic(cons
         if (k + 1 < nch) issue_copies(k + 1);
         if (!has || r >= nl) continue;
         const double* const Zb = Zs + b * VS;
-        double h[3], vbot[NIN][3], vtop[NIN][3], yb[NOUT][3], yt[NOUT][3];
+        double h[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) h[q] = Zb[vb[q] + r + 1] - Zb[vb[q] + r];
+        // the element of inputs i0, i1 (u and f, or u and w) into outputs o0 ..
+        auto element = [&](auto form, int i1, int o0) {
+            constexpr int EF = decltype(form)::value;
+            constexpr int NO = EF == 1 ? 1 : 2;
+            double vbot[2][3], vtop[2][3], yb[NO][3], yt[NO][3];
 #pragma unroll
-        for (int i = 0; i < NIN; ++i) {
-            const double* const Xb = Xs + (b * NIN + i) * VS;
+            for (int i = 0; i < 2; ++i) {
+                const double* const Xb = Xs + (b * NIN + (i == 0 ? 0 : i1)) * VS;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                vbot[i][q] = Xb[vb[q] + r];
-                vtop[i][q] = Xb[vb[q] + r + 1];
+                for (int q = 0; q < 3; ++q) {
+                    vbot[i][q] = Xb[vb[q] + r];
+                    vtop[i][q] = Xb[vb[q] + r + 1];
+                }
             }
-        }
-        cubic_element<FORM>(twoA, h, vbot, vtop, yb, yt);
+            cubic_element<EF>(twoA, h, vbot, vtop, yb, yt);
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o)
+            for (int o = 0; o < NO; ++o)
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                lds_add(A + o * VS + vb[q] + r, yb[o][q]);
-                lds_add(A + o * VS + vb[q] + r + 1, yt[o][q]);
-            }
+                for (int q = 0; q < 3; ++q) {
+                    lds_add(A + (o0 + o) * VS + vb[q] + r, yb[o][q]);
+                    lds_add(A + (o0 + o) * VS + vb[q] + r + 1, yt[o][q]);
+                }
+        };
+        // the fused form runs the residual, then the adjoint, on one prism:
+        // half the live values of evaluating both at once
+        if constexpr (FORM == 1 || FORM == 3) element(std::integral_constant<int, 1>{}, 1, 0);
+        if constexpr (FORM == 2) element(std::integral_constant<int, 2>{}, 1, 0);
+        if constexpr (FORM == 3) element(std::integral_constant<int, 2>{}, 2, 1);
     }
     // write back the last chunk, its top level included
     lds_barrier();
