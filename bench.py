@@ -535,18 +535,25 @@ def secondary(torch, exm, W, meshgen):
     import numpy as np
     out = {}
     # the RHS on the paper's nine spaces ({CG1, DG0, DG1} horizontally x vertically), 256 x 256 x 64
+    # (working sets of 30-900 MB, some inside the 256 MB MALL: each is also
+    # timed with the caches flushed before every launch)
     e9 = W.extruded(256, 64)
     nine = {}
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     for name in ("P1", "CG1xDG0", "CG1xDG1", "DG0xCG1", "DG0", "DG0xDG1", "DG1xCG1", "DG1xDG0", "DG1"):
         V = e9.space(name)
         x = W.device_values(V.n_dofs, meshgen.SEED_FIELD)
         y = V.zeros()
         cfg = exm.autotune(exm.EXM_K_MASS, e9.mesh, e9.X, e9.Vx, W.mass_args(e9, name, x, y))
         t, _ = timed(torch, lambda: W.run_mass(e9, name, x, y, **cfg), 10)
+        tf, _ = timed_flushed(torch, lambda: W.run_mass(e9, name, x, y, **cfg), 10, flush)
         b = W.mass_bytes(e9, name)
         nine[name] = {"ms": round(t, 4), "gbs": round(b["algorithmic"] / t / 1e6, 1),
-                      "dofs_per_s": round(V.n_dofs / t * 1e3), "schedule": cfg["schedule"]}
+                      "dofs_per_s": round(V.n_dofs / t * 1e3), "schedule": cfg["schedule"],
+                      "working_set_mb": round(b["algorithmic"] / 1e6, 1),
+                      "flushed": {"ms": round(tf, 4), "gbs": round(b["algorithmic"] / tf / 1e6, 1)}}
         del x, y
+    del flush
     out["rhs_nine_spaces_256x256x64"] = nine
     log("nine spaces: " + ", ".join(f"{k} {v['gbs']:.0f}" for k, v in nine.items()))
     del e9
@@ -595,9 +602,13 @@ def secondary(torch, exm, W, meshgen):
     margs = [(x, Vm, exm.EXM_READ), (y, Vm, exm.EXM_WRITE)]
     cfg = exm.autotune(exm.EXM_K_MASS, em.mesh, em.X, em.Vx, margs)
     t, _ = timed(torch, lambda: exm.par_loop(exm.EXM_K_MASS, em.mesh, em.X, em.Vx, margs, **cfg), 10)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    tf, _ = timed_flushed(torch, lambda: exm.par_loop(exm.EXM_K_MASS, em.mesh, em.X, em.Vx, margs, **cfg), 10, flush)
+    del flush
     mbytes = 16 * Vm.n_dofs + W.coord_bytes(em) + 4 * (em.base.n_cells + 1) + 4 * int(nd.sum()) + 24 * em.base.n_cells
     out["mass_dg_mixed_degree_256x256x64"] = {"dofs": Vm.n_dofs, "ms": round(t, 4),
-                                              "gbs": round(mbytes / t / 1e6, 1), "launch": cfg}
+                                              "gbs": round(mbytes / t / 1e6, 1), "launch": cfg,
+                                              "flushed": {"ms": round(tf, 4), "gbs": round(mbytes / tf / 1e6, 1)}}
     log(f"mixed-degree DG mass {t:.3f} ms")
     del x, y, Vm, em
     # horizontal facets (lambda + 1 per column), the jump form: DG0 on 512 x 512 x 100, DG1 on 256 x 256 x 64
@@ -625,9 +636,14 @@ def secondary(torch, exm, W, meshgen):
         args_ = W.mass_args(e3, name, x, y)
         cfg = exm.autotune(exm.EXM_K_MASS, e3.mesh, e3.X, e3.Vx, args_)
         t, _ = timed(torch, lambda: W.run_mass(e3, name, x, y), 10)
+        flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        tf, _ = timed_flushed(torch, lambda: W.run_mass(e3, name, x, y), 10, flush)
+        del flush
         b = W.mass_bytes(e3, name)
         out[f"mass_{name.lower()}_256x256x64"] = {"ms": round(t, 4), "gbs": round(b["algorithmic"] / t / 1e6, 1),
-                                                  "launch": cfg}
+                                                  "launch": cfg,
+                                                  "flushed": {"ms": round(tf, 4),
+                                                              "gbs": round(b["algorithmic"] / tf / 1e6, 1)}}
         log(f"mass {name}: {t:.3f} ms")
         del x, y
     del e3
