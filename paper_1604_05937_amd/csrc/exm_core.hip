@@ -1,5 +1,7 @@
 // Handles, validation and the numbering builder (Algorithms 1 and 2) of
 // libexm.so, plus the base-cell colouring and the STREAM triad.
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
 #include <cstring>
 
@@ -234,6 +236,11 @@ static int32_t mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
         if ((s = m->d_cell_lo.upload(m->lo[2].data(), m->lo[2].size())) != EXM_OK) return s;
         if ((s = m->d_vert_lo.upload(m->lo[0].data(), m->lo[0].size())) != EXM_OK) return s;
         if ((s = m->d_vert_hi.upload(m->hi[0].data(), m->hi[0].size())) != EXM_OK) return s;
+        if ((s = m->d_cell_hi.upload(m->hi[2].data(), m->hi[2].size())) != EXM_OK) return s;
+        if (n_edges > 0) {
+            if ((s = m->d_edge_lo.upload(m->lo[1].data(), m->lo[1].size())) != EXM_OK) return s;
+            if ((s = m->d_edge_hi.upload(m->hi[1].data(), m->hi[1].size())) != EXM_OK) return s;
+        }
     }
     *out = m.release();
     return EXM_OK;
@@ -318,72 +325,152 @@ static bool element_delta(int32_t element, int32_t d[6])
 }
 
 // Algorithm 1 with a layer range per entity column: column sizes differ, so
-// the column starts are a prefix sum over the entities of each dimension (in
-// the order Algorithm 1 visits them); the explicit list of a cell is that of
-// its bottom prism, so that L(c) + l * offset still addresses layer l of the
-// cell's column.  Built on the host (the ranges are host data) and uploaded.
-static int32_t space_create_var(const exm_mesh* mesh, const int32_t* delta, std::unique_ptr<exm_space> s,
-                                exm_space** out)
+// the column starts are one exclusive prefix sum of the column sizes over the
+// entities in the order Algorithm 1 visits them (dimension-major, then by
+// index); the explicit list of a cell is that of its bottom prism, so that
+// L(c) + l * offset still addresses layer l of the cell's column.  Built on
+// the device: the sizes, the scan, then the lists and the int32 starts.
+
+// Size of the column of entity i (levels lo .. hi, hi - lo layers).
+__global__ void k_var_col_sizes(int32_t n, const int32_t* __restrict__ lo, const int32_t* __restrict__ hi,
+                                int32_t dh, int32_t dv, int64_t* __restrict__ size)
 {
-    std::vector<int64_t> start[3];
-    int64_t c = 0;
-    for (int d = 0; d < 3; ++d) {
-        s->base[d] = c;
-        s->col_size[d] = -1;   // columns differ in size
-        start[d].resize(mesh->n[d]);
-        for (int32_t i = 0; i < mesh->n[d]; ++i) {
-            start[d][i] = c;
-            const int64_t nl = mesh->hi[d][i] - mesh->lo[d][i];
-            c += (nl + 1) * delta[2 * d] + nl * delta[2 * d + 1];
-        }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t nl = (int64_t)hi[i] - lo[i];
+    size[i] = (nl + 1) * dh + nl * dv;
+}
+
+__global__ void k_var_starts(int32_t n, const int64_t* __restrict__ start, int32_t has, int32_t* __restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = has ? (int32_t)start[i] : -1;
+}
+
+// One position of a cell's explicit list on columns of different heights:
+// closure entity e (0..2 vertex, 3..5 edge, 6 cell), its DoFs per level
+// (Algorithm 2's offset) and the DoF's place within the level.
+struct VarPos {
+    int32_t entity;
+    int32_t per_level;
+    int32_t shift;
+};
+
+// start: the column starts of all entities in visiting order (vertices, then
+// edges from first_edge, then cells from first_cell); lo: the first level of
+// every entity column, per dimension.
+__global__ void k_var_bottom_map(int32_t n_cells, int32_t k, const VarPos* __restrict__ pos,
+                                 const int32_t* __restrict__ cell_vertex, const int32_t* __restrict__ cell_edge,
+                                 const int64_t* __restrict__ start, int64_t first_edge, int64_t first_cell,
+                                 const int32_t* __restrict__ lo0, const int32_t* __restrict__ lo1,
+                                 const int32_t* __restrict__ lo2, int32_t* __restrict__ map)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_cells * k) return;
+    const int64_t c = t / k;
+    const int32_t p = (int32_t)(t - c * k);
+    const VarPos vp = pos[p];
+    const int32_t b = lo2[c];   // the cell's first layer
+    int64_t s;
+    int32_t l;
+    if (vp.entity < 3) {
+        const int32_t v = cell_vertex[c * 3 + vp.entity];
+        s = start[v];
+        l = lo0[v];
+    } else if (vp.entity < 6) {
+        const int32_t e = cell_edge[c * 3 + vp.entity - 3];
+        s = start[first_edge + e];
+        l = lo1[e];
+    } else {
+        s = start[first_cell + c];
+        l = b;
     }
-    s->n_dofs = c;
+    map[t] = (int32_t)(s + (int64_t)(b - l) * vp.per_level + vp.shift);
+}
+
+static int32_t space_create_var(const exm_mesh* mesh, const int32_t* delta, std::unique_ptr<exm_space> s,
+                                hipStream_t hs, exm_space** out)
+{
+    const int64_t n0 = mesh->n[0], n1 = mesh->n[1], n2 = mesh->n[2];
+    const int64_t ntot = n0 + n1 + n2;
+    EXM_CHECK(ntot < INT32_MAX, EXM_EOVERFLOW, "%lld entity columns exceed the int32 range", (long long)ntot);
+    DevBuf<int64_t> size, start;
+    int32_t st;
+    if ((st = size.alloc((size_t)ntot)) != EXM_OK) return st;
+    if ((st = start.alloc((size_t)ntot)) != EXM_OK) return st;
+    const int bs = 256;
+    const int32_t* los[3] = {mesh->d_vert_lo.p, mesh->d_edge_lo.p, mesh->d_cell_lo.p};
+    const int32_t* his[3] = {mesh->d_vert_hi.p, mesh->d_edge_hi.p, mesh->d_cell_hi.p};
+    const int64_t first[3] = {0, n0, n0 + n1};
+    for (int d = 0; d < 3; ++d) {
+        const int32_t n = mesh->n[d];
+        if (n == 0) continue;
+        if (delta[2 * d] + delta[2 * d + 1] == 0) {   // no DoFs: columns of size 0
+            EXM_TRY_HIP(hipMemsetAsync(size.p + first[d], 0, sizeof(int64_t) * (size_t)n, hs));
+            continue;
+        }
+        EXM_CHECK(los[d] && his[d], EXM_EINVAL, "dimension %d carries DoFs but the mesh has no ranges for it", d);
+        hipLaunchKernelGGL(k_var_col_sizes, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, hs, n, los[d], his[d],
+                           delta[2 * d], delta[2 * d + 1], size.p + first[d]);
+        EXM_TRY_HIP(hipGetLastError());
+    }
+    size_t tmp_bytes = 0;
+    EXM_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, size.p, start.p, (int)ntot, hs));
+    DevBuf<unsigned char> tmp;
+    if ((st = tmp.alloc(tmp_bytes)) != EXM_OK) return st;
+    EXM_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tmp_bytes, size.p, start.p, (int)ntot, hs));
+    // read back: the last start and size (the DoF count) and where each dimension begins
+    int64_t last[2], dim0[3] = {0, -1, -1};
+    EXM_TRY_HIP(hipMemcpyAsync(&last[0], start.p + ntot - 1, sizeof(int64_t), hipMemcpyDeviceToHost, hs));
+    EXM_TRY_HIP(hipMemcpyAsync(&last[1], size.p + ntot - 1, sizeof(int64_t), hipMemcpyDeviceToHost, hs));
+    for (int d = 1; d < 3; ++d)
+        if (first[d] < ntot)
+            EXM_TRY_HIP(hipMemcpyAsync(&dim0[d], start.p + first[d], sizeof(int64_t), hipMemcpyDeviceToHost, hs));
+    EXM_TRY_HIP(hipStreamSynchronize(hs));
+    s->n_dofs = last[0] + last[1];
     EXM_CHECK(s->n_dofs < (int64_t)INT32_MAX, EXM_EOVERFLOW,
               "space has %lld DoFs; the int32 numbering allows at most %d", (long long)s->n_dofs, INT32_MAX - 1);
+    for (int d = 0; d < 3; ++d) {
+        s->base[d] = dim0[d] < 0 ? s->n_dofs : dim0[d];
+        s->col_size[d] = -1;   // columns differ in size: the starts are a table
+    }
     // stencil layout and offsets (Algorithm 2), as for uniform columns
-    std::vector<int32_t> row_ent, row_part, row_j;   // per position: closure entity 0..6, part (0 bottom, 1 top, 2 vertical), index
+    std::vector<VarPos> pos;
     for (int e = 0; e < 7; ++e) {
         const int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
         const int nh = delta[2 * d], nv = delta[2 * d + 1];
         for (int part = 0; part < 3; ++part) {
             const int cnt = part < 2 ? nh : nv;
             for (int j = 0; j < cnt; ++j) {
-                row_ent.push_back(e);
-                row_part.push_back(part);
-                row_j.push_back(j);
+                // bottom level: j; top level: the next level's horizontal DoFs; vertical entity: after nh
+                pos.push_back({e, nh + nv, (part == 1 ? nh + nv : (part == 2 ? nh : 0)) + j});
                 s->offsets.push_back(nh + nv);
                 s->entity_dim.push_back(d);
             }
         }
     }
     s->k = (int32_t)s->offsets.size();
-    const int32_t nc = mesh->n[2];
-    std::vector<int32_t> map((size_t)nc * s->k);
-    const int32_t* cv = mesh->h_cell_vertex.data();
-    const int32_t* ce = mesh->h_cell_edge.empty() ? nullptr : mesh->h_cell_edge.data();
-    for (int32_t cell = 0; cell < nc; ++cell) {
-        const int32_t b = mesh->lo[2][cell];   // the cell's first layer
-        for (int32_t p = 0; p < s->k; ++p) {
-            const int e = row_ent[p];
-            const int d = e < 3 ? 0 : (e < 6 ? 1 : 2);
-            const int32_t i = d == 0 ? cv[cell * 3 + e] : (d == 1 ? ce[cell * 3 + (e - 3)] : cell);
-            const int nh = delta[2 * d], nv = delta[2 * d + 1];
-            int64_t dof = start[d][i] + (int64_t)(b - mesh->lo[d][i]) * (nh + nv);
-            if (row_part[p] == 1) dof += nh + nv;          // top level: the next level's horizontal DoFs
-            else if (row_part[p] == 2) dof += nh;          // vertical entity of the layer
-            map[(size_t)cell * s->k + p] = (int32_t)(dof + row_j[p]);
-        }
+    const int64_t nmap = n2 * s->k;
+    if ((st = s->d_map.alloc((size_t)nmap)) != EXM_OK) return st;
+    DevBuf<VarPos> dpos;
+    if ((st = dpos.upload(pos.data(), pos.size())) != EXM_OK) return st;
+    if (nmap > 0) {
+        hipLaunchKernelGGL(k_var_bottom_map, dim3((unsigned)((nmap + bs - 1) / bs)), dim3(bs), 0, hs, mesh->n[2], s->k,
+                           dpos.p, mesh->d_cell_vertex.p, mesh->d_cell_edge.p, start.p, first[1], first[2],
+                           mesh->d_vert_lo.p, mesh->d_edge_lo.p, mesh->d_cell_lo.p, s->d_map.p);
+        EXM_TRY_HIP(hipGetLastError());
     }
-    int32_t st = s->d_map.upload(map.data(), map.size());
-    if (st != EXM_OK) return st;
     for (int d = 0; d < 3; ++d) {
-        if (mesh->n[d] == 0) continue;
-        const bool has = delta[2 * d] + delta[2 * d + 1] > 0;
-        std::vector<int32_t> h(mesh->n[d]);
-        for (int32_t i = 0; i < mesh->n[d]; ++i) h[i] = has ? (int32_t)start[d][i] : -1;
-        st = s->d_starts[d].upload(h.data(), h.size());
-        if (st != EXM_OK) return st;
+        const int32_t n = mesh->n[d];
+        if (n == 0) continue;
+        if ((st = s->d_starts[d].alloc((size_t)n)) != EXM_OK) return st;
+        hipLaunchKernelGGL(k_var_starts, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, hs, n, start.p + first[d],
+                           delta[2 * d] + delta[2 * d + 1] > 0 ? 1 : 0, s->d_starts[d].p);
+        EXM_TRY_HIP(hipGetLastError());
     }
+    // the scan buffers are freed on return: wait for the kernels that read them
+    EXM_TRY_HIP(hipStreamSynchronize(hs));
     *out = s.release();
     return EXM_OK;
 }
@@ -415,7 +502,7 @@ int32_t exm_space_create(const exm_mesh* mesh, const int32_t* delta, int32_t ele
     s->mesh = mesh;
     s->element = element;
     std::memcpy(s->delta, delta, sizeof(s->delta));
-    if (mesh->variable) return space_create_var(mesh, delta, std::move(s), out);
+    if (mesh->variable) return space_create_var(mesh, delta, std::move(s), (hipStream_t)stream, out);
     int64_t base = 0;
     for (int d = 0; d < 3; ++d) {
         int64_t cs = (lam + 1) * delta[2 * d] + lam * delta[2 * d + 1];

@@ -124,6 +124,8 @@ struct exm_mesh {
     exm::DevBuf<int32_t> d_cell_lam;     // variable: layers of every cell column
     exm::DevBuf<int32_t> d_cell_lo;      // variable: first layer of every cell column
     exm::DevBuf<int32_t> d_vert_lo, d_vert_hi;   // variable: level range of every vertex column
+    exm::DevBuf<int32_t> d_edge_lo, d_edge_hi;   // variable: ... of every edge column
+    exm::DevBuf<int32_t> d_cell_hi;              // variable: last layer + 1 of every cell column
     std::vector<int32_t> h_cell_vertex, h_cell_edge;
     exm::DevBuf<int32_t> d_cell_vertex, d_cell_edge;
     mutable std::mutex mu;
