@@ -225,6 +225,154 @@ constexpr double kWz[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
 
 }  // namespace cubic
 
+// The terms in u^3 and 3 u^2 w of the nonlinear P1 x P1 forms on one prism,
+// added to the bottom and top rows fb, ft (F) and gb, gt (g_u); ub, ut and
+// wb, wt are the bottom and top nodal values of u and w at the three
+// vertices.  Along a vertical column det J is constant in zeta and, at a
+// triangle point, u and w are linear in zeta between their bottom and top
+// values there, so the zeta integrals against the test functions 1 - zeta
+// and zeta are closed forms.  Written in the Bernstein basis of degree 3
+// (a cubic c(zeta) with coefficients c_0 .. c_3 against C(3,k) (1 - zeta)^(3-k)
+// zeta^k), the two moments are (4 c_0 + 3 c_1 + 2 c_2 + c_3) / 20 and
+// (c_0 + 2 c_1 + 3 c_2 + 4 c_3) / 20.  For u^3 the coefficients are
+// ub^(3-k) ut^k; for u^2 w they are ub^2 wb, (ub^2 wt + 2 ub ut wb) / 3,
+// (2 ub ut wt + ut^2 wb) / 3 and ut^2 wt; grouped by p = ub^2, q = ut^2 and
+// r = ub ut below.
+//
+// Every point of the triangle rule is the centroid or one of the three
+// permutations of (a, a, b) of an orbit, so a linear field at the orbit point
+// with b on vertex k is a X + (b - a) x_k (X the sum over the three vertices),
+// and the sum over an orbit of lambda_j s is a (the orbit's sum of s) +
+// (b - a) s at the point with b on vertex j; at the centroid both are a
+// third of the sums.
+template <bool F, bool GU>
+__device__ __forceinline__ void cubic_points_orbits(double twoA, const double h[3], const double ub[3],
+                                                    const double ut[3], const double wb[3], const double wt[3],
+                                                    double fb[3], double ft[3], double gb[3], double gt[3])
+{
+    using namespace cubic;
+    const double Hs = h[0] + h[1] + h[2];
+    const double U0 = ub[0] + ub[1] + ub[2], U1 = ut[0] + ut[1] + ut[2];
+    double W0 = 0.0, W1 = 0.0;
+    if constexpr (GU) {
+        W0 = wb[0] + wb[1] + wb[2];
+        W1 = wt[0] + wt[1] + wt[2];
+    }
+    // the moments at one point: weight cw (rule weight / 20 times 2A), column
+    // height hq, u and w at the bottom and top
+    auto point = [&](double cw, double hq, double u0, double u1, double w0, double w1, double& sfb, double& sft,
+                     double& sgb, double& sgt) {
+        const double wj = cw * hq;
+        const double p = u0 * u0, q = u1 * u1;
+        if constexpr (F) {
+            sfb = wj * (p * (4.0 * u0 + 3.0 * u1) + q * (2.0 * u0 + u1));
+            sft = wj * (p * (u0 + 2.0 * u1) + q * (3.0 * u0 + 4.0 * u1));
+        }
+        if constexpr (GU) {
+            const double r = u0 * u1, w3 = 3.0 * wj;
+            sgb = w3 * (p * (4.0 * w0 + w1) + r * (2.0 * w0 + (4.0 / 3.0) * w1) + q * ((2.0 / 3.0) * w0 + w1));
+            sgt = w3 * (p * (w0 + (2.0 / 3.0) * w1) + r * ((4.0 / 3.0) * w0 + 2.0 * w1) + q * (w0 + 4.0 * w1));
+        }
+    };
+    // parts of the rows common to the three vertices
+    double cfb, cft, cgb = 0.0, cgt = 0.0;
+    {
+        constexpr double t = 1.0 / 3.0;
+        double sfb = 0.0, sft = 0.0, sgb = 0.0, sgt = 0.0;
+        point(kWt[0] * (1.0 / 20.0) * twoA, t * Hs, t * U0, t * U1, t * W0, t * W1, sfb, sft, sgb, sgt);
+        cfb = t * sfb;
+        cft = t * sft;
+        if constexpr (GU) {
+            cgb = t * sgb;
+            cgt = t * sgt;
+        }
+    }
+    constexpr double kOa[2] = {kA1, kA2}, kOb[2] = {kB1, kB2}, kOw[2] = {kW1, kW2};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const double a = kOa[m], d = kOb[m] - kOa[m];
+        const double cw = kOw[m] * (1.0 / 20.0) * twoA;
+        const double aH = a * Hs, aU0 = a * U0, aU1 = a * U1, aW0 = a * W0, aW1 = a * W1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double sfb = 0.0, sft = 0.0, sgb = 0.0, sgt = 0.0;
+            point(cw, aH + d * h[k], aU0 + d * ub[k], aU1 + d * ut[k], GU ? aW0 + d * wb[k] : 0.0,
+                  GU ? aW1 + d * wt[k] : 0.0, sfb, sft, sgb, sgt);
+            if constexpr (F) {
+                fb[k] += d * sfb;
+                ft[k] += d * sft;
+                cfb += a * sfb;
+                cft += a * sft;
+            }
+            if constexpr (GU) {
+                gb[k] += d * sgb;
+                gt[k] += d * sgt;
+                cgb += a * sgb;
+                cgt += a * sgt;
+            }
+            __builtin_amdgcn_sched_barrier(0);   // one point at a time: fewer live values
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if constexpr (F) {
+            fb[k] += cfb;
+            ft[k] += cft;
+        }
+        if constexpr (GU) {
+            gb[k] += cgb;
+            gt[k] += cgt;
+        }
+    }
+}
+
+// Both forms at once.  With w = u the moments of 3 u^2 w are three times
+// those of u^3, and both are linear in the second factor x (u for F, w for
+// g_u): (alpha x0 + beta x1, beta x0 + gamma x1) with alpha = 4p + 2r + 2q/3,
+// beta = p + q + 4r/3, gamma = 2p/3 + 2r + 4q, so one set of alpha, beta,
+// gamma per point serves both.  The points come from the table: the orbit
+// sums would cost this form its fourth wave per SIMD.
+__device__ __forceinline__ void cubic_points_both(double twoA, const double h[3], const double ub[3],
+                                                  const double ut[3], const double wb[3], const double wt[3],
+                                                  double fb[3], double ft[3], double gb[3], double gt[3])
+{
+    using namespace cubic;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const double wj =
+            (kWt[i] * (1.0 / 20.0)) * (twoA * (kLam[i][0] * h[0] + kLam[i][1] * h[1] + kLam[i][2] * h[2]));
+        const double u0 = kLam[i][0] * ub[0] + kLam[i][1] * ub[1] + kLam[i][2] * ub[2];
+        const double u1 = kLam[i][0] * ut[0] + kLam[i][1] * ut[1] + kLam[i][2] * ut[2];
+        const double w0 = kLam[i][0] * wb[0] + kLam[i][1] * wb[1] + kLam[i][2] * wb[2];
+        const double w1 = kLam[i][0] * wt[0] + kLam[i][1] * wt[1] + kLam[i][2] * wt[2];
+        const double p = u0 * u0, q = u1 * u1, r = u0 * u1;
+        const double al = 4.0 * p + 2.0 * r + (2.0 / 3.0) * q;
+        const double be = (p + q) + (4.0 / 3.0) * r;
+        const double ga = (2.0 / 3.0) * p + 2.0 * r + 4.0 * q;
+        const double w3 = 3.0 * wj;
+        const double sfb = wj * (al * u0 + be * u1), sft = wj * (be * u0 + ga * u1);
+        const double sgb = w3 * (al * w0 + be * w1), sgt = w3 * (be * w0 + ga * w1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            fb[a] += kLam[i][a] * sfb;
+            ft[a] += kLam[i][a] * sft;
+            gb[a] += kLam[i][a] * sgb;
+            gt[a] += kLam[i][a] * sgt;
+        }
+    }
+}
+
+template <bool F, bool GU>
+__device__ __forceinline__ void cubic_points(double twoA, const double h[3], const double ub[3], const double ut[3],
+                                             const double wb[3], const double wt[3], double fb[3], double ft[3],
+                                             double gb[3], double gt[3])
+{
+    if constexpr (F && GU)
+        cubic_points_both(twoA, h, ub, ut, wb, wt, fb, ft, gb, gt);
+    else
+        cubic_points_orbits<F, GU>(twoA, h, ub, ut, wb, wt, fb, ft, gb, gt);
+}
+
 // Nonlinear P1 x P1 element forms on one prism (b, t: bottom / top nodal
 // values of each input at the three vertices; yb, yt: outputs likewise).
 //   FORM 1: F = integral (u^3 - f) v             inputs u, f;    output F
@@ -236,7 +384,6 @@ template <int FORM>
 __device__ __forceinline__ void cubic_element(double twoA, const double h[3], const double b[][3],
                                               const double t[][3], double yb[][3], double yt[][3])
 {
-    using namespace cubic;
     constexpr bool F = FORM == 1 || FORM == 3;
     constexpr bool GU = FORM == 2 || FORM == 3;
     constexpr int iw = FORM == 2 ? 1 : 2;      // input index of w
@@ -251,43 +398,7 @@ __device__ __forceinline__ void cubic_element(double twoA, const double h[3], co
             ft[a] = -ft[a];
         }
     }
-    // Along a vertical column the integrand is a polynomial in zeta: at each
-    // triangle point u = u0 + zeta u1 and w = w0 + zeta w1, det J is constant
-    // in zeta, and the bottom and top test functions are 1 - zeta and zeta,
-    // so the zeta integrals are closed forms: the moments of zeta^k against
-    // them are 1 / ((k + 1)(k + 2)) and 1 / (k + 2).
-#pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        const double wj = kWt[i] * twoA * (kLam[i][0] * h[0] + kLam[i][1] * h[1] + kLam[i][2] * h[2]);
-        const double u0 = kLam[i][0] * b[0][0] + kLam[i][1] * b[0][1] + kLam[i][2] * b[0][2];
-        const double u1 = kLam[i][0] * t[0][0] + kLam[i][1] * t[0][1] + kLam[i][2] * t[0][2] - u0;
-        const double u00 = u0 * u0, u01 = u0 * u1, u11 = u1 * u1;
-        double sfb = 0.0, sft = 0.0, sgb = 0.0, sgt = 0.0;
-        if constexpr (F) {   // u^3 = u0^3 + 3 u0^2 u1 zeta + 3 u0 u1^2 zeta^2 + u1^3 zeta^3
-            const double a0 = u00 * u0, a1 = 3.0 * u00 * u1, a2 = 3.0 * u01 * u1, a3 = u11 * u1;
-            sfb = wj * (a0 * (1.0 / 2) + a1 * (1.0 / 6) + a2 * (1.0 / 12) + a3 * (1.0 / 20));
-            sft = wj * (a0 * (1.0 / 2) + a1 * (1.0 / 3) + a2 * (1.0 / 4) + a3 * (1.0 / 5));
-        }
-        if constexpr (GU) {   // 3 u^2 w = c0 + c1 zeta + c2 zeta^2 + c3 zeta^3
-            const double w0 = kLam[i][0] * b[iw][0] + kLam[i][1] * b[iw][1] + kLam[i][2] * b[iw][2];
-            const double w1 = kLam[i][0] * t[iw][0] + kLam[i][1] * t[iw][1] + kLam[i][2] * t[iw][2] - w0;
-            const double c0 = 3.0 * u00 * w0, c1 = 3.0 * (u00 * w1 + 2.0 * u01 * w0);
-            const double c2 = 3.0 * (2.0 * u01 * w1 + u11 * w0), c3 = 3.0 * u11 * w1;
-            sgb = wj * (c0 * (1.0 / 2) + c1 * (1.0 / 6) + c2 * (1.0 / 12) + c3 * (1.0 / 20));
-            sgt = wj * (c0 * (1.0 / 2) + c1 * (1.0 / 3) + c2 * (1.0 / 4) + c3 * (1.0 / 5));
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if constexpr (F) {
-                fb[a] += kLam[i][a] * sfb;
-                ft[a] += kLam[i][a] * sft;
-            }
-            if constexpr (GU) {
-                gb[a] += kLam[i][a] * sgb;
-                gt[a] += kLam[i][a] * sgt;
-            }
-        }
-    }
+    cubic_points<F, GU>(twoA, h, b[0], t[0], b[iw], t[iw], fb, ft, gb, gt);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if constexpr (F) {

@@ -1906,11 +1906,54 @@ __global__ void __launch_bounds__(kThreads, FORM == 3 && NI > 1 ? 3 : 4) k_pipe_
                     lds_add(A + (o0 + o) * VS + vb[q] + r + 1, yt[o][q]);
                 }
         };
-        // the fused form runs the residual, then the adjoint, on one prism:
-        // half the live values of evaluating both at once
-        if constexpr (FORM == 1 || FORM == 3) element(std::integral_constant<int, 1>{}, 1, 0);
+        if constexpr (FORM == 1) element(std::integral_constant<int, 1>{}, 1, 0);
         if constexpr (FORM == 2) element(std::integral_constant<int, 2>{}, 1, 0);
-        if constexpr (FORM == 3) element(std::integral_constant<int, 2>{}, 2, 1);
+        if constexpr (FORM == 3) {
+            // both forms on one prism, sharing u at the triangle points; the
+            // linear terms first, so that f and the rows of g_f are done with
+            // before the points' loop: F from -M f, g_f = -M w into LDS, then
+            // the terms in u^3 and 3 u^2 w
+            auto load = [&](int i, double (&vb_)[3], double (&vt_)[3]) {
+                const double* const Xb = Xs + (b * NIN + i) * VS;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    vb_[q] = Xb[vb[q] + r];
+                    vt_[q] = Xb[vb[q] + r + 1];
+                }
+            };
+            double fb[3], ft[3], gb[3] = {0.0, 0.0, 0.0}, gt[3] = {0.0, 0.0, 0.0};
+            {
+                double xb[3], xt[3];
+                load(1, xb, xt);
+                p1_mass(twoA, h, xb, xt, fb, ft);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    fb[q] = -fb[q];
+                    ft[q] = -ft[q];
+                }
+            }
+            double wb[3], wt[3];
+            load(2, wb, wt);
+            {
+                double mb[3], mt[3];
+                p1_mass(twoA, h, wb, wt, mb, mt);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    lds_add(A + 2 * VS + vb[q] + r, -mb[q]);
+                    lds_add(A + 2 * VS + vb[q] + r + 1, -mt[q]);
+                }
+            }
+            double ub[3], ut[3];
+            load(0, ub, ut);
+            cubic_points<true, true>(twoA, h, ub, ut, wb, wt, fb, ft, gb, gt);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                lds_add(A + vb[q] + r, fb[q]);
+                lds_add(A + vb[q] + r + 1, ft[q]);
+                lds_add(A + VS + vb[q] + r, gb[q]);
+                lds_add(A + VS + vb[q] + r + 1, gt[q]);
+            }
+        }
     }
     // write back the last chunk, its top level included
     lds_barrier();
