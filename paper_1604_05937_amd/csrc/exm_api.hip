@@ -337,24 +337,28 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
                   "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1, 8 or 16 on P2xP2, CG1xDG* "
                   "and the cubic forms, and 8, 16 or 32 on the spaces discontinuous horizontally",
                   d.chunk_layers);
-        if (!d.tile_cells)
-            d.tile_cells = std::min(one_layer ? 32 : 64, pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers));
-        EXM_CHECK(d.tile_cells <= pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+        // the fixed-height P1 x P1 walk takes larger tiles in wider workgroups
+        const bool wide = P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1 && !mesh->variable &&
+                          pipe_p1_wide_max_cells(d.chunk_layers) > 0;
+        const int32_t max_cells =
+            wide ? pipe_p1_wide_max_cells(d.chunk_layers) : pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers);
+        const int32_t max_verts =
+            wide ? pipe_p1_wide_max_verts(d.chunk_layers) : pipe_max_tile_verts(P.kernel, P.element, d.chunk_layers);
+        if (!d.tile_cells) d.tile_cells = std::min(one_layer ? 32 : 64, max_cells);
+        EXM_CHECK(d.tile_cells <= max_cells, EXM_EUNSUPPORTED,
                   "PIPELINED: tiles of %d cells with %d-layer chunks exceed %d cells", d.tile_cells, d.chunk_layers,
-                  pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers));
+                  max_cells);
         const TilePlan* plan = nullptr;
         const bool owner = d.race == EXM_RACE_OWNER;
         int32_t s = owner ? build_owner_plan(mesh, d.tile_cells, &plan) : build_tile_plan(mesh, d.tile_cells, &plan);
         if (s != EXM_OK) return s;
-        EXM_CHECK(plan->max_cells <= pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+        EXM_CHECK(plan->max_cells <= max_cells, EXM_EUNSUPPORTED,
                   "PIPELINED: owner tiles of about %d cells reach %d cells with their neighbours, more than %d "
-                  "with %d-layer chunks", d.tile_cells, plan->max_cells, pipe_max_tile_cells(P.kernel, P.element, d.chunk_layers),
-                  d.chunk_layers);
+                  "with %d-layer chunks", d.tile_cells, plan->max_cells, max_cells, d.chunk_layers);
         if (P.element == EXM_ELEMENT_P1P1 || P.element == EXM_ELEMENT_P1DG0 || P.element == EXM_ELEMENT_P1DG1)
-            EXM_CHECK(plan->max_verts <= pipe_max_tile_verts(P.kernel, P.element, d.chunk_layers), EXM_EUNSUPPORTED,
+            EXM_CHECK(plan->max_verts <= max_verts, EXM_EUNSUPPORTED,
                       "PIPELINED: tiles of %d cells touch up to %d vertices, more than %d with %d-layer chunks",
-                      d.tile_cells, plan->max_verts, pipe_max_tile_verts(P.kernel, P.element, d.chunk_layers),
-                      d.chunk_layers);
+                      d.tile_cells, plan->max_verts, max_verts, d.chunk_layers);
         if (p2) {
             EXM_CHECK(plan->has_edges, EXM_EINVAL, "P2 needs the mesh's cell_edge map");
             EXM_CHECK(plan->max_verts + plan->max_edges <= pipe_max_tile_entities(d.chunk_layers), EXM_EUNSUPPORTED,
@@ -702,17 +706,20 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
         if (pipe_supported(P.kernel, P.element))
             for (int32_t tc : {16, 24, 32, 48, 64, 96, 128, 256})
-                for (int32_t S : {8, 12, 16, 20, 24, 32})
-                    if (pipe_chunk_ok(P.kernel, P.element, S) && tc <= pipe_max_tile_cells(P.kernel, P.element, S) &&
+                for (int32_t S : {8, 12, 16, 20, 24, 32}) {
+                    const bool p1 = P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1;
+                    const int32_t narrow = pipe_max_tile_cells(P.kernel, P.element, S);
+                    const int32_t limit = p1 ? std::max(narrow, pipe_p1_wide_max_cells(S)) : narrow;
+                    if (pipe_chunk_ok(P.kernel, P.element, S) && tc <= limit &&
                         (tc >= 32 || P.element == EXM_ELEMENT_P2P2 || P.kernel != EXM_K_MASS)) {
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
-                        if (r == 0 && P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1)
-                            cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
-                        if (P.element == EXM_ELEMENT_P1P1 && (S & (S - 1)) == 0) {
+                        if (r == 0 && p1) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
+                        if (p1 && (S & (S - 1)) == 0 && tc <= narrow) {
                             cand.push_back(exm_loop_opts{races[r], EXM_SCHED_CHUNKED, 0, 4, tc, S});
                             if (r == 0) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_CHUNKED, 0, 4, tc, S});
                         }
                     }
+                }
         if (cg)
             for (int32_t t : {8, 16, 24, 32, 64, 128, 256})
                 for (int32_t c : {0, 1, 2, 4})

@@ -144,12 +144,12 @@ struct ManyFields {
 // start (ints) per tile vertex; (x, y) per vertex only during set-up, inside
 // A.  The old output values of a chunk are loaded into registers while the
 // chunk computes and added when it is written back, during the next chunk.
-template <int S, int MODE, bool OVERWRITE, class Fields>
+template <int S, int MODE, bool OVERWRITE, class Fields, int NT = kThreads>
 __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t, const int32_t tile, const Fields& F)
 {
     static_assert(!OVERWRITE || MODE == kOwner, "overwriting needs one writer per vertex");
     constexpr bool ATOMIC = MODE == kAtomic;
-    constexpr int P2 = S + 2, PP = P2 / 2, R = kLayers, G = S / R, CPP = kThreads / G;
+    constexpr int P2 = S + 2, PP = P2 / 2, R = kLayers, G = S / R, CPP = NT / G;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
@@ -181,7 +181,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
         for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
     }
     // tile vertex table: tag, column start, (x, y) of the column
-    for (int v = tid; v < nv; v += kThreads) {
+    for (int v = tid; v < nv; v += NT) {
         const int32_t tag = t.verts[vb0 + v];
         const int32_t xs = column_start(t.xstart, t.xbase, t.xstep, vid(tag));
         Ttag[v] = tag;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
     int32_t ipos[kItems], iglb[kItems];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-        const int it = tid + kThreads * i;
+        const int it = tid + NT * i;
         const int v = it / S, jj = it - (it / S) * S;
         const bool ok = v < no;
         const int32_t xs = ok ? Txst[v] : 0;
@@ -237,7 +237,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
         const int l0 = k * S;
         const int nl = min(S, lam - l0);
         const int b = k & 1;
-        for (int e0 = 0; e0 < nv * PP; e0 += kThreads) {
+        for (int e0 = 0; e0 < nv * PP; e0 += NT) {
             const int e = e0 + tid;
             const int v = e / PP, w = e - (e / PP) * PP;
             if (v >= nv) continue;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
         const int nl = min(S, lam - l0);
 #pragma unroll
         for (int i = 0; i < kItems; ++i)
-            dst[i] = (((uint32_t)ipos[i] >> 30) == 1 && (tid + kThreads * i) % S < nl) ? y[(int64_t)iglb[i] + l0] : 0.0;
+            dst[i] = (((uint32_t)ipos[i] >> 30) == 1 && (tid + NT * i) % S < nl) ? y[(int64_t)iglb[i] + l0] : 0.0;
     };
     // write chunk k back (levels l0 .. l0 + nl - 1); with `carry`, move its
     // top level to level 0 for chunk k + 1
@@ -271,7 +271,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
         const int nl = min(S, lam - l0);
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            const int jj = (tid + kThreads * i) % S;
+            const int jj = (tid + NT * i) % S;
             const int kind = (int)((uint32_t)ipos[i] >> 30);
             const int pos = ipos[i] & 0x3fffffff;
             if (kind == 0 || jj >= nl) continue;
@@ -297,7 +297,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
             y = F.dst(pass);
             lds_barrier();
         }
-        for (int i = tid; i < VS; i += kThreads) A[i] = 0.0;
+        for (int i = tid; i < VS; i += NT) A[i] = 0.0;
         // yA: old values of the next chunk to be written back (loading); yB: of
         // the chunk written back next
         double yA[kItems], yB[kItems];
@@ -365,7 +365,7 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
             const int k = nch - 1;
             const int l0 = k * S, nl = lam - l0;
             write_back(k, yB, false);
-            for (int v = tid; v < no; v += kThreads) {
+            for (int v = tid; v < no; v += NT) {
                 const int32_t xs = Txst[v];
                 const double s = A[v * P2 + (xs & 1) + nl];
                 const int64_t g = (int64_t)xs + lam;
@@ -380,12 +380,14 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
     }
 }
 
-template <int S, int MODE>
-__global__ void __launch_bounds__(kThreads) k_pipe_p1(const ColArgs a, const TileArgs t)
+// NT threads per workgroup: 256, or 384 and 512 for tiles of more cells
+// (fewer halo columns and shared vertices per cell, fewer workgroups per CU).
+template <int S, int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_pipe_p1(const ColArgs a, const TileArgs t)
 {
     const int32_t blk = (int32_t)xcd_block_p(blockIdx.x, gridDim.x);
     const int32_t tile = t.tiles ? t.tiles[t.tile_begin + blk] : t.tile_begin + blk;
-    pipe_p1_tile<S, MODE, false>(a, t, tile, OneField{a.in0, a.out0});
+    pipe_p1_tile<S, MODE, false, OneField, NT>(a, t, tile, OneField{a.in0, a.out0});
 }
 
 // The P1 x P1 items of a batch, b = M f and g = M w for every field: one
@@ -2252,25 +2254,61 @@ int32_t pipe_max_tile_verts(int32_t kernel, int32_t element, int32_t S)
     return kThreads * (cubic_kernel(kernel) ? kItemsC : kItems) / S;
 }
 
+// The fixed-height P1 x P1 tile walk also runs in workgroups of 384 and 512
+// threads (chunks of 8, 16 or 32 layers): its limits then, 0 where it does not.
+int32_t pipe_p1_wide_max_cells(int32_t S) { return S == 8 || S == 16 || S == 32 ? kPasses * (512 / (S / kLayers)) : 0; }
+int32_t pipe_p1_wide_max_verts(int32_t S) { return S == 8 || S == 16 || S == 32 ? 512 * kItems / S : 0; }
+
 int32_t pipe_max_tile_entities(int32_t S) { return kThreads * kItems2 / (2 * S); }
 
-template <int S>
-static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
+template <int S, int NT>
+static void launch_pipe_p1_nt(int32_t race, const ColArgs& a, const TileArgs& t, size_t lds, hipStream_t s)
 {
-    const dim3 grid((unsigned)t.tile_count), block(kThreads);
+    const dim3 grid((unsigned)t.tile_count), block(NT);
+    if (race == EXM_RACE_OWNER)
+        hipLaunchKernelGGL((k_pipe_p1<S, kOwner, NT>), grid, block, lds, s, a, t);
+    else if (race == EXM_RACE_COLOUR)
+        hipLaunchKernelGGL((k_pipe_p1<S, kPlain, NT>), grid, block, lds, s, a, t);
+    else
+        hipLaunchKernelGGL((k_pipe_p1<S, kAtomic, NT>), grid, block, lds, s, a, t);
+}
+
+// Workgroup size of the fixed-height P1 tile walk: the smallest of 256, 384
+// and 512 threads that takes every cell of the largest tile in one pass and
+// its vertices x S levels in kItems items per thread; otherwise two passes
+// of 256 (or 512) threads.
+int32_t pipe_p1_threads(int32_t S, int32_t cells, int32_t verts)
+{
+    const int G = S / kLayers;
+    const bool wide_ok = S == 8 || S == 16 || S == 32;
+    for (int nt : {128, 192, 256, 384, 512}) {
+        if (nt != 256 && !wide_ok) continue;
+        if (cells * G <= nt && verts * S <= nt * kItems) return nt;
+    }
+    if (cells * G <= kPasses * 256 && verts * S <= 256 * kItems) return 256;
+    return wide_ok ? 512 : 256;
+}
+
+template <int S>
+static void launch_pipe_s(int32_t race, const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds,
+                          hipStream_t s)
+{
     if (t.vlo) {   // columns of different heights
+        const dim3 grid((unsigned)t.tile_count), block(kThreads);
         if (race == EXM_RACE_COLOUR)
             hipLaunchKernelGGL((k_pipe_p1_var<S, kPlain>), grid, block, lds, s, a, t);
         else
             hipLaunchKernelGGL((k_pipe_p1_var<S, kAtomic>), grid, block, lds, s, a, t);
         return;
     }
-    if (race == EXM_RACE_OWNER)
-        hipLaunchKernelGGL((k_pipe_p1<S, kOwner>), grid, block, lds, s, a, t);
-    else if (race == EXM_RACE_COLOUR)
-        hipLaunchKernelGGL((k_pipe_p1<S, kPlain>), grid, block, lds, s, a, t);
-    else
-        hipLaunchKernelGGL((k_pipe_p1<S, kAtomic>), grid, block, lds, s, a, t);
+    if constexpr (S == 8 || S == 16 || S == 32) {
+        const int nt = pipe_p1_threads(S, cstride, t.vstride);
+        if (nt == 512) return launch_pipe_p1_nt<S, 512>(race, a, t, lds, s);
+        if (nt == 384) return launch_pipe_p1_nt<S, 384>(race, a, t, lds, s);
+        if (nt == 192) return launch_pipe_p1_nt<S, 192>(race, a, t, lds, s);
+        if (nt == 128) return launch_pipe_p1_nt<S, 128>(race, a, t, lds, s);
+    }
+    launch_pipe_p1_nt<S, kThreads>(race, a, t, lds, s);
 }
 
 int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
@@ -2474,12 +2512,12 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
     }
     EXM_CHECK(P.race != EXM_RACE_OWNER || t.owned != nullptr, EXM_EINVAL, "owner-computes needs an owner plan");
     switch (S) {
-    case 8: launch_pipe_s<8>(P.race, a, t, lds, s); break;
-    case 12: launch_pipe_s<12>(P.race, a, t, lds, s); break;
-    case 16: launch_pipe_s<16>(P.race, a, t, lds, s); break;
-    case 20: launch_pipe_s<20>(P.race, a, t, lds, s); break;
-    case 24: launch_pipe_s<24>(P.race, a, t, lds, s); break;
-    case 32: launch_pipe_s<32>(P.race, a, t, lds, s); break;
+    case 8: launch_pipe_s<8>(P.race, a, t, cstride, lds, s); break;
+    case 12: launch_pipe_s<12>(P.race, a, t, cstride, lds, s); break;
+    case 16: launch_pipe_s<16>(P.race, a, t, cstride, lds, s); break;
+    case 20: launch_pipe_s<20>(P.race, a, t, cstride, lds, s); break;
+    case 24: launch_pipe_s<24>(P.race, a, t, cstride, lds, s); break;
+    case 32: launch_pipe_s<32>(P.race, a, t, cstride, lds, s); break;
     default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 12, 16, 20, 24 or 32 on P1xP1", S);
     }
     EXM_TRY_HIP(hipGetLastError());

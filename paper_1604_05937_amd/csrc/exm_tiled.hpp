@@ -91,6 +91,8 @@ size_t pipe_lds_bytes(int32_t kernel, int32_t element, int32_t vstride, int32_t 
 bool pipe_supported(int32_t kernel, int32_t element);
 int32_t pipe_max_tile_cells(int32_t kernel, int32_t element, int32_t S);
 int32_t pipe_max_tile_verts(int32_t kernel, int32_t element, int32_t S);
+int32_t pipe_p1_wide_max_cells(int32_t S);
+int32_t pipe_p1_wide_max_verts(int32_t S);
 int32_t pipe_max_tile_entities(int32_t S);
 bool pipe_chunk_ok(int32_t kernel, int32_t element, int32_t S);
 int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t cstride, int32_t S, size_t lds,

@@ -140,6 +140,31 @@ def test_mass_pipelined_shapes(schedule, space, tile, chunk, race):
         assert_close(c.host(y), want, scale, what=f"pipelined mass {space} tile={tile} S={chunk} lam={lam}")
 
 
+@pytest.mark.parametrize("tile,chunk", [(8, 16), (32, 16), (48, 16), (96, 16), (128, 16), (192, 16), (256, 8),
+                                        (96, 8), (64, 32), (48, 32)])
+@pytest.mark.parametrize("race", RACES + [exm.EXM_RACE_OWNER])
+def test_p1_pipelined_workgroup_widths(tile, chunk, race):
+    # the fixed-height P1 tile walk in workgroups of 128 to 512 threads (one
+    # pass over the tile's cells) and two passes of 512
+    say(f"P1 pipelined width tile={tile} chunk={chunk} race={race}")
+    base = meshgen.tri_square(14)
+    for lam in (1, chunk - 1, 2 * chunk + 3):
+        c = Case(base, lam, "P1", terrain=0.2)
+        x = meshgen.uniform_values(c.n, seed=17)
+        y0 = meshgen.uniform_values(c.n, seed=18)
+        xd, y = c.dev(x), c.dev(y0)
+        try:
+            exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
+                         schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=chunk, race=race)
+        except exm.ExmError as e:
+            # more vertices than the widest workgroup's items take: refused before any launch
+            assert e.status == exm._abi.EXM_EUNSUPPORTED and "PIPELINED" in str(e), str(e)
+            assert tile * chunk >= 2048, str(e)
+            return
+        assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0),
+                     what=f"P1 pipelined tile={tile} S={chunk} lam={lam}")
+
+
 @pytest.mark.parametrize("space", ["DG0", "DG1", "DG0xDG1", "DG1xDG0", "DG0xCG1", "DG1xCG1"])
 def test_pipelined_dg_inc(space):
     base = meshgen.tri_square(7)
