@@ -459,11 +459,15 @@ int32_t exm_autotune_load(const char* path);
  * field on the same mesh; n_fields inputs f[j] with outputs b[j] = M f[j], and
  * optionally cotangents w[j] with adjoint outputs g[j] = M^T w[j] = M w[j].
  * Pointer arrays are host arrays of device pointers (copied at create).
- * Outputs are overwritten: every output DoF is written once (each P1 vertex
- * column by the one tile that owns it, or, on vertex units, by its own
- * wavefront as in EXM_SCHED_GATHER; no atomics), so the result does not
- * depend on the order in which work runs.  Tiles need 16-byte aligned
- * coordinates (and P1 fields); otherwise the kind runs on work units.
+ * Outputs are overwritten.  P1 items run on owner tiles (each vertex
+ * column written once by the one tile that owns it; no atomics, so the
+ * result does not depend on the order in which work runs) or on shared
+ * tiles (a column only one tile touches is written by it; the columns of
+ * vertices on tile boundaries are zeroed first, in the same graph, and the
+ * tiles add into them with FP64 atomics, so their last bits depend on the
+ * order); on vertex units each column is written by its own wavefront as in
+ * EXM_SCHED_GATHER.  Tiles need 16-byte aligned coordinates (and P1
+ * fields); otherwise the kind runs on work units.
  * The meshes, spaces and buffers must outlive the batch.
  */
 typedef struct {
@@ -484,7 +488,8 @@ typedef struct exm_batch exm_batch;
  * vertices of P1 units, scaled by 64 / layers) and makes each kind take the
  * first tiling that fits; 0 = timed choice of unit size and tilings;
  * opts->chunk_layers fixes the tiles' chunk length (8 or 16 for P1, 8, 16
- * or 32 for DG0). */
+ * or 32 for DG0); opts->race = EXM_RACE_OWNER or EXM_RACE_ATOMIC restricts
+ * the P1 items to owner or to shared tiles (0 = timed choice of both). */
 int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm_loop_opts* opts,
                          void* stream, exm_batch** out);
 /* Replay the captured graph on `stream`. */

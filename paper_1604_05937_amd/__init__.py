@@ -390,7 +390,7 @@ class Batch:
     optionally w, g (lists of device FP64 tensors on `space`)."""
 
     def __init__(self, items, cols_per_wave: int = 0, unit_cells: int = 0, schedule: int = 0,
-                 chunk_layers: int = 0, stream=None):
+                 chunk_layers: int = 0, race: int = 0, stream=None):
         _abi.load()
         self._keep = []
         arr = (_abi.exm_batch_item * len(items))()
@@ -419,7 +419,7 @@ class Batch:
         self._keep.append(arr)
         self.items = items
         opts = loop_opts(cols_per_wave=cols_per_wave, tile_cells=unit_cells, schedule=schedule,
-                         chunk_layers=chunk_layers)
+                         chunk_layers=chunk_layers, race=race)
         h = ctypes.c_void_p()
         _abi.exm_batch_create(len(items), arr, ctypes.byref(opts), stream_handle(stream), ctypes.byref(h))
         self.handle = h

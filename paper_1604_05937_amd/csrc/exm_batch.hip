@@ -238,10 +238,13 @@ __global__ void __launch_bounds__(256) k_batch(const BatchItemDev* __restrict__ 
 // workgroup per (item, tile), every field of the item through one set-up.
 struct TileSet {
     bool on = false;
+    bool shared = false;           // P1: shared tiles (atomic adds into zeroed columns), else owner tiles
     DevBuf<BatchPipeItem> items;   // the kind's items, largest columns first
     DevBuf<int32_t> units;         // (item, tile) pairs
     DevBuf<const double*> ptrs;    // per item, inputs (f, w) then outputs (b, g)
-    int32_t n_units = 0, tile = 0, S = 0, cstride = 0;
+    DevBuf<ZeroUnit> zero;         // shared tiles: the columns to zero before the walk
+    DevBuf<int32_t> zstarts;       // ... their column starts
+    int32_t n_units = 0, tile = 0, S = 0, cstride = 0, n_zero = 0, zero_out = 0;
     size_t lds = 0;
 };
 
@@ -297,14 +300,16 @@ int32_t batch_cpw(int32_t n_layers)
     return best;
 }
 
-// The items of one kind (P1: owner tiles, DG0: tiles) on tiles of about T
-// cells with S-layer chunks: the item table, the units and the pass
-// pointers.  *fits stays false (and the set is left as it was) when some
-// item's tiles exceed the kernel's limits or its pointers are not 16-byte
-// aligned where the tile walk copies 16 bytes at a time.
+// The items of one kind (P1: owner tiles, or shared tiles with `shared`;
+// DG0: tiles) on tiles of about T cells with S-layer chunks: the item table,
+// the units and the pass pointers (and for shared P1 tiles the columns to
+// zero).  *fits stays false (and the set is left as it was) when some item's
+// tiles exceed the kernel's limits or its pointers are not 16-byte aligned
+// where the tile walk copies 16 bytes at a time.
 int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item* items, int32_t T, int32_t S,
-                    bool* fits)
+                    bool shared, bool* fits)
 {
+    shared = shared && p1;
     constexpr size_t kLds = 160 * 1024;
     const int32_t element = p1 ? EXM_ELEMENT_P1P1 : EXM_ELEMENT_DG0DG0;
     TileSet& ts = B->tiles[p1 ? 0 : 1];
@@ -328,7 +333,8 @@ int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item
                                   it.space->col_size[0] == it.coord_space->col_size[0]);
         if ((al & 15) != 0 || !same) return EXM_OK;
         const TilePlan* plan = nullptr;
-        int32_t s = p1 ? build_owner_plan(it.space->mesh, T, &plan) : build_tile_plan(it.space->mesh, T, &plan);
+        int32_t s = p1 && !shared ? build_owner_plan(it.space->mesh, T, &plan)
+                                  : build_tile_plan(it.space->mesh, T, &plan);
         if (s != EXM_OK) return s;
         const size_t l = pipe_lds_bytes(EXM_K_MASS, element, plan->max_verts, 0, plan->max_cells, S);
         if (plan->max_cells > pipe_max_tile_cells(EXM_K_MASS, element, S) ||
@@ -341,7 +347,15 @@ int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item
     std::vector<const double*> ptrs;
     std::vector<size_t> pbase;
     std::vector<int32_t> units;
+    std::vector<int32_t> zstarts;
+    std::vector<size_t> zbase;   // per item: its first entry in zstarts
     for (size_t i = 0; i < order.size(); ++i) {
+        if (shared) {   // the shared vertices' columns, in the P1 numbering (one value per level)
+            const exm_batch_item& it = items[order[i]];
+            zbase.push_back(zstarts.size());
+            for (int32_t v : plans[i]->shared_verts)
+                zstarts.push_back((int32_t)(it.space->base[0] + (int64_t)v * it.space->col_size[0]));
+        }
         const exm_batch_item& it = items[order[i]];
         pbase.push_back(ptrs.size());
         for (int32_t k = 0; k < it.n_fields; ++k) ptrs.push_back(it.f[k]);
@@ -378,7 +392,7 @@ int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item
         d.t.vert_off = plan->vert_off.p;
         d.t.verts = plan->verts.p;
         d.t.lcv = plan->local_cv.p;
-        d.t.owned = p1 ? plan->owned.p : nullptr;
+        d.t.owned = p1 && !shared ? plan->owned.p : nullptr;
         d.t.xstart = it.coord_space->d_starts[0].p;
         d.t.xbase = it.coord_space->base[0];
         d.t.xstep = it.coord_space->col_size[0];   // closed-form column starts: one layer count per mesh
@@ -390,6 +404,23 @@ int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item
     if ((s = ts.items.upload(dev.data(), dev.size())) != EXM_OK) return s;
     if ((s = ts.units.upload(units.data(), units.size())) != EXM_OK) return s;
     ts.n_units = (int32_t)(units.size() / 2);
+    ts.shared = shared;
+    ts.n_zero = ts.zero_out = 0;
+    if (shared) {   // zero units of up to 256 columns, every output of the item
+        if (!zstarts.empty() && (s = ts.zstarts.upload(zstarts.data(), zstarts.size())) != EXM_OK) return s;
+        std::vector<ZeroUnit> zu;
+        for (size_t i = 0; i < order.size(); ++i) {
+            const exm_batch_item& it = items[order[i]];
+            const size_t b = zbase[i], e = i + 1 < order.size() ? zbase[i + 1] : zstarts.size();
+            for (size_t k = b; k < e; k += 256)
+                zu.push_back(ZeroUnit{dev[i].dst, ts.zstarts.p + k, dev[i].n_pass, (int32_t)std::min<size_t>(256, e - k),
+                                      it.space->col_size[0]});
+            ts.zero_out = std::max(ts.zero_out, dev[i].n_pass);
+        }
+        EXM_CHECK(zu.size() < (size_t)INT32_MAX, EXM_EOVERFLOW, "too many columns to zero");
+        if (!zu.empty() && (s = ts.zero.upload(zu.data(), zu.size())) != EXM_OK) return s;
+        ts.n_zero = (int32_t)zu.size();
+    }
     ts.tile = T;
     ts.S = S;
     ts.cstride = cstride;
@@ -400,7 +431,11 @@ int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item
 
 int32_t launch_tiles(const TileSet& ts, bool p1, hipStream_t s)
 {
-    return p1 ? launch_batch_pipe_p1(ts.items.p, ts.units.p, ts.n_units, ts.S, ts.lds, s)
+    if (p1 && ts.shared) {
+        const int32_t st = launch_zero_columns(ts.zero.p, ts.n_zero, ts.zero_out, s);
+        if (st != EXM_OK) return st;
+    }
+    return p1 ? launch_batch_pipe_p1(ts.items.p, ts.units.p, ts.n_units, ts.S, ts.shared, ts.lds, s)
               : launch_batch_pipe_dg0(ts.items.p, ts.units.p, ts.n_units, ts.S, ts.cstride, ts.lds, s);
 }
 
@@ -617,10 +652,26 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
     for (int kind = 0; kind < 2 && !(opts && opts->schedule == EXM_SCHED_GATHER); ++kind) {
         const bool p1 = kind == 0;
         if (std::find(B->p1.begin(), B->p1.end(), p1) == B->p1.end()) continue;
-        // (tile cells, chunk layers)
-        const std::vector<std::pair<int32_t, int32_t>> cand =
-            p1 ? std::vector<std::pair<int32_t, int32_t>>{{64, 16}, {32, 16}, {64, 8}, {128, 8}}
-               : std::vector<std::pair<int32_t, int32_t>>{{32, 32}, {32, 16}, {64, 16}, {64, 8}};
+        // (tile cells, chunk layers, shared tiles): P1 on owner tiles and on
+        // shared tiles (race EXM_RACE_OWNER or EXM_RACE_ATOMIC picks one)
+        struct Cand {
+            int32_t T, S;
+            bool shared;
+        };
+        std::vector<Cand> cand;
+        if (p1) {
+            const int32_t race = opts ? opts->race : 0;
+            for (bool sh : {false, true}) {
+                if ((race == EXM_RACE_ATOMIC && !sh) || (race == EXM_RACE_OWNER && sh)) continue;
+                for (const auto& c : {std::make_pair(64, 16), std::make_pair(32, 16), std::make_pair(64, 8),
+                                      std::make_pair(128, 8)})
+                    cand.push_back(Cand{c.first, c.second, sh});
+            }
+        } else {
+            for (const auto& c : {std::make_pair(32, 32), std::make_pair(32, 16), std::make_pair(64, 16),
+                                  std::make_pair(64, 8)})
+                cand.push_back(Cand{c.first, c.second, false});
+        }
         const bool tune = !(opts && opts->tile_cells);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tune) {
@@ -639,22 +690,25 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         };
         float best = 1e30f;
         int32_t bt = 0, bs = 0;
-        for (const auto& c : cand) {
-            if (opts && opts->chunk_layers && opts->chunk_layers != c.second) continue;
+        bool bsh = false;
+        for (const Cand& c : cand) {
+            if (opts && opts->chunk_layers && opts->chunk_layers != c.S) continue;
             bool fits = false;
-            if ((s = build_tiles(B.get(), p1, n_items, items, c.first, c.second, &fits)) != EXM_OK) break;
+            if ((s = build_tiles(B.get(), p1, n_items, items, c.T, c.S, c.shared, &fits)) != EXM_OK) break;
             if (!fits) continue;
             if (!tune) {
-                bt = c.first;
-                bs = c.second;
+                bt = c.T;
+                bs = c.S;
+                bsh = c.shared;
                 break;
             }
             float ms = 0.f;
             if ((s = time_one(&ms)) != EXM_OK) break;
             if (ms < best) {
                 best = ms;
-                bt = c.first;
-                bs = c.second;
+                bt = c.T;
+                bs = c.S;
+                bsh = c.shared;
             }
         }
         if (e0) (void)hipEventDestroy(e0);
@@ -662,7 +716,7 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
         if (s != EXM_OK) return s;
         if (bt) {
             bool fits = false;
-            if ((s = build_tiles(B.get(), p1, n_items, items, bt, bs, &fits)) != EXM_OK) return s;
+            if ((s = build_tiles(B.get(), p1, n_items, items, bt, bs, bsh, &fits)) != EXM_OK) return s;
             B->tiles[kind].on = fits;
         }
     }

@@ -147,7 +147,10 @@ struct ManyFields {
 template <int S, int MODE, bool OVERWRITE, class Fields, int NT = kThreads>
 __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t, const int32_t tile, const Fields& F)
 {
-    static_assert(!OVERWRITE || MODE == kOwner, "overwriting needs one writer per vertex");
+    // OVERWRITE: owner tiles write their vertices once; shared tiles (kAtomic)
+    // overwrite the vertices no other tile touches and add the shared ones
+    // atomically, into outputs that hold zeros there
+    static_assert(!OVERWRITE || MODE == kOwner || MODE == kAtomic, "overwriting needs one writer per vertex");
     constexpr bool ATOMIC = MODE == kAtomic;
     constexpr int P2 = S + 2, PP = P2 / 2, R = kLayers, G = S / R, CPP = NT / G;
     extern __shared__ double lds[];
@@ -391,16 +394,35 @@ __global__ void __launch_bounds__(NT) k_pipe_p1(const ColArgs a, const TileArgs 
 }
 
 // The P1 x P1 items of a batch, b = M f and g = M w for every field: one
-// workgroup per (item, owner tile) unit, in list order (largest columns
-// first), runs every field of its item through the tile walk, overwriting the
-// outputs of the vertices the tile owns.
-template <int S>
+// workgroup per (item, tile) unit, in list order (largest columns first),
+// runs every field of its item through the tile walk.  On owner tiles
+// (kOwner) it overwrites the outputs of the vertices the tile owns; on
+// shared tiles (kAtomic) it overwrites those of the vertices only it touches
+// and adds those of the shared vertices atomically (k_zero_columns has
+// zeroed them).
+template <int S, int MODE>
 __global__ void __launch_bounds__(kThreads) k_batch_pipe_p1(const BatchPipeItem* __restrict__ items,
                                                             const int32_t* __restrict__ units)
 {
     const int32_t u = (int32_t)blockIdx.x;
     const BatchPipeItem& I = items[units[2 * u]];
-    pipe_p1_tile<S, kOwner, true>(I.a, I.t, units[2 * u + 1], ManyFields{I.src, I.dst, I.n_pass});
+    pipe_p1_tile<S, MODE, true>(I.a, I.t, units[2 * u + 1], ManyFields{I.src, I.dst, I.n_pass});
+}
+
+// Zero the vertex columns a batch's shared P1 tiles add into: block
+// (b, k) takes the columns of unit b (an item and a range of its shared
+// vertices) in output k of the item, one wavefront per column at a time.
+__global__ void __launch_bounds__(256) k_zero_columns(const ZeroUnit* __restrict__ units)
+{
+    const ZeroUnit U = units[blockIdx.x];
+    const int32_t k = (int32_t)blockIdx.y;
+    if (k >= U.n_out) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* const y = U.dst[k];
+    for (int32_t i = wave; i < U.count; i += 4) {
+        const int64_t c = U.starts[i];
+        for (int32_t l = lane; l < U.len; l += 64) y[c + l] = 0.0;
+    }
 }
 
 // P1 x P1 mass action / RHS (INC) on a mesh whose cell columns have layer
@@ -2344,15 +2366,26 @@ int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, 
 }
 
 int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
-                             size_t lds, hipStream_t s)
+                             bool shared, size_t lds, hipStream_t s)
 {
     if (n_units <= 0) return EXM_OK;
     const dim3 grid((unsigned)n_units), block(kThreads);
-    switch (S) {
-    case 8: hipLaunchKernelGGL(k_batch_pipe_p1<8>, grid, block, lds, s, items, units); break;
-    case 16: hipLaunchKernelGGL(k_batch_pipe_p1<16>, grid, block, lds, s, items, units); break;
+    switch (S * 2 + (shared ? 1 : 0)) {
+    case 16: hipLaunchKernelGGL((k_batch_pipe_p1<8, kOwner>), grid, block, lds, s, items, units); break;
+    case 17: hipLaunchKernelGGL((k_batch_pipe_p1<8, kAtomic>), grid, block, lds, s, items, units); break;
+    case 32: hipLaunchKernelGGL((k_batch_pipe_p1<16, kOwner>), grid, block, lds, s, items, units); break;
+    case 33: hipLaunchKernelGGL((k_batch_pipe_p1<16, kAtomic>), grid, block, lds, s, items, units); break;
     default: return fail(EXM_ERANGE, "chunk_layers = %d: batched P1 tiles take 8 or 16", S);
     }
+    EXM_TRY_HIP(hipGetLastError());
+    return EXM_OK;
+}
+
+int32_t launch_zero_columns(const ZeroUnit* units, int32_t n_units, int32_t max_out, hipStream_t s)
+{
+    if (n_units <= 0 || max_out <= 0) return EXM_OK;
+    EXM_CHECK(max_out <= 65535, EXM_ERANGE, "%d outputs per batch item exceed the grid", max_out);
+    hipLaunchKernelGGL(k_zero_columns, dim3((unsigned)n_units, (unsigned)max_out), dim3(256), 0, s, units);
     EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;
 }

@@ -75,8 +75,20 @@ struct BatchPipeItem {
     double* const* dst;
     int32_t n_pass;
 };
+// shared: the items' tiles are shared tiles (shared vertices added
+// atomically into zeroed columns), else owner tiles.
 int32_t launch_batch_pipe_p1(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
-                             size_t lds, hipStream_t s);
+                             bool shared, size_t lds, hipStream_t s);
+
+// A range of vertex columns to zero in every output of a batch item: column
+// starts starts[0 .. count), len values each, in the n_out arrays dst.
+struct ZeroUnit {
+    double* const* dst;
+    const int32_t* starts;
+    int32_t n_out, count, len;
+};
+// max_out: the most outputs of any unit's item.
+int32_t launch_zero_columns(const ZeroUnit* units, int32_t n_units, int32_t max_out, hipStream_t s);
 // cstride: the largest tile of the DG0 items (cells).
 int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, int32_t n_units, int32_t S,
                               int32_t cstride, size_t lds, hipStream_t s);

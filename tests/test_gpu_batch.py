@@ -78,6 +78,39 @@ def test_batch_matches_single_launches(cpw, unit, sched, chunk):
                 assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what=f"replay {replay}")
 
 
+@pytest.mark.parametrize("race", [exm.EXM_RACE_OWNER, exm.EXM_RACE_ATOMIC])
+@pytest.mark.parametrize("chunk", [8, 16])
+def test_batch_p1_tile_kinds(race, chunk):
+    # P1 items on owner tiles, or on shared tiles whose boundary columns are
+    # zeroed in the graph and added atomically: every replay equals the single
+    # launches and the oracle, whatever the outputs held before
+    say(f"batch P1 tiles race={race} chunk={chunk}")
+    items, vcs = _setup(6, 0.01, 2, True, seed=13)
+    B = exm.Batch(items, chunk_layers=chunk, race=race)
+    t1 = B.tiles("P1")
+    assert t1[0] > 0 and t1[1] == chunk
+    ref = [([_single(d, f) for f in d["f"]], [_single(d, w) for w in d["w"]]) for d in items]
+    torch.cuda.synchronize()
+    for replay in range(3):
+        for d in items:
+            for t in d["b"] + d["g"]:
+                t.fill_(-7.5 if replay % 2 else 123.0)
+        torch.cuda.synchronize()
+        B.launch()
+        torch.cuda.synchronize()
+        for d, (rb, rg) in zip(items, ref):
+            for got, want in zip(d["b"] + d["g"], rb + rg):
+                g_, w_ = got.cpu().numpy(), want.cpu().numpy()
+                assert_close(g_, w_, np.abs(w_) + np.abs(w_).max() * 1e-3, rtol=1e-13, what=f"replay {replay}")
+    for d, vc in zip(items, vcs):
+        if d["space"].element != exm.EXM_ELEMENT_P1P1:
+            continue
+        pr = oracle.Problem(d["base"].mesh, d["base"].n_layers, "P1", vc)
+        for x, y in zip(d["f"] + d["w"], d["b"] + d["g"]):
+            xn = x.cpu().numpy()
+            assert_close(y.cpu().numpy(), pr.mass(xn), pr.mass_abs(xn), what=f"batch P1 race={race} vs oracle")
+
+
 @pytest.mark.parametrize("sched", [0, "gather"])
 def test_batch_matches_oracle(sched):
     items, vcs = _setup(4, 0.004, 2, True, seed=9)
