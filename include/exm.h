@@ -356,8 +356,9 @@ typedef struct {
     int32_t tile_cells;        /* TILED, STAGED, PIPELINED: 8..1024 target cells per tile */
                                /* (0 = choose)                                           */
     int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64; PIPELINED: 8, 12, 16, 20, 24  */
-                               /* or 32 on P1xP1, 8, 16 or 32 on DG; CHUNKED: 8, 16 or 32 */
-                               /* per chunk (0 = choose)                                 */
+                               /* or 32 on P1xP1, 8, 16 or 32 on DG (and 34 on DG0xDG0   */
+                               /* with columns of one height: 100 layers in three        */
+                               /* chunks); CHUNKED: 8, 16 or 32 per chunk (0 = choose)   */
 } exm_loop_opts;
 
 /* opts may be NULL (all defaults). */
@@ -487,8 +488,8 @@ typedef struct exm_batch exm_batch;
  * opts->tile_cells sets the work-unit size (base cells of DG0 units, base
  * vertices of P1 units, scaled by 64 / layers) and makes each kind take the
  * first tiling that fits; 0 = timed choice of unit size and tilings;
- * opts->chunk_layers fixes the tiles' chunk length (8 or 16 for P1, 8, 16
- * or 32 for DG0); opts->race = EXM_RACE_OWNER or EXM_RACE_ATOMIC restricts
+ * opts->chunk_layers fixes the tiles' chunk length (8 or 16 for P1, 8, 16,
+ * 32 or 34 for DG0); opts->race = EXM_RACE_OWNER or EXM_RACE_ATOMIC restricts
  * the P1 items to owner or to shared tiles (0 = timed choice of both). */
 int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm_loop_opts* opts,
                          void* stream, exm_batch** out);

@@ -234,8 +234,8 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
                   "tile_cells = %d outside [8, 1024]", opts->tile_cells);
         EXM_CHECK(opts->chunk_layers == 0 || opts->chunk_layers == 8 || opts->chunk_layers == 12 ||
                       opts->chunk_layers == 16 || opts->chunk_layers == 20 || opts->chunk_layers == 24 ||
-                      opts->chunk_layers == 32 || opts->chunk_layers == 64,
-                  EXM_ERANGE, "chunk_layers = %d: use 8, 12, 16, 20, 24, 32 or 64 (0 = choose)", opts->chunk_layers);
+                      opts->chunk_layers == 32 || opts->chunk_layers == 34 || opts->chunk_layers == 64,
+                  EXM_ERANGE, "chunk_layers = %d: use 8, 12, 16, 20, 24, 32, 34 or 64 (0 = choose)", opts->chunk_layers);
         if (opts->race) d.race = opts->race;
         if (opts->schedule) {
             if (opts->schedule != d.schedule) {
@@ -335,7 +335,8 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 && !one_layer ? 16 : 8;
         EXM_CHECK(pipe_chunk_ok(P.kernel, P.element, d.chunk_layers), EXM_ERANGE,
                   "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1, 8 or 16 on P2xP2, CG1xDG* "
-                  "and the cubic forms, and 8, 16 or 32 on the spaces discontinuous horizontally",
+                  "and the cubic forms, and 8, 16 or 32 on the spaces discontinuous horizontally (34 also on "
+                  "DG0xDG0)",
                   d.chunk_layers);
         // the fixed-height P1 x P1 walk takes larger tiles in wider workgroups
         const bool wide = P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1 && !mesh->variable &&
@@ -705,8 +706,9 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                     if (tc <= staged_max_tile_cells(S))
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
         if (pipe_supported(P.kernel, P.element))
-            for (int32_t tc : {16, 24, 32, 48, 64, 96, 128, 256})
-                for (int32_t S : {8, 12, 16, 20, 24, 32}) {
+            for (int32_t tc : {16, 24, 30, 32, 48, 64, 96, 128, 256})
+                for (int32_t S : {8, 12, 16, 20, 24, 32, 34}) {
+                    if ((tc == 30) != (S == 34)) continue;   // 30-cell tiles go with 34-layer chunks (DG0)
                     const bool p1 = P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1;
                     const int32_t narrow = pipe_max_tile_cells(P.kernel, P.element, S);
                     const int32_t limit = p1 ? std::max(narrow, pipe_p1_wide_max_cells(S)) : narrow;

@@ -668,8 +668,8 @@ int32_t exm_batch_create(int32_t n_items, const exm_batch_item* items, const exm
                     cand.push_back(Cand{c.first, c.second, sh});
             }
         } else {
-            for (const auto& c : {std::make_pair(32, 32), std::make_pair(32, 16), std::make_pair(64, 16),
-                                  std::make_pair(64, 8)})
+            for (const auto& c : {std::make_pair(32, 32), std::make_pair(30, 34), std::make_pair(32, 16),
+                                  std::make_pair(64, 16), std::make_pair(64, 8)})
                 cand.push_back(Cand{c.first, c.second, false});
         }
         const bool tune = !(opts && opts->tile_cells);

@@ -723,8 +723,8 @@ __device__ __forceinline__ void pipe_dg_tile(const ColArgs& a, const TileArgs& t
 {
     constexpr int NDOF = NH * NV;
     using C = Chunk<S>;
-    constexpr int P2 = C::P2, PP = C::PP, LS = C::LS;
-    constexpr int CPP = NT >> LS;   // one layer per thread
+    constexpr int P2 = C::P2, PP = C::PP;
+    constexpr int CPP = NT / S;   // one layer per thread (S need not be a power of two)
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
     const int32_t cb = t.cell_off[tile], nc = t.cell_off[tile + 1] - cb;
@@ -747,8 +747,8 @@ __device__ __forceinline__ void pipe_dg_tile(const ColArgs& a, const TileArgs& t
     int32_t d0[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const int c = (tid >> LS) + p * CPP;
-        has[p] = c < nc;
+        const int c = tid / S + p * CPP;
+        has[p] = tid < CPP * S && c < nc;
 #pragma unroll
         for (int q = 0; q < 3; ++q) lvq[p][q] = has[p] ? (int)t.lcv[(int64_t)(cb + c) * 3 + q] : 0;
         d0[p] = has[p] ? a.fmap[(int64_t)t.cells[cb + c] * NDOF] : 0;
@@ -761,7 +761,7 @@ __device__ __forceinline__ void pipe_dg_tile(const ColArgs& a, const TileArgs& t
     }
     lds_barrier();
 
-    const int j = tid & (S - 1);
+    const int j = tid % S;
     int vb[NP][3];
     double twoA[NP];
 #pragma unroll
@@ -2267,6 +2267,7 @@ bool pipe_chunk_ok(int32_t kernel, int32_t element, int32_t S)
     if (cubic_kernel(kernel) || cgdg_element(element)) return S == 8 || S == 16;
     if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 20 || S == 24 || S == 32;
     if (element == EXM_ELEMENT_P2P2) return S == 8 || S == 16;
+    if (element == EXM_ELEMENT_DG0DG0 && S == 34) return true;   // 100 layers in three chunks
     return S == 8 || S == 16 || S == 32;
 }
 
@@ -2339,7 +2340,7 @@ int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, 
     if (n_units <= 0) return EXM_OK;
     const dim3 grid((unsigned)n_units);
     // tiles beyond two cells per thread of a 256-thread workgroup take 512 threads
-    const bool wide = cstride > 2 * kThreads / S;
+    const bool wide = cstride > 2 * (kThreads / S);
     switch (S) {
     case 8:
         if (wide)
@@ -2359,7 +2360,13 @@ int32_t launch_batch_pipe_dg0(const BatchPipeItem* items, const int32_t* units, 
         else
             hipLaunchKernelGGL((k_batch_pipe_dg0<32, 2, 256>), grid, dim3(256), lds, s, items, units);
         break;
-    default: return fail(EXM_ERANGE, "chunk_layers = %d: batched DG0 tiles take 8, 16 or 32", S);
+    case 34:   // 100 layers in three chunk steps
+        if (wide)
+            hipLaunchKernelGGL((k_batch_pipe_dg0<34, 2, 512>), grid, dim3(512), lds, s, items, units);
+        else
+            hipLaunchKernelGGL((k_batch_pipe_dg0<34, 2, 256>), grid, dim3(256), lds, s, items, units);
+        break;
+    default: return fail(EXM_ERANGE, "chunk_layers = %d: batched DG0 tiles take 8, 16, 32 or 34", S);
     }
     EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;
@@ -2450,7 +2457,7 @@ static void launch_pipe_dg_e(const ColArgs& a, const TileArgs& t, int32_t cstrid
 {
     const dim3 grid((unsigned)t.tile_count);
     // tiles beyond two cells per thread of a 256-thread workgroup take 512 threads
-    if (cstride > 2 * kThreads / S)
+    if (cstride > 2 * (kThreads / S))
         hipLaunchKernelGGL((k_pipe_dg<NH, NV, S, 2, 512>), grid, dim3(512), lds, s, a, t);
     else
         hipLaunchKernelGGL((k_pipe_dg<NH, NV, S, 2, 256>), grid, dim3(kThreads), lds, s, a, t);
@@ -2460,7 +2467,7 @@ template <int NH, int S>
 static void launch_pipe_dgv_e(const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds, hipStream_t s)
 {
     const dim3 grid((unsigned)t.tile_count);
-    if (cstride > 2 * kThreads / S)
+    if (cstride > 2 * (kThreads / S))
         hipLaunchKernelGGL((k_pipe_dgv<NH, S, 2, 512>), grid, dim3(512), lds, s, a, t);
     else
         hipLaunchKernelGGL((k_pipe_dgv<NH, S, 2, 256>), grid, dim3(kThreads), lds, s, a, t);
@@ -2470,9 +2477,13 @@ template <int S>
 static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds,
                            hipStream_t s)
 {
+    if constexpr (S == 34) {   // DG0 x DG0 on columns of one height only (checked by the caller)
+        launch_pipe_dg_e<1, 1, S>(a, t, cstride, lds, s);
+        return;
+    }
     if (t.vlo) {   // columns of different heights (DG0 x DG0 only)
         const dim3 grid((unsigned)t.tile_count);
-        if (cstride > 2 * kThreads / S)
+        if (cstride > 2 * (kThreads / S))
             hipLaunchKernelGGL((k_pipe_dg0_var<S, 2, 512>), grid, dim3(512), lds, s, a, t);
         else
             hipLaunchKernelGGL((k_pipe_dg0_var<S, 2, 256>), grid, dim3(kThreads), lds, s, a, t);
@@ -2538,6 +2549,11 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
         case 8: launch_pipe_dg<8>(P.element, a, t, cstride, lds, s); break;
         case 16: launch_pipe_dg<16>(P.element, a, t, cstride, lds, s); break;
         case 32: launch_pipe_dg<32>(P.element, a, t, cstride, lds, s); break;
+        case 34:
+            EXM_CHECK(P.element == EXM_ELEMENT_DG0DG0 && !t.vlo, EXM_ERANGE,
+                      "chunk_layers = 34: the PIPELINED schedule takes it on DG0xDG0 with columns of one height");
+            launch_pipe_dg<34>(P.element, a, t, cstride, lds, s);
+            break;
         default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 16 or 32", S);
         }
         EXM_TRY_HIP(hipGetLastError());

@@ -43,9 +43,10 @@ def _single(d, x):
 
 # items on tiles (default: timed tile sizes; a fixed unit size takes the
 # first tiling that fits; chunk_layers fixes the chunk: 8 and 16 tile both
-# kinds, 32 only DG0) or on work units (GATHER)
+# kinds, 32 and 34 only DG0) or on work units (GATHER)
 @pytest.mark.parametrize("cpw,unit,sched,chunk", [(0, 0, 0, 0), (1, 8, 0, 0), (3, 64, 0, 8), (2, 1000, 0, 16),
-                                                  (0, 0, 0, 32), (0, 0, "gather", 0), (3, 64, "gather", 0)])
+                                                  (0, 0, 0, 32), (0, 0, 0, 34), (0, 0, "gather", 0),
+                                                  (3, 64, "gather", 0)])
 def test_batch_matches_single_launches(cpw, unit, sched, chunk):
     say(f"batch cpw={cpw} unit={unit} sched={sched} chunk={chunk}")
     items, _ = _setup(6, 0.01, 3, True)
@@ -57,11 +58,11 @@ def test_batch_matches_single_launches(cpw, unit, sched, chunk):
         assert t1 == (0, 0) and t0 == (0, 0)
         assert n_units >= len(items) and n_blocks > 0
     else:
-        if chunk == 32:   # P1 tiles take 8 or 16: the P1 items run on vertex units
+        if chunk in (32, 34):   # P1 tiles take 8 or 16: the P1 items run on vertex units
             assert t1 == (0, 0) and n_units > 0
         else:
             assert t1[0] > 0 and t1[1] == (chunk or t1[1]) and t1[1] in (8, 16)
-        assert t0[0] > 0 and t0[1] == (chunk or t0[1]) and t0[1] in (8, 16, 32)
+        assert t0[0] > 0 and t0[1] == (chunk or t0[1]) and t0[1] in (8, 16, 32, 34)
     ref = [([_single(d, f) for f in d["f"]], [_single(d, w) for w in d["w"]]) for d in items]
     torch.cuda.synchronize()
     for replay in range(3):

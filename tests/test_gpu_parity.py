@@ -177,6 +177,33 @@ def test_pipelined_dg_inc(space):
     assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what=f"pipelined {space} INC")
 
 
+@pytest.mark.parametrize("tile", [16, 24, 30])
+def test_pipelined_dg0_34_layer_chunks(tile):
+    # DG0xDG0 on columns of one height takes chunks of 34 layers (100 layers in
+    # three steps); a short, a one-chunk, a one-over and a ragged height
+    say(f"DG0 pipelined 34-layer chunks tile={tile}")
+    base = meshgen.tri_square(9)
+    for lam in (1, 33, 34, 35, 100):
+        c = Case(base, lam, "DG0", terrain=0.2)
+        x = meshgen.uniform_values(c.n, seed=23)
+        y0 = meshgen.uniform_values(c.n, seed=24)
+        xd, y = c.dev(x), c.dev(y0)
+        exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
+                     schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=34)
+        assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0),
+                     what=f"DG0 pipelined tile={tile} S=34 lam={lam}")
+        got = c.mass(x, schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=34)
+        assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"DG0 pipelined WRITE tile={tile} lam={lam}")
+
+
+def test_pipelined_34_layer_chunks_only_on_dg0():
+    c = Case(meshgen.tri_square(4), 10, "DG1")
+    x = meshgen.uniform_values(c.n, seed=25)
+    with pytest.raises(exm.ExmError) as e:
+        c.mass(x, schedule=exm.EXM_SCHED_PIPELINED, tile_cells=16, chunk_layers=34)
+    assert e.value.status == exm._abi.EXM_ERANGE, str(e.value)
+
+
 @pytest.mark.parametrize("n,lam", SHAPES)
 def test_owner_computes_matches_oracle(n, lam):
     say(f"owner computes n={n} lam={lam}")
