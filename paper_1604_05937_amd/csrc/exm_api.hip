@@ -827,7 +827,8 @@ int32_t exm_autotune_load(const char* path)
                       o.cols_per_wave <= 16 && o.waves_per_block >= 1 && o.waves_per_block <= 16 &&
                       o.tile_cells >= 0 && o.tile_cells <= 1024 &&
                       (o.chunk_layers == 0 || o.chunk_layers == 8 || o.chunk_layers == 12 || o.chunk_layers == 16 ||
-                       o.chunk_layers == 20 || o.chunk_layers == 24 || o.chunk_layers == 32 || o.chunk_layers == 64),
+                       o.chunk_layers == 20 || o.chunk_layers == 24 || o.chunk_layers == 32 || o.chunk_layers == 34 ||
+                       o.chunk_layers == 64),
                   EXM_ERANGE, "%s:%d: values out of range", path, ln);
         table[TuneKey(k, e, l, b)] = o;
     }

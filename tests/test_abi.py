@@ -75,3 +75,18 @@ def test_new_entry_points_validate_on_the_host():
     # the Jacobian and the facet loop are kernels of their own entry points only
     assert lib.exm_par_loop(_abi.EXM_K_CUBIC_JAC, None, 0, None, None, None) == _abi.EXM_EINVAL
     assert lib.exm_par_loop(_abi.EXM_K_FACET_JUMP, None, 0, None, None, None) == _abi.EXM_EINVAL
+
+
+def test_stored_launch_table_loads(tmp_path):
+    # the shipped table of tuned launches parses and passes the loader's range
+    # checks; a line with a chunk length no schedule takes is refused
+    lib = _abi.load()
+    table = os.path.join(ROOT, "paper_1604_05937_amd", "tuned_mi355x.txt")
+    assert lib.exm_autotune_load(table.encode()) == _abi.EXM_OK, _abi.last_error()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("# kernel element n_layers log2_cells race schedule cpw wpb tile_cells chunk_layers\n"
+                   "1 2 100 19 1 4 0 4 30 33\n")
+    assert lib.exm_autotune_load(str(bad).encode()) == _abi.EXM_ERANGE
+    assert "out of range" in _abi.last_error()
+    bad.write_text("1 2 100 19 1 4 0 4 30\n")
+    assert lib.exm_autotune_load(str(bad).encode()) == _abi.EXM_EINVAL
