@@ -65,7 +65,10 @@ int32_t exm_sync(void* stream);
  * Extruded mesh (Section 3.1): base mesh adjacency + number of layers.
  *
  * n_vertices, n_edges, n_cells: N_0, N_1, N_2 of the triangular base mesh.
- * cell_vertex: host [n_cells * 3]; every entry in [0, n_vertices).
+ * cell_vertex: host [n_cells * 3]; every entry in [0, n_vertices) and the
+ *              three vertices of a cell distinct (EXM_ERANGE, EXM_EINVAL
+ *              otherwise).  A vertex may belong to no cell: its columns
+ *              receive nothing (zeros where a loop overwrites its output).
  * cell_edge:   host [n_cells * 3] or NULL (needed only by spaces with DoFs on
  *              edges); every entry in [0, n_edges) and consistent with
  *              cell_vertex is NOT checked beyond range.
@@ -89,12 +92,13 @@ void exm_mesh_destroy(exm_mesh* mesh);
  * numbers every entity over its own range, so column starts become a prefix
  * sum, and a cell's explicit list is the stencil of its bottom prism, so that
  * L(c) + l * offset addresses layer layers[2c] + l of its column.  Loops on
- * such a mesh run the DIRECT schedule whatever the options ask (or GATHER,
- * when asked for, on the mass of P1P1, CG1xDG0 and CG1xDG1), and refuse
- * EXM_RACE_OWNER with the tiled schedules (EXM_EUNSUPPORTED); batches take
- * uniform meshes only.
- * Other arguments and errors as exm_mesh_create; a vertex that belongs to no
- * cell is rejected (EXM_EINVAL). */
+ * such a mesh run the DIRECT schedule whatever the options ask, except the
+ * PIPELINED schedule when asked for on the mass of P1P1 and DG0DG0 (n_layers
+ * <= 2000) and GATHER when asked for on the mass of P1P1, CG1xDG0 and CG1xDG1;
+ * they refuse EXM_RACE_OWNER with the tiled schedules (EXM_EUNSUPPORTED);
+ * batches take uniform meshes only.
+ * Other arguments and errors as exm_mesh_create; here every vertex must
+ * belong to a cell (EXM_EINVAL). */
 int32_t exm_mesh_create_var(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
                             const int32_t* cell_vertex, const int32_t* cell_edge,
                             int32_t n_layers, const int32_t* layers, exm_mesh** out);

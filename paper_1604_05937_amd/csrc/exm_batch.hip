@@ -350,10 +350,10 @@ int32_t build_tiles(exm_batch* B, bool p1, int32_t n_items, const exm_batch_item
     std::vector<int32_t> zstarts;
     std::vector<size_t> zbase;   // per item: its first entry in zstarts
     for (size_t i = 0; i < order.size(); ++i) {
-        if (shared) {   // the shared vertices' columns, in the P1 numbering (one value per level)
+        if (shared) {   // columns of the shared vertices and of those in no cell, in the P1 numbering
             const exm_batch_item& it = items[order[i]];
             zbase.push_back(zstarts.size());
-            for (int32_t v : plans[i]->shared_verts)
+            for (int32_t v : plans[i]->zero_verts)
                 zstarts.push_back((int32_t)(it.space->base[0] + (int64_t)v * it.space->col_size[0]));
         }
         const exm_batch_item& it = items[order[i]];

@@ -103,7 +103,8 @@ struct TilePlan {
     DevBuf<int32_t> colour_tiles;      // tiles grouped by colour
     DevBuf<int32_t> owned;             // owner plan: [n_tiles] vertices owned (the first of each vertex list)
     int64_t n_cell_entries = 0;        // owner plan: cells summed over tiles (>= n_cells)
-    std::vector<int32_t> shared_verts; // tile plan: the base vertices more than one tile touches (host)
+    std::vector<int32_t> zero_verts;   // tile plan: the base vertices no single tile writes alone: touched
+                                       // by more than one tile, or by none (host)
 };
 
 // Fans of base cells around every vertex (the GATHER schedule).

@@ -149,7 +149,7 @@ int32_t build_tile_plan(const exm_mesh* m, int32_t target, const TilePlan** out)
     plan->n_tile_verts = (int64_t)verts.size();
     plan->n_shared_verts = shared_v;
     for (int32_t v = 0; v < nv; ++v)
-        if (touch_v[v] > 1) plan->shared_verts.push_back(v);
+        if (touch_v[v] != 1) plan->zero_verts.push_back(v);
 
     // 3. greedy tile colouring: tiles sharing a vertex differ in colour
     std::vector<int32_t> tcol(nt, -1), mark;

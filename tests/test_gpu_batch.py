@@ -267,3 +267,45 @@ def test_batch_refuses_columns_of_different_heights():
     with pytest.raises(exm.ExmError) as e:
         exm.Batch([dict(space=Vx, coord_space=Vx, coords=X, mesh=mesh, f=f, b=b)])
     assert e.value.status == exm._abi.EXM_EUNSUPPORTED and "layer count" in str(e.value)
+
+
+@pytest.mark.parametrize("how", [dict(race=exm.EXM_RACE_ATOMIC), dict(race=exm.EXM_RACE_OWNER),
+                                 dict(schedule=exm.EXM_SCHED_GATHER)])
+def test_batch_vertices_in_no_cell(how):
+    # checkerboard bases of even n hold vertices that belong to no cell: on
+    # shared tiles, owner tiles and vertex units alike their output columns
+    # come out zero whatever the outputs held, and every other entry matches
+    # the oracle
+    say(f"batch, vertices in no cell, {how}")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(41)
+    items, probs, lone = [], [], []
+    for n, lam in ((4, 9), (12, 20)):
+        base = meshgen.tri_checkerboard(n)
+        mesh = exm.Mesh(base, lam)
+        V = exm.Space(mesh, "P1")
+        vc = meshgen.extruded_vertex_coords(base, lam, terrain=0.2)
+        X = exm.coordinate_field(V, vc)
+        rnd = lambda: torch.rand(V.n_dofs, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        items.append(dict(space=V, coord_space=V, coords=X, mesh=mesh, f=[rnd() for _ in range(2)],
+                          b=[V.zeros() for _ in range(2)], w=[rnd() for _ in range(2)], g=[V.zeros() for _ in range(2)]))
+        probs.append(oracle.Problem(base, lam, "P1", vc))
+        no_cell = np.nonzero(np.bincount(base.cell_vertex.ravel(), minlength=base.n_vertices) == 0)[0]
+        assert no_cell.size > 0
+        # P1 numbering: vertex v's column holds levels 0 .. lam at v * (lam + 1)
+        lone.append((no_cell[:, None] * (lam + 1) + np.arange(lam + 1)).ravel())
+    B = exm.Batch(items, **how)
+    if "race" in how:
+        assert B.tiles("P1")[0] > 0
+    for replay in range(2):
+        for d in items:
+            for t in d["b"] + d["g"]:
+                t.fill_(5.0 if replay else -3.0)
+        torch.cuda.synchronize()
+        B.launch()
+        torch.cuda.synchronize()
+        for d, pr, idx in zip(items, probs, lone):
+            for x, y in zip(d["f"] + d["w"], d["b"] + d["g"]):
+                yn, xn = y.cpu().numpy(), x.cpu().numpy()
+                assert np.all(yn[idx] == 0.0), f"replay {replay}: a column of a vertex in no cell holds {yn[idx]}"
+                assert_close(yn, pr.mass(xn), pr.mass_abs(xn), what=f"batch {how} replay {replay}")
