@@ -738,7 +738,8 @@ def layer_points(torch, exm, W, meshgen):
     import numpy as np
     out = {}
     A = exm.EXM_RACE_ATOMIC
-    shapes = {"P1": [(64, 16), (64, 8), (128, 8), (256, 8)], "DG0": [(32, 32), (32, 16), (64, 16)]}
+    shapes = {"P1": [(64, 16), (64, 8), (128, 8), (256, 8)],
+              "DG0": [(32, 32), (32, 16), (64, 16), (50, 20), (38, 26), (30, 34)]}
     for lam, order in ((20, "rcm"), (50, "rcm"), (200, "rcm"), (100, "random")):
         n = 512 if order == "random" else int(round(512 * np.sqrt(100.0 / lam)))
         t0 = time.time()

@@ -360,9 +360,10 @@ typedef struct {
     int32_t tile_cells;        /* TILED, STAGED, PIPELINED: 8..1024 target cells per tile */
                                /* (0 = choose)                                           */
     int32_t chunk_layers;      /* STAGED: 8, 16, 32 or 64; PIPELINED: 8, 12, 16, 20, 24  */
-                               /* or 32 on P1xP1, 8, 16 or 32 on DG (and 34 on DG0xDG0   */
-                               /* with columns of one height: 100 layers in three        */
-                               /* chunks); CHUNKED: 8, 16 or 32 per chunk (0 = choose)   */
+                               /* or 32 on P1xP1, 8, 16 or 32 on DG (and 20, 26 or 34 on */
+                               /* DG0xDG0 with columns of one height: 20, 50 and 100     */
+                               /* layers in one, two and three chunks); CHUNKED: 8, 16   */
+                               /* or 32 per chunk (0 = choose)                           */
 } exm_loop_opts;
 
 /* opts may be NULL (all defaults). */

@@ -234,8 +234,10 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
                   "tile_cells = %d outside [8, 1024]", opts->tile_cells);
         EXM_CHECK(opts->chunk_layers == 0 || opts->chunk_layers == 8 || opts->chunk_layers == 12 ||
                       opts->chunk_layers == 16 || opts->chunk_layers == 20 || opts->chunk_layers == 24 ||
-                      opts->chunk_layers == 32 || opts->chunk_layers == 34 || opts->chunk_layers == 64,
-                  EXM_ERANGE, "chunk_layers = %d: use 8, 12, 16, 20, 24, 32, 34 or 64 (0 = choose)", opts->chunk_layers);
+                      opts->chunk_layers == 26 || opts->chunk_layers == 32 || opts->chunk_layers == 34 ||
+                      opts->chunk_layers == 64,
+                  EXM_ERANGE, "chunk_layers = %d: use 8, 12, 16, 20, 24, 26, 32, 34 or 64 (0 = choose)",
+                  opts->chunk_layers);
         if (opts->race) d.race = opts->race;
         if (opts->schedule) {
             if (opts->schedule != d.schedule) {
@@ -335,8 +337,11 @@ static int32_t choose(const exm_mesh* mesh, const LoopLaunch& P, const exm_loop_
         if (!d.chunk_layers) d.chunk_layers = P.n_layers >= 12 && !one_layer ? 16 : 8;
         EXM_CHECK(pipe_chunk_ok(P.kernel, P.element, d.chunk_layers), EXM_ERANGE,
                   "PIPELINED: chunk_layers = %d, use 8, 12, 16, 20, 24 or 32 on P1xP1, 8 or 16 on P2xP2, CG1xDG* "
-                  "and the cubic forms, and 8, 16 or 32 on the spaces discontinuous horizontally (34 also on "
-                  "DG0xDG0)",
+                  "and the cubic forms, and 8, 16 or 32 on the spaces discontinuous horizontally (20, 26 and 34 "
+                  "also on DG0xDG0 with columns of one height)",
+                  d.chunk_layers);
+        EXM_CHECK(!(mesh->variable && P.element == EXM_ELEMENT_DG0DG0 && dg0_long_chunk(d.chunk_layers)), EXM_ERANGE,
+                  "PIPELINED: chunk_layers = %d on DG0xDG0 needs columns of one height (use 8, 16 or 32)",
                   d.chunk_layers);
         // the fixed-height P1 x P1 walk takes larger tiles in wider workgroups
         const bool wide = P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1 && !mesh->variable &&
@@ -706,14 +711,16 @@ int32_t exm_autotune(int32_t kernel, const exm_mesh* iterset, int32_t nargs, con
                     if (tc <= staged_max_tile_cells(S))
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_STAGED, 0, 4, tc, S});
         if (pipe_supported(P.kernel, P.element))
-            for (int32_t tc : {16, 24, 30, 32, 48, 64, 96, 128, 256})
-                for (int32_t S : {8, 12, 16, 20, 24, 32, 34}) {
-                    if ((tc == 30) != (S == 34)) continue;   // 30-cell tiles go with 34-layer chunks (DG0)
+            for (int32_t tc : {16, 24, 30, 32, 38, 48, 50, 64, 96, 128, 256})
+                for (int32_t S : {8, 12, 16, 20, 24, 26, 32, 34}) {
                     const bool p1 = P.kernel == EXM_K_MASS && P.element == EXM_ELEMENT_P1P1;
                     const int32_t narrow = pipe_max_tile_cells(P.kernel, P.element, S);
+                    // 30, 38 and 50 cells: the full tiles of DG0's 34-, 26- and 20-layer chunks
+                    const bool full_dg0 = P.element == EXM_ELEMENT_DG0DG0 && dg0_long_chunk(S) && tc == narrow;
+                    if ((tc == 30 || tc == 38 || tc == 50) && !full_dg0) continue;
                     const int32_t limit = p1 ? std::max(narrow, pipe_p1_wide_max_cells(S)) : narrow;
                     if (pipe_chunk_ok(P.kernel, P.element, S) && tc <= limit &&
-                        (tc >= 32 || P.element == EXM_ELEMENT_P2P2 || P.kernel != EXM_K_MASS)) {
+                        (tc >= 32 || full_dg0 || P.element == EXM_ELEMENT_P2P2 || P.kernel != EXM_K_MASS)) {
                         cand.push_back(exm_loop_opts{races[r], EXM_SCHED_PIPELINED, 0, 4, tc, S});
                         if (r == 0 && p1) cand.push_back(exm_loop_opts{EXM_RACE_OWNER, EXM_SCHED_PIPELINED, 0, 4, tc, S});
                         if (p1 && (S & (S - 1)) == 0 && tc <= narrow) {
@@ -827,8 +834,8 @@ int32_t exm_autotune_load(const char* path)
                       o.cols_per_wave <= 16 && o.waves_per_block >= 1 && o.waves_per_block <= 16 &&
                       o.tile_cells >= 0 && o.tile_cells <= 1024 &&
                       (o.chunk_layers == 0 || o.chunk_layers == 8 || o.chunk_layers == 12 || o.chunk_layers == 16 ||
-                       o.chunk_layers == 20 || o.chunk_layers == 24 || o.chunk_layers == 32 || o.chunk_layers == 34 ||
-                       o.chunk_layers == 64),
+                       o.chunk_layers == 20 || o.chunk_layers == 24 || o.chunk_layers == 26 || o.chunk_layers == 32 ||
+                       o.chunk_layers == 34 || o.chunk_layers == 64),
                   EXM_ERANGE, "%s:%d: values out of range", path, ln);
         table[TuneKey(k, e, l, b)] = o;
     }

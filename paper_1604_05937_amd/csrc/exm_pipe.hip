@@ -2257,7 +2257,7 @@ bool pipe_supported(int32_t kernel, int32_t element)
 int32_t pipe_max_tile_cells(int32_t kernel, int32_t element, int32_t S)
 {
     if (cubic_kernel(kernel) || cgdg_element(element)) return kThreads / S;   // one layer of one cell per thread
-    if (dg_element(element)) return 2 * 512 / S;
+    if (dg_element(element)) return 2 * (512 / S);   // two passes of a 512-thread workgroup
     if (element == EXM_ELEMENT_P2P2) return kThreads / (S / kLayers2);
     return kPasses * (kThreads / (S / kLayers));
 }
@@ -2267,7 +2267,7 @@ bool pipe_chunk_ok(int32_t kernel, int32_t element, int32_t S)
     if (cubic_kernel(kernel) || cgdg_element(element)) return S == 8 || S == 16;
     if (element == EXM_ELEMENT_P1P1) return S == 8 || S == 12 || S == 16 || S == 20 || S == 24 || S == 32;
     if (element == EXM_ELEMENT_P2P2) return S == 8 || S == 16;
-    if (element == EXM_ELEMENT_DG0DG0 && S == 34) return true;   // 100 layers in three chunks
+    if (element == EXM_ELEMENT_DG0DG0 && dg0_long_chunk(S)) return true;
     return S == 8 || S == 16 || S == 32;
 }
 
@@ -2477,7 +2477,7 @@ template <int S>
 static void launch_pipe_dg(int32_t element, const ColArgs& a, const TileArgs& t, int32_t cstride, size_t lds,
                            hipStream_t s)
 {
-    if constexpr (S == 34) {   // DG0 x DG0 on columns of one height only (checked by the caller)
+    if constexpr (S == 20 || S == 26 || S == 34) {   // DG0 x DG0 on columns of one height only (checked by the caller)
         launch_pipe_dg_e<1, 1, S>(a, t, cstride, lds, s);
         return;
     }
@@ -2549,10 +2549,17 @@ int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, in
         case 8: launch_pipe_dg<8>(P.element, a, t, cstride, lds, s); break;
         case 16: launch_pipe_dg<16>(P.element, a, t, cstride, lds, s); break;
         case 32: launch_pipe_dg<32>(P.element, a, t, cstride, lds, s); break;
+        case 20:
+        case 26:
         case 34:
             EXM_CHECK(P.element == EXM_ELEMENT_DG0DG0 && !t.vlo, EXM_ERANGE,
-                      "chunk_layers = 34: the PIPELINED schedule takes it on DG0xDG0 with columns of one height");
-            launch_pipe_dg<34>(P.element, a, t, cstride, lds, s);
+                      "chunk_layers = %d: the PIPELINED schedule takes it on DG0xDG0 with columns of one height", S);
+            if (S == 20)
+                launch_pipe_dg<20>(P.element, a, t, cstride, lds, s);
+            else if (S == 26)
+                launch_pipe_dg<26>(P.element, a, t, cstride, lds, s);
+            else
+                launch_pipe_dg<34>(P.element, a, t, cstride, lds, s);
             break;
         default: return fail(EXM_ERANGE, "chunk_layers = %d: the PIPELINED schedule takes 8, 16 or 32", S);
         }

@@ -107,6 +107,10 @@ int32_t pipe_p1_wide_max_cells(int32_t S);
 int32_t pipe_p1_wide_max_verts(int32_t S);
 int32_t pipe_max_tile_entities(int32_t S);
 bool pipe_chunk_ok(int32_t kernel, int32_t element, int32_t S);
+// Chunk lengths the DG0 x DG0 tile walk takes beside 8, 16 and 32 on columns
+// of one height (one layer per thread, so any even length): 20, 26 and 34
+// layers cover 20, 50 and 100 layers in one, two and three chunk steps.
+inline bool dg0_long_chunk(int32_t S) { return S == 20 || S == 26 || S == 34; }
 int32_t launch_pipe(const LoopLaunch& P, const ColArgs& a, const TileArgs& t, int32_t cstride, int32_t S, size_t lds,
                     hipStream_t s);
 size_t chunk_lds_bytes(int32_t vstride, int32_t S);

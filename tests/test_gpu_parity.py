@@ -177,31 +177,42 @@ def test_pipelined_dg_inc(space):
     assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0), what=f"pipelined {space} INC")
 
 
-@pytest.mark.parametrize("tile", [16, 24, 30])
-def test_pipelined_dg0_34_layer_chunks(tile):
-    # DG0xDG0 on columns of one height takes chunks of 34 layers (100 layers in
-    # three steps); a short, a one-chunk, a one-over and a ragged height
-    say(f"DG0 pipelined 34-layer chunks tile={tile}")
+@pytest.mark.parametrize("chunk,tile", [(20, 16), (20, 32), (20, 50), (26, 24), (26, 38), (34, 16), (34, 24),
+                                        (34, 30)])
+def test_pipelined_dg0_long_chunks(chunk, tile):
+    # DG0xDG0 on columns of one height takes chunks of 20, 26 or 34 layers
+    # (20, 50 and 100 layers in one, two and three steps); a single layer, one
+    # short of a chunk, one chunk, one over, a ragged height and 100 layers
+    say(f"DG0 pipelined {chunk}-layer chunks tile={tile}")
     base = meshgen.tri_square(9)
-    for lam in (1, 33, 34, 35, 100):
+    for lam in (1, chunk - 1, chunk, chunk + 1, 2 * chunk + 3, 100):
         c = Case(base, lam, "DG0", terrain=0.2)
         x = meshgen.uniform_values(c.n, seed=23)
         y0 = meshgen.uniform_values(c.n, seed=24)
         xd, y = c.dev(x), c.dev(y0)
         exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(xd, c.V, exm.EXM_READ), (y, c.V, exm.EXM_INC)],
-                     schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=34)
+                     schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=chunk)
         assert_close(c.host(y), c.ref.mass(x) + y0, c.ref.mass_abs(x) + np.abs(y0),
-                     what=f"DG0 pipelined tile={tile} S=34 lam={lam}")
-        got = c.mass(x, schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=34)
-        assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"DG0 pipelined WRITE tile={tile} lam={lam}")
+                     what=f"DG0 pipelined tile={tile} S={chunk} lam={lam}")
+        got = c.mass(x, schedule=exm.EXM_SCHED_PIPELINED, tile_cells=tile, chunk_layers=chunk)
+        assert_close(got, c.ref.mass(x), c.ref.mass_abs(x), what=f"DG0 pipelined WRITE tile={tile} S={chunk} lam={lam}")
 
 
-def test_pipelined_34_layer_chunks_only_on_dg0():
+@pytest.mark.parametrize("chunk", [20, 26, 34])
+def test_pipelined_long_chunks_only_on_dg0(chunk):
+    # other spaces, and DG0 on columns of different heights, refuse them
+    # before any launch
     c = Case(meshgen.tri_square(4), 10, "DG1")
     x = meshgen.uniform_values(c.n, seed=25)
     with pytest.raises(exm.ExmError) as e:
-        c.mass(x, schedule=exm.EXM_SCHED_PIPELINED, tile_cells=16, chunk_layers=34)
+        c.mass(x, schedule=exm.EXM_SCHED_PIPELINED, tile_cells=16, chunk_layers=chunk)
     assert e.value.status == exm._abi.EXM_ERANGE, str(e.value)
+    base = meshgen.tri_square(4)
+    v = Case(base, 10, "DG0", layers=meshgen.layer_ranges(base, 10, "random"))
+    with pytest.raises(exm.ExmError) as e:
+        v.mass(meshgen.uniform_values(v.n, seed=26), schedule=exm.EXM_SCHED_PIPELINED, tile_cells=16,
+               chunk_layers=chunk)
+    assert e.value.status == exm._abi.EXM_ERANGE and "one height" in str(e.value), str(e.value)
 
 
 @pytest.mark.parametrize("n,lam", SHAPES)
