@@ -70,8 +70,10 @@ int32_t exm_sync(void* stream);
  *              otherwise).  A vertex may belong to no cell: its columns
  *              receive nothing (zeros where a loop overwrites its output).
  * cell_edge:   host [n_cells * 3] or NULL (needed only by spaces with DoFs on
- *              edges); every entry in [0, n_edges) and consistent with
- *              cell_vertex is NOT checked beyond range.
+ *              edges); every entry in [0, n_edges) (EXM_ERANGE); edge a of
+ *              cell c joins the cell's vertices (a+1)%3 and (a+2)%3, every
+ *              cell that lists an edge sees the same two vertices, and no two
+ *              edges join the same pair (EXM_EINVAL otherwise).
  * n_layers:    lambda >= 1, the number of layers (prisms per column).
  * The arrays are copied to the current HIP device.  Returns the handle in
  * *out (library-owned; free with exm_mesh_destroy).
@@ -261,7 +263,8 @@ int32_t exm_coordinates_verify(const exm_space* space, const double* X, void* st
  *
  * INC adds into the caller's buffer (zero it first for a plain assembly);
  * WRITE overwrites every DoF of the space.  All field args of one call must
- * be distinct buffers, all on one space.  Floating-point results may differ in
+ * be on one space, and no output may share a byte with another argument,
+ * the coordinate field included (EXM_EINVAL).  Floating-point results may differ in
  * the last bits between race strategies (different summation order).
  */
 #define EXM_READ 1

@@ -166,9 +166,17 @@ static int32_t prepare(int32_t kernel, const exm_mesh* m, int32_t nargs, const e
             write = w;
         }
     }
+    // an output may share no byte with another argument: the walks read
+    // neighbouring columns of the inputs while other workgroups write outputs
+    auto bytes = [&](int i) {   // dim components per DoF (three for the coordinate field)
+        return (uintptr_t)args[i].dim * (uintptr_t)args[i].space->n_dofs * sizeof(double);
+    };
     for (int i = 1 + sig.n_in; i < nargs; ++i)
-        for (int j = 0; j < nargs; ++j)
-            EXM_CHECK(i == j || args[i].data != args[j].data, EXM_EINVAL, "output args[%d] aliases args[%d]", i, j);
+        for (int j = 0; j < nargs; ++j) {
+            const uintptr_t a0 = (uintptr_t)args[i].data, b0 = (uintptr_t)args[j].data;
+            EXM_CHECK(i == j || a0 + bytes(i) <= b0 || b0 + bytes(j) <= a0, EXM_EINVAL,
+                      "output args[%d] overlaps args[%d]", i, j);
+        }
     std::memset(&P, 0, sizeof(P));
     P.fspace = V;
     P.xspace = X.space;

@@ -177,10 +177,36 @@ static int32_t mesh_create(int32_t n_vertices, int32_t n_edges, int32_t n_cells,
         EXM_CHECK(v[0] != v[1] && v[1] != v[2] && v[0] != v[2], EXM_EINVAL,
                   "cell %lld repeats a vertex", (long long)c);
     }
-    if (cell_edge)
+    if (cell_edge) {
         for (int64_t i = 0; i < (int64_t)n_cells * 3; ++i)
             EXM_CHECK(cell_edge[i] >= 0 && cell_edge[i] < n_edges, EXM_ERANGE,
                       "cell_edge[%lld] = %d outside [0, %d)", (long long)i, cell_edge[i], n_edges);
+        // edge a of a cell joins its vertices (a + 1) % 3 and (a + 2) % 3: every
+        // cell that lists an edge must see the same two vertices, and no two
+        // edges may join the same pair (a shared edge would get two columns)
+        std::vector<int64_t> ends((size_t)n_edges, -1);
+        for (int64_t c = 0; c < n_cells; ++c)
+            for (int a = 0; a < 3; ++a) {
+                const int32_t e = cell_edge[c * 3 + a];
+                const int64_t u = cell_vertex[c * 3 + (a + 1) % 3], w = cell_vertex[c * 3 + (a + 2) % 3];
+                const int64_t key = std::min(u, w) * n_vertices + std::max(u, w);
+                EXM_CHECK(ends[e] < 0 || ends[e] == key, EXM_EINVAL,
+                          "cell_edge: edge %d, opposite local vertex %d of cell %lld, joins vertices %lld and %lld "
+                          "there but %lld and %lld in an earlier cell",
+                          e, a, (long long)c, (long long)u, (long long)w, (long long)(ends[e] / n_vertices),
+                          (long long)(ends[e] % n_vertices));
+                ends[e] = key;
+            }
+        std::vector<int64_t> sorted;
+        sorted.reserve(ends.size());
+        for (int64_t k : ends)
+            if (k >= 0) sorted.push_back(k);
+        std::sort(sorted.begin(), sorted.end());
+        const auto dup = std::adjacent_find(sorted.begin(), sorted.end());
+        EXM_CHECK(dup == sorted.end(), EXM_EINVAL, "cell_edge: two edges join vertices %lld and %lld",
+                  (long long)(dup == sorted.end() ? 0 : *dup / n_vertices),
+                  (long long)(dup == sorted.end() ? 0 : *dup % n_vertices));
+    }
     if (layers)
         for (int64_t c = 0; c < n_cells; ++c)
             EXM_CHECK(layers[2 * c] >= 0 && layers[2 * c] < layers[2 * c + 1] && layers[2 * c + 1] <= n_layers,

@@ -90,3 +90,28 @@ def test_stored_launch_table_loads(tmp_path):
     assert "out of range" in _abi.last_error()
     bad.write_text("1 2 100 19 1 4 0 4 30\n")
     assert lib.exm_autotune_load(str(bad).encode()) == _abi.EXM_EINVAL
+
+
+def test_edge_convention_is_checked():
+    # two triangles sharing the edge (1, 2); edge a of a cell joins its
+    # vertices (a+1)%3 and (a+2)%3.  A consistent map is [[0, 1, 2], [3, 4, 0]]
+    # (it reaches the device upload, so it is exercised by the GPU tests).
+    lib = _abi.load()
+    h = ctypes.c_void_p()
+    cv = np.array([[0, 1, 2], [2, 1, 3]], dtype=np.int32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    # cell 1 names edge 1 (0-2 in cell 0) for its edge joining 2 and 1
+    ce = np.array([[0, 1, 2], [3, 4, 1]], dtype=np.int32)
+    assert lib.exm_mesh_create(4, 5, 2, ptr(cv), ptr(ce), 3, ctypes.byref(h)) == _abi.EXM_EINVAL
+    assert "joins vertices" in _abi.last_error() and "earlier cell" in _abi.last_error()
+    # a sixth edge joining 1 and 2 again: the shared edge would get two columns
+    ce = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    assert lib.exm_mesh_create(4, 6, 2, ptr(cv), ptr(ce), 3, ctypes.byref(h)) == _abi.EXM_EINVAL
+    assert "two edges join vertices 1 and 2" in _abi.last_error()
+    # an edge index out of range is a range error, as before
+    ce = np.array([[0, 1, 2], [3, 4, 7]], dtype=np.int32)
+    assert lib.exm_mesh_create(4, 5, 2, ptr(cv), ptr(ce), 3, ctypes.byref(h)) == _abi.EXM_ERANGE
+    # the same checks on the variable-height entry point
+    lay = np.array([[0, 3], [1, 3]], dtype=np.int32)
+    ce = np.array([[0, 1, 2], [3, 4, 1]], dtype=np.int32)
+    assert lib.exm_mesh_create_var(4, 5, 2, ptr(cv), ptr(ce), 3, ptr(lay), ctypes.byref(h)) == _abi.EXM_EINVAL

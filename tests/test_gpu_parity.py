@@ -3,6 +3,7 @@ inputs: numbering and lists bit-exact, FP64 values to the componentwise
 tolerance of tests/gpu_common.py."""
 import numpy as np
 import pytest
+import torch
 
 import paper_1604_05937_amd as exm
 from paper_1604_05937_amd import meshgen
@@ -339,3 +340,33 @@ def test_colour_counts():
     n = mesh.colours()
     # a vertex of the triangulated square touches at most 6 cells
     assert 6 <= n <= 13
+
+
+@pytest.mark.parametrize("case", ["same_buffer", "output_inside_input", "input_inside_output", "output_in_coords",
+                                  "two_outputs_overlap"])
+def test_par_loop_refuses_overlapping_arguments(case):
+    # an output may share no byte with any other argument (refused on the
+    # host, before any launch); disjoint views of one allocation are fine
+    c = Case(meshgen.tri_square(4), 5, "P1")
+    n = c.n
+    big = torch.zeros(3 * n + 8, dtype=torch.float64, device="cuda")
+    x = big[:n]
+    R, I = exm.EXM_READ, exm.EXM_INC
+    if case == "same_buffer":
+        fields = [(x, c.V, R), (x, c.V, I)]
+    elif case == "output_inside_input":
+        fields = [(x, c.V, R), (big[n - 1:2 * n - 1], c.V, I)]
+    elif case == "input_inside_output":
+        fields = [(big[1:n + 1], c.V, R), (x, c.V, I)]
+    elif case == "output_in_coords":
+        fields = [(x, c.V, R), (c.X.view(-1)[2 * n:3 * n], c.V, I)]
+    else:
+        u = big[n:2 * n]
+        fields = [(x, c.V, R), (u, c.V, R), (big[2 * n:3 * n], c.V, I), (big[2 * n + 4:3 * n + 4], c.V, I)]
+    kernel = exm.EXM_K_CUBIC_VJP if case == "two_outputs_overlap" else exm.EXM_K_MASS
+    with pytest.raises(exm.ExmError) as e:
+        exm.par_loop(kernel, c.mesh, c.X, c.Vx, fields)
+    assert e.value.status == exm._abi.EXM_EINVAL and "overlaps" in str(e.value), str(e.value)
+    # back to back views of one allocation are accepted
+    exm.par_loop(exm.EXM_K_MASS, c.mesh, c.X, c.Vx, [(x, c.V, R), (big[n:2 * n], c.V, I)])
+    torch.cuda.synchronize()
