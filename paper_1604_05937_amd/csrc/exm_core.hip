@@ -139,6 +139,24 @@ __global__ void k_triad(double* __restrict__ a, const double* __restrict__ b, co
         a[i] = b[i] + alpha * c[i];
 }
 
+// The same on 16-byte pairs with non-temporal loads and stores (arrays
+// 16-byte aligned): the faster of the two on gfx950 by about 8 %, so the
+// yardstick is not set low by the access width.
+typedef double double2v __attribute__((ext_vector_type(2)));
+__global__ void k_triad2(double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+                         double alpha, int64_t n)
+{
+    const int64_t np = n / 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < np; i += stride) {
+        const double2v x = __builtin_nontemporal_load((const double2v*)b + i);
+        const double2v y = __builtin_nontemporal_load((const double2v*)c + i);
+        __builtin_nontemporal_store(x + alpha * y, (double2v*)a + i);
+    }
+    if (t0 == 0 && (n & 1)) a[n - 1] = b[n - 1] + alpha * c[n - 1];
+}
+
 }  // namespace exm
 
 using namespace exm;
@@ -784,9 +802,14 @@ int32_t exm_stream_triad(double* a, const double* b, const double* c, double alp
     EXM_CHECK(block >= 64 && block <= 1024 && block % 64 == 0, EXM_ERANGE, "block = %d not a multiple of 64 in [64, 1024]", block);
     EXM_CHECK(grid >= 0, EXM_ERANGE, "grid < 0");
     if (n == 0) return EXM_OK;
-    int64_t g = grid ? grid : (n + block - 1) / block;
+    const bool pairs = (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) == 0 && n >= 2;
+    const int64_t items = pairs ? n / 2 : n;
+    int64_t g = grid ? grid : (items + block - 1) / block;
     EXM_CHECK(g <= INT32_MAX, EXM_ERANGE, "grid too large");
-    hipLaunchKernelGGL(k_triad, dim3((unsigned)g), dim3(block), 0, (hipStream_t)stream, a, b, c, alpha, n);
+    if (pairs)
+        hipLaunchKernelGGL(k_triad2, dim3((unsigned)g), dim3(block), 0, (hipStream_t)stream, a, b, c, alpha, n);
+    else
+        hipLaunchKernelGGL(k_triad, dim3((unsigned)g), dim3(block), 0, (hipStream_t)stream, a, b, c, alpha, n);
     EXM_TRY_HIP(hipGetLastError());
     return EXM_OK;
 }

@@ -64,3 +64,24 @@ def test_one_layer_one_cell(space):
         assert_close(c.mass(x, schedule=schedule), c.ref.mass(x), c.ref.mass_abs(x), what=f"one prism {space}")
     # the volume of the one prism, from the residual of 1
     assert abs(c.mass(np.ones(c.n)).sum() - 0.5) < 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 1001, 4096])
+@pytest.mark.parametrize("offset", [0, 1])
+@pytest.mark.parametrize("grid", [0, 3])
+def test_stream_triad(n, offset, grid):
+    # 16-byte pairs (aligned arrays, odd n ends in a single element) and one
+    # element per lane (arrays 8 bytes off), one element or pair per thread
+    # or a grid-stride loop over few workgroups
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    # three allocations (each 16-byte aligned), viewed from element `offset`
+    a, b, c = (torch.rand(n + 1, dtype=torch.float64, device="cuda", generator=g)[offset:offset + n]
+               for _ in range(3))
+    assert all((t.data_ptr() % 16 == 0) == (offset == 0) for t in (a, b, c))
+    want = b.cpu().numpy() + 3.0 * c.cpu().numpy()
+    exm.stream_triad(a, b, c, 3.0, block=256, grid=grid)
+    torch.cuda.synchronize()
+    # within one rounding of the fused or separate multiply-add
+    np.testing.assert_allclose(a.cpu().numpy(), want, rtol=4.5e-16, atol=0)
