@@ -259,25 +259,31 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
             }
         }
     };
-    // old output values of chunk k (levels below its top), into registers
+    // levels chunk k writes back: its nl layers' bottom levels, and on a
+    // last chunk shorter than S its top level too (an item of the chunk's
+    // level range, so its old value is loaded a step ahead like the others)
+    const int nch = (lam + S - 1) / S;
+    const int top_in_items = lam - (nch - 1) * S < S;
+    auto levels_written = [&](int k) { return min(S, lam - k * S) + (k == nch - 1 ? top_in_items : 0); };
+    // old output values of chunk k (the levels it writes), into registers
     auto load_old = [&](int k, double (&dst)[kItems]) {
         const int l0 = k * S;
-        const int nl = min(S, lam - l0);
+        const int nw = levels_written(k);
 #pragma unroll
         for (int i = 0; i < kItems; ++i)
-            dst[i] = (((uint32_t)ipos[i] >> 30) == 1 && (tid + NT * i) % S < nl) ? y[(int64_t)iglb[i] + l0] : 0.0;
+            dst[i] = (((uint32_t)ipos[i] >> 30) == 1 && (tid + NT * i) % S < nw) ? y[(int64_t)iglb[i] + l0] : 0.0;
     };
-    // write chunk k back (levels l0 .. l0 + nl - 1); with `carry`, move its
-    // top level to level 0 for chunk k + 1
+    // write chunk k back (its levels_written levels from l0); with `carry`,
+    // move its top level to level 0 for chunk k + 1
     auto write_back = [&](int k, const double (&old)[kItems], bool carry) {
         const int l0 = k * S;
-        const int nl = min(S, lam - l0);
+        const int nw = levels_written(k);
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const int jj = (tid + NT * i) % S;
             const int kind = (int)((uint32_t)ipos[i] >> 30);
             const int pos = ipos[i] & 0x3fffffff;
-            if (kind == 0 || jj >= nl) continue;
+            if (kind == 0 || jj >= nw) continue;
             const double s = A[pos];
             const int64_t g = (int64_t)iglb[i] + l0;
             if (kind == 2)
@@ -293,7 +299,6 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
         }
     };
 
-    const int nch = (lam + S - 1) / S;
     for (int pass = 0; pass < F.count(); ++pass) {
         if (pass > 0) {   // the previous pass's last write-back has read A
             x = F.src(pass);
@@ -362,13 +367,14 @@ __device__ __forceinline__ void pipe_p1_tile(const ColArgs& a, const TileArgs& t
                     if (MODE != kOwner || (wmask[p] >> q & 1)) lds_add(A + o[q] + r, acc[q]);
             }
         }
-        // write back the last chunk, its top level included
+        // write back the last chunk, its top level included (by the items
+        // when the chunk is shorter than S, else here)
         lds_barrier();
         {
             const int k = nch - 1;
             const int l0 = k * S, nl = lam - l0;
             write_back(k, yB, false);
-            for (int v = tid; v < no; v += NT) {
+            for (int v = top_in_items ? no : tid; v < no; v += NT) {
                 const int32_t xs = Txst[v];
                 const double s = A[v * P2 + (xs & 1) + nl];
                 const int64_t g = (int64_t)xs + lam;
@@ -1846,26 +1852,32 @@ __global__ void __launch_bounds__(kThreads, FORM == 3 && NI > 1 ? 3 : 4) k_pipe_
         const int v = (tid + kThreads * i) / S;
         return v >= nv ? 0 : ((ATOMIC && vshared(Ttag[v])) ? 2 : 1);
     };
+    // levels chunk k writes back: its layers' bottom levels, and on a last
+    // chunk shorter than S its top level too (so that its old value is
+    // loaded a step ahead like the others)
+    const int nch = (lam + S - 1) / S;
+    const int top_in_items = lam - (nch - 1) * S < S;
+    auto levels_written = [&](int k) { return min(S, lam - k * S) + (k == nch - 1 ? top_in_items : 0); };
     auto load_old = [&](int k, double (&dst)[NOUT][NI]) {
-        const int nl = min(S, lam - k * S);
+        const int nw = levels_written(k);
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int it = tid + kThreads * i;
             const int v = it / S, jj = it % S;
-            const bool ld = item_kind(i) == 1 && jj < nl;
+            const bool ld = item_kind(i) == 1 && jj < nw;
             const int64_t g = ld ? (int64_t)Txst[v] + k * S + jj : 0;
 #pragma unroll
             for (int o = 0; o < NOUT; ++o) dst[o][i] = ld ? out[o][g] : 0.0;
         }
     };
     auto write_back = [&](int k, const double (&old)[NOUT][NI], bool carry) {
-        const int nl = min(S, lam - k * S);
+        const int nw = levels_written(k);
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int it = tid + kThreads * i;
             const int v = it / S, jj = it % S;
             const int kind = item_kind(i);
-            if (kind == 0 || jj >= nl) continue;
+            if (kind == 0 || jj >= nw) continue;
             const int32_t xs = Txst[v];
             const int pos = v * P2 + (xs & 1) + jj;
             const int64_t g = (int64_t)xs + k * S + jj;
@@ -1888,7 +1900,6 @@ __global__ void __launch_bounds__(kThreads, FORM == 3 && NI > 1 ? 3 : 4) k_pipe_
     };
 
     double yO[NOUT][NI];   // old output values of the chunk written back next
-    const int nch = (lam + S - 1) / S;
     issue_copies(0);
     load_old(0, yO);
     for (int k = 0; k < nch; ++k) {
@@ -1979,13 +1990,14 @@ __global__ void __launch_bounds__(kThreads, FORM == 3 && NI > 1 ? 3 : 4) k_pipe_
             }
         }
     }
-    // write back the last chunk, its top level included
+    // write back the last chunk, its top level included (by the items when
+    // the chunk is shorter than S, else here)
     lds_barrier();
     {
         const int k = nch - 1;
         const int nl = lam - k * S;
         write_back(k, yO, false);
-        for (int v = tid; v < nv; v += kThreads) {
+        for (int v = top_in_items ? nv : tid; v < nv; v += kThreads) {
             const int32_t xs = Txst[v];
             const int64_t g = (int64_t)xs + lam;
 #pragma unroll

@@ -29,7 +29,9 @@ def _run(c, kernel, ins, nout, **opts):
 
 
 @pytest.mark.parametrize("opts", OPTS)
-@pytest.mark.parametrize("n,lam,terrain", [(8, 10, 0.0), (6, 33, 0.3), (3, 1, 0.0), (5, 70, 0.1)])
+# heights with a last chunk shorter than the chunk length (its top level
+# written by the chunk's own items) and one that fills it (16 layers)
+@pytest.mark.parametrize("n,lam,terrain", [(8, 10, 0.0), (6, 33, 0.3), (3, 1, 0.0), (5, 70, 0.1), (4, 16, 0.2)])
 def test_cubic_forward_vjp_fused(opts, n, lam, terrain):
     say(f"cubic n={n} lam={lam} opts={opts}")
     base = meshgen.tri_square(n)
@@ -54,12 +56,14 @@ def test_cubic_forward_vjp_fused(opts, n, lam, terrain):
 
 @pytest.mark.parametrize("race", [exm.EXM_RACE_ATOMIC, exm.EXM_RACE_COLOUR])
 @pytest.mark.parametrize("chunk", [8, 16])
-def test_cubic_pipelined_inc_into_nonzero(race, chunk):
+@pytest.mark.parametrize("extra", [5, 0])
+def test_cubic_pipelined_inc_into_nonzero(race, chunk, extra):
     # INC: the pipelined write-back adds the old output values it loaded one
-    # chunk ahead; outputs start from random values here
-    say(f"cubic pipelined INC race={race} chunk={chunk}")
+    # chunk ahead; outputs start from random values here (a ragged last chunk,
+    # whose top level the chunk's items write, and a full one)
+    say(f"cubic pipelined INC race={race} chunk={chunk} extra={extra}")
     base = meshgen.tri_square(9, order="random")
-    c = Case(base, 2 * chunk + 5, "P1", terrain=0.2)
+    c = Case(base, 2 * chunk + extra, "P1", terrain=0.2)
     u = meshgen.uniform_values(c.n, seed=41)
     f = meshgen.uniform_values(c.n, seed=42)
     w = meshgen.uniform_values(c.n, seed=43)
