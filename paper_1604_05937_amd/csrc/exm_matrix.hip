@@ -92,8 +92,8 @@ void position_nodes(int32_t el, int p, int& a, int& b)
     }
 }
 
-template <int HK, int VK>
-__device__ __forceinline__ double mass_entry(double twoA, const double h[3], int ai, int aj, int bi, int bj)
+template <int HK>
+__device__ __forceinline__ double mass_T(const double h[3], int ai, int aj)
 {
     const double H = h[0] + h[1] + h[2];
     double T;
@@ -108,6 +108,12 @@ __device__ __forceinline__ double mass_entry(double twoA, const double h[3], int
         constexpr double K[3][6][6] = EXM_P2_K_TABLE;
         T = (h[0] * K[0][ai][aj] + h[1] * K[1][ai][aj] + h[2] * K[2][ai][aj]) * (1.0 / 2520.0);
     }
+    return T;
+}
+
+template <int VK>
+__device__ __forceinline__ double mass_V(int bi, int bj)
+{
     double V;
     if constexpr (VK == 0) {
         V = bi == bj ? 1.0 / 3.0 : 1.0 / 6.0;
@@ -117,7 +123,13 @@ __device__ __forceinline__ double mass_entry(double twoA, const double h[3], int
         constexpr double V2[3][3] = {{4.0, -1.0, 2.0}, {-1.0, 4.0, 2.0}, {2.0, 2.0, 16.0}};
         V = V2[bi][bj] * (1.0 / 30.0);
     }
-    return twoA * T * V;
+    return V;
+}
+
+template <int HK, int VK>
+__device__ __forceinline__ double mass_entry(double twoA, const double h[3], int ai, int aj, int bi, int bj)
+{
+    return twoA * mass_T<HK>(h, ai, aj) * mass_V<VK>(bi, bj);
 }
 
 // Jacobian of the cubic residual on a P1 prism, integral 3 u^2 phi_j phi_i
@@ -253,6 +265,17 @@ __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
             }
             cubic_jac_moments(twoA, hhi, ub, ut, mhi);
         }
+        // the horizontal nodes of the row and column classes are the same in
+        // every contribution of this cell: 2A T(h) of both layers once
+        int ai0 = 0, aj0 = 0;
+        double Tlo = 0.0, Thi = 0.0;
+        if constexpr (!JAC) {
+            const int info0 = g.pc_info[e];
+            ai0 = info0 & 7;
+            aj0 = (info0 >> 3) & 7;
+            Tlo = twoA * mass_T<HK>(hlo, ai0, aj0);
+            Thi = twoA * mass_T<HK>(hhi, ai0, aj0);
+        }
         for (; e < end && g.pc_cell[e] == c; ++e) {
             const int info = g.pc_info[e];
             const int ai = info & 7, aj = (info >> 3) & 7, bi = (info >> 6) & 3, bj = (info >> 8) & 3;
@@ -264,6 +287,8 @@ __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
                 const double vlo = cubic_jac_entry(mlo, ai, aj, bi + bj);
                 const double vhi = cubic_jac_entry(mhi, ai, aj, bi + bj);
                 v = ti ? vlo : vhi;
+            } else if (ai == ai0 && aj == aj0) {   // (always, by the class layout; uniform)
+                v = (ti ? Tlo : Thi) * mass_V<VK>(bi, bj);
             } else {
                 double h[3];
 #pragma unroll
