@@ -126,11 +126,6 @@ __device__ __forceinline__ double mass_V(int bi, int bj)
     return V;
 }
 
-template <int HK, int VK>
-__device__ __forceinline__ double mass_entry(double twoA, const double h[3], int ai, int aj, int bi, int bj)
-{
-    return twoA * mass_T<HK>(h, ai, aj) * mass_V<VK>(bi, bj);
-}
 
 // Jacobian of the cubic residual on a P1 prism, integral 3 u^2 phi_j phi_i
 // det J, with the rule of the residual (7-point Radon triangle x 3-point
@@ -266,34 +261,36 @@ __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
             cubic_jac_moments(twoA, hhi, ub, ut, mhi);
         }
         // the horizontal nodes of the row and column classes are the same in
-        // every contribution of this cell: 2A T(h) of both layers once
-        int ai0 = 0, aj0 = 0;
+        // every contribution of this cell (checked when the plan is built):
+        // 2A T(h) of both layers, or the Jacobian's entries, once
+        const int info0 = g.pc_info[e];
+        const int ai0 = info0 & 7, aj0 = (info0 >> 3) & 7;
         double Tlo = 0.0, Thi = 0.0;
+        double Jlo[3], Jhi[3];   // Jacobian: the entry of either layer for vertical nodes summing to 0, 1, 2
         if constexpr (!JAC) {
-            const int info0 = g.pc_info[e];
-            ai0 = info0 & 7;
-            aj0 = (info0 >> 3) & 7;
             Tlo = twoA * mass_T<HK>(hlo, ai0, aj0);
             Thi = twoA * mass_T<HK>(hhi, ai0, aj0);
+        } else {
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+                Jlo[bb] = cubic_jac_entry(mlo, ai0, aj0, bb);
+                Jhi[bb] = cubic_jac_entry(mhi, ai0, aj0, bb);
+            }
         }
         for (; e < end && g.pc_cell[e] == c; ++e) {
             const int info = g.pc_info[e];
-            const int ai = info & 7, aj = (info >> 3) & 7, bi = (info >> 6) & 3, bj = (info >> 8) & 3;
+            const int bi = (info >> 6) & 3, bj = (info >> 8) & 3;
             const int ti = (info >> 10) & 1, tj = (info >> 11) & 1;
             const int l = s - ti;   // the prism: the row node is its top (layer s - 1) or bottom / inside (layer s)
             if (l < 0 || l >= g.lam) continue;
             double v;
             if constexpr (JAC) {
-                const double vlo = cubic_jac_entry(mlo, ai, aj, bi + bj);
-                const double vhi = cubic_jac_entry(mhi, ai, aj, bi + bj);
+                const int bb = bi + bj;
+                const double vlo = bb == 0 ? Jlo[0] : (bb == 1 ? Jlo[1] : Jlo[2]);
+                const double vhi = bb == 0 ? Jhi[0] : (bb == 1 ? Jhi[1] : Jhi[2]);
                 v = ti ? vlo : vhi;
-            } else if (ai == ai0 && aj == aj0) {   // (always, by the class layout; uniform)
-                v = (ti ? Tlo : Thi) * mass_V<VK>(bi, bj);
             } else {
-                double h[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) h[a] = ti ? hlo[a] : hhi[a];
-                v = mass_entry<HK, VK>(twoA, h, ai, aj, bi, bj);
+                v = (ti ? Tlo : Thi) * mass_V<VK>(bi, bj);
             }
             const int d = tj - ti;
             if (d < 0) acc[0] += v;
@@ -658,6 +655,15 @@ int32_t exm_matrix_create(const exm_space* space, exm_matrix** out)
                 }
     }
     A->n_contrib = ncon;
+    // the assembly forms a cell's horizontal factor once per pattern entry:
+    // every contribution of one cell to one entry must pair the same
+    // horizontal nodes (a class is one node of one entity)
+    for (int64_t p = 0; p < A->n_pat; ++p)
+        for (int64_t c = pc_ptr[p] + 1; c < pc_ptr[p + 1]; ++c)
+            if (pc_cell[c] == pc_cell[c - 1])
+                EXM_CHECK((pc_info[c] & 63) == (pc_info[c - 1] & 63), EXM_EINVAL,
+                          "internal: pattern entry %lld pairs different horizontal nodes within cell %d",
+                          (long long)p, pc_cell[c]);
     // structural entries (the CSR count)
     int64_t cnt[2][2][3] = {};
     for (int kr = 0; kr < 2; ++kr)
