@@ -218,10 +218,6 @@ constexpr double kW1 = (155.0 - kS15) / 2400.0, kW2 = (155.0 + kS15) / 2400.0;
 constexpr double kLam[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {kA1, kA1, kB1}, {kA1, kB1, kA1}, {kB1, kA1, kA1},
                                {kA2, kA2, kB2}, {kA2, kB2, kA2}, {kB2, kA2, kA2}};
 constexpr double kWt[7] = {9.0 / 80.0, kW1, kW1, kW1, kW2, kW2, kW2};
-// Gauss-Legendre on [0, 1]
-constexpr double kG = 0.5 * 0.774596669241483377;   // sqrt(3/5) / 2
-constexpr double kZ[3] = {0.5 - kG, 0.5, 0.5 + kG};
-constexpr double kWz[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
 
 }  // namespace cubic
 

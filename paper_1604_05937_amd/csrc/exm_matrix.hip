@@ -128,13 +128,16 @@ __device__ __forceinline__ double mass_V(int bi, int bj)
 
 
 // Jacobian of the cubic residual on a P1 prism, integral 3 u^2 phi_j phi_i
-// det J, with the rule of the residual (7-point Radon triangle x 3-point
-// Gauss-Legendre, exact for this degree).  Per prism, the vertical moments
-// of 3 u^2 det J at every triangle point,
-//     m[t][k] = 3 w_t dj_t sum_z w_z u(t, z)^2 (1 - z)^(2 - k) z^k,  k = 0, 1, 2,
+// det J, with the triangle rule of the residual (7-point Radon, exact for
+// this degree) and the zeta integrals in closed form.  Per prism, the
+// vertical moments of 3 u^2 det J at every triangle point,
+//     m[t][k] = 3 w_t dj_t integral_0^1 u(t, z)^2 (1 - z)^(2 - k) z^k dz,  k = 0, 1, 2,
 // serve all its entries: entry (a_i, b_i), (a_j, b_j) = sum_t lambda_ai
 // lambda_aj m[t][b_i + b_j].  ub, ut: u at the bottom and top node of the
-// three vertices.
+// three vertices.  With u = u0 (1 - z) + u1 z, u^2 = p (1 - z)^2 + 2 r z (1 - z)
+// + q z^2 (p = u0^2, r = u0 u1, q = u1^2), and the integral of (1 - z)^a z^b
+// over [0, 1] is a! b! / (a + b + 1)!, so the three moments are
+// p/5 + r/10 + q/30, p/20 + r/15 + q/20 and p/30 + r/10 + q/5.
 __device__ __forceinline__ void cubic_jac_moments(double twoA, const double h[3], const double ub[3],
                                                   const double ut[3], double m[7][3])
 {
@@ -143,16 +146,11 @@ __device__ __forceinline__ void cubic_jac_moments(double twoA, const double h[3]
     for (int t = 0; t < 7; ++t) {
         const double dj = twoA * (kLam[t][0] * h[0] + kLam[t][1] * h[1] + kLam[t][2] * h[2]);
         const double u0 = kLam[t][0] * ub[0] + kLam[t][1] * ub[1] + kLam[t][2] * ub[2];
-        const double u1 = kLam[t][0] * ut[0] + kLam[t][1] * ut[1] + kLam[t][2] * ut[2] - u0;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int z = 0; z < 3; ++z) {
-            const double u = u0 + kZ[z] * u1;
-            const double g = kWz[z] * u * u;
-            s0 += g * (1.0 - kZ[z]) * (1.0 - kZ[z]);
-            s1 += g * (1.0 - kZ[z]) * kZ[z];
-            s2 += g * kZ[z] * kZ[z];
-        }
+        const double u1 = kLam[t][0] * ut[0] + kLam[t][1] * ut[1] + kLam[t][2] * ut[2];
+        const double p = u0 * u0, r = u0 * u1, q = u1 * u1;
+        const double s0 = p * (1.0 / 5.0) + r * (1.0 / 10.0) + q * (1.0 / 30.0);
+        const double s1 = p * (1.0 / 20.0) + r * (1.0 / 15.0) + q * (1.0 / 20.0);
+        const double s2 = p * (1.0 / 30.0) + r * (1.0 / 10.0) + q * (1.0 / 5.0);
         const double c = 3.0 * kWt[t] * dj;
         m[t][0] = c * s0;
         m[t][1] = c * s1;
