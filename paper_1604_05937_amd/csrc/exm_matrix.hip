@@ -179,6 +179,9 @@ __device__ __forceinline__ unsigned xcd_block_m(unsigned b, unsigned G)
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Rows of at most this many pattern entries take the Jacobian by rows.
+constexpr int kRowEntries = 8;
+
 struct GatherArgs {
     int32_t lam, L, band;
     int64_t n_pat;                        // pattern entries
@@ -191,6 +194,13 @@ struct GatherArgs {
     const int32_t* __restrict__ fmap;     // field lists (Jacobian: u's space, P1 x P1)
     const double* __restrict__ u;
     double* __restrict__ val;             // [n_pat][band][L]
+    // by rows (k_mat_jac_rows): the contributions to the entries of each row
+    // class, ordered by cell, with the entry's place in its row
+    int32_t n_rows;
+    const int32_t* __restrict__ pptr;     // [n_rows + 1] first pattern entry of every row
+    const int64_t* __restrict__ rc_ptr;   // [n_rows + 1]
+    const int32_t* __restrict__ rc_cell;
+    const int32_t* __restrict__ rc_info;  // pc_info | (entry - first entry of the row) << 12
 };
 
 // One wavefront per (pattern entry p, 64 consecutive slots): the entry, its
@@ -302,6 +312,103 @@ __global__ void __launch_bounds__(256) k_mat_gather(const GatherArgs g)
         for (int d = 0; d < 3; ++d) g.val[(p * 3 + d) * g.L + s] = acc[d];
     } else {
         g.val[p * g.L + s] = acc[1];
+    }
+}
+
+// The cubic Jacobian by rows (P1 x P1, every row of at most NE entries): one
+// wavefront per (row class r, 64 consecutive slots) takes the cells around
+// the row's vertex once each.  A cell's moments of either layer become the
+// nine entries of the row's vertex against the cell's three vertices (one
+// per sum of vertical nodes) right away, so that the moments do not stay
+// live, and every contribution of the cell picks its entry.
+template <int NE>
+__global__ void __launch_bounds__(256) k_mat_jac_rows(const GatherArgs g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_m(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int nsteps = (g.L + 63) >> 6;
+    const int64_t r = wid / nsteps;
+    if (r >= g.n_rows) return;   // uniform over the wavefront
+    const int s = (int)(wid - r * nsteps) * 64 + lane;
+    const bool act = s < g.L;
+    double acc[NE][3];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+    int64_t e = g.rc_ptr[r];
+    const int64_t end = g.rc_ptr[r + 1];
+    const double* __restrict__ Z = g.X + 2 * g.xn;
+    while (e < end) {
+        const int32_t c = g.rc_cell[e];
+        const int ai = g.rc_info[e] & 7;   // the row's vertex in this cell (the same in all its contributions)
+        double x[3], y[3], hlo[3], hhi[3], ul[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int xb = g.xmap[(int64_t)c * 6 + 2 * a];
+            x[a] = g.X[xb];
+            y[a] = g.X[g.xn + xb];
+            double z[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int lev = s - 1 + k;
+                z[k] = act && lev >= 0 && lev <= g.lam ? Z[xb + lev] : 0.0;
+            }
+            hlo[a] = z[1] - z[0];
+            hhi[a] = z[2] - z[1];
+            const int fb = g.fmap[(int64_t)c * 6 + 2 * a];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int lev = s - 1 + k;
+                ul[a][k] = act && lev >= 0 && lev <= g.lam ? g.u[fb + lev] : 0.0;
+            }
+        }
+        const double twoA = twice_area(x, y);
+        double J[2][3][3];   // layer (s - 1, s), column vertex aj, sum of vertical nodes
+#pragma unroll
+        for (int ly = 0; ly < 2; ++ly) {
+            double m[7][3], ub[3], ut[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ub[a] = ul[a][ly];
+                ut[a] = ul[a][ly + 1];
+            }
+            cubic_jac_moments(twoA, ly == 0 ? hlo : hhi, ub, ut, m);
+#pragma unroll
+            for (int aj = 0; aj < 3; ++aj)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) J[ly][aj][bb] = cubic_jac_entry(m, ai, aj, bb);
+        }
+        for (; e < end && g.rc_cell[e] == c; ++e) {
+            const int info = g.rc_info[e];
+            const int aj = (info >> 3) & 7, bi = (info >> 6) & 3, bj = (info >> 8) & 3;
+            const int ti = (info >> 10) & 1, tj = (info >> 11) & 1, le = info >> 12;
+            const int l = s - ti;   // the prism: the row node is its top (layer s - 1) or bottom (layer s)
+            if (l < 0 || l >= g.lam) continue;
+            const int ly = ti ? 0 : 1, bb = bi + bj;
+            double v = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)   // aj, bb and ti are the same on every lane
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    if (a == aj && b == bb) v = ly == 0 ? J[0][a][b] : J[1][a][b];
+            const int d = tj - ti + 1;
+#pragma unroll
+            for (int q = 0; q < NE; ++q)   // le is the same on every lane
+                if (q == le) {
+                    if (d == 0) acc[q][0] += v;
+                    else if (d == 1) acc[q][1] += v;
+                    else acc[q][2] += v;
+                }
+        }
+    }
+    if (!act) return;
+    const int32_t p0 = g.pptr[r], ne = g.pptr[r + 1] - p0;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        if (q >= ne) break;
+        const int64_t p = p0 + q;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g.val[(p * 3 + d) * g.L + s] = acc[q][d];
     }
 }
 
@@ -540,6 +647,8 @@ struct exm_matrix {
     DevBuf<int32_t> c0, wk, pptr, pcol;
     DevBuf<int64_t> pc_ptr;
     DevBuf<int32_t> pc_cell, pc_info;
+    DevBuf<int64_t> rc_ptr;   // by rows, for the P1 x P1 Jacobian when no row has more than kRowEntries entries
+    DevBuf<int32_t> rc_cell, rc_info;
     DevBuf<double> val;
 };
 
@@ -662,6 +771,38 @@ int32_t exm_matrix_create(const exm_space* space, exm_matrix** out)
                 EXM_CHECK((pc_info[c] & 63) == (pc_info[c - 1] & 63), EXM_EINVAL,
                           "internal: pattern entry %lld pairs different horizontal nodes within cell %d",
                           (long long)p, pc_cell[c]);
+    // by rows, for the Jacobian of P1 x P1 when no row has more than
+    // kRowEntries entries: the contributions of a row's entries merged in
+    // cell order (within a cell, in entry order)
+    std::vector<int64_t> rc_ptr;
+    std::vector<int32_t> rc_cell, rc_info;
+    int32_t max_row = 0;
+    for (int64_t r = 0; r < nclass; ++r) max_row = std::max(max_row, pptr[r + 1] - pptr[r]);
+    if (A->element == EXM_ELEMENT_P1P1 && max_row <= kRowEntries) {
+        rc_ptr.assign(nclass + 1, 0);
+        rc_cell.resize(ncon);
+        rc_info.resize(ncon);
+        std::vector<std::pair<int32_t, int32_t>> row;
+        for (int64_t r = 0; r < nclass; ++r) {
+            row.clear();
+            for (int32_t p = pptr[r]; p < pptr[r + 1]; ++p)
+                for (int64_t c = pc_ptr[p]; c < pc_ptr[p + 1]; ++c)
+                    row.emplace_back(pc_cell[c], pc_info[c] | (p - pptr[r]) << 12);
+            std::stable_sort(row.begin(), row.end(),
+                             [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                                 return a.first < b.first;
+                             });
+            const int64_t at = rc_ptr[r];
+            for (size_t i = 0; i < row.size(); ++i) {
+                rc_cell[at + i] = row[i].first;
+                rc_info[at + i] = row[i].second;
+                // the row's vertex has one place in a cell
+                EXM_CHECK(i == 0 || row[i].first != row[i - 1].first || (row[i].second & 7) == (row[i - 1].second & 7),
+                          EXM_EINVAL, "internal: row %lld meets cell %d at two places", (long long)r, row[i].first);
+            }
+            rc_ptr[r + 1] = at + (int64_t)row.size();
+        }
+    }
     // structural entries (the CSR count)
     int64_t cnt[2][2][3] = {};
     for (int kr = 0; kr < 2; ++kr)
@@ -683,6 +824,11 @@ int32_t exm_matrix_create(const exm_space* space, exm_matrix** out)
     if ((st = A->pc_ptr.upload(pc_ptr.data(), pc_ptr.size())) != EXM_OK) return st;
     if ((st = A->pc_cell.upload(pc_cell.data(), pc_cell.size())) != EXM_OK) return st;
     if ((st = A->pc_info.upload(pc_info.data(), pc_info.size())) != EXM_OK) return st;
+    if (!rc_ptr.empty()) {
+        if ((st = A->rc_ptr.upload(rc_ptr.data(), rc_ptr.size())) != EXM_OK) return st;
+        if ((st = A->rc_cell.upload(rc_cell.data(), rc_cell.size())) != EXM_OK) return st;
+        if ((st = A->rc_info.upload(rc_info.data(), rc_info.size())) != EXM_OK) return st;
+    }
     if ((st = A->val.alloc((size_t)A->n_pat * A->band * A->L)) != EXM_OK) return st;
     EXM_TRY_HIP(hipMemset(A->val.p, 0, sizeof(double) * A->val.n));
     *out = A.release();
@@ -744,6 +890,18 @@ int32_t exm_matrix_assemble(int32_t kernel, exm_matrix* A, int32_t nargs, const 
     const int64_t nb = (waves + 3) / 4;
     hipStream_t hs = (hipStream_t)stream;
     const ElementKinds ek = element_kinds(A->element);
+    if (jac && A->rc_ptr.p) {   // the Jacobian by rows
+        g.n_rows = A->n_classes;
+        g.pptr = A->pptr.p;
+        g.rc_ptr = A->rc_ptr.p;
+        g.rc_cell = A->rc_cell.p;
+        g.rc_info = A->rc_info.p;
+        const int64_t rwaves = (int64_t)A->n_classes * ((A->L + 63) / 64);
+        EXM_CHECK(rwaves < INT32_MAX, EXM_EOVERFLOW, "grid too large");
+        hipLaunchKernelGGL((k_mat_jac_rows<kRowEntries>), dim3((unsigned)((rwaves + 3) / 4)), dim3(bs), 0, hs, g);
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
 #define EXM_GATHER(HK, VK, J) hipLaunchKernelGGL((k_mat_gather<HK, VK, J>), dim3((unsigned)nb), dim3(bs), 0, hs, g)
     if (jac) EXM_GATHER(0, 0, true);
     else if (ek.hk == 0 && ek.vk == 0) EXM_GATHER(0, 0, false);
