@@ -63,6 +63,30 @@ def test_cubic_jacobian_matches_oracle(n, lam, terrain):
     assert_close(y, ref, c.ref.cubic_jacobian_abs(u) @ np.abs(du), what="J du")
 
 
+def _fan(k):
+    # a vertex with k neighbours (k triangles around it): its row has k + 1
+    # entries
+    ang = 2 * np.pi * np.arange(k) / k
+    xy = np.vstack([[0.0, 0.0], np.stack([np.cos(ang), np.sin(ang)], 1)])
+    cells = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)])
+    return meshgen._assemble(xy, cells, "natural", 0, {})
+
+
+@pytest.mark.parametrize("k", [6, 8, 11])
+def test_cubic_jacobian_rows_of_many_entries(k):
+    # rows of up to 8 entries take the Jacobian by rows, longer ones by
+    # pattern entries: both against the oracle
+    say(f"matrix cubic jacobian on a fan of {k} cells")
+    c = Case(_fan(k), 7, "P1", terrain=0.2)
+    u = meshgen.uniform_values(c.n, seed=24)
+    J = exm.Matrix(c.V)
+    J.assemble(exm.EXM_K_CUBIC_JAC, c.X, c.Vx, u=c.dev(u))
+    _check_csr(c, J, c.ref.cubic_jacobian(u), c.ref.cubic_jacobian_abs(u), f"cubic Jacobian, fan of {k}")
+    M = exm.Matrix(c.V)
+    M.assemble(exm.EXM_K_MASS, c.X, c.Vx)
+    _check_csr(c, M, c.ref.mass_matrix(), c.ref.mass_matrix_abs(), f"mass matrix, fan of {k}")
+
+
 def test_assembly_is_bitwise_reproducible_and_overwrites():
     c = Case(meshgen.tri_square(8), 12, "P1", terrain=0.2)
     u = c.dev(meshgen.uniform_values(c.n, seed=24))
