@@ -412,6 +412,86 @@ __global__ void __launch_bounds__(256) k_mat_jac_rows(const GatherArgs g)
     }
 }
 
+// The mass form by rows (every row of at most NE entries): one wavefront per
+// (row class r, 64 consecutive slots) takes the cells around the row's
+// entity once each; a cell's contributions come in entry order, and 2A T(h)
+// of both layers is formed once per entry.
+template <int HK, int VK, int NE>
+__global__ void __launch_bounds__(256) k_mat_mass_rows(const GatherArgs g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = __builtin_amdgcn_readfirstlane(
+        (int32_t)(xcd_block_m(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int nsteps = (g.L + 63) >> 6;
+    const int64_t r = wid / nsteps;
+    if (r >= g.n_rows) return;   // uniform over the wavefront
+    const int s = (int)(wid - r * nsteps) * 64 + lane;
+    const bool act = s < g.L;
+    double acc[NE][3];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+    int64_t e = g.rc_ptr[r];
+    const int64_t end = g.rc_ptr[r + 1];
+    const double* __restrict__ Z = g.X + 2 * g.xn;
+    while (e < end) {
+        const int32_t c = g.rc_cell[e];
+        double x[3], y[3], hlo[3], hhi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int xb = g.xmap[(int64_t)c * 6 + 2 * a];
+            x[a] = g.X[xb];
+            y[a] = g.X[g.xn + xb];
+            double z[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int lev = s - 1 + k;
+                z[k] = act && lev >= 0 && lev <= g.lam ? Z[xb + lev] : 0.0;
+            }
+            hlo[a] = z[1] - z[0];
+            hhi[a] = z[2] - z[1];
+        }
+        const double twoA = twice_area(x, y);
+        int cur = -1;   // the entry whose factors are formed
+        double Tlo = 0.0, Thi = 0.0;
+        for (; e < end && g.rc_cell[e] == c; ++e) {
+            const int info = g.rc_info[e];
+            const int le = info >> 12;
+            if (le != cur) {   // the same on every lane
+                const int ai = info & 7, aj = (info >> 3) & 7;
+                Tlo = twoA * mass_T<HK>(hlo, ai, aj);
+                Thi = twoA * mass_T<HK>(hhi, ai, aj);
+                cur = le;
+            }
+            const int bi = (info >> 6) & 3, bj = (info >> 8) & 3;
+            const int ti = (info >> 10) & 1, tj = (info >> 11) & 1;
+            const int l = s - ti;
+            if (l < 0 || l >= g.lam) continue;
+            const double v = (ti ? Tlo : Thi) * mass_V<VK>(bi, bj);
+            const int d = tj - ti + 1;
+#pragma unroll
+            for (int q = 0; q < NE; ++q)   // le is the same on every lane
+                if (q == le) {
+                    if (d == 0) acc[q][0] += v;
+                    else if (d == 1) acc[q][1] += v;
+                    else acc[q][2] += v;
+                }
+        }
+    }
+    if (!act) return;
+    const int32_t p0 = g.pptr[r], ne = g.pptr[r + 1] - p0;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        if (q >= ne) break;
+        const int64_t p = p0 + q;
+        if (g.band == 3) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g.val[(p * 3 + d) * g.L + s] = acc[q][d];
+        } else {
+            g.val[p * g.L + s] = acc[q][1];
+        }
+    }
+}
+
 struct RowArgs {
     int32_t lam, L, band, write;
     int32_t n_classes;
@@ -647,7 +727,7 @@ struct exm_matrix {
     DevBuf<int32_t> c0, wk, pptr, pcol;
     DevBuf<int64_t> pc_ptr;
     DevBuf<int32_t> pc_cell, pc_info;
-    DevBuf<int64_t> rc_ptr;   // by rows, for the P1 x P1 Jacobian when no row has more than kRowEntries entries
+    DevBuf<int64_t> rc_ptr;   // by rows, when no row has more than kRowEntries entries
     DevBuf<int32_t> rc_cell, rc_info;
     DevBuf<double> val;
 };
@@ -771,14 +851,14 @@ int32_t exm_matrix_create(const exm_space* space, exm_matrix** out)
                 EXM_CHECK((pc_info[c] & 63) == (pc_info[c - 1] & 63), EXM_EINVAL,
                           "internal: pattern entry %lld pairs different horizontal nodes within cell %d",
                           (long long)p, pc_cell[c]);
-    // by rows, for the Jacobian of P1 x P1 when no row has more than
-    // kRowEntries entries: the contributions of a row's entries merged in
-    // cell order (within a cell, in entry order)
+    // by rows, when no row has more than kRowEntries entries: the
+    // contributions of a row's entries merged in cell order (within a cell,
+    // in entry order)
     std::vector<int64_t> rc_ptr;
     std::vector<int32_t> rc_cell, rc_info;
     int32_t max_row = 0;
     for (int64_t r = 0; r < nclass; ++r) max_row = std::max(max_row, pptr[r + 1] - pptr[r]);
-    if (A->element == EXM_ELEMENT_P1P1 && max_row <= kRowEntries) {
+    if (max_row <= kRowEntries) {
         rc_ptr.assign(nclass + 1, 0);
         rc_cell.resize(ncon);
         rc_info.resize(ncon);
@@ -899,6 +979,25 @@ int32_t exm_matrix_assemble(int32_t kernel, exm_matrix* A, int32_t nargs, const 
         const int64_t rwaves = (int64_t)A->n_classes * ((A->L + 63) / 64);
         EXM_CHECK(rwaves < INT32_MAX, EXM_EOVERFLOW, "grid too large");
         hipLaunchKernelGGL((k_mat_jac_rows<kRowEntries>), dim3((unsigned)((rwaves + 3) / 4)), dim3(bs), 0, hs, g);
+        EXM_TRY_HIP(hipGetLastError());
+        return EXM_OK;
+    }
+    if (!jac && A->rc_ptr.p) {   // the mass by rows
+        g.n_rows = A->n_classes;
+        g.pptr = A->pptr.p;
+        g.rc_ptr = A->rc_ptr.p;
+        g.rc_cell = A->rc_cell.p;
+        g.rc_info = A->rc_info.p;
+        const int64_t rwaves = (int64_t)A->n_classes * ((A->L + 63) / 64);
+        EXM_CHECK(rwaves < INT32_MAX, EXM_EOVERFLOW, "grid too large");
+        const dim3 grid((unsigned)((rwaves + 3) / 4));
+#define EXM_ROWS(HK, VK) hipLaunchKernelGGL((k_mat_mass_rows<HK, VK, kRowEntries>), grid, dim3(bs), 0, hs, g)
+        if (ek.hk == 0 && ek.vk == 0) EXM_ROWS(0, 0);
+        else if (ek.hk == 0) EXM_ROWS(0, 1);
+        else if (ek.hk == 1 && ek.vk == 0) EXM_ROWS(1, 0);
+        else if (ek.hk == 1) EXM_ROWS(1, 1);
+        else EXM_ROWS(2, 2);
+#undef EXM_ROWS
         EXM_TRY_HIP(hipGetLastError());
         return EXM_OK;
     }
